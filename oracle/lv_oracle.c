@@ -1,0 +1,557 @@
+/*
+ * FP64 CPU oracle for learning-free feature uplifting (LUDVIG, arXiv
+ * 2410.14462).  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark are its only callers.  It shares no code,
+ * header or constant table with the GPU library; it is written from the
+ * paper's definitions:
+ *
+ *   - Sec. 3.1, Eq. (1): pixel p of view d blends the ordered set S_{d,p};
+ *     w_i(d,p) = alpha_i(d,p) * prod_{j<i} (1 - alpha_j(d,p)), with alpha_i the
+ *     opacity times the projected 2D Gaussian density at p.
+ *   - Sec. 3.2, Eq. (3) / Eq. (5): f_i = sum_{(d,p) in S_i} w_i(d,p) F_{d,p}
+ *     / sum_{(d,p) in S_i} w_i(d,p), i.e. f = diag(beta)^-1 W^T F with beta the
+ *     column sums of W (Gaussian filtering paragraph: beta_i = sum w_i).
+ *   - Sec. 3.2, Eq. (4): the forward render F^ = W g (used for the adjoint pin).
+ *
+ * Conventions the paper leaves open (the projection, the tile support, the
+ * clamp/skip/stop constants) follow the 3D Gaussian Splatting rasteriser the
+ * paper relies on (Sec. 5); every choice is spelled out below.
+ *
+ * Evaluation is brute force: every pixel of every view walks, in order, every
+ * Gaussian whose tile rectangle contains the pixel's tile.  Which Gaussians a
+ * pixel counts (the alpha >= 1/255 skip and the T < 1e-4 stop) is a discrete
+ * outcome decided by floating point, so it is decided in FP32 by a fixed
+ * sequence of IEEE operations ("S32") that the GPU library follows too; the
+ * VALUES (alpha, T, w, every sum) are computed in FP64 from the FP32 inputs.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -fPIC -shared
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_TILE 16
+
+/* FP32 constants, exactly as FP32 literals (also promoted to FP64 for values). */
+static const float K_ALPHA_MAX = 0x1.fae148p-1f;   /* 0.99f   */
+static const float K_ALPHA_MIN = 0x1.010102p-8f;   /* 1/255.f */
+static const float K_T_EPS = 0x1.a36e2ep-14f;      /* 1e-4f   */
+static const float K_DILATE = 0x1.333334p-2f;      /* 0.3f    */
+static const float K_CLAMP = 0x1.4cccccp+0f;       /* 1.3f    */
+
+/* ----------------------------------------------------------------------- */
+/* S32 exponential (decision path only): exp(x) for x <= 0 by Cody-Waite
+ * reduction x = k ln2 + r, |r| <= ln2/2, and the degree-7 Taylor polynomial
+ * of e^r in Horner form with fmaf; 0 below -80.                              */
+static float orc_exp32(float x)
+{
+    if (x < -80.0f) return 0.0f;
+    float kf = rintf(x * 0x1.715476p+0f);
+    float r = fmaf(kf, -0x1.62e4p-1f, x);
+    r = fmaf(kf, -0x1.7f7d1cp-20f, r);
+    float p = 0x1.a01a02p-13f;
+    p = fmaf(p, r, 0x1.6c16c2p-10f);
+    p = fmaf(p, r, 0x1.111112p-7f);
+    p = fmaf(p, r, 0x1.555556p-5f);
+    p = fmaf(p, r, 0x1.555556p-3f);
+    p = fmaf(p, r, 0x1.0p-1f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    int k = (int)kf;
+    uint32_t sb = (uint32_t)(k + 127) << 23;
+    float s;
+    memcpy(&s, &sb, 4);
+    return p * s;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Camera: 17 floats = R[9] (world->camera, row-major), t[3], fx, fy, cx, cy,
+ * znear; x_c = R x_w + t; x right, y down, z forward; pixel (i,j) is the unit
+ * square [i,i+1) x [j,j+1), its centre (i+0.5, j+0.5).                       */
+typedef struct { const float* c; int W, H; } orc_cam;
+
+/* Per-Gaussian, per-view quantities. */
+typedef struct {
+    int vis;
+    uint32_t depth;                 /* bits of FP32 z_c (z_c > 0 orders as unsigned) */
+    int x0, y0, x1, y1;             /* tile rectangle [x0,x1) x [y0,y1)              */
+    float ux, uy, A, B, C, op;      /* S32: power = A dx^2 + B dx dy + C dy^2        */
+    double ux64, uy64, A64, B64, C64, op64;
+} orc_proj;
+
+/* Sec. 3.1: covariance from scale and rotation, Sigma = R diag(s)^2 R^T, with
+ * R the rotation of the normalised quaternion (w,x,y,z).  S32 op order.     */
+static void orc_cov32(const float* s, const float* q, float out[6])
+{
+    float n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+    float w = 1.0f, x = 0.0f, y = 0.0f, z = 0.0f;
+    if (n2 > 0.0f) {
+        float nr = sqrtf(n2);
+        w = q[0] / nr; x = q[1] / nr; y = q[2] / nr; z = q[3] / nr;
+    }
+    float R[9];
+    R[0] = 1.0f - 2.0f * (y * y + z * z);
+    R[1] = 2.0f * (x * y - w * z);
+    R[2] = 2.0f * (x * z + w * y);
+    R[3] = 2.0f * (x * y + w * z);
+    R[4] = 1.0f - 2.0f * (x * x + z * z);
+    R[5] = 2.0f * (y * z - w * x);
+    R[6] = 2.0f * (x * z - w * y);
+    R[7] = 2.0f * (y * z + w * x);
+    R[8] = 1.0f - 2.0f * (x * x + y * y);
+    float M[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
+    static const int I[6] = {0, 0, 0, 1, 1, 2}, J[6] = {0, 1, 2, 1, 2, 2};
+    for (int e = 0; e < 6; e++) {
+        const float* a = M + 3 * I[e];
+        const float* b = M + 3 * J[e];
+        out[e] = (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+    }
+}
+
+static void orc_cov64(const float* s, const float* q, double out[6])
+{
+    double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    double n2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    double w = 1, x = 0, y = 0, z = 0;
+    if (n2 > 0) { double nr = sqrt(n2); w = q0 / nr; x = q1 / nr; y = q2 / nr; z = q3 / nr; }
+    double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                   2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                   2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    double M[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * (double)s[j];
+    static const int I[6] = {0, 0, 0, 1, 1, 2}, J[6] = {0, 1, 2, 1, 2, 2};
+    for (int e = 0; e < 6; e++) {
+        const double* a = M + 3 * I[e];
+        const double* b = M + 3 * J[e];
+        out[e] = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    }
+}
+
+/* Projection of one Gaussian into one view: EWA local-affine approximation
+ * of the perspective map (Jacobian with x/z, y/z clamped to 1.3x the half-FoV
+ * tangent), 2D covariance plus 0.3 px^2, conic = inverse, radius
+ * ceil(3 sqrt(lambda_max)), 16x16 tile rectangle.  Structure in S32, values
+ * in FP64 from the same FP32 inputs.                                         */
+static void orc_project(const float* mu, const float* cov32, const double* cov64, float op,
+                        const orc_cam* cam, orc_proj* g)
+{
+    const float* c = cam->c;
+    const float *Rc = c, *t = c + 9;
+    float fx = c[12], fy = c[13], cx = c[14], cy = c[15], zn = c[16];
+    int TX = (cam->W + ORC_TILE - 1) / ORC_TILE, TY = (cam->H + ORC_TILE - 1) / ORC_TILE;
+    memset(g, 0, sizeof(*g));
+
+    /* ---- S32 ---- */
+    float xc = (Rc[0] * mu[0] + Rc[1] * mu[1]) + Rc[2] * mu[2] + t[0];
+    float yc = (Rc[3] * mu[0] + Rc[4] * mu[1]) + Rc[5] * mu[2] + t[1];
+    float zc = (Rc[6] * mu[0] + Rc[7] * mu[1]) + Rc[8] * mu[2] + t[2];
+    if (!(zc > zn)) return;
+    float ix = xc / zc, iy = yc / zc;
+    float ux = fx * ix + cx, uy = fy * iy + cy;
+    float limx = K_CLAMP * ((0.5f * (float)cam->W) / fx);
+    float limy = K_CLAMP * ((0.5f * (float)cam->H) / fy);
+    float tx = fminf(limx, fmaxf(-limx, ix));
+    float ty = fminf(limy, fmaxf(-limy, iy));
+    float j00 = fx / zc, j11 = fy / zc;
+    float j02 = -(j00 * tx), j12 = -(j11 * ty);
+    float T[6];
+    for (int k = 0; k < 3; k++) {
+        T[k] = j00 * Rc[k] + j02 * Rc[6 + k];
+        T[3 + k] = j11 * Rc[3 + k] + j12 * Rc[6 + k];
+    }
+    float S[9] = {cov32[0], cov32[1], cov32[2], cov32[1], cov32[3], cov32[4],
+                  cov32[2], cov32[4], cov32[5]};
+    float V[6];
+    for (int i = 0; i < 2; i++)
+        for (int k = 0; k < 3; k++)
+            V[3 * i + k] = (T[3 * i] * S[k] + T[3 * i + 1] * S[3 + k]) + T[3 * i + 2] * S[6 + k];
+    float a = ((V[0] * T[0] + V[1] * T[1]) + V[2] * T[2]) + K_DILATE;
+    float b = (V[0] * T[3] + V[1] * T[4]) + V[2] * T[5];
+    float cc = ((V[3] * T[3] + V[4] * T[4]) + V[5] * T[5]) + K_DILATE;
+    float det = a * cc - b * b;
+    if (!(det > 0.0f)) return;
+    float h = 0.5f * (a + cc), dd = 0.5f * (a - cc);
+    float lam = h + sqrtf(dd * dd + b * b);
+    float r = ceilf(3.0f * sqrtf(lam));
+    float fx0 = floorf((ux - r) / (float)ORC_TILE);
+    float fx1 = floorf((ux + r) / (float)ORC_TILE) + 1.0f;
+    float fy0 = floorf((uy - r) / (float)ORC_TILE);
+    float fy1 = floorf((uy + r) / (float)ORC_TILE) + 1.0f;
+    int x0 = (int)fminf(fmaxf(fx0, 0.0f), (float)TX), x1 = (int)fminf(fmaxf(fx1, 0.0f), (float)TX);
+    int y0 = (int)fminf(fmaxf(fy0, 0.0f), (float)TY), y1 = (int)fminf(fmaxf(fy1, 0.0f), (float)TY);
+    if (x1 <= x0 || y1 <= y0) return;
+    g->vis = 1;
+    memcpy(&g->depth, &zc, 4);
+    g->x0 = x0; g->x1 = x1; g->y0 = y0; g->y1 = y1;
+    g->ux = ux; g->uy = uy;
+    g->A = -0.5f * (cc / det);
+    g->B = b / det;
+    g->C = -0.5f * (a / det);
+    g->op = op;
+
+    /* ---- FP64 values ---- */
+    double X = (double)Rc[0] * mu[0] + (double)Rc[1] * mu[1] + (double)Rc[2] * mu[2] + t[0];
+    double Y = (double)Rc[3] * mu[0] + (double)Rc[4] * mu[1] + (double)Rc[5] * mu[2] + t[1];
+    double Z = (double)Rc[6] * mu[0] + (double)Rc[7] * mu[1] + (double)Rc[8] * mu[2] + t[2];
+    double IX = X / Z, IY = Y / Z;
+    g->ux64 = (double)fx * IX + cx;
+    g->uy64 = (double)fy * IY + cy;
+    double LX = (double)K_CLAMP * (0.5 * cam->W / (double)fx);
+    double LY = (double)K_CLAMP * (0.5 * cam->H / (double)fy);
+    double TXc = fmin(LX, fmax(-LX, IX)), TYc = fmin(LY, fmax(-LY, IY));
+    double J00 = fx / Z, J11 = fy / Z, J02 = -J00 * TXc, J12 = -J11 * TYc;
+    double TT[6];
+    for (int k = 0; k < 3; k++) {
+        TT[k] = J00 * Rc[k] + J02 * Rc[6 + k];
+        TT[3 + k] = J11 * Rc[3 + k] + J12 * Rc[6 + k];
+    }
+    double SS[9] = {cov64[0], cov64[1], cov64[2], cov64[1], cov64[3], cov64[4],
+                    cov64[2], cov64[4], cov64[5]};
+    double VV[6];
+    for (int i = 0; i < 2; i++)
+        for (int k = 0; k < 3; k++)
+            VV[3 * i + k] = TT[3 * i] * SS[k] + TT[3 * i + 1] * SS[3 + k] + TT[3 * i + 2] * SS[6 + k];
+    double A2 = VV[0] * TT[0] + VV[1] * TT[1] + VV[2] * TT[2] + (double)K_DILATE;
+    double B2 = VV[0] * TT[3] + VV[1] * TT[4] + VV[2] * TT[5];
+    double C2 = VV[3] * TT[3] + VV[4] * TT[4] + VV[5] * TT[5] + (double)K_DILATE;
+    double DET = A2 * C2 - B2 * B2;
+    g->A64 = -0.5 * C2 / DET;
+    g->B64 = B2 / DET;
+    g->C64 = -0.5 * A2 / DET;
+    g->op64 = op;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Scene: precomputed FP32 and FP64 covariances.                            */
+typedef struct {
+    int64_t n;
+    const float *mu, *op;
+    float* cov32;
+    double* cov64;
+} orc_scene;
+
+static int orc_scene_init(orc_scene* sc, int64_t n, const float* mu, const float* s,
+                          const float* q, const float* op)
+{
+    sc->n = n; sc->mu = mu; sc->op = op;
+    sc->cov32 = (float*)malloc(sizeof(float) * 6 * (size_t)(n ? n : 1));
+    sc->cov64 = (double*)malloc(sizeof(double) * 6 * (size_t)(n ? n : 1));
+    if (!sc->cov32 || !sc->cov64) return -1;
+    for (int64_t i = 0; i < n; i++) {
+        orc_cov32(s + 3 * i, q + 4 * i, sc->cov32 + 6 * i);
+        orc_cov64(s + 3 * i, q + 4 * i, sc->cov64 + 6 * i);
+    }
+    return 0;
+}
+
+static void orc_scene_free(orc_scene* sc) { free(sc->cov32); free(sc->cov64); }
+
+/* Per-view structure: projections and, per tile, the Gaussians whose tile
+ * rectangle contains it, sorted by (depth key, Gaussian index) -- the ordered
+ * set S_{d,p} of Sec. 3.1 shared by all pixels of the tile.                  */
+typedef struct {
+    orc_proj* g;
+    int TX, TY;
+    int64_t* start;   /* [TX*TY + 1] */
+    int32_t* ids;     /* [P]         */
+    int64_t P, nvis;
+} orc_view;
+
+static const orc_proj* g_sort_base;
+static int orc_cmp(const void* a, const void* b)
+{
+    int32_t i = *(const int32_t*)a, j = *(const int32_t*)b;
+    uint32_t di = g_sort_base[i].depth, dj = g_sort_base[j].depth;
+    if (di != dj) return di < dj ? -1 : 1;
+    return (i > j) - (i < j);
+}
+
+static int orc_view_build(const orc_scene* sc, const orc_cam* cam, orc_view* v)
+{
+    int64_t n = sc->n;
+    v->TX = (cam->W + ORC_TILE - 1) / ORC_TILE;
+    v->TY = (cam->H + ORC_TILE - 1) / ORC_TILE;
+    int64_t nt = (int64_t)v->TX * v->TY;
+    v->g = (orc_proj*)malloc(sizeof(orc_proj) * (size_t)(n ? n : 1));
+    v->start = (int64_t*)calloc((size_t)nt + 1, sizeof(int64_t));
+    if (!v->g || !v->start) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++)
+        orc_project(sc->mu + 3 * i, sc->cov32 + 6 * i, sc->cov64 + 6 * i, sc->op[i], cam, v->g + i);
+    v->nvis = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const orc_proj* g = v->g + i;
+        if (!g->vis) continue;
+        v->nvis++;
+        for (int y = g->y0; y < g->y1; y++)
+            for (int x = g->x0; x < g->x1; x++) v->start[(int64_t)y * v->TX + x + 1]++;
+    }
+    for (int64_t t = 0; t < nt; t++) v->start[t + 1] += v->start[t];
+    v->P = v->start[nt];
+    v->ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(v->P ? v->P : 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nt ? nt : 1));
+    if (!v->ids || !fill) return -1;
+    memcpy(fill, v->start, sizeof(int64_t) * (size_t)nt);
+    for (int64_t i = 0; i < n; i++) {
+        const orc_proj* g = v->g + i;
+        if (!g->vis) continue;
+        for (int y = g->y0; y < g->y1; y++)
+            for (int x = g->x0; x < g->x1; x++) v->ids[fill[(int64_t)y * v->TX + x]++] = (int32_t)i;
+    }
+    free(fill);
+    g_sort_base = v->g;
+    for (int64_t t = 0; t < nt; t++)
+        qsort(v->ids + v->start[t], (size_t)(v->start[t + 1] - v->start[t]), sizeof(int32_t), orc_cmp);
+    return 0;
+}
+
+static void orc_view_free(orc_view* v) { free(v->g); free(v->start); free(v->ids); }
+
+/* One pixel's front-to-back walk.  Calls `emit(i, w64)` for every Gaussian the
+ * pixel counts, in order; returns the final transmittance (FP64), writes the
+ * FP32 one to *t32 when non-NULL.                                            */
+typedef void (*orc_emit_fn)(void* ctx, int32_t i, double w);
+
+static double orc_walk(const orc_view* v, int64_t tile, int px, int py, orc_emit_fn emit,
+                       void* ctx, float* t32)
+{
+    float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
+    double pxd = px + 0.5, pyd = py + 0.5;
+    float T = 1.0f;
+    double T64 = 1.0;
+    for (int64_t k = v->start[tile]; k < v->start[tile + 1]; k++) {
+        int32_t i = v->ids[k];
+        const orc_proj* g = v->g + i;
+        /* decision path (S32) */
+        float dx = pxf - g->ux, dy = pyf - g->uy;
+        float pw = (g->B * dx) * dy;
+        pw = fmaf(g->C * dy, dy, pw);
+        pw = fmaf(g->A * dx, dx, pw);
+        pw = fminf(pw, 0.0f);
+        float al = fminf(K_ALPHA_MAX, g->op * orc_exp32(pw));
+        if (al < K_ALPHA_MIN) continue;
+        float Tn = T * (1.0f - al);
+        if (Tn < K_T_EPS) break;
+        /* values (FP64) */
+        double ex = pxd - g->ux64, ey = pyd - g->uy64;
+        double p64 = fmin(0.0, g->A64 * ex * ex + g->B64 * ex * ey + g->C64 * ey * ey);
+        double a64 = fmin((double)K_ALPHA_MAX, g->op64 * exp(p64));
+        emit(ctx, i, a64 * T64);
+        T = Tn;
+        T64 *= 1.0 - a64;
+    }
+    if (t32) *t32 = T;
+    return T64;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Accumulation context: U_r += w F_p, a_r += w |F_p| for accumulated rows r,
+ * beta_i += w and count_i += 1 for every Gaussian.                           */
+typedef struct {
+    const float* F;    /* current pixel's D features */
+    int D;
+    const int32_t* row;  /* Gaussian -> accumulated row or -1; NULL = identity */
+    double *U, *A, *beta;
+    int64_t* cnt;
+    int64_t nnz;
+} orc_acc;
+
+static void orc_emit_acc(void* vctx, int32_t i, double w)
+{
+    orc_acc* c = (orc_acc*)vctx;
+    c->beta[i] += w;
+    c->cnt[i] += 1;
+    c->nnz++;
+    int64_t r = c->row ? c->row[i] : i;
+    if (r < 0) return;
+    double* u = c->U + r * c->D;
+    double* a = c->A + r * c->D;
+    for (int k = 0; k < c->D; k++) {
+        double f = c->F[k];
+        u[k] += w * f;
+        a[k] += w * fabs(f);
+    }
+}
+
+static int orc_threads(int req)
+{
+#ifdef _OPENMP
+    return req > 0 ? req : omp_get_max_threads();
+#else
+    (void)req;
+    return 1;
+#endif
+}
+
+/* Uplift one view (Eq. 3 numerator and denominator), ADDING into the
+ * caller's FP64 accumulators:
+ *   U[nrows][D] += sum_p w_i(p) F_p,   A[nrows][D] += sum_p w_i(p) |F_p|,
+ *   beta[n] += sum_p w_i(p),           cnt[n] += #{p : i counted at p}.
+ * F is [H][W][D] FP32 (HWC).  row[n] maps Gaussian -> accumulated row (or -1);
+ * NULL means every Gaussian, nrows = n.  tfinal (nullable) gets the FP64 final
+ * transmittance per pixel [H][W].  stats[0..2] += nnz, P, n_visible.
+ * Returns 0, or -1 on allocation failure.                                    */
+int orc_uplift_view(int64_t n, const float* mu, const float* s, const float* q, const float* op,
+                    const float* cam17, int W, int H, const float* F, int D, const int32_t* row,
+                    int64_t nrows, double* U, double* A, double* beta, int64_t* cnt,
+                    double* tfinal, int64_t* stats, int nthreads)
+{
+    orc_scene sc;
+    orc_view v;
+    orc_cam cam = {cam17, W, H};
+    memset(&v, 0, sizeof(v));
+    if (orc_scene_init(&sc, n, mu, s, q, op) || orc_view_build(&sc, &cam, &v)) {
+        orc_scene_free(&sc); orc_view_free(&v);
+        return -1;
+    }
+    int nth = orc_threads(nthreads);
+    int64_t nt = (int64_t)v.TX * v.TY;
+    size_t rs = (size_t)nrows * (size_t)D;
+    double** pu = (double**)calloc((size_t)nth, sizeof(double*));
+    double** pa = (double**)calloc((size_t)nth, sizeof(double*));
+    double** pb = (double**)calloc((size_t)nth, sizeof(double*));
+    int64_t** pc = (int64_t**)calloc((size_t)nth, sizeof(int64_t*));
+    int64_t* pn = (int64_t*)calloc((size_t)nth, sizeof(int64_t));
+    int fail = !pu || !pa || !pb || !pc || !pn;
+    for (int t = 0; t < nth && !fail; t++) {
+        pu[t] = (double*)calloc(rs ? rs : 1, sizeof(double));
+        pa[t] = (double*)calloc(rs ? rs : 1, sizeof(double));
+        pb[t] = (double*)calloc((size_t)(n ? n : 1), sizeof(double));
+        pc[t] = (int64_t*)calloc((size_t)(n ? n : 1), sizeof(int64_t));
+        fail |= !pu[t] || !pa[t] || !pb[t] || !pc[t];
+    }
+    if (!fail) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+        for (int64_t tile = 0; tile < nt; tile++) {
+#ifdef _OPENMP
+            int th = omp_get_thread_num();
+#else
+            int th = 0;
+#endif
+            orc_acc ctx = {0, D, row, pu[th], pa[th], pb[th], pc[th], 0};
+            int tx = (int)(tile % v.TX), ty = (int)(tile / v.TX);
+            for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < H; py++)
+                for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < W; px++) {
+                    ctx.F = F + ((int64_t)py * W + px) * D;
+                    double T = orc_walk(&v, tile, px, py, orc_emit_acc, &ctx, NULL);
+                    if (tfinal) tfinal[(int64_t)py * W + px] = T;
+                }
+            pn[th] += ctx.nnz;
+        }
+        for (int t = 0; t < nth; t++) {
+            for (size_t k = 0; k < rs; k++) { U[k] += pu[t][k]; A[k] += pa[t][k]; }
+            for (int64_t i = 0; i < n; i++) { beta[i] += pb[t][i]; cnt[i] += pc[t][i]; }
+            stats[0] += pn[t];
+        }
+        stats[1] += v.P;
+        stats[2] += v.nvis;
+    }
+    for (int t = 0; t < nth; t++) {
+        if (pu) free(pu[t]);
+        if (pa) free(pa[t]);
+        if (pb) free(pb[t]);
+        if (pc) free(pc[t]);
+    }
+    free(pu); free(pa); free(pb); free(pc); free(pn);
+    orc_view_free(&v);
+    orc_scene_free(&sc);
+    return fail ? -1 : 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Forward render of one view, Eq. (4): out[H][W][D] = sum_i w_i(p) g_i
+ * (FP64 g [n][D]); alpha[H][W] (nullable) = sum_i w_i(p).                   */
+typedef struct { const double* g; double* out; double asum; int D; } orc_rctx;
+
+static void orc_emit_render(void* vctx, int32_t i, double w)
+{
+    orc_rctx* c = (orc_rctx*)vctx;
+    for (int k = 0; k < c->D; k++) c->out[k] += w * c->g[(int64_t)i * c->D + k];
+    c->asum += w;
+}
+
+int orc_render_view(int64_t n, const float* mu, const float* s, const float* q, const float* op,
+                    const float* cam17, int W, int H, const double* g, int D, double* out,
+                    double* alpha, int nthreads)
+{
+    orc_scene sc;
+    orc_view v;
+    orc_cam cam = {cam17, W, H};
+    memset(&v, 0, sizeof(v));
+    if (orc_scene_init(&sc, n, mu, s, q, op) || orc_view_build(&sc, &cam, &v)) {
+        orc_scene_free(&sc); orc_view_free(&v);
+        return -1;
+    }
+    int nth = orc_threads(nthreads);
+    int64_t nt = (int64_t)v.TX * v.TY;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+    for (int64_t tile = 0; tile < nt; tile++) {
+        int tx = (int)(tile % v.TX), ty = (int)(tile / v.TX);
+        for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < H; py++)
+            for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < W; px++) {
+                orc_rctx c = {g, out + ((int64_t)py * W + px) * D, 0.0, D};
+                for (int k = 0; k < D; k++) c.out[k] = 0.0;
+                orc_walk(&v, tile, px, py, orc_emit_render, &c, NULL);
+                if (alpha) alpha[(int64_t)py * W + px] = c.asum;
+            }
+    }
+    orc_view_free(&v);
+    orc_scene_free(&sc);
+    return 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Structure of one view, for bit-exact comparison.  Call with ids == NULL to
+ * get P (returned); then with ids[P] and tile_start[TX*TY+1].  visible[n],
+ * depth[n], rect[n][4] = (x0,y0,x1,y1), rec32[n][6] = (ux,uy,A,B,C,opacity)
+ * are filled when non-NULL.  Returns P, or -1 on allocation failure.         */
+int64_t orc_view_structure(int64_t n, const float* mu, const float* s, const float* q,
+                           const float* op, const float* cam17, int W, int H, uint8_t* visible,
+                           uint32_t* depth, int32_t* rect, float* rec32, int64_t* tile_start,
+                           int32_t* ids)
+{
+    orc_scene sc;
+    orc_view v;
+    orc_cam cam = {cam17, W, H};
+    memset(&v, 0, sizeof(v));
+    if (orc_scene_init(&sc, n, mu, s, q, op) || orc_view_build(&sc, &cam, &v)) {
+        orc_scene_free(&sc); orc_view_free(&v);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        const orc_proj* g = v.g + i;
+        if (visible) visible[i] = (uint8_t)g->vis;
+        if (depth) depth[i] = g->depth;
+        if (rect) { rect[4 * i] = g->x0; rect[4 * i + 1] = g->y0; rect[4 * i + 2] = g->x1; rect[4 * i + 3] = g->y1; }
+        if (rec32) {
+            float* r = rec32 + 6 * i;
+            r[0] = g->ux; r[1] = g->uy; r[2] = g->A; r[3] = g->B; r[4] = g->C; r[5] = g->op;
+        }
+    }
+    int64_t nt = (int64_t)v.TX * v.TY;
+    if (tile_start) memcpy(tile_start, v.start, sizeof(int64_t) * (size_t)(nt + 1));
+    if (ids) memcpy(ids, v.ids, sizeof(int32_t) * (size_t)v.P);
+    int64_t P = v.P;
+    orc_view_free(&v);
+    orc_scene_free(&sc);
+    return P;
+}
+
+/* FP32 covariance of the S32 convention, [n][6] upper triangle. */
+void orc_covariance32(int64_t n, const float* s, const float* q, float* out)
+{
+    for (int64_t i = 0; i < n; i++) orc_cov32(s + 3 * i, q + 4 * i, out + 6 * i);
+}
+
+/* The S32 exponential, exposed for its own pins. */
+void orc_exp32_array(int64_t n, const float* x, float* y)
+{
+    for (int64_t i = 0; i < n; i++) y[i] = orc_exp32(x[i]);
+}
