@@ -1,0 +1,190 @@
+/*
+ * lv.h -- C ABI of the MI355X (gfx950) library for learning-free uplifting of
+ * 2D feature maps onto 3D Gaussian Splatting scenes and graph diffusion over
+ * the Gaussians (LUDVIG, arXiv 2410.14462).
+ *
+ * Method (paper references are to sections and equations):
+ *   Sec. 3.1, Eq. (1)  each pixel p of view d alpha-blends an ordered set of
+ *                      Gaussians; w_i(d,p) = alpha_i(d,p) prod_{j<i}(1-alpha_j).
+ *   Sec. 3.2, Eq. (3)  f_i = sum_{(d,p)} w_i(d,p) F_{d,p} / sum_{(d,p)} w_i(d,p).
+ *   Sec. 3.2, Eq. (5)  the same as f = diag(beta)^-1 W^T F; beta_i = sum w_i is
+ *                      also the Gaussian importance (Gaussian filtering).
+ *   Sec. 3.3, Eq. (8)  diffusion g_{t+1} = A g_t / ||g_t||_2.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - Gaussian i: mean mu (3 floats), per-axis scale s (linear, 3 floats),
+ *     rotation quaternion (w,x,y,z) (normalised by the library), opacity in
+ *     (0,1).  Covariance = R diag(s)^2 R^T.
+ *   - Camera: world->camera rotation R (row-major) and t, x_c = R x_w + t,
+ *     x right / y down / z forward; pinhole fx, fy, cx, cy in pixels; pixel
+ *     (i,j) covers [i,i+1) x [j,j+1) and is sampled at its centre.
+ *   - Gaussians with z_c <= znear are culled.  The 2D footprint is the EWA
+ *     projection (Jacobian with x/z, y/z clamped to 1.3 x the half-FoV
+ *     tangent) plus 0.3 px^2; alpha = min(0.99, opacity * exp(-d^T C d / 2));
+ *     a Gaussian with alpha < 1/255 at a pixel is skipped; a pixel stops at
+ *     the Gaussian that would take its transmittance below 1e-4 (that Gaussian
+ *     is not counted).  Each 16x16 tile walks the Gaussians whose tile
+ *     rectangle (radius ceil(3 sqrt(lambda_max))) covers it, sorted by the
+ *     FP32 bits of z_c, ties by Gaussian index.  Which Gaussians a pixel counts
+ *     is decided by a fixed sequence of FP32 operations, so it is reproducible
+ *     bit for bit on any IEEE-754 machine.
+ *   - Feature maps are HWC: view v is [height][width][D] contiguous.
+ *
+ * Memory: every pointer named "device" is HIP device memory (e.g. a torch
+ * tensor's data_ptr()).  Handles (lv_scene, lv_accum, lv_graph) are owned by
+ * the library; free them with the matching *_destroy.  Output buffers are
+ * owned by the caller.  Every call is asynchronous on the HIP stream passed
+ * as `stream` (hipStream_t; NULL = the null stream) unless stated otherwise;
+ * inputs must stay valid until the stream passes the call.
+ *
+ * Errors: every call returns an lv_status.  On a non-OK status nothing is
+ * enqueued and outputs are untouched; lv_last_error() describes the failure
+ * (thread-local).  No C++ exception crosses this interface.
+ *
+ * Threads: distinct handles may be used from different threads.  One handle
+ * must not be used by two threads at once.
+ */
+#ifndef LV_H
+#define LV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LV_OK = 0,
+    LV_ERR_INVALID_ARG = 1,
+    LV_ERR_OUT_OF_MEMORY = 2,
+    LV_ERR_DEVICE = 3,
+    LV_ERR_UNSUPPORTED = 4
+} lv_status;
+
+/* Storage type of feature maps / diffusion signals.  Arithmetic is FP32. */
+typedef enum {
+    LV_F32 = 0,
+    LV_BF16 = 1,       /* bfloat16, round-to-nearest-even                     */
+    LV_FP8_E4M3 = 2    /* OCP E4M3FN with a per-(view, channel) FP32 scale     */
+} lv_dtype;
+
+/* Pinhole camera, 80 bytes. */
+typedef struct lv_camera {
+    float R[9];        /* world->camera rotation, row-major                    */
+    float t[3];        /* x_c = R x_w + t                                      */
+    float fx, fy;      /* focal lengths in pixels                              */
+    float cx, cy;      /* principal point in pixels                            */
+    float znear;       /* Gaussians with z_c <= znear are culled               */
+    int32_t width;     /* image size in pixels, 1..16384                       */
+    int32_t height;
+    int32_t reserved;  /* must be 0                                            */
+} lv_camera;
+
+typedef struct lv_scene lv_scene;
+typedef struct lv_accum lv_accum;
+typedef struct lv_graph lv_graph;
+
+/* Thread-local description of the last non-OK status of this thread. */
+const char* lv_last_error(void);
+
+/* Library version string. */
+const char* lv_version(void);
+
+/* ---------------------------------------------------------------- scenes -- */
+/* Make a scene resident on the current device (Sec. 3.1 scene
+ * representation).  means [n][3], scales [n][3], quats [n][4] (w,x,y,z),
+ * opacity [n]: device FP32 arrays, read (not retained) by the call.  The
+ * library derives the covariances R diag(s)^2 R^T and keeps its own copy
+ * (48 bytes per Gaussian).  n = 0 is valid.  Errors: LV_ERR_INVALID_ARG
+ * (null pointers with n > 0, n >= 2^31), LV_ERR_OUT_OF_MEMORY. */
+lv_status lv_scene_create(const float* means, const float* scales, const float* quats,
+                          const float* opacity, int64_t n, void* stream, lv_scene** out);
+lv_status lv_scene_destroy(lv_scene* scene);
+int64_t lv_scene_size(const lv_scene* scene);
+
+/* --------------------------------------------------------------- uplift -- */
+/* Eq. (3) / Eq. (5): uplift m feature maps of D channels onto the scene.
+ *   cams      host array [m] of cameras.
+ *   maps      host array [m] of device pointers; maps[v] is [H_v][W_v][D] of
+ *             `dtype` (HWC, contiguous).
+ *   scales    LV_FP8_E4M3 only: device FP32 [m][D], the value of channel c of
+ *             view v is scales[v*D + c] * decode(byte); NULL otherwise.
+ *   out_feat  device FP32 [n][D]: f_i = U_i / beta_i, 0 where beta_i = 0.
+ *   out_wsum  device FP32 [n]: beta_i = sum over views and pixels of w_i
+ *             (nullable).
+ * D in [1, 4096]; m >= 0 (m = 0 writes zeros).  Views are processed in
+ * chunks; scratch is allocated by the library and cached in the scene.
+ * Errors: LV_ERR_INVALID_ARG (bad sizes, null maps, reserved != 0),
+ * LV_ERR_OUT_OF_MEMORY, LV_ERR_DEVICE. */
+lv_status lv_uplift(lv_scene* scene, const lv_camera* cams, int32_t m, const void* const* maps,
+                    lv_dtype dtype, const float* scales, int32_t D, float* out_feat,
+                    float* out_wsum, void* stream);
+
+/* Streaming form of lv_uplift: the accumulator holds U = W^T F [n][D] (FP32)
+ * and beta (compensated FP32 pair), to which views are added in any grouping
+ * (accumulating views [0,k) then [k,m) equals all m).  With
+ * LV_ACCUM_COUNTS it also counts, per Gaussian, the (view, pixel) pairs
+ * that contribute (exact integers). */
+#define LV_ACCUM_COUNTS 1u
+lv_status lv_accum_create(lv_scene* scene, int32_t D, uint32_t flags, void* stream, lv_accum** out);
+lv_status lv_accum_reset(lv_accum* acc, void* stream);
+lv_status lv_uplift_accumulate(lv_accum* acc, const lv_camera* cams, int32_t m,
+                               const void* const* maps, lv_dtype dtype, const float* scales,
+                               void* stream);
+/* f = U / beta (0 where beta = 0) into out_feat [n][D]; beta into out_wsum
+ * [n] (nullable); raw U into out_sum [n][D] (nullable). */
+lv_status lv_accum_finalize(lv_accum* acc, float* out_feat, float* out_wsum, float* out_sum,
+                            void* stream);
+/* Per-Gaussian contribution counts (device uint32 [n]); the accumulator must
+ * have been created with LV_ACCUM_COUNTS. */
+lv_status lv_accum_counts(lv_accum* acc, uint32_t* out_counts, void* stream);
+lv_status lv_accum_destroy(lv_accum* acc);
+
+/* ---------------------------------------------------------- storage codec -- */
+/* Encode one FP32 map src [pixels][D] (device) into dst (device) of dtype:
+ * LV_BF16 rounds to nearest even; LV_FP8_E4M3 computes, per channel,
+ * scale = absmax / 448 (1 where the channel is all zero) into scales [D]
+ * (device FP32) and stores the saturating round-to-nearest-even E4M3 code
+ * of x / scale.  LV_F32 copies. */
+lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,
+                    float* scales, void* stream);
+
+/* -------------------------------------------------------------- diffusion -- */
+/* Sec. 3.3: a graph A over the n Gaussians as CSR (row_ptr [n+1], col [nnz]
+ * int32, val [nnz] of val_dtype = LV_F32 or LV_BF16), device arrays copied by
+ * the call.  Columns must be in [0, n).  Errors: LV_ERR_INVALID_ARG. */
+lv_status lv_graph_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                              const void* val, lv_dtype val_dtype, void* stream, lv_graph** out);
+lv_status lv_graph_destroy(lv_graph* graph);
+
+/* Eq. (8): `steps` diffusion steps g_{t+1} = A (g_t / ||g_t||_2), each of the
+ * D channels normalised by its own norm (a zero-norm channel stays 0).
+ * g0 and out are device [n][D] of dtype (LV_F32 or LV_BF16; sums and norms
+ * are FP32).  out = g_steps (steps = 0 copies g0).  scene may be NULL; if
+ * given, its size must equal the graph's.  Scratch: 2 n D FP32 + 2 D FP32. */
+lv_status lv_diffuse(const lv_scene* scene, const lv_graph* graph, const void* g0, lv_dtype dtype,
+                     int32_t D, int32_t steps, void* out, void* stream);
+
+/* ------------------------------------------------------------ inspection -- */
+/* Per-view structure for verification; synchronous.  Host buffers (each
+ * nullable): visible [n], depth [n] (FP32 bits of z_c), rect [n][4]
+ * (x0,y0,x1,y1 tile rectangle), rec [n][6] (ux, uy, A, B, C, opacity with
+ * the exponent A dx^2 + B dx dy + C dy^2), tile_start [tiles+1] and ids
+ * [ids_capacity] (per tile, Gaussian indices in blending order).  *P_out
+ * receives the number of (tile, Gaussian) pairs; ids is filled only when
+ * ids_capacity >= P. */
+typedef struct lv_view_debug {
+    uint8_t* visible;
+    uint32_t* depth;
+    int32_t* rect;
+    float* rec;
+    int64_t* tile_start;
+    int32_t* ids;
+    int64_t ids_capacity;
+} lv_view_debug;
+lv_status lv_debug_view(lv_scene* scene, const lv_camera* cam, lv_view_debug* out, int64_t* P_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LV_H */

@@ -1,0 +1,292 @@
+"""Python binding of liblv.so, the gfx950 library for learning-free feature
+uplifting onto Gaussian Splatting scenes and graph diffusion (LUDVIG,
+arXiv 2410.14462).  Argument marshalling only: every step of the computation
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+current stream.  The names follow include/lv.h.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblv.so")
+
+LV_F32, LV_BF16, LV_FP8_E4M3 = 0, 1, 2
+LV_ACCUM_COUNTS = 1
+_DTYPES = {"f32": LV_F32, "bf16": LV_BF16, "fp8": LV_FP8_E4M3}
+
+
+class LvError(RuntimeError):
+    pass
+
+
+class lv_camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("znear", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class lv_view_debug(ctypes.Structure):
+    _fields_ = [("visible", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("rect", ctypes.c_void_p),
+                ("rec", ctypes.c_void_p), ("tile_start", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                ("ids_capacity", ctypes.c_int64)]
+
+
+assert ctypes.sizeof(lv_camera) == 80
+
+_lib = None
+
+
+def lib():
+    """Load liblv.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LvError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_14462_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        sig = {
+            "lv_last_error": ([], ctypes.c_char_p),
+            "lv_version": ([], ctypes.c_char_p),
+            "lv_scene_create": ([P, P, P, P, i64, P, ctypes.POINTER(P)], i32),
+            "lv_scene_destroy": ([P], i32),
+            "lv_scene_size": ([P], i64),
+            "lv_uplift": ([P, P, i32, P, i32, P, i32, P, P, P], i32),
+            "lv_accum_create": ([P, i32, u32, P, ctypes.POINTER(P)], i32),
+            "lv_accum_reset": ([P, P], i32),
+            "lv_uplift_accumulate": ([P, P, i32, P, i32, P, P], i32),
+            "lv_accum_finalize": ([P, P, P, P, P], i32),
+            "lv_accum_counts": ([P, P, P], i32),
+            "lv_accum_destroy": ([P], i32),
+            "lv_encode": ([P, i64, i32, i32, P, P, P], i32),
+            "lv_graph_create_csr": ([i64, i64, P, P, P, i32, P, ctypes.POINTER(P)], i32),
+            "lv_graph_destroy": ([P], i32),
+            "lv_diffuse": ([P, P, P, i32, i32, i32, P, P], i32),
+            "lv_debug_view": ([P, P, ctypes.POINTER(lv_view_debug), ctypes.POINTER(i64)], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["lv_last_error", "lv_version", "lv_scene_create", "lv_scene_destroy", "lv_scene_size",
+            "lv_uplift", "lv_accum_create", "lv_accum_reset", "lv_uplift_accumulate",
+            "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode",
+            "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view"]
+
+
+def _check(status):
+    if status != 0:
+        msg = lib().lv_last_error().decode(errors="replace")
+        raise LvError(f"lv status {status}: {msg}")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, shape=None):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise LvError("expected a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise LvError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+def camera_struct(cam):
+    c = lv_camera()
+    R = np.asarray(cam.R, np.float32).reshape(9)
+    t = np.asarray(cam.t, np.float32).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.znear = float(cam.znear)
+    c.width, c.height, c.reserved = int(cam.width), int(cam.height), 0
+    return c
+
+
+def camera_array(cams):
+    arr = (lv_camera * max(1, len(cams)))()
+    for i, cam in enumerate(cams):
+        arr[i] = camera_struct(cam)
+    return arr
+
+
+def _map_table(maps, dtype):
+    import torch
+    want = {LV_F32: (torch.float32,), LV_BF16: (torch.bfloat16,),
+            LV_FP8_E4M3: (torch.uint8, getattr(torch, "float8_e4m3fn", torch.uint8))}[dtype]
+    tab = (ctypes.c_void_p * max(1, len(maps)))()
+    for i, mp in enumerate(maps):
+        if not (mp.is_cuda and mp.is_contiguous() and mp.dtype in want):
+            raise LvError(f"map {i}: expected a contiguous CUDA tensor of {want}")
+        tab[i] = mp.data_ptr()
+    return tab
+
+
+class Scene:
+    """lv_scene: Gaussians resident on the GPU (means, scales, quats, opacity)."""
+
+    def __init__(self, means, scales, quats, opacity):
+        n = means.shape[0]
+        _dev_f32(means, (n, 3)); _dev_f32(scales, (n, 3)); _dev_f32(quats, (n, 4)); _dev_f32(opacity, (n,))
+        h = ctypes.c_void_p()
+        _check(lib().lv_scene_create(_ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), n,
+                                     _stream(), ctypes.byref(h)))
+        self.handle, self.n = h, n
+
+    @classmethod
+    def from_arrays(cls, scene, device="cuda"):
+        import torch
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
+        return cls(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacity))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lv_scene_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def uplift(self, cams, maps, dtype="f32", scales=None, out=None, wsum=None):
+        """Eq. (3): returns (f [n,D] f32, beta [n] f32)."""
+        import torch
+        dt = _DTYPES[dtype]
+        D = maps[0].shape[-1] if maps else (out.shape[1] if out is not None else 1)
+        if out is None:
+            out = torch.empty((self.n, D), device="cuda", dtype=torch.float32)
+        if wsum is None:
+            wsum = torch.empty((self.n,), device="cuda", dtype=torch.float32)
+        ca = camera_array(cams)
+        tab = _map_table(maps, dt)
+        _check(lib().lv_uplift(self.handle, ca, len(cams), tab, dt, _ptr(scales), D, _ptr(out),
+                               _ptr(wsum), _stream()))
+        return out, wsum
+
+    def debug_view(self, cam):
+        """Structure of one view (synchronous, host arrays)."""
+        n = self.n
+        TX, TY = -(-cam.width // 16), -(-cam.height // 16)
+        vis = np.zeros(n, np.uint8)
+        depth = np.zeros(n, np.uint32)
+        rect = np.zeros((n, 4), np.int32)
+        rec = np.zeros((n, 6), np.float32)
+        ts = np.zeros(TX * TY + 1, np.int64)
+        dbg = lv_view_debug(vis.ctypes.data, depth.ctypes.data, rect.ctypes.data, rec.ctypes.data,
+                            ts.ctypes.data, None, 0)
+        P = ctypes.c_int64()
+        c = camera_struct(cam)
+        _check(lib().lv_debug_view(self.handle, ctypes.byref(c), ctypes.byref(dbg), ctypes.byref(P)))
+        ids = np.zeros(max(1, P.value), np.int32)
+        dbg.ids, dbg.ids_capacity = ids.ctypes.data, P.value
+        _check(lib().lv_debug_view(self.handle, ctypes.byref(c), ctypes.byref(dbg), ctypes.byref(P)))
+        return dict(visible=vis.astype(bool), depth=depth, rect=rect, rec=rec, tile_start=ts,
+                    ids=ids[:P.value])
+
+
+class Accum:
+    """lv_accum: streaming accumulator U = W^T F, beta (and counts)."""
+
+    def __init__(self, scene, D, counts=False):
+        h = ctypes.c_void_p()
+        _check(lib().lv_accum_create(scene.handle, D, LV_ACCUM_COUNTS if counts else 0, _stream(),
+                                     ctypes.byref(h)))
+        self.handle, self.scene, self.D = h, scene, D
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lv_accum_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def reset(self):
+        _check(lib().lv_accum_reset(self.handle, _stream()))
+
+    def add(self, cams, maps, dtype="f32", scales=None):
+        dt = _DTYPES[dtype]
+        _check(lib().lv_uplift_accumulate(self.handle, camera_array(cams), len(cams),
+                                          _map_table(maps, dt), dt, _ptr(scales), _stream()))
+
+    def finalize(self, want_sum=False):
+        import torch
+        n = self.scene.n
+        f = torch.empty((n, self.D), device="cuda", dtype=torch.float32)
+        b = torch.empty((n,), device="cuda", dtype=torch.float32)
+        u = torch.empty((n, self.D), device="cuda", dtype=torch.float32) if want_sum else None
+        _check(lib().lv_accum_finalize(self.handle, _ptr(f), _ptr(b), _ptr(u), _stream()))
+        return (f, b, u) if want_sum else (f, b)
+
+    def counts(self):
+        import torch
+        c = torch.empty((self.scene.n,), device="cuda", dtype=torch.int32)
+        _check(lib().lv_accum_counts(self.handle, _ptr(c), _stream()))
+        return c
+
+
+def encode(src, dtype):
+    """Encode an FP32 map [..., D] to 'bf16' or 'fp8' (+ per-channel scales)."""
+    import torch
+    _dev_f32(src)
+    D = src.shape[-1]
+    pixels = src.numel() // D
+    dt = _DTYPES[dtype]
+    if dt == LV_BF16:
+        dst = torch.empty(src.shape, device="cuda", dtype=torch.bfloat16)
+        scales = None
+    elif dt == LV_FP8_E4M3:
+        dst = torch.empty(src.shape, device="cuda", dtype=torch.uint8)
+        scales = torch.empty((D,), device="cuda", dtype=torch.float32)
+    else:
+        dst = torch.empty_like(src)
+        scales = None
+    _check(lib().lv_encode(_ptr(src), pixels, D, dt, _ptr(dst), _ptr(scales), _stream()))
+    return dst, scales
+
+
+class Graph:
+    """lv_graph: CSR matrix over the Gaussians (int32 row_ptr/col, f32 or bf16 values)."""
+
+    def __init__(self, row_ptr, col, val):
+        import torch
+        n = row_ptr.shape[0] - 1
+        nnz = col.shape[0]
+        dt = LV_BF16 if val.dtype == torch.bfloat16 else LV_F32
+        if val.dtype not in (torch.float32, torch.bfloat16):
+            raise LvError("graph values must be float32 or bfloat16")
+        h = ctypes.c_void_p()
+        _check(lib().lv_graph_create_csr(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), dt, _stream(),
+                                         ctypes.byref(h)))
+        self.handle, self.n = h, n
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lv_graph_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def diffuse(self, g0, steps, scene=None, out=None):
+        """Eq. (8): g0 [n] or [n, D] (f32 or bf16) -> g_steps, same dtype and shape."""
+        import torch
+        dt = LV_BF16 if g0.dtype == torch.bfloat16 else LV_F32
+        D = 1 if g0.dim() == 1 else g0.shape[1]
+        if out is None:
+            out = torch.empty_like(g0)
+        _check(lib().lv_diffuse(scene.handle if scene is not None else None, self.handle, _ptr(g0),
+                                dt, D, steps, _ptr(out), _stream()))
+        return out

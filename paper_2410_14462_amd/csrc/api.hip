@@ -1,0 +1,604 @@
+// C ABI (include/lv.h): argument checking, scratch management and the order
+// of launches.  Per chunk of views the uplift runs
+//   preprocess -> depth sort -> count scan -> duplicate -> tile sort ->
+//   ranges -> blend-accumulate
+// with a single stream synchronisation (the number of (tile, Gaussian) pairs
+// sizes the pair buffers).  Scratch is cached per scene and only grows.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lv_internal.h"
+
+using namespace lv;
+
+namespace {
+
+thread_local std::string g_err;
+
+lv_status fail(lv_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      if (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation)                     \
+        return fail(LV_ERR_OUT_OF_MEMORY, "%s: %s", #expr, hipGetErrorString(e_));         \
+      return fail(LV_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));                  \
+    }                                                                                      \
+  } while (0)
+
+// Grow-only device buffer.
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes, hipStream_t s) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) {
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      cap = 0;
+    }
+    size_t want = bytes + bytes / 8 + 256;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct HostBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) cap = bytes;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+struct Workspace {
+  Buf rec, key0, val0, key1, val1, rect, cnt, off, scan_tmp, hist, seg, pseg, total;
+  Buf pk0, pv0, pk1, pv1, hist2, ranges, cams, geom, maps;
+  HostBuf up, down;
+  void release() {
+    Buf* all[] = {&rec, &key0, &val0, &key1, &val1, &rect, &cnt, &off, &scan_tmp, &hist, &seg,
+                  &pseg, &total, &pk0, &pv0, &pk1, &pv1, &hist2, &ranges, &cams, &geom, &maps};
+    for (Buf* b : all) b->release();
+    up.release();
+    down.release();
+  }
+};
+
+int64_t chunk_budget_bytes() {
+  const char* e = getenv("LV_CHUNK_BYTES");
+  if (e) {
+    long long v = atoll(e);
+    if (v > 0) return v;
+  }
+  return (int64_t)4 << 30;
+}
+
+}  // namespace
+
+struct lv_scene {
+  int64_t n = 0;
+  int device = 0;
+  Buf p0, p1, p2;
+  Workspace ws;
+};
+
+struct lv_accum {
+  lv_scene* scene = nullptr;
+  int32_t D = 0;
+  uint32_t flags = 0;
+  Buf U, beta, counts;
+};
+
+struct lv_graph {
+  int64_t n = 0, nnz = 0;
+  lv_dtype val_dtype = LV_F32;
+  Buf row_ptr, col, val, b0, b1, norms;
+};
+
+namespace {
+
+size_t dtype_size(lv_dtype d) { return d == LV_F32 ? 4 : d == LV_BF16 ? 2 : 1; }
+
+lv_status check_cams(const lv_camera* cams, int32_t m) {
+  if (m < 0) return fail(LV_ERR_INVALID_ARG, "m = %d < 0", m);
+  if (m > 0 && !cams) return fail(LV_ERR_INVALID_ARG, "cams is NULL");
+  for (int v = 0; v < m; v++) {
+    const lv_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+      return fail(LV_ERR_INVALID_ARG, "camera %d: size %dx%d out of [1,16384]", v, c.width, c.height);
+    if (c.reserved != 0) return fail(LV_ERR_INVALID_ARG, "camera %d: reserved must be 0", v);
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f))
+      return fail(LV_ERR_INVALID_ARG, "camera %d: focal lengths must be > 0", v);
+  }
+  return LV_OK;
+}
+
+int ceil_log2(int64_t x) {
+  int b = 0;
+  while (((int64_t)1 << b) < x) b++;
+  return b;
+}
+
+// Structure of one chunk of views: everything up to the tile ranges.  On
+// return, the sorted pair values (Gaussian ids) are in *ids, the ranges in
+// ws.ranges with row stride *stride, and the pair count in *P.
+lv_status build_structure(lv_scene* sc, const lv_camera* cams, int mv, hipStream_t s,
+                          const uint32_t** ids, const uint32_t** pkeys, int* stride, int64_t* P,
+                          int* max_tiles_out) {
+  Workspace& ws = sc->ws;
+  const int64_t n = sc->n;
+  const int64_t items = n * (int64_t)mv;
+  std::vector<ViewGeom> geom(mv);
+  int max_tiles = 0;
+  for (int v = 0; v < mv; v++) {
+    geom[v].W = cams[v].width;
+    geom[v].H = cams[v].height;
+    geom[v].TX = (cams[v].width + kTile - 1) / kTile;
+    geom[v].TY = (cams[v].height + kTile - 1) / kTile;
+    max_tiles = std::max(max_tiles, geom[v].TX * geom[v].TY);
+  }
+  *max_tiles_out = max_tiles;
+  *stride = max_tiles;
+  HIP_TRY(ws.rec.ensure(sizeof(Rec) * items, s));
+  HIP_TRY(ws.key0.ensure(4 * items, s));
+  HIP_TRY(ws.val0.ensure(4 * items, s));
+  HIP_TRY(ws.key1.ensure(4 * items, s));
+  HIP_TRY(ws.val1.ensure(4 * items, s));
+  HIP_TRY(ws.rect.ensure(8 * items, s));
+  HIP_TRY(ws.cnt.ensure(4 * items, s));
+  HIP_TRY(ws.off.ensure(4 * items, s));
+  HIP_TRY(ws.scan_tmp.ensure(4 * scan_tmp_size(items), s));
+  HIP_TRY(ws.hist.ensure(4 * sort_hist_size(mv, n), s));
+  HIP_TRY(ws.seg.ensure(8 * (size_t)mv, s));
+  HIP_TRY(ws.pseg.ensure(8 * (size_t)mv, s));
+  HIP_TRY(ws.total.ensure(16, s));
+  HIP_TRY(ws.cams.ensure(sizeof(Cam) * mv, s));
+  HIP_TRY(ws.geom.ensure(sizeof(ViewGeom) * mv, s));
+  HIP_TRY(ws.ranges.ensure(sizeof(uint2) * (size_t)mv * max_tiles, s));
+  size_t up_bytes = sizeof(Cam) * mv + sizeof(ViewGeom) * mv + 8 * (size_t)mv;
+  size_t down_bytes = 4 * ((size_t)mv + 4);
+  // the pinned staging buffers may still feed an earlier upload on this stream
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(ws.up.ensure(up_bytes));
+  HIP_TRY(ws.down.ensure(down_bytes));
+  char* up = static_cast<char*>(ws.up.p);
+  memcpy(up, cams, sizeof(Cam) * mv);
+  memcpy(up + sizeof(Cam) * mv, geom.data(), sizeof(ViewGeom) * mv);
+  uint32_t* segh = reinterpret_cast<uint32_t*>(up + sizeof(Cam) * mv + sizeof(ViewGeom) * mv);
+  for (int v = 0; v < mv; v++) {
+    segh[v] = (uint32_t)(v * n);
+    segh[mv + v] = (uint32_t)n;
+  }
+  HIP_TRY(hipMemcpyAsync(ws.cams.p, up, sizeof(Cam) * mv, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ws.geom.p, up + sizeof(Cam) * mv, sizeof(ViewGeom) * mv,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ws.seg.p, segh, 8 * (size_t)mv, hipMemcpyHostToDevice, s));
+
+  HIP_TRY(launch_preprocess(sc->p0.as<float4>(), sc->p1.as<float4>(), sc->p2.as<float4>(), n,
+                            ws.cams.as<Cam>(), ws.geom.as<ViewGeom>(), mv, ws.rec.as<Rec>(),
+                            ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.rect.as<uint2>(),
+                            ws.cnt.as<uint32_t>(), s));
+  bool second = false;
+  const uint32_t* seg = ws.seg.as<uint32_t>();
+  HIP_TRY(radix_sort(ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.key1.as<uint32_t>(),
+                     ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, 32, ws.hist.as<uint32_t>(),
+                     &second, s));
+  const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
+  uint32_t* pseg = ws.pseg.as<uint32_t>();
+  HIP_TRY(scan_counts(ws.cnt.as<uint32_t>(), sval, n, mv, ws.off.as<uint32_t>(), pseg, pseg + mv,
+                      ws.total.as<uint32_t>(), ws.scan_tmp.as<uint32_t>(), s));
+  uint32_t* down = static_cast<uint32_t*>(ws.down.p);
+  HIP_TRY(hipMemcpyAsync(down, ws.total.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(down + 4, pseg + mv, 4 * (size_t)mv, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  uint64_t total = down[0];
+  if (total >= 0x80000000ull)
+    return fail(LV_ERR_UNSUPPORTED, "%llu (tile, Gaussian) pairs in one chunk (limit 2^31)",
+                (unsigned long long)total);
+  int64_t max_len = 0;
+  for (int v = 0; v < mv; v++) max_len = std::max<int64_t>(max_len, down[4 + v]);
+  *P = (int64_t)total;
+  HIP_TRY(ws.pk0.ensure(4 * total + 4, s));
+  HIP_TRY(ws.pv0.ensure(4 * total + 4, s));
+  HIP_TRY(ws.pk1.ensure(4 * total + 4, s));
+  HIP_TRY(ws.pv1.ensure(4 * total + 4, s));
+  HIP_TRY(ws.hist2.ensure(4 * sort_hist_size(mv, max_len), s));
+  HIP_TRY(launch_duplicate(sval, ws.off.as<uint32_t>(), ws.rect.as<uint2>(), ws.cnt.as<uint32_t>(),
+                           ws.geom.as<ViewGeom>(), n, mv, ws.pk0.as<uint32_t>(),
+                           ws.pv0.as<uint32_t>(), s));
+  int tile_bits = ceil_log2(max_tiles);
+  HIP_TRY(radix_sort(ws.pk0.as<uint32_t>(), ws.pv0.as<uint32_t>(), ws.pk1.as<uint32_t>(),
+                     ws.pv1.as<uint32_t>(), pseg, pseg + mv, mv, max_len, tile_bits,
+                     ws.hist2.as<uint32_t>(), &second, s));
+  const uint32_t* pk = second ? ws.pk1.as<uint32_t>() : ws.pk0.as<uint32_t>();
+  *ids = second ? ws.pv1.as<uint32_t>() : ws.pv0.as<uint32_t>();
+  *pkeys = pk;
+  HIP_TRY(hipMemsetAsync(ws.ranges.p, 0, sizeof(uint2) * (size_t)mv * max_tiles, s));
+  HIP_TRY(launch_ranges(pk, (int64_t)total, max_tiles, ws.ranges.as<uint2>(), s));
+  return LV_OK;
+}
+
+lv_status check_maps(const void* const* maps, int32_t m, lv_dtype dtype, const float* scales) {
+  if (dtype != LV_F32 && dtype != LV_BF16 && dtype != LV_FP8_E4M3)
+    return fail(LV_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+  if (m > 0 && !maps) return fail(LV_ERR_INVALID_ARG, "maps is NULL");
+  for (int v = 0; v < m; v++)
+    if (!maps[v]) return fail(LV_ERR_INVALID_ARG, "maps[%d] is NULL", v);
+  if (dtype == LV_FP8_E4M3 && m > 0 && !scales)
+    return fail(LV_ERR_INVALID_ARG, "FP8 maps need scales");
+  return LV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lv_last_error(void) { return g_err.c_str(); }
+
+const char* lv_version(void) { return "lv 0.1 gfx950"; }
+
+lv_status lv_scene_create(const float* means, const float* scales, const float* quats,
+                          const float* opacity, int64_t n, void* stream, lv_scene** out) {
+  if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n > 0 && (!means || !scales || !quats || !opacity))
+    return fail(LV_ERR_INVALID_ARG, "null scene array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv_scene* sc = new (std::nothrow) lv_scene();
+  if (!sc) return fail(LV_ERR_OUT_OF_MEMORY, "host allocation");
+  sc->n = n;
+  (void)hipGetDevice(&sc->device);
+  size_t b = sizeof(float4) * (size_t)(n > 0 ? n : 1);
+  hipError_t e = sc->p0.ensure(b, s);
+  if (e == hipSuccess) e = sc->p1.ensure(b, s);
+  if (e == hipSuccess) e = sc->p2.ensure(b, s);
+  if (e == hipSuccess)
+    e = launch_scene_derive(means, scales, quats, opacity, n, sc->p0.as<float4>(), sc->p1.as<float4>(),
+                            sc->p2.as<float4>(), s);
+  if (e != hipSuccess) {
+    sc->p0.release(); sc->p1.release(); sc->p2.release();
+    delete sc;
+    return fail(e == hipErrorOutOfMemory ? LV_ERR_OUT_OF_MEMORY : LV_ERR_DEVICE, "scene: %s",
+                hipGetErrorString(e));
+  }
+  *out = sc;
+  return LV_OK;
+}
+
+lv_status lv_scene_destroy(lv_scene* sc) {
+  if (!sc) return LV_OK;
+  (void)hipDeviceSynchronize();
+  sc->p0.release(); sc->p1.release(); sc->p2.release();
+  sc->ws.release();
+  delete sc;
+  return LV_OK;
+}
+
+int64_t lv_scene_size(const lv_scene* sc) { return sc ? sc->n : -1; }
+
+lv_status lv_accum_create(lv_scene* sc, int32_t D, uint32_t flags, void* stream, lv_accum** out) {
+  if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sc) return fail(LV_ERR_INVALID_ARG, "scene is NULL");
+  if (D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "D = %d out of [1, 4096]", D);
+  if (flags & ~LV_ACCUM_COUNTS) return fail(LV_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv_accum* a = new (std::nothrow) lv_accum();
+  if (!a) return fail(LV_ERR_OUT_OF_MEMORY, "host allocation");
+  a->scene = sc;
+  a->D = D;
+  a->flags = flags;
+  size_t n1 = (size_t)(sc->n > 0 ? sc->n : 1);
+  hipError_t e = a->U.ensure(sizeof(float) * n1 * D, s);
+  if (e == hipSuccess) e = a->beta.ensure(sizeof(float2) * n1, s);
+  if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->counts.ensure(4 * n1, s);
+  if (e != hipSuccess) {
+    a->U.release(); a->beta.release(); a->counts.release();
+    delete a;
+    return fail(LV_ERR_OUT_OF_MEMORY, "accumulator: %s", hipGetErrorString(e));
+  }
+  lv_status st = lv_accum_reset(a, stream);
+  if (st != LV_OK) {
+    lv_accum_destroy(a);
+    return st;
+  }
+  *out = a;
+  return LV_OK;
+}
+
+lv_status lv_accum_reset(lv_accum* a, void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  size_t n = (size_t)a->scene->n;
+  if (n == 0) return LV_OK;
+  HIP_TRY(hipMemsetAsync(a->U.p, 0, sizeof(float) * n * a->D, s));
+  HIP_TRY(hipMemsetAsync(a->beta.p, 0, sizeof(float2) * n, s));
+  if (a->counts.p) HIP_TRY(hipMemsetAsync(a->counts.p, 0, 4 * n, s));
+  return LV_OK;
+}
+
+lv_status lv_accum_destroy(lv_accum* a) {
+  if (!a) return LV_OK;
+  (void)hipDeviceSynchronize();
+  a->U.release(); a->beta.release(); a->counts.release();
+  delete a;
+  return LV_OK;
+}
+
+lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, const void* const* maps,
+                               lv_dtype dtype, const float* scales, void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  lv_status st = check_cams(cams, m);
+  if (st != LV_OK) return st;
+  st = check_maps(maps, m, dtype, scales);
+  if (st != LV_OK) return st;
+  lv_scene* sc = a->scene;
+  const int64_t n = sc->n;
+  if (n == 0 || m == 0) return LV_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t per_view = n * (int64_t)(sizeof(Rec) + 7 * 4 + 8);
+  int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
+  mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
+  for (int v0 = 0; v0 < m; v0 += (int)mc) {
+    int mv = (int)std::min<int64_t>(mc, m - v0);
+    const uint32_t* ids = nullptr;
+    const uint32_t* pkeys = nullptr;
+    int stride = 0, max_tiles = 0;
+    int64_t P = 0;
+    st = build_structure(sc, cams + v0, mv, s, &ids, &pkeys, &stride, &P, &max_tiles);
+    if (st != LV_OK) return st;
+    Workspace& ws = sc->ws;
+    HIP_TRY(ws.maps.ensure(sizeof(void*) * mv, s));
+    // ws.up was synchronised inside build_structure; reuse it for the map table
+    HIP_TRY(ws.up.ensure(sizeof(void*) * mv));
+    memcpy(ws.up.p, maps + v0, sizeof(void*) * mv);
+    HIP_TRY(hipMemcpyAsync(ws.maps.p, ws.up.p, sizeof(void*) * mv, hipMemcpyHostToDevice, s));
+    BlendArgs ba;
+    ba.rec = ws.rec.as<Rec>();
+    ba.ids = ids;
+    ba.ranges = ws.ranges.as<uint2>();
+    ba.geom = ws.geom.as<ViewGeom>();
+    ba.maps = ws.maps.as<const void*>();
+    ba.fp8_scales = scales;
+    ba.view_base = v0;
+    ba.n = n;
+    ba.D = a->D;
+    ba.tiles_stride = stride;
+    ba.U = a->U.as<float>();
+    ba.beta = a->beta.as<float2>();
+    ba.counts = a->counts.as<uint32_t>();
+    HIP_TRY(launch_blend(ba, dtype, mv, max_tiles, s));
+    if (v0 + mc < m) HIP_TRY(hipStreamSynchronize(s));  // staging buffers are reused
+  }
+  return LV_OK;
+}
+
+lv_status lv_accum_finalize(lv_accum* a, float* out_feat, float* out_wsum, float* out_sum,
+                            void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  if (a->scene->n > 0 && !out_feat && !out_wsum && !out_sum)
+    return fail(LV_ERR_INVALID_ARG, "no output requested");
+  HIP_TRY(launch_finalize(a->U.as<float>(), a->beta.as<float2>(), a->scene->n, a->D, out_feat,
+                          out_wsum, out_sum, static_cast<hipStream_t>(stream)));
+  return LV_OK;
+}
+
+lv_status lv_accum_counts(lv_accum* a, uint32_t* out, void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");
+  if (!out && a->scene->n > 0) return fail(LV_ERR_INVALID_ARG, "out is NULL");
+  if (a->scene->n == 0) return LV_OK;
+  HIP_TRY(hipMemcpyAsync(out, a->counts.p, 4 * (size_t)a->scene->n, hipMemcpyDeviceToDevice,
+                         static_cast<hipStream_t>(stream)));
+  return LV_OK;
+}
+
+lv_status lv_uplift(lv_scene* sc, const lv_camera* cams, int32_t m, const void* const* maps,
+                    lv_dtype dtype, const float* scales, int32_t D, float* out_feat,
+                    float* out_wsum, void* stream) {
+  if (!sc) return fail(LV_ERR_INVALID_ARG, "scene is NULL");
+  if (D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "D = %d out of [1, 4096]", D);
+  if (sc->n > 0 && !out_feat) return fail(LV_ERR_INVALID_ARG, "out_feat is NULL");
+  lv_status st = check_cams(cams, m);
+  if (st != LV_OK) return st;
+  st = check_maps(maps, m, dtype, scales);
+  if (st != LV_OK) return st;
+  lv_accum* a = nullptr;
+  st = lv_accum_create(sc, D, 0, stream, &a);
+  if (st != LV_OK) return st;
+  st = lv_uplift_accumulate(a, cams, m, maps, dtype, scales, stream);
+  if (st == LV_OK) st = lv_accum_finalize(a, out_feat, out_wsum, nullptr, stream);
+  (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  lv_accum_destroy(a);
+  return st;
+}
+
+lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,
+                    float* scales, void* stream) {
+  if (pixels < 0 || D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "bad size");
+  if (pixels > 0 && (!src || !dst)) return fail(LV_ERR_INVALID_ARG, "null buffer");
+  if (dtype == LV_FP8_E4M3 && !scales) return fail(LV_ERR_INVALID_ARG, "FP8 needs scales");
+  if (dtype != LV_F32 && dtype != LV_BF16 && dtype != LV_FP8_E4M3)
+    return fail(LV_ERR_INVALID_ARG, "unknown dtype");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  static thread_local Buf tmp;
+  if (dtype == LV_FP8_E4M3) HIP_TRY(tmp.ensure(4 * (size_t)D, s));
+  HIP_TRY(launch_encode(src, pixels, D, dtype, dst, scales, tmp.as<float>(), s));
+  return LV_OK;
+}
+
+lv_status lv_graph_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                              const void* val, lv_dtype val_dtype, void* stream, lv_graph** out) {
+  if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || nnz < 0 || n >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 31))
+    return fail(LV_ERR_INVALID_ARG, "graph size out of range");
+  if (val_dtype != LV_F32 && val_dtype != LV_BF16)
+    return fail(LV_ERR_INVALID_ARG, "graph values must be LV_F32 or LV_BF16");
+  if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(LV_ERR_INVALID_ARG, "null CSR array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // validate the CSR on the host (row_ptr monotone, columns in range)
+  std::vector<int32_t> rp(n + 1);
+  std::vector<int32_t> cl(nnz);
+  HIP_TRY(hipMemcpyAsync(rp.data(), row_ptr, 4 * (size_t)(n + 1), hipMemcpyDeviceToHost, s));
+  if (nnz) HIP_TRY(hipMemcpyAsync(cl.data(), col, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (rp[0] != 0 || rp[n] != nnz) return fail(LV_ERR_INVALID_ARG, "row_ptr must run from 0 to nnz");
+  for (int64_t i = 0; i < n; i++)
+    if (rp[i + 1] < rp[i]) return fail(LV_ERR_INVALID_ARG, "row_ptr decreases at row %lld", (long long)i);
+  for (int64_t k = 0; k < nnz; k++)
+    if (cl[k] < 0 || cl[k] >= n) return fail(LV_ERR_INVALID_ARG, "column %lld out of range", (long long)k);
+  lv_graph* g = new (std::nothrow) lv_graph();
+  if (!g) return fail(LV_ERR_OUT_OF_MEMORY, "host allocation");
+  g->n = n;
+  g->nnz = nnz;
+  g->val_dtype = val_dtype;
+  hipError_t e = g->row_ptr.ensure(4 * (size_t)(n + 1), s);
+  if (e == hipSuccess) e = g->col.ensure(4 * (size_t)(nnz + 1), s);
+  if (e == hipSuccess) e = g->val.ensure(dtype_size(val_dtype) * (size_t)(nnz + 1), s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->row_ptr.p, row_ptr, 4 * (size_t)(n + 1), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && nnz) e = hipMemcpyAsync(g->col.p, col, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && nnz)
+    e = hipMemcpyAsync(g->val.p, val, dtype_size(val_dtype) * (size_t)nnz, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    g->row_ptr.release(); g->col.release(); g->val.release();
+    delete g;
+    return fail(LV_ERR_DEVICE, "graph: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return LV_OK;
+}
+
+lv_status lv_graph_destroy(lv_graph* g) {
+  if (!g) return LV_OK;
+  (void)hipDeviceSynchronize();
+  g->row_ptr.release(); g->col.release(); g->val.release();
+  g->b0.release(); g->b1.release(); g->norms.release();
+  delete g;
+  return LV_OK;
+}
+
+lv_status lv_diffuse(const lv_scene* sc, const lv_graph* gc, const void* g0, lv_dtype dtype, int32_t D,
+                     int32_t steps, void* out, void* stream) {
+  if (!gc) return fail(LV_ERR_INVALID_ARG, "graph is NULL");
+  if (sc && sc->n != gc->n) return fail(LV_ERR_INVALID_ARG, "scene and graph sizes differ");
+  if (D < 1 || D > 4096 || steps < 0) return fail(LV_ERR_INVALID_ARG, "bad D or steps");
+  if (dtype != LV_F32 && dtype != LV_BF16) return fail(LV_ERR_INVALID_ARG, "dtype must be F32 or BF16");
+  if (gc->n > 0 && (!g0 || !out)) return fail(LV_ERR_INVALID_ARG, "null signal buffer");
+  if (g0 == out && steps > 0) return fail(LV_ERR_INVALID_ARG, "out must not alias g0");
+  lv_graph* g = const_cast<lv_graph*>(gc);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  size_t sig = dtype_size(dtype) * (size_t)(g->n > 0 ? g->n : 1) * D;
+  HIP_TRY(g->b0.ensure(sig, s));
+  HIP_TRY(g->b1.ensure(sig, s));
+  HIP_TRY(g->norms.ensure(sizeof(float) * (size_t)D * (steps + 1), s));
+  HIP_TRY(launch_diffuse(g->row_ptr.as<int32_t>(), g->col.as<int32_t>(), g->val.p, g->val_dtype, g->n,
+                         g0, dtype, D, steps, out, g->b0.as<float>(), g->b1.as<float>(),
+                         g->norms.as<float>(), s));
+  return LV_OK;
+}
+
+lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, int64_t* P_out) {
+  if (!sc || !cam || !out) return fail(LV_ERR_INVALID_ARG, "null argument");
+  lv_status st = check_cams(cam, 1);
+  if (st != LV_OK) return st;
+  const int64_t n = sc->n;
+  hipStream_t s = nullptr;
+  if (n == 0) {
+    if (P_out) *P_out = 0;
+    return LV_OK;
+  }
+  const uint32_t *ids = nullptr, *pkeys = nullptr;
+  int stride = 0, max_tiles = 0;
+  int64_t P = 0;
+  st = build_structure(sc, cam, 1, s, &ids, &pkeys, &stride, &P, &max_tiles);
+  if (st != LV_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  Workspace& ws = sc->ws;
+  if (P_out) *P_out = P;
+  std::vector<uint32_t> key(n);
+  std::vector<Rec> rec(n);
+  std::vector<uint2> rect(n);
+  std::vector<uint32_t> cnt(n);
+  HIP_TRY(hipMemcpy(rec.data(), ws.rec.p, sizeof(Rec) * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(rect.data(), ws.rect.p, 8 * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(cnt.data(), ws.cnt.p, 4 * n, hipMemcpyDeviceToHost));
+  // depth keys in Gaussian order: the depth sort (4 passes) left the sorted
+  // (key, id) pairs in key0/val0; scatter them back by id
+  std::vector<uint32_t> sk(n), sv(n);
+  HIP_TRY(hipMemcpy(sk.data(), ws.key0.p, 4 * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sv.data(), ws.val0.p, 4 * n, hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < n; k++) key[sv[k]] = sk[k];
+  for (int64_t i = 0; i < n; i++) {
+    bool vis = cnt[i] != 0;
+    if (out->visible) out->visible[i] = vis ? 1 : 0;
+    if (out->depth) out->depth[i] = key[i];
+    if (out->rect) {
+      out->rect[4 * i] = (int32_t)(rect[i].x & 0xFFFF);
+      out->rect[4 * i + 1] = (int32_t)(rect[i].x >> 16);
+      out->rect[4 * i + 2] = (int32_t)(rect[i].y & 0xFFFF);
+      out->rect[4 * i + 3] = (int32_t)(rect[i].y >> 16);
+    }
+    if (out->rec) {
+      float* r = out->rec + 6 * i;
+      r[0] = rec[i].r0.x; r[1] = rec[i].r0.y; r[2] = rec[i].r0.z; r[3] = rec[i].r0.w;
+      r[4] = rec[i].r1.x; r[5] = rec[i].r1.y;
+    }
+  }
+  if (out->tile_start) {
+    std::vector<uint2> rg(max_tiles);
+    HIP_TRY(hipMemcpy(rg.data(), ws.ranges.p, sizeof(uint2) * max_tiles, hipMemcpyDeviceToHost));
+    int64_t run = 0;
+    for (int t = 0; t < max_tiles; t++) {
+      out->tile_start[t] = run;
+      if (rg[t].y > rg[t].x) run += rg[t].y - rg[t].x;
+    }
+    out->tile_start[max_tiles] = run;
+  }
+  if (out->ids && out->ids_capacity >= P && P > 0)
+    HIP_TRY(hipMemcpy(out->ids, ids, 4 * (size_t)P, hipMemcpyDeviceToHost));
+  return LV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Feature-map storage codec: FP32 -> BF16 (round to nearest even) and
+// FP32 -> OCP FP8 E4M3FN with one FP32 scale per channel
+// (scale = absmax / 448, 1 for an all-zero channel; code = saturating
+// round-to-nearest-even of x / scale).  Decoding happens inside the blend
+// kernel's tile staging.
+#include "lv_internal.h"
+
+namespace lv {
+
+namespace {
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint8_t to_e4m3(float x) {
+  uint32_t u = __float_as_uint(x);
+  uint32_t sign = (u >> 24) & 0x80u;
+  float ax = fabsf(x);
+  uint32_t code;
+  if (!(ax < 448.0f)) {
+    code = 0x7Eu;                                   // saturate (also +inf)
+  } else if (ax < 0x1.0p-6f) {
+    code = (uint32_t)rintf(ax * 0x1.0p9f);          // subnormal quantum 2^-9; 8 -> min normal
+  } else {
+    uint32_t a = __float_as_uint(ax);
+    a += 0x7FFFFu + ((a >> 20) & 1u);               // round to 3 mantissa bits, ties to even
+    a &= ~0xFFFFFu;
+    int e = (int)(a >> 23) - 127;
+    uint32_t mt = (a >> 20) & 7u;
+    if (e > 8 || (e == 8 && mt > 6u)) code = 0x7Eu;
+    else code = ((uint32_t)(e + 7) << 3) | mt;
+  }
+  return (uint8_t)(sign | code);
+}
+
+__global__ void encode_bf16_kernel(const float* __restrict__ src, int64_t total,
+                                   uint16_t* __restrict__ dst) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < total) dst[e] = to_bf16(src[e]);
+}
+
+// Per-channel absmax: block = 4 waves over a pixel range, lane = channel.
+__global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ src, int64_t pixels,
+                                                     int D, int rows_per_block,
+                                                     uint32_t* __restrict__ amax) {
+  __shared__ float part[4][64];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int c = blockIdx.y * 64 + lane;
+  int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
+  int64_t p1 = p0 + rows_per_block < pixels ? p0 + rows_per_block : pixels;
+  float m = 0.0f;
+  if (c < D)
+    for (int64_t p = p0 + w; p < p1; p += 4) m = fmaxf(m, fabsf(src[p * D + c]));
+  part[w][lane] = m;
+  __syncthreads();
+  if (w == 0 && c < D) {
+    m = fmaxf(fmaxf(part[0][lane], part[1][lane]), fmaxf(part[2][lane], part[3][lane]));
+    atomicMax(&amax[c], __float_as_uint(m));
+  }
+}
+
+__global__ void scale_kernel(const uint32_t* __restrict__ amax, int D, float* __restrict__ scales) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D) return;
+  float a = __uint_as_float(amax[c]);
+  scales[c] = a > 0.0f ? a / 448.0f : 1.0f;
+}
+
+__global__ void encode_fp8_kernel(const float* __restrict__ src, int64_t total, int D,
+                                  const float* __restrict__ scales, uint8_t* __restrict__ dst) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < total) dst[e] = to_e4m3(src[e] / scales[e % D]);
+}
+
+}  // namespace
+
+hipError_t launch_encode(const float* src, int64_t pixels, int D, lv_dtype dtype, void* dst,
+                         float* scales, float* tmp_absmax, hipStream_t s) {
+  int64_t total = pixels * (int64_t)D;
+  if (total == 0) return hipSuccess;
+  unsigned nb = (unsigned)((total + 255) / 256);
+  if (dtype == LV_F32) {
+    return hipMemcpyAsync(dst, src, (size_t)total * sizeof(float), hipMemcpyDeviceToDevice, s);
+  }
+  if (dtype == LV_BF16) {
+    hipLaunchKernelGGL(encode_bf16_kernel, dim3(nb), dim3(256), 0, s, src, total,
+                       static_cast<uint16_t*>(dst));
+    return hipGetLastError();
+  }
+  uint32_t* amax = reinterpret_cast<uint32_t*>(tmp_absmax);
+  hipError_t e = hipMemsetAsync(amax, 0, sizeof(uint32_t) * (size_t)D, s);
+  if (e != hipSuccess) return e;
+  int rows = 512;
+  hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)((pixels + rows - 1) / rows), (D + 63) / 64),
+                     dim3(256), 0, s, src, pixels, D, rows, amax);
+  hipLaunchKernelGGL(scale_kernel, dim3((D + 255) / 256), dim3(256), 0, s, amax, D, scales);
+  hipLaunchKernelGGL(encode_fp8_kernel, dim3(nb), dim3(256), 0, s, src, total, D, scales,
+                     static_cast<uint8_t*>(dst));
+  return hipGetLastError();
+}
+
+}  // namespace lv

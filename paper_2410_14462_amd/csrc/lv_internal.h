@@ -1,0 +1,150 @@
+// Internal declarations of the gfx950 uplifting library.  Device code is
+// compiled with -ffp-contract=off: every FP32 expression below is evaluated
+// exactly as written (explicit fmaf where an FMA is meant), which keeps the
+// structure and the blend decisions reproducible bit for bit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lv.h"
+
+namespace lv {
+
+constexpr int kTile = 16;           // tile edge in pixels
+constexpr int kBlendThreads = 256;  // one thread per pixel of a tile
+constexpr int kChunk = 32;          // Gaussians staged per blend step
+constexpr int kSortItems = 2048;    // items per radix-sort block
+constexpr int kSortThreads = 256;
+constexpr int kViewShift = 20;      // pair key = view << 20 | tile
+
+// Method constants as FP32 literals (0.99f, 1/255.f, 1e-4f, 0.3f, 1.3f).
+constexpr float kAlphaMax = 0x1.fae148p-1f;
+constexpr float kAlphaMin = 0x1.010102p-8f;
+constexpr float kTEps = 0x1.a36e2ep-14f;
+constexpr float kDilate = 0x1.333334p-2f;
+constexpr float kClamp = 0x1.4cccccp+0f;
+
+// Camera as the kernels see it (same field order as lv_camera).
+struct Cam {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, znear;
+  int32_t width, height, reserved;
+};
+static_assert(sizeof(Cam) == sizeof(lv_camera), "camera layout");
+
+// Per (view, Gaussian) projected record, 32 bytes:
+//   r0 = (ux, uy, A, B), r1 = (C, opacity, hx, hy)
+// power(d) = A dx^2 + B dx dy + C dy^2 (<= 0); hx, hy bound the pixels where
+// alpha can reach 1/255 (conservative, used only to skip work).
+struct Rec {
+  float4 r0, r1;
+};
+
+// S32 exponential for x <= 0: Cody-Waite reduction to |r| <= ln2/2, degree-7
+// Taylor polynomial in Horner form with fmaf, scaling by 2^k; 0 below -80.
+__device__ __forceinline__ float exp32(float x) {
+  if (x < -80.0f) return 0.0f;
+  float kf = rintf(x * 0x1.715476p+0f);
+  float r = __builtin_fmaf(kf, -0x1.62e4p-1f, x);
+  r = __builtin_fmaf(kf, -0x1.7f7d1cp-20f, r);
+  float p = 0x1.a01a02p-13f;
+  p = __builtin_fmaf(p, r, 0x1.6c16c2p-10f);
+  p = __builtin_fmaf(p, r, 0x1.111112p-7f);
+  p = __builtin_fmaf(p, r, 0x1.555556p-5f);
+  p = __builtin_fmaf(p, r, 0x1.555556p-3f);
+  p = __builtin_fmaf(p, r, 0x1.0p-1f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  int k = (int)kf;
+  return p * __uint_as_float((uint32_t)(k + 127) << 23);
+}
+
+// Compensated (hi, lo) FP32 accumulator update: TwoSum(hi, x), the rounding
+// error goes to lo.  One 64-bit CAS per update.
+__device__ __forceinline__ void kahan_atomic_add(float2* p, float x) {
+  unsigned long long* a = reinterpret_cast<unsigned long long*>(p);
+  unsigned long long old = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long assumed;
+  do {
+    assumed = old;
+    float hi = __uint_as_float((uint32_t)(assumed & 0xffffffffull));
+    float lo = __uint_as_float((uint32_t)(assumed >> 32));
+    float s = hi + x;
+    float bp = s - hi;
+    float e = (hi - (s - bp)) + (x - bp);
+    float nlo = lo + e;
+    unsigned long long nv = (unsigned long long)__float_as_uint(s) |
+                            ((unsigned long long)__float_as_uint(nlo) << 32);
+    old = atomicCAS(a, assumed, nv);
+  } while (old != assumed);
+}
+
+// ---------------------------------------------------------------- launches
+// All launchers enqueue on `s` and return hipGetLastError().
+hipError_t launch_scene_derive(const float* means, const float* scales, const float* quats,
+                               const float* opacity, int64_t n, float4* p0, float4* p1, float4* p2,
+                               hipStream_t s);
+
+struct ViewGeom {      // per view of a chunk (device array)
+  int32_t W, H, TX, TY;
+};
+
+hipError_t launch_preprocess(const float4* p0, const float4* p1, const float4* p2, int64_t n,
+                             const Cam* cams, const ViewGeom* geom, int m, Rec* rec,
+                             uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt,
+                             hipStream_t s);
+
+// Segmented stable LSD radix sort of (key, val) pairs on key bits [0, bits).
+// Segment g occupies [seg_start[g], seg_start[g] + seg_len[g]); max_len bounds
+// seg_len.  Result ends in (k0, v0) if the number of passes is even, else in
+// (k1, v1); *in_second tells which.  hist needs sort_hist_size() uint32.
+size_t sort_hist_size(int nseg, int64_t max_len);
+hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                      const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
+                      int64_t max_len, int bits, uint32_t* hist, bool* in_second, hipStream_t s);
+
+// Exclusive scan of cnt[v*n + val[v*n+k]]-ordered counts: off[v*n+k] for the
+// m*n sorted items (global running offset over the whole chunk).  seg_start /
+// seg_len per view get the view's pair range; total[0] = sum.
+size_t scan_tmp_size(int64_t items);
+hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t n, int m,
+                       uint32_t* off, uint32_t* seg_start, uint32_t* seg_len, uint32_t* total,
+                       uint32_t* tmp, hipStream_t s);
+
+hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off, const uint2* rect,
+                            const uint32_t* cnt, const ViewGeom* geom, int64_t n, int m,
+                            uint32_t* pair_key, uint32_t* pair_val, hipStream_t s);
+
+hipError_t launch_ranges(const uint32_t* pair_key, int64_t P, int tiles_stride, uint2* ranges,
+                         hipStream_t s);
+
+struct BlendArgs {
+  const Rec* rec;              // [m][n]
+  const uint32_t* ids;         // sorted pair values (Gaussian ids)
+  const uint2* ranges;         // [m][tiles_stride]
+  const ViewGeom* geom;        // [m]
+  const void* const* maps;     // [m] device pointers
+  const float* fp8_scales;     // [m][D] or null
+  int32_t view_base;           // index of the chunk's first view in fp8_scales
+  int64_t n;
+  int32_t D;
+  int32_t tiles_stride;
+  float* U;                    // [n][D]
+  float2* beta;                // [n] compensated
+  uint32_t* counts;            // [n] or null
+};
+hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, int max_tiles, hipStream_t s);
+
+hipError_t launch_finalize(const float* U, const float2* beta, int64_t n, int D, float* f,
+                           float* wsum, float* usum, hipStream_t s);
+
+hipError_t launch_encode(const float* src, int64_t pixels, int D, lv_dtype dtype, void* dst,
+                         float* scales, float* tmp_absmax, hipStream_t s);
+
+hipError_t launch_diffuse(const int32_t* row_ptr, const int32_t* col, const void* val,
+                          lv_dtype val_dtype, int64_t n, const void* g0, lv_dtype dtype, int D,
+                          int steps, void* out, float* buf0, float* buf1, float* norms,
+                          hipStream_t s);
+
+}  // namespace lv

@@ -1,0 +1,361 @@
+// Per-view ordering (Sec. 3.1: each pixel blends its Gaussians in the order
+// the ray meets them): depth sort of the Gaussians, tile duplication in depth
+// order, stable sort of the (tile, Gaussian) pairs by tile, tile ranges.
+// The result per tile is its Gaussians sorted by (depth key, index).
+//
+// The radix sort is a segmented, stable LSD sort with 8-bit digits in three
+// kernels per pass (block histograms, per-segment scan, stable scatter).
+// Within a block, items are ranked in rounds of 256 in index order; lanes
+// holding the same digit are found with eight wave ballots, so ranking needs
+// no atomics and keeps input order among equal digits.
+#include "lv_internal.h"
+
+namespace lv {
+
+namespace {
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  uint32_t lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Lanes of the wave (among `active`) whose digit equals this lane's digit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t active) {
+  uint64_t peers = active;
+  for (int b = 0; b < bits; b++) {
+    uint64_t bal = __ballot((d >> b) & 1u);
+    peers &= ((d >> b) & 1u) ? bal : ~bal;
+  }
+  return peers;
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ seg_start,
+    const uint32_t* __restrict__ seg_len, int shift, int bits, int nb, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  uint32_t len = seg_len[g];
+  const uint32_t* k = keys + seg_start[g];
+  uint32_t mask = (1u << bits) - 1u;
+  uint32_t base = (uint32_t)b * kSortItems;
+  for (int r = 0; r < kSortItems / kSortThreads; r++) {
+    uint32_t i = base + r * kSortThreads + t;
+    bool valid = i < len;
+    uint32_t d = valid ? (k[i] >> shift) & mask : 0u;
+    uint64_t act = __ballot(valid);
+    if (act == 0) break;
+    if (valid) {
+      uint64_t peers = match_digit(d, bits, act);
+      if ((peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    } else {
+      match_digit(d, bits, act);  // keep ballots wave-uniform
+    }
+  }
+  __syncthreads();
+  hist[((size_t)g * 256 + t) * nb + b] = h[t];
+}
+
+// Exclusive scan, per segment, over (digit, block) in digit-major order.
+__global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__ hist, int nb) {
+  __shared__ uint32_t part[1024 / 64];
+  __shared__ uint32_t carry_s;
+  int g = blockIdx.x, t = threadIdx.x;
+  uint32_t* h = hist + (size_t)g * 256 * nb;
+  size_t total = (size_t)256 * nb;
+  uint32_t carry = 0;
+  for (size_t base = 0; base < total; base += 1024) {
+    size_t i = base + t;
+    uint32_t x = i < total ? h[i] : 0u;
+    // inclusive wave scan
+    uint32_t incl = x;
+    int lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) part[w] = incl;
+    __syncthreads();
+    if (t < 16) {
+      uint32_t p = part[t];
+      uint32_t s = p;
+      for (int o = 1; o < 16; o <<= 1) {
+        uint32_t y = __shfl_up(s, o, 16);
+        if ((t & 15) >= o) s += y;
+      }
+      part[t] = s - p;  // exclusive
+      if (t == 15) carry_s = s;
+    }
+    __syncthreads();
+    if (i < total) h[i] = carry + part[w] + incl - x;
+    carry += carry_s;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
+    const uint32_t* __restrict__ seg_len, int shift, int bits, int nb,
+    const uint32_t* __restrict__ hist) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[kSortThreads / 64][256];
+  int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+  int w = t >> 6;
+  uint32_t s0 = seg_start[g];
+  uint32_t len = seg_len[g];
+  uint32_t base = (uint32_t)b * kSortItems;
+  if (base >= len) return;  // whole block idle (uniform)
+  run[t] = s0 + hist[((size_t)g * 256 + t) * nb + b];
+#pragma unroll
+  for (int q = 0; q < kSortThreads / 64; q++) wc[q][t] = 0;
+  __syncthreads();
+  uint32_t mask = (1u << bits) - 1u;
+  for (int r = 0; r < kSortItems / kSortThreads; r++) {
+    uint32_t i = base + r * kSortThreads + t;
+    if (base + r * kSortThreads >= len) break;  // uniform across the block
+    bool valid = i < len;
+    uint32_t key = valid ? kin[s0 + i] : 0u;
+    uint32_t val = valid ? vin[s0 + i] : 0u;
+    uint32_t d = (key >> shift) & mask;
+    uint64_t act = __ballot(valid);
+    uint64_t peers = match_digit(d, bits, act);
+    uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+    if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int q = 0; q < w; q++) pos += wc[q][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int q = 0; q < kSortThreads / 64; q++) {
+      add += wc[q][t];
+      wc[q][t] = 0;
+    }
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// ---- scan of per-(view, Gaussian) tile counts in depth order
+constexpr int kScanItems = 4096;
+
+__global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __restrict__ cnt,
+                                                           const uint32_t* __restrict__ sval,
+                                                           int64_t n, int64_t items,
+                                                           unsigned long long* __restrict__ bsum) {
+  __shared__ unsigned long long red[4];
+  int64_t base = (int64_t)blockIdx.x * kScanItems;
+  unsigned long long s = 0;
+  for (int k = threadIdx.x; k < kScanItems; k += 256) {
+    int64_t i = base + k;
+    if (i < items) {
+      int64_t v = i / n;
+      s += cnt[v * n + sval[i]];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Exclusive scan of the block sums (one block); total into bsum[nblocks].
+__global__ __launch_bounds__(1024) void bsum_scan_kernel(unsigned long long* __restrict__ bsum,
+                                                         int64_t nblocks) {
+  __shared__ unsigned long long part[16];
+  __shared__ unsigned long long carry_s;
+  int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  unsigned long long carry = 0;
+  for (int64_t base = 0; base < nblocks; base += 1024) {
+    int64_t i = base + t;
+    unsigned long long x = i < nblocks ? bsum[i] : 0ull;
+    unsigned long long incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+      unsigned long long y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) part[w] = incl;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long s = 0;
+      for (int q = 0; q < 16; q++) {
+        unsigned long long p = part[q];
+        part[q] = s;
+        s += p;
+      }
+      carry_s = s;
+    }
+    __syncthreads();
+    if (i < nblocks) bsum[i] = carry + part[w] + incl - x;
+    carry += carry_s;
+    __syncthreads();
+  }
+  if (t == 0) bsum[nblocks] = carry;
+}
+
+__global__ __launch_bounds__(256) void count_scan_kernel(const uint32_t* __restrict__ cnt,
+                                                         const uint32_t* __restrict__ sval,
+                                                         int64_t n, int64_t items,
+                                                         const unsigned long long* __restrict__ bsum,
+                                                         uint32_t* __restrict__ off) {
+  // 256 threads x 16 consecutive items
+  __shared__ uint32_t part[4];
+  int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)t * 16;
+  uint32_t x[16];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    int64_t i = base + k;
+    uint32_t c = 0;
+    if (i < items) c = cnt[(i / n) * n + sval[i]];
+    x[k] = c;
+    s += c;
+  }
+  uint32_t incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) part[w] = incl;
+  __syncthreads();
+  uint32_t wo = 0;
+  for (int q = 0; q < w; q++) wo += part[q];
+  uint32_t run = (uint32_t)bsum[blockIdx.x] + wo + incl - s;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    int64_t i = base + k;
+    if (i < items) off[i] = run;
+    run += x[k];
+  }
+}
+
+__global__ void seg_kernel(const uint32_t* __restrict__ off, int64_t n, int m,
+                           const unsigned long long* __restrict__ total,
+                           uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_len,
+                           uint32_t* __restrict__ tot32) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) tot32[0] = (uint32_t)(*total > 0xFFFFFFFFull ? 0xFFFFFFFFull : *total);
+  if (v >= m) return;
+  uint32_t a = n ? off[(int64_t)v * n] : 0u;
+  uint32_t b = (v + 1 < m && n) ? off[(int64_t)(v + 1) * n] : (uint32_t)*total;
+  seg_start[v] = a;
+  seg_len[v] = b - a;
+}
+
+__global__ void duplicate_kernel(const uint32_t* __restrict__ sval, const uint32_t* __restrict__ off,
+                                 const uint2* __restrict__ rect, const uint32_t* __restrict__ cnt,
+                                 const ViewGeom* __restrict__ geom, int64_t n,
+                                 uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int v = blockIdx.y;
+  if (k >= n) return;
+  int64_t o = (int64_t)v * n + k;
+  uint32_t gi = sval[o];
+  uint32_t c = cnt[(int64_t)v * n + gi];
+  if (c == 0) return;
+  uint2 r = rect[(int64_t)v * n + gi];
+  uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+  uint32_t TX = (uint32_t)geom[v].TX;
+  uint32_t p = off[o];
+  uint32_t hv = (uint32_t)v << kViewShift;
+  for (uint32_t y = y0; y < y1; y++)
+    for (uint32_t x = x0; x < x1; x++) {
+      pkey[p] = hv | (y * TX + x);
+      pval[p] = gi;
+      p++;
+    }
+}
+
+__global__ void ranges_kernel(const uint32_t* __restrict__ key, int64_t P, int stride,
+                              uint2* __restrict__ ranges) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  uint32_t k = key[i];
+  uint32_t v = k >> kViewShift, tile = k & ((1u << kViewShift) - 1u);
+  uint2* r = ranges + (int64_t)v * stride + tile;
+  if (i == 0 || key[i - 1] != k) r->x = (uint32_t)i;
+  if (i + 1 == P || key[i + 1] != k) r->y = (uint32_t)(i + 1);
+}
+
+}  // namespace
+
+size_t sort_hist_size(int nseg, int64_t max_len) {
+  int64_t nb = (max_len + kSortItems - 1) / kSortItems;
+  if (nb < 1) nb = 1;
+  return (size_t)nseg * 256 * (size_t)nb;
+}
+
+hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                      const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
+                      int64_t max_len, int bits, uint32_t* hist, bool* in_second, hipStream_t s) {
+  *in_second = false;
+  if (nseg == 0 || max_len == 0 || bits == 0) return hipSuccess;
+  int nb = (int)((max_len + kSortItems - 1) / kSortItems);
+  uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  for (int shift = 0; shift < bits; shift += 8) {
+    int pb = bits - shift < 8 ? bits - shift : 8;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, seg_start,
+                       seg_len, shift, pb, nb, hist);
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, vi, ko,
+                       vo, seg_start, seg_len, shift, pb, nb, hist);
+    uint32_t* t;
+    t = ki; ki = ko; ko = t;
+    t = vi; vi = vo; vo = t;
+    *in_second = !*in_second;
+  }
+  return hipGetLastError();
+}
+
+size_t scan_tmp_size(int64_t items) {
+  // block sums as u64 (+1 for the total), in units of uint32
+  int64_t nb = (items + kScanItems - 1) / kScanItems;
+  return (size_t)(nb + 1) * 2 + 2;
+}
+
+hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t n, int m,
+                       uint32_t* off, uint32_t* seg_start, uint32_t* seg_len, uint32_t* total,
+                       uint32_t* tmp, hipStream_t s) {
+  int64_t items = n * (int64_t)m;
+  int64_t nb = (items + kScanItems - 1) / kScanItems;
+  unsigned long long* bsum = reinterpret_cast<unsigned long long*>(tmp);
+  if (nb > 0) {
+    hipLaunchKernelGGL(count_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, cnt, sorted_val, n,
+                       items, bsum);
+  }
+  hipLaunchKernelGGL(bsum_scan_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
+  if (nb > 0) {
+    hipLaunchKernelGGL(count_scan_kernel, dim3((unsigned)nb), dim3(256), 0, s, cnt, sorted_val, n,
+                       items, bsum, off);
+  }
+  hipLaunchKernelGGL(seg_kernel, dim3((m + 255) / 256 > 0 ? (m + 255) / 256 : 1), dim3(256), 0, s,
+                     off, n, m, bsum + nb, seg_start, seg_len, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off, const uint2* rect,
+                            const uint32_t* cnt, const ViewGeom* geom, int64_t n, int m,
+                            uint32_t* pair_key, uint32_t* pair_val, hipStream_t s) {
+  if (n == 0 || m == 0) return hipSuccess;
+  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
+                     s, sorted_val, off, rect, cnt, geom, n, pair_key, pair_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t* pair_key, int64_t P, int tiles_stride, uint2* ranges,
+                         hipStream_t s) {
+  if (P == 0) return hipSuccess;
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, pair_key, P,
+                     tiles_stride, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace lv

@@ -1,0 +1,189 @@
+"""GPU parity of the uplift path against the FP64 oracle, through the C ABI.
+
+Bars: visibility, depth keys, tile rectangles, projected records and
+per-tile sorted lists bit-exact; per-Gaussian contribution counts exact;
+features within 1e-4 (error relative to sum w|F| / beta, the convex
+combination magnitude) and weight sums within 1e-4 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2410_14462_amd as lv
+from synth import philox, scenes
+from synth.scenes import Scene
+from helpers import beta_error, feature_error
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def run_accum(scene_gpu, cams, maps, D, dtype="f32", scales=None):
+    acc = lv.Accum(scene_gpu, D, counts=True)
+    acc.add(cams, maps, dtype=dtype, scales=scales)
+    f, b = acc.finalize()
+    c = acc.counts()
+    torch.cuda.synchronize()
+    out = f.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy().astype(np.int64)
+    acc.close()
+    return out
+
+
+def check_structure(gs, sc, cam):
+    print(f"structure: n={sc.n} {cam.width}x{cam.height}", flush=True)
+    d = gs.debug_view(cam)
+    o = oracle.structure(sc, cam)
+    assert np.array_equal(d["visible"], o.visible)
+    vis = o.visible
+    assert np.array_equal(d["depth"][vis], o.depth[vis])
+    assert np.array_equal(d["rect"][vis], o.rect[vis])
+    assert np.array_equal(d["rec"][vis].view(np.uint32), o.rec32[vis].view(np.uint32))
+    assert np.array_equal(d["tile_start"], o.tile_start)
+    assert np.array_equal(d["ids"], o.ids)
+    return len(o.ids)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = scenes.WORKLOADS["tiny"]
+    sc = scenes.scene_for(w)
+    cams = scenes.cameras_for(w)
+    maps = [scenes.map_uniform(w.seed, v, w.height, w.width, w.D) for v in range(w.m)]
+    return w, sc, cams, maps, lv.Scene.from_arrays(sc)
+
+
+def test_structure_bit_exact_tiny(tiny):
+    _, sc, cams, _, gs = tiny
+    for cam in cams:
+        assert check_structure(gs, sc, cam) > 10000
+
+
+def test_structure_bit_exact_ragged_and_near_plane():
+    """Odd image sizes (partial edge tiles), cameras inside the cloud (near-plane
+    culling, Jacobian clamp) and depth-key ties (FP32 z collisions)."""
+    sc = scenes.make_scene(5, 20000, -4.0, 0.5, 0.0, 1.0)
+    gs = lv.Scene.from_arrays(sc)
+    cams = [scenes.look_at(e, 129, 77, 70.0) for e in scenes.fibonacci_eyes(2, 4.0)]
+    cams += [scenes.look_at(e, 200, 150, 90.0) for e in scenes.fibonacci_eyes(2, 0.5)]
+    for cam in cams:
+        check_structure(gs, sc, cam)
+
+
+def test_uplift_tiny_parity(tiny):
+    w, sc, cams, maps, gs = tiny
+    f, b, c = run_accum(gs, cams, [dev(m) for m in maps], w.D)
+    ref = oracle.uplift(sc, cams, maps)
+    assert np.array_equal(c, ref.count)
+    e = feature_error(f, ref)
+    print(f"tiny: nnz={ref.nnz} max err f={e.max():.3e} beta={beta_error(b, ref).max():.3e}")
+    assert e.max() < TOL
+    assert beta_error(b, ref).max() < TOL
+    assert np.all(f[ref.beta == 0] == 0) and np.all(b[ref.beta == 0] == 0)
+
+
+def test_lv_uplift_one_call_equals_accumulator(tiny):
+    w, sc, cams, maps, gs = tiny
+    f, b = gs.uplift(cams, [dev(m) for m in maps])
+    torch.cuda.synchronize()
+    ref = oracle.uplift(sc, cams, maps)
+    assert feature_error(f.cpu().numpy(), ref).max() < TOL
+    assert beta_error(b.cpu().numpy(), ref).max() < TOL
+
+
+@pytest.mark.parametrize("D", [1, 3, 64, 65, 130])
+def test_channel_groups_and_ragged_D(D):
+    sc = scenes.make_scene(6, 3000, -3.8, 0.5, 0.0, 1.0)
+    cams = [scenes.look_at(e, 96, 80, 60.0) for e in scenes.fibonacci_eyes(2, 4.0)]
+    maps = [philox.normal(60 + D, v, 80 * 96 * D).reshape(80, 96, D) for v in range(2)]
+    gs = lv.Scene.from_arrays(sc)
+    f, b, c = run_accum(gs, cams, [dev(m) for m in maps], D)
+    ref = oracle.uplift(sc, cams, maps)
+    assert np.array_equal(c, ref.count)
+    assert feature_error(f, ref).max() < TOL
+    assert beta_error(b, ref).max() < TOL
+
+
+def test_view_additivity(tiny):
+    w, sc, cams, maps, gs = tiny
+    acc = lv.Accum(gs, w.D, counts=True)
+    acc.add(cams[:1], [dev(maps[0])])
+    acc.add(cams[1:], [dev(m) for m in maps[1:]])
+    f, b = acc.finalize()
+    c = acc.counts().cpu().numpy()
+    ref = oracle.uplift(sc, cams, maps)
+    assert np.array_equal(c.astype(np.int64), ref.count)
+    assert feature_error(f.cpu().numpy(), ref).max() < TOL
+    acc.reset()
+    acc.add(cams[2:3], [dev(maps[2])])
+    f2, _ = acc.finalize()
+    ref2 = oracle.uplift(sc, cams[2:3], maps[2:3])
+    assert feature_error(f2.cpu().numpy(), ref2).max() < TOL
+
+
+def test_edge_cases():
+    # n = 0
+    empty = Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32),
+                  np.zeros((0, 4), np.float32), np.zeros(0, np.float32))
+    cam = scenes.look_at([0, 0, 4.0], 64, 48, 60.0)
+    g0 = lv.Scene.from_arrays(empty)
+    f, b = g0.uplift([cam], [torch.zeros((48, 64, 4), device="cuda")])
+    assert f.shape == (0, 4)
+    # m = 0 and a view that sees nothing: zeros everywhere
+    sc = scenes.make_scene(7, 500, -4.0, 0.5, 0.0, 1.0)
+    gs = lv.Scene.from_arrays(sc)
+    f, b = gs.uplift([], [], out=torch.full((500, 2), 7.0, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.all(f == 0) and torch.all(b == 0)
+    away = scenes.look_at([0, 0, 40.0], 64, 48, 60.0)
+    away.t = -away.t  # the cloud is behind this camera
+    assert not oracle.structure(sc, away).visible.any()
+    f, b = gs.uplift([away], [torch.ones((48, 64, 2), device="cuda")])
+    torch.cuda.synchronize()
+    assert torch.all(f == 0) and torch.all(b == 0)
+    # bad arguments are rejected before any work
+    with pytest.raises(lv.LvError):
+        gs.uplift([cam], [torch.ones((48, 64, 2), device="cuda", dtype=torch.float64)])
+    bad = scenes.look_at([0, 0, 4.0], 64, 48, 60.0)
+    bad.width = 0
+    with pytest.raises(lv.LvError):
+        gs.uplift([bad], [torch.ones((48, 64, 2), device="cuda")])
+
+
+def test_mid_full_size_sampled():
+    """200k Gaussians, 50 views of 512x384, D = 64 FP32 and the D = 1 ellipse
+    mask, in the launch configuration the benchmark times (one call over all
+    views).  The oracle walks every pixel and accumulates a 2,000-Gaussian
+    sample; counts and weight sums are checked for every Gaussian."""
+    w = scenes.WORKLOADS["mid"]
+    sc = scenes.scene_for(w)
+    cams = scenes.cameras_for(w)
+    gs = lv.Scene.from_arrays(sc)
+    print("mid: generating maps", flush=True)
+    maps = [scenes.feature_map(w, v, device="cuda") for v in range(w.m)]
+    f, b, c = run_accum(gs, cams, maps, w.D)
+    rows = scenes.subsample(11, sc.n, 2000)
+    up = oracle.Uplifter(sc, w.D, rows=rows)
+    for v, cam in enumerate(cams):
+        up.add_view(cam, maps[v].cpu().numpy())
+    ref = up.result()
+    print(f"mid: nnz={ref.nnz} P={ref.P}", flush=True)
+    assert np.array_equal(c, ref.count)
+    assert beta_error(b, ref).max() < TOL
+    e = feature_error(f[rows], ref)
+    print(f"mid D=64: max err {e.max():.3e} mean {e.mean():.3e}")
+    assert e.max() < TOL
+    del maps
+    masks = [dev(scenes.ellipse_mask(w.seed, v, w.height, w.width)) for v in range(w.m)]
+    fm, bm, cm = run_accum(gs, cams, masks, 1)
+    upm = oracle.Uplifter(sc, 1, rows=rows)
+    for v, cam in enumerate(cams):
+        upm.add_view(cam, masks[v].cpu().numpy())
+    refm = upm.result()
+    assert np.array_equal(cm, refm.count)
+    assert feature_error(fm[rows], refm).max() < TOL
