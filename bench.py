@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the uplift hot path on one MI355X.
+
+Workload (the mid configuration): 200,000 Gaussians (centres U[-1,1]^3,
+scales exp(N(-4, 0.5^2)), uniform rotations, opacities sigmoid(N(0,1))), 50
+Fibonacci-sphere cameras at radius 4, 512x384 px, 55 deg horizontal FoV; two
+feature sets per view: D = 64 FP32 maps (N(0,1) at 1/14 resolution, bilinearly
+upsampled) and a D = 1 ellipse mask.  Inputs are generated before timing and
+are resident in HBM.
+
+One step = the whole job on that workload: make the scene resident
+(lv_scene_create), uplift the D = 64 maps and the D = 1 masks of all 50 views
+(lv_uplift, FP32), release the scene.  value = ms per (view x channel) over
+the 50 x 65 view-channels of a step.
+
+Also reported, measured in the same run outside the timed steps:
+  roofline      the blend-and-accumulate kernel of the D = 64 uplift, timed with
+                HIP events around each launch during the timed steps;
+  bf16          BF16 storage of the D = 64 maps (encode + uplift) and its error
+                against the FP32 result;
+  diffuse       100 steps of Eq. (8) on a 16-NN graph of the scene (D = 1 and 64);
+  cpu_baseline  the FP64 oracle on a sample of the same workload, host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "uplift ms/view/channel + % HBM roofline, BF16 vs FP32 @ tol; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# FP32 FMA on the vector ALUs without packed-FP32 instructions:
+# 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6
+ALU_PEAK_PACKED_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-views", type=int, default=6,
+                    help="views of the workload the CPU-baseline oracle runs (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2410_14462_amd as lv
+    from synth import scenes
+
+    torch.cuda.set_device(0)
+    w = scenes.WORKLOADS["mid"]
+    n, m, H, W, D = w.n, w.m, w.height, w.width, w.D
+    log(f"bench: {w.name}: generating inputs")
+    sc = scenes.scene_for(w)
+    cams = scenes.cameras_for(w)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    means, scales, quats, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacity)
+    maps = [scenes.feature_map(w, v, device="cuda") for v in range(m)]
+    masks = [dev(scenes.ellipse_mask(w.seed, v, H, W)) for v in range(m)]
+    f64 = torch.empty((n, D), device="cuda")
+    b64 = torch.empty((n,), device="cuda")
+    f1 = torch.empty((n, 1), device="cuda")
+    b1 = torch.empty((n,), device="cuda")
+    torch.cuda.synchronize()
+
+    def step():
+        s = lv.Scene(means, scales, quats, opac)
+        s.uplift(cams, maps, out=f64, wsum=b64)
+        s.uplift(cams, masks, out=f1, wsum=b1)
+        s.close()
+
+    # work statistics (untimed pass with counters)
+    s = lv.Scene(means, scales, quats, opac)
+    acc = lv.Accum(s, D, counts=True)
+    acc.add(cams, maps)
+    st64 = acc.stats()
+    acc.close()
+    s.close()
+    log(f"bench: stats {st64}")
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    log(f"bench: timing {args.steps} steps")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    lv.profile_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        step()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches = lv.profile_stop()
+    lat = [a.elapsed_time(b) for a, b in ev]
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = ms_step / (m * (D + 1))
+    log(f"bench: {ms_step:.3f} ms/step, {value * 1e3:.4f} us/view/channel")
+
+    # blend kernel of the D = 64 uplift: launches alternate D=64, D=1 per step
+    k64 = launches[0::2]
+    k1 = launches[1::2]
+    t64 = sum(k64) / len(k64) * 1e-3
+    bytes64 = (st64["covered_pixels"] * D * 4 + st64["visible"] * 32 + st64["pairs"] * 4
+               + n * (D + 2) * 4)
+    flops64 = 2.0 * st64["contributions"] * (D + 1)
+    hbm_gbs = bytes64 / t64 / 1e9
+    alu_tflops = flops64 / t64 / 1e12
+    t_hbm, t_alu = bytes64 / (HBM_PEAK_GBS * 1e9), flops64 / (ALU_PEAK_TFLOPS * 1e12)
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": round(alu_tflops, 3), "peak": ALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu_tflops / ALU_PEAK_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
+    roof.update({
+        "traffic": None,
+        "kernel": "blend_kernel<LV_F32> (D=64, 50 views per launch)",
+        "launch_ms": round(t64 * 1e3, 4),
+        "hbm": {"achieved_GBs": round(hbm_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
+                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "alg_bytes": int(bytes64)},
+        "alu": {"achieved_TFLOPs": round(alu_tflops, 3), "peak_TFLOPs": ALU_PEAK_TFLOPS,
+                "frac": round(alu_tflops / ALU_PEAK_TFLOPS, 4),
+                "frac_of_packed_peak": round(alu_tflops / ALU_PEAK_PACKED_TFLOPS, 4),
+                "alg_flops": flops64},
+        "mask_launch_ms": round(sum(k1) / max(1, len(k1)), 4),
+    })
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 7),
+        "unit": "ms/view/channel",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "gaussians": n, "views": m, "width": W, "height": H,
+                   "channels": [D, 1], "map_dtype": "f32"},
+        "latency_ms": {"p50": round(percentile(lat, 0.5), 4), "p99": round(percentile(lat, 0.99), 4)},
+        "contributions_per_s": round(st64["contributions"] / t64, 1),
+        "work": st64,
+        "roofline": roof,
+    }
+
+    if not args.no_extras:
+        out.update(extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac))
+
+    if args.cpu_views > 0:
+        out["cpu_baseline"] = cpu_baseline(w, sc, cams, maps, masks, args.cpu_views)
+        out["cpu_baseline"]["gpu_over_cpu"] = round(out["cpu_baseline"]["value"] / value, 1)
+
+    print(json.dumps(out), flush=True)
+
+
+def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
+    import numpy as np
+    import torch
+    from synth import graph
+
+    res = {}
+    n, m, D = w.n, w.m, w.D
+    s = lv.Scene(means, scales, quats, opac)
+    # ---- BF16 storage (codec + uplift) against the FP32 result
+    log("bench: bf16 leg")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    enc = [lv.encode(mp, "bf16")[0] for mp in maps]
+    torch.cuda.synchronize()
+    t_enc = time.perf_counter() - t0
+    fb = torch.empty((n, D), device="cuda")
+    bb = torch.empty((n,), device="cuda")
+    s.uplift(cams, enc, dtype="bf16", out=fb, wsum=bb)  # warm
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.uplift(cams, enc, dtype="bf16", out=fb, wsum=bb)
+    torch.cuda.synchronize()
+    t_bf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.uplift(cams, maps, out=f64, wsum=b64)
+    torch.cuda.synchronize()
+    t_f32 = (time.perf_counter() - t0) / reps
+    # error scale a = uplift of |F| (sum w |F| / beta)
+    absmaps = [mp.abs() for mp in maps]
+    fa, _ = s.uplift(cams, absmaps)
+    seen = b64 > 0
+    err = ((fb - f64).abs() / fa.clamp_min(1e-30))[seen]
+    res["bf16"] = {
+        "encode_ms": round(t_enc * 1e3, 3),
+        "uplift_ms": round(t_bf * 1e3, 3),
+        "uplift_ms_f32": round(t_f32 * 1e3, 3),
+        "ms_per_view_channel": round(t_bf * 1e3 / (m * D), 7),
+        "ms_per_view_channel_f32": round(t_f32 * 1e3 / (m * D), 7),
+        "err_vs_f32": {"max": float(err.max()), "p99": float(torch.quantile(err[:1000000], 0.99)),
+                       "mean": float(err.mean()), "bound": 2.0 ** -8},
+    }
+    del enc, absmaps
+    # ---- diffusion over the 16-NN graph of the scene (graph built on the host)
+    log("bench: diffusion leg (building the 16-NN graph on the host)")
+    feats = f64.cpu().numpy()
+    rp, col, val = graph.knn_graph(sc.means, feats, 16)
+    G = lv.Graph(torch.as_tensor(rp, device="cuda"), torch.as_tensor(col, device="cuda"),
+                 torch.as_tensor(val, device="cuda"))
+    nnz = int(col.shape[0])
+    dres = {"graph_nnz": nnz, "steps": 100}
+    for name, g0 in (("D1", f1.contiguous()), ("D64", f64)):
+        out = G.diffuse(g0, 100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = G.diffuse(g0, 100, out=out)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / 100
+        Dg = g0.shape[1]
+        byts = 4 * (n + 1) + nnz * 8 + 2 * n * Dg * 4
+        dres[name] = {"ms_per_step": round(t * 1e3, 4), "GBs": round(byts / t / 1e9, 1),
+                      "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4)}
+    res["diffuse"] = dres
+    G.close()
+    s.close()
+    return res
+
+
+def cpu_baseline(w, sc, cams, maps, masks, views):
+    """The FP64 oracle (unchanged) on the first `views` views of the workload,
+    both feature sets, all Gaussians; host threads as the oracle uses them."""
+    import oracle
+    log(f"bench: cpu baseline ({views} views)")
+    hm = [maps[v].cpu().numpy() for v in range(views)]
+    hk = [masks[v].cpu().numpy() for v in range(views)]
+    t0 = time.perf_counter()
+    oracle.uplift(sc, cams[:views], hm)
+    oracle.uplift(sc, cams[:views], hk)
+    t = time.perf_counter() - t0
+    return {"value": round(t * 1e3 / (views * (w.D + 1)), 4), "unit": "ms/view/channel",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{views} of {w.m} views, D=64 and D=1, all {w.n} Gaussians, FP64",
+            "seconds": round(t, 2)}
+
+
+if __name__ == "__main__":
+    main()

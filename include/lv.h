@@ -113,7 +113,8 @@ int64_t lv_scene_size(const lv_scene* scene);
  *   out_wsum  device FP32 [n]: beta_i = sum over views and pixels of w_i
  *             (nullable).
  * D in [1, 4096]; m >= 0 (m = 0 writes zeros).  Views are processed in
- * chunks; scratch is allocated by the library and cached in the scene.
+ * chunks (one host synchronisation per chunk); scratch is allocated by the
+ * library and cached per (device, stream) for the life of the process.
  * Errors: LV_ERR_INVALID_ARG (bad sizes, null maps, reserved != 0),
  * LV_ERR_OUT_OF_MEMORY, LV_ERR_DEVICE. */
 lv_status lv_uplift(lv_scene* scene, const lv_camera* cams, int32_t m, const void* const* maps,
@@ -139,6 +140,26 @@ lv_status lv_accum_finalize(lv_accum* acc, float* out_feat, float* out_wsum, flo
  * have been created with LV_ACCUM_COUNTS. */
 lv_status lv_accum_counts(lv_accum* acc, uint32_t* out_counts, void* stream);
 lv_status lv_accum_destroy(lv_accum* acc);
+
+/* Work statistics of an accumulator since its creation or last reset
+ * (synchronous): views processed, (tile, Gaussian) pairs, visible
+ * (view, Gaussian) items, and -- only with LV_ACCUM_COUNTS, else -1 --
+ * pixels with at least one counted Gaussian and counted (Gaussian, view,
+ * pixel) contributions (the non-zeros of W). */
+typedef struct lv_uplift_stats {
+    int64_t views, pairs, visible, covered_pixels, contributions;
+} lv_uplift_stats;
+lv_status lv_accum_stats(lv_accum* acc, lv_uplift_stats* out);
+
+/* Benchmark timing of the blend-and-accumulate kernel: after
+ * lv_profile_start, every blend launch is bracketed by HIP events on its
+ * stream; lv_profile_stop waits for them and returns the number of launches,
+ * their summed duration in milliseconds and, in per_launch_ms (host, nullable,
+ * `capacity` entries), each launch's duration in launch order.
+ * Process-wide. */
+lv_status lv_profile_start(void);
+lv_status lv_profile_stop(int64_t* launches, double* total_ms, double* per_launch_ms,
+                          int64_t capacity);
 
 /* ---------------------------------------------------------- storage codec -- */
 /* Encode one FP32 map src [pixels][D] (device) into dst (device) of dtype:

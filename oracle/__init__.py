@@ -49,6 +49,8 @@ def lib():
         L.orc_covariance32.restype = None
         L.orc_exp32_array.argtypes = [i64, P, P]
         L.orc_exp32_array.restype = None
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = i32
         _lib = L
     return _lib
 
@@ -199,6 +201,10 @@ def covariance32(scales, quats):
     out = np.zeros((s.shape[0], 6), np.float32)
     lib().orc_covariance32(s.shape[0], _p(s), _p(q), _p(out))
     return out
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def exp32(x):

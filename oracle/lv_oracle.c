@@ -550,6 +550,9 @@ void orc_covariance32(int64_t n, const float* s, const float* q, float* out)
     for (int64_t i = 0; i < n; i++) orc_cov32(s + 3 * i, q + 4 * i, out + 6 * i);
 }
 
+/* Threads an oracle call uses by default. */
+int orc_num_threads(void) { return orc_threads(0); }
+
 /* The S32 exponential, exposed for its own pins. */
 void orc_exp32_array(int64_t n, const float* x, float* y)
 {

@@ -34,6 +34,11 @@ class lv_view_debug(ctypes.Structure):
                 ("ids_capacity", ctypes.c_int64)]
 
 
+class lv_uplift_stats(ctypes.Structure):
+    _fields_ = [("views", ctypes.c_int64), ("pairs", ctypes.c_int64), ("visible", ctypes.c_int64),
+                ("covered_pixels", ctypes.c_int64), ("contributions", ctypes.c_int64)]
+
+
 assert ctypes.sizeof(lv_camera) == 80
 
 _lib = None
@@ -65,6 +70,9 @@ def lib():
             "lv_graph_destroy": ([P], i32),
             "lv_diffuse": ([P, P, P, i32, i32, i32, P, P], i32),
             "lv_debug_view": ([P, P, ctypes.POINTER(lv_view_debug), ctypes.POINTER(i64)], i32),
+            "lv_accum_stats": ([P, ctypes.POINTER(lv_uplift_stats)], i32),
+            "lv_profile_start": ([], i32),
+            "lv_profile_stop": ([ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), P, i64], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -78,7 +86,8 @@ def exported_symbols():
     return ["lv_last_error", "lv_version", "lv_scene_create", "lv_scene_destroy", "lv_scene_size",
             "lv_uplift", "lv_accum_create", "lv_accum_reset", "lv_uplift_accumulate",
             "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode",
-            "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view"]
+            "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view",
+            "lv_accum_stats", "lv_profile_start", "lv_profile_stop"]
 
 
 def _check(status):
@@ -156,8 +165,8 @@ class Scene:
         return cls(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacity))
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().lv_scene_destroy(self.handle)
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lv_scene_destroy(self.handle)
             self.handle = None
 
     __del__ = close
@@ -208,8 +217,8 @@ class Accum:
         self.handle, self.scene, self.D = h, scene, D
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().lv_accum_destroy(self.handle)
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lv_accum_destroy(self.handle)
             self.handle = None
 
     __del__ = close
@@ -231,11 +240,28 @@ class Accum:
         _check(lib().lv_accum_finalize(self.handle, _ptr(f), _ptr(b), _ptr(u), _stream()))
         return (f, b, u) if want_sum else (f, b)
 
+    def stats(self):
+        st = lv_uplift_stats()
+        _check(lib().lv_accum_stats(self.handle, ctypes.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in lv_uplift_stats._fields_}
+
     def counts(self):
         import torch
         c = torch.empty((self.scene.n,), device="cuda", dtype=torch.int32)
         _check(lib().lv_accum_counts(self.handle, _ptr(c), _stream()))
         return c
+
+
+def profile_start():
+    _check(lib().lv_profile_start())
+
+
+def profile_stop(capacity=4096):
+    """-> list of blend-launch durations (ms), in launch order, since profile_start()."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    per = np.zeros(capacity, np.float64)
+    _check(lib().lv_profile_stop(ctypes.byref(n), ctypes.byref(ms), per.ctypes.data, capacity))
+    return [float(x) for x in per[:min(n.value, capacity)]]
 
 
 def encode(src, dtype):
@@ -274,8 +300,8 @@ class Graph:
         self.handle, self.n = h, n
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().lv_graph_destroy(self.handle)
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lv_graph_destroy(self.handle)
             self.handle = None
 
     __del__ = close

@@ -9,6 +9,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -91,18 +93,34 @@ struct HostBuf {
   }
 };
 
+// Scratch of the uplift pipeline.  One workspace per (device, stream),
+// created on first use and kept for the life of the process; calls on the
+// same stream serialise on its mutex (they would serialise on the stream
+// anyway).
 struct Workspace {
+  std::mutex mu;
   Buf rec, key0, val0, key1, val1, rect, cnt, off, scan_tmp, hist, seg, pseg, total;
   Buf pk0, pv0, pk1, pv1, hist2, ranges, cams, geom, maps;
+  Buf accU, accB;  // accumulators of the one-call lv_uplift
   HostBuf up, down;
-  void release() {
-    Buf* all[] = {&rec, &key0, &val0, &key1, &val1, &rect, &cnt, &off, &scan_tmp, &hist, &seg,
-                  &pseg, &total, &pk0, &pv0, &pk1, &pv1, &hist2, &ranges, &cams, &geom, &maps};
-    for (Buf* b : all) b->release();
-    up.release();
-    down.release();
-  }
 };
+
+std::mutex g_pool_mu;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_pool;
+
+Workspace* workspace_for(hipStream_t s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  Workspace*& w = g_pool[std::make_pair(dev, s)];
+  if (!w) w = new Workspace();
+  return w;
+}
+
+// Blend-kernel timing (HIP events around every blend launch) for benchmarks.
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
 
 int64_t chunk_budget_bytes() {
   const char* e = getenv("LV_CHUNK_BYTES");
@@ -119,14 +137,14 @@ struct lv_scene {
   int64_t n = 0;
   int device = 0;
   Buf p0, p1, p2;
-  Workspace ws;
 };
 
 struct lv_accum {
   lv_scene* scene = nullptr;
   int32_t D = 0;
   uint32_t flags = 0;
-  Buf U, beta, counts;
+  Buf U, beta, counts, dstats;
+  int64_t views = 0, pairs = 0, visible = 0;
 };
 
 struct lv_graph {
@@ -162,10 +180,9 @@ int ceil_log2(int64_t x) {
 // Structure of one chunk of views: everything up to the tile ranges.  On
 // return, the sorted pair values (Gaussian ids) are in *ids, the ranges in
 // ws.ranges with row stride *stride, and the pair count in *P.
-lv_status build_structure(lv_scene* sc, const lv_camera* cams, int mv, hipStream_t s,
-                          const uint32_t** ids, const uint32_t** pkeys, int* stride, int64_t* P,
-                          int* max_tiles_out) {
-  Workspace& ws = sc->ws;
+lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, int mv,
+                          hipStream_t s, const uint32_t** ids, const uint32_t** pkeys, int* stride,
+                          int64_t* P, int64_t* nvis, int* max_tiles_out) {
   const int64_t n = sc->n;
   const int64_t items = n * (int64_t)mv;
   std::vector<ViewGeom> geom(mv);
@@ -196,7 +213,7 @@ lv_status build_structure(lv_scene* sc, const lv_camera* cams, int mv, hipStream
   HIP_TRY(ws.geom.ensure(sizeof(ViewGeom) * mv, s));
   HIP_TRY(ws.ranges.ensure(sizeof(uint2) * (size_t)mv * max_tiles, s));
   size_t up_bytes = sizeof(Cam) * mv + sizeof(ViewGeom) * mv + 8 * (size_t)mv;
-  size_t down_bytes = 4 * ((size_t)mv + 4);
+  size_t down_bytes = 4 * ((size_t)mv + 8);
   // the pinned staging buffers may still feed an earlier upload on this stream
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(ws.up.ensure(up_bytes));
@@ -226,12 +243,14 @@ lv_status build_structure(lv_scene* sc, const lv_camera* cams, int mv, hipStream
   const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
   uint32_t* pseg = ws.pseg.as<uint32_t>();
   HIP_TRY(scan_counts(ws.cnt.as<uint32_t>(), sval, n, mv, ws.off.as<uint32_t>(), pseg, pseg + mv,
-                      ws.total.as<uint32_t>(), ws.scan_tmp.as<uint32_t>(), s));
+                      ws.total.as<unsigned long long>(), ws.scan_tmp.as<uint32_t>(), s));
   uint32_t* down = static_cast<uint32_t*>(ws.down.p);
-  HIP_TRY(hipMemcpyAsync(down, ws.total.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(down, ws.total.p, 16, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(down + 4, pseg + mv, 4 * (size_t)mv, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  uint64_t total = down[0];
+  const unsigned long long* tot64 = reinterpret_cast<const unsigned long long*>(down);
+  uint64_t total = tot64[0];
+  *nvis = (int64_t)tot64[1];
   if (total >= 0x80000000ull)
     return fail(LV_ERR_UNSUPPORTED, "%llu (tile, Gaussian) pairs in one chunk (limit 2^31)",
                 (unsigned long long)total);
@@ -310,7 +329,6 @@ lv_status lv_scene_destroy(lv_scene* sc) {
   if (!sc) return LV_OK;
   (void)hipDeviceSynchronize();
   sc->p0.release(); sc->p1.release(); sc->p2.release();
-  sc->ws.release();
   delete sc;
   return LV_OK;
 }
@@ -333,8 +351,9 @@ lv_status lv_accum_create(lv_scene* sc, int32_t D, uint32_t flags, void* stream,
   hipError_t e = a->U.ensure(sizeof(float) * n1 * D, s);
   if (e == hipSuccess) e = a->beta.ensure(sizeof(float2) * n1, s);
   if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->counts.ensure(4 * n1, s);
+  if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->dstats.ensure(16, s);
   if (e != hipSuccess) {
-    a->U.release(); a->beta.release(); a->counts.release();
+    a->U.release(); a->beta.release(); a->counts.release(); a->dstats.release();
     delete a;
     return fail(LV_ERR_OUT_OF_MEMORY, "accumulator: %s", hipGetErrorString(e));
   }
@@ -351,6 +370,8 @@ lv_status lv_accum_reset(lv_accum* a, void* stream) {
   if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   size_t n = (size_t)a->scene->n;
+  a->views = a->pairs = a->visible = 0;
+  if (a->dstats.p) HIP_TRY(hipMemsetAsync(a->dstats.p, 0, 16, s));
   if (n == 0) return LV_OK;
   HIP_TRY(hipMemsetAsync(a->U.p, 0, sizeof(float) * n * a->D, s));
   HIP_TRY(hipMemsetAsync(a->beta.p, 0, sizeof(float2) * n, s));
@@ -361,7 +382,7 @@ lv_status lv_accum_reset(lv_accum* a, void* stream) {
 lv_status lv_accum_destroy(lv_accum* a) {
   if (!a) return LV_OK;
   (void)hipDeviceSynchronize();
-  a->U.release(); a->beta.release(); a->counts.release();
+  a->U.release(); a->beta.release(); a->counts.release(); a->dstats.release();
   delete a;
   return LV_OK;
 }
@@ -377,6 +398,8 @@ lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, co
   const int64_t n = sc->n;
   if (n == 0 || m == 0) return LV_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace& ws = *workspace_for(s);
+  std::lock_guard<std::mutex> lk(ws.mu);
   int64_t per_view = n * (int64_t)(sizeof(Rec) + 7 * 4 + 8);
   int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
   mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
@@ -385,10 +408,12 @@ lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, co
     const uint32_t* ids = nullptr;
     const uint32_t* pkeys = nullptr;
     int stride = 0, max_tiles = 0;
-    int64_t P = 0;
-    st = build_structure(sc, cams + v0, mv, s, &ids, &pkeys, &stride, &P, &max_tiles);
+    int64_t P = 0, nvis = 0;
+    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &pkeys, &stride, &P, &nvis, &max_tiles);
     if (st != LV_OK) return st;
-    Workspace& ws = sc->ws;
+    a->views += mv;
+    a->pairs += P;
+    a->visible += nvis;
     HIP_TRY(ws.maps.ensure(sizeof(void*) * mv, s));
     // ws.up was synchronised inside build_structure; reuse it for the map table
     HIP_TRY(ws.up.ensure(sizeof(void*) * mv));
@@ -408,7 +433,21 @@ lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, co
     ba.U = a->U.as<float>();
     ba.beta = a->beta.as<float2>();
     ba.counts = a->counts.as<uint32_t>();
-    HIP_TRY(launch_blend(ba, dtype, mv, max_tiles, s));
+    ba.stats = a->dstats.as<unsigned long long>();
+    {
+      std::lock_guard<std::mutex> pk(g_prof_mu);
+      if (g_prof_on) {
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, s));
+        HIP_TRY(launch_blend(ba, dtype, mv, max_tiles, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        g_prof_events.emplace_back(e0, e1);
+      } else {
+        HIP_TRY(launch_blend(ba, dtype, mv, max_tiles, s));
+      }
+    }
     if (v0 + mc < m) HIP_TRY(hipStreamSynchronize(s));  // staging buffers are reused
   }
   return LV_OK;
@@ -434,6 +473,55 @@ lv_status lv_accum_counts(lv_accum* a, uint32_t* out, void* stream) {
   return LV_OK;
 }
 
+lv_status lv_accum_stats(lv_accum* a, lv_uplift_stats* out) {
+  if (!a || !out) return fail(LV_ERR_INVALID_ARG, "null argument");
+  out->views = a->views;
+  out->pairs = a->pairs;
+  out->visible = a->visible;
+  out->covered_pixels = -1;
+  out->contributions = -1;
+  if (a->dstats.p) {
+    unsigned long long h[2];
+    HIP_TRY(hipMemcpy(h, a->dstats.p, 16, hipMemcpyDeviceToHost));
+    out->covered_pixels = (int64_t)h[0];
+    out->contributions = (int64_t)h[1];
+  }
+  return LV_OK;
+}
+
+lv_status lv_profile_start(void) {
+  std::lock_guard<std::mutex> pk(g_prof_mu);
+  for (auto& e : g_prof_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  g_prof_events.clear();
+  g_prof_on = true;
+  return LV_OK;
+}
+
+lv_status lv_profile_stop(int64_t* launches, double* total_ms, double* per_launch_ms,
+                          int64_t capacity) {
+  std::lock_guard<std::mutex> pk(g_prof_mu);
+  g_prof_on = false;
+  double ms = 0.0;
+  int64_t k = 0;
+  for (auto& e : g_prof_events) {
+    HIP_TRY(hipEventSynchronize(e.second));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
+    ms += t;
+    if (per_launch_ms && k < capacity) per_launch_ms[k] = t;
+    k++;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (launches) *launches = (int64_t)g_prof_events.size();
+  if (total_ms) *total_ms = ms;
+  g_prof_events.clear();
+  return LV_OK;
+}
+
 lv_status lv_uplift(lv_scene* sc, const lv_camera* cams, int32_t m, const void* const* maps,
                     lv_dtype dtype, const float* scales, int32_t D, float* out_feat,
                     float* out_wsum, void* stream) {
@@ -444,13 +532,24 @@ lv_status lv_uplift(lv_scene* sc, const lv_camera* cams, int32_t m, const void* 
   if (st != LV_OK) return st;
   st = check_maps(maps, m, dtype, scales);
   if (st != LV_OK) return st;
-  lv_accum* a = nullptr;
-  st = lv_accum_create(sc, D, 0, stream, &a);
-  if (st != LV_OK) return st;
-  st = lv_uplift_accumulate(a, cams, m, maps, dtype, scales, stream);
-  if (st == LV_OK) st = lv_accum_finalize(a, out_feat, out_wsum, nullptr, stream);
-  (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
-  lv_accum_destroy(a);
+  // a transient accumulator whose buffers live in the stream's workspace
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace& ws = *workspace_for(s);
+  lv_accum a;
+  a.scene = sc;
+  a.D = D;
+  {
+    std::lock_guard<std::mutex> lk(ws.mu);
+    size_t n1 = (size_t)(sc->n > 0 ? sc->n : 1);
+    HIP_TRY(ws.accU.ensure(sizeof(float) * n1 * D, s));
+    HIP_TRY(ws.accB.ensure(sizeof(float2) * n1, s));
+    a.U.p = ws.accU.p;
+    a.beta.p = ws.accB.p;
+  }
+  st = lv_accum_reset(&a, stream);
+  if (st == LV_OK) st = lv_uplift_accumulate(&a, cams, m, maps, dtype, scales, stream);
+  if (st == LV_OK) st = lv_accum_finalize(&a, out_feat, out_wsum, nullptr, stream);
+  a.U.p = a.beta.p = nullptr;  // owned by the workspace
   return st;
 }
 
@@ -551,11 +650,12 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
   }
   const uint32_t *ids = nullptr, *pkeys = nullptr;
   int stride = 0, max_tiles = 0;
-  int64_t P = 0;
-  st = build_structure(sc, cam, 1, s, &ids, &pkeys, &stride, &P, &max_tiles);
+  int64_t P = 0, nvis = 0;
+  Workspace& ws = *workspace_for(s);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  st = build_structure(sc, ws, cam, 1, s, &ids, &pkeys, &stride, &P, &nvis, &max_tiles);
   if (st != LV_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));
-  Workspace& ws = sc->ws;
   if (P_out) *P_out = P;
   std::vector<uint32_t> key(n);
   std::vector<Rec> rec(n);

@@ -4,22 +4,26 @@
 // pixel (Eq. 1), and scatter w_i(p) F(p) and w_i(p) into the per-Gaussian
 // accumulators U_i and beta_i.  W is never materialised.
 //
-// One workgroup = one 16x16 tile x one group of 64 channels; 4 wave64s, each
-// owning an 8x8 quadrant (one pixel per lane).  Per step of 32 Gaussians:
-//   A. walk: each lane evaluates the 32 Gaussians for its pixel in order
-//      (records fetched with scalar loads; a wave skips a Gaussian whose
-//      conservative footprint box misses its quadrant), keeping w in VGPRs;
-//   B. accumulate: per Gaussian, the wave visits the lanes with w > 0 and,
-//      one channel per lane, sums w * F from the LDS-staged tile; the four
-//      waves' partials meet in LDS; then one global atomic per (Gaussian,
-//      channel) and one compensated update of beta.
+// One workgroup = one wave64 = one 8x8 quadrant of a 16x16 tile (one pixel
+// per lane) x one group of DG channels.  Waves never wait for each other: no
+// barriers, a wave retires as soon as its 64 pixels are done.  Per step of 32
+// Gaussians of the tile's list:
+//   0. lane j loads Gaussian j's record (vector loads, all in flight
+//      together) and tests whether its alpha >= 1/255 region can touch the
+//      quadrant (exact minimum of the conic over the quadrant, conservative
+//      slack); a ballot gives the step's hit mask;
+//   A. walk: each lane evaluates the hit Gaussians for its pixel in order
+//      (record fields broadcast with readlane), keeping w in VGPRs;
+//   B. accumulate and scatter: per hit Gaussian with some w > 0, the wave
+//      visits those lanes and sums w * F (DG = 64: one channel per lane, w by
+//      readlane, eight feature reads in flight; DG < 64: 64/DG pixel slots of
+//      DG channels, w by permute, slots reduced by shuffles), then issues one
+//      global atomic per channel and one compensated update of beta.
 #include "lv_internal.h"
 
 namespace lv {
 
 namespace {
-
-constexpr int kDG = 64;  // channels per workgroup
 
 template <lv_dtype DT>
 __device__ __forceinline__ float load_feature(const void* map, int64_t idx, float scale) {
@@ -36,86 +40,146 @@ __device__ __forceinline__ float load_feature(const void* map, int64_t idx, floa
   }
 }
 
-template <lv_dtype DT>
-__global__ __launch_bounds__(kBlendThreads, 2) void blend_kernel(
+// Can -power(d) <= tau hold for some d in the rectangle [X0,X1] x [Y0,Y1]
+// (offsets from the Gaussian's centre)?  -power = a dx^2 + b dx dy + c dy^2 is
+// convex with its minimum at 0, so outside the rectangle its minimum over the
+// rectangle lies on an edge; each edge is a 1D quadratic with a clamped vertex.
+__device__ __forceinline__ bool region_hits(float4 r0, float4 r1, float X0, float X1, float Y0,
+                                            float Y1) {
+  const float tau = r1.z;
+  if (!(tau >= 0.0f)) return false;
+  if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
+  const float a = -r0.z, b = -r0.w, c = -r1.x;
+  const float h2c = 0.5f / c, h2a = 0.5f / a;
+  float dy0 = fminf(fmaxf(-b * X0 * h2c, Y0), Y1);
+  float dy1 = fminf(fmaxf(-b * X1 * h2c, Y0), Y1);
+  float dx0 = fminf(fmaxf(-b * Y0 * h2a, X0), X1);
+  float dx1 = fminf(fmaxf(-b * Y1 * h2a, X0), X1);
+  float q0 = (a * X0 + b * dy0) * X0 + c * dy0 * dy0;
+  float q1 = (a * X1 + b * dy1) * X1 + c * dy1 * dy1;
+  float q2 = a * dx0 * dx0 + (b * dx0 + c * Y0) * Y0;
+  float q3 = a * dx1 * dx1 + (b * dx1 + c * Y1) * Y1;
+  return fminf(fminf(q0, q1), fminf(q2, q3)) <= tau;
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Sum over the 64 lanes of the wave with DPP (within rows: quad swaps and
+// mirrors; across rows: row broadcasts), returned as a wave-uniform value.
+__device__ __forceinline__ float wave_sum(float x) {
+  x += dpp_f<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f<0x141, 0xF>(x);  // row_half_mirror
+  x += dpp_f<0x140, 0xF>(x);  // row_mirror
+  x += dpp_f<0x142, 0xA>(x);  // row_bcast:15 into rows 1, 3
+  x += dpp_f<0x143, 0xC>(x);  // row_bcast:31 into rows 2, 3
+  return readlane_f(x, 63);
+}
+
+template <lv_dtype DT, int DG, bool FLDS>
+__global__ __launch_bounds__(64) void blend_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, const void* const* __restrict__ maps,
     const float* __restrict__ fp8_scales, int view_base, int64_t n, int D, int tiles_stride,
-    float* __restrict__ U, float2* __restrict__ beta, uint32_t* __restrict__ counts) {
-  extern __shared__ float smem[];
-  float* Fs = smem;                                    // [256][kDG]
-  float* red = Fs + kBlendThreads * kDG;               // [kChunk][kDG]
-  float* redb = red + kChunk * kDG;                    // [kChunk]
-  uint32_t* redc = reinterpret_cast<uint32_t*>(redb + kChunk);  // [kChunk]
-  uint32_t* gids = redc + kChunk;                      // [kChunk]
+    float* __restrict__ U, float2* __restrict__ beta, uint32_t* __restrict__ counts,
+    unsigned long long* __restrict__ stats) {
+  constexpr int G = kChunk;
+  constexpr int SLOTS = 64 / DG;  // pixel slots per wave in step B
+  extern __shared__ float Fs[];   // [64][DG] when FLDS
 
-  const int v = blockIdx.y, tile = blockIdx.x, cg = blockIdx.z;
+  const int v = blockIdx.y, quad = blockIdx.x & 3, tile = blockIdx.x >> 2, cg = blockIdx.z;
   const ViewGeom g = geom[v];
   if (tile >= g.TX * g.TY) return;
   const uint2 rg = ranges[(int64_t)v * tiles_stride + tile];
   if (rg.y <= rg.x) return;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lane = threadIdx.x;
   const int tx = tile % g.TX, ty = tile / g.TX;
-  const int qx = tx * kTile + (w & 1) * 8, qy = ty * kTile + (w >> 1) * 8;
+  const int qx = tx * kTile + (quad & 1) * 8, qy = ty * kTile + (quad >> 1) * 8;
+  if (qx >= g.W || qy >= g.H) return;  // quadrant entirely outside the image
   const int px = qx + (lane & 7), py = qy + (lane >> 3);
   const bool inside = px < g.W && py < g.H;
-  const int c0 = cg * kDG;
-  const int dv = D - c0 < kDG ? D - c0 : kDG;  // valid channels in this group
-
-  // Stage the tile's features for channels [c0, c0 + dv) in LDS.  Pixel index
-  // of thread t is t (quadrant-major), matching the walk below.
+  const int c0 = cg * DG;
+  const int dv = D - c0 < DG ? D - c0 : DG;  // valid channels in this group
   const void* map = maps[v];
-  for (int e = t; e < kBlendThreads * kDG; e += kBlendThreads) {
-    int p = e / kDG, c = e - p * kDG;
-    int ww = p >> 6, ll = p & 63;
-    int gx = tx * kTile + (ww & 1) * 8 + (ll & 7), gy = ty * kTile + (ww >> 1) * 8 + (ll >> 3);
-    float val = 0.0f;
-    if (c < dv && gx < g.W && gy < g.H) {
-      float sc = 1.0f;
-      if constexpr (DT == LV_FP8_E4M3) sc = fp8_scales[(int64_t)(view_base + v) * D + c0 + c];
-      val = load_feature<DT>(map, ((int64_t)gy * g.W + gx) * D + c0 + c, sc);
+  float fsc = 1.0f;  // FP8 scale of this lane's channel
+  const int slot = lane / DG, ch = lane - slot * DG;
+  if constexpr (DT == LV_FP8_E4M3) {
+    if (ch < dv) fsc = fp8_scales[(int64_t)(view_base + v) * D + c0 + ch];
+  }
+
+  if constexpr (FLDS) {
+    // this quadrant's features for channels [c0, c0 + dv); pixel p = lane index
+    for (int e = lane; e < 64 * DG; e += 64) {
+      int p = e / DG, c = e - p * DG;
+      int gx = qx + (p & 7), gy = qy + (p >> 3);
+      float val = 0.0f;
+      if (c < dv && gx < g.W && gy < g.H) {
+        float sc = 1.0f;
+        if constexpr (DT == LV_FP8_E4M3) sc = fp8_scales[(int64_t)(view_base + v) * D + c0 + c];
+        val = load_feature<DT>(map, ((int64_t)gy * g.W + gx) * D + c0 + c, sc);
+      }
+      Fs[e] = val;
     }
-    Fs[e] = val;
+    __syncthreads();
   }
-  for (int e = t; e < kChunk * kDG; e += kBlendThreads) red[e] = 0.0f;
-  if (t < kChunk) {
-    redb[t] = 0.0f;
-    redc[t] = 0u;
-  }
-  __syncthreads();
+  // feature of channel ch at the wave's pixel l
+  auto feat = [&](int l) -> float {
+    if constexpr (FLDS) {
+      return Fs[l * DG + ch];
+    } else {
+      const int gx = qx + (l & 7), gy = qy + (l >> 3);
+      if (ch >= dv || gx >= g.W || gy >= g.H) return 0.0f;
+      return load_feature<DT>(map, ((int64_t)gy * g.W + gx) * D + c0 + ch, fsc);
+    }
+  };
 
   const Rec* vrec = rec + (int64_t)v * n;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
-  const float qlox = (float)qx + 0.5f, qhix = (float)qx + 7.5f;
-  const float qloy = (float)qy + 0.5f, qhiy = (float)qy + 7.5f;
+  const float qx0 = (float)qx + 0.5f, qx1 = (float)qx + 7.5f;
+  const float qy0 = (float)qy + 0.5f, qy1 = (float)qy + 7.5f;
   float T = 1.0f;
   bool alive = inside;
-  const float* fcol = Fs + (w * 64) * kDG + lane;  // this lane's channel, pixel 0 of the wave
+  uint32_t ncontrib = 0;  // this pixel's counted Gaussians (statistics only)
 
-  for (uint32_t base = rg.x; base < rg.y; base += kChunk) {
-    if (!__syncthreads_or(alive)) break;
-    const int cnt = (int)(rg.y - base < (uint32_t)kChunk ? rg.y - base : (uint32_t)kChunk);
-    if (t < cnt) gids[t] = ids[base + t];
+  for (uint32_t base = rg.x; base < rg.y; base += G) {
+    if (__ballot(alive) == 0ull) break;
+    const int cnt = (int)(rg.y - base < (uint32_t)G ? rg.y - base : (uint32_t)G);
+
+    // ---- 0: records of this step, one per lane; quadrant test
+    float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+    uint32_t my_id = 0;
+    if (lane < cnt) {
+      my_id = ids[base + lane];
+      q0 = vrec[my_id].r0;
+      q1 = vrec[my_id].r1;
+    }
+    const bool lane_hit =
+        lane < cnt && region_hits(q0, q1, qx0 - q0.x, qx1 - q0.x, qy0 - q0.y, qy1 - q0.y);
+    const uint64_t hits = __ballot(lane_hit);
 
     // ---- A: walk
-    float wv[kChunk];
-    const bool wave_alive = __ballot(alive) != 0ull;
+    float wv[G];
 #pragma unroll
-    for (int j = 0; j < kChunk; j++) {
+    for (int j = 0; j < G; j++) {
       wv[j] = 0.0f;
-      if (j < cnt && wave_alive) {
-        const uint32_t gid = __builtin_amdgcn_readfirstlane(ids[base + j]);
-        const float4 r0 = vrec[gid].r0;
-        const float4 r1 = vrec[gid].r1;
-        const bool hit = !(r0.x + r1.z < qlox || r0.x - r1.z > qhix || r0.y + r1.w < qloy ||
-                           r0.y - r1.w > qhiy);
-        if (hit && alive) {
-          float dx = pxf - r0.x, dy = pyf - r0.y;
-          float pw = (r0.w * dx) * dy;
-          pw = __builtin_fmaf(r1.x * dy, dy, pw);
-          pw = __builtin_fmaf(r0.z * dx, dx, pw);
+      if ((hits >> j) & 1ull) {
+        const float ux = readlane_f(q0.x, j), uy = readlane_f(q0.y, j);
+        const float A = readlane_f(q0.z, j), B = readlane_f(q0.w, j);
+        const float C = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
+        if (alive) {
+          float dx = pxf - ux, dy = pyf - uy;
+          float pw = (B * dx) * dy;
+          pw = __builtin_fmaf(C * dy, dy, pw);
+          pw = __builtin_fmaf(A * dx, dx, pw);
           pw = fminf(pw, 0.0f);
-          float al = fminf(kAlphaMax, r1.y * exp32(pw));
+          float al = fminf(kAlphaMax, op * exp32(pw));
           if (al >= kAlphaMin) {
             float Tn = T * (1.0f - al);
             if (Tn < kTEps) {
@@ -123,73 +187,110 @@ __global__ __launch_bounds__(kBlendThreads, 2) void blend_kernel(
             } else {
               wv[j] = al * T;
               T = Tn;
+              ncontrib++;
             }
           }
         }
       }
     }
-    __syncthreads();  // gids visible
 
-    // ---- B: accumulate, one Gaussian at a time, one channel per lane
+    // ---- B: accumulate and scatter, one Gaussian at a time
 #pragma unroll
-    for (int j = 0; j < kChunk; j++) {
-      if (j < cnt) {
-        uint64_t msk = __ballot(wv[j] > 0.0f);
+    for (int j = 0; j < G; j++) {
+      if ((hits >> j) & 1ull) {
+        const uint64_t msk = __ballot(wv[j] > 0.0f);
         if (msk) {
-          const uint32_t nc = (uint32_t)__popcll(msk);
-          float acc = 0.0f, ws = 0.0f;
-          const int wj = __float_as_int(wv[j]);
-          while (msk) {
-            const int l = (int)__builtin_ctzll(msk);
-            msk &= msk - 1ull;
-            const float wl = __int_as_float(__builtin_amdgcn_readlane(wj, l));
-            acc = __builtin_fmaf(wl, fcol[l * kDG], acc);
-            ws += wl;
+          float acc = 0.0f, ws;
+          if constexpr (SLOTS == 1) {
+            // eight contributions per round: their feature reads are in flight together
+            uint64_t mm = msk;
+            const int wj = __float_as_int(wv[j]);
+            while (mm) {
+              int l[8];
+              float wl[8], fv[8];
+#pragma unroll
+              for (int k = 0; k < 8; k++) {
+                if (mm) {
+                  l[k] = (int)__builtin_ctzll(mm);
+                  mm &= mm - 1ull;
+                  wl[k] = __int_as_float(__builtin_amdgcn_readlane(wj, l[k]));
+                } else {
+                  l[k] = 0;
+                  wl[k] = 0.0f;
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < 8; k++) fv[k] = feat(l[k]);
+#pragma unroll
+              for (int k = 0; k < 8; k++) acc = __builtin_fmaf(wl[k], fv[k], acc);
+            }
+            ws = wave_sum(wv[j]);
+          } else {
+            // slot s takes the pixels p = s (mod SLOTS) of the wave
+            uint64_t sel = 0ull;
+#pragma unroll
+            for (int k = 0; k < 64; k += SLOTS) sel |= 1ull << k;
+            uint64_t mm = msk & (sel << slot);
+            float wsl = 0.0f;
+            while (__ballot(mm != 0ull)) {
+              const bool has = mm != 0ull;
+              const int l = has ? (int)__builtin_ctzll(mm) : 0;
+              if (has) mm &= mm - 1ull;
+              const float wl = __shfl(wv[j], l, 64);  // every lane takes part
+              if (has) {
+                acc = __builtin_fmaf(wl, feat(l), acc);
+                wsl += wl;
+              }
+            }
+#pragma unroll
+            for (int o = DG; o < 64; o <<= 1) {
+              acc += __shfl_down(acc, o, 64);
+              wsl += __shfl_down(wsl, o, 64);
+            }
+            ws = wsl;
           }
-          atomicAdd(&red[j * kDG + lane], acc);
-          if (lane == 0) {
-            atomicAdd(&redb[j], ws);
-            atomicAdd(&redc[j], nc);
+          const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
+          if (lane < dv && acc != 0.0f) unsafeAtomicAdd(&U[(int64_t)gid * D + c0 + lane], acc);
+          if (lane == 0 && cg == 0) {
+            twosum_atomic_add(&beta[gid], ws);
+            if (counts) atomicAdd(&counts[gid], (uint32_t)__popcll(msk));
           }
         }
       }
     }
-    __syncthreads();
-
-    // ---- flush the step: one atomic per (Gaussian, channel)
-    for (int e = t; e < cnt * kDG; e += kBlendThreads) {
-      int j = e / kDG, c = e - j * kDG;
-      if (redc[j] != 0u && c < dv) unsafeAtomicAdd(&U[(int64_t)gids[j] * D + c0 + c], red[e]);
-      red[e] = 0.0f;
-    }
-    __syncthreads();
-    if (t < cnt) {
-      if (redc[t] != 0u && cg == 0) {
-        kahan_atomic_add(&beta[gids[t]], redb[t]);
-        if (counts) atomicAdd(&counts[gids[t]], redc[t]);
-      }
-      redb[t] = 0.0f;
-      redc[t] = 0u;
+  }
+  if (counts && cg == 0) {
+    // covered pixels and contributions of this quadrant
+    const uint64_t covered = __ballot(ncontrib != 0u);
+    uint64_t s = ncontrib;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) {
+      atomicAdd(&stats[1], (unsigned long long)s);
+      atomicAdd(&stats[0], (unsigned long long)__popcll(covered));
     }
   }
 }
 
+template <lv_dtype DT, int DG, bool FLDS>
+hipError_t launch_blend_dg(const BlendArgs& a, int m, int max_tiles, hipStream_t s) {
+  size_t lds = FLDS ? sizeof(float) * 64 * DG : 0;
+  int groups = (a.D + DG - 1) / DG;
+  hipLaunchKernelGGL((blend_kernel<DT, DG, FLDS>), dim3(max_tiles * 4, m, groups), dim3(64), lds, s,
+                     a.rec, a.ids, a.ranges, a.geom, a.maps, a.fp8_scales, a.view_base, a.n, a.D,
+                     a.tiles_stride, a.U, a.beta, a.counts, a.stats);
+  return hipGetLastError();
+}
+
 template <lv_dtype DT>
 hipError_t launch_blend_t(const BlendArgs& a, int m, int max_tiles, hipStream_t s) {
-  size_t lds = sizeof(float) * (kBlendThreads * kDG + kChunk * kDG + kChunk) +
-               sizeof(uint32_t) * 2 * kChunk;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&blend_kernel<DT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  int groups = (a.D + kDG - 1) / kDG;
-  hipLaunchKernelGGL(blend_kernel<DT>, dim3(max_tiles, m, groups), dim3(kBlendThreads), lds, s,
-                     a.rec, a.ids, a.ranges, a.geom, a.maps, a.fp8_scales, a.view_base, a.n, a.D,
-                     a.tiles_stride, a.U, a.beta, a.counts);
-  return hipGetLastError();
+  if (a.D <= 1) return launch_blend_dg<DT, 1, true>(a, m, max_tiles, s);
+  if (a.D <= 2) return launch_blend_dg<DT, 2, true>(a, m, max_tiles, s);
+  if (a.D <= 4) return launch_blend_dg<DT, 4, true>(a, m, max_tiles, s);
+  if (a.D <= 8) return launch_blend_dg<DT, 8, true>(a, m, max_tiles, s);
+  if (a.D <= 16) return launch_blend_dg<DT, 16, true>(a, m, max_tiles, s);
+  if (a.D <= 32) return launch_blend_dg<DT, 32, true>(a, m, max_tiles, s);
+  return launch_blend_dg<DT, 64, true>(a, m, max_tiles, s);
 }
 
 __global__ void finalize_kernel(const float* __restrict__ U, const float2* __restrict__ beta,

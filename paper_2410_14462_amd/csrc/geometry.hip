@@ -136,25 +136,15 @@ __global__ void preprocess_kernel(const float4* __restrict__ p0, const float4* _
   float A = -0.5f * (sc / det);
   float B = sb / det;
   float C = -0.5f * (sa / det);
-  // Culling half-extents of {d : -(A dx^2 + B dx dy + C dy^2) <= tau}, tau from
-  // alpha >= 1/255 with generous slack; alpha < 1/255 outside, whatever the
-  // rounding of the exponent.  Never reachable when opacity < 1/255.
-  float hx = -1.0f, hy = -1.0f;
-  if (op >= kAlphaMin) {
-    float tau = (logf(op / kAlphaMin) + 0.01f) * 1.01f;
-    float dm = A * C - 0.25f * (B * B);
-    if (dm > 0.0f) {
-      hx = sqrtf(tau * (-C) / dm) * 1.001f + 0.01f;
-      hy = sqrtf(tau * (-A) / dm) * 1.001f + 0.01f;
-    } else {
-      hx = hy = 3.0e38f;
-    }
-  }
+  // Culling bound: alpha >= 1/255 needs -(A dx^2 + B dx dy + C dy^2) <=
+  // ln(opacity * 255); tau adds generous slack so that rounding of the
+  // exponent can never make a skipped pixel count.  -1: never reachable.
+  float tau = op >= kAlphaMin ? (logf(op / kAlphaMin) + 0.01f) * 1.01f : -1.0f;
   key[o] = __float_as_uint(zc);
   cnt[o] = (uint32_t)((x1 - x0) * (y1 - y0));
   rect[o] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
   rec[o].r0 = make_float4(ux, uy, A, B);
-  rec[o].r1 = make_float4(C, op, hx, hy);
+  rec[o].r1 = make_float4(C, op, tau, 0.0f);
 }
 
 hipError_t launch_preprocess(const float4* p0, const float4* p1, const float4* p2, int64_t n,

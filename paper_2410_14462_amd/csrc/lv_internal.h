@@ -12,7 +12,7 @@ namespace lv {
 
 constexpr int kTile = 16;           // tile edge in pixels
 constexpr int kBlendThreads = 256;  // one thread per pixel of a tile
-constexpr int kChunk = 32;          // Gaussians staged per blend step
+constexpr int kChunk = 32;          // Gaussians per blend step (one per lane)
 constexpr int kSortItems = 2048;    // items per radix-sort block
 constexpr int kSortThreads = 256;
 constexpr int kViewShift = 20;      // pair key = view << 20 | tile
@@ -34,9 +34,9 @@ struct Cam {
 static_assert(sizeof(Cam) == sizeof(lv_camera), "camera layout");
 
 // Per (view, Gaussian) projected record, 32 bytes:
-//   r0 = (ux, uy, A, B), r1 = (C, opacity, hx, hy)
-// power(d) = A dx^2 + B dx dy + C dy^2 (<= 0); hx, hy bound the pixels where
-// alpha can reach 1/255 (conservative, used only to skip work).
+//   r0 = (ux, uy, A, B), r1 = (C, opacity, tau, 0)
+// power(d) = A dx^2 + B dx dy + C dy^2 (<= 0); alpha can reach 1/255 only
+// where -power <= tau (conservative, used only to skip work; tau < 0: never).
 struct Rec {
   float4 r0, r1;
 };
@@ -80,6 +80,17 @@ __device__ __forceinline__ void kahan_atomic_add(float2* p, float x) {
   } while (old != assumed);
 }
 
+// Compensated accumulation without a CAS loop: the returning atomic add on hi
+// tells which sum was rounded (old + x), its exact rounding error (TwoSum) is
+// added to lo.  beta = hi + lo.
+__device__ __forceinline__ void twosum_atomic_add(float2* p, float x) {
+  const float old = atomicAdd(&p->x, x);
+  const float s = old + x;
+  const float bp = s - old;
+  const float e = (old - (s - bp)) + (x - bp);
+  if (e != 0.0f) unsafeAtomicAdd(&p->y, e);
+}
+
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `s` and return hipGetLastError().
 hipError_t launch_scene_derive(const float* means, const float* scales, const float* quats,
@@ -106,11 +117,12 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
 
 // Exclusive scan of cnt[v*n + val[v*n+k]]-ordered counts: off[v*n+k] for the
 // m*n sorted items (global running offset over the whole chunk).  seg_start /
-// seg_len per view get the view's pair range; total[0] = sum.
+// seg_len per view get the view's pair range; totals[0] = number of pairs,
+// totals[1] = number of visible (view, Gaussian) items.
 size_t scan_tmp_size(int64_t items);
 hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t n, int m,
-                       uint32_t* off, uint32_t* seg_start, uint32_t* seg_len, uint32_t* total,
-                       uint32_t* tmp, hipStream_t s);
+                       uint32_t* off, uint32_t* seg_start, uint32_t* seg_len,
+                       unsigned long long* totals, uint32_t* tmp, hipStream_t s);
 
 hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off, const uint2* rect,
                             const uint32_t* cnt, const ViewGeom* geom, int64_t n, int m,
@@ -132,7 +144,8 @@ struct BlendArgs {
   int32_t tiles_stride;
   float* U;                    // [n][D]
   float2* beta;                // [n] compensated
-  uint32_t* counts;            // [n] or null
+  uint32_t* counts;            // [n] or null; also enables the two counters below
+  unsigned long long* stats;   // [2]: covered pixels, contributions (with counts)
 };
 hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, int max_tiles, hipStream_t s);
 

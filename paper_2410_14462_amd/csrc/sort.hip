@@ -46,12 +46,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
     uint32_t d = valid ? (k[i] >> shift) & mask : 0u;
     uint64_t act = __ballot(valid);
     if (act == 0) break;
-    if (valid) {
-      uint64_t peers = match_digit(d, bits, act);
-      if ((peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
-    } else {
-      match_digit(d, bits, act);  // keep ballots wave-uniform
-    }
+    uint64_t peers = match_digit(d, bits, act);
+    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
   hist[((size_t)g * 256 + t) * nb + b] = h[t];
@@ -149,21 +145,33 @@ constexpr int kScanItems = 4096;
 __global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __restrict__ cnt,
                                                            const uint32_t* __restrict__ sval,
                                                            int64_t n, int64_t items,
-                                                           unsigned long long* __restrict__ bsum) {
-  __shared__ unsigned long long red[4];
+                                                           unsigned long long* __restrict__ bsum,
+                                                           unsigned long long* __restrict__ nvis) {
+  __shared__ unsigned long long red[4], redv[4];
   int64_t base = (int64_t)blockIdx.x * kScanItems;
-  unsigned long long s = 0;
+  unsigned long long s = 0, nv = 0;
   for (int k = threadIdx.x; k < kScanItems; k += 256) {
     int64_t i = base + k;
     if (i < items) {
       int64_t v = i / n;
-      s += cnt[v * n + sval[i]];
+      uint32_t c = cnt[v * n + sval[i]];
+      s += c;
+      nv += c != 0u;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_down(s, o, 64);
+    nv += __shfl_down(nv, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = s;
+    redv[threadIdx.x >> 6] = nv;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    atomicAdd(nvis, redv[0] + redv[1] + redv[2] + redv[3]);
+  }
 }
 
 // Exclusive scan of the block sums (one block); total into bsum[nblocks].
@@ -240,9 +248,9 @@ __global__ __launch_bounds__(256) void count_scan_kernel(const uint32_t* __restr
 __global__ void seg_kernel(const uint32_t* __restrict__ off, int64_t n, int m,
                            const unsigned long long* __restrict__ total,
                            uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_len,
-                           uint32_t* __restrict__ tot32) {
+                           unsigned long long* __restrict__ out_total) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v == 0) tot32[0] = (uint32_t)(*total > 0xFFFFFFFFull ? 0xFFFFFFFFull : *total);
+  if (v == 0) out_total[0] = *total;
   if (v >= m) return;
   uint32_t a = n ? off[(int64_t)v * n] : 0u;
   uint32_t b = (v + 1 < m && n) ? off[(int64_t)(v + 1) * n] : (uint32_t)*total;
@@ -322,14 +330,16 @@ size_t scan_tmp_size(int64_t items) {
 }
 
 hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t n, int m,
-                       uint32_t* off, uint32_t* seg_start, uint32_t* seg_len, uint32_t* total,
-                       uint32_t* tmp, hipStream_t s) {
+                       uint32_t* off, uint32_t* seg_start, uint32_t* seg_len,
+                       unsigned long long* totals, uint32_t* tmp, hipStream_t s) {
   int64_t items = n * (int64_t)m;
   int64_t nb = (items + kScanItems - 1) / kScanItems;
   unsigned long long* bsum = reinterpret_cast<unsigned long long*>(tmp);
+  hipError_t e = hipMemsetAsync(totals, 0, 2 * sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
   if (nb > 0) {
     hipLaunchKernelGGL(count_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, cnt, sorted_val, n,
-                       items, bsum);
+                       items, bsum, totals + 1);
   }
   hipLaunchKernelGGL(bsum_scan_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
   if (nb > 0) {
@@ -337,7 +347,7 @@ hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t 
                        items, bsum, off);
   }
   hipLaunchKernelGGL(seg_kernel, dim3((m + 255) / 256 > 0 ? (m + 255) / 256 : 1), dim3(256), 0, s,
-                     off, n, m, bsum + nb, seg_start, seg_len, total);
+                     off, n, m, bsum + nb, seg_start, seg_len, totals);
   return hipGetLastError();
 }
 
