@@ -173,24 +173,21 @@ __global__ __launch_bounds__(64) void blend_kernel(
         const float ux = readlane_f(q0.x, j), uy = readlane_f(q0.y, j);
         const float A = readlane_f(q0.z, j), B = readlane_f(q0.w, j);
         const float C = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
-        if (alive) {
-          float dx = pxf - ux, dy = pyf - uy;
-          float pw = (B * dx) * dy;
-          pw = __builtin_fmaf(C * dy, dy, pw);
-          pw = __builtin_fmaf(A * dx, dx, pw);
-          pw = fminf(pw, 0.0f);
-          float al = fminf(kAlphaMax, op * exp32(pw));
-          if (al >= kAlphaMin) {
-            float Tn = T * (1.0f - al);
-            if (Tn < kTEps) {
-              alive = false;
-            } else {
-              wv[j] = al * T;
-              T = Tn;
-              ncontrib++;
-            }
-          }
-        }
+        // branch-free: every lane evaluates, selects keep the walk exact
+        float dx = pxf - ux, dy = pyf - uy;
+        float pw = (B * dx) * dy;
+        pw = __builtin_fmaf(C * dy, dy, pw);
+        pw = __builtin_fmaf(A * dx, dx, pw);
+        pw = fminf(pw, 0.0f);
+        const float al = fminf(kAlphaMax, op * exp32(pw));
+        const bool ok = alive && al >= kAlphaMin;
+        const float Tn = T * (1.0f - al);
+        const bool stop = ok && Tn < kTEps;
+        const bool take = ok && !stop;
+        wv[j] = take ? al * T : 0.0f;
+        T = take ? Tn : T;
+        alive = alive && !stop;
+        ncontrib += take ? 1u : 0u;
       }
     }
 
@@ -202,27 +199,22 @@ __global__ __launch_bounds__(64) void blend_kernel(
         if (msk) {
           float acc = 0.0f, ws;
           if constexpr (SLOTS == 1) {
-            // eight contributions per round: their feature reads are in flight together
-            uint64_t mm = msk;
+            // rows of 8 pixels of the quadrant that hold a contribution; within
+            // an active row every pixel is visited (w = 0 adds nothing): lanes
+            // and LDS offsets are compile-time constants, no scalar bit loops
             const int wj = __float_as_int(wv[j]);
-            while (mm) {
-              int l[8];
-              float wl[8], fv[8];
 #pragma unroll
-              for (int k = 0; k < 8; k++) {
-                if (mm) {
-                  l[k] = (int)__builtin_ctzll(mm);
-                  mm &= mm - 1ull;
-                  wl[k] = __int_as_float(__builtin_amdgcn_readlane(wj, l[k]));
-                } else {
-                  l[k] = 0;
-                  wl[k] = 0.0f;
+            for (int r = 0; r < 8; r++) {
+              if ((msk >> (8 * r)) & 0xFFull) {
+                float wl[8], fv[8];
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                  wl[k] = __int_as_float(__builtin_amdgcn_readlane(wj, 8 * r + k));
+                  fv[k] = feat(8 * r + k);
                 }
+#pragma unroll
+                for (int k = 0; k < 8; k++) acc = __builtin_fmaf(wl[k], fv[k], acc);
               }
-#pragma unroll
-              for (int k = 0; k < 8; k++) fv[k] = feat(l[k]);
-#pragma unroll
-              for (int k = 0; k < 8; k++) acc = __builtin_fmaf(wl[k], fv[k], acc);
             }
             ws = wave_sum(wv[j]);
           } else {

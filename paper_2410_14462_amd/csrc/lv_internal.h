@@ -43,8 +43,9 @@ struct Rec {
 
 // S32 exponential for x <= 0: Cody-Waite reduction to |r| <= ln2/2, degree-7
 // Taylor polynomial in Horner form with fmaf, scaling by 2^k; 0 below -80.
-__device__ __forceinline__ float exp32(float x) {
-  if (x < -80.0f) return 0.0f;
+// Branch-free: the polynomial runs on max(x, -80) and the result is selected.
+__device__ __forceinline__ float exp32(float x0) {
+  const float x = fmaxf(x0, -80.0f);
   float kf = rintf(x * 0x1.715476p+0f);
   float r = __builtin_fmaf(kf, -0x1.62e4p-1f, x);
   r = __builtin_fmaf(kf, -0x1.7f7d1cp-20f, r);
@@ -57,7 +58,8 @@ __device__ __forceinline__ float exp32(float x) {
   p = __builtin_fmaf(p, r, 1.0f);
   p = __builtin_fmaf(p, r, 1.0f);
   int k = (int)kf;
-  return p * __uint_as_float((uint32_t)(k + 127) << 23);
+  const float e = p * __uint_as_float((uint32_t)(k + 127) << 23);
+  return x0 < -80.0f ? 0.0f : e;
 }
 
 // Compensated (hi, lo) FP32 accumulator update: TwoSum(hi, x), the rounding
