@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=6,
                     help="views of the workload the CPU-baseline oracle runs (0 = skip)")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -142,7 +144,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
     roof.update({
-        "traffic": None,
+        "traffic": measured_traffic(),
         "kernel": "blend_kernel<LV_F32> (D=64, 50 views per launch)",
         "launch_ms": round(t64 * 1e3, 4),
         "hbm": {"achieved_GBs": round(hbm_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
@@ -175,6 +177,15 @@ def main():
         "roofline": roof,
     }
 
+    if args.calib_copy:
+        src = torch.empty(1 << 28, device="cuda", dtype=torch.float32).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 4
+        del src, dst
+
     if not args.no_extras:
         out.update(extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac))
 
@@ -183,6 +194,22 @@ def main():
         out["cpu_baseline"]["gpu_over_cpu"] = round(out["cpu_baseline"]["value"] / value, 1)
 
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per D=64 blend launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "uplift-200k-50v-512x384-D64_blend_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2410_14462_amd", "csrc")
+    src = open(os.path.join(csrc, "blend.hip"), "rb").read() + \
+        open(os.path.join(csrc, "lv_internal.h"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return int(rec["traffic_bytes"])
 
 
 def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
