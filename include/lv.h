@@ -121,6 +121,20 @@ lv_status lv_uplift(lv_scene* scene, const lv_camera* cams, int32_t m, const voi
                     lv_dtype dtype, const float* scales, int32_t D, float* out_feat,
                     float* out_wsum, void* stream);
 
+/* lv_uplift for several feature sets over the same views in one pass (one
+ * structure build and one blend walk; see lv_uplift_accumulate_sets).  Set k
+ * has its own maps (device pointers, HWC with D_k channels), FP8 scales and
+ * outputs.  1 <= nsets <= 8. */
+typedef struct lv_uplift_set {
+    const void* const* maps;   /* host array [m] of device pointers */
+    const float* scales;       /* FP8 only: device [m][D], else NULL */
+    int32_t D;
+    float* out_feat;           /* device [n][D] */
+    float* out_wsum;           /* device [n], nullable */
+} lv_uplift_set;
+lv_status lv_uplift_sets(lv_scene* scene, const lv_camera* cams, int32_t m, const lv_uplift_set* sets,
+                         int32_t nsets, lv_dtype dtype, void* stream);
+
 /* Streaming form of lv_uplift: the accumulator holds U = W^T F [n][D] (FP32)
  * and beta (compensated FP32 pair), to which views are added in any grouping
  * (accumulating views [0,k) then [k,m) equals all m).  With
@@ -132,6 +146,20 @@ lv_status lv_accum_reset(lv_accum* acc, void* stream);
 lv_status lv_uplift_accumulate(lv_accum* acc, const lv_camera* cams, int32_t m,
                                const void* const* maps, lv_dtype dtype, const float* scales,
                                void* stream);
+/* Several feature sets over the same views in one pass (the same weights
+ * w_i(p) serve every set, Eq. 5 with F the concatenation of the sets'
+ * channels): set k adds maps[k] (host array [m] of device pointers, HWC with
+ * its accumulator's D) to sets[k].acc.  1 <= nsets <= 8; all accumulators on
+ * the same scene and distinct; one storage dtype for all sets.  Each set's
+ * result equals lv_uplift_accumulate of that set alone (within FP32
+ * accumulation order). */
+typedef struct lv_feature_set {
+    lv_accum* acc;
+    const void* const* maps;
+    const float* scales;       /* FP8 only: device [m][D], else NULL */
+} lv_feature_set;
+lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_feature_set* sets,
+                                   int32_t nsets, lv_dtype dtype, void* stream);
 /* f = U / beta (0 where beta = 0) into out_feat [n][D]; beta into out_wsum
  * [n] (nullable); raw U into out_sum [n][D] (nullable). */
 lv_status lv_accum_finalize(lv_accum* acc, float* out_feat, float* out_wsum, float* out_sum,

@@ -34,6 +34,15 @@ class lv_view_debug(ctypes.Structure):
                 ("ids_capacity", ctypes.c_int64)]
 
 
+class lv_feature_set(ctypes.Structure):
+    _fields_ = [("acc", ctypes.c_void_p), ("maps", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
+
+
+class lv_uplift_set(ctypes.Structure):
+    _fields_ = [("maps", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("D", ctypes.c_int32),
+                ("out_feat", ctypes.c_void_p), ("out_wsum", ctypes.c_void_p)]
+
+
 class lv_uplift_stats(ctypes.Structure):
     _fields_ = [("views", ctypes.c_int64), ("pairs", ctypes.c_int64), ("visible", ctypes.c_int64),
                 ("covered_pixels", ctypes.c_int64), ("contributions", ctypes.c_int64)]
@@ -71,6 +80,8 @@ def lib():
             "lv_diffuse": ([P, P, P, i32, i32, i32, P, P], i32),
             "lv_debug_view": ([P, P, ctypes.POINTER(lv_view_debug), ctypes.POINTER(i64)], i32),
             "lv_accum_stats": ([P, ctypes.POINTER(lv_uplift_stats)], i32),
+            "lv_uplift_sets": ([P, P, i32, P, i32, i32, P], i32),
+            "lv_uplift_accumulate_sets": ([P, i32, P, i32, i32, P], i32),
             "lv_profile_start": ([], i32),
             "lv_profile_stop": ([ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), P, i64], i32),
         }
@@ -87,7 +98,8 @@ def exported_symbols():
             "lv_uplift", "lv_accum_create", "lv_accum_reset", "lv_uplift_accumulate",
             "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode",
             "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view",
-            "lv_accum_stats", "lv_profile_start", "lv_profile_stop"]
+            "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
+            "lv_uplift_accumulate_sets"]
 
 
 def _check(status):
@@ -186,6 +198,29 @@ class Scene:
                                _ptr(wsum), _stream()))
         return out, wsum
 
+    def uplift_sets(self, cams, sets, dtype="f32", outs=None):
+        """Several feature sets over the same views in one pass.  sets: list of
+        map lists (or (maps, scales) pairs).  Returns [(f, beta)] per set."""
+        import torch
+        dt = _DTYPES[dtype]
+        arr = (lv_uplift_set * len(sets))()
+        keep, res = [], []
+        for k, st in enumerate(sets):
+            maps, scales = st if isinstance(st, tuple) else (st, None)
+            D = maps[0].shape[-1]
+            f, b = outs[k] if outs is not None else (
+                torch.empty((self.n, D), device="cuda", dtype=torch.float32),
+                torch.empty((self.n,), device="cuda", dtype=torch.float32))
+            tab = _map_table(maps, dt)
+            keep.append(tab)
+            arr[k] = lv_uplift_set(ctypes.cast(tab, ctypes.c_void_p),
+                                   None if scales is None else scales.data_ptr(), D,
+                                   f.data_ptr(), b.data_ptr())
+            res.append((f, b))
+        _check(lib().lv_uplift_sets(self.handle, camera_array(cams), len(cams), arr, len(sets), dt,
+                                    _stream()))
+        return res
+
     def debug_view(self, cam):
         """Structure of one view (synchronous, host arrays)."""
         n = self.n
@@ -250,6 +285,22 @@ class Accum:
         c = torch.empty((self.scene.n,), device="cuda", dtype=torch.int32)
         _check(lib().lv_accum_counts(self.handle, _ptr(c), _stream()))
         return c
+
+
+def accumulate_sets(cams, sets, dtype="f32"):
+    """sets: list of (Accum, maps[, scales]) sharing one scene; one pass."""
+    dt = _DTYPES[dtype]
+    arr = (lv_feature_set * len(sets))()
+    keep = []
+    for k, st in enumerate(sets):
+        acc, maps = st[0], st[1]
+        scales = st[2] if len(st) > 2 else None
+        tab = _map_table(maps, dt)
+        keep.append(tab)
+        arr[k] = lv_feature_set(acc.handle.value, ctypes.cast(tab, ctypes.c_void_p),
+                                None if scales is None else scales.data_ptr())
+    _check(lib().lv_uplift_accumulate_sets(camera_array(cams), len(cams), arr, len(sets), dt,
+                                           _stream()))
 
 
 def profile_start():

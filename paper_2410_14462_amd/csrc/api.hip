@@ -99,9 +99,10 @@ struct HostBuf {
 // anyway).
 struct Workspace {
   std::mutex mu;
+  std::mutex accmu;  // held by a one-call uplift while it uses accU/accB
+  Buf accUs[kMaxSets], accBs[kMaxSets];
   Buf rec, key0, val0, key1, val1, rect, cnt, off, scan_tmp, hist, seg, pseg, total;
   Buf pk0, pv0, pk1, pv1, hist2, ranges, cams, geom, maps;
-  Buf accU, accB;  // accumulators of the one-call lv_uplift
   HostBuf up, down;
 };
 
@@ -387,16 +388,82 @@ lv_status lv_accum_destroy(lv_accum* a) {
   return LV_OK;
 }
 
-lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, const void* const* maps,
-                               lv_dtype dtype, const float* scales, void* stream) {
-  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_feature_set* fsets,
+                                   int32_t nsets, lv_dtype dtype, void* stream) {
+  if (nsets < 1 || nsets > kMaxSets)
+    return fail(LV_ERR_INVALID_ARG, "nsets = %d out of [1, %d]", nsets, kMaxSets);
+  if (!fsets) return fail(LV_ERR_INVALID_ARG, "sets is NULL");
   lv_status st = check_cams(cams, m);
   if (st != LV_OK) return st;
-  st = check_maps(maps, m, dtype, scales);
-  if (st != LV_OK) return st;
-  lv_scene* sc = a->scene;
+  lv_scene* sc = nullptr;
+  int total = 0;
+  for (int k = 0; k < nsets; k++) {
+    if (!fsets[k].acc) return fail(LV_ERR_INVALID_ARG, "set %d: accumulator is NULL", k);
+    if (sc && fsets[k].acc->scene != sc)
+      return fail(LV_ERR_INVALID_ARG, "set %d: accumulators belong to different scenes", k);
+    for (int q = 0; q < k; q++)
+      if (fsets[q].acc == fsets[k].acc)
+        return fail(LV_ERR_INVALID_ARG, "set %d repeats the accumulator of set %d", k, q);
+    sc = fsets[k].acc->scene;
+    st = check_maps(fsets[k].maps, m, dtype, fsets[k].scales);
+    if (st != LV_OK) return st;
+    total += fsets[k].acc->D;
+  }
   const int64_t n = sc->n;
   if (n == 0 || m == 0) return LV_OK;
+
+  // channel groups: one set of D <= 32 -> small kernel; otherwise the sets'
+  // channels concatenated and cut into groups of 64, a tail of <= 16 channels
+  // joining the previous group
+  int small_dg = 0;
+  std::vector<ChanGroup> groups;
+  if (nsets == 1 && total <= 32) {
+    small_dg = 1;
+    while (small_dg < total) small_dg <<= 1;
+  } else {
+    // 64-channel main parts; a last part of <= 4 channels becomes the
+    // register tail of the previous group
+    std::vector<int> starts;
+    for (int b = 0; b < total; b += 64) starts.push_back(b);
+    int tail_lo = total;
+    if (starts.size() > 1 && total - starts.back() <= kMaxTail) {
+      tail_lo = starts.back();
+      starts.pop_back();
+    }
+    for (size_t gi = 0; gi < starts.size(); gi++) {
+      const bool last = gi + 1 == starts.size();
+      const int lo = starts[gi], hi = last ? std::min(total, tail_lo) : starts[gi + 1];
+      const int thi = last ? total : hi;  // channels [hi, thi) form the tail
+      ChanGroup g;
+      memset(&g, 0, sizeof(g));
+      g.width = hi - lo;
+      int off = 0;
+      for (int k = 0; k < nsets; k++) {
+        const int D = fsets[k].acc->D;
+        const int a0 = std::max(lo, off), a1 = std::min(hi, off + D);
+        if (a0 < a1) {
+          if (g.nseg == kMaxSegs)
+            return fail(LV_ERR_UNSUPPORTED, "more than %d feature sets share 64 channels", kMaxSegs);
+          g.set[g.nseg] = k;
+          g.c0[g.nseg] = a0 - off;
+          g.vc0[g.nseg] = a0 - lo;
+          g.cnt[g.nseg] = a1 - a0;
+          g.nseg++;
+        }
+        for (int c = std::max(hi, off); c < std::min(thi, off + D); c++) {
+          g.tset[g.ntail] = k;
+          g.tc[g.ntail] = c - off;
+          g.ntail++;
+        }
+        if (off >= lo && off < thi) g.beta_sets |= 1 << k;
+        off += D;
+      }
+      groups.push_back(g);
+    }
+  }
+  int max_width = 0;
+  for (const ChanGroup& g : groups) max_width = std::max(max_width, g.width);
+
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
@@ -411,29 +478,49 @@ lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, co
     int64_t P = 0, nvis = 0;
     st = build_structure(sc, ws, cams + v0, mv, s, &ids, &pkeys, &stride, &P, &nvis, &max_tiles);
     if (st != LV_OK) return st;
-    a->views += mv;
-    a->pairs += P;
-    a->visible += nvis;
-    HIP_TRY(ws.maps.ensure(sizeof(void*) * mv, s));
-    // ws.up was synchronised inside build_structure; reuse it for the map table
-    HIP_TRY(ws.up.ensure(sizeof(void*) * mv));
-    memcpy(ws.up.p, maps + v0, sizeof(void*) * mv);
-    HIP_TRY(hipMemcpyAsync(ws.maps.p, ws.up.p, sizeof(void*) * mv, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < nsets; k++) {
+      fsets[k].acc->views += mv;
+      fsets[k].acc->pairs += P;
+      fsets[k].acc->visible += nvis;
+    }
+    // set descriptors, channel groups and per-set map tables in one upload
+    // (ws.up is idle: build_structure synchronised the stream)
+    const size_t b_sets = sizeof(SetDesc) * nsets;
+    const size_t b_groups = sizeof(ChanGroup) * groups.size();
+    const size_t b_maps = sizeof(void*) * (size_t)mv * nsets;
+    const size_t bytes = b_sets + b_groups + b_maps;
+    HIP_TRY(ws.maps.ensure(bytes, s));
+    HIP_TRY(ws.up.ensure(bytes));
+    char* up = static_cast<char*>(ws.up.p);
+    char* dev = static_cast<char*>(ws.maps.p);
+    SetDesc* sd = reinterpret_cast<SetDesc*>(up);
+    const void** mt = reinterpret_cast<const void**>(up + b_sets + b_groups);
+    for (int k = 0; k < nsets; k++) {
+      lv_accum* a = fsets[k].acc;
+      memcpy(mt + (size_t)k * mv, fsets[k].maps + v0, sizeof(void*) * mv);
+      sd[k].maps = reinterpret_cast<const void* const*>(dev + b_sets + b_groups) + (size_t)k * mv;
+      sd[k].scales = fsets[k].scales;
+      sd[k].U = a->U.as<float>();
+      sd[k].beta = a->beta.as<float2>();
+      sd[k].counts = a->counts.as<uint32_t>();
+      sd[k].stats = a->dstats.as<unsigned long long>();
+      sd[k].D = a->D;
+      sd[k].view_base = v0;
+    }
+    if (b_groups) memcpy(up + b_sets, groups.data(), b_groups);
+    HIP_TRY(hipMemcpyAsync(dev, up, bytes, hipMemcpyHostToDevice, s));
     BlendArgs ba;
     ba.rec = ws.rec.as<Rec>();
     ba.ids = ids;
     ba.ranges = ws.ranges.as<uint2>();
     ba.geom = ws.geom.as<ViewGeom>();
-    ba.maps = ws.maps.as<const void*>();
-    ba.fp8_scales = scales;
-    ba.view_base = v0;
     ba.n = n;
-    ba.D = a->D;
     ba.tiles_stride = stride;
-    ba.U = a->U.as<float>();
-    ba.beta = a->beta.as<float2>();
-    ba.counts = a->counts.as<uint32_t>();
-    ba.stats = a->dstats.as<unsigned long long>();
+    ba.sets = reinterpret_cast<const SetDesc*>(dev);
+    ba.groups = reinterpret_cast<const ChanGroup*>(dev + b_sets);
+    ba.ngroups = (int32_t)groups.size();
+    ba.max_width = max_width;
+    ba.small_dg = small_dg;
     {
       std::lock_guard<std::mutex> pk(g_prof_mu);
       if (g_prof_on) {
@@ -441,16 +528,26 @@ lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, co
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, s));
-        HIP_TRY(launch_blend(ba, dtype, mv, max_tiles, s));
+        HIP_TRY(launch_blend(ba, dtype, mv, s));
         HIP_TRY(hipEventRecord(e1, s));
         g_prof_events.emplace_back(e0, e1);
       } else {
-        HIP_TRY(launch_blend(ba, dtype, mv, max_tiles, s));
+        HIP_TRY(launch_blend(ba, dtype, mv, s));
       }
     }
     if (v0 + mc < m) HIP_TRY(hipStreamSynchronize(s));  // staging buffers are reused
   }
   return LV_OK;
+}
+
+lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, const void* const* maps,
+                               lv_dtype dtype, const float* scales, void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  lv_feature_set fs;
+  fs.acc = a;
+  fs.maps = maps;
+  fs.scales = scales;
+  return lv_uplift_accumulate_sets(cams, m, &fs, 1, dtype, stream);
 }
 
 lv_status lv_accum_finalize(lv_accum* a, float* out_feat, float* out_wsum, float* out_sum,
@@ -522,35 +619,62 @@ lv_status lv_profile_stop(int64_t* launches, double* total_ms, double* per_launc
   return LV_OK;
 }
 
+lv_status lv_uplift_sets(lv_scene* sc, const lv_camera* cams, int32_t m, const lv_uplift_set* sets,
+                         int32_t nsets, lv_dtype dtype, void* stream) {
+  if (!sc) return fail(LV_ERR_INVALID_ARG, "scene is NULL");
+  if (nsets < 1 || nsets > kMaxSets || !sets)
+    return fail(LV_ERR_INVALID_ARG, "nsets = %d out of [1, %d]", nsets, kMaxSets);
+  for (int k = 0; k < nsets; k++) {
+    if (sets[k].D < 1 || sets[k].D > 4096)
+      return fail(LV_ERR_INVALID_ARG, "set %d: D = %d out of [1, 4096]", k, sets[k].D);
+    if (sc->n > 0 && !sets[k].out_feat) return fail(LV_ERR_INVALID_ARG, "set %d: out_feat is NULL", k);
+  }
+  lv_status st = check_cams(cams, m);
+  if (st != LV_OK) return st;
+  for (int k = 0; k < nsets; k++) {
+    st = check_maps(sets[k].maps, m, dtype, sets[k].scales);
+    if (st != LV_OK) return st;
+  }
+  // transient accumulators whose buffers live in the stream's workspace
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace& ws = *workspace_for(s);
+  std::lock_guard<std::mutex> alk(ws.accmu);
+  lv_accum acc[kMaxSets];
+  lv_feature_set fs[kMaxSets];
+  size_t n1 = (size_t)(sc->n > 0 ? sc->n : 1);
+  for (int k = 0; k < nsets; k++) {
+    {
+      std::lock_guard<std::mutex> lk(ws.mu);
+      HIP_TRY(ws.accUs[k].ensure(sizeof(float) * n1 * sets[k].D, s));
+      HIP_TRY(ws.accBs[k].ensure(sizeof(float2) * n1, s));
+    }
+    acc[k].scene = sc;
+    acc[k].D = sets[k].D;
+    acc[k].U.p = ws.accUs[k].p;
+    acc[k].beta.p = ws.accBs[k].p;
+    fs[k].acc = &acc[k];
+    fs[k].maps = sets[k].maps;
+    fs[k].scales = sets[k].scales;
+    st = lv_accum_reset(&acc[k], stream);
+    if (st != LV_OK) break;
+  }
+  if (st == LV_OK) st = lv_uplift_accumulate_sets(cams, m, fs, nsets, dtype, stream);
+  for (int k = 0; k < nsets && st == LV_OK; k++)
+    st = lv_accum_finalize(&acc[k], sets[k].out_feat, sets[k].out_wsum, nullptr, stream);
+  for (int k = 0; k < nsets; k++) acc[k].U.p = acc[k].beta.p = nullptr;  // owned by the workspace
+  return st;
+}
+
 lv_status lv_uplift(lv_scene* sc, const lv_camera* cams, int32_t m, const void* const* maps,
                     lv_dtype dtype, const float* scales, int32_t D, float* out_feat,
                     float* out_wsum, void* stream) {
-  if (!sc) return fail(LV_ERR_INVALID_ARG, "scene is NULL");
-  if (D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "D = %d out of [1, 4096]", D);
-  if (sc->n > 0 && !out_feat) return fail(LV_ERR_INVALID_ARG, "out_feat is NULL");
-  lv_status st = check_cams(cams, m);
-  if (st != LV_OK) return st;
-  st = check_maps(maps, m, dtype, scales);
-  if (st != LV_OK) return st;
-  // a transient accumulator whose buffers live in the stream's workspace
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Workspace& ws = *workspace_for(s);
-  lv_accum a;
-  a.scene = sc;
-  a.D = D;
-  {
-    std::lock_guard<std::mutex> lk(ws.mu);
-    size_t n1 = (size_t)(sc->n > 0 ? sc->n : 1);
-    HIP_TRY(ws.accU.ensure(sizeof(float) * n1 * D, s));
-    HIP_TRY(ws.accB.ensure(sizeof(float2) * n1, s));
-    a.U.p = ws.accU.p;
-    a.beta.p = ws.accB.p;
-  }
-  st = lv_accum_reset(&a, stream);
-  if (st == LV_OK) st = lv_uplift_accumulate(&a, cams, m, maps, dtype, scales, stream);
-  if (st == LV_OK) st = lv_accum_finalize(&a, out_feat, out_wsum, nullptr, stream);
-  a.U.p = a.beta.p = nullptr;  // owned by the workspace
-  return st;
+  lv_uplift_set set;
+  set.maps = maps;
+  set.scales = scales;
+  set.D = D;
+  set.out_feat = out_feat;
+  set.out_wsum = out_wsum;
+  return lv_uplift_sets(sc, cams, m, &set, 1, dtype, stream);
 }
 
 lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,

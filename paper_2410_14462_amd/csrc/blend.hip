@@ -5,7 +5,7 @@
 // accumulators U_i and beta_i.  W is never materialised.
 //
 // One workgroup = one wave64 = one 8x8 quadrant of a 16x16 tile (one pixel
-// per lane) x one group of DG channels.  Waves never wait for each other: no
+// per lane) x one group of channels.  Waves never wait for each other: no
 // barriers, a wave retires as soon as its 64 pixels are done.  Per step of 32
 // Gaussians of the tile's list:
 //   0. lane j loads Gaussian j's record (vector loads, all in flight
@@ -13,17 +13,21 @@
 //      quadrant (exact minimum of the conic over the quadrant, conservative
 //      slack); a ballot gives the step's hit mask;
 //   A. walk: each lane evaluates the hit Gaussians for its pixel in order
-//      (record fields broadcast with readlane), keeping w in VGPRs;
-//   B. accumulate and scatter: per hit Gaussian with some w > 0, the wave
-//      visits those lanes and sums w * F (DG = 64: one channel per lane, w by
-//      readlane, eight feature reads in flight; DG < 64: 64/DG pixel slots of
-//      DG channels, w by permute, slots reduced by shuffles), then issues one
-//      global atomic per channel and one compensated update of beta.
+//      (record fields broadcast with readlane), branch-free, w kept in VGPRs;
+//   B. accumulate and scatter, per hit Gaussian with some w > 0:
+//      wide kernel (any number of feature sets, up to 64 channels per wave
+//        plus 4 tail channels): one channel per lane; the rows of 8 pixels
+//        holding a contribution are visited with compile-time lanes and LDS
+//        offsets (features staged pixel-major, 64 words per pixel);
+//        tail channels stay in registers and are reduced across the wave;
+//      small kernel (one set, D <= 32): 64/DG pixel slots of DG channels;
+//      then one global atomic per channel and a compensated beta update.
 #include "lv_internal.h"
 
 namespace lv {
 
 namespace {
+
 
 template <lv_dtype DT>
 __device__ __forceinline__ float load_feature(const void* map, int64_t idx, float scale) {
@@ -83,206 +87,370 @@ __device__ __forceinline__ float wave_sum(float x) {
   return readlane_f(x, 63);
 }
 
-template <lv_dtype DT, int DG, bool FLDS>
-__global__ __launch_bounds__(64) void blend_kernel(
-    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
-    const ViewGeom* __restrict__ geom, const void* const* __restrict__ maps,
-    const float* __restrict__ fp8_scales, int view_base, int64_t n, int D, int tiles_stride,
-    float* __restrict__ U, float2* __restrict__ beta, uint32_t* __restrict__ counts,
-    unsigned long long* __restrict__ stats) {
-  constexpr int G = kChunk;
-  constexpr int SLOTS = 64 / DG;  // pixel slots per wave in step B
-  extern __shared__ float Fs[];   // [64][DG] when FLDS
+// The quadrant a workgroup handles.  Workgroups go to the 8 XCDs
+// round-robin, so the four quadrant waves of a tile get ids that are equal
+// mod 8 and consecutive within the XCD: they share that XCD's L2 for the
+// tile's records.
+struct Quad {
+  int v, tile, cg, qx, qy;
+  uint2 rg;
+  ViewGeom g;
+};
 
-  const int v = blockIdx.y, quad = blockIdx.x & 3, tile = blockIdx.x >> 2, cg = blockIdx.z;
-  const ViewGeom g = geom[v];
-  if (tile >= g.TX * g.TY) return;
-  const uint2 rg = ranges[(int64_t)v * tiles_stride + tile];
-  if (rg.y <= rg.x) return;
-  const int lane = threadIdx.x;
-  const int tx = tile % g.TX, ty = tile / g.TX;
-  const int qx = tx * kTile + (quad & 1) * 8, qy = ty * kTile + (quad >> 1) * 8;
-  if (qx >= g.W || qy >= g.H) return;  // quadrant entirely outside the image
-  const int px = qx + (lane & 7), py = qy + (lane >> 3);
-  const bool inside = px < g.W && py < g.H;
-  const int c0 = cg * DG;
-  const int dv = D - c0 < DG ? D - c0 : DG;  // valid channels in this group
-  const void* map = maps[v];
-  float fsc = 1.0f;  // FP8 scale of this lane's channel
-  const int slot = lane / DG, ch = lane - slot * DG;
-  if constexpr (DT == LV_FP8_E4M3) {
-    if (ch < dv) fsc = fp8_scales[(int64_t)(view_base + v) * D + c0 + ch];
+__device__ __forceinline__ bool decode_quad(const uint2* __restrict__ ranges,
+                                            const ViewGeom* __restrict__ geom, int tiles_stride,
+                                            int nviews, int ngroups, Quad& q) {
+  const uint32_t L = blockIdx.x;
+  const uint32_t kx = L >> 3;
+  const uint32_t work = ((kx >> 2) << 3) | (L & 7u);
+  if (work >= (uint32_t)tiles_stride * (uint32_t)nviews * (uint32_t)ngroups) return false;
+  const int quad = (int)(kx & 3u);
+  q.tile = (int)(work % (uint32_t)tiles_stride);
+  q.v = (int)((work / (uint32_t)tiles_stride) % (uint32_t)nviews);
+  q.cg = (int)(work / ((uint32_t)tiles_stride * (uint32_t)nviews));
+  q.g = geom[q.v];
+  if (q.tile >= q.g.TX * q.g.TY) return false;
+  q.rg = ranges[(int64_t)q.v * tiles_stride + q.tile];
+  if (q.rg.y <= q.rg.x) return false;
+  const int tx = q.tile % q.g.TX, ty = q.tile / q.g.TX;
+  q.qx = tx * kTile + (quad & 1) * 8;
+  q.qy = ty * kTile + (quad >> 1) * 8;
+  return q.qx < q.g.W && q.qy < q.g.H;  // else the quadrant lies outside the image
+}
+
+// Per-lane walk state.
+struct Walk {
+  float pxf, pyf, qx0, qx1, qy0, qy1, T;
+  bool alive;
+  uint32_t ncontrib;  // this pixel's counted Gaussians (statistics only)
+};
+
+__device__ __forceinline__ void walk_init(const Quad& q, int lane, Walk& s) {
+  const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
+  s.pxf = (float)px + 0.5f;
+  s.pyf = (float)py + 0.5f;
+  s.qx0 = (float)q.qx + 0.5f;
+  s.qx1 = (float)q.qx + 7.5f;
+  s.qy0 = (float)q.qy + 0.5f;
+  s.qy1 = (float)q.qy + 7.5f;
+  s.T = 1.0f;
+  s.alive = px < q.g.W && py < q.g.H;
+  s.ncontrib = 0;
+}
+
+// Step 0: records of Gaussians [base, base + cnt) one per lane; hit mask.
+__device__ __forceinline__ uint64_t step_records(const Rec* __restrict__ vrec,
+                                                 const uint32_t* __restrict__ ids, uint32_t base,
+                                                 int cnt, int lane, const Walk& s, float4& q0,
+                                                 float4& q1, uint32_t& my_id) {
+  q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  q1 = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+  my_id = 0;
+  if (lane < cnt) {
+    my_id = ids[base + lane];
+    q0 = vrec[my_id].r0;
+    q1 = vrec[my_id].r1;
   }
+  const bool hit = lane < cnt &&
+                   region_hits(q0, q1, s.qx0 - q0.x, s.qx1 - q0.x, s.qy0 - q0.y, s.qy1 - q0.y);
+  return __ballot(hit);
+}
 
-  if constexpr (FLDS) {
-    // this quadrant's features for channels [c0, c0 + dv); pixel p = lane index
-    for (int e = lane; e < 64 * DG; e += 64) {
-      int p = e / DG, c = e - p * DG;
-      int gx = qx + (p & 7), gy = qy + (p >> 3);
-      float val = 0.0f;
-      if (c < dv && gx < g.W && gy < g.H) {
-        float sc = 1.0f;
-        if constexpr (DT == LV_FP8_E4M3) sc = fp8_scales[(int64_t)(view_base + v) * D + c0 + c];
-        val = load_feature<DT>(map, ((int64_t)gy * g.W + gx) * D + c0 + c, sc);
-      }
-      Fs[e] = val;
-    }
-    __syncthreads();
-  }
-  // feature of channel ch at the wave's pixel l
-  auto feat = [&](int l) -> float {
-    if constexpr (FLDS) {
-      return Fs[l * DG + ch];
-    } else {
-      const int gx = qx + (l & 7), gy = qy + (l >> 3);
-      if (ch >= dv || gx >= g.W || gy >= g.H) return 0.0f;
-      return load_feature<DT>(map, ((int64_t)gy * g.W + gx) * D + c0 + ch, fsc);
-    }
-  };
-
-  const Rec* vrec = rec + (int64_t)v * n;
-  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
-  const float qx0 = (float)qx + 0.5f, qx1 = (float)qx + 7.5f;
-  const float qy0 = (float)qy + 0.5f, qy1 = (float)qy + 7.5f;
-  float T = 1.0f;
-  bool alive = inside;
-  uint32_t ncontrib = 0;  // this pixel's counted Gaussians (statistics only)
-
-  for (uint32_t base = rg.x; base < rg.y; base += G) {
-    if (__ballot(alive) == 0ull) break;
-    const int cnt = (int)(rg.y - base < (uint32_t)G ? rg.y - base : (uint32_t)G);
-
-    // ---- 0: records of this step, one per lane; quadrant test
-    float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
-    uint32_t my_id = 0;
-    if (lane < cnt) {
-      my_id = ids[base + lane];
-      q0 = vrec[my_id].r0;
-      q1 = vrec[my_id].r1;
-    }
-    const bool lane_hit =
-        lane < cnt && region_hits(q0, q1, qx0 - q0.x, qx1 - q0.x, qy0 - q0.y, qy1 - q0.y);
-    const uint64_t hits = __ballot(lane_hit);
-
-    // ---- A: walk
-    float wv[G];
+// Step A: the front-to-back walk of the hit Gaussians, branch-free; every
+// decision is the S32 sequence (see lv_internal.h).
+template <int G>
+__device__ __forceinline__ void step_walk(uint64_t hits, float4 q0, float4 q1, Walk& s,
+                                          float (&wv)[G]) {
 #pragma unroll
-    for (int j = 0; j < G; j++) {
-      wv[j] = 0.0f;
-      if ((hits >> j) & 1ull) {
-        const float ux = readlane_f(q0.x, j), uy = readlane_f(q0.y, j);
-        const float A = readlane_f(q0.z, j), B = readlane_f(q0.w, j);
-        const float C = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
-        // branch-free: every lane evaluates, selects keep the walk exact
-        float dx = pxf - ux, dy = pyf - uy;
-        float pw = (B * dx) * dy;
-        pw = __builtin_fmaf(C * dy, dy, pw);
-        pw = __builtin_fmaf(A * dx, dx, pw);
-        pw = fminf(pw, 0.0f);
-        const float al = fminf(kAlphaMax, op * exp32(pw));
-        const bool ok = alive && al >= kAlphaMin;
-        const float Tn = T * (1.0f - al);
-        const bool stop = ok && Tn < kTEps;
-        const bool take = ok && !stop;
-        wv[j] = take ? al * T : 0.0f;
-        T = take ? Tn : T;
-        alive = alive && !stop;
-        ncontrib += take ? 1u : 0u;
+  for (int j = 0; j < G; j++) {
+    wv[j] = 0.0f;
+    if ((hits >> j) & 1ull) {
+      const float ux = readlane_f(q0.x, j), uy = readlane_f(q0.y, j);
+      const float A = readlane_f(q0.z, j), B = readlane_f(q0.w, j);
+      const float C = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
+      float dx = s.pxf - ux, dy = s.pyf - uy;
+      float pw = (B * dx) * dy;
+      pw = __builtin_fmaf(C * dy, dy, pw);
+      pw = __builtin_fmaf(A * dx, dx, pw);
+      pw = fminf(pw, 0.0f);
+      const float al = fminf(kAlphaMax, op * exp32(pw));
+      const bool ok = s.alive && al >= kAlphaMin;
+      const float Tn = s.T * (1.0f - al);
+      const bool stop = ok && Tn < kTEps;
+      const bool take = ok && !stop;
+      wv[j] = take ? al * s.T : 0.0f;
+      s.T = take ? Tn : s.T;
+      s.alive = s.alive && !stop;
+      s.ncontrib += take ? 1u : 0u;
+    }
+  }
+}
+
+__device__ __forceinline__ void quad_stats(const Walk& s, int lane, unsigned long long* stats) {
+  const uint64_t covered = __ballot(s.ncontrib != 0u);
+  uint64_t c = s.ncontrib;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  if (lane == 0) {
+    atomicAdd(&stats[1], (unsigned long long)c);
+    atomicAdd(&stats[0], (unsigned long long)__popcll(covered));
+  }
+}
+
+// ---------------------------------------------------------------- wide kernel
+// Any number of feature sets; the workgroup's channel group has up to 64
+// channels made of segments of the sets (lane = channel) plus up to 4 tail
+// channels (lane = pixel, reduced across the wave).
+template <lv_dtype DT>
+__global__ __launch_bounds__(64) void blend_wide_kernel(
+    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
+    const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
+  constexpr int G = kChunk;
+  extern __shared__ float Fs[];  // [64 pixels][64 channels], pixel-major
+  Quad q;
+  if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
+  const int lane = threadIdx.x;
+  const ChanGroup& grp = groups[q.cg];
+  const int width = grp.width, nseg = grp.nseg, ntail = grp.ntail;
+  const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
+  const bool inside = px < q.g.W && py < q.g.H;
+
+  // Stage the quadrant's features, one segment at a time (uniform loop):
+  // wide segments row by row (lane = channel, coalesced), narrow ones channel
+  // by channel (lane = pixel).  This lane's output channel is noted on the way.
+  float* out0 = nullptr;
+  int D0 = 0;
+  for (int k = 0; k < nseg; k++) {
+    const SetDesc& sd = sets[grp.set[k]];
+    const int D = sd.D, c0 = grp.c0[k], vc0 = grp.vc0[k], cnt = grp.cnt[k];
+    const void* map = sd.maps[q.v];
+    const float* scl = nullptr;
+    if constexpr (DT == LV_FP8_E4M3) scl = sd.scales + (int64_t)(sd.view_base + q.v) * D + c0;
+    if (lane >= vc0 && lane < vc0 + cnt) {
+      out0 = sd.U + c0 + (lane - vc0);
+      D0 = D;
+    }
+    if (cnt >= 16) {
+      const bool mine = lane < cnt;
+      float sc = 1.0f;
+      if constexpr (DT == LV_FP8_E4M3) sc = mine ? scl[lane] : 1.0f;
+      for (int p = 0; p < 64; p++) {
+        const int gx = q.qx + (p & 7), gy = q.qy + (p >> 3);
+        float val = 0.0f;
+        if (mine && gx < q.g.W && gy < q.g.H)
+          val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * D + c0 + lane, sc);
+        if (mine) Fs[p * 64 + vc0 + lane] = val;
+      }
+    } else {
+      for (int c = 0; c < cnt; c++) {
+        float sc = 1.0f;
+        if constexpr (DT == LV_FP8_E4M3) sc = scl[c];
+        float val = 0.0f;
+        if (inside) val = load_feature<DT>(map, ((int64_t)py * q.g.W + px) * D + c0 + c, sc);
+        Fs[lane * 64 + vc0 + c] = val;
       }
     }
+  }
+  // tail channels: this lane's pixel, in registers
+  float ft[kMaxTail];
+  float* tout[kMaxTail];
+  int tD[kMaxTail];
+#pragma unroll
+  for (int t = 0; t < kMaxTail; t++) {
+    ft[t] = 0.0f;
+    tout[t] = nullptr;
+    tD[t] = 0;
+    if (t < ntail) {
+      const SetDesc& sd = sets[grp.tset[t]];
+      const int c = grp.tc[t];
+      float sc = 1.0f;
+      if constexpr (DT == LV_FP8_E4M3) sc = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
+      if (inside) ft[t] = load_feature<DT>(sd.maps[q.v], ((int64_t)py * q.g.W + px) * sd.D + c, sc);
+      tout[t] = sd.U + c;
+      tD[t] = sd.D;
+    }
+  }
+  __syncthreads();
+  const float* f0 = Fs + lane;  // this lane's channel of pixel 0 (lanes >= width idle)
+  const int beta_sets = grp.beta_sets;
+  float2* my_beta = nullptr;
+  uint32_t* my_counts = nullptr;
+  if (lane < kMaxSets && ((beta_sets >> lane) & 1)) {
+    my_beta = sets[lane].beta;
+    my_counts = sets[lane].counts;
+  }
 
-    // ---- B: accumulate and scatter, one Gaussian at a time
+  Walk s;
+  walk_init(q, lane, s);
+  const Rec* vrec = rec + (int64_t)q.v * n;
+  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
+    if (__ballot(s.alive) == 0ull) break;
+    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
+    float4 q0, q1;
+    uint32_t my_id;
+    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
+    float wv[G];
+    step_walk<G>(hits, q0, q1, s, wv);
+
 #pragma unroll
     for (int j = 0; j < G; j++) {
       if ((hits >> j) & 1ull) {
         const uint64_t msk = __ballot(wv[j] > 0.0f);
         if (msk) {
-          float acc = 0.0f, ws;
-          if constexpr (SLOTS == 1) {
-            // rows of 8 pixels of the quadrant that hold a contribution; within
-            // an active row every pixel is visited (w = 0 adds nothing): lanes
-            // and LDS offsets are compile-time constants, no scalar bit loops
-            const int wj = __float_as_int(wv[j]);
+          const int wj = __float_as_int(wv[j]);
+          float acc0 = 0.0f;
 #pragma unroll
-            for (int r = 0; r < 8; r++) {
-              if ((msk >> (8 * r)) & 0xFFull) {
-                float wl[8], fv[8];
+          for (int r = 0; r < 8; r++) {
+            if ((msk >> (8 * r)) & 0xFFull) {
+              float wl[8], fv[8];
 #pragma unroll
-                for (int k = 0; k < 8; k++) {
-                  wl[k] = __int_as_float(__builtin_amdgcn_readlane(wj, 8 * r + k));
-                  fv[k] = feat(8 * r + k);
-                }
-#pragma unroll
-                for (int k = 0; k < 8; k++) acc = __builtin_fmaf(wl[k], fv[k], acc);
+              for (int k = 0; k < 8; k++) {
+                wl[k] = __int_as_float(__builtin_amdgcn_readlane(wj, 8 * r + k));
+                fv[k] = f0[(8 * r + k) * 64];
               }
-            }
-            ws = wave_sum(wv[j]);
-          } else {
-            // slot s takes the pixels p = s (mod SLOTS) of the wave
-            uint64_t sel = 0ull;
 #pragma unroll
-            for (int k = 0; k < 64; k += SLOTS) sel |= 1ull << k;
-            uint64_t mm = msk & (sel << slot);
-            float wsl = 0.0f;
-            while (__ballot(mm != 0ull)) {
-              const bool has = mm != 0ull;
-              const int l = has ? (int)__builtin_ctzll(mm) : 0;
-              if (has) mm &= mm - 1ull;
-              const float wl = __shfl(wv[j], l, 64);  // every lane takes part
-              if (has) {
-                acc = __builtin_fmaf(wl, feat(l), acc);
-                wsl += wl;
-              }
+              for (int k = 0; k < 8; k++) acc0 = __builtin_fmaf(wl[k], fv[k], acc0);
             }
-#pragma unroll
-            for (int o = DG; o < 64; o <<= 1) {
-              acc += __shfl_down(acc, o, 64);
-              wsl += __shfl_down(wsl, o, 64);
-            }
-            ws = wsl;
           }
-          const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-          if (lane < dv && acc != 0.0f) unsafeAtomicAdd(&U[(int64_t)gid * D + c0 + lane], acc);
-          if (lane == 0 && cg == 0) {
-            twosum_atomic_add(&beta[gid], ws);
-            if (counts) atomicAdd(&counts[gid], (uint32_t)__popcll(msk));
+          const float ws = wave_sum(wv[j]);
+          const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
+          if (out0 && acc0 != 0.0f) unsafeAtomicAdd(out0 + gid * D0, acc0);
+          if (ntail) {
+#pragma unroll
+            for (int t = 0; t < kMaxTail; t++) {
+              if (t < ntail) {
+                const float at = wave_sum(wv[j] * ft[t]);
+                if (lane == 0 && at != 0.0f) unsafeAtomicAdd(tout[t] + gid * tD[t], at);
+              }
+            }
+          }
+          if (my_beta) {
+            twosum_atomic_add(my_beta + gid, ws);
+            if (my_counts) atomicAdd(my_counts + gid, (uint32_t)__popcll(msk));
           }
         }
       }
     }
   }
-  if (counts && cg == 0) {
-    // covered pixels and contributions of this quadrant
-    const uint64_t covered = __ballot(ncontrib != 0u);
-    uint64_t s = ncontrib;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if (lane == 0) {
-      atomicAdd(&stats[1], (unsigned long long)s);
-      atomicAdd(&stats[0], (unsigned long long)__popcll(covered));
-    }
+  // statistics go to the first set that takes this group's beta
+  if (beta_sets) {
+    unsigned long long* st = sets[__builtin_ctz(beta_sets)].stats;
+    if (st) quad_stats(s, lane, st);
   }
 }
 
-template <lv_dtype DT, int DG, bool FLDS>
-hipError_t launch_blend_dg(const BlendArgs& a, int m, int max_tiles, hipStream_t s) {
-  size_t lds = FLDS ? sizeof(float) * 64 * DG : 0;
-  int groups = (a.D + DG - 1) / DG;
-  hipLaunchKernelGGL((blend_kernel<DT, DG, FLDS>), dim3(max_tiles * 4, m, groups), dim3(64), lds, s,
-                     a.rec, a.ids, a.ranges, a.geom, a.maps, a.fp8_scales, a.view_base, a.n, a.D,
-                     a.tiles_stride, a.U, a.beta, a.counts, a.stats);
+// --------------------------------------------------------------- small kernel
+// One feature set with D <= 32 channels: 64/DG pixel slots of DG channels.
+template <lv_dtype DT, int DG>
+__global__ __launch_bounds__(64) void blend_small_kernel(
+    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
+    const SetDesc* __restrict__ sets) {
+  constexpr int G = kChunk;
+  constexpr int SLOTS = 64 / DG;
+  extern __shared__ float Fs[];  // [64][DG], pixel-major
+  Quad q;
+  if (!decode_quad(ranges, geom, tiles_stride, nviews, 1, q)) return;
+  const int lane = threadIdx.x;
+  const SetDesc& sd = sets[0];
+  const int D = sd.D;
+  const void* map = sd.maps[q.v];
+  for (int e = lane; e < 64 * DG; e += 64) {
+    const int p = e / DG, c = e - p * DG;
+    const int gx = q.qx + (p & 7), gy = q.qy + (p >> 3);
+    float val = 0.0f;
+    if (c < D && gx < q.g.W && gy < q.g.H) {
+      float sc = 1.0f;
+      if constexpr (DT == LV_FP8_E4M3) sc = sd.scales[(int64_t)(sd.view_base + q.v) * D + c];
+      val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * D + c, sc);
+    }
+    Fs[e] = val;
+  }
+  __syncthreads();
+  const int slot = lane / DG, ch = lane - slot * DG;
+  const float* fbase = Fs + ch;
+  uint64_t sel = 0ull;
+#pragma unroll
+  for (int k = 0; k < 64; k += SLOTS) sel |= 1ull << k;
+  sel <<= slot;  // slot s takes the pixels p = s (mod SLOTS)
+
+  Walk s;
+  walk_init(q, lane, s);
+  const Rec* vrec = rec + (int64_t)q.v * n;
+  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
+    if (__ballot(s.alive) == 0ull) break;
+    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
+    float4 q0, q1;
+    uint32_t my_id;
+    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
+    float wv[G];
+    step_walk<G>(hits, q0, q1, s, wv);
+
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+      if ((hits >> j) & 1ull) {
+        const uint64_t msk = __ballot(wv[j] > 0.0f);
+        if (msk) {
+          float acc = 0.0f, wsl = 0.0f;
+          uint64_t mm = msk & sel;
+          while (__ballot(mm != 0ull)) {
+            const bool has = mm != 0ull;
+            const int l = has ? (int)__builtin_ctzll(mm) : 0;
+            if (has) mm &= mm - 1ull;
+            const float wl = __shfl(wv[j], l, 64);  // every lane takes part
+            if (has) {
+              acc = __builtin_fmaf(wl, fbase[l * DG], acc);
+              wsl += wl;
+            }
+          }
+#pragma unroll
+          for (int o = DG; o < 64; o <<= 1) {
+            acc += __shfl_down(acc, o, 64);
+            wsl += __shfl_down(wsl, o, 64);
+          }
+          const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
+          if (lane < D && acc != 0.0f) unsafeAtomicAdd(&sd.U[gid * D + lane], acc);
+          if (lane == 0) {
+            twosum_atomic_add(&sd.beta[gid], wsl);
+            if (sd.counts) atomicAdd(&sd.counts[gid], (uint32_t)__popcll(msk));
+          }
+        }
+      }
+    }
+  }
+  if (sd.stats) quad_stats(s, lane, sd.stats);
+}
+
+template <lv_dtype DT, int DG>
+hipError_t launch_small(const BlendArgs& a, int m, hipStream_t s) {
+  int64_t work = (int64_t)a.tiles_stride * m;
+  int64_t blocks = (work + 7) / 8 * 32;  // 4 quadrants per tile, whole rounds of 8 XCDs
+  hipLaunchKernelGGL((blend_small_kernel<DT, DG>), dim3((unsigned)blocks), dim3(64),
+                     sizeof(float) * 64 * DG, s, a.rec, a.ids, a.ranges, a.geom, a.n,
+                     a.tiles_stride, m, a.sets);
   return hipGetLastError();
 }
 
 template <lv_dtype DT>
-hipError_t launch_blend_t(const BlendArgs& a, int m, int max_tiles, hipStream_t s) {
-  if (a.D <= 1) return launch_blend_dg<DT, 1, true>(a, m, max_tiles, s);
-  if (a.D <= 2) return launch_blend_dg<DT, 2, true>(a, m, max_tiles, s);
-  if (a.D <= 4) return launch_blend_dg<DT, 4, true>(a, m, max_tiles, s);
-  if (a.D <= 8) return launch_blend_dg<DT, 8, true>(a, m, max_tiles, s);
-  if (a.D <= 16) return launch_blend_dg<DT, 16, true>(a, m, max_tiles, s);
-  if (a.D <= 32) return launch_blend_dg<DT, 32, true>(a, m, max_tiles, s);
-  return launch_blend_dg<DT, 64, true>(a, m, max_tiles, s);
+hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
+  if (a.small_dg > 0) {
+    switch (a.small_dg) {
+      case 1: return launch_small<DT, 1>(a, m, s);
+      case 2: return launch_small<DT, 2>(a, m, s);
+      case 4: return launch_small<DT, 4>(a, m, s);
+      case 8: return launch_small<DT, 8>(a, m, s);
+      case 16: return launch_small<DT, 16>(a, m, s);
+      case 32: return launch_small<DT, 32>(a, m, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  int64_t work = (int64_t)a.tiles_stride * m * a.ngroups;
+  int64_t blocks = (work + 7) / 8 * 32;
+  hipLaunchKernelGGL(blend_wide_kernel<DT>, dim3((unsigned)blocks), dim3(64),
+                     sizeof(float) * 64 * 64, s, a.rec, a.ids, a.ranges, a.geom, a.n,
+                     a.tiles_stride, m, a.sets, a.groups, a.ngroups);
+  return hipGetLastError();
 }
 
 __global__ void finalize_kernel(const float* __restrict__ U, const float2* __restrict__ beta,
@@ -301,12 +469,12 @@ __global__ void finalize_kernel(const float* __restrict__ U, const float2* __res
 
 }  // namespace
 
-hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, int max_tiles, hipStream_t s) {
-  if (m == 0 || max_tiles == 0) return hipSuccess;
+hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s) {
+  if (m == 0 || a.tiles_stride == 0) return hipSuccess;
   switch (dtype) {
-    case LV_F32: return launch_blend_t<LV_F32>(a, m, max_tiles, s);
-    case LV_BF16: return launch_blend_t<LV_BF16>(a, m, max_tiles, s);
-    case LV_FP8_E4M3: return launch_blend_t<LV_FP8_E4M3>(a, m, max_tiles, s);
+    case LV_F32: return launch_blend_t<LV_F32>(a, m, s);
+    case LV_BF16: return launch_blend_t<LV_BF16>(a, m, s);
+    case LV_FP8_E4M3: return launch_blend_t<LV_FP8_E4M3>(a, m, s);
   }
   return hipErrorInvalidValue;
 }

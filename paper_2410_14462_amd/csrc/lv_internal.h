@@ -133,23 +133,49 @@ hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off, con
 hipError_t launch_ranges(const uint32_t* pair_key, int64_t P, int tiles_stride, uint2* ranges,
                          hipStream_t s);
 
+constexpr int kMaxSets = 8;   // feature sets per blend launch
+constexpr int kMaxSegs = 4;   // set segments per channel group
+
+// One feature set of a blend launch (device array).
+struct SetDesc {
+  const void* const* maps;    // [views] device pointers, HWC [H][W][D]
+  const float* scales;        // FP8: [all views][D] scales, else null
+  float* U;                   // [n][D]
+  float2* beta;               // [n] compensated (hi, lo)
+  uint32_t* counts;           // [n] or null
+  unsigned long long* stats;  // [2] covered pixels, contributions; or null
+  int32_t D;
+  int32_t view_base;          // index of the launch's first view in scales
+};
+
+constexpr int kMaxTail = 4;   // channels of a group kept in registers
+
+// The channels one workgroup handles.  Main part: segments [vc0, vc0 + cnt)
+// of the group's (<= 64) channels taken from set `set`, channels
+// [c0, c0 + cnt), vc0 ascending from 0, one channel per lane.  Tail: up to 4
+// further single channels (set tset[t], channel tc[t]) reduced across the
+// wave.  beta_sets: bit s set if this group adds beta (and counts and
+// statistics) of set s.
+struct ChanGroup {
+  int32_t width, nseg, ntail, beta_sets;
+  int32_t set[kMaxSegs], c0[kMaxSegs], vc0[kMaxSegs], cnt[kMaxSegs];
+  int32_t tset[kMaxTail], tc[kMaxTail];
+};
+
 struct BlendArgs {
   const Rec* rec;              // [m][n]
   const uint32_t* ids;         // sorted pair values (Gaussian ids)
   const uint2* ranges;         // [m][tiles_stride]
   const ViewGeom* geom;        // [m]
-  const void* const* maps;     // [m] device pointers
-  const float* fp8_scales;     // [m][D] or null
-  int32_t view_base;           // index of the chunk's first view in fp8_scales
   int64_t n;
-  int32_t D;
   int32_t tiles_stride;
-  float* U;                    // [n][D]
-  float2* beta;                // [n] compensated
-  uint32_t* counts;            // [n] or null; also enables the two counters below
-  unsigned long long* stats;   // [2]: covered pixels, contributions (with counts)
+  const SetDesc* sets;         // device
+  const ChanGroup* groups;     // device (wide kernel)
+  int32_t ngroups;
+  int32_t max_width;           // widest group (LDS size)
+  int32_t small_dg;            // > 0: one set of D <= small_dg <= 32 on the small kernel
 };
-hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, int max_tiles, hipStream_t s);
+hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s);
 
 hipError_t launch_finalize(const float* U, const float2* beta, int64_t n, int D, float* f,
                            float* wsum, float* usum, hipStream_t s);
