@@ -101,6 +101,8 @@ struct Workspace {
   std::mutex mu;
   std::mutex accmu;  // held by a one-call uplift while it uses accU/accB
   Buf accUs[kMaxSets], accBs[kMaxSets];
+  const uint32_t* dkey = nullptr;  // depth-sorted keys / ids of the last structure build
+  const uint32_t* dval = nullptr;
   Buf rec, key0, val0, key1, val1, rect, cnt, off, scan_tmp, hist, seg, pseg, total;
   Buf pk0, pv0, pk1, pv1, hist2, ranges, cams, geom, maps;
   HostBuf up, down;
@@ -242,6 +244,8 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
                      ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, 32, ws.hist.as<uint32_t>(),
                      &second, s));
   const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
+  ws.dkey = second ? ws.key1.as<uint32_t>() : ws.key0.as<uint32_t>();
+  ws.dval = sval;
   uint32_t* pseg = ws.pseg.as<uint32_t>();
   HIP_TRY(scan_counts(ws.cnt.as<uint32_t>(), sval, n, mv, ws.off.as<uint32_t>(), pseg, pseg + mv,
                       ws.total.as<unsigned long long>(), ws.scan_tmp.as<uint32_t>(), s));
@@ -788,11 +792,11 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
   HIP_TRY(hipMemcpy(rec.data(), ws.rec.p, sizeof(Rec) * n, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(rect.data(), ws.rect.p, 8 * n, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(cnt.data(), ws.cnt.p, 4 * n, hipMemcpyDeviceToHost));
-  // depth keys in Gaussian order: the depth sort (4 passes) left the sorted
-  // (key, id) pairs in key0/val0; scatter them back by id
+  // depth keys in Gaussian order: scatter the depth-sorted (key, id) pairs
+  // back by id
   std::vector<uint32_t> sk(n), sv(n);
-  HIP_TRY(hipMemcpy(sk.data(), ws.key0.p, 4 * n, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(sv.data(), ws.val0.p, 4 * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sk.data(), ws.dkey, 4 * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sv.data(), ws.dval, 4 * n, hipMemcpyDeviceToHost));
   for (int64_t k = 0; k < n; k++) key[sv[k]] = sk[k];
   for (int64_t i = 0; i < n; i++) {
     bool vis = cnt[i] != 0;

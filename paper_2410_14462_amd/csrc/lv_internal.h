@@ -13,7 +13,8 @@ namespace lv {
 constexpr int kTile = 16;           // tile edge in pixels
 constexpr int kBlendThreads = 256;  // one thread per pixel of a tile
 constexpr int kChunk = 32;          // Gaussians per blend step (one per lane)
-constexpr int kSortItems = 2048;    // items per radix-sort block
+constexpr int kSortItems = 4096;    // items per radix-sort block (4 waves x 1024)
+constexpr int kRadixBits = 11;      // digit bits per radix pass
 constexpr int kSortThreads = 256;
 constexpr int kViewShift = 20;      // pair key = view << 20 | tile
 
@@ -108,10 +109,11 @@ hipError_t launch_preprocess(const float4* p0, const float4* p1, const float4* p
                              uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt,
                              hipStream_t s);
 
-// Segmented stable LSD radix sort of (key, val) pairs on key bits [0, bits).
-// Segment g occupies [seg_start[g], seg_start[g] + seg_len[g]); max_len bounds
-// seg_len.  Result ends in (k0, v0) if the number of passes is even, else in
-// (k1, v1); *in_second tells which.  hist needs sort_hist_size() uint32.
+// Segmented stable LSD radix sort of (key, val) pairs on key bits [0, bits),
+// in ceil(bits / 11) passes.  Segment g occupies [seg_start[g], seg_start[g] +
+// seg_len[g]); max_len bounds seg_len.  Result ends in (k0, v0) if the number
+// of passes is even, else in (k1, v1); *in_second tells which.  hist needs
+// sort_hist_size() uint32.
 size_t sort_hist_size(int nseg, int64_t max_len);
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,

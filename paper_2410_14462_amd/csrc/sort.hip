@@ -29,37 +29,55 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
   return peers;
 }
 
+constexpr int kBins = 1 << kRadixBits;        // digit values per pass
+constexpr int kWaveItems = kSortItems / 4;    // contiguous items per wave
+
+// Per-wave digit counts of the wave's contiguous share of a block's items
+// into cnt[wave][digit] (pre-zeroed).  One ballot match per 64 items; the
+// lowest lane of each digit group adds the group size (distinct digits,
+// distinct addresses: no atomics needed).
+__device__ __forceinline__ void wave_count(const uint32_t* __restrict__ k, uint32_t lo, uint32_t hi,
+                                           int shift, int bits, uint32_t* cnt) {
+  const uint32_t mask = (1u << bits) - 1u;
+  const int lane = threadIdx.x & 63;
+  for (uint32_t r = lo; r < hi; r += 64) {
+    const uint32_t i = r + lane;
+    const bool valid = i < hi;
+    const uint32_t d = valid ? (k[i] >> shift) & mask : 0u;
+    const uint64_t act = __ballot(valid);
+    const uint64_t peers = match_digit(d, bits, act);
+    if (valid && (peers & lanemask_lt()) == 0) cnt[d] += (uint32_t)__popcll(peers);
+  }
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
-  h[t] = 0;
+  __shared__ uint32_t wc[4][kBins];
+  const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x, w = t >> 6;
+  const uint32_t len = seg_len[g];
+  const uint32_t base = (uint32_t)b * kSortItems;
+  for (int e = t; e < 4 * kBins; e += kSortThreads) (&wc[0][0])[e] = 0u;
   __syncthreads();
-  uint32_t len = seg_len[g];
-  const uint32_t* k = keys + seg_start[g];
-  uint32_t mask = (1u << bits) - 1u;
-  uint32_t base = (uint32_t)b * kSortItems;
-  for (int r = 0; r < kSortItems / kSortThreads; r++) {
-    uint32_t i = base + r * kSortThreads + t;
-    bool valid = i < len;
-    uint32_t d = valid ? (k[i] >> shift) & mask : 0u;
-    uint64_t act = __ballot(valid);
-    if (act == 0) break;
-    uint64_t peers = match_digit(d, bits, act);
-    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+  if (base < len) {
+    const uint32_t lo = base + w * kWaveItems;
+    const uint32_t hi = min(len, lo + kWaveItems);
+    if (lo < hi) wave_count(keys + seg_start[g], lo, hi, shift, bits, wc[w]);
   }
   __syncthreads();
-  hist[((size_t)g * 256 + t) * nb + b] = h[t];
+  const int nbins = 1 << bits;
+  for (int d = t; d < nbins; d += kSortThreads)
+    hist[((size_t)g * nbins + d) * nb + b] = (wc[0][d] + wc[1][d]) + (wc[2][d] + wc[3][d]);
 }
 
 // Exclusive scan, per segment, over (digit, block) in digit-major order.
-__global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__ hist, int nb) {
+__global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__ hist, int nb,
+                                                          int bits) {
   __shared__ uint32_t part[1024 / 64];
   __shared__ uint32_t carry_s;
-  int g = blockIdx.x, t = threadIdx.x;
-  uint32_t* h = hist + (size_t)g * 256 * nb;
-  size_t total = (size_t)256 * nb;
+  const int g = blockIdx.x, t = threadIdx.x;
+  const size_t total = ((size_t)1 << bits) * nb;
+  uint32_t* h = hist + (size_t)g * total;
   uint32_t carry = 0;
   for (size_t base = 0; base < total; base += 1024) {
     size_t i = base + t;
@@ -91,51 +109,57 @@ __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__
   }
 }
 
+// Stable scatter: the block counts its items per (wave, digit), turns the
+// counts into starting positions (block offset from the scan, then waves in
+// order), and each wave places its contiguous share in order, advancing its
+// own per-digit cursors -- no block barrier inside the placement loop.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb,
     const uint32_t* __restrict__ hist) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wc[kSortThreads / 64][256];
-  int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
-  int w = t >> 6;
-  uint32_t s0 = seg_start[g];
-  uint32_t len = seg_len[g];
-  uint32_t base = (uint32_t)b * kSortItems;
+  __shared__ uint32_t wc[4][kBins];
+  const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const uint32_t s0 = seg_start[g];
+  const uint32_t len = seg_len[g];
+  const uint32_t base = (uint32_t)b * kSortItems;
   if (base >= len) return;  // whole block idle (uniform)
-  run[t] = s0 + hist[((size_t)g * 256 + t) * nb + b];
-#pragma unroll
-  for (int q = 0; q < kSortThreads / 64; q++) wc[q][t] = 0;
+  for (int e = t; e < 4 * kBins; e += kSortThreads) (&wc[0][0])[e] = 0u;
   __syncthreads();
-  uint32_t mask = (1u << bits) - 1u;
-  for (int r = 0; r < kSortItems / kSortThreads; r++) {
-    uint32_t i = base + r * kSortThreads + t;
-    if (base + r * kSortThreads >= len) break;  // uniform across the block
-    bool valid = i < len;
-    uint32_t key = valid ? kin[s0 + i] : 0u;
-    uint32_t val = valid ? vin[s0 + i] : 0u;
-    uint32_t d = (key >> shift) & mask;
-    uint64_t act = __ballot(valid);
-    uint64_t peers = match_digit(d, bits, act);
-    uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
-    if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
+  const uint32_t lo = base + w * kWaveItems;
+  const uint32_t hi = min(len, lo + kWaveItems);
+  if (lo < hi) wave_count(kin + s0, lo, hi, shift, bits, wc[w]);
+  __syncthreads();
+  const int nbins = 1 << bits;
+  for (int d = t; d < nbins; d += kSortThreads) {
+    uint32_t run = s0 + hist[((size_t)g * nbins + d) * nb + b];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const uint32_t c = wc[q][d];
+      wc[q][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const uint32_t mask = (1u << bits) - 1u;
+  uint32_t* cur = wc[w];
+  for (uint32_t r = lo; r < hi; r += 64) {
+    const uint32_t i = r + lane;
+    const bool valid = i < hi;
+    const uint32_t key = valid ? kin[s0 + i] : 0u;
+    const uint32_t val = valid ? vin[s0 + i] : 0u;
+    const uint32_t d = (key >> shift) & mask;
+    const uint64_t act = __ballot(valid);
+    const uint64_t peers = match_digit(d, bits, act);
+    const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
     if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int q = 0; q < w; q++) pos += wc[q][d];
+      const uint32_t pos = cur[d] + rank;
       kout[pos] = key;
       vout[pos] = val;
     }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int q = 0; q < kSortThreads / 64; q++) {
-      add += wc[q][t];
-      wc[q][t] = 0;
-    }
-    run[t] += add;
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();  // every lane has read cur[d]
+    if (valid && rank == 0) cur[d] += (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -298,7 +322,7 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ key, int64_t P, int s
 size_t sort_hist_size(int nseg, int64_t max_len) {
   int64_t nb = (max_len + kSortItems - 1) / kSortItems;
   if (nb < 1) nb = 1;
-  return (size_t)nseg * 256 * (size_t)nb;
+  return (size_t)nseg * kBins * (size_t)nb;
 }
 
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
@@ -308,13 +332,16 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
   if (nseg == 0 || max_len == 0 || bits == 0) return hipSuccess;
   int nb = (int)((max_len + kSortItems - 1) / kSortItems);
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
-  for (int shift = 0; shift < bits; shift += 8) {
-    int pb = bits - shift < 8 ? bits - shift : 8;
+  // fewest passes of at most kRadixBits bits, widths balanced
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  for (int p = 0, shift = 0; p < passes; p++) {
+    const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
     hipLaunchKernelGGL(radix_hist_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, seg_start,
                        seg_len, shift, pb, nb, hist);
-    hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb);
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, vi, ko,
                        vo, seg_start, seg_len, shift, pb, nb, hist);
+    shift += pb;
     uint32_t* t;
     t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
