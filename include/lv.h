@@ -217,8 +217,9 @@ lv_status lv_diffuse(const lv_scene* scene, const lv_graph* graph, const void* g
 /* ------------------------------------------------------------ inspection -- */
 /* Per-view structure for verification; synchronous.  Host buffers (each
  * nullable): visible [n], depth [n] (FP32 bits of z_c), rect [n][4]
- * (x0,y0,x1,y1 tile rectangle), rec [n][6] (ux, uy, A, B, C, opacity with
- * the exponent A dx^2 + B dx dy + C dy^2), tile_start [tiles+1] and ids
+ * (x0,y0,x1,y1 tile rectangle), rec [n][8] (ux, uy, ux_lo, uy_lo, L11, L12,
+ * L22, opacity: the centre is ux + ux_lo, uy + uy_lo, the exponent
+ * -((L11 dx + L12 dy)^2 + (L22 dy)^2)), tile_start [tiles+1] and ids
  * [ids_capacity] (per tile, Gaussian indices in blending order).  *P_out
  * receives the number of (tile, Gaussian) pairs; ids is filled only when
  * ids_capacity >= P. */

@@ -45,8 +45,8 @@ def lib():
         L.orc_render_view.restype = i32
         L.orc_view_structure.argtypes = [i64, P, P, P, P, P, i32, i32, P, P, P, P, P, P]
         L.orc_view_structure.restype = i64
-        L.orc_covariance32.argtypes = [i64, P, P, P]
-        L.orc_covariance32.restype = None
+        L.orc_factor32_array.argtypes = [i64, P, P, P]
+        L.orc_factor32_array.restype = None
         L.orc_exp32_array.argtypes = [i64, P, P]
         L.orc_exp32_array.restype = None
         L.orc_num_threads.argtypes = []
@@ -170,7 +170,7 @@ class ViewStructure:
     visible: np.ndarray   # [n] bool
     depth: np.ndarray     # [n] uint32 key (bits of FP32 view-space z)
     rect: np.ndarray      # [n,4] int32 (x0, y0, x1, y1) tile rectangle
-    rec32: np.ndarray     # [n,6] f32 (ux, uy, A, B, C, opacity)
+    rec32: np.ndarray     # [n,8] f32 (ux, uy, ux_lo, uy_lo, L11, L12, L22, opacity)
     tile_start: np.ndarray  # [TX*TY+1] int64
     ids: np.ndarray       # [P] int32, per tile sorted by (depth, index)
 
@@ -188,7 +188,7 @@ def structure(scene, cam):
     vis = np.zeros(n, np.uint8)
     depth = np.zeros(n, np.uint32)
     rect = np.zeros((n, 4), np.int32)
-    rec = np.zeros((n, 6), np.float32)
+    rec = np.zeros((n, 8), np.float32)
     ts = np.zeros(TX * TY + 1, np.int64)
     ids = np.zeros(max(P, 1), np.int32)
     L.orc_view_structure(n, *[_p(a) for a in arrs], _p(c), cam.width, cam.height, _p(vis),
@@ -196,10 +196,11 @@ def structure(scene, cam):
     return ViewStructure(vis.astype(bool), depth, rect, rec, ts, ids[:P])
 
 
-def covariance32(scales, quats):
+def factor32(scales, quats):
+    """S32 covariance factor M = R diag(s), [n,3,3]; Sigma = M M^T."""
     s, q = _f32(scales), _f32(quats)
-    out = np.zeros((s.shape[0], 6), np.float32)
-    lib().orc_covariance32(s.shape[0], _p(s), _p(q), _p(out))
+    out = np.zeros((s.shape[0], 3, 3), np.float32)
+    lib().orc_factor32_array(s.shape[0], _p(s), _p(q), _p(out))
     return out
 
 

@@ -79,13 +79,17 @@ typedef struct {
     int vis;
     uint32_t depth;                 /* bits of FP32 z_c (z_c > 0 orders as unsigned) */
     int x0, y0, x1, y1;             /* tile rectangle [x0,x1) x [y0,y1)              */
-    float ux, uy, A, B, C, op;      /* S32: power = A dx^2 + B dx dy + C dy^2        */
+    float ux, uy, L11, L12, L22, op; /* S32: power = -((L11 dx + L12 dy)^2 + (L22 dy)^2) */
+    float uxl, uyl;                 /* S32: low parts of the centre (see below)      */
     double ux64, uy64, A64, B64, C64, op64;
 } orc_proj;
 
-/* Sec. 3.1: covariance from scale and rotation, Sigma = R diag(s)^2 R^T, with
- * R the rotation of the normalised quaternion (w,x,y,z).  S32 op order.     */
-static void orc_cov32(const float* s, const float* q, float out[6])
+/* Sec. 3.1: covariance from scale and rotation, Sigma = R diag(s)^2 R^T =
+ * M M^T with M = R diag(s), R the rotation of the normalised quaternion
+ * (w,x,y,z).  S32 keeps the factor M (row-major): the 2D covariance is then
+ * formed from V = T M, which avoids the cancellation that a stored Sigma
+ * suffers for thin Gaussians.                                                */
+static void orc_factor32(const float* s, const float* q, float M[9])
 {
     float n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
     float w = 1.0f, x = 0.0f, y = 0.0f, z = 0.0f;
@@ -103,15 +107,16 @@ static void orc_cov32(const float* s, const float* q, float out[6])
     R[6] = 2.0f * (x * z - w * y);
     R[7] = 2.0f * (y * z + w * x);
     R[8] = 1.0f - 2.0f * (x * x + y * y);
-    float M[9];
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) M[3 * i + j] = R[3 * i + j] * s[j];
-    static const int I[6] = {0, 0, 0, 1, 1, 2}, J[6] = {0, 1, 2, 1, 2, 2};
-    for (int e = 0; e < 6; e++) {
-        const float* a = M + 3 * I[e];
-        const float* b = M + 3 * J[e];
-        out[e] = (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
-    }
+}
+
+/* a*b - c*d to within ~1.5 ulp (Kahan's algorithm with fmaf). */
+static float orc_diff_prod(float a, float b, float c, float d)
+{
+    float w = c * d;
+    float e = fmaf(-c, d, w);
+    return fmaf(a, b, -w) + e;
 }
 
 static void orc_cov64(const float* s, const float* q, double out[6])
@@ -134,12 +139,90 @@ static void orc_cov64(const float* s, const float* q, double out[6])
     }
 }
 
+/* S32 centre.  Pixel coordinates reach ~10^3, where one FP32 ulp (6e-5 px)
+ * already moves the exponent of a compact Gaussian by ~1e-4; so the centre
+ * is carried as an unevaluated sum hi + lo of two floats, built with
+ * error-free transformations: Knuth's TwoSum, TwoProduct by fmaf, the
+ * compensated dot product Dot2 of Ogita, Rump and Oishi (SIAM J. Sci.
+ * Comput. 26(6), 2005) for x_c = R x_w + t, one Newton-style correction of
+ * the quotient x_c / z_c, and a compensated affine map u = f i + c.  lo is
+ * then kept to its 8 leading significand bits (its low 16 bits cleared), so
+ * that both halves fit a 32-bit word.                                      */
+static void orc_two_sum(float a, float b, float* s, float* e)
+{
+    float x = a + b, bb = x - a;
+    *s = x;
+    *e = (a - (x - bb)) + (b - bb);
+}
+
+static void orc_two_prod(float a, float b, float* p, float* e)
+{
+    float x = a * b;
+    *p = x;
+    *e = fmaf(a, b, -x);
+}
+
+/* hi + lo = r0 m0 + r1 m1 + r2 m2 + t (Dot2 with the extra addend t). */
+static void orc_dot3(const float* r, const float* m, float t, float* hi, float* lo)
+{
+    float p, s, h, q, e;
+    orc_two_prod(r[0], m[0], &p, &s);
+    orc_two_prod(r[1], m[1], &h, &q);
+    orc_two_sum(p, h, &p, &e);
+    s = s + (q + e);
+    orc_two_prod(r[2], m[2], &h, &q);
+    orc_two_sum(p, h, &p, &e);
+    s = s + (q + e);
+    orc_two_sum(p, t, &p, &e);
+    s = s + e;
+    *hi = p + s;
+    *lo = s - (*hi - p);
+}
+
+/* hi + lo = f (xh + xl) / (zh + zl) + c */
+static void orc_center(float f, float c, float xh, float xl, float zh, float zl, float* hi,
+                       float* lo)
+{
+    float q = xh / zh;
+    float r = fmaf(-q, zh, xh);
+    r = (r + xl) - q * zl;
+    float ql = r / zh;
+    float p, e, s, g;
+    orc_two_prod(f, q, &p, &e);
+    e = fmaf(f, ql, e);
+    orc_two_sum(p, c, &s, &g);
+    g = g + e;
+    *hi = s + g;
+    float l = g - (*hi - s);
+    uint32_t b;
+    memcpy(&b, &l, 4);
+    b &= 0xFFFF0000u;
+    memcpy(lo, &b, 4);
+}
+
+/* Offset of pixel column (or row) px from a centre hi + lo, in S32: relative
+ * to the centre of the first pixel of px's 16-pixel tile, so that the
+ * rounding is that of numbers of the size of the Gaussian, not of the image. */
+static float orc_offset(int px, float hi, float lo)
+{
+    int o = px - px % ORC_TILE;
+    float c = (hi - ((float)o + 0.5f)) + lo;
+    return (float)(px - o) - c;
+}
+
 /* Projection of one Gaussian into one view: EWA local-affine approximation
  * of the perspective map (Jacobian with x/z, y/z clamped to 1.3x the half-FoV
  * tangent), 2D covariance plus 0.3 px^2, conic = inverse, radius
- * ceil(3 sqrt(lambda_max)), 16x16 tile rectangle.  Structure in S32, values
- * in FP64 from the same FP32 inputs.                                         */
-static void orc_project(const float* mu, const float* cov32, const double* cov64, float op,
+ * ceil(3 sqrt(lambda_max)), 16x16 tile rectangle.  Values in FP64 from the
+ * same FP32 inputs, as the textbook formulas.  Structure in S32: x_c, y_c,
+ * z_c and the centre compensated as above (the depth key is the high part of
+ * z_c); the 2D covariance [[a, b], [b, c]] = V V^T + 0.3 I from V = T M, its
+ * determinant by Lagrange's identity |v0|^2 |v1|^2 - (v0.v1)^2 = |v0 x v1|^2
+ * (a sum of squares), and the exponent -d^T Sigma2^-1 d / 2 in the Cholesky
+ * form -((L11 dx + L12 dy)^2 + (L22 dy)^2) with L22 = sqrt(1 / (2c)),
+ * L11 = sqrt(c / (2 det)), L12 = -(b / c) L11: conditional variance of x
+ * given y, then the marginal of y.  Neither step cancels.                    */
+static void orc_project(const float* mu, const float* M, const double* cov64, float op,
                         const orc_cam* cam, orc_proj* g)
 {
     const float* c = cam->c;
@@ -149,12 +232,15 @@ static void orc_project(const float* mu, const float* cov32, const double* cov64
     memset(g, 0, sizeof(*g));
 
     /* ---- S32 ---- */
-    float xc = (Rc[0] * mu[0] + Rc[1] * mu[1]) + Rc[2] * mu[2] + t[0];
-    float yc = (Rc[3] * mu[0] + Rc[4] * mu[1]) + Rc[5] * mu[2] + t[1];
-    float zc = (Rc[6] * mu[0] + Rc[7] * mu[1]) + Rc[8] * mu[2] + t[2];
+    float xc, xl, yc, yl, zc, zl;
+    orc_dot3(Rc, mu, t[0], &xc, &xl);
+    orc_dot3(Rc + 3, mu, t[1], &yc, &yl);
+    orc_dot3(Rc + 6, mu, t[2], &zc, &zl);
     if (!(zc > zn)) return;
     float ix = xc / zc, iy = yc / zc;
-    float ux = fx * ix + cx, uy = fy * iy + cy;
+    float ux, uxl, uy, uyl;
+    orc_center(fx, cx, xc, xl, zc, zl, &ux, &uxl);
+    orc_center(fy, cy, yc, yl, zc, zl, &uy, &uyl);
     float limx = K_CLAMP * ((0.5f * (float)cam->W) / fx);
     float limy = K_CLAMP * ((0.5f * (float)cam->H) / fy);
     float tx = fminf(limx, fmaxf(-limx, ix));
@@ -166,16 +252,18 @@ static void orc_project(const float* mu, const float* cov32, const double* cov64
         T[k] = j00 * Rc[k] + j02 * Rc[6 + k];
         T[3 + k] = j11 * Rc[3 + k] + j12 * Rc[6 + k];
     }
-    float S[9] = {cov32[0], cov32[1], cov32[2], cov32[1], cov32[3], cov32[4],
-                  cov32[2], cov32[4], cov32[5]};
     float V[6];
     for (int i = 0; i < 2; i++)
         for (int k = 0; k < 3; k++)
-            V[3 * i + k] = (T[3 * i] * S[k] + T[3 * i + 1] * S[3 + k]) + T[3 * i + 2] * S[6 + k];
-    float a = ((V[0] * T[0] + V[1] * T[1]) + V[2] * T[2]) + K_DILATE;
-    float b = (V[0] * T[3] + V[1] * T[4]) + V[2] * T[5];
-    float cc = ((V[3] * T[3] + V[4] * T[4]) + V[5] * T[5]) + K_DILATE;
-    float det = a * cc - b * b;
+            V[3 * i + k] = (T[3 * i] * M[k] + T[3 * i + 1] * M[3 + k]) + T[3 * i + 2] * M[6 + k];
+    float n0 = (V[0] * V[0] + V[1] * V[1]) + V[2] * V[2];
+    float n1 = (V[3] * V[3] + V[4] * V[4]) + V[5] * V[5];
+    float b = (V[0] * V[3] + V[1] * V[4]) + V[2] * V[5];
+    float a = n0 + K_DILATE, cc = n1 + K_DILATE;
+    float k0 = orc_diff_prod(V[1], V[5], V[2], V[4]);
+    float k1 = orc_diff_prod(V[2], V[3], V[0], V[5]);
+    float k2 = orc_diff_prod(V[0], V[4], V[1], V[3]);
+    float det = (((k0 * k0 + k1 * k1) + k2 * k2) + K_DILATE * (n0 + n1)) + K_DILATE * K_DILATE;
     if (!(det > 0.0f)) return;
     float h = 0.5f * (a + cc), dd = 0.5f * (a - cc);
     float lam = h + sqrtf(dd * dd + b * b);
@@ -191,9 +279,10 @@ static void orc_project(const float* mu, const float* cov32, const double* cov64
     memcpy(&g->depth, &zc, 4);
     g->x0 = x0; g->x1 = x1; g->y0 = y0; g->y1 = y1;
     g->ux = ux; g->uy = uy;
-    g->A = -0.5f * (cc / det);
-    g->B = b / det;
-    g->C = -0.5f * (a / det);
+    g->uxl = uxl; g->uyl = uyl;
+    g->L11 = sqrtf((0.5f * cc) / det);
+    g->L12 = -((b / cc) * g->L11);
+    g->L22 = sqrtf(0.5f / cc);
     g->op = op;
 
     /* ---- FP64 values ---- */
@@ -229,11 +318,11 @@ static void orc_project(const float* mu, const float* cov32, const double* cov64
 }
 
 /* ----------------------------------------------------------------------- */
-/* Scene: precomputed FP32 and FP64 covariances.                            */
+/* Scene: precomputed FP32 covariance factors and FP64 covariances.         */
 typedef struct {
     int64_t n;
     const float *mu, *op;
-    float* cov32;
+    float* fac32;
     double* cov64;
 } orc_scene;
 
@@ -241,17 +330,17 @@ static int orc_scene_init(orc_scene* sc, int64_t n, const float* mu, const float
                           const float* q, const float* op)
 {
     sc->n = n; sc->mu = mu; sc->op = op;
-    sc->cov32 = (float*)malloc(sizeof(float) * 6 * (size_t)(n ? n : 1));
+    sc->fac32 = (float*)malloc(sizeof(float) * 9 * (size_t)(n ? n : 1));
     sc->cov64 = (double*)malloc(sizeof(double) * 6 * (size_t)(n ? n : 1));
-    if (!sc->cov32 || !sc->cov64) return -1;
+    if (!sc->fac32 || !sc->cov64) return -1;
     for (int64_t i = 0; i < n; i++) {
-        orc_cov32(s + 3 * i, q + 4 * i, sc->cov32 + 6 * i);
+        orc_factor32(s + 3 * i, q + 4 * i, sc->fac32 + 9 * i);
         orc_cov64(s + 3 * i, q + 4 * i, sc->cov64 + 6 * i);
     }
     return 0;
 }
 
-static void orc_scene_free(orc_scene* sc) { free(sc->cov32); free(sc->cov64); }
+static void orc_scene_free(orc_scene* sc) { free(sc->fac32); free(sc->cov64); }
 
 /* Per-view structure: projections and, per tile, the Gaussians whose tile
  * rectangle contains it, sorted by (depth key, Gaussian index) -- the ordered
@@ -284,7 +373,7 @@ static int orc_view_build(const orc_scene* sc, const orc_cam* cam, orc_view* v)
     if (!v->g || !v->start) return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++)
-        orc_project(sc->mu + 3 * i, sc->cov32 + 6 * i, sc->cov64 + 6 * i, sc->op[i], cam, v->g + i);
+        orc_project(sc->mu + 3 * i, sc->fac32 + 9 * i, sc->cov64 + 6 * i, sc->op[i], cam, v->g + i);
     v->nvis = 0;
     for (int64_t i = 0; i < n; i++) {
         const orc_proj* g = v->g + i;
@@ -322,7 +411,6 @@ typedef void (*orc_emit_fn)(void* ctx, int32_t i, double w);
 static double orc_walk(const orc_view* v, int64_t tile, int px, int py, orc_emit_fn emit,
                        void* ctx, float* t32)
 {
-    float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
     double pxd = px + 0.5, pyd = py + 0.5;
     float T = 1.0f;
     double T64 = 1.0;
@@ -330,12 +418,10 @@ static double orc_walk(const orc_view* v, int64_t tile, int px, int py, orc_emit
         int32_t i = v->ids[k];
         const orc_proj* g = v->g + i;
         /* decision path (S32) */
-        float dx = pxf - g->ux, dy = pyf - g->uy;
-        float pw = (g->B * dx) * dy;
-        pw = fmaf(g->C * dy, dy, pw);
-        pw = fmaf(g->A * dx, dx, pw);
-        pw = fminf(pw, 0.0f);
-        float al = fminf(K_ALPHA_MAX, g->op * orc_exp32(pw));
+        float dx = orc_offset(px, g->ux, g->uxl), dy = orc_offset(py, g->uy, g->uyl);
+        float u = fmaf(g->L12, dy, g->L11 * dx), w = g->L22 * dy;
+        float q = fmaf(u, u, w * w);
+        float al = fminf(K_ALPHA_MAX, g->op * orc_exp32(-q));
         if (al < K_ALPHA_MIN) continue;
         float Tn = T * (1.0f - al);
         if (Tn < K_T_EPS) break;
@@ -510,7 +596,8 @@ int orc_render_view(int64_t n, const float* mu, const float* s, const float* q, 
 /* ----------------------------------------------------------------------- */
 /* Structure of one view, for bit-exact comparison.  Call with ids == NULL to
  * get P (returned); then with ids[P] and tile_start[TX*TY+1].  visible[n],
- * depth[n], rect[n][4] = (x0,y0,x1,y1), rec32[n][6] = (ux,uy,A,B,C,opacity)
+ * depth[n], rect[n][4] = (x0,y0,x1,y1), rec32[n][8] = (ux,uy,uxl,uyl,L11,L12,L22,
+ * opacity)
  * are filled when non-NULL.  Returns P, or -1 on allocation failure.         */
 int64_t orc_view_structure(int64_t n, const float* mu, const float* s, const float* q,
                            const float* op, const float* cam17, int W, int H, uint8_t* visible,
@@ -531,8 +618,9 @@ int64_t orc_view_structure(int64_t n, const float* mu, const float* s, const flo
         if (depth) depth[i] = g->depth;
         if (rect) { rect[4 * i] = g->x0; rect[4 * i + 1] = g->y0; rect[4 * i + 2] = g->x1; rect[4 * i + 3] = g->y1; }
         if (rec32) {
-            float* r = rec32 + 6 * i;
-            r[0] = g->ux; r[1] = g->uy; r[2] = g->A; r[3] = g->B; r[4] = g->C; r[5] = g->op;
+            float* r = rec32 + 8 * i;
+            r[0] = g->ux; r[1] = g->uy; r[2] = g->uxl; r[3] = g->uyl;
+            r[4] = g->L11; r[5] = g->L12; r[6] = g->L22; r[7] = g->op;
         }
     }
     int64_t nt = (int64_t)v.TX * v.TY;
@@ -544,10 +632,10 @@ int64_t orc_view_structure(int64_t n, const float* mu, const float* s, const flo
     return P;
 }
 
-/* FP32 covariance of the S32 convention, [n][6] upper triangle. */
-void orc_covariance32(int64_t n, const float* s, const float* q, float* out)
+/* FP32 covariance factor M = R diag(s) of the S32 convention, [n][3][3]. */
+void orc_factor32_array(int64_t n, const float* s, const float* q, float* out)
 {
-    for (int64_t i = 0; i < n; i++) orc_cov32(s + 3 * i, q + 4 * i, out + 6 * i);
+    for (int64_t i = 0; i < n; i++) orc_factor32(s + 3 * i, q + 4 * i, out + 9 * i);
 }
 
 /* Threads an oracle call uses by default. */

@@ -228,7 +228,7 @@ class Scene:
         vis = np.zeros(n, np.uint8)
         depth = np.zeros(n, np.uint32)
         rect = np.zeros((n, 4), np.int32)
-        rec = np.zeros((n, 6), np.float32)
+        rec = np.zeros((n, 8), np.float32)
         ts = np.zeros(TX * TY + 1, np.int64)
         dbg = lv_view_debug(vis.ctypes.data, depth.ctypes.data, rect.ctypes.data, rec.ctypes.data,
                             ts.ctypes.data, None, 0)

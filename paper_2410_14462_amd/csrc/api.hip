@@ -809,9 +809,14 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
       out->rect[4 * i + 3] = (int32_t)(rect[i].y >> 16);
     }
     if (out->rec) {
-      float* r = out->rec + 6 * i;
-      r[0] = rec[i].r0.x; r[1] = rec[i].r0.y; r[2] = rec[i].r0.z; r[3] = rec[i].r0.w;
-      r[4] = rec[i].r1.x; r[5] = rec[i].r1.y;
+      float* r = out->rec + 8 * i;
+      uint32_t lo;
+      memcpy(&lo, &rec[i].r1.w, 4);
+      const uint32_t lx = lo << 16, ly = lo & 0xFFFF0000u;
+      r[0] = rec[i].r0.x; r[1] = rec[i].r0.y;
+      memcpy(&r[2], &lx, 4);
+      memcpy(&r[3], &ly, 4);
+      r[4] = rec[i].r0.z; r[5] = rec[i].r0.w; r[6] = rec[i].r1.x; r[7] = rec[i].r1.y;
     }
   }
   if (out->tile_start) {

@@ -45,25 +45,31 @@ __device__ __forceinline__ float load_feature(const void* map, int64_t idx, floa
 }
 
 // Can -power(d) <= tau hold for some d in the rectangle [X0,X1] x [Y0,Y1]
-// (offsets from the Gaussian's centre)?  -power = a dx^2 + b dx dy + c dy^2 is
-// convex with its minimum at 0, so outside the rectangle its minimum over the
-// rectangle lies on an edge; each edge is a 1D quadratic with a clamped vertex.
+// (offsets from the Gaussian's centre)?  -power = (L11 dx + L12 dy)^2 +
+// (L22 dy)^2 is convex with its minimum at 0, so outside the rectangle its
+// minimum over the rectangle lies on an edge; along each edge it is a 1D
+// quadratic with a clamped vertex.  Evaluated in the factored form, which
+// stays accurate for thin Gaussians.
+__device__ __forceinline__ float neg_power(float L11, float L12, float L22, float dx, float dy) {
+  const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
+  return __builtin_fmaf(u, u, w * w);
+}
+
 __device__ __forceinline__ bool region_hits(float4 r0, float4 r1, float X0, float X1, float Y0,
                                             float Y1) {
   const float tau = r1.z;
   if (!(tau >= 0.0f)) return false;
   if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
-  const float a = -r0.z, b = -r0.w, c = -r1.x;
-  const float h2c = 0.5f / c, h2a = 0.5f / a;
-  float dy0 = fminf(fmaxf(-b * X0 * h2c, Y0), Y1);
-  float dy1 = fminf(fmaxf(-b * X1 * h2c, Y0), Y1);
-  float dx0 = fminf(fmaxf(-b * Y0 * h2a, X0), X1);
-  float dx1 = fminf(fmaxf(-b * Y1 * h2a, X0), X1);
-  float q0 = (a * X0 + b * dy0) * X0 + c * dy0 * dy0;
-  float q1 = (a * X1 + b * dy1) * X1 + c * dy1 * dy1;
-  float q2 = a * dx0 * dx0 + (b * dx0 + c * Y0) * Y0;
-  float q3 = a * dx1 * dx1 + (b * dx1 + c * Y1) * Y1;
-  return fminf(fminf(q0, q1), fminf(q2, q3)) <= tau;
+  const float L11 = r0.z, L12 = r0.w, L22 = r1.x;
+  const float ky = -(L11 * L12) / __builtin_fmaf(L12, L12, L22 * L22);  // edge dx = X: dy* = ky X
+  const float kx = -L12 / L11;                                          // edge dy = Y: dx* = kx Y
+  const float dy0 = fminf(fmaxf(ky * X0, Y0), Y1);
+  const float dy1 = fminf(fmaxf(ky * X1, Y0), Y1);
+  const float dx0 = fminf(fmaxf(kx * Y0, X0), X1);
+  const float dx1 = fminf(fmaxf(kx * Y1, X0), X1);
+  const float m0 = fminf(neg_power(L11, L12, L22, X0, dy0), neg_power(L11, L12, L22, X1, dy1));
+  const float m1 = fminf(neg_power(L11, L12, L22, dx0, Y0), neg_power(L11, L12, L22, dx1, Y1));
+  return fminf(m0, m1) <= tau;
 }
 
 __device__ __forceinline__ float readlane_f(float v, int l) {
@@ -119,26 +125,33 @@ __device__ __forceinline__ bool decode_quad(const uint2* __restrict__ ranges,
 }
 
 // Per-lane walk state.
+// Coordinates are relative to the tile: pixel offsets px - ox in [0, 16) and
+// centres as (ux - (ox + 0.5)) + ux_lo (see Rec).
 struct Walk {
-  float pxf, pyf, qx0, qx1, qy0, qy1, T;
+  float pxo, pyo;  // this lane's pixel, relative to the tile
+  float ocx, ocy;  // first pixel centre of the tile, ox + 0.5, oy + 0.5
+  float qx0, qy0;  // the quadrant's first pixel, relative to the tile
+  float T;
   bool alive;
   uint32_t ncontrib;  // this pixel's counted Gaussians (statistics only)
 };
 
 __device__ __forceinline__ void walk_init(const Quad& q, int lane, Walk& s) {
   const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
-  s.pxf = (float)px + 0.5f;
-  s.pyf = (float)py + 0.5f;
-  s.qx0 = (float)q.qx + 0.5f;
-  s.qx1 = (float)q.qx + 7.5f;
-  s.qy0 = (float)q.qy + 0.5f;
-  s.qy1 = (float)q.qy + 7.5f;
+  const int ox = q.qx & ~(kTile - 1), oy = q.qy & ~(kTile - 1);
+  s.pxo = (float)(px - ox);
+  s.pyo = (float)(py - oy);
+  s.ocx = (float)ox + 0.5f;
+  s.ocy = (float)oy + 0.5f;
+  s.qx0 = (float)(q.qx - ox);
+  s.qy0 = (float)(q.qy - oy);
   s.T = 1.0f;
   s.alive = px < q.g.W && py < q.g.H;
   s.ncontrib = 0;
 }
 
-// Step 0: records of Gaussians [base, base + cnt) one per lane; hit mask.
+// Step 0: records of Gaussians [base, base + cnt) one per lane, centres made
+// tile-relative; hit mask.
 __device__ __forceinline__ uint64_t step_records(const Rec* __restrict__ vrec,
                                                  const uint32_t* __restrict__ ids, uint32_t base,
                                                  int cnt, int lane, const Walk& s, float4& q0,
@@ -150,9 +163,13 @@ __device__ __forceinline__ uint64_t step_records(const Rec* __restrict__ vrec,
     my_id = ids[base + lane];
     q0 = vrec[my_id].r0;
     q1 = vrec[my_id].r1;
+    // centre relative to the tile (see Rec)
+    const uint32_t lo = __float_as_uint(q1.w);
+    q0.x = (q0.x - s.ocx) + __uint_as_float(lo << 16);
+    q0.y = (q0.y - s.ocy) + __uint_as_float(lo & 0xFFFF0000u);
   }
-  const bool hit = lane < cnt &&
-                   region_hits(q0, q1, s.qx0 - q0.x, s.qx1 - q0.x, s.qy0 - q0.y, s.qy1 - q0.y);
+  const float X0 = s.qx0 - q0.x, Y0 = s.qy0 - q0.y;
+  const bool hit = lane < cnt && region_hits(q0, q1, X0, X0 + 7.0f, Y0, Y0 + 7.0f);
   return __ballot(hit);
 }
 
@@ -165,15 +182,12 @@ __device__ __forceinline__ void step_walk(uint64_t hits, float4 q0, float4 q1, W
   for (int j = 0; j < G; j++) {
     wv[j] = 0.0f;
     if ((hits >> j) & 1ull) {
-      const float ux = readlane_f(q0.x, j), uy = readlane_f(q0.y, j);
-      const float A = readlane_f(q0.z, j), B = readlane_f(q0.w, j);
-      const float C = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
-      float dx = s.pxf - ux, dy = s.pyf - uy;
-      float pw = (B * dx) * dy;
-      pw = __builtin_fmaf(C * dy, dy, pw);
-      pw = __builtin_fmaf(A * dx, dx, pw);
-      pw = fminf(pw, 0.0f);
-      const float al = fminf(kAlphaMax, op * exp32(pw));
+      const float cx = readlane_f(q0.x, j), cy = readlane_f(q0.y, j);
+      const float L11 = readlane_f(q0.z, j), L12 = readlane_f(q0.w, j);
+      const float L22 = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
+      const float dx = s.pxo - cx, dy = s.pyo - cy;
+      const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
+      const float al = fminf(kAlphaMax, op * exp32(-__builtin_fmaf(u, u, w * w)));
       const bool ok = s.alive && al >= kAlphaMin;
       const float Tn = s.T * (1.0f - al);
       const bool stop = ok && Tn < kTEps;

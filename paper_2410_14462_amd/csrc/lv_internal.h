@@ -35,9 +35,14 @@ struct Cam {
 static_assert(sizeof(Cam) == sizeof(lv_camera), "camera layout");
 
 // Per (view, Gaussian) projected record, 32 bytes:
-//   r0 = (ux, uy, A, B), r1 = (C, opacity, tau, 0)
-// power(d) = A dx^2 + B dx dy + C dy^2 (<= 0); alpha can reach 1/255 only
-// where -power <= tau (conservative, used only to skip work; tau < 0: never).
+//   r0 = (ux, uy, L11, L12), r1 = (L22, opacity, tau, lo)
+// The centre is (ux + ux_lo, uy + uy_lo); lo packs the upper 16 bits of
+// ux_lo (low half) and of uy_lo (high half).  Offsets of a pixel from the
+// centre are taken relative to the first pixel centre of the pixel's tile:
+// dx = (px - ox) - ((ux - (ox + 0.5)) + ux_lo), ox = 16 floor(px / 16).
+// power(d) = -((L11 dx + L12 dy)^2 + (L22 dy)^2); alpha can reach 1/255
+// only where -power <= tau (conservative, used only to skip work; tau < 0:
+// never).
 struct Rec {
   float4 r0, r1;
 };

@@ -118,3 +118,70 @@ def test_diffuse_bf16_storage_and_constant_signal():
     err = np.max(np.abs(out - ref) / np.max(np.abs(ref), axis=0))
     print(f"diffuse bf16: max err {err:.3e}")
     assert err < steps * 2.0 ** -8
+
+
+def test_large_full_size_precision_sampled():
+    """The large configuration at full size: 1,000,000 Gaussians (scales
+    exp(N(-5, 0.7^2)), opacities sigmoid(N(0.5, 1))), 1008x756 views, D = 384
+    maps (N(0,1) at 1/14 resolution, upsampled), stored FP32, BF16 and FP8 with
+    FP32 accumulation, 5 of the 100 rig views.  The oracle walks every pixel and
+    accumulates a 20,000-Gaussian sample (drawn without replacement); counts
+    and weight sums are compared for all Gaussians."""
+    w = scenes.WORKLOADS["large"]
+    sc = scenes.scene_for(w)
+    rig = scenes.cameras_for(w)
+    views = [0, 20, 40, 60, 80]
+    cams = [rig[v] for v in views]
+    gs = lv.Scene.from_arrays(sc)
+    rows = scenes.subsample(2, sc.n, 20000)
+    print("large: maps", flush=True)
+    maps32 = [scenes.feature_map(w, v, device="cuda") for v in views]
+    results = {}
+    for dtype in ("f32", "bf16", "fp8"):
+        acc = lv.Accum(gs, w.D, counts=True)
+        smax = 0.0
+        if dtype == "f32":
+            acc.add(cams, maps32)
+            dec = maps32
+        else:
+            enc = [lv.encode(m, dtype) for m in maps32]
+            if dtype == "bf16":
+                acc.add(cams, [e[0] for e in enc], dtype="bf16")
+                dec = [e[0].float() for e in enc]
+            else:
+                scales = torch.stack([e[1] for e in enc]).contiguous()
+                acc.add(cams, [e[0] for e in enc], dtype="fp8", scales=scales)
+                dec = [e[0].view(torch.float8_e4m3fn).float() * e[1] for e in enc]
+            if dtype == "fp8":
+                smax = max(float(e[1].max()) for e in enc)
+            del enc
+        f, b = acc.finalize()
+        c = acc.counts().cpu().numpy().astype(np.int64)
+        f = f.cpu().numpy()[rows]
+        b = b.cpu().numpy()
+        acc.close()
+        print(f"large {dtype}: oracle", flush=True)
+        up = oracle.Uplifter(sc, w.D, rows=rows)
+        for k, cam in enumerate(cams):
+            up.add_view(cam, dec[k].cpu().numpy())
+        ref = up.result()
+        del dec
+        assert np.array_equal(c, ref.count)
+        assert beta_error(b, ref).max() < 1e-4
+        e = feature_error(f, ref)
+        print(f"large {dtype} vs decoded maps: max {e.max():.3e}", flush=True)
+        assert e.max() < 1e-4
+        results[dtype] = (f, smax)
+    # low-precision results against the FP32 result's oracle (same rows)
+    up = oracle.Uplifter(sc, w.D, rows=rows)
+    for k, cam in enumerate(cams):
+        up.add_view(cam, maps32[k].cpu().numpy())
+    ref32 = up.result()
+    seen = ref32.beta[rows] > 0
+    a = ref32.a[seen]
+    for dtype, (f, smax) in results.items():
+        d = np.abs(f[seen] - ref32.f[seen])
+        bound = {"f32": 1e-4 * a, "bf16": 2.0 ** -8 * a + 1e-4 * a,
+                 "fp8": 2.0 ** -4 * a + 2.0 ** -10 * smax + 1e-4 * a}[dtype]
+        print(f"large {dtype} vs FP32 maps: max |df|/a {np.max(d / np.maximum(a, 1e-30)):.3e}")
+        assert np.all(d <= bound)

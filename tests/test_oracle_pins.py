@@ -64,16 +64,19 @@ def test_exp32_accuracy_and_exact_points():
     assert oracle.exp32(np.array([-81.0], F32))[0] == 0.0
 
 
-def test_covariance_matches_library_rotation():
+def test_covariance_factor_matches_library_rotation():
+    """M = R diag(s) against scipy's quaternion rotation, and M M^T against the
+    covariance R diag(s)^2 R^T (Sec. 3.1)."""
     rng = np.random.default_rng(3)
     q = rng.normal(size=(500, 4)).astype(F32)
     s = np.exp(rng.normal(-3, 0.7, size=(500, 3))).astype(F32)
-    cov = oracle.covariance32(s, q)
+    M = oracle.factor32(s, q).astype(np.float64)
     R = Rotation.from_quat(q[:, [1, 2, 3, 0]].astype(np.float64)).as_matrix()  # scalar-last
+    ref = R * s.astype(np.float64)[:, None, :]
+    assert np.max(np.abs(M - ref) / s.max(1)[:, None, None]) < 1e-6
     full = R @ (np.square(s.astype(np.float64))[:, :, None] * np.transpose(R, (0, 2, 1)))
-    ref = full[:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
-    scale = np.max(np.abs(full), axis=(1, 2))[:, None]
-    assert np.max(np.abs(cov - ref) / scale) < 2e-6
+    scale = np.max(np.abs(full), axis=(1, 2))[:, None, None]
+    assert np.max(np.abs(M @ M.transpose(0, 2, 1) - full) / scale) < 2e-6
 
 
 # --------------------------------------------------- single-Gaussian forms
