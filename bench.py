@@ -263,11 +263,14 @@ def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
                  torch.as_tensor(val, device="cuda"))
     nnz = int(col.shape[0])
     dres = {"graph_nnz": nnz, "steps": 100}
-    for name, g0 in (("D1", f1.contiguous()), ("D64", f64)):
-        out = G.diffuse(g0, 100)
+    # with the scene: rows in the Morton order of the centres (built on the
+    # first call); without: the caller's order
+    for name, g0, scene in (("D1", f1.contiguous(), s), ("D64", f64, s),
+                            ("D64_caller_order", f64, None)):
+        out = G.diffuse(g0, 100, scene=scene)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = G.diffuse(g0, 100, out=out)
+        out = G.diffuse(g0, 100, scene=scene, out=out)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / 100
         Dg = g0.shape[1]

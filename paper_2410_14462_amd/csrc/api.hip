@@ -154,6 +154,12 @@ struct lv_graph {
   int64_t n = 0, nnz = 0;
   lv_dtype val_dtype = LV_F32;
   Buf row_ptr, col, val, b0, b1, norms;
+  // locality order (built on the first call that passes a scene)
+  bool ordered = false;
+  Buf perm, inv, rp2, col2, val2, bin, bout;
+  // calls share the buffers above: each call's stream waits for the last one
+  std::mutex mu;
+  hipEvent_t last = nullptr;
 };
 
 namespace {
@@ -742,6 +748,9 @@ lv_status lv_graph_destroy(lv_graph* g) {
   (void)hipDeviceSynchronize();
   g->row_ptr.release(); g->col.release(); g->val.release();
   g->b0.release(); g->b1.release(); g->norms.release();
+  g->perm.release(); g->inv.release(); g->rp2.release(); g->col2.release(); g->val2.release();
+  g->bin.release(); g->bout.release();
+  if (g->last) (void)hipEventDestroy(g->last);
   delete g;
   return LV_OK;
 }
@@ -756,13 +765,50 @@ lv_status lv_diffuse(const lv_scene* sc, const lv_graph* gc, const void* g0, lv_
   if (g0 == out && steps > 0) return fail(LV_ERR_INVALID_ARG, "out must not alias g0");
   lv_graph* g = const_cast<lv_graph*>(gc);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  size_t sig = dtype_size(dtype) * (size_t)(g->n > 0 ? g->n : 1) * D;
+  std::lock_guard<std::mutex> lk(g->mu);
+  if (g->last) HIP_TRY(hipStreamWaitEvent(s, g->last, 0));
+  else HIP_TRY(hipEventCreateWithFlags(&g->last, hipEventDisableTiming));
+  const bool order = sc && g->n > 0 && steps > 0;
+  const size_t sig = dtype_size(dtype) * (size_t)(g->n > 0 ? g->n : 1) * D;
   HIP_TRY(g->b0.ensure(sig, s));
   HIP_TRY(g->b1.ensure(sig, s));
   HIP_TRY(g->norms.ensure(sizeof(float) * (size_t)D * (steps + 1), s));
-  HIP_TRY(launch_diffuse(g->row_ptr.as<int32_t>(), g->col.as<int32_t>(), g->val.p, g->val_dtype, g->n,
-                         g0, dtype, D, steps, out, g->b0.as<float>(), g->b1.as<float>(),
-                         g->norms.as<float>(), s));
+  if (order && !g->ordered) {
+    // P A P^T along the Morton order of the scene's centres; any permutation
+    // gives the same result, so the order is built once per graph.
+    const int64_t n = g->n, nnz = g->nnz;
+    Buf scratch;
+    HIP_TRY(scratch.ensure(4 * reorder_scratch_words(n), s));
+    hipError_t e = g->perm.ensure(4 * (size_t)n, s);
+    if (e == hipSuccess) e = g->inv.ensure(4 * (size_t)n, s);
+    if (e == hipSuccess) e = g->rp2.ensure(4 * (size_t)(n + 1), s);
+    if (e == hipSuccess) e = g->col2.ensure(4 * (size_t)(nnz + 1), s);
+    if (e == hipSuccess) e = g->val2.ensure(dtype_size(g->val_dtype) * (size_t)(nnz + 1), s);
+    if (e == hipSuccess)
+      e = launch_graph_reorder(sc->p0.as<float4>(), n, g->row_ptr.as<int32_t>(), g->col.as<int32_t>(),
+                               g->val.p, g->val_dtype, nnz, scratch.as<uint32_t>(),
+                               g->perm.as<uint32_t>(), g->inv.as<uint32_t>(), g->rp2.as<int32_t>(),
+                               g->col2.as<int32_t>(), g->val2.p, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    scratch.release();
+    if (e != hipSuccess) return fail(LV_ERR_DEVICE, "graph order: %s", hipGetErrorString(e));
+    g->ordered = true;
+  }
+  if (order) {
+    HIP_TRY(g->bin.ensure(sig, s));
+    HIP_TRY(g->bout.ensure(sig, s));
+    const uint32_t* perm = g->perm.as<uint32_t>();
+    HIP_TRY(launch_permute_rows(g0, g->bin.p, perm, g->n, D, dtype, false, s));
+    HIP_TRY(launch_diffuse(g->rp2.as<int32_t>(), g->col2.as<int32_t>(), g->val2.p, g->val_dtype, g->n,
+                           g->bin.p, dtype, D, steps, g->bout.p, g->b0.as<float>(), g->b1.as<float>(),
+                           g->norms.as<float>(), s));
+    HIP_TRY(launch_permute_rows(g->bout.p, out, perm, g->n, D, dtype, true, s));
+  } else {
+    HIP_TRY(launch_diffuse(g->row_ptr.as<int32_t>(), g->col.as<int32_t>(), g->val.p, g->val_dtype, g->n,
+                           g0, dtype, D, steps, out, g->b0.as<float>(), g->b1.as<float>(),
+                           g->norms.as<float>(), s));
+  }
+  HIP_TRY(hipEventRecord(g->last, s));
   return LV_OK;
 }
 

@@ -195,4 +195,17 @@ hipError_t launch_diffuse(const int32_t* row_ptr, const int32_t* col, const void
                           int steps, void* out, float* buf0, float* buf1, float* norms,
                           hipStream_t s);
 
+// Locality order for diffusion: perm (new row -> old row) sorts the Gaussians
+// by the Morton code of their centres (10 bits per axis over the bounding
+// box); inv is its inverse; (rp2, col2, val2) is P A P^T.  scratch holds
+// reorder_scratch_words(n) uint32.
+size_t reorder_scratch_words(int64_t n);
+hipError_t launch_graph_reorder(const float4* p0, int64_t n, const int32_t* rp, const int32_t* col,
+                                const void* val, lv_dtype vt, int64_t nnz, uint32_t* scratch,
+                                uint32_t* perm, uint32_t* inv, int32_t* rp2, int32_t* col2,
+                                void* val2, hipStream_t s);
+// dst[r] = src[perm[r]] (gather) or dst[perm[r]] = src[r] (scatter), rows of D.
+hipError_t launch_permute_rows(const void* src, void* dst, const uint32_t* perm, int64_t n, int D,
+                               lv_dtype dt, bool scatter, hipStream_t s);
+
 }  // namespace lv

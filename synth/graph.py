@@ -14,7 +14,7 @@ def knn(points, k):
     """Directed kNN (self excluded): (idx [n,k], dist [n,k]) in FP64."""
     pts = np.asarray(points, np.float64)
     tree = cKDTree(pts)
-    d, i = tree.query(pts, k=k + 1)
+    d, i = tree.query(pts, k=k + 1, workers=-1)
     # drop self (distance 0, normally first); keep k others
     out_i = np.empty((pts.shape[0], k), np.int64)
     out_d = np.empty((pts.shape[0], k))
@@ -41,7 +41,12 @@ def knn_graph(points, feats, k=16):
     nrm = np.linalg.norm(f, axis=1)
     rows = np.repeat(np.arange(n), k)
     cols = idx.reshape(-1)
-    num = np.einsum("ij,ij->i", f[rows], f[cols])
+    num = np.empty(n * k)
+    step = max(1, (1 << 22) // max(1, f.shape[1] * k))  # rows per chunk (bounded temporaries)
+    for r0 in range(0, n, step):
+        r1 = min(n, r0 + step)
+        nb = f[idx[r0:r1]]                                   # [rows, k, D]
+        num[r0 * k:r1 * k] = np.einsum("rd,rkd->rk", f[r0:r1], nb).reshape(-1)
     den = nrm[rows] * nrm[cols]
     cos = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
     w = np.exp(-(dist.reshape(-1) ** 2) / (sigma * sigma)) * np.maximum(0.0, cos)

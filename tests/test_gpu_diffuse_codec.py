@@ -82,7 +82,7 @@ def gpu_graph(n, k, seed, D):
     return rp, col, val
 
 
-@pytest.mark.parametrize("D,steps", [(1, 10), (3, 5), (64, 20), (70, 3), (8, 0)])
+@pytest.mark.parametrize("D,steps", [(1, 10), (3, 5), (64, 20), (70, 3), (8, 0), (12, 4), (384, 3)])
 def test_diffuse_fp32_parity(D, steps):
     n = 5000
     rp, col, val = gpu_graph(n, 16, D, D)
@@ -97,6 +97,32 @@ def test_diffuse_fp32_parity(D, steps):
     err = np.max(np.abs(out - ref) / scale)
     print(f"diffuse D={D} steps={steps}: max err {err:.3e}")
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("D,vdt", [(1, "f32"), (64, "f32"), (5, "bf16")])
+def test_diffuse_locality_order(D, vdt):
+    """With the scene given, rows run in the Morton order of the centres
+    (P A P^T, undone on output): same result as the caller's order, and as
+    the oracle."""
+    sc = scenes.make_scene(12, 6000, -4.0, 0.5, 0.0, 1.0)
+    gs = lv.Scene.from_arrays(sc)
+    feats = philox.normal(12, 1, sc.n * 8).reshape(sc.n, 8)
+    rp, col, val = graph.knn_graph(sc.means, feats, 16)
+    dt = torch.float32 if vdt == "f32" else torch.bfloat16
+    G = lv.Graph(torch.as_tensor(rp, device="cuda"), torch.as_tensor(col, device="cuda"),
+                 torch.as_tensor(val, device="cuda").to(dt))
+    g0 = torch.as_tensor(philox.uniform(13, D, sc.n * D).reshape(sc.n, D), device="cuda").to(dt)
+    a = G.diffuse(g0, 30, scene=gs).float().cpu().numpy().astype(np.float64)
+    b = G.diffuse(g0, 30).float().cpu().numpy().astype(np.float64)
+    a2 = G.diffuse(g0, 30, scene=gs).float().cpu().numpy().astype(np.float64)  # cached order
+    aval = val if vdt == "f32" else torch.as_tensor(val).to(dt).float().numpy()
+    ref = od.diffuse(od.csr_matrix(sc.n, rp, col, aval), g0.float().cpu().numpy(), 30)
+    scale = np.max(np.abs(ref), axis=0)
+    tol = 1e-5 if vdt == "f32" else 30 * 2.0 ** -9
+    assert np.max(np.abs(a - a2) / scale) < (1e-6 if vdt == "f32" else 2.0 ** -7)  # norm sums are atomics
+    assert np.max(np.abs(a - ref) / scale) < tol and np.max(np.abs(b - ref) / scale) < tol
+    if vdt == "f32":
+        assert np.max(np.abs(a - b) / scale) < 1e-5
 
 
 def test_diffuse_bf16_storage_and_constant_signal():
