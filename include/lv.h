@@ -148,15 +148,20 @@ lv_status lv_uplift_accumulate(lv_accum* acc, const lv_camera* cams, int32_t m,
                                void* stream);
 /* Several feature sets over the same views in one pass (the same weights
  * w_i(p) serve every set, Eq. 5 with F the concatenation of the sets'
- * channels): set k adds maps[k] (host array [m] of device pointers, HWC with
- * its accumulator's D) to sets[k].acc.  1 <= nsets <= 8; all accumulators on
- * the same scene and distinct; one storage dtype for all sets.  Each set's
- * result equals lv_uplift_accumulate of that set alone (within FP32
- * accumulation order). */
+ * channels): set k adds maps[k] (host array [m] of device pointers) to
+ * sets[k].acc.  maps[k][v] may be NULL: set k does not take view v (nothing
+ * is added to it for that view, its beta included).  A map is HWC with the
+ * accumulator's D channels per pixel, consecutive pixels `stride` elements
+ * apart (stride 0 means D; stride > D reads channels [0, D) of a wider map).
+ * 1 <= nsets <= 8; all accumulators on the same scene and distinct; one
+ * storage dtype for all sets.  Each set's result equals
+ * lv_uplift_accumulate of that set alone over the views it takes (within
+ * FP32 accumulation order). */
 typedef struct lv_feature_set {
     lv_accum* acc;
     const void* const* maps;
     const float* scales;       /* FP8 only: device [m][D], else NULL */
+    int32_t stride;            /* elements between consecutive pixels; 0 = D */
 } lv_feature_set;
 lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_feature_set* sets,
                                    int32_t nsets, lv_dtype dtype, void* stream);
@@ -213,6 +218,67 @@ lv_status lv_graph_destroy(lv_graph* graph);
  * given, its size must equal the graph's.  Scratch: 2 n D FP32 + 2 D FP32. */
 lv_status lv_diffuse(const lv_scene* scene, const lv_graph* graph, const void* g0, lv_dtype dtype,
                      int32_t D, int32_t steps, void* out, void* stream);
+
+/* -------------------------------------------------------------- serving -- */
+/* A request server for uplift (Eq. 3 / Eq. 5) over resident scenes.  Requests
+ * are admitted first come, first served while the memory they need (the
+ * accumulators, n (D + 2) x 4 bytes) fits in hbm_budget; a request larger
+ * than the budget is refused.  Each of `workers` threads runs one pass at a
+ * time on its own HIP stream, so passes overlap on the device; a free worker
+ * takes the oldest admitted request and merges into the same pass the other
+ * admitted requests on the same scene with the same storage dtype (at most
+ * max_sets requests and max_channels channels): one structure build and one
+ * blend walk over the union of their views, each request adding only its own
+ * views.  FP8 requests are not merged (their scales are per view).  Memory of
+ * finished passes returns to the budget at once, admitting waiting requests
+ * while other passes run.  Each result equals lv_uplift of that request alone
+ * (within FP32 accumulation order). */
+typedef struct lv_server lv_server;
+typedef struct lv_server_opts {
+    int64_t hbm_budget;     /* bytes; <= 0: half of the free device memory */
+    int32_t workers;        /* passes in flight, 1..8 (0: 2) */
+    int32_t max_sets;       /* requests per pass, 1..8 (0: 8) */
+    int32_t max_channels;   /* channels per pass (0: 1024) */
+} lv_server_opts;
+/* One request: as lv_uplift, plus the pixel stride of its maps (0 = D) and a
+ * caller tag.  cams and the maps table are copied at submission; the scene,
+ * the maps, scales and outputs must stay valid until the request completes. */
+typedef struct lv_request {
+    lv_scene* scene;
+    const lv_camera* cams;
+    int32_t m;
+    const void* const* maps;
+    int32_t stride;
+    lv_dtype dtype;
+    const float* scales;
+    int32_t D;
+    float* out_feat;
+    float* out_wsum;
+    uint64_t tag;
+} lv_request;
+/* A finished request: status, the number of requests in its pass, and times
+ * in ns since the server was created (submission, start and end of its
+ * pass; the outputs are complete at t_end). */
+typedef struct lv_completion {
+    uint64_t tag;
+    int32_t status;
+    int32_t batch_size;
+    int64_t t_submit, t_start, t_end;
+} lv_completion;
+typedef struct lv_server_stats {
+    int64_t submitted, completed, passes, peak_bytes, budget;
+} lv_server_stats;
+lv_status lv_server_create(const lv_server_opts* opts, lv_server** out);
+/* Non-blocking.  LV_ERR_INVALID_ARG for a malformed request,
+ * LV_ERR_OUT_OF_MEMORY if it can never fit the budget. */
+lv_status lv_server_submit(lv_server* srv, const lv_request* req);
+/* Moves up to cap completions into out (oldest first); *n receives the count. */
+lv_status lv_server_poll(lv_server* srv, lv_completion* out, int32_t cap, int32_t* n);
+/* Blocks until every submitted request has completed. */
+lv_status lv_server_drain(lv_server* srv);
+lv_status lv_server_stats_get(lv_server* srv, lv_server_stats* out);
+/* Drains, stops the workers and frees the server. */
+lv_status lv_server_destroy(lv_server* srv);
 
 /* ------------------------------------------------------------ inspection -- */
 /* Per-view structure for verification; synchronous.  Host buffers (each

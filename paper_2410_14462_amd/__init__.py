@@ -35,7 +35,30 @@ class lv_view_debug(ctypes.Structure):
 
 
 class lv_feature_set(ctypes.Structure):
-    _fields_ = [("acc", ctypes.c_void_p), ("maps", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
+    _fields_ = [("acc", ctypes.c_void_p), ("maps", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("stride", ctypes.c_int32)]
+
+
+class lv_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("workers", ctypes.c_int32),
+                ("max_sets", ctypes.c_int32), ("max_channels", ctypes.c_int32)]
+
+
+class lv_request(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("cams", ctypes.c_void_p), ("m", ctypes.c_int32),
+                ("maps", ctypes.c_void_p), ("stride", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("scales", ctypes.c_void_p), ("D", ctypes.c_int32), ("out_feat", ctypes.c_void_p),
+                ("out_wsum", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class lv_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("t_submit", ctypes.c_int64), ("t_start", ctypes.c_int64), ("t_end", ctypes.c_int64)]
+
+
+class lv_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("passes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("budget", ctypes.c_int64)]
 
 
 class lv_uplift_set(ctypes.Structure):
@@ -84,6 +107,12 @@ def lib():
             "lv_uplift_accumulate_sets": ([P, i32, P, i32, i32, P], i32),
             "lv_profile_start": ([], i32),
             "lv_profile_stop": ([ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), P, i64], i32),
+            "lv_server_create": ([ctypes.POINTER(lv_server_opts), ctypes.POINTER(P)], i32),
+            "lv_server_submit": ([P, ctypes.POINTER(lv_request)], i32),
+            "lv_server_poll": ([P, P, i32, ctypes.POINTER(i32)], i32),
+            "lv_server_drain": ([P], i32),
+            "lv_server_stats_get": ([P, ctypes.POINTER(lv_server_stats)], i32),
+            "lv_server_destroy": ([P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -99,7 +128,8 @@ def exported_symbols():
             "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode",
             "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view",
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
-            "lv_uplift_accumulate_sets"]
+            "lv_uplift_accumulate_sets", "lv_server_create", "lv_server_submit", "lv_server_poll",
+            "lv_server_drain", "lv_server_stats_get", "lv_server_destroy"]
 
 
 def _check(status):
@@ -287,18 +317,49 @@ class Accum:
         return c
 
 
+def _slice_table(maps, dtype, D):
+    """Maps of one set for lv_feature_set: each [H, W, D] (None: the set does
+    not take that view), channels contiguous, pixels `stride` elements apart
+    (a channel slice [..., :D] of a wider map is accepted).  Returns (table,
+    stride)."""
+    import torch
+    want = {LV_F32: (torch.float32,), LV_BF16: (torch.bfloat16,),
+            LV_FP8_E4M3: (torch.uint8, getattr(torch, "float8_e4m3fn", torch.uint8))}[dtype]
+    tab = (ctypes.c_void_p * max(1, len(maps)))()
+    stride = None
+    for i, mp in enumerate(maps):
+        if mp is None:
+            tab[i] = None
+            continue
+        ok = mp.is_cuda and mp.dtype in want and mp.dim() == 3 and mp.shape[2] == D
+        if ok and mp.is_contiguous():
+            px = D
+        else:  # a channel slice: channels adjacent, rows of W pixels
+            st = mp.stride() if ok else (0, 0, 0)
+            px = st[1]
+            ok = ok and (st[2] == 1 or D == 1) and px >= D and st[0] == px * mp.shape[1]
+        if not ok or (stride is not None and px != stride):
+            raise LvError(f"map {i}: expected a CUDA [H, W, {D}] tensor of {want} with "
+                          f"contiguous channels and one pixel stride per set")
+        stride = px
+        tab[i] = mp.data_ptr()
+    return tab, (stride or D)
+
+
 def accumulate_sets(cams, sets, dtype="f32"):
-    """sets: list of (Accum, maps[, scales]) sharing one scene; one pass."""
+    """sets: list of (Accum, maps[, scales]) sharing one scene; one pass.
+    maps[v] may be None (the set does not take view v) or a channel slice of a
+    wider map."""
     dt = _DTYPES[dtype]
     arr = (lv_feature_set * len(sets))()
     keep = []
     for k, st in enumerate(sets):
         acc, maps = st[0], st[1]
         scales = st[2] if len(st) > 2 else None
-        tab = _map_table(maps, dt)
+        tab, stride = _slice_table(maps, dt, acc.D)
         keep.append(tab)
         arr[k] = lv_feature_set(acc.handle.value, ctypes.cast(tab, ctypes.c_void_p),
-                                None if scales is None else scales.data_ptr())
+                                None if scales is None else scales.data_ptr(), stride)
     _check(lib().lv_uplift_accumulate_sets(camera_array(cams), len(cams), arr, len(sets), dt,
                                            _stream()))
 
@@ -367,3 +428,70 @@ class Graph:
         _check(lib().lv_diffuse(scene.handle if scene is not None else None, self.handle, _ptr(g0),
                                 dt, D, steps, _ptr(out), _stream()))
         return out
+
+
+class Server:
+    """lv_server: uplift requests admitted by memory budget, merged per scene
+    into wide passes, several passes in flight (one HIP stream per worker)."""
+
+    def __init__(self, budget=0, workers=2, max_sets=8, max_channels=1024):
+        o = lv_server_opts(int(budget), workers, max_sets, max_channels)
+        h = ctypes.c_void_p()
+        _check(lib().lv_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self._live = {}
+        self._next = 0
+
+    def submit(self, scene, cams, maps, dtype="f32", scales=None, out=None, wsum=None, tag=None):
+        """maps: one [H, W, D] tensor per camera (channel slices of wider maps
+        allowed).  Returns the tag; the tensors are kept alive until the
+        request is polled."""
+        import torch
+        dt = _DTYPES[dtype]
+        D = int(maps[0].shape[2])
+        tab, stride = _slice_table(maps, dt, D)
+        if out is None:
+            out = torch.empty((scene.n, D), device="cuda", dtype=torch.float32)
+        if wsum is None:
+            wsum = torch.empty((scene.n,), device="cuda", dtype=torch.float32)
+        if tag is None:
+            tag = self._next
+        self._next = max(self._next, tag + 1)
+        ca = camera_array(cams)
+        q = lv_request(scene.handle.value, ctypes.cast(ca, ctypes.c_void_p), len(cams),
+                       ctypes.cast(tab, ctypes.c_void_p), stride, dt,
+                       None if scales is None else scales.data_ptr(), D, out.data_ptr(),
+                       wsum.data_ptr(), tag)
+        _check(lib().lv_server_submit(self.handle, ctypes.byref(q)))
+        self._live[tag] = (scene, list(maps), scales, out, wsum)
+        return tag
+
+    def poll(self, cap=4096):
+        """Finished requests: dicts with tag, status, batch_size, times (s) and
+        the outputs (features, weight sums)."""
+        buf = (lv_completion * cap)()
+        n = ctypes.c_int32()
+        _check(lib().lv_server_poll(self.handle, buf, cap, ctypes.byref(n)))
+        res = []
+        for c in buf[:n.value]:
+            live = self._live.pop(c.tag, None)
+            res.append({"tag": c.tag, "status": c.status, "batch_size": c.batch_size,
+                        "t_submit": c.t_submit * 1e-9, "t_start": c.t_start * 1e-9,
+                        "t_end": c.t_end * 1e-9,
+                        "out": live[3] if live else None, "wsum": live[4] if live else None})
+        return res
+
+    def drain(self):
+        _check(lib().lv_server_drain(self.handle))
+
+    def stats(self):
+        st = lv_server_stats()
+        _check(lib().lv_server_stats_get(self.handle, ctypes.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in lv_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lv_server_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close

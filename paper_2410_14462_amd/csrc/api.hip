@@ -288,11 +288,12 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   return LV_OK;
 }
 
-lv_status check_maps(const void* const* maps, int32_t m, lv_dtype dtype, const float* scales) {
+lv_status check_maps(const void* const* maps, int32_t m, lv_dtype dtype, const float* scales,
+                     bool allow_null = false) {
   if (dtype != LV_F32 && dtype != LV_BF16 && dtype != LV_FP8_E4M3)
     return fail(LV_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
   if (m > 0 && !maps) return fail(LV_ERR_INVALID_ARG, "maps is NULL");
-  for (int v = 0; v < m; v++)
+  for (int v = 0; v < m && !allow_null; v++)
     if (!maps[v]) return fail(LV_ERR_INVALID_ARG, "maps[%d] is NULL", v);
   if (dtype == LV_FP8_E4M3 && m > 0 && !scales)
     return fail(LV_ERR_INVALID_ARG, "FP8 maps need scales");
@@ -415,8 +416,11 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
       if (fsets[q].acc == fsets[k].acc)
         return fail(LV_ERR_INVALID_ARG, "set %d repeats the accumulator of set %d", k, q);
     sc = fsets[k].acc->scene;
-    st = check_maps(fsets[k].maps, m, dtype, fsets[k].scales);
+    st = check_maps(fsets[k].maps, m, dtype, fsets[k].scales, true);
     if (st != LV_OK) return st;
+    if (fsets[k].stride != 0 && fsets[k].stride < fsets[k].acc->D)
+      return fail(LV_ERR_INVALID_ARG, "set %d: pixel stride %d < D = %d", k, fsets[k].stride,
+                  fsets[k].acc->D);
     total += fsets[k].acc->D;
   }
   const int64_t n = sc->n;
@@ -515,6 +519,7 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
       sd[k].counts = a->counts.as<uint32_t>();
       sd[k].stats = a->dstats.as<unsigned long long>();
       sd[k].D = a->D;
+      sd[k].stride = fsets[k].stride ? fsets[k].stride : a->D;
       sd[k].view_base = v0;
     }
     if (b_groups) memcpy(up + b_sets, groups.data(), b_groups);
@@ -554,9 +559,12 @@ lv_status lv_uplift_accumulate(lv_accum* a, const lv_camera* cams, int32_t m, co
                                lv_dtype dtype, const float* scales, void* stream) {
   if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
   lv_feature_set fs;
+  lv_status st = check_maps(maps, m, dtype, scales);
+  if (st != LV_OK) return st;
   fs.acc = a;
   fs.maps = maps;
   fs.scales = scales;
+  fs.stride = 0;
   return lv_uplift_accumulate_sets(cams, m, &fs, 1, dtype, stream);
 }
 
@@ -665,6 +673,7 @@ lv_status lv_uplift_sets(lv_scene* sc, const lv_camera* cams, int32_t m, const l
     fs[k].acc = &acc[k];
     fs[k].maps = sets[k].maps;
     fs[k].scales = sets[k].scales;
+    fs[k].stride = 0;
     st = lv_accum_reset(&acc[k], stream);
     if (st != LV_OK) break;
   }
@@ -881,3 +890,54 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
 }
 
 }  // extern "C"
+
+namespace lv {
+
+lv_status set_error(lv_status st, const char* msg) { return fail(st, "%s", msg); }
+
+// One pass of the server: per-set accumulators from the stream-ordered
+// allocator (no device-wide synchronisation), lv_uplift_accumulate_sets over
+// the union of the sets' views, finalize into each set's outputs, accumulators
+// returned to the allocator on the same stream.
+lv_status run_batch(lv_scene* sc, const lv_camera* cams, int32_t m, const BatchSet* sets,
+                    int nsets, lv_dtype dtype, hipStream_t s) {
+  if (!sc || nsets < 1 || nsets > kMaxSets) return fail(LV_ERR_INVALID_ARG, "bad batch");
+  lv_accum acc[kMaxSets];
+  lv_feature_set fs[kMaxSets];
+  const size_t n1 = (size_t)(sc->n > 0 ? sc->n : 1);
+  lv_status st = LV_OK;
+  int made = 0;
+  for (int k = 0; k < nsets; k++) {
+    void* U = nullptr;
+    void* B = nullptr;
+    hipError_t e = hipMallocAsync(&U, sizeof(float) * n1 * sets[k].D, s);
+    if (e == hipSuccess) e = hipMallocAsync(&B, sizeof(float2) * n1, s);
+    if (e != hipSuccess) {
+      if (U) (void)hipFreeAsync(U, s);
+      st = fail(LV_ERR_OUT_OF_MEMORY, "server accumulator: %s", hipGetErrorString(e));
+      break;
+    }
+    acc[k].scene = sc;
+    acc[k].D = sets[k].D;
+    acc[k].U.p = U;
+    acc[k].beta.p = B;
+    fs[k].acc = &acc[k];
+    fs[k].maps = sets[k].maps;
+    fs[k].scales = sets[k].scales;
+    fs[k].stride = sets[k].stride;
+    made = k + 1;
+    st = lv_accum_reset(&acc[k], s);
+    if (st != LV_OK) break;
+  }
+  if (st == LV_OK) st = lv_uplift_accumulate_sets(cams, m, fs, nsets, dtype, s);
+  for (int k = 0; k < nsets && st == LV_OK; k++)
+    st = lv_accum_finalize(&acc[k], sets[k].out_feat, sets[k].out_wsum, nullptr, s);
+  for (int k = 0; k < made; k++) {
+    (void)hipFreeAsync(acc[k].U.p, s);
+    (void)hipFreeAsync(acc[k].beta.p, s);
+    acc[k].U.p = acc[k].beta.p = nullptr;
+  }
+  return st;
+}
+
+}  // namespace lv

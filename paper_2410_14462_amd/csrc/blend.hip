@@ -235,10 +235,13 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   // by channel (lane = pixel).  This lane's output channel is noted on the way.
   float* out0 = nullptr;
   int D0 = 0;
+  bool active = false;  // some segment or tail channel takes this view
   for (int k = 0; k < nseg; k++) {
     const SetDesc& sd = sets[grp.set[k]];
-    const int D = sd.D, c0 = grp.c0[k], vc0 = grp.vc0[k], cnt = grp.cnt[k];
     const void* map = sd.maps[q.v];
+    if (!map) continue;  // this set does not take the view
+    active = true;
+    const int D = sd.D, ld = sd.stride, c0 = grp.c0[k], vc0 = grp.vc0[k], cnt = grp.cnt[k];
     const float* scl = nullptr;
     if constexpr (DT == LV_FP8_E4M3) scl = sd.scales + (int64_t)(sd.view_base + q.v) * D + c0;
     if (lane >= vc0 && lane < vc0 + cnt) {
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
         const int gx = q.qx + (p & 7), gy = q.qy + (p >> 3);
         float val = 0.0f;
         if (mine && gx < q.g.W && gy < q.g.H)
-          val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * D + c0 + lane, sc);
+          val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * ld + c0 + lane, sc);
         if (mine) Fs[p * 64 + vc0 + lane] = val;
       }
     } else {
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
         float sc = 1.0f;
         if constexpr (DT == LV_FP8_E4M3) sc = scl[c];
         float val = 0.0f;
-        if (inside) val = load_feature<DT>(map, ((int64_t)py * q.g.W + px) * D + c0 + c, sc);
+        if (inside) val = load_feature<DT>(map, ((int64_t)py * q.g.W + px) * ld + c0 + c, sc);
         Fs[lane * 64 + vc0 + c] = val;
       }
     }
@@ -275,22 +278,25 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     ft[t] = 0.0f;
     tout[t] = nullptr;
     tD[t] = 0;
-    if (t < ntail) {
+    if (t < ntail && sets[grp.tset[t]].maps[q.v]) {
       const SetDesc& sd = sets[grp.tset[t]];
       const int c = grp.tc[t];
       float sc = 1.0f;
       if constexpr (DT == LV_FP8_E4M3) sc = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
-      if (inside) ft[t] = load_feature<DT>(sd.maps[q.v], ((int64_t)py * q.g.W + px) * sd.D + c, sc);
+      if (inside)
+        ft[t] = load_feature<DT>(sd.maps[q.v], ((int64_t)py * q.g.W + px) * sd.stride + c, sc);
       tout[t] = sd.U + c;
       tD[t] = sd.D;
+      active = true;
     }
   }
+  if (!active) return;  // wave-uniform: no set of this group takes the view
   __syncthreads();
   const float* f0 = Fs + lane;  // this lane's channel of pixel 0 (lanes >= width idle)
   const int beta_sets = grp.beta_sets;
   float2* my_beta = nullptr;
   uint32_t* my_counts = nullptr;
-  if (lane < kMaxSets && ((beta_sets >> lane) & 1)) {
+  if (lane < kMaxSets && ((beta_sets >> lane) & 1) && sets[lane].maps[q.v]) {
     my_beta = sets[lane].beta;
     my_counts = sets[lane].counts;
   }
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
           if (ntail) {
 #pragma unroll
             for (int t = 0; t < kMaxTail; t++) {
-              if (t < ntail) {
+              if (t < ntail && tout[t]) {
                 const float at = wave_sum(wv[j] * ft[t]);
                 if (lane == 0 && at != 0.0f) unsafeAtomicAdd(tout[t] + gid * tD[t], at);
               }
@@ -347,10 +353,10 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
       }
     }
   }
-  // statistics go to the first set that takes this group's beta
-  if (beta_sets) {
-    unsigned long long* st = sets[__builtin_ctz(beta_sets)].stats;
-    if (st) quad_stats(s, lane, st);
+  // statistics go to every set whose beta this group takes for this view
+  for (int b = beta_sets; b; b &= b - 1) {
+    const SetDesc& sd = sets[__builtin_ctz(b)];
+    if (sd.stats && sd.maps[q.v]) quad_stats(s, lane, sd.stats);
   }
 }
 
@@ -368,8 +374,9 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
   if (!decode_quad(ranges, geom, tiles_stride, nviews, 1, q)) return;
   const int lane = threadIdx.x;
   const SetDesc& sd = sets[0];
-  const int D = sd.D;
+  const int D = sd.D, ld = sd.stride;
   const void* map = sd.maps[q.v];
+  if (!map) return;  // the set does not take this view
   for (int e = lane; e < 64 * DG; e += 64) {
     const int p = e / DG, c = e - p * DG;
     const int gx = q.qx + (p & 7), gy = q.qy + (p >> 3);
@@ -377,7 +384,7 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
     if (c < D && gx < q.g.W && gy < q.g.H) {
       float sc = 1.0f;
       if constexpr (DT == LV_FP8_E4M3) sc = sd.scales[(int64_t)(sd.view_base + q.v) * D + c];
-      val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * D + c, sc);
+      val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * ld + c, sc);
     }
     Fs[e] = val;
   }

@@ -145,13 +145,15 @@ constexpr int kMaxSegs = 4;   // set segments per channel group
 
 // One feature set of a blend launch (device array).
 struct SetDesc {
-  const void* const* maps;    // [views] device pointers, HWC [H][W][D]
+  const void* const* maps;    // [views] device pointers, HWC [H][W][stride];
+                              // NULL: the set does not take that view
   const float* scales;        // FP8: [all views][D] scales, else null
   float* U;                   // [n][D]
   float2* beta;               // [n] compensated (hi, lo)
   uint32_t* counts;           // [n] or null
   unsigned long long* stats;  // [2] covered pixels, contributions; or null
   int32_t D;
+  int32_t stride;             // elements between consecutive pixels (>= D)
   int32_t view_base;          // index of the launch's first view in scales
 };
 
@@ -189,6 +191,22 @@ hipError_t launch_finalize(const float* U, const float2* beta, int64_t n, int D,
 
 hipError_t launch_encode(const float* src, int64_t pixels, int D, lv_dtype dtype, void* dst,
                          float* scales, float* tmp_absmax, hipStream_t s);
+
+// One merged pass of the uplift server (see serve.hip): set k takes maps[k]
+// (host array [m], NULL where the set lacks the view) and writes f and beta
+// to its outputs.
+struct BatchSet {
+  const void* const* maps;
+  const float* scales;
+  int32_t stride;
+  int32_t D;
+  float* out_feat;
+  float* out_wsum;
+};
+lv_status run_batch(lv_scene* sc, const lv_camera* cams, int32_t m, const BatchSet* sets,
+                    int nsets, lv_dtype dtype, hipStream_t s);
+// Records msg as the calling thread's lv_last_error and returns st.
+lv_status set_error(lv_status st, const char* msg);
 
 hipError_t launch_diffuse(const int32_t* row_ptr, const int32_t* col, const void* val,
                           lv_dtype val_dtype, int64_t n, const void* g0, lv_dtype dtype, int D,

@@ -1,0 +1,116 @@
+"""The uplift server and the pieces it relies on, through the C ABI: sets that
+skip views, maps that are channel slices of wider maps, and requests served
+in merged passes (each result equal to the request run alone)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2410_14462_amd as lv
+from synth import philox, scenes
+from helpers import beta_error, feature_error
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_diff(a, b):
+    a = a.double().cpu()
+    b = b.double().cpu()
+    scale = b.abs().max(dim=0).values.clamp_min(1e-30)
+    return float(((a - b).abs() / scale).max())
+
+
+@pytest.fixture(scope="module")
+def rig():
+    sc = scenes.make_scene(21, 4000, -3.8, 0.5, 0.0, 1.0)
+    cams = [scenes.look_at(e, 96, 72, 60.0) for e in scenes.fibonacci_eyes(8, 4.0)]
+    bank = torch.as_tensor(philox.normal(22, 0, 8 * 72 * 96 * 80).reshape(8, 72, 96, 80),
+                           device="cuda")
+    return sc, lv.Scene.from_arrays(sc), cams, bank
+
+
+def test_set_skips_views_and_channel_slices(rig):
+    """maps[v] = None leaves view v out of that set (its beta included); a map
+    given as channels [0, D) of a wider map reads only those channels."""
+    sc, gs, cams, bank = rig
+    D = 5
+    a = lv.Accum(gs, D, counts=True)
+    b = lv.Accum(gs, 3, counts=True)
+    maps_a = [bank[v, :, :, :D] if v % 2 == 0 else None for v in range(8)]  # slices, stride 80
+    maps_b = [bank[v, :, :, 10:13].contiguous() for v in range(8)]
+    lv.accumulate_sets(cams, [(a, maps_a), (b, maps_b)])
+    fa, ba = a.finalize()
+    fb, bb = b.finalize()
+    host_a = [bank[v, :, :, :D].cpu().numpy() for v in range(0, 8, 2)]
+    ref_a = oracle.uplift(sc, cams[0::2], host_a)
+    ref_b = oracle.uplift(sc, cams, [m.cpu().numpy() for m in maps_b])
+    assert np.array_equal(a.counts().cpu().numpy().astype(np.int64), ref_a.count)
+    assert np.array_equal(b.counts().cpu().numpy().astype(np.int64), ref_b.count)
+    assert feature_error(fa.cpu().numpy(), ref_a).max() < 1e-4
+    assert beta_error(ba.cpu().numpy(), ref_a).max() < 1e-4
+    assert feature_error(fb.cpu().numpy(), ref_b).max() < 1e-4
+    assert a.stats()["covered_pixels"] > 0 and b.stats()["covered_pixels"] > a.stats()["covered_pixels"]
+
+
+def make_requests(rig, seed, count):
+    sc, gs, cams, bank = rig
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        D = int(rng.choice([1, 3, 16, 64, 70]))
+        views = sorted(rng.choice(8, size=int(rng.integers(1, 8)), replace=False).tolist())
+        c0 = int(rng.integers(0, 80 - D + 1))
+        dtype = "bf16" if i % 3 == 2 else "f32"
+        src = bank if dtype == "f32" else bank.to(torch.bfloat16)
+        maps = [src[v, :, :, c0:c0 + D] for v in views]
+        reqs.append((D, views, maps, dtype))
+    return reqs
+
+
+@pytest.mark.parametrize("workers,budget", [(1, 0), (3, 0), (2, 4000 * 80 * 4)])
+def test_server_results_equal_alone(rig, workers, budget):
+    """Requests of different D, views and dtype on one scene, submitted at
+    once: the server merges them into passes (several in flight with more
+    workers, a tight budget admits a few at a time); every result equals the
+    request uplifted alone."""
+    sc, gs, cams, bank = rig
+    reqs = make_requests(rig, workers, 14)
+    srv = lv.Server(budget=budget, workers=workers, max_sets=4, max_channels=160)
+    for i, (D, views, maps, dtype) in enumerate(reqs):
+        srv.submit(gs, [cams[v] for v in views], maps, dtype=dtype, tag=i)
+    srv.drain()
+    done = {c["tag"]: c for c in srv.poll()}
+    st = srv.stats()
+    srv.close()
+    assert sorted(done) == list(range(len(reqs)))
+    assert all(c["status"] == 0 for c in done.values())
+    if budget:
+        assert st["peak_bytes"] <= budget
+    assert st["passes"] < len(reqs)  # some passes served several requests
+    for i, (D, views, maps, dtype) in enumerate(reqs):
+        f_alone, b_alone = gs.uplift([cams[v] for v in views], [m.contiguous() for m in maps],
+                                     dtype=dtype)
+        c = done[i]
+        assert c["t_submit"] <= c["t_start"] <= c["t_end"]
+        assert rel_diff(c["out"], f_alone) < 1e-5, (i, D, views, dtype, c["batch_size"])
+        assert rel_diff(c["wsum"][:, None], b_alone[:, None]) < 1e-5
+
+
+def test_server_rejects_and_recovers(rig):
+    sc, gs, cams, bank = rig
+    srv = lv.Server(budget=1000, workers=1)
+    with pytest.raises(lv.LvError):  # larger than the whole budget
+        srv.submit(gs, cams[:1], [bank[0, :, :, :4]])
+    srv.close()
+    srv = lv.Server(workers=1)
+    with pytest.raises(lv.LvError):  # camera with zero width
+        bad = scenes.look_at([0, 0, 4.0], 96, 72, 60.0)
+        bad.width = 0
+        srv.submit(gs, [bad], [bank[0, :, :, :4]])
+    t = srv.submit(gs, cams[:2], [bank[0, :, :, :4], bank[1, :, :, :4]])
+    srv.drain()
+    (c,) = srv.poll()
+    assert c["tag"] == t and c["status"] == 0
+    f, b = gs.uplift(cams[:2], [bank[0, :, :, :4].contiguous(), bank[1, :, :, :4].contiguous()])
+    assert rel_diff(c["out"], f) < 1e-5
+    srv.close()
