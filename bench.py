@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM traffic counters)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the serving trace (0 = skip the serving leg)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, req/s")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -187,6 +190,13 @@ def main():
     if not args.no_extras:
         out.update(extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac))
 
+    if args.serve_requests > 0:
+        del maps, masks, f64, b64, f1, b1
+        torch.cuda.empty_cache()
+        out["serving"] = serving(lv, args.serve_requests, args.serve_rate)
+        maps = [scenes.feature_map(w, v, device="cuda") for v in range(args.cpu_views)]
+        masks = [dev(scenes.ellipse_mask(w.seed, v, H, W)) for v in range(args.cpu_views)]
+
     if args.cpu_views > 0:
         out["cpu_baseline"] = cpu_baseline(w, sc, cams, maps, masks, args.cpu_views)
         out["cpu_baseline"]["gpu_over_cpu"] = round(out["cpu_baseline"]["value"] / value, 1)
@@ -281,6 +291,77 @@ def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
     G.close()
     s.close()
     return res
+
+
+def serving(lv, nreq, rate, bank_k=4):
+    """The serving trace (synth.trace) twice: BF16 maps through the server
+    (2 workers, same-scene requests merged into one pass, admission by a
+    64 GiB accumulator budget), and FP32 maps one request at a time (1 worker,
+    no merging).  Latency = completion - submission; submissions follow the
+    trace's arrival times."""
+    import torch
+    from synth import trace
+    log(f"bench: serving leg ({nreq} requests at {rate}/s): scenes, rigs, map bank")
+    scs = [lv.Scene.from_arrays(s) for s in trace.scenes()]
+    rigs = [trace.rig(r) for r in range(len(trace.RESOLUTIONS))]
+    bank32 = [trace.bank(r, bank_k) for r in range(len(trace.RESOLUTIONS))]
+    bank16 = [[b.to(torch.bfloat16) for b in bk] for bk in bank32]
+    reqs = trace.requests(nreq, rate)
+    check = list(range(min(6, nreq)))  # requests whose BF16 and FP32 results are compared
+
+    def run(dtype, workers, max_sets):
+        bank = bank16 if dtype == "bf16" else bank32
+        srv = lv.Server(budget=64 << 30, workers=workers, max_sets=max_sets, max_channels=1024)
+        # warm each worker's stream workspace on every scene (not timed)
+        for k, g in enumerate(scs):
+            for _ in range(workers):
+                srv.submit(g, rigs[2][:1], [bank[2][0][..., :4]], dtype=dtype, tag=1_000_000 + k)
+        srv.drain()
+        srv.poll()
+        torch.cuda.synchronize()
+        kept, comps = {}, []
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            while time.perf_counter() - t0 < r.arrival:
+                time.sleep(0.0005)
+            maps = [bank[r.res][v % bank_k][..., :r.D] for v in r.views]
+            srv.submit(scs[r.scene], [rigs[r.res][v] for v in r.views], maps, dtype=dtype, tag=i)
+            for c in srv.poll():
+                comps.append(c)
+        srv.drain()
+        comps += srv.poll()
+        st = srv.stats()
+        srv.close()
+        for c in comps:
+            if c["tag"] in check:
+                kept[c["tag"]] = c["out"]
+        assert len(comps) == nreq and all(c["status"] == 0 for c in comps)
+        lat = [(c["t_end"] - c["t_submit"]) * 1e3 for c in comps]
+        span = max(c["t_end"] for c in comps) - min(c["t_submit"] for c in comps)
+        res = {"p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),
+               "req_per_s": round(nreq / span, 3), "makespan_s": round(span, 3),
+               "passes": st["passes"] - len(scs) * workers,
+               "mean_requests_per_pass": round(nreq / max(1, st["passes"] - len(scs) * workers), 2)}
+        return res, kept
+
+    served, out16 = run("bf16", 2, 8)
+    log(f"bench: served {served}")
+    base, out32 = run("f32", 1, 1)
+    log(f"bench: baseline {base}")
+    err = 0.0
+    for k in check:
+        a, b = out16[k].double(), out32[k].double()
+        err = max(err, float(((a - b).abs().max(dim=0).values / b.abs().max(dim=0).values.clamp_min(1e-30)).max()))
+    views = [len(r.views) for r in reqs]
+    return {
+        "trace": {"requests": nreq, "rate_per_s": rate, "scenes": list(trace.SCENE_SIZES),
+                  "resolutions": [list(x) for x in trace.RESOLUTIONS], "D": list(trace.D_CHOICES),
+                  "views_mean": round(sum(views) / len(views), 1)},
+        "served_bf16": served,
+        "baseline_f32_one_at_a_time": base,
+        "speedup_req_per_s": round(served["req_per_s"] / base["req_per_s"], 3),
+        "bf16_vs_f32_max_rel_err": err,
+    }
 
 
 def cpu_baseline(w, sc, cams, maps, masks, views):

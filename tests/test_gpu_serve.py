@@ -114,3 +114,29 @@ def test_server_rejects_and_recovers(rig):
     f, b = gs.uplift(cams[:2], [bank[0, :, :, :4].contiguous(), bank[1, :, :, :4].contiguous()])
     assert rel_diff(c["out"], f) < 1e-5
     srv.close()
+
+
+def test_serving_trace_mix_equals_alone():
+    """A short serving trace (all requests at once, so they queue and merge):
+    three small scenes, the trace's D, resolution and view draws (at most 12
+    views), BF16 maps; each served result equals the request alone."""
+    from synth import trace
+    scs = [lv.Scene.from_arrays(s) for s in trace.scenes((20_000, 40_000, 60_000))]
+    rigs = [trace.rig(r) for r in range(3)]
+    bank = [[b.to(torch.bfloat16) for b in trace.bank(r, 2)] for r in range(3)]
+    reqs = trace.requests(12, rate=1e6, max_views=12)
+    srv = lv.Server(workers=2, max_sets=8)
+    for i, r in enumerate(reqs):
+        srv.submit(scs[r.scene], [rigs[r.res][v] for v in r.views],
+                   [bank[r.res][v % 2][..., :r.D] for v in r.views], dtype="bf16", tag=i)
+    srv.drain()
+    done = {c["tag"]: c for c in srv.poll()}
+    st = srv.stats()
+    srv.close()
+    assert len(done) == len(reqs) and st["passes"] < len(reqs)
+    for i, r in enumerate(reqs):
+        maps = [bank[r.res][v % 2][..., :r.D].contiguous() for v in r.views]
+        f, b = scs[r.scene].uplift([rigs[r.res][v] for v in r.views], maps, dtype="bf16")
+        assert done[i]["status"] == 0
+        assert rel_diff(done[i]["out"], f) < 1e-5, (i, r.D, r.res, len(r.views), done[i]["batch_size"])
+        assert rel_diff(done[i]["wsum"][:, None], b[:, None]) < 1e-5
