@@ -208,7 +208,7 @@ def measured_traffic():
     """HBM bytes per D=64 blend launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, if it was taken on the current kernel source (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "uplift-200k-50v-512x384-D64_blend_traffic.json")
+    path = os.path.join(ROOT, "profiles", "uplift-200k-50v-512x384-D64+mask_blend_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
