@@ -262,7 +262,7 @@ def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
         "ms_per_view_channel": round(t_bf * 1e3 / (m * D), 7),
         "ms_per_view_channel_f32": round(t_f32 * 1e3 / (m * D), 7),
         "err_vs_f32": {"max": float(err.max()), "p99": float(torch.quantile(err[:1000000], 0.99)),
-                       "mean": float(err.mean()), "bound": 2.0 ** -8},
+                       "mean": float(err.mean()), "bound": 2.0 ** -8 + 1e-4},
     }
     del enc, absmaps
     # ---- diffusion over the 16-NN graph of the scene (graph built on the host)
@@ -335,7 +335,9 @@ def serving(lv, nreq, rate, bank_k=4):
         for c in comps:
             if c["tag"] in check:
                 kept[c["tag"]] = c["out"]
-        assert len(comps) == nreq and all(c["status"] == 0 for c in comps)
+        bad = [(c["tag"], c["status"]) for c in comps if c["status"] != 0]
+        if len(comps) != nreq or bad:
+            raise RuntimeError(f"serving: {len(comps)} of {nreq} completed, failed: {bad[:8]}")
         lat = [(c["t_end"] - c["t_submit"]) * 1e3 for c in comps]
         span = max(c["t_end"] for c in comps) - min(c["t_submit"] for c in comps)
         res = {"p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),

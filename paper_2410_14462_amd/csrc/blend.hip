@@ -213,15 +213,66 @@ __device__ __forceinline__ void quad_stats(const Walk& s, int lane, unsigned lon
 
 // ---------------------------------------------------------------- wide kernel
 // Any number of feature sets; the workgroup's channel group has up to 64
-// channels made of segments of the sets (lane = channel) plus up to 4 tail
-// channels (lane = pixel, reduced across the wave).
+// channels made of segments of the sets plus up to 4 tail channels (lane =
+// pixel, reduced across the wave).
+//
+// Accumulation on the matrix cores.  After the walk of a step, the weights
+// of its 32 Gaussians at the quadrant's 64 pixels form W_s (32 x 64), and
+// the contribution of the step to the group's channels is the dense product
+// U_s = W_s F (F: 64 pixels x 64 channels).  It runs as 32x32x8 BF16 MFMAs
+// with FP32 accumulation on split operands: x = hi + lo, hi = bf16(x) and
+// lo = bf16(x - hi) (both round-to-nearest-even), so |x - hi - lo| <=
+// 2^-18 |x|; U_s = W_hi F_hi + W_lo F_hi + W_hi F_lo (the dropped W_lo F_lo
+// and residuals are below 2^-16 |W| |F|; BF16 maps are exact, F_lo = 0).
+// K-steps of 8 pixels are one pixel row of the quadrant: rows without any
+// contribution are skipped.  Operand layouts (32x32x8): lane l holds
+// A[l % 32][4 (l / 32) + i] and B[4 (l / 32) + i][l % 32], i = 0..3, and
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in accumulator r.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWtPitch = 68;  // LDS row pitch (floats) of the transposed weights
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const __bf16 ha = (__bf16)a, hb = (__bf16)b;  // round to nearest even
+  return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+}
+
+__device__ __forceinline__ void split4(float x0, float x1, float x2, float x3, bf16x4& hi,
+                                       bf16x4& lo) {
+  const uint32_t h01 = pack_bf16(x0, x1), h23 = pack_bf16(x2, x3);
+  const float r0 = x0 - __uint_as_float(h01 << 16), r1 = x1 - __uint_as_float(h01 & 0xFFFF0000u);
+  const float r2 = x2 - __uint_as_float(h23 << 16), r3 = x3 - __uint_as_float(h23 & 0xFFFF0000u);
+  u32x2 h, l;
+  h.x = h01;
+  h.y = h23;
+  l.x = pack_bf16(r0, r1);
+  l.y = pack_bf16(r2, r3);
+  hi = __builtin_bit_cast(bf16x4, h);
+  lo = __builtin_bit_cast(bf16x4, l);
+}
+
+__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Rows (8 pixels each) of a 64-pixel mask that hold a set bit.
+__device__ __forceinline__ uint32_t row_bits(uint64_t m) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) r |= (((m >> (8 * k)) & 0xFFull) != 0ull ? 1u : 0u) << k;
+  return r;
+}
+
 template <lv_dtype DT>
 __global__ __launch_bounds__(64) void blend_wide_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
     const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
   constexpr int G = kChunk;
-  extern __shared__ float Fs[];  // [64 pixels][64 channels], pixel-major
+  constexpr bool kSplitF = DT != LV_BF16;  // BF16 maps are exact in one BF16 operand
+  __shared__ __align__(16) float Wt[G * kWtPitch];  // a step's weights, [Gaussian][pixel]
   Quad q;
   if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
   const int lane = threadIdx.x;
@@ -229,43 +280,33 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   const int width = grp.width, nseg = grp.nseg, ntail = grp.ntail;
   const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
   const bool inside = px < q.g.W && py < q.g.H;
+  const bool two = width > 32;  // second block of 32 channels
 
-  // Stage the quadrant's features, one segment at a time (uniform loop):
-  // wide segments row by row (lane = channel, coalesced), narrow ones channel
-  // by channel (lane = pixel).  This lane's output channel is noted on the way.
-  float* out0 = nullptr;
-  int D0 = 0;
+  // This lane's channel in each block (n = l % 32) and where it comes from.
+  float* outp[2] = {nullptr, nullptr};
+  int outD[2] = {0, 0};
   bool active = false;  // some segment or tail channel takes this view
+  const void* src[2] = {nullptr, nullptr};
+  int64_t srcc[2] = {0, 0};
+  int srcld[2] = {0, 0};
+  float srcsc[2] = {1.0f, 1.0f};
   for (int k = 0; k < nseg; k++) {
     const SetDesc& sd = sets[grp.set[k]];
     const void* map = sd.maps[q.v];
     if (!map) continue;  // this set does not take the view
     active = true;
-    const int D = sd.D, ld = sd.stride, c0 = grp.c0[k], vc0 = grp.vc0[k], cnt = grp.cnt[k];
-    const float* scl = nullptr;
-    if constexpr (DT == LV_FP8_E4M3) scl = sd.scales + (int64_t)(sd.view_base + q.v) * D + c0;
-    if (lane >= vc0 && lane < vc0 + cnt) {
-      out0 = sd.U + c0 + (lane - vc0);
-      D0 = D;
-    }
-    if (cnt >= 16) {
-      const bool mine = lane < cnt;
-      float sc = 1.0f;
-      if constexpr (DT == LV_FP8_E4M3) sc = mine ? scl[lane] : 1.0f;
-      for (int p = 0; p < 64; p++) {
-        const int gx = q.qx + (p & 7), gy = q.qy + (p >> 3);
-        float val = 0.0f;
-        if (mine && gx < q.g.W && gy < q.g.H)
-          val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * ld + c0 + lane, sc);
-        if (mine) Fs[p * 64 + vc0 + lane] = val;
-      }
-    } else {
-      for (int c = 0; c < cnt; c++) {
-        float sc = 1.0f;
-        if constexpr (DT == LV_FP8_E4M3) sc = scl[c];
-        float val = 0.0f;
-        if (inside) val = load_feature<DT>(map, ((int64_t)py * q.g.W + px) * ld + c0 + c, sc);
-        Fs[lane * 64 + vc0 + c] = val;
+    const int vc0 = grp.vc0[k], cnt = grp.cnt[k];
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      const int ch = b * 32 + (lane & 31);
+      if (ch >= vc0 && ch < vc0 + cnt) {
+        const int c = grp.c0[k] + (ch - vc0);
+        outp[b] = sd.U + c;
+        outD[b] = sd.D;
+        src[b] = map;
+        srcc[b] = c;
+        srcld[b] = sd.stride;
+        if constexpr (DT == LV_FP8_E4M3) srcsc[b] = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
       }
     }
   }
@@ -291,19 +332,41 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     }
   }
   if (!active) return;  // wave-uniform: no set of this group takes the view
-  __syncthreads();
-  const float* f0 = Fs + lane;  // this lane's channel of pixel 0 (lanes >= width idle)
-  const int beta_sets = grp.beta_sets;
-  float2* my_beta = nullptr;
-  uint32_t* my_counts = nullptr;
-  if (lane < kMaxSets && ((beta_sets >> lane) & 1) && sets[lane].maps[q.v]) {
-    my_beta = sets[lane].beta;
-    my_counts = sets[lane].counts;
+
+  // B operands: F[pixel (row ks, column 4 (l / 32) + i)][channel], split
+  bf16x4 fh[2][8], fl[2][8];
+  {
+    const int cx = q.qx + 4 * (lane >> 5);
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+#pragma unroll
+      for (int ks = 0; ks < 8; ks++) {
+        float v[4];
+        const int gy = q.qy + ks;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int gx = cx + i;
+          v[i] = 0.0f;
+          if (src[b] && gx < q.g.W && gy < q.g.H)
+            v[i] = load_feature<DT>(src[b], ((int64_t)gy * q.g.W + gx) * srcld[b] + srcc[b], srcsc[b]);
+        }
+        split4(v[0], v[1], v[2], v[3], fh[b][ks], fl[b][ks]);
+      }
+    }
   }
+
+  // sets whose beta (and counts) this group adds for this view (wave-uniform)
+  int bsets = 0;
+  for (int b = grp.beta_sets; b; b &= b - 1)
+    if (sets[__builtin_ctz(b)].maps[q.v]) bsets |= b & -b;
+
+  // wave-uniform: some lane owns a main channel (else only tail channels)
+  const bool has_main = __ballot(outp[0] != nullptr || outp[1] != nullptr) != 0ull;
 
   Walk s;
   walk_init(q, lane, s);
   const Rec* vrec = rec + (int64_t)q.v * n;
+  const float* wrow = Wt + (lane & 31) * kWtPitch + 4 * (lane >> 5);
   for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
     if (__ballot(s.alive) == 0ull) break;
     const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
@@ -313,30 +376,27 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     float wv[G];
     step_walk<G>(hits, q0, q1, s, wv);
 
+    // per Gaussian with a contribution: weight sum and count (kept by lane j
+    // for one round of atomics after the loop), tail channels; W_s to LDS
+    uint32_t anyw = 0u;
+    uint64_t allm = 0ull;
+    float my_ws = 0.0f;
+    uint32_t my_cnt = 0u;
 #pragma unroll
     for (int j = 0; j < G; j++) {
       if ((hits >> j) & 1ull) {
         const uint64_t msk = __ballot(wv[j] > 0.0f);
         if (msk) {
-          const int wj = __float_as_int(wv[j]);
-          float acc0 = 0.0f;
-#pragma unroll
-          for (int r = 0; r < 8; r++) {
-            if ((msk >> (8 * r)) & 0xFFull) {
-              float wl[8], fv[8];
-#pragma unroll
-              for (int k = 0; k < 8; k++) {
-                wl[k] = __int_as_float(__builtin_amdgcn_readlane(wj, 8 * r + k));
-                fv[k] = f0[(8 * r + k) * 64];
-              }
-#pragma unroll
-              for (int k = 0; k < 8; k++) acc0 = __builtin_fmaf(wl[k], fv[k], acc0);
-            }
-          }
+          anyw |= 1u << j;
+          allm |= msk;
+          Wt[j * kWtPitch + lane] = wv[j];
           const float ws = wave_sum(wv[j]);
-          const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-          if (out0 && acc0 != 0.0f) unsafeAtomicAdd(out0 + gid * D0, acc0);
+          if (lane == j) {
+            my_ws = ws;
+            my_cnt = (uint32_t)__popcll(msk);
+          }
           if (ntail) {
+            const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
 #pragma unroll
             for (int t = 0; t < kMaxTail; t++) {
               if (t < ntail && tout[t]) {
@@ -345,18 +405,60 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
               }
             }
           }
-          if (my_beta) {
-            twosum_atomic_add(my_beta + gid, ws);
-            if (my_counts) atomicAdd(my_counts + gid, (uint32_t)__popcll(msk));
-          }
+        }
+      }
+    }
+    if (lane < G && ((anyw >> lane) & 1u)) {  // lanes j < 32 whose Gaussian contributed
+      for (int b = bsets; b; b &= b - 1) {
+        const SetDesc& sd = sets[__builtin_ctz(b)];
+        twosum_atomic_add(sd.beta + my_id, my_ws);
+        if (sd.counts) atomicAdd(sd.counts + my_id, my_cnt);
+      }
+    }
+    if (!anyw || !has_main) continue;
+    __syncthreads();  // W_s written (one wave per workgroup: orders LDS)
+
+    // U_s = W_s F on the matrix cores, K-steps = pixel rows with contributions
+    const uint32_t rows = row_bits(allm);
+    f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+    for (int ks = 0; ks < 8; ks++) {
+      if ((rows >> ks) & 1u) {
+        const float4 w4 = *reinterpret_cast<const float4*>(wrow + ks * 8);
+        bf16x4 ah, al;
+        split4(w4.x, w4.y, w4.z, w4.w, ah, al);
+        acc0 = mfma(ah, fh[0][ks], acc0);
+        acc0 = mfma(al, fh[0][ks], acc0);
+        if constexpr (kSplitF) acc0 = mfma(ah, fl[0][ks], acc0);
+        if (two) {
+          acc1 = mfma(ah, fh[1][ks], acc1);
+          acc1 = mfma(al, fh[1][ks], acc1);
+          if constexpr (kSplitF) acc1 = mfma(ah, fl[1][ks], acc1);
+        }
+      }
+    }
+    __syncthreads();  // W_s read before the next step overwrites it
+
+    // one atomic per (Gaussian with a contribution, channel)
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int m0 = 8 * (r >> 2) + (r & 3), m1 = m0 + 4;
+      if (((anyw >> m0) | (anyw >> m1)) & 1u) {
+        const uint32_t g0 = (uint32_t)__builtin_amdgcn_readlane((int)my_id, m0);
+        const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)my_id, m1);
+        const bool upper = lane >= 32;
+        const int64_t gid = (int64_t)(upper ? g1 : g0);
+        if ((anyw >> (upper ? m1 : m0)) & 1u) {
+          if (outp[0] && acc0[r] != 0.0f) unsafeAtomicAdd(outp[0] + gid * outD[0], acc0[r]);
+          if (two && outp[1] && acc1[r] != 0.0f) unsafeAtomicAdd(outp[1] + gid * outD[1], acc1[r]);
         }
       }
     }
   }
   // statistics go to every set whose beta this group takes for this view
-  for (int b = beta_sets; b; b &= b - 1) {
+  for (int b = bsets; b; b &= b - 1) {
     const SetDesc& sd = sets[__builtin_ctz(b)];
-    if (sd.stats && sd.maps[q.v]) quad_stats(s, lane, sd.stats);
+    if (sd.stats) quad_stats(s, lane, sd.stats);
   }
 }
 
@@ -407,6 +509,9 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
     const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
     float wv[G];
     step_walk<G>(hits, q0, q1, s, wv);
+    float my_ws = 0.0f;
+    uint32_t my_cnt = 0u;
+    bool mine = false;
 
 #pragma unroll
     for (int j = 0; j < G; j++) {
@@ -432,12 +537,19 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
           }
           const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
           if (lane < D && acc != 0.0f) unsafeAtomicAdd(&sd.U[gid * D + lane], acc);
-          if (lane == 0) {
-            twosum_atomic_add(&sd.beta[gid], wsl);
-            if (sd.counts) atomicAdd(&sd.counts[gid], (uint32_t)__popcll(msk));
+          const float ws = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wsl), 0));
+          if (lane == j) {
+            my_ws = ws;
+            my_cnt = (uint32_t)__popcll(msk);
+            mine = true;
           }
         }
       }
+    }
+    // one round of weight-sum atomics per step (lane j: Gaussian j)
+    if (mine) {
+      twosum_atomic_add(&sd.beta[my_id], my_ws);
+      if (sd.counts) atomicAdd(&sd.counts[my_id], my_cnt);
     }
   }
   if (sd.stats) quad_stats(s, lane, sd.stats);
@@ -468,8 +580,8 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   }
   int64_t work = (int64_t)a.tiles_stride * m * a.ngroups;
   int64_t blocks = (work + 7) / 8 * 32;
-  hipLaunchKernelGGL(blend_wide_kernel<DT>, dim3((unsigned)blocks), dim3(64),
-                     sizeof(float) * 64 * 64, s, a.rec, a.ids, a.ranges, a.geom, a.n,
+  hipLaunchKernelGGL(blend_wide_kernel<DT>, dim3((unsigned)blocks), dim3(64), 0, s, a.rec,
+                     a.ids, a.ranges, a.geom, a.n,
                      a.tiles_stride, m, a.sets, a.groups, a.ngroups);
   return hipGetLastError();
 }

@@ -13,6 +13,14 @@ from helpers import beta_error, feature_error
 pytestmark = pytest.mark.gpu
 
 
+# Served and alone results may come from different kernels (a merged pass
+# accumulates on the matrix cores with split BF16 operands, error <= ~2^-16
+# |w| |F| per term; a lone narrow request uses FP32 FMAs): both are within the
+# path's 1e-4 of the FP64 result, so they are compared at 1e-4 of the
+# channel's largest value.  Weight sums use the same FP32 reduction: 1e-5.
+TOL_F, TOL_B = 1e-4, 1e-5
+
+
 def rel_diff(a, b):
     a = a.double().cpu()
     b = b.double().cpu()
@@ -92,8 +100,8 @@ def test_server_results_equal_alone(rig, workers, budget):
                                      dtype=dtype)
         c = done[i]
         assert c["t_submit"] <= c["t_start"] <= c["t_end"]
-        assert rel_diff(c["out"], f_alone) < 1e-5, (i, D, views, dtype, c["batch_size"])
-        assert rel_diff(c["wsum"][:, None], b_alone[:, None]) < 1e-5
+        assert rel_diff(c["out"], f_alone) < TOL_F, (i, D, views, dtype, c["batch_size"])
+        assert rel_diff(c["wsum"][:, None], b_alone[:, None]) < TOL_B
 
 
 def test_server_rejects_and_recovers(rig):
@@ -112,7 +120,7 @@ def test_server_rejects_and_recovers(rig):
     (c,) = srv.poll()
     assert c["tag"] == t and c["status"] == 0
     f, b = gs.uplift(cams[:2], [bank[0, :, :, :4].contiguous(), bank[1, :, :, :4].contiguous()])
-    assert rel_diff(c["out"], f) < 1e-5
+    assert rel_diff(c["out"], f) < TOL_F
     srv.close()
 
 
@@ -138,5 +146,5 @@ def test_serving_trace_mix_equals_alone():
         maps = [bank[r.res][v % 2][..., :r.D].contiguous() for v in r.views]
         f, b = scs[r.scene].uplift([rigs[r.res][v] for v in r.views], maps, dtype="bf16")
         assert done[i]["status"] == 0
-        assert rel_diff(done[i]["out"], f) < 1e-5, (i, r.D, r.res, len(r.views), done[i]["batch_size"])
-        assert rel_diff(done[i]["wsum"][:, None], b[:, None]) < 1e-5
+        assert rel_diff(done[i]["out"], f) < TOL_F, (i, r.D, r.res, len(r.views), done[i]["batch_size"])
+        assert rel_diff(done[i]["wsum"][:, None], b[:, None]) < TOL_B
