@@ -361,7 +361,7 @@ lv_status lv_accum_create(lv_scene* sc, int32_t D, uint32_t flags, void* stream,
   a->flags = flags;
   size_t n1 = (size_t)(sc->n > 0 ? sc->n : 1);
   hipError_t e = a->U.ensure(sizeof(float) * n1 * D, s);
-  if (e == hipSuccess) e = a->beta.ensure(sizeof(float2) * n1, s);
+  if (e == hipSuccess) e = a->beta.ensure(sizeof(beta_t) * n1, s);
   if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->counts.ensure(4 * n1, s);
   if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->dstats.ensure(16, s);
   if (e != hipSuccess) {
@@ -386,7 +386,7 @@ lv_status lv_accum_reset(lv_accum* a, void* stream) {
   if (a->dstats.p) HIP_TRY(hipMemsetAsync(a->dstats.p, 0, 16, s));
   if (n == 0) return LV_OK;
   HIP_TRY(hipMemsetAsync(a->U.p, 0, sizeof(float) * n * a->D, s));
-  HIP_TRY(hipMemsetAsync(a->beta.p, 0, sizeof(float2) * n, s));
+  HIP_TRY(hipMemsetAsync(a->beta.p, 0, sizeof(beta_t) * n, s));
   if (a->counts.p) HIP_TRY(hipMemsetAsync(a->counts.p, 0, 4 * n, s));
   return LV_OK;
 }
@@ -515,7 +515,7 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
       sd[k].maps = reinterpret_cast<const void* const*>(dev + b_sets + b_groups) + (size_t)k * mv;
       sd[k].scales = fsets[k].scales;
       sd[k].U = a->U.as<float>();
-      sd[k].beta = a->beta.as<float2>();
+      sd[k].beta = a->beta.as<beta_t>();
       sd[k].counts = a->counts.as<uint32_t>();
       sd[k].stats = a->dstats.as<unsigned long long>();
       sd[k].D = a->D;
@@ -573,7 +573,7 @@ lv_status lv_accum_finalize(lv_accum* a, float* out_feat, float* out_wsum, float
   if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
   if (a->scene->n > 0 && !out_feat && !out_wsum && !out_sum)
     return fail(LV_ERR_INVALID_ARG, "no output requested");
-  HIP_TRY(launch_finalize(a->U.as<float>(), a->beta.as<float2>(), a->scene->n, a->D, out_feat,
+  HIP_TRY(launch_finalize(a->U.as<float>(), a->beta.as<beta_t>(), a->scene->n, a->D, out_feat,
                           out_wsum, out_sum, static_cast<hipStream_t>(stream)));
   return LV_OK;
 }
@@ -664,7 +664,7 @@ lv_status lv_uplift_sets(lv_scene* sc, const lv_camera* cams, int32_t m, const l
     {
       std::lock_guard<std::mutex> lk(ws.mu);
       HIP_TRY(ws.accUs[k].ensure(sizeof(float) * n1 * sets[k].D, s));
-      HIP_TRY(ws.accBs[k].ensure(sizeof(float2) * n1, s));
+      HIP_TRY(ws.accBs[k].ensure(sizeof(beta_t) * n1, s));
     }
     acc[k].scene = sc;
     acc[k].D = sets[k].D;
@@ -911,7 +911,7 @@ lv_status run_batch(lv_scene* sc, const lv_camera* cams, int32_t m, const BatchS
     void* U = nullptr;
     void* B = nullptr;
     hipError_t e = hipMallocAsync(&U, sizeof(float) * n1 * sets[k].D, s);
-    if (e == hipSuccess) e = hipMallocAsync(&B, sizeof(float2) * n1, s);
+    if (e == hipSuccess) e = hipMallocAsync(&B, sizeof(beta_t) * n1, s);
     if (e != hipSuccess) {
       if (U) (void)hipFreeAsync(U, s);
       st = fail(LV_ERR_OUT_OF_MEMORY, "server accumulator: %s", hipGetErrorString(e));

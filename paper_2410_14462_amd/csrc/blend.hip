@@ -21,7 +21,7 @@
 //        offsets (features staged pixel-major, 64 words per pixel);
 //        tail channels stay in registers and are reduced across the wave;
 //      small kernel (one set, D <= 32): 64/DG pixel slots of DG channels;
-//      then one global atomic per channel and a compensated beta update.
+//      then one global atomic per channel; beta in exact fixed point.
 #include "lv_internal.h"
 
 namespace lv {
@@ -219,42 +219,40 @@ __device__ __forceinline__ void quad_stats(const Walk& s, int lane, unsigned lon
 // Accumulation on the matrix cores.  After the walk of a step, the weights
 // of its 32 Gaussians at the quadrant's 64 pixels form W_s (32 x 64), and
 // the contribution of the step to the group's channels is the dense product
-// U_s = W_s F (F: 64 pixels x 64 channels).  It runs as 32x32x8 BF16 MFMAs
+// U_s = W_s F (F: 64 pixels x 64 channels).  It runs as 32x32x16 BF16 MFMAs
 // with FP32 accumulation on split operands: x = hi + lo, hi = bf16(x) and
 // lo = bf16(x - hi) (both round-to-nearest-even), so |x - hi - lo| <=
 // 2^-18 |x|; U_s = W_hi F_hi + W_lo F_hi + W_hi F_lo (the dropped W_lo F_lo
-// and residuals are below 2^-16 |W| |F|; BF16 maps are exact, F_lo = 0).
-// K-steps of 8 pixels are one pixel row of the quadrant: rows without any
-// contribution are skipped.  Operand layouts (32x32x8): lane l holds
-// A[l % 32][4 (l / 32) + i] and B[4 (l / 32) + i][l % 32], i = 0..3, and
-// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in accumulator r.
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// and residuals are below 2^-16 |W| |F|;
+// BF16 maps are exact, F_lo = 0).  A K-step of 16 pixels is two pixel rows of
+// the quadrant: steps whose rows hold no contribution are skipped.  Operand
+// layouts (32x32x16): lane l holds A[l % 32][8 (l / 32) + i] and
+// B[8 (l / 32) + i][l % 32], i = 0..7, and D[8 (r / 4) + 4 (l / 32) + r % 4]
+// [l % 32] in accumulator r.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kWtPitch = 68;  // LDS row pitch (floats) of the transposed weights
 
-__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
-  const __bf16 ha = (__bf16)a, hb = (__bf16)b;  // round to nearest even
-  return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+// x = hi + lo + O(2^-18 |x|), conversions round to nearest even
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    hi[i] = (__bf16)x[i];
+    lo[i] = (__bf16)(x[i] - (float)hi[i]);
+  }
 }
 
-__device__ __forceinline__ void split4(float x0, float x1, float x2, float x3, bf16x4& hi,
-                                       bf16x4& lo) {
-  const uint32_t h01 = pack_bf16(x0, x1), h23 = pack_bf16(x2, x3);
-  const float r0 = x0 - __uint_as_float(h01 << 16), r1 = x1 - __uint_as_float(h01 & 0xFFFF0000u);
-  const float r2 = x2 - __uint_as_float(h23 << 16), r3 = x3 - __uint_as_float(h23 & 0xFFFF0000u);
-  u32x2 h, l;
-  h.x = h01;
-  h.y = h23;
-  l.x = pack_bf16(r0, r1);
-  l.y = pack_bf16(r2, r3);
-  hi = __builtin_bit_cast(bf16x4, h);
-  lo = __builtin_bit_cast(bf16x4, l);
+// A operand of one K-step: this lane's 8 weights (two float4 from LDS), split
+__device__ __forceinline__ void load_split_w(const float* w, bf16x8& hi, bf16x8& lo) {
+  const float4 wa = *reinterpret_cast<const float4*>(w);
+  const float4 wb = *reinterpret_cast<const float4*>(w + 4);
+  const float w8[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+  split8(w8, hi, lo);
 }
 
-__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
 // Rows (8 pixels each) of a 64-pixel mask that hold a set bit.
@@ -333,25 +331,22 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   }
   if (!active) return;  // wave-uniform: no set of this group takes the view
 
-  // B operands: F[pixel (row ks, column 4 (l / 32) + i)][channel], split
-  bf16x4 fh[2][8], fl[2][8];
-  {
-    const int cx = q.qx + 4 * (lane >> 5);
+  // B operands: F[pixel (row 2 t + l / 32, column i)][channel], split
+  bf16x8 fh[2][4], fl[2][4];
 #pragma unroll
-    for (int b = 0; b < 2; b++) {
+  for (int b = 0; b < 2; b++) {
 #pragma unroll
-      for (int ks = 0; ks < 8; ks++) {
-        float v[4];
-        const int gy = q.qy + ks;
+    for (int t = 0; t < 4; t++) {
+      float v[8];
+      const int gy = q.qy + 2 * t + (lane >> 5);
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int gx = cx + i;
-          v[i] = 0.0f;
-          if (src[b] && gx < q.g.W && gy < q.g.H)
-            v[i] = load_feature<DT>(src[b], ((int64_t)gy * q.g.W + gx) * srcld[b] + srcc[b], srcsc[b]);
-        }
-        split4(v[0], v[1], v[2], v[3], fh[b][ks], fl[b][ks]);
+      for (int i = 0; i < 8; i++) {
+        const int gx = q.qx + i;
+        v[i] = 0.0f;
+        if (src[b] && gx < q.g.W && gy < q.g.H)
+          v[i] = load_feature<DT>(src[b], ((int64_t)gy * q.g.W + gx) * srcld[b] + srcc[b], srcsc[b]);
       }
+      split8(v, fh[b][t], fl[b][t]);
     }
   }
 
@@ -366,7 +361,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   Walk s;
   walk_init(q, lane, s);
   const Rec* vrec = rec + (int64_t)q.v * n;
-  const float* wrow = Wt + (lane & 31) * kWtPitch + 4 * (lane >> 5);
+  const float* wrow = Wt + (lane & 31) * kWtPitch + 8 * (lane >> 5);
   for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
     if (__ballot(s.alive) == 0ull) break;
     const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
@@ -411,29 +406,43 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     if (lane < G && ((anyw >> lane) & 1u)) {  // lanes j < 32 whose Gaussian contributed
       for (int b = bsets; b; b &= b - 1) {
         const SetDesc& sd = sets[__builtin_ctz(b)];
-        twosum_atomic_add(sd.beta + my_id, my_ws);
+        beta_atomic_add(sd.beta + my_id, my_ws);
         if (sd.counts) atomicAdd(sd.counts + my_id, my_cnt);
       }
     }
     if (!anyw || !has_main) continue;
     __syncthreads();  // W_s written (one wave per workgroup: orders LDS)
 
-    // U_s = W_s F on the matrix cores, K-steps = pixel rows with contributions
+    // U_s = W_s F on the matrix cores; K-steps = pairs of pixel rows holding
+    // a contribution; hi*hi and the two cross terms in separate accumulators
     const uint32_t rows = row_bits(allm);
     f32x16 acc0 = {}, acc1 = {};
+    // (no branch between the MFMAs of one chain: separate loops per width)
+    if (two) {
 #pragma unroll
-    for (int ks = 0; ks < 8; ks++) {
-      if ((rows >> ks) & 1u) {
-        const float4 w4 = *reinterpret_cast<const float4*>(wrow + ks * 8);
-        bf16x4 ah, al;
-        split4(w4.x, w4.y, w4.z, w4.w, ah, al);
-        acc0 = mfma(ah, fh[0][ks], acc0);
-        acc0 = mfma(al, fh[0][ks], acc0);
-        if constexpr (kSplitF) acc0 = mfma(ah, fl[0][ks], acc0);
-        if (two) {
-          acc1 = mfma(ah, fh[1][ks], acc1);
-          acc1 = mfma(al, fh[1][ks], acc1);
-          if constexpr (kSplitF) acc1 = mfma(ah, fl[1][ks], acc1);
+      for (int t = 0; t < 4; t++) {
+        if ((rows >> (2 * t)) & 3u) {
+          bf16x8 ah, al;
+          load_split_w(wrow + 16 * t, ah, al);
+          acc0 = mfma(ah, fh[0][t], acc0);
+          acc1 = mfma(ah, fh[1][t], acc1);
+          acc0 = mfma(al, fh[0][t], acc0);
+          acc1 = mfma(al, fh[1][t], acc1);
+          if constexpr (kSplitF) {
+            acc0 = mfma(ah, fl[0][t], acc0);
+            acc1 = mfma(ah, fl[1][t], acc1);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        if ((rows >> (2 * t)) & 3u) {
+          bf16x8 ah, al;
+          load_split_w(wrow + 16 * t, ah, al);
+          acc0 = mfma(ah, fh[0][t], acc0);
+          acc0 = mfma(al, fh[0][t], acc0);
+          if constexpr (kSplitF) acc0 = mfma(ah, fl[0][t], acc0);
         }
       }
     }
@@ -548,7 +557,7 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
     }
     // one round of weight-sum atomics per step (lane j: Gaussian j)
     if (mine) {
-      twosum_atomic_add(&sd.beta[my_id], my_ws);
+      beta_atomic_add(&sd.beta[my_id], my_ws);
       if (sd.counts) atomicAdd(&sd.counts[my_id], my_cnt);
     }
   }
@@ -586,14 +595,13 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void finalize_kernel(const float* __restrict__ U, const float2* __restrict__ beta,
+__global__ void finalize_kernel(const float* __restrict__ U, const beta_t* __restrict__ beta,
                                 int64_t n, int D, float* __restrict__ f, float* __restrict__ wsum,
                                 float* __restrict__ usum) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * D) return;
   int64_t i = e / D;
-  float2 b = beta[i];
-  float bs = b.x + b.y;
+  const float bs = (float)((double)beta[i] * (1.0 / kBetaUnit));
   float u = U[e];
   if (f) f[e] = bs > 0.0f ? u / bs : 0.0f;
   if (usum) usum[e] = u;
@@ -612,7 +620,7 @@ hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize(const float* U, const float2* beta, int64_t n, int D, float* f,
+hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,
                            float* wsum, float* usum, hipStream_t s) {
   int64_t total = n * (int64_t)D;
   if (total == 0) return hipSuccess;
