@@ -200,6 +200,32 @@ __device__ __forceinline__ void step_walk(uint64_t hits, float4 q0, float4 q1, W
   }
 }
 
+// The same walk, handing each hit Gaussian's weight to fn(j, w) as soon as it
+// is known (no array of the step's weights stays live in registers).
+template <int G, typename Fn>
+__device__ __forceinline__ void step_walk_each(uint64_t hits, float4 q0, float4 q1, Walk& s, Fn&& fn) {
+#pragma unroll
+  for (int j = 0; j < G; j++) {
+    if ((hits >> j) & 1ull) {
+      const float cx = readlane_f(q0.x, j), cy = readlane_f(q0.y, j);
+      const float L11 = readlane_f(q0.z, j), L12 = readlane_f(q0.w, j);
+      const float L22 = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
+      const float dx = s.pxo - cx, dy = s.pyo - cy;
+      const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
+      const float al = fminf(kAlphaMax, op * exp32(-__builtin_fmaf(u, u, w * w)));
+      const bool ok = s.alive && al >= kAlphaMin;
+      const float Tn = s.T * (1.0f - al);
+      const bool stop = ok && Tn < kTEps;
+      const bool take = ok && !stop;
+      const float wj = take ? al * s.T : 0.0f;
+      s.T = take ? Tn : s.T;
+      s.alive = s.alive && !stop;
+      s.ncontrib += take ? 1u : 0u;
+      fn(j, wj);
+    }
+  }
+}
+
 __device__ __forceinline__ void quad_stats(const Walk& s, int lane, unsigned long long* stats) {
   const uint64_t covered = __ballot(s.ncontrib != 0u);
   uint64_t c = s.ncontrib;
@@ -270,7 +296,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
   constexpr int G = kChunk;
   constexpr bool kSplitF = DT != LV_BF16;  // BF16 maps are exact in one BF16 operand
-  __shared__ __align__(16) float Wt[G * kWtPitch];  // a step's weights, [Gaussian][pixel]
+  __shared__ __align__(16) float Wt[64 * kWtPitch];  // ring of queued Gaussians: [row][pixel]
   Quad q;
   if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
   const int lane = threadIdx.x;
@@ -358,64 +384,19 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   // wave-uniform: some lane owns a main channel (else only tail channels)
   const bool has_main = __ballot(outp[0] != nullptr || outp[1] != nullptr) != 0ull;
 
-  Walk s;
-  walk_init(q, lane, s);
-  const Rec* vrec = rec + (int64_t)q.v * n;
-  const float* wrow = Wt + (lane & 31) * kWtPitch + 8 * (lane >> 5);
-  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
-    if (__ballot(s.alive) == 0ull) break;
-    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
-    float4 q0, q1;
-    uint32_t my_id;
-    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
-    float wv[G];
-    step_walk<G>(hits, q0, q1, s, wv);
+  // Gaussians with a contribution queue up in a ring of 64 LDS rows (row r:
+  // the Gaussian's weights at the 64 pixels, its id in lane r's ring_gid);
+  // every 32 of them, and at the end, one batch of MFMAs (M = 32 rows) and
+  // one round of atomics: the matrix products run on full rows whatever the
+  // number of contributing Gaussians per step of the walk.
+  int head = 0, queued = 0;          // ring rows [head, head + queued)
+  uint64_t pix_cur = 0ull, pix_next = 0ull;  // pixels used by the current batch / the next
+  uint32_t ring_gid = 0u;
 
-    // per Gaussian with a contribution: weight sum and count (kept by lane j
-    // for one round of atomics after the loop), tail channels; W_s to LDS
-    uint32_t anyw = 0u;
-    uint64_t allm = 0ull;
-    float my_ws = 0.0f;
-    uint32_t my_cnt = 0u;
-#pragma unroll
-    for (int j = 0; j < G; j++) {
-      if ((hits >> j) & 1ull) {
-        const uint64_t msk = __ballot(wv[j] > 0.0f);
-        if (msk) {
-          anyw |= 1u << j;
-          allm |= msk;
-          Wt[j * kWtPitch + lane] = wv[j];
-          const float ws = wave_sum(wv[j]);
-          if (lane == j) {
-            my_ws = ws;
-            my_cnt = (uint32_t)__popcll(msk);
-          }
-          if (ntail) {
-            const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-#pragma unroll
-            for (int t = 0; t < kMaxTail; t++) {
-              if (t < ntail && tout[t]) {
-                const float at = wave_sum(wv[j] * ft[t]);
-                if (lane == 0 && at != 0.0f) unsafeAtomicAdd(tout[t] + gid * tD[t], at);
-              }
-            }
-          }
-        }
-      }
-    }
-    if (lane < G && ((anyw >> lane) & 1u)) {  // lanes j < 32 whose Gaussian contributed
-      for (int b = bsets; b; b &= b - 1) {
-        const SetDesc& sd = sets[__builtin_ctz(b)];
-        beta_atomic_add(sd.beta + my_id, my_ws);
-        if (sd.counts) atomicAdd(sd.counts + my_id, my_cnt);
-      }
-    }
-    if (!anyw || !has_main) continue;
-    __syncthreads();  // W_s written (one wave per workgroup: orders LDS)
-
-    // U_s = W_s F on the matrix cores; K-steps = pairs of pixel rows holding
-    // a contribution; hi*hi and the two cross terms in separate accumulators
-    const uint32_t rows = row_bits(allm);
+  auto flush = [&](int count, uint64_t pix) {
+    __syncthreads();  // ring rows written (one wave per workgroup: orders LDS)
+    const uint32_t rows = row_bits(pix);
+    const float* wrow = Wt + ((head + (lane & 31)) & 63) * kWtPitch + 8 * (lane >> 5);
     f32x16 acc0 = {}, acc1 = {};
     // (no branch between the MFMAs of one chain: separate loops per width)
     if (two) {
@@ -446,24 +427,85 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
         }
       }
     }
-    __syncthreads();  // W_s read before the next step overwrites it
-
-    // one atomic per (Gaussian with a contribution, channel)
+    __syncthreads();  // rows read before they are written again
+    // one atomic per (queued Gaussian, channel)
+    const bool upper = lane >= 32;
 #pragma unroll
     for (int r = 0; r < 16; r++) {
       const int m0 = 8 * (r >> 2) + (r & 3), m1 = m0 + 4;
-      if (((anyw >> m0) | (anyw >> m1)) & 1u) {
-        const uint32_t g0 = (uint32_t)__builtin_amdgcn_readlane((int)my_id, m0);
-        const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)my_id, m1);
-        const bool upper = lane >= 32;
+      if (m0 < count) {
+        const uint32_t g0 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m0) & 63);
+        const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m1) & 63);
         const int64_t gid = (int64_t)(upper ? g1 : g0);
-        if ((anyw >> (upper ? m1 : m0)) & 1u) {
+        if ((upper ? m1 : m0) < count) {
           if (outp[0] && acc0[r] != 0.0f) unsafeAtomicAdd(outp[0] + gid * outD[0], acc0[r]);
           if (two && outp[1] && acc1[r] != 0.0f) unsafeAtomicAdd(outp[1] + gid * outD[1], acc1[r]);
         }
       }
     }
+  };
+
+  Walk s;
+  walk_init(q, lane, s);
+  const Rec* vrec = rec + (int64_t)q.v * n;
+  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
+    if (__ballot(s.alive) == 0ull) break;
+    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
+    float4 q0, q1;
+    uint32_t my_id;
+    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
+    // per Gaussian with a contribution, as the walk reaches it: weight sum
+    // and count (kept by lane j for one round of atomics after the step),
+    // tail channels, a ring row
+    uint32_t anyw = 0u;
+    float my_ws = 0.0f;
+    uint32_t my_cnt = 0u;
+    step_walk_each<G>(hits, q0, q1, s, [&](const int j, const float wj) {
+      const uint64_t msk = __ballot(wj > 0.0f);
+      if (msk) {
+        anyw |= 1u << j;
+        const float ws = wave_sum(wj);
+        if (lane == j) {
+          my_ws = ws;
+          my_cnt = (uint32_t)__popcll(msk);
+        }
+        if (has_main) {
+          const int row = (head + queued) & 63;
+          Wt[row * kWtPitch + lane] = wj;
+          const uint32_t gj = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
+          if (lane == row) ring_gid = gj;
+          if (queued < 32) pix_cur |= msk;
+          else pix_next |= msk;
+          queued++;
+        }
+        if (ntail) {
+          const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
+#pragma unroll
+          for (int t = 0; t < kMaxTail; t++) {
+            if (t < ntail && tout[t]) {
+              const float at = wave_sum(wj * ft[t]);
+              if (lane == 0 && at != 0.0f) unsafeAtomicAdd(tout[t] + gid * tD[t], at);
+            }
+          }
+        }
+      }
+    });
+    if (lane < G && ((anyw >> lane) & 1u)) {  // lanes j < 32 whose Gaussian contributed
+      for (int b = bsets; b; b &= b - 1) {
+        const SetDesc& sd = sets[__builtin_ctz(b)];
+        beta_atomic_add(sd.beta + my_id, my_ws);
+        if (sd.counts) atomicAdd(sd.counts + my_id, my_cnt);
+      }
+    }
+    if (queued >= 32) {  // a full batch
+      flush(32, pix_cur);
+      head = (head + 32) & 63;
+      queued -= 32;
+      pix_cur = pix_next;
+      pix_next = 0ull;
+    }
   }
+  if (queued > 0) flush(queued, pix_cur);
   // statistics go to every set whose beta this group takes for this view
   for (int b = bsets; b; b &= b - 1) {
     const SetDesc& sd = sets[__builtin_ctz(b)];
