@@ -109,40 +109,83 @@ __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__
   }
 }
 
-// Stable scatter: the block counts its items per (wave, digit), turns the
-// counts into starting positions (block offset from the scan, then waves in
-// order), and each wave places its contiguous share in order, advancing its
-// own per-digit cursors -- no block barrier inside the placement loop.
+// Stable scatter through LDS: the block counts its items per (wave, digit),
+// ranks them block-locally in digit order (waves in order, lanes in order),
+// places them in LDS at those ranks, and then writes the LDS contents out in
+// order: items of one digit are consecutive in LDS and go to consecutive
+// global positions, so the writes are runs instead of scattered words.
+template <typename T>
+__device__ __forceinline__ void wave_count_t(const uint32_t* __restrict__ k, uint32_t lo, uint32_t hi,
+                                             int shift, int bits, T* cnt) {
+  const uint32_t mask = (1u << bits) - 1u;
+  const int lane = threadIdx.x & 63;
+  for (uint32_t r = lo; r < hi; r += 64) {
+    const uint32_t i = r + lane;
+    const bool valid = i < hi;
+    const uint32_t d = valid ? (k[i] >> shift) & mask : 0u;
+    const uint64_t act = __ballot(valid);
+    const uint64_t peers = match_digit(d, bits, act);
+    if (valid && (peers & lanemask_lt()) == 0) cnt[d] = (T)(cnt[d] + (uint32_t)__popcll(peers));
+  }
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb,
     const uint32_t* __restrict__ hist) {
-  __shared__ uint32_t wc[4][kBins];
+  constexpr int kPer = kBins / kSortThreads;       // digits per thread in the scan
+  __shared__ uint16_t wc[4][kBins];                 // per-wave counts, then local cursors
+  __shared__ uint32_t gdelta[kBins];                // global minus local position, per digit
+  __shared__ uint32_t lk[kSortItems], lval[kSortItems];
+  __shared__ uint32_t wsum[kSortThreads / 64];
   const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint32_t s0 = seg_start[g];
   const uint32_t len = seg_len[g];
   const uint32_t base = (uint32_t)b * kSortItems;
   if (base >= len) return;  // whole block idle (uniform)
-  for (int e = t; e < 4 * kBins; e += kSortThreads) (&wc[0][0])[e] = 0u;
+  const uint32_t items = min(len - base, (uint32_t)kSortItems);
+  for (int e = t; e < 4 * kBins; e += kSortThreads) (&wc[0][0])[e] = 0;
   __syncthreads();
   const uint32_t lo = base + w * kWaveItems;
   const uint32_t hi = min(len, lo + kWaveItems);
-  if (lo < hi) wave_count(kin + s0, lo, hi, shift, bits, wc[w]);
+  if (lo < hi) wave_count_t<uint16_t>(kin + s0, lo, hi, shift, bits, wc[w]);
   __syncthreads();
+  // block-local exclusive scan over digits (thread t owns digits [kPer t, kPer t + kPer))
   const int nbins = 1 << bits;
-  for (int d = t; d < nbins; d += kSortThreads) {
-    uint32_t run = s0 + hist[((size_t)g * nbins + d) * nb + b];
+  uint32_t tot = 0;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const uint32_t c = wc[q][d];
-      wc[q][d] = run;
-      run += c;
+  for (int k = 0; k < kPer; k++) {
+    const int d = kPer * t + k;
+    if (d < nbins) tot += (uint32_t)wc[0][d] + wc[1][d] + wc[2][d] + wc[3][d];
+  }
+  uint32_t incl = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t run = incl - tot;
+  for (int q = 0; q < w; q++) run += wsum[q];
+#pragma unroll
+  for (int k = 0; k < kPer; k++) {
+    const int d = kPer * t + k;
+    if (d < nbins) {
+      gdelta[d] = s0 + hist[((size_t)g * nbins + d) * nb + b] - run;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t c = wc[q][d];
+        wc[q][d] = (uint16_t)run;
+        run += c;
+      }
     }
   }
   __syncthreads();
+  // each wave places its contiguous share at its block-local ranks
   const uint32_t mask = (1u << bits) - 1u;
-  uint32_t* cur = wc[w];
+  uint16_t* cur = wc[w];
   for (uint32_t r = lo; r < hi; r += 64) {
     const uint32_t i = r + lane;
     const bool valid = i < hi;
@@ -153,13 +196,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint64_t peers = match_digit(d, bits, act);
     const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
     if (valid) {
-      const uint32_t pos = cur[d] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+      const uint32_t pos = (uint32_t)cur[d] + rank;
+      lk[pos] = key;
+      lval[pos] = val;
     }
     __builtin_amdgcn_wave_barrier();  // every lane has read cur[d]
-    if (valid && rank == 0) cur[d] += (uint32_t)__popcll(peers);
+    if (valid && rank == 0) cur[d] = (uint16_t)(cur[d] + (uint32_t)__popcll(peers));
     __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // write out in local order: runs of one digit land on consecutive positions
+  for (uint32_t p = t; p < items; p += kSortThreads) {
+    const uint32_t key = lk[p];
+    const uint32_t pos = gdelta[(key >> shift) & mask] + p;
+    kout[pos] = key;
+    vout[pos] = lval[p];
   }
 }
 
