@@ -136,7 +136,8 @@ lv_status lv_uplift_sets(lv_scene* scene, const lv_camera* cams, int32_t m, cons
                          int32_t nsets, lv_dtype dtype, void* stream);
 
 /* Streaming form of lv_uplift: the accumulator holds U = W^T F [n][D] (FP32)
- * and beta (compensated FP32 pair), to which views are added in any grouping
+ * and beta (exact 64-bit fixed point in units of 2^-35, at most 2^29 units of
+ * weight per Gaussian), to which views are added in any grouping
  * (accumulating views [0,k) then [k,m) equals all m).  With
  * LV_ACCUM_COUNTS it also counts, per Gaussian, the (view, pixel) pairs
  * that contribute (exact integers). */
