@@ -220,6 +220,17 @@ lv_status lv_graph_destroy(lv_graph* graph);
 lv_status lv_diffuse(const lv_scene* scene, const lv_graph* graph, const void* g0, lv_dtype dtype,
                      int32_t D, int32_t steps, void* out, void* stream);
 
+/* ---------------------------------------------------------------- render -- */
+/* Eq. (4): the forward render F^ = W g of per-Gaussian features, the map the
+ * uplift is the normalised transpose of.  g: device FP32 [n][D]; outs: host
+ * array [m] of device FP32 [H_v][W_v][D] outputs, F^(p) = sum_i w_i(p) g_i;
+ * alphas: host array [m] (nullable, entries nullable) of device FP32
+ * [H_v][W_v], the accumulated opacity sum_i w_i(p).  The weights are those of
+ * the uplift (same structure and walk).  D in [1, 4096]; every output pixel
+ * is written (0 where no Gaussian counts).  Errors as lv_uplift. */
+lv_status lv_render(lv_scene* scene, const lv_camera* cams, int32_t m, const float* g, int32_t D,
+                    float* const* outs, float* const* alphas, void* stream);
+
 /* -------------------------------------------------------------- serving -- */
 /* A request server for uplift (Eq. 3 / Eq. 5) over resident scenes.  Requests
  * are admitted first come, first served while the memory they need (the

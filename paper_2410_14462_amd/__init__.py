@@ -107,6 +107,7 @@ def lib():
             "lv_uplift_accumulate_sets": ([P, i32, P, i32, i32, P], i32),
             "lv_profile_start": ([], i32),
             "lv_profile_stop": ([ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), P, i64], i32),
+            "lv_render": ([P, P, i32, P, i32, P, P, P], i32),
             "lv_server_create": ([ctypes.POINTER(lv_server_opts), ctypes.POINTER(P)], i32),
             "lv_server_submit": ([P, ctypes.POINTER(lv_request)], i32),
             "lv_server_poll": ([P, P, i32, ctypes.POINTER(i32)], i32),
@@ -128,7 +129,7 @@ def exported_symbols():
             "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode",
             "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view",
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
-            "lv_uplift_accumulate_sets", "lv_server_create", "lv_server_submit", "lv_server_poll",
+            "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",
             "lv_server_drain", "lv_server_stats_get", "lv_server_destroy"]
 
 
@@ -227,6 +228,20 @@ class Scene:
         _check(lib().lv_uplift(self.handle, ca, len(cams), tab, dt, _ptr(scales), D, _ptr(out),
                                _ptr(wsum), _stream()))
         return out, wsum
+
+    def render(self, cams, g, alpha=True):
+        """Eq. (4): g [n, D] f32 -> ([H, W, D] per camera, [H, W] opacity per camera)."""
+        import torch
+        if g.dim() == 1:
+            g = g[:, None]
+        _dev_f32(g, (self.n, g.shape[1]))
+        D = g.shape[1]
+        outs = [torch.empty((c.height, c.width, D), device="cuda") for c in cams]
+        alps = [torch.empty((c.height, c.width), device="cuda") for c in cams] if alpha else []
+        to = (ctypes.c_void_p * max(1, len(cams)))(*[o.data_ptr() for o in outs])
+        ta = (ctypes.c_void_p * max(1, len(cams)))(*[a.data_ptr() for a in alps]) if alpha else None
+        _check(lib().lv_render(self.handle, camera_array(cams), len(cams), _ptr(g), D, to, ta, _stream()))
+        return outs, alps
 
     def uplift_sets(self, cams, sets, dtype="f32", outs=None):
         """Several feature sets over the same views in one pass.  sets: list of

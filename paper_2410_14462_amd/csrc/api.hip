@@ -821,6 +821,62 @@ lv_status lv_diffuse(const lv_scene* sc, const lv_graph* gc, const void* g0, lv_
   return LV_OK;
 }
 
+lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float* g, int32_t D,
+                    float* const* outs, float* const* alphas, void* stream) {
+  if (!sc) return fail(LV_ERR_INVALID_ARG, "scene is NULL");
+  if (D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "D = %d out of [1, 4096]", D);
+  lv_status st = check_cams(cams, m);
+  if (st != LV_OK) return st;
+  if (m > 0 && !outs) return fail(LV_ERR_INVALID_ARG, "outs is NULL");
+  for (int v = 0; v < m; v++)
+    if (!outs[v]) return fail(LV_ERR_INVALID_ARG, "outs[%d] is NULL", v);
+  const int64_t n = sc->n;
+  if (n > 0 && !g) return fail(LV_ERR_INVALID_ARG, "g is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // pixels no Gaussian reaches stay 0
+  for (int v = 0; v < m; v++) {
+    const size_t px = (size_t)cams[v].width * cams[v].height;
+    HIP_TRY(hipMemsetAsync(outs[v], 0, sizeof(float) * px * D, s));
+    if (alphas && alphas[v]) HIP_TRY(hipMemsetAsync(alphas[v], 0, sizeof(float) * px, s));
+  }
+  if (n == 0 || m == 0) return LV_OK;
+  Workspace& ws = *workspace_for(s);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  int64_t per_view = n * (int64_t)(sizeof(Rec) + 7 * 4 + 8);
+  int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
+  mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
+  for (int v0 = 0; v0 < m; v0 += (int)mc) {
+    const int mv = (int)std::min<int64_t>(mc, m - v0);
+    const uint32_t* ids = nullptr;
+    const uint32_t* pkeys = nullptr;
+    int stride = 0, max_tiles = 0;
+    int64_t P = 0, nvis = 0;
+    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &pkeys, &stride, &P, &nvis, &max_tiles);
+    if (st != LV_OK) return st;
+    // output tables (ws.up is idle: build_structure synchronised the stream)
+    const size_t bytes = 2 * sizeof(float*) * (size_t)mv;
+    HIP_TRY(ws.maps.ensure(bytes, s));
+    HIP_TRY(ws.up.ensure(bytes));
+    float** up = static_cast<float**>(ws.up.p);
+    for (int v = 0; v < mv; v++) {
+      up[v] = outs[v0 + v];
+      up[mv + v] = alphas ? alphas[v0 + v] : nullptr;
+    }
+    HIP_TRY(hipMemcpyAsync(ws.maps.p, up, bytes, hipMemcpyHostToDevice, s));
+    BlendArgs ba;
+    memset(&ba, 0, sizeof(ba));
+    ba.rec = ws.rec.as<Rec>();
+    ba.ids = ids;
+    ba.ranges = ws.ranges.as<uint2>();
+    ba.geom = ws.geom.as<ViewGeom>();
+    ba.n = n;
+    ba.tiles_stride = stride;
+    float* const* dtab = static_cast<float* const*>(ws.maps.p);
+    HIP_TRY(launch_render(ba, mv, g, D, dtab, dtab + mv, s));
+  }
+  return LV_OK;
+}
+
 lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, int64_t* P_out) {
   if (!sc || !cam || !out) return fail(LV_ERR_INVALID_ARG, "null argument");
   lv_status st = check_cams(cam, 1);

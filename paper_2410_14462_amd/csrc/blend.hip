@@ -637,6 +637,61 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ forward render
+// Eq. (4): F^(p) = sum_i w_i(p) g_i.  Each quadrant wave walks its tile's
+// list exactly as the uplift does and accumulates, per pixel, up to
+// kRenderCh channels of g in registers; the row of g of a Gaussian is the
+// same for the whole wave (its id comes from readlane), so it is read once
+// per wave.  The accumulated opacity sum_i w_i(p) goes to alpha[v] (group 0).
+constexpr int kRenderCh = 32;
+
+__global__ __launch_bounds__(64) void render_kernel(
+    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews, int ngroups,
+    const float* __restrict__ g, int D, float* const* __restrict__ outs,
+    float* const* __restrict__ alphas) {
+  constexpr int G = kChunk;
+  Quad q;
+  if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
+  const int lane = threadIdx.x;
+  const int c0 = q.cg * kRenderCh;
+  float acc[kRenderCh];
+#pragma unroll
+  for (int k = 0; k < kRenderCh; k++) acc[k] = 0.0f;
+  float asum = 0.0f;
+  Walk s;
+  walk_init(q, lane, s);
+  const Rec* vrec = rec + (int64_t)q.v * n;
+  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
+    if (__ballot(s.alive) == 0ull) break;
+    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
+    float4 q0, q1;
+    uint32_t my_id;
+    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
+    step_walk_each<G>(hits, q0, q1, s, [&](const int j, const float wj) {
+      if (__ballot(wj > 0.0f)) {
+        const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
+        const float* fr = g + (int64_t)gid * D + c0;
+#pragma unroll
+        for (int k = 0; k < kRenderCh; k++) {
+          const float fv = c0 + k < D ? fr[k] : 0.0f;
+          acc[k] = __builtin_fmaf(wj, fv, acc[k]);
+        }
+        asum += wj;
+      }
+    });
+  }
+  const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
+  if (px < q.g.W && py < q.g.H) {
+    const int64_t pix = (int64_t)py * q.g.W + px;
+    float* o = outs[q.v] + pix * D + c0;
+#pragma unroll
+    for (int k = 0; k < kRenderCh; k++)
+      if (c0 + k < D) o[k] = acc[k];
+    if (q.cg == 0 && alphas[q.v]) alphas[q.v][pix] = asum;
+  }
+}
+
 __global__ void finalize_kernel(const float* __restrict__ U, const beta_t* __restrict__ beta,
                                 int64_t n, int D, float* __restrict__ f, float* __restrict__ wsum,
                                 float* __restrict__ usum) {
@@ -660,6 +715,17 @@ hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s
     case LV_FP8_E4M3: return launch_blend_t<LV_FP8_E4M3>(a, m, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float* const* outs,
+                         float* const* alphas, hipStream_t s) {
+  if (m == 0 || a.tiles_stride == 0) return hipSuccess;
+  const int ngroups = (D + kRenderCh - 1) / kRenderCh;
+  const int64_t work = (int64_t)a.tiles_stride * m * ngroups;
+  const int64_t blocks = (work + 7) / 8 * 32;  // 4 quadrants per tile, whole rounds of 8 XCDs
+  hipLaunchKernelGGL(render_kernel, dim3((unsigned)blocks), dim3(64), 0, s, a.rec, a.ids, a.ranges,
+                     a.geom, a.n, a.tiles_stride, m, ngroups, g, D, outs, alphas);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,

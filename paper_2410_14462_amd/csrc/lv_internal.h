@@ -169,6 +169,11 @@ struct BlendArgs {
 };
 hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s);
 
+// Eq. (4) forward render of g [n][D] into outs[v] [H][W][D] (device table of
+// m pointers) and the accumulated opacity into alphas[v] [H][W] (entries may
+// be null); pixels of empty tiles are not written.
+hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float* const* outs,
+                         float* const* alphas, hipStream_t s);
 hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,
                            float* wsum, float* usum, hipStream_t s);
 

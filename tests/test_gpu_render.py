@@ -1,0 +1,64 @@
+"""Forward render (Eq. 4) through the C ABI: against the FP64 oracle's render,
+and as the adjoint of the uplift's raw sums W^T F."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2410_14462_amd as lv
+from synth import philox, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    sc = scenes.make_scene(31, 3000, -3.8, 0.5, 0.0, 1.0)
+    cams = [scenes.look_at(e, 96, 80, 60.0) for e in scenes.fibonacci_eyes(3, 4.0)]
+    cams.append(scenes.look_at([0.3, 0.2, 0.6], 77, 45, 90.0))  # inside the cloud, ragged tiles
+    return sc, cams, lv.Scene.from_arrays(sc)
+
+
+@pytest.mark.parametrize("D", [1, 5, 40])
+def test_render_matches_oracle(setup, D):
+    sc, cams, gs = setup
+    g = philox.normal(40 + D, 0, sc.n * D).reshape(sc.n, D)
+    outs, alphas = gs.render(cams, torch.as_tensor(g, device="cuda"))
+    for v, cam in enumerate(cams):
+        ref, ref_a = oracle.render(sc, cam, g)
+        scale, _ = oracle.render(sc, cam, np.abs(g))  # sum_i w_i(p) |g_i|
+        got = outs[v].cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref) / np.maximum(scale, 1e-30)
+        print(f"render D={D} view {v}: max err {err.max():.3e}")
+        assert err.max() < 1e-4
+        assert np.abs(alphas[v].cpu().numpy() - ref_a).max() < 1e-5
+        assert np.all(ref_a <= 1.0 + 1e-12)
+
+
+def test_render_is_the_adjoint_of_the_uplift(setup):
+    """<W g, F> = <g, W^T F> over all views, with W^T F the uplift's raw sums."""
+    sc, cams, gs = setup
+    D = 7
+    g = torch.as_tensor(philox.normal(50, 0, sc.n * D).reshape(sc.n, D), device="cuda")
+    maps = [torch.as_tensor(philox.normal(51, v, c.height * c.width * D).reshape(c.height, c.width, D),
+                            device="cuda") for v, c in enumerate(cams)]
+    outs, _ = gs.render(cams, g, alpha=False)
+    lhs = sum(float((o.double() * m.double()).sum()) for o, m in zip(outs, maps))
+    acc = lv.Accum(gs, D)
+    acc.add(cams, maps)
+    _, _, U = acc.finalize(want_sum=True)
+    rhs = float((g.double() * U.double()).sum())
+    mag = sum(float((o.double().abs() * m.double().abs()).sum()) for o, m in zip(outs, maps))
+    print(f"adjoint: {lhs:.6e} vs {rhs:.6e} (scale {mag:.3e})")
+    assert abs(lhs - rhs) <= 1e-5 * mag
+
+
+def test_render_empty_view_and_bad_args(setup):
+    sc, cams, gs = setup
+    away = scenes.look_at([0, 0, 40.0], 64, 48, 60.0)
+    away.t = -away.t  # the cloud is behind this camera
+    outs, alphas = gs.render([away], torch.ones((sc.n, 3), device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.all(outs[0] == 0) and torch.all(alphas[0] == 0)
+    with pytest.raises(lv.LvError):
+        gs.render(cams[:1], torch.ones((sc.n + 1, 3), device="cuda"))
