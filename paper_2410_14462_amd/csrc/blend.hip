@@ -289,32 +289,33 @@ __device__ __forceinline__ uint32_t row_bits(uint64_t m) {
   return r;
 }
 
-template <lv_dtype DT>
-__global__ __launch_bounds__(64) void blend_wide_kernel(
-    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
-    const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
-    const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
-  constexpr int G = kChunk;
-  constexpr bool kSplitF = DT != LV_BF16;  // BF16 maps are exact in one BF16 operand
-  __shared__ __align__(16) float Wt[64 * kWtPitch];  // ring of queued Gaussians: [row][pixel]
-  Quad q;
-  if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
-  const int lane = threadIdx.x;
-  const ChanGroup& grp = groups[q.cg];
-  const int width = grp.width, nseg = grp.nseg, ntail = grp.ntail;
-  const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
-  const bool inside = px < q.g.W && py < q.g.H;
-  const bool two = width > 32;  // second block of 32 channels
+// This lane's channel in each 32-channel block of a group (n = l % 32):
+// where its features come from and where its sums go.
+struct GroupLanes {
+  float* outp[2];
+  int outD[2];
+  const void* src[2];
+  int64_t srcc[2];
+  int srcld[2];
+  float srcsc[2];
+};
 
-  // This lane's channel in each block (n = l % 32) and where it comes from.
-  float* outp[2] = {nullptr, nullptr};
-  int outD[2] = {0, 0};
-  bool active = false;  // some segment or tail channel takes this view
-  const void* src[2] = {nullptr, nullptr};
-  int64_t srcc[2] = {0, 0};
-  int srcld[2] = {0, 0};
-  float srcsc[2] = {1.0f, 1.0f};
-  for (int k = 0; k < nseg; k++) {
+// Fills L for group grp and view q.v; false if no segment of the group takes
+// the view (wave-uniform).
+template <lv_dtype DT>
+__device__ __forceinline__ bool group_lanes(const ChanGroup& grp, const SetDesc* __restrict__ sets,
+                                            const Quad& q, int lane, GroupLanes& L) {
+  bool active = false;
+#pragma unroll
+  for (int b = 0; b < 2; b++) {
+    L.outp[b] = nullptr;
+    L.outD[b] = 0;
+    L.src[b] = nullptr;
+    L.srcc[b] = 0;
+    L.srcld[b] = 0;
+    L.srcsc[b] = 1.0f;
+  }
+  for (int k = 0; k < grp.nseg; k++) {
     const SetDesc& sd = sets[grp.set[k]];
     const void* map = sd.maps[q.v];
     if (!map) continue;  // this set does not take the view
@@ -325,71 +326,174 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
       const int ch = b * 32 + (lane & 31);
       if (ch >= vc0 && ch < vc0 + cnt) {
         const int c = grp.c0[k] + (ch - vc0);
-        outp[b] = sd.U + c;
-        outD[b] = sd.D;
-        src[b] = map;
-        srcc[b] = c;
-        srcld[b] = sd.stride;
-        if constexpr (DT == LV_FP8_E4M3) srcsc[b] = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
+        L.outp[b] = sd.U + c;
+        L.outD[b] = sd.D;
+        L.src[b] = map;
+        L.srcc[b] = c;
+        L.srcld[b] = sd.stride;
+        if constexpr (DT == LV_FP8_E4M3) L.srcsc[b] = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
       }
     }
   }
-  // tail channels: this lane's pixel, in registers
+  return active;
+}
+
+// B operands of K-step t (pixel rows 2t, 2t + 1) for both blocks: F[pixel (row
+// 2t + l / 32, column i)][channel], split into hi and lo.
+template <lv_dtype DT>
+__device__ __forceinline__ void stage_fragment(const GroupLanes& L, const Quad& q, int lane, int t,
+                                               int b, bf16x8& fh, bf16x8& fl) {
+  float v[8];
+  const int gy = q.qy + 2 * t + (lane >> 5);
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const int gx = q.qx + i;
+    v[i] = 0.0f;
+    if (L.src[b] && gx < q.g.W && gy < q.g.H)
+      v[i] = load_feature<DT>(L.src[b], ((int64_t)gy * q.g.W + gx) * L.srcld[b] + L.srcc[b], L.srcsc[b]);
+  }
+  split8(v, fh, fl);
+}
+
+// U_b = W_b F for a batch of queued rows, one or two blocks of 32 channels.
+// No branch separates dependent MFMAs (the widths run in separate loops).
+template <bool kSplitF>
+__device__ __forceinline__ void batch_mfma(bool two, uint32_t rows, const float* wrow,
+                                           const bf16x8 (&fh)[2][4], const bf16x8 (&fl)[2][4],
+                                           f32x16& acc0, f32x16& acc1) {
+  if (two) {
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      if ((rows >> (2 * t)) & 3u) {
+        bf16x8 ah, al;
+        load_split_w(wrow + 16 * t, ah, al);
+        acc0 = mfma(ah, fh[0][t], acc0);
+        acc1 = mfma(ah, fh[1][t], acc1);
+        acc0 = mfma(al, fh[0][t], acc0);
+        acc1 = mfma(al, fh[1][t], acc1);
+        if constexpr (kSplitF) {
+          acc0 = mfma(ah, fl[0][t], acc0);
+          acc1 = mfma(ah, fl[1][t], acc1);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      if ((rows >> (2 * t)) & 3u) {
+        bf16x8 ah, al;
+        load_split_w(wrow + 16 * t, ah, al);
+        acc0 = mfma(ah, fh[0][t], acc0);
+        acc0 = mfma(al, fh[0][t], acc0);
+        if constexpr (kSplitF) acc0 = mfma(ah, fl[0][t], acc0);
+      }
+    }
+  }
+}
+
+// One atomic per (queued Gaussian, channel): D row m of the batch is ring
+// row head + m, whose Gaussian id lane (head + m) % 64 holds.
+__device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int count, int head,
+                                              uint32_t ring_gid, int lane, const f32x16& acc0,
+                                              const f32x16& acc1) {
+  const bool upper = lane >= 32;
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    const int m0 = 8 * (r >> 2) + (r & 3), m1 = m0 + 4;
+    if (m0 < count) {
+      const uint32_t g0 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m0) & 63);
+      const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m1) & 63);
+      const int64_t gid = (int64_t)(upper ? g1 : g0);
+      if ((upper ? m1 : m0) < count) {
+        if (L.outp[0] && acc0[r] != 0.0f) unsafeAtomicAdd(L.outp[0] + gid * L.outD[0], acc0[r]);
+        if (two && L.outp[1] && acc1[r] != 0.0f) unsafeAtomicAdd(L.outp[1] + gid * L.outD[1], acc1[r]);
+      }
+    }
+  }
+}
+
+// MULTI = false: one wave per (view, quadrant, channel group); the group's F
+// fragments are staged once in registers.  MULTI = true (several groups):
+// one wave per (view, quadrant) walks once for all groups; each batch runs
+// every group in turn, staging that group's fragments for the K-steps it
+// needs (the walk, the larger part of a group's cost, is shared).
+template <lv_dtype DT, bool MULTI>
+__global__ __launch_bounds__(64) void blend_wide_kernel(
+    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
+    const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
+  constexpr int G = kChunk;
+  constexpr bool kSplitF = DT != LV_BF16;  // BF16 maps are exact in one BF16 operand
+  __shared__ __align__(16) float Wt[64 * kWtPitch];  // ring of queued Gaussians: [row][pixel]
+  Quad q;
+  if (!decode_quad(ranges, geom, tiles_stride, nviews, MULTI ? 1 : ngroups, q)) return;
+  const int lane = threadIdx.x;
+  const int g_lo = MULTI ? 0 : q.cg, g_hi = MULTI ? ngroups : q.cg + 1;
+  const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
+  const bool inside = px < q.g.W && py < q.g.H;
+
+  // groups taking the view, sets whose beta (and counts) are added here;
+  // tail channels (only the last group has them)
+  bool has_main = false;
+  int bsets = 0;
+  uint32_t gmask = 0u;  // groups (relative to g_lo) with a segment taking the view
+  for (int cg = g_lo; cg < g_hi; cg++) {
+    const ChanGroup& grp = groups[cg];
+    for (int b = grp.beta_sets; b; b &= b - 1)
+      if (sets[__builtin_ctz(b)].maps[q.v]) bsets |= b & -b;
+    bool any = false;
+    for (int k = 0; k < grp.nseg; k++) any = any || sets[grp.set[k]].maps[q.v] != nullptr;
+    if (any) {
+      gmask |= 1u << (cg - g_lo);
+      has_main = true;
+    }
+  }
+  const ChanGroup& last = groups[g_hi - 1];
+  const int ntail = last.ntail;
   float ft[kMaxTail];
   float* tout[kMaxTail];
   int tD[kMaxTail];
+  bool any_tail = false;
 #pragma unroll
   for (int t = 0; t < kMaxTail; t++) {
     ft[t] = 0.0f;
     tout[t] = nullptr;
     tD[t] = 0;
-    if (t < ntail && sets[grp.tset[t]].maps[q.v]) {
-      const SetDesc& sd = sets[grp.tset[t]];
-      const int c = grp.tc[t];
+    if (t < ntail && sets[last.tset[t]].maps[q.v]) {
+      const SetDesc& sd = sets[last.tset[t]];
+      const int c = last.tc[t];
       float sc = 1.0f;
       if constexpr (DT == LV_FP8_E4M3) sc = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
       if (inside)
         ft[t] = load_feature<DT>(sd.maps[q.v], ((int64_t)py * q.g.W + px) * sd.stride + c, sc);
       tout[t] = sd.U + c;
       tD[t] = sd.D;
-      active = true;
+      any_tail = true;
     }
   }
-  if (!active) return;  // wave-uniform: no set of this group takes the view
+  if (!has_main && !any_tail) return;  // wave-uniform: nothing of this work takes the view
 
-  // B operands: F[pixel (row 2 t + l / 32, column i)][channel], split
+  // single group: its lanes and fragments once, in registers
+  GroupLanes L1;
   bf16x8 fh[2][4], fl[2][4];
+  bool two1 = false;
+  if constexpr (!MULTI) {
+    const ChanGroup& grp = groups[q.cg];
+    group_lanes<DT>(grp, sets, q, lane, L1);
+    two1 = grp.width > 32;
 #pragma unroll
-  for (int b = 0; b < 2; b++) {
+    for (int b = 0; b < 2; b++)
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      float v[8];
-      const int gy = q.qy + 2 * t + (lane >> 5);
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const int gx = q.qx + i;
-        v[i] = 0.0f;
-        if (src[b] && gx < q.g.W && gy < q.g.H)
-          v[i] = load_feature<DT>(src[b], ((int64_t)gy * q.g.W + gx) * srcld[b] + srcc[b], srcsc[b]);
-      }
-      split8(v, fh[b][t], fl[b][t]);
-    }
+      for (int t = 0; t < 4; t++) stage_fragment<DT>(L1, q, lane, t, b, fh[b][t], fl[b][t]);
+    has_main = has_main && __ballot(L1.outp[0] != nullptr || L1.outp[1] != nullptr) != 0ull;
   }
-
-  // sets whose beta (and counts) this group adds for this view (wave-uniform)
-  int bsets = 0;
-  for (int b = grp.beta_sets; b; b &= b - 1)
-    if (sets[__builtin_ctz(b)].maps[q.v]) bsets |= b & -b;
-
-  // wave-uniform: some lane owns a main channel (else only tail channels)
-  const bool has_main = __ballot(outp[0] != nullptr || outp[1] != nullptr) != 0ull;
 
   // Gaussians with a contribution queue up in a ring of 64 LDS rows (row r:
   // the Gaussian's weights at the 64 pixels, its id in lane r's ring_gid);
   // every 32 of them, and at the end, one batch of MFMAs (M = 32 rows) and
-  // one round of atomics: the matrix products run on full rows whatever the
-  // number of contributing Gaussians per step of the walk.
-  int head = 0, queued = 0;          // ring rows [head, head + queued)
+  // one round of atomics per group: the matrix products run on full rows
+  // whatever the number of contributing Gaussians per step of the walk.
+  int head = 0, queued = 0;                  // ring rows [head, head + queued)
   uint64_t pix_cur = 0ull, pix_next = 0ull;  // pixels used by the current batch / the next
   uint32_t ring_gid = 0u;
 
@@ -397,51 +501,55 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     __syncthreads();  // ring rows written (one wave per workgroup: orders LDS)
     const uint32_t rows = row_bits(pix);
     const float* wrow = Wt + ((head + (lane & 31)) & 63) * kWtPitch + 8 * (lane >> 5);
-    f32x16 acc0 = {}, acc1 = {};
-    // (no branch between the MFMAs of one chain: separate loops per width)
-    if (two) {
+    if constexpr (!MULTI) {
+      f32x16 acc0 = {}, acc1 = {};
+      batch_mfma<kSplitF>(two1, rows, wrow, fh, fl, acc0, acc1);
+      __syncthreads();  // rows read before they are written again
+      batch_scatter(L1, two1, count, head, ring_gid, lane, acc0, acc1);
+    } else {
+      for (int cg = g_lo; cg < g_hi; cg++) {
+        if (!((gmask >> (cg - g_lo)) & 1u)) continue;
+        const ChanGroup& grp = groups[cg];
+        GroupLanes L;
+        group_lanes<DT>(grp, sets, q, lane, L);
+        const bool two = grp.width > 32;
+        // fragments staged K-step by K-step, right before their MFMAs (only
+        // one K-step's operands live at a time)
+        f32x16 acc0 = {}, acc1 = {};
+        if (two) {
 #pragma unroll
-      for (int t = 0; t < 4; t++) {
-        if ((rows >> (2 * t)) & 3u) {
-          bf16x8 ah, al;
-          load_split_w(wrow + 16 * t, ah, al);
-          acc0 = mfma(ah, fh[0][t], acc0);
-          acc1 = mfma(ah, fh[1][t], acc1);
-          acc0 = mfma(al, fh[0][t], acc0);
-          acc1 = mfma(al, fh[1][t], acc1);
-          if constexpr (kSplitF) {
-            acc0 = mfma(ah, fl[0][t], acc0);
-            acc1 = mfma(ah, fl[1][t], acc1);
+          for (int t = 0; t < 4; t++) {
+            if ((rows >> (2 * t)) & 3u) {
+              bf16x8 h0, l0, h1, l1, ah, al;
+              stage_fragment<DT>(L, q, lane, t, 0, h0, l0);
+              stage_fragment<DT>(L, q, lane, t, 1, h1, l1);
+              load_split_w(wrow + 16 * t, ah, al);
+              acc0 = mfma(ah, h0, acc0);
+              acc1 = mfma(ah, h1, acc1);
+              acc0 = mfma(al, h0, acc0);
+              acc1 = mfma(al, h1, acc1);
+              if constexpr (kSplitF) {
+                acc0 = mfma(ah, l0, acc0);
+                acc1 = mfma(ah, l1, acc1);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            if ((rows >> (2 * t)) & 3u) {
+              bf16x8 h0, l0, ah, al;
+              stage_fragment<DT>(L, q, lane, t, 0, h0, l0);
+              load_split_w(wrow + 16 * t, ah, al);
+              acc0 = mfma(ah, h0, acc0);
+              acc0 = mfma(al, h0, acc0);
+              if constexpr (kSplitF) acc0 = mfma(ah, l0, acc0);
+            }
           }
         }
+        batch_scatter(L, two, count, head, ring_gid, lane, acc0, acc1);
       }
-    } else {
-#pragma unroll
-      for (int t = 0; t < 4; t++) {
-        if ((rows >> (2 * t)) & 3u) {
-          bf16x8 ah, al;
-          load_split_w(wrow + 16 * t, ah, al);
-          acc0 = mfma(ah, fh[0][t], acc0);
-          acc0 = mfma(al, fh[0][t], acc0);
-          if constexpr (kSplitF) acc0 = mfma(ah, fl[0][t], acc0);
-        }
-      }
-    }
-    __syncthreads();  // rows read before they are written again
-    // one atomic per (queued Gaussian, channel)
-    const bool upper = lane >= 32;
-#pragma unroll
-    for (int r = 0; r < 16; r++) {
-      const int m0 = 8 * (r >> 2) + (r & 3), m1 = m0 + 4;
-      if (m0 < count) {
-        const uint32_t g0 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m0) & 63);
-        const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m1) & 63);
-        const int64_t gid = (int64_t)(upper ? g1 : g0);
-        if ((upper ? m1 : m0) < count) {
-          if (outp[0] && acc0[r] != 0.0f) unsafeAtomicAdd(outp[0] + gid * outD[0], acc0[r]);
-          if (two && outp[1] && acc1[r] != 0.0f) unsafeAtomicAdd(outp[1] + gid * outD[1], acc1[r]);
-        }
-      }
+      __syncthreads();  // rows read before they are written again
     }
   };
 
@@ -454,6 +562,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     float4 q0, q1;
     uint32_t my_id;
     const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
+
     // per Gaussian with a contribution, as the walk reaches it: weight sum
     // and count (kept by lane j for one round of atomics after the step),
     // tail channels, a ring row
@@ -478,7 +587,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
           else pix_next |= msk;
           queued++;
         }
-        if (ntail) {
+        if (any_tail) {
           const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
 #pragma unroll
           for (int t = 0; t < kMaxTail; t++) {
@@ -506,7 +615,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     }
   }
   if (queued > 0) flush(queued, pix_cur);
-  // statistics go to every set whose beta this group takes for this view
+  // statistics go to every set whose beta this work item takes for this view
   for (int b = bsets; b; b &= b - 1) {
     const SetDesc& sd = sets[__builtin_ctz(b)];
     if (sd.stats) quad_stats(s, lane, sd.stats);
@@ -629,11 +738,19 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
       default: return hipErrorInvalidValue;
     }
   }
-  int64_t work = (int64_t)a.tiles_stride * m * a.ngroups;
+  // one group: one wave per (view, quadrant, group); several: one wave per
+  // (view, quadrant) for all groups, sharing the walk
+  const bool multi = a.ngroups > 1;
+  int64_t work = (int64_t)a.tiles_stride * m * (multi ? 1 : a.ngroups);
   int64_t blocks = (work + 7) / 8 * 32;
-  hipLaunchKernelGGL(blend_wide_kernel<DT>, dim3((unsigned)blocks), dim3(64), 0, s, a.rec,
-                     a.ids, a.ranges, a.geom, a.n,
-                     a.tiles_stride, m, a.sets, a.groups, a.ngroups);
+  if (multi)
+    hipLaunchKernelGGL((blend_wide_kernel<DT, true>), dim3((unsigned)blocks), dim3(64), 0, s, a.rec,
+                       a.ids, a.ranges, a.geom, a.n, a.tiles_stride, m, a.sets, a.groups,
+                       a.ngroups);
+  else
+    hipLaunchKernelGGL((blend_wide_kernel<DT, false>), dim3((unsigned)blocks), dim3(64), 0, s,
+                       a.rec, a.ids, a.ranges, a.geom, a.n, a.tiles_stride, m, a.sets, a.groups,
+                       a.ngroups);
   return hipGetLastError();
 }
 
