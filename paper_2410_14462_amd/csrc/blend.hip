@@ -32,17 +32,22 @@ namespace {
 template <lv_dtype DT>
 __device__ __forceinline__ float load_feature(const void* map, int64_t idx, float scale) {
   if constexpr (DT == LV_F32) {
-    return static_cast<const float*>(map)[idx];
+    return gptr(static_cast<const float*>(map))[idx];
   } else if constexpr (DT == LV_BF16) {
-    uint32_t b = static_cast<const uint16_t*>(map)[idx];
+    uint32_t b = gptr(static_cast<const uint16_t*>(map))[idx];
     return __uint_as_float(b << 16);
   } else {
-    uint32_t b = static_cast<const uint8_t*>(map)[idx];
-    uint32_t e = (b >> 3) & 0xFu, mt = b & 7u;
-    float mag = e ? __uint_as_float(((e + 120u) << 23) | (mt << 20)) : (float)mt * 0x1.0p-9f;
-    return ((b & 0x80u) ? -mag : mag) * scale;
+    // without branches: a subnormal (e = 0) is built as 2^-6 (1 + m/8) and
+    // 2^-6 taken off again, which is exact; the sign bit goes on last
+    const uint32_t b = gptr(static_cast<const uint8_t*>(map))[idx];
+    const uint32_t e = (b >> 3) & 0xFu, mt = b & 7u, sub = e == 0u;
+    const float mag = __uint_as_float(((e + 120u + sub) << 23) | (mt << 20)) - __uint_as_float(sub * 0x3C800000u);
+    return __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24)) * scale;
   }
 }
+
+// Map of set sd for view v (NULL: the set does not take the view).
+__device__ __forceinline__ const void* map_of(const SetDesc& sd, int v) { return gptr(sd.maps)[v]; }
 
 // Can -power(d) <= tau hold for some d in the rectangle [X0,X1] x [Y0,Y1]
 // (offsets from the Gaussian's centre)?  -power = (L11 dx + L12 dy)^2 +
@@ -232,8 +237,8 @@ __device__ __forceinline__ void quad_stats(const Walk& s, int lane, unsigned lon
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
   if (lane == 0) {
-    atomicAdd(&stats[1], (unsigned long long)c);
-    atomicAdd(&stats[0], (unsigned long long)__popcll(covered));
+    gatomic_add(&stats[1], (unsigned long long)c);
+    gatomic_add(&stats[0], (unsigned long long)__popcll(covered));
   }
 }
 
@@ -294,7 +299,8 @@ __device__ __forceinline__ uint32_t row_bits(uint64_t m) {
 struct GroupLanes {
   float* outp[2];
   int outD[2];
-  const void* src[2];
+  const void* src[2];  // a readable map even where the lane owns no channel
+  bool own[2];         // the lane owns a channel of block b
   int64_t srcc[2];
   int srcld[2];
   float srcsc[2];
@@ -311,27 +317,30 @@ __device__ __forceinline__ bool group_lanes(const ChanGroup& grp, const SetDesc*
     L.outp[b] = nullptr;
     L.outD[b] = 0;
     L.src[b] = nullptr;
+    L.own[b] = false;
     L.srcc[b] = 0;
     L.srcld[b] = 0;
     L.srcsc[b] = 1.0f;
   }
   for (int k = 0; k < grp.nseg; k++) {
     const SetDesc& sd = sets[grp.set[k]];
-    const void* map = sd.maps[q.v];
+    const void* map = map_of(sd, q.v);
     if (!map) continue;  // this set does not take the view
     active = true;
     const int vc0 = grp.vc0[k], cnt = grp.cnt[k];
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       const int ch = b * 32 + (lane & 31);
+      if (!L.src[b]) L.src[b] = map;  // readable, for lanes without a channel
       if (ch >= vc0 && ch < vc0 + cnt) {
         const int c = grp.c0[k] + (ch - vc0);
         L.outp[b] = sd.U + c;
         L.outD[b] = sd.D;
         L.src[b] = map;
+        L.own[b] = true;
         L.srcc[b] = c;
         L.srcld[b] = sd.stride;
-        if constexpr (DT == LV_FP8_E4M3) L.srcsc[b] = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
+        if constexpr (DT == LV_FP8_E4M3) L.srcsc[b] = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * sd.D + c];
       }
     }
   }
@@ -339,18 +348,22 @@ __device__ __forceinline__ bool group_lanes(const ChanGroup& grp, const SetDesc*
 }
 
 // B operands of K-step t (pixel rows 2t, 2t + 1) for both blocks: F[pixel (row
-// 2t + l / 32, column i)][channel], split into hi and lo.
+// 2t + l / 32, column i)][channel], split into hi and lo.  Only for a group
+// that takes the view (group_lanes true: L.src holds a map for every lane).
 template <lv_dtype DT>
 __device__ __forceinline__ void stage_fragment(const GroupLanes& L, const Quad& q, int lane, int t,
                                                int b, bf16x8& fh, bf16x8& fl) {
+  // every lane loads (a safe index where it has nothing to load), then selects:
+  // no branch around the loads, so they are all in flight together
   float v[8];
   const int gy = q.qy + 2 * t + (lane >> 5);
 #pragma unroll
   for (int i = 0; i < 8; i++) {
     const int gx = q.qx + i;
-    v[i] = 0.0f;
-    if (L.src[b] && gx < q.g.W && gy < q.g.H)
-      v[i] = load_feature<DT>(L.src[b], ((int64_t)gy * q.g.W + gx) * L.srcld[b] + L.srcc[b], L.srcsc[b]);
+    const bool ok = L.own[b] && gx < q.g.W && gy < q.g.H;
+    const int64_t idx = ok ? ((int64_t)gy * q.g.W + gx) * L.srcld[b] + L.srcc[b] : 0;
+    const float x = load_feature<DT>(L.src[b], idx, L.srcsc[b]);
+    v[i] = ok ? x : 0.0f;
   }
   split8(v, fh, fl);
 }
@@ -405,8 +418,8 @@ __device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int
       const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m1) & 63);
       const int64_t gid = (int64_t)(upper ? g1 : g0);
       if ((upper ? m1 : m0) < count) {
-        if (L.outp[0] && acc0[r] != 0.0f) unsafeAtomicAdd(L.outp[0] + gid * L.outD[0], acc0[r]);
-        if (two && L.outp[1] && acc1[r] != 0.0f) unsafeAtomicAdd(L.outp[1] + gid * L.outD[1], acc1[r]);
+        if (L.outp[0] && acc0[r] != 0.0f) gatomic_add(L.outp[0] + gid * L.outD[0], acc0[r]);
+        if (two && L.outp[1] && acc1[r] != 0.0f) gatomic_add(L.outp[1] + gid * L.outD[1], acc1[r]);
       }
     }
   }
@@ -440,9 +453,9 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   for (int cg = g_lo; cg < g_hi; cg++) {
     const ChanGroup& grp = groups[cg];
     for (int b = grp.beta_sets; b; b &= b - 1)
-      if (sets[__builtin_ctz(b)].maps[q.v]) bsets |= b & -b;
+      if (map_of(sets[__builtin_ctz(b)], q.v)) bsets |= b & -b;
     bool any = false;
-    for (int k = 0; k < grp.nseg; k++) any = any || sets[grp.set[k]].maps[q.v] != nullptr;
+    for (int k = 0; k < grp.nseg; k++) any = any || map_of(sets[grp.set[k]], q.v) != nullptr;
     if (any) {
       gmask |= 1u << (cg - g_lo);
       has_main = true;
@@ -459,18 +472,23 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     ft[t] = 0.0f;
     tout[t] = nullptr;
     tD[t] = 0;
-    if (t < ntail && sets[last.tset[t]].maps[q.v]) {
+    if (t < ntail && map_of(sets[last.tset[t]], q.v)) {
       const SetDesc& sd = sets[last.tset[t]];
       const int c = last.tc[t];
       float sc = 1.0f;
-      if constexpr (DT == LV_FP8_E4M3) sc = sd.scales[(int64_t)(sd.view_base + q.v) * sd.D + c];
-      if (inside)
-        ft[t] = load_feature<DT>(sd.maps[q.v], ((int64_t)py * q.g.W + px) * sd.stride + c, sc);
+      if constexpr (DT == LV_FP8_E4M3) sc = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * sd.D + c];
+      const int64_t idx = inside ? ((int64_t)py * q.g.W + px) * sd.stride + c : 0;
+      const float x = load_feature<DT>(map_of(sd, q.v), idx, sc);  // no branch around the load
+      ft[t] = inside ? x : 0.0f;
       tout[t] = sd.U + c;
       tD[t] = sd.D;
       any_tail = true;
     }
   }
+  // the tail values are taken here, before the walk: a first use inside the
+  // walk would wait there for every atomic in flight as well
+#pragma unroll
+  for (int t = 0; t < kMaxTail; t++) asm volatile("" ::"v"(ft[t]));
   if (!has_main && !any_tail) return;  // wave-uniform: nothing of this work takes the view
 
   // single group: its lanes and fragments once, in registers
@@ -479,13 +497,15 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   bool two1 = false;
   if constexpr (!MULTI) {
     const ChanGroup& grp = groups[q.cg];
-    group_lanes<DT>(grp, sets, q, lane, L1);
+    const bool takes = group_lanes<DT>(grp, sets, q, lane, L1);
     two1 = grp.width > 32;
+    if (takes) {
 #pragma unroll
-    for (int b = 0; b < 2; b++)
+      for (int b = 0; b < 2; b++)
 #pragma unroll
-      for (int t = 0; t < 4; t++) stage_fragment<DT>(L1, q, lane, t, b, fh[b][t], fl[b][t]);
-    has_main = has_main && __ballot(L1.outp[0] != nullptr || L1.outp[1] != nullptr) != 0ull;
+        for (int t = 0; t < 4; t++) stage_fragment<DT>(L1, q, lane, t, b, fh[b][t], fl[b][t]);
+    }
+    has_main = has_main && takes && __ballot(L1.outp[0] != nullptr || L1.outp[1] != nullptr) != 0ull;
   }
 
   // Gaussians with a contribution queue up in a ring of 64 LDS rows (row r:
@@ -511,7 +531,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
         if (!((gmask >> (cg - g_lo)) & 1u)) continue;
         const ChanGroup& grp = groups[cg];
         GroupLanes L;
-        group_lanes<DT>(grp, sets, q, lane, L);
+        if (!group_lanes<DT>(grp, sets, q, lane, L)) continue;
         const bool two = grp.width > 32;
         // fragments staged K-step by K-step, right before their MFMAs (only
         // one K-step's operands live at a time)
@@ -593,7 +613,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
           for (int t = 0; t < kMaxTail; t++) {
             if (t < ntail && tout[t]) {
               const float at = wave_sum(wj * ft[t]);
-              if (lane == 0 && at != 0.0f) unsafeAtomicAdd(tout[t] + gid * tD[t], at);
+              if (lane == 0 && at != 0.0f) gatomic_add(tout[t] + gid * tD[t], at);
             }
           }
         }
@@ -603,7 +623,7 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
       for (int b = bsets; b; b &= b - 1) {
         const SetDesc& sd = sets[__builtin_ctz(b)];
         beta_atomic_add(sd.beta + my_id, my_ws);
-        if (sd.counts) atomicAdd(sd.counts + my_id, my_cnt);
+        if (sd.counts) gatomic_add(sd.counts + my_id, my_cnt);
       }
     }
     if (queued >= 32) {  // a full batch
@@ -637,7 +657,7 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
   const int lane = threadIdx.x;
   const SetDesc& sd = sets[0];
   const int D = sd.D, ld = sd.stride;
-  const void* map = sd.maps[q.v];
+  const void* map = map_of(sd, q.v);
   if (!map) return;  // the set does not take this view
   for (int e = lane; e < 64 * DG; e += 64) {
     const int p = e / DG, c = e - p * DG;
@@ -645,7 +665,7 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
     float val = 0.0f;
     if (c < D && gx < q.g.W && gy < q.g.H) {
       float sc = 1.0f;
-      if constexpr (DT == LV_FP8_E4M3) sc = sd.scales[(int64_t)(sd.view_base + q.v) * D + c];
+      if constexpr (DT == LV_FP8_E4M3) sc = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * D + c];
       val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * ld + c, sc);
     }
     Fs[e] = val;
@@ -696,7 +716,7 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
             wsl += __shfl_down(wsl, o, 64);
           }
           const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-          if (lane < D && acc != 0.0f) unsafeAtomicAdd(&sd.U[gid * D + lane], acc);
+          if (lane < D && acc != 0.0f) gatomic_add(&sd.U[gid * D + lane], acc);
           const float ws = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wsl), 0));
           if (lane == j) {
             my_ws = ws;
@@ -709,7 +729,7 @@ __global__ __launch_bounds__(64) void blend_small_kernel(
     // one round of weight-sum atomics per step (lane j: Gaussian j)
     if (mine) {
       beta_atomic_add(&sd.beta[my_id], my_ws);
-      if (sd.counts) atomicAdd(&sd.counts[my_id], my_cnt);
+      if (sd.counts) gatomic_add(&sd.counts[my_id], my_cnt);
     }
   }
   if (sd.stats) quad_stats(s, lane, sd.stats);
@@ -801,11 +821,11 @@ __global__ __launch_bounds__(64) void render_kernel(
   const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
   if (px < q.g.W && py < q.g.H) {
     const int64_t pix = (int64_t)py * q.g.W + px;
-    float* o = outs[q.v] + pix * D + c0;
+    LV_GLOBAL float* o = gptr(outs[q.v] + pix * D + c0);
 #pragma unroll
     for (int k = 0; k < kRenderCh; k++)
       if (c0 + k < D) o[k] = acc[k];
-    if (q.cg == 0 && alphas[q.v]) alphas[q.v][pix] = asum;
+    if (q.cg == 0 && alphas[q.v]) gptr(alphas[q.v])[pix] = asum;
   }
 }
 

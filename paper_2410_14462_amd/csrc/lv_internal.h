@@ -68,6 +68,27 @@ __device__ __forceinline__ float exp32(float x0) {
   return x0 < -80.0f ? 0.0f : e;
 }
 
+// Global-memory accesses through pointers held in structures: the compiler
+// cannot tell their address space and would emit FLAT instructions, which
+// also count as LDS operations, so every wait for an LDS result would wait
+// for them too.  These helpers make them global loads and atomics.
+#define LV_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ LV_GLOBAL T* gptr(T* p) {
+  return (LV_GLOBAL T*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ const LV_GLOBAL T* gptr(const T* p) {
+  return (const LV_GLOBAL T*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void gatomic_add(T* p, T v) {  // relaxed, device scope
+  __hip_atomic_fetch_add(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // beta_i accumulates in 64-bit fixed point, in units of 2^-35: each weight
 // sum is rounded to the nearest unit and added with an integer atomic, so the
 // total is exact (the sum of the rounded terms) and independent of the order
@@ -79,7 +100,7 @@ typedef unsigned long long beta_t;
 constexpr double kBetaUnit = 34359738368.0;  // 2^35
 
 __device__ __forceinline__ void beta_atomic_add(beta_t* p, float w) {
-  atomicAdd(p, (beta_t)__double2ull_rn((double)w * kBetaUnit));
+  gatomic_add(p, (beta_t)__double2ull_rn((double)w * kBetaUnit));
 }
 
 // ---------------------------------------------------------------- launches
