@@ -190,7 +190,7 @@ int ceil_log2(int64_t x) {
 // return, the sorted pair values (Gaussian ids) are in *ids, the ranges in
 // ws.ranges with row stride *stride, and the pair count in *P.
 lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, int mv,
-                          hipStream_t s, const uint32_t** ids, const uint32_t** pkeys, int* stride,
+                          hipStream_t s, const uint32_t** ids, int* stride,
                           int64_t* P, int64_t* nvis, int* max_tiles_out) {
   const int64_t n = sc->n;
   const int64_t items = n * (int64_t)mv;
@@ -248,7 +248,7 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   const uint32_t* seg = ws.seg.as<uint32_t>();
   HIP_TRY(radix_sort(ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.key1.as<uint32_t>(),
                      ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, 32, ws.hist.as<uint32_t>(),
-                     &second, s));
+                     true, &second, s));
   const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
   ws.dkey = second ? ws.key1.as<uint32_t>() : ws.key0.as<uint32_t>();
   ws.dval = sval;
@@ -276,15 +276,22 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   HIP_TRY(launch_duplicate(sval, ws.off.as<uint32_t>(), ws.rect.as<uint2>(), ws.cnt.as<uint32_t>(),
                            ws.geom.as<ViewGeom>(), n, mv, ws.pk0.as<uint32_t>(),
                            ws.pv0.as<uint32_t>(), s));
-  int tile_bits = ceil_log2(max_tiles);
+  // one pass (up to 2048 tiles): the tile ranges come from the pass's scanned
+  // counts and the sorted keys are not written; else from the sorted keys
+  const int tile_bits = ceil_log2(max_tiles);
+  const bool one_pass = total > 0 && radix_passes(tile_bits) == 1;
   HIP_TRY(radix_sort(ws.pk0.as<uint32_t>(), ws.pv0.as<uint32_t>(), ws.pk1.as<uint32_t>(),
                      ws.pv1.as<uint32_t>(), pseg, pseg + mv, mv, max_len, tile_bits,
-                     ws.hist2.as<uint32_t>(), &second, s));
+                     ws.hist2.as<uint32_t>(), !one_pass, &second, s));
   const uint32_t* pk = second ? ws.pk1.as<uint32_t>() : ws.pk0.as<uint32_t>();
   *ids = second ? ws.pv1.as<uint32_t>() : ws.pv0.as<uint32_t>();
-  *pkeys = pk;
-  HIP_TRY(hipMemsetAsync(ws.ranges.p, 0, sizeof(uint2) * (size_t)mv * max_tiles, s));
-  HIP_TRY(launch_ranges(pk, (int64_t)total, max_tiles, ws.ranges.as<uint2>(), s));
+  if (one_pass) {
+    HIP_TRY(launch_hist_ranges(ws.hist2.as<uint32_t>(), pseg, pseg + mv, mv, max_len, tile_bits,
+                               max_tiles, ws.ranges.as<uint2>(), s));
+  } else {
+    HIP_TRY(hipMemsetAsync(ws.ranges.p, 0, sizeof(uint2) * (size_t)mv * max_tiles, s));
+    HIP_TRY(launch_ranges(pk, (int64_t)total, max_tiles, ws.ranges.as<uint2>(), s));
+  }
   return LV_OK;
 }
 
@@ -487,10 +494,9 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
   for (int v0 = 0; v0 < m; v0 += (int)mc) {
     int mv = (int)std::min<int64_t>(mc, m - v0);
     const uint32_t* ids = nullptr;
-    const uint32_t* pkeys = nullptr;
     int stride = 0, max_tiles = 0;
     int64_t P = 0, nvis = 0;
-    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &pkeys, &stride, &P, &nvis, &max_tiles);
+    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &stride, &P, &nvis, &max_tiles);
     if (st != LV_OK) return st;
     for (int k = 0; k < nsets; k++) {
       fsets[k].acc->views += mv;
@@ -848,10 +854,9 @@ lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float*
   for (int v0 = 0; v0 < m; v0 += (int)mc) {
     const int mv = (int)std::min<int64_t>(mc, m - v0);
     const uint32_t* ids = nullptr;
-    const uint32_t* pkeys = nullptr;
     int stride = 0, max_tiles = 0;
     int64_t P = 0, nvis = 0;
-    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &pkeys, &stride, &P, &nvis, &max_tiles);
+    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &stride, &P, &nvis, &max_tiles);
     if (st != LV_OK) return st;
     // output tables (ws.up is idle: build_structure synchronised the stream)
     const size_t bytes = 2 * sizeof(float*) * (size_t)mv;
@@ -887,12 +892,12 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
     if (P_out) *P_out = 0;
     return LV_OK;
   }
-  const uint32_t *ids = nullptr, *pkeys = nullptr;
+  const uint32_t* ids = nullptr;
   int stride = 0, max_tiles = 0;
   int64_t P = 0, nvis = 0;
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
-  st = build_structure(sc, ws, cam, 1, s, &ids, &pkeys, &stride, &P, &nvis, &max_tiles);
+  st = build_structure(sc, ws, cam, 1, s, &ids, &stride, &P, &nvis, &max_tiles);
   if (st != LV_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));
   if (P_out) *P_out = P;

@@ -362,7 +362,7 @@ hipError_t launch_graph_reorder(const float4* p0, int64_t n, const int32_t* rp, 
   hipLaunchKernelGGL(morton_kernel, dim3(nb), dim3(256), 0, s, p0, n, box, k0, v0, deg, rp);
   hipLaunchKernelGGL(seg_init_kernel, dim3(1), dim3(64), 0, s, seg, n);
   bool second = false;
-  hipError_t e = radix_sort(k0, v0, k1, v1, seg, seg + 1, 1, n, 30, hist, &second, s);
+  hipError_t e = radix_sort(k0, v0, k1, v1, seg, seg + 1, 1, n, 30, hist, false, &second, s);
   if (e != hipSuccess) return e;
   const uint32_t* sorted = second ? v1 : v0;
   hipLaunchKernelGGL(invert_kernel, dim3(nb), dim3(256), 0, s, sorted, n, inv);

@@ -119,14 +119,23 @@ hipError_t launch_preprocess(const float4* p0, const float4* p1, const float4* p
                              hipStream_t s);
 
 // Segmented stable LSD radix sort of (key, val) pairs on key bits [0, bits),
-// in ceil(bits / 11) passes.  Segment g occupies [seg_start[g], seg_start[g] +
-// seg_len[g]); max_len bounds seg_len.  Result ends in (k0, v0) if the number
-// of passes is even, else in (k1, v1); *in_second tells which.  hist needs
-// sort_hist_size() uint32.
+// in radix_passes(bits) passes.  Segment g occupies [seg_start[g],
+// seg_start[g] + seg_len[g]); max_len bounds seg_len.  Result ends in (k0, v0)
+// if the number of passes is even, else in (k1, v1); *in_second tells which.
+// keys_last false: the last pass writes only the values.  hist needs
+// sort_hist_size() uint32; after the sort it holds the last pass's scanned
+// counts.
+inline int radix_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
 size_t sort_hist_size(int nseg, int64_t max_len);
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
-                      int64_t max_len, int bits, uint32_t* hist, bool* in_second, hipStream_t s);
+                      int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
+                      hipStream_t s);
+// Tile ranges (absolute [start, end) per view and tile, tiles_stride per view)
+// after a one-pass radix_sort by tile over the same segments, from its hist.
+hipError_t launch_hist_ranges(const uint32_t* hist, const uint32_t* seg_start,
+                              const uint32_t* seg_len, int nseg, int64_t max_len, int bits,
+                              int tiles_stride, uint2* ranges, hipStream_t s);
 
 // Exclusive scan of cnt[v*n + val[v*n+k]]-ordered counts: off[v*n+k] for the
 // m*n sorted items (global running offset over the whole chunk).  seg_start /

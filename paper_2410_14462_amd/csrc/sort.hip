@@ -3,11 +3,12 @@
 // order, stable sort of the (tile, Gaussian) pairs by tile, tile ranges.
 // The result per tile is its Gaussians sorted by (depth key, index).
 //
-// The radix sort is a segmented, stable LSD sort with 8-bit digits in three
-// kernels per pass (block histograms, per-segment scan, stable scatter).
-// Within a block, items are ranked in rounds of 256 in index order; lanes
-// holding the same digit are found with eight wave ballots, so ranking needs
-// no atomics and keeps input order among equal digits.
+// The radix sort is a segmented, stable LSD sort with digits of up to 11 bits
+// in three kernels per pass (block histograms, per-segment scan, stable
+// scatter).
+// Within a block, each wave ranks its items in rounds of 64 in index order;
+// lanes holding the same digit are found with one wave ballot per digit bit,
+// so ranking needs no atomics and keeps input order among equal digits.
 #include "lv_internal.h"
 
 namespace lv {
@@ -30,105 +31,118 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
 }
 
 constexpr int kBins = 1 << kRadixBits;        // digit values per pass
+static_assert(kBins <= 2048, "the scan gives each of its 1024 threads at most two digits");
 constexpr int kWaveItems = kSortItems / 4;    // contiguous items per wave
+constexpr int kPerLane = kWaveItems / 64;     // items per lane, held in registers
+constexpr int kPerThread = kSortItems / kSortThreads;
+static_assert(kSortThreads == 256 && kWaveItems % 64 == 0, "four waves per block");
 
-// Per-wave digit counts of the wave's contiguous share of a block's items
-// into cnt[wave][digit] (pre-zeroed).  One ballot match per 64 items; the
-// lowest lane of each digit group adds the group size (distinct digits,
-// distinct addresses: no atomics needed).
-__device__ __forceinline__ void wave_count(const uint32_t* __restrict__ k, uint32_t lo, uint32_t hi,
-                                           int shift, int bits, uint32_t* cnt) {
-  const uint32_t mask = (1u << bits) - 1u;
-  const int lane = threadIdx.x & 63;
-  for (uint32_t r = lo; r < hi; r += 64) {
-    const uint32_t i = r + lane;
-    const bool valid = i < hi;
-    const uint32_t d = valid ? (k[i] >> shift) & mask : 0u;
-    const uint64_t act = __ballot(valid);
-    const uint64_t peers = match_digit(d, bits, act);
-    if (valid && (peers & lanemask_lt()) == 0) cnt[d] += (uint32_t)__popcll(peers);
-  }
-}
-
+// Digit counts of one block's items (LDS atomics: the order of counting does
+// not matter), written as the block's row hist[segment][block][digit].  All
+// of the block's keys are loaded before any is counted.
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t wc[4][kBins];
-  const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x, w = t >> 6;
+  __shared__ uint32_t hs[kBins];
+  const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+  const int nbins = 1 << bits;
+  const uint32_t mask = (uint32_t)nbins - 1u;
   const uint32_t len = seg_len[g];
   const uint32_t base = (uint32_t)b * kSortItems;
-  for (int e = t; e < 4 * kBins; e += kSortThreads) (&wc[0][0])[e] = 0u;
-  __syncthreads();
-  if (base < len) {
-    const uint32_t lo = base + w * kWaveItems;
-    const uint32_t hi = min(len, lo + kWaveItems);
-    if (lo < hi) wave_count(keys + seg_start[g], lo, hi, shift, bits, wc[w]);
+  const uint32_t* k = keys + seg_start[g];
+  uint32_t d[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; r++) {
+    const uint32_t i = base + (uint32_t)(r * kSortThreads + t);
+    d[r] = i < len ? (k[i] >> shift) & mask : ~0u;
   }
+  for (int e = t; e < nbins; e += kSortThreads) hs[e] = 0u;
   __syncthreads();
-  const int nbins = 1 << bits;
-  for (int d = t; d < nbins; d += kSortThreads)
-    hist[((size_t)g * nbins + d) * nb + b] = (wc[0][d] + wc[1][d]) + (wc[2][d] + wc[3][d]);
+#pragma unroll
+  for (int r = 0; r < kPerThread; r++)
+    if (d[r] != ~0u) atomicAdd(&hs[d[r]], 1u);
+  __syncthreads();
+  uint32_t* hb = hist + ((size_t)g * nb + b) * nbins;  // this block's row: contiguous writes
+  for (int e = t; e < nbins; e += kSortThreads) hb[e] = hs[e];
 }
 
-// Exclusive scan, per segment, over (digit, block) in digit-major order.
+// Exclusive scan, per segment, over (digit, block) in digit-major order, of
+// counts stored block-major (hist[segment][block][digit]).  Thread t owns
+// digits [k t, k t + k): it sums its columns over the blocks, the digit totals
+// are scanned across the threads, and a second walk down the columns writes
+// each entry's start.  Rows are read whole by the block (coalesced).
 __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__ hist, int nb,
                                                           int bits) {
   __shared__ uint32_t part[1024 / 64];
-  __shared__ uint32_t carry_s;
-  const int g = blockIdx.x, t = threadIdx.x;
-  const size_t total = ((size_t)1 << bits) * nb;
-  uint32_t* h = hist + (size_t)g * total;
-  uint32_t carry = 0;
-  for (size_t base = 0; base < total; base += 1024) {
-    size_t i = base + t;
-    uint32_t x = i < total ? h[i] : 0u;
-    // inclusive wave scan
-    uint32_t incl = x;
-    int lane = t & 63, w = t >> 6;
+  const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nbins = 1 << bits;
+  const int k = nbins > 1024 ? nbins / 1024 : 1;  // digits per thread (1 or 2)
+  const int d0 = k * t;
+  const bool own = d0 < nbins;
+  uint32_t* h = hist + (size_t)g * nb * nbins;
+  uint32_t tot[2] = {0u, 0u};
+  if (own) {
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+      uint32_t x[8][2];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      uint32_t y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    if (lane == 63) part[w] = incl;
-    __syncthreads();
-    if (t < 16) {
-      uint32_t p = part[t];
-      uint32_t s = p;
-      for (int o = 1; o < 16; o <<= 1) {
-        uint32_t y = __shfl_up(s, o, 16);
-        if ((t & 15) >= o) s += y;
+      for (int u = 0; u < 8; u++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) x[u][j] = j < k ? h[(size_t)(b + u) * nbins + d0 + j] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        tot[0] += x[u][0];
+        tot[1] += x[u][1];
       }
-      part[t] = s - p;  // exclusive
-      if (t == 15) carry_s = s;
     }
-    __syncthreads();
-    if (i < total) h[i] = carry + part[w] + incl - x;
-    carry += carry_s;
-    __syncthreads();
+    for (; b < nb; b++)
+      for (int j = 0; j < k; j++) tot[j] += h[(size_t)b * nbins + d0 + j];
   }
+  const uint32_t mine = tot[0] + tot[1];
+  uint32_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) part[w] = incl;
+  __syncthreads();
+  uint32_t run0 = incl - mine;
+  for (int q = 0; q < w; q++) run0 += part[q];
+  if (!own) return;
+  uint32_t run[2] = {run0, run0 + tot[0]};
+  int b = 0;
+  for (; b + 8 <= nb; b += 8) {
+    uint32_t x[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+#pragma unroll
+      for (int j = 0; j < 2; j++) x[u][j] = j < k ? h[(size_t)(b + u) * nbins + d0 + j] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+        if (j < k) {
+          h[(size_t)(b + u) * nbins + d0 + j] = run[j];
+          run[j] += x[u][j];
+        }
+  }
+  for (; b < nb; b++)
+    for (int j = 0; j < k; j++) {
+      const uint32_t x = h[(size_t)b * nbins + d0 + j];
+      h[(size_t)b * nbins + d0 + j] = run[j];
+      run[j] += x;
+    }
 }
 
-// Stable scatter through LDS: the block counts its items per (wave, digit),
-// ranks them block-locally in digit order (waves in order, lanes in order),
-// places them in LDS at those ranks, and then writes the LDS contents out in
-// order: items of one digit are consecutive in LDS and go to consecutive
-// global positions, so the writes are runs instead of scattered words.
-template <typename T>
-__device__ __forceinline__ void wave_count_t(const uint32_t* __restrict__ k, uint32_t lo, uint32_t hi,
-                                             int shift, int bits, T* cnt) {
-  const uint32_t mask = (1u << bits) - 1u;
-  const int lane = threadIdx.x & 63;
-  for (uint32_t r = lo; r < hi; r += 64) {
-    const uint32_t i = r + lane;
-    const bool valid = i < hi;
-    const uint32_t d = valid ? (k[i] >> shift) & mask : 0u;
-    const uint64_t act = __ballot(valid);
-    const uint64_t peers = match_digit(d, bits, act);
-    if (valid && (peers & lanemask_lt()) == 0) cnt[d] = (T)(cnt[d] + (uint32_t)__popcll(peers));
-  }
-}
-
+// Stable scatter through LDS.  Each wave takes a contiguous quarter of the
+// block's items into registers (item lo + 64 r + lane), finds for each round
+// of 64 the lanes sharing its digit (kept for both uses below), and counts
+// per (wave, digit).  The block then ranks its items locally in digit order
+// (waves in order, rounds in order, lanes in order), places them in LDS at
+// those ranks and writes the LDS contents out in order: items of one digit
+// are consecutive in LDS and go to consecutive global positions.  kout may
+// be NULL (keys not needed after this pass).
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
@@ -145,12 +159,37 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   const uint32_t base = (uint32_t)b * kSortItems;
   if (base >= len) return;  // whole block idle (uniform)
   const uint32_t items = min(len - base, (uint32_t)kSortItems);
+  const uint32_t lo = base + w * kWaveItems;
+  const uint32_t hi = min(len, lo + kWaveItems);  // lo >= hi: the wave has no items
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint64_t lt = lanemask_lt();
+
+  uint32_t key[kPerLane], val[kPerLane];
+#pragma unroll
+  for (int r = 0; r < kPerLane; r++) {
+    const uint32_t i = lo + 64u * r + lane;
+    key[r] = i < hi ? kin[s0 + i] : 0u;
+    val[r] = i < hi ? vin[s0 + i] : 0u;
+  }
   for (int e = t; e < 4 * kBins; e += kSortThreads) (&wc[0][0])[e] = 0;
   __syncthreads();
-  const uint32_t lo = base + w * kWaveItems;
-  const uint32_t hi = min(len, lo + kWaveItems);
-  if (lo < hi) wave_count_t<uint16_t>(kin + s0, lo, hi, shift, bits, wc[w]);
+
+  // count per (wave, digit): the lowest lane of each group of equal digits
+  // adds the group's size
+  uint64_t peers[kPerLane];
+  uint16_t* cur = wc[w];
+#pragma unroll
+  for (int r = 0; r < kPerLane; r++) {
+    peers[r] = 0ull;
+    if (lo + 64u * r < hi) {  // wave-uniform
+      const bool valid = lo + 64u * r + lane < hi;
+      const uint32_t d = (key[r] >> shift) & mask;
+      peers[r] = match_digit(d, bits, __ballot(valid));
+      if (valid && (peers[r] & lt) == 0) cur[d] = (uint16_t)(cur[d] + (uint32_t)__popcll(peers[r]));
+    }
+  }
   __syncthreads();
+
   // block-local exclusive scan over digits (thread t owns digits [kPer t, kPer t + kPer))
   const int nbins = 1 << bits;
   uint32_t tot = 0;
@@ -169,11 +208,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   __syncthreads();
   uint32_t run = incl - tot;
   for (int q = 0; q < w; q++) run += wsum[q];
+  const uint32_t* hrow = hist + ((size_t)g * nb + b) * nbins;
 #pragma unroll
   for (int k = 0; k < kPer; k++) {
     const int d = kPer * t + k;
     if (d < nbins) {
-      gdelta[d] = s0 + hist[((size_t)g * nbins + d) * nb + b] - run;
+      gdelta[d] = s0 + hrow[d] - run;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         const uint32_t c = wc[q][d];
@@ -183,35 +223,50 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     }
   }
   __syncthreads();
-  // each wave places its contiguous share at its block-local ranks
-  const uint32_t mask = (1u << bits) - 1u;
-  uint16_t* cur = wc[w];
-  for (uint32_t r = lo; r < hi; r += 64) {
-    const uint32_t i = r + lane;
-    const bool valid = i < hi;
-    const uint32_t key = valid ? kin[s0 + i] : 0u;
-    const uint32_t val = valid ? vin[s0 + i] : 0u;
-    const uint32_t d = (key >> shift) & mask;
-    const uint64_t act = __ballot(valid);
-    const uint64_t peers = match_digit(d, bits, act);
-    const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
-    if (valid) {
-      const uint32_t pos = (uint32_t)cur[d] + rank;
-      lk[pos] = key;
-      lval[pos] = val;
+
+  // each wave places its items at their block-local ranks
+#pragma unroll
+  for (int r = 0; r < kPerLane; r++) {
+    if (lo + 64u * r < hi) {  // wave-uniform
+      const bool valid = lo + 64u * r + lane < hi;
+      const uint32_t d = (key[r] >> shift) & mask;
+      const uint32_t rank = (uint32_t)__popcll(peers[r] & lt);
+      if (valid) {
+        const uint32_t pos = (uint32_t)cur[d] + rank;
+        lk[pos] = key[r];
+        lval[pos] = val[r];
+      }
+      __builtin_amdgcn_wave_barrier();  // every lane has read cur[d]
+      if (valid && rank == 0) cur[d] = (uint16_t)(cur[d] + (uint32_t)__popcll(peers[r]));
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();  // every lane has read cur[d]
-    if (valid && rank == 0) cur[d] = (uint16_t)(cur[d] + (uint32_t)__popcll(peers));
-    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
+
   // write out in local order: runs of one digit land on consecutive positions
   for (uint32_t p = t; p < items; p += kSortThreads) {
-    const uint32_t key = lk[p];
-    const uint32_t pos = gdelta[(key >> shift) & mask] + p;
-    kout[pos] = key;
+    const uint32_t k = lk[p];
+    const uint32_t pos = gdelta[(k >> shift) & mask] + p;
+    if (kout) kout[pos] = k;
     vout[pos] = lval[p];
   }
+}
+
+// Tile ranges of a single-pass tile sort, from its scanned counts: block 0's
+// row holds the start of every digit (tile) within the segment (view).
+__global__ void hist_ranges_kernel(const uint32_t* __restrict__ hist,
+                                   const uint32_t* __restrict__ seg_start,
+                                   const uint32_t* __restrict__ seg_len, int nb, int bits,
+                                   int stride, uint2* __restrict__ ranges) {
+  const int g = blockIdx.y;
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= stride) return;
+  const int nbins = 1 << bits;
+  const uint32_t* h0 = hist + (size_t)g * nb * nbins;
+  const uint32_t s0 = seg_start[g], len = seg_len[g];
+  const uint32_t a = d < nbins ? h0[d] : len;
+  const uint32_t e = d + 1 < nbins ? h0[d + 1] : len;
+  ranges[(int64_t)g * stride + d] = make_uint2(s0 + a, s0 + e);
 }
 
 // ---- scan of per-(view, Gaussian) tile counts in depth order
@@ -378,26 +433,38 @@ size_t sort_hist_size(int nseg, int64_t max_len) {
 
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
-                      int64_t max_len, int bits, uint32_t* hist, bool* in_second, hipStream_t s) {
+                      int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
+                      hipStream_t s) {
   *in_second = false;
   if (nseg == 0 || max_len == 0 || bits == 0) return hipSuccess;
   int nb = (int)((max_len + kSortItems - 1) / kSortItems);
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   // fewest passes of at most kRadixBits bits, widths balanced
-  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  const int passes = radix_passes(bits);
   for (int p = 0, shift = 0; p < passes; p++) {
     const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
     hipLaunchKernelGGL(radix_hist_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, seg_start,
                        seg_len, shift, pb, nb, hist);
     hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, vi, ko,
-                       vo, seg_start, seg_len, shift, pb, nb, hist);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, vi,
+                       (p + 1 < passes || keys_last) ? ko : nullptr, vo, seg_start, seg_len, shift,
+                       pb, nb, hist);
     shift += pb;
     uint32_t* t;
     t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
     *in_second = !*in_second;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_ranges(const uint32_t* hist, const uint32_t* seg_start,
+                              const uint32_t* seg_len, int nseg, int64_t max_len, int bits,
+                              int tiles_stride, uint2* ranges, hipStream_t s) {
+  if (nseg == 0 || tiles_stride == 0) return hipSuccess;
+  const int nb = (int)((max_len + kSortItems - 1) / kSortItems);
+  hipLaunchKernelGGL(hist_ranges_kernel, dim3((unsigned)((tiles_stride + 255) / 256), nseg),
+                     dim3(256), 0, s, hist, seg_start, seg_len, nb, bits, tiles_stride, ranges);
   return hipGetLastError();
 }
 
