@@ -103,7 +103,7 @@ struct Workspace {
   Buf accUs[kMaxSets], accBs[kMaxSets];
   const uint32_t* dkey = nullptr;  // depth-sorted keys / ids of the last structure build
   const uint32_t* dval = nullptr;
-  Buf rec, key0, val0, key1, val1, rect, cnt, off, scan_tmp, hist, seg, pseg, total;
+  Buf rec, key0, val0, key1, val1, rect, cnt, scnt, srect, off, scan_tmp, hist, seg, pseg, total;
   Buf pk0, pv0, pk1, pv1, hist2, ranges, cams, geom, maps;
   HostBuf up, down;
 };
@@ -124,6 +124,10 @@ Workspace* workspace_for(hipStream_t s) {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+
+// Workspace bytes per (view, Gaussian) item of a structure build: record,
+// two key/value buffers, rect and count (Gaussian and depth order), offset.
+constexpr int64_t kItemBytes = sizeof(Rec) + 4 * 4 + 2 * (8 + 4) + 4;
 
 int64_t chunk_budget_bytes() {
   const char* e = getenv("LV_CHUNK_BYTES");
@@ -212,6 +216,8 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   HIP_TRY(ws.val1.ensure(4 * items, s));
   HIP_TRY(ws.rect.ensure(8 * items, s));
   HIP_TRY(ws.cnt.ensure(4 * items, s));
+  HIP_TRY(ws.scnt.ensure(4 * items, s));
+  HIP_TRY(ws.srect.ensure(8 * items, s));
   HIP_TRY(ws.off.ensure(4 * items, s));
   HIP_TRY(ws.scan_tmp.ensure(4 * scan_tmp_size(items), s));
   HIP_TRY(ws.hist.ensure(4 * sort_hist_size(mv, n), s));
@@ -248,12 +254,13 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   const uint32_t* seg = ws.seg.as<uint32_t>();
   HIP_TRY(radix_sort(ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.key1.as<uint32_t>(),
                      ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, 32, ws.hist.as<uint32_t>(),
-                     true, &second, s));
+                     true, &second, s,
+                     SortPayload{ws.rect.as<uint2>(), ws.scnt.as<uint32_t>(), ws.srect.as<uint2>()}));
   const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
   ws.dkey = second ? ws.key1.as<uint32_t>() : ws.key0.as<uint32_t>();
   ws.dval = sval;
   uint32_t* pseg = ws.pseg.as<uint32_t>();
-  HIP_TRY(scan_counts(ws.cnt.as<uint32_t>(), sval, n, mv, ws.off.as<uint32_t>(), pseg, pseg + mv,
+  HIP_TRY(scan_counts(ws.scnt.as<uint32_t>(), nullptr, n, mv, ws.off.as<uint32_t>(), pseg, pseg + mv,
                       ws.total.as<unsigned long long>(), ws.scan_tmp.as<uint32_t>(), s));
   uint32_t* down = static_cast<uint32_t*>(ws.down.p);
   HIP_TRY(hipMemcpyAsync(down, ws.total.p, 16, hipMemcpyDeviceToHost, s));
@@ -273,7 +280,7 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   HIP_TRY(ws.pk1.ensure(4 * total + 4, s));
   HIP_TRY(ws.pv1.ensure(4 * total + 4, s));
   HIP_TRY(ws.hist2.ensure(4 * sort_hist_size(mv, max_len), s));
-  HIP_TRY(launch_duplicate(sval, ws.off.as<uint32_t>(), ws.rect.as<uint2>(), ws.cnt.as<uint32_t>(),
+  HIP_TRY(launch_duplicate(sval, ws.off.as<uint32_t>(), ws.srect.as<uint2>(), ws.scnt.as<uint32_t>(),
                            ws.geom.as<ViewGeom>(), n, mv, ws.pk0.as<uint32_t>(),
                            ws.pv0.as<uint32_t>(), s));
   // one pass (up to 2048 tiles): the tile ranges come from the pass's scanned
@@ -488,7 +495,7 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
-  int64_t per_view = n * (int64_t)(sizeof(Rec) + 7 * 4 + 8);
+  int64_t per_view = n * kItemBytes;
   int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
   mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
   for (int v0 = 0; v0 < m; v0 += (int)mc) {
@@ -848,7 +855,7 @@ lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float*
   if (n == 0 || m == 0) return LV_OK;
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
-  int64_t per_view = n * (int64_t)(sizeof(Rec) + 7 * 4 + 8);
+  int64_t per_view = n * kItemBytes;
   int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
   mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
   for (int v0 = 0; v0 < m; v0 += (int)mc) {

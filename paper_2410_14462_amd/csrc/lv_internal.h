@@ -125,20 +125,29 @@ hipError_t launch_preprocess(const float4* p0, const float4* p1, const float4* p
 // keys_last false: the last pass writes only the values.  hist needs
 // sort_hist_size() uint32; after the sort it holds the last pass's scanned
 // counts.
+// payload (optional): the last pass also writes orect[i] = rect[seg_start[g]
+// + val] beside each sorted value, and ocnt[i] = that rect's area in tiles
+// (rect packed as x0 | y0 << 16, x1 | y1 << 16).
+struct SortPayload {
+  const uint2* rect = nullptr;
+  uint32_t* ocnt = nullptr;
+  uint2* orect = nullptr;
+};
 inline int radix_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
 size_t sort_hist_size(int nseg, int64_t max_len);
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
                       int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
-                      hipStream_t s);
+                      hipStream_t s, SortPayload payload = SortPayload{});
 // Tile ranges (absolute [start, end) per view and tile, tiles_stride per view)
 // after a one-pass radix_sort by tile over the same segments, from its hist.
 hipError_t launch_hist_ranges(const uint32_t* hist, const uint32_t* seg_start,
                               const uint32_t* seg_len, int nseg, int64_t max_len, int bits,
                               int tiles_stride, uint2* ranges, hipStream_t s);
 
-// Exclusive scan of cnt[v*n + val[v*n+k]]-ordered counts: off[v*n+k] for the
-// m*n sorted items (global running offset over the whole chunk).  seg_start /
+// Exclusive scan of the counts of the m*n sorted items, cnt[v*n + val[v*n+k]]
+// (or cnt[v*n+k] when sorted_val is NULL: counts already in sorted order):
+// off[v*n+k] (global running offset over the whole chunk).  seg_start /
 // seg_len per view get the view's pair range; totals[0] = number of pairs,
 // totals[1] = number of visible (view, Gaussian) items.
 size_t scan_tmp_size(int64_t items);
@@ -146,9 +155,12 @@ hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t 
                        uint32_t* off, uint32_t* seg_start, uint32_t* seg_len,
                        unsigned long long* totals, uint32_t* tmp, hipStream_t s);
 
-hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off, const uint2* rect,
-                            const uint32_t* cnt, const ViewGeom* geom, int64_t n, int m,
-                            uint32_t* pair_key, uint32_t* pair_val, hipStream_t s);
+// (tile, Gaussian) pairs of the depth-sorted items, given their ids, pair
+// offsets, rects and counts in the same sorted order.
+hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off,
+                            const uint2* sorted_rect, const uint32_t* sorted_cnt,
+                            const ViewGeom* geom, int64_t n, int m, uint32_t* pair_key,
+                            uint32_t* pair_val, hipStream_t s);
 
 hipError_t launch_ranges(const uint32_t* pair_key, int64_t P, int tiles_stride, uint2* ranges,
                          hipStream_t s);

@@ -142,12 +142,13 @@ __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__
 // (waves in order, rounds in order, lanes in order), places them in LDS at
 // those ranks and writes the LDS contents out in order: items of one digit
 // are consecutive in LDS and go to consecutive global positions.  kout may
-// be NULL (keys not needed after this pass).
+// be NULL (keys not needed after this pass).  With a payload, each item also
+// takes rect[s0 + val] (and its area, the count) to its output position.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb,
-    const uint32_t* __restrict__ hist) {
+    const uint32_t* __restrict__ hist, SortPayload pl) {
   constexpr int kPer = kBins / kSortThreads;       // digits per thread in the scan
   __shared__ uint16_t wc[4][kBins];                 // per-wave counts, then local cursors
   __shared__ uint32_t gdelta[kBins];                // global minus local position, per digit
@@ -244,11 +245,40 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   __syncthreads();
 
   // write out in local order: runs of one digit land on consecutive positions
-  for (uint32_t p = t; p < items; p += kSortThreads) {
-    const uint32_t k = lk[p];
-    const uint32_t pos = gdelta[(k >> shift) & mask] + p;
-    if (kout) kout[pos] = k;
-    vout[pos] = lval[p];
+  if (!pl.orect) {
+    for (uint32_t p = t; p < items; p += kSortThreads) {
+      const uint32_t k = lk[p];
+      const uint32_t pos = gdelta[(k >> shift) & mask] + p;
+      if (kout) kout[pos] = k;
+      vout[pos] = lval[p];
+    }
+    return;
+  }
+  // with the payload: every rect gathered first (all in flight together),
+  // then the writes; the count is the rect's area
+  uint32_t pos[kPerThread], vv[kPerThread];
+  uint2 rr[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; r++) {
+    const uint32_t p = (uint32_t)(t + r * kSortThreads);
+    pos[r] = 0u;
+    vv[r] = 0u;
+    rr[r] = make_uint2(0u, 0u);
+    if (p < items) {
+      const uint32_t k = lk[p];
+      pos[r] = gdelta[(k >> shift) & mask] + p;
+      vv[r] = lval[p];
+      rr[r] = pl.rect[s0 + vv[r]];
+      if (kout) kout[pos[r]] = k;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kPerThread; r++) {
+    if ((uint32_t)(t + r * kSortThreads) < items) {
+      vout[pos[r]] = vv[r];
+      pl.orect[pos[r]] = rr[r];
+      pl.ocnt[pos[r]] = ((rr[r].y & 0xFFFFu) - (rr[r].x & 0xFFFFu)) * ((rr[r].y >> 16) - (rr[r].x >> 16));
+    }
   }
 }
 
@@ -278,13 +308,16 @@ __global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __res
                                                            unsigned long long* __restrict__ bsum,
                                                            unsigned long long* __restrict__ nvis) {
   __shared__ unsigned long long red[4], redv[4];
-  int64_t base = (int64_t)blockIdx.x * kScanItems;
+  const int64_t base = (int64_t)blockIdx.x * kScanItems;
   unsigned long long s = 0, nv = 0;
-  for (int k = threadIdx.x; k < kScanItems; k += 256) {
-    int64_t i = base + k;
+  // item i belongs to view i / n: one division, then the view start moves
+  // along with i (steps of 256 may cross several views when n is small)
+  int64_t i = base + threadIdx.x;
+  int64_t vs = (i / n) * n;  // start of i's view
+  for (int k = threadIdx.x; k < kScanItems; k += 256, i += 256) {
+    while (i >= vs + n) vs += n;
     if (i < items) {
-      int64_t v = i / n;
-      uint32_t c = cnt[v * n + sval[i]];
+      const uint32_t c = sval ? cnt[vs + sval[i]] : cnt[i];
       s += c;
       nv += c != 0u;
     }
@@ -349,11 +382,13 @@ __global__ __launch_bounds__(256) void count_scan_kernel(const uint32_t* __restr
   int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)t * 16;
   uint32_t x[16];
   uint32_t s = 0;
+  int64_t vs = (base / n) * n;  // start of the view of item base (one division)
 #pragma unroll
   for (int k = 0; k < 16; k++) {
-    int64_t i = base + k;
+    const int64_t i = base + k;
+    while (i >= vs + n) vs += n;
     uint32_t c = 0;
-    if (i < items) c = cnt[(i / n) * n + sval[i]];
+    if (i < items) c = sval ? cnt[vs + sval[i]] : cnt[i];
     x[k] = c;
     s += c;
   }
@@ -388,28 +423,62 @@ __global__ void seg_kernel(const uint32_t* __restrict__ off, int64_t n, int m,
   seg_len[v] = b - a;
 }
 
-__global__ void duplicate_kernel(const uint32_t* __restrict__ sval, const uint32_t* __restrict__ off,
-                                 const uint2* __restrict__ rect, const uint32_t* __restrict__ cnt,
-                                 const ViewGeom* __restrict__ geom, int64_t n,
-                                 uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int v = blockIdx.y;
-  if (k >= n) return;
-  int64_t o = (int64_t)v * n + k;
-  uint32_t gi = sval[o];
-  uint32_t c = cnt[(int64_t)v * n + gi];
-  if (c == 0) return;
-  uint2 r = rect[(int64_t)v * n + gi];
-  uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
-  uint32_t TX = (uint32_t)geom[v].TX;
-  uint32_t p = off[o];
-  uint32_t hv = (uint32_t)v << kViewShift;
-  for (uint32_t y = y0; y < y1; y++)
-    for (uint32_t x = x0; x < x1; x++) {
-      pkey[p] = hv | (y * TX + x);
-      pval[p] = gi;
-      p++;
+// Pairs of 64 consecutive depth-sorted items of a view, written by their wave
+// together: the items' pairs are consecutive in the output (off is the
+// exclusive scan of the counts in this order), so the wave walks them 64 at a
+// time, each lane finding the item that owns its pair by a binary search over
+// the wave's inclusive count prefix.  Within an item, tiles go row by row.
+__global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restrict__ sval,
+                                                        const uint32_t* __restrict__ off,
+                                                        const uint2* __restrict__ srect,
+                                                        const uint32_t* __restrict__ scnt,
+                                                        const ViewGeom* __restrict__ geom, int64_t n,
+                                                        uint32_t* __restrict__ pkey,
+                                                        uint32_t* __restrict__ pval) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  if (k - lane >= n) return;  // the whole wave is past the view's end
+  uint32_t gi = 0u, c = 0u, p = 0u, x0 = 0u, y0 = 0u, w = 1u;
+  if (k < n) {
+    const int64_t o = (int64_t)v * n + k;
+    gi = sval[o];
+    c = scnt[o];
+    p = off[o];
+    if (c) {
+      const uint2 r = srect[o];
+      x0 = r.x & 0xFFFFu;
+      y0 = r.x >> 16;
+      w = (r.y & 0xFFFFu) - x0;
     }
+  }
+  uint32_t incl = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  const uint32_t p0 = __shfl(p, 0, 64);  // lane 0 is inside the view
+  const uint32_t excl = incl - c;
+  const uint32_t TX = (uint32_t)geom[v].TX;
+  const uint32_t hv = (uint32_t)v << kViewShift;
+  for (uint32_t j = 0; j < total; j += 64) {
+    const uint32_t slot = j + lane;
+    // owner: the number of lanes whose inclusive prefix is <= slot
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (__shfl(incl, pos + step - 1, 64) <= slot) pos += step;
+    const uint32_t kk = slot - __shfl(excl, pos, 64);
+    const uint32_t ow = __shfl(w, pos, 64), ox = __shfl(x0, pos, 64), oy = __shfl(y0, pos, 64);
+    const uint32_t og = __shfl(gi, pos, 64);
+    if (slot < total) {
+      const uint32_t dy = kk / ow;
+      pkey[p0 + slot] = hv | ((oy + dy) * TX + ox + (kk - dy * ow));
+      pval[p0 + slot] = og;
+    }
+  }
 }
 
 __global__ void ranges_kernel(const uint32_t* __restrict__ key, int64_t P, int stride,
@@ -434,7 +503,7 @@ size_t sort_hist_size(int nseg, int64_t max_len) {
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
                       int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
-                      hipStream_t s) {
+                      hipStream_t s, SortPayload payload) {
   *in_second = false;
   if (nseg == 0 || max_len == 0 || bits == 0) return hipSuccess;
   int nb = (int)((max_len + kSortItems - 1) / kSortItems);
@@ -448,7 +517,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
     hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, vi,
                        (p + 1 < passes || keys_last) ? ko : nullptr, vo, seg_start, seg_len, shift,
-                       pb, nb, hist);
+                       pb, nb, hist, p + 1 < passes ? SortPayload{} : payload);
     shift += pb;
     uint32_t* t;
     t = ki; ki = ko; ko = t;
@@ -496,12 +565,13 @@ hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off, const uint2* rect,
-                            const uint32_t* cnt, const ViewGeom* geom, int64_t n, int m,
-                            uint32_t* pair_key, uint32_t* pair_val, hipStream_t s) {
+hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off,
+                            const uint2* sorted_rect, const uint32_t* sorted_cnt,
+                            const ViewGeom* geom, int64_t n, int m, uint32_t* pair_key,
+                            uint32_t* pair_val, hipStream_t s) {
   if (n == 0 || m == 0) return hipSuccess;
   hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
-                     s, sorted_val, off, rect, cnt, geom, n, pair_key, pair_val);
+                     s, sorted_val, off, sorted_rect, sorted_cnt, geom, n, pair_key, pair_val);
   return hipGetLastError();
 }
 
