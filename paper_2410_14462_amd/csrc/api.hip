@@ -440,23 +440,21 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
   const int64_t n = sc->n;
   if (n == 0 || m == 0) return LV_OK;
 
-  // channel groups: one set of D <= 32 -> small kernel; otherwise the sets'
-  // channels concatenated and cut into groups of 64, a tail of <= 16 channels
-  // joining the previous group
-  int small_dg = 0;
+  // channel groups: the sets' channels concatenated and cut into groups of
+  // 64, a last part of <= kMaxTail channels joining the previous group as its
+  // tail
   std::vector<ChanGroup> groups;
-  if (nsets == 1 && total <= 32) {
-    small_dg = 1;
-    while (small_dg < total) small_dg <<= 1;
-  } else {
-    // 64-channel main parts; a last part of <= 4 channels becomes the
-    // register tail of the previous group
+  {
+    // 64-channel main parts; a last part of <= 4 channels becomes the tail
+    // of the previous group (or the only channels of a group without a
+    // main part)
     std::vector<int> starts;
     for (int b = 0; b < total; b += 64) starts.push_back(b);
     int tail_lo = total;
-    if (starts.size() > 1 && total - starts.back() <= kMaxTail) {
+    if (total - starts.back() <= kMaxTail) {
       tail_lo = starts.back();
       starts.pop_back();
+      if (starts.empty()) starts.push_back(0);
     }
     for (size_t gi = 0; gi < starts.size(); gi++) {
       const bool last = gi + 1 == starts.size();
@@ -548,7 +546,6 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
     ba.groups = reinterpret_cast<const ChanGroup*>(dev + b_sets);
     ba.ngroups = (int32_t)groups.size();
     ba.max_width = max_width;
-    ba.small_dg = small_dg;
     {
       std::lock_guard<std::mutex> pk(g_prof_mu);
       if (g_prof_on) {

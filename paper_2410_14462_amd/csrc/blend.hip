@@ -1,27 +1,26 @@
 // Blend-and-accumulate (Sec. 3.2, Eq. 3 / Eq. 5): for every tile of every
 // view, walk the tile's depth-ordered Gaussians front to back, form the
 // alpha-blending weight w_i(p) = alpha_i(p) T_i(p) of each Gaussian at each
-// pixel (Eq. 1), and scatter w_i(p) F(p) and w_i(p) into the per-Gaussian
+// pixel (Eq. 1), and add w_i(p) F(p) and w_i(p) into the per-Gaussian
 // accumulators U_i and beta_i.  W is never materialised.
 //
 // One workgroup = one wave64 = one 8x8 quadrant of a 16x16 tile (one pixel
-// per lane) x one group of channels.  Waves never wait for each other: no
-// barriers, a wave retires as soon as its 64 pixels are done.  Per step of 32
-// Gaussians of the tile's list:
+// per lane), for one group of up to 64 channels (or, with several groups,
+// all of them).  Waves never wait for each other.  Per step of 32 Gaussians
+// of the tile's list:
 //   0. lane j loads Gaussian j's record (vector loads, all in flight
 //      together) and tests whether its alpha >= 1/255 region can touch the
 //      quadrant (exact minimum of the conic over the quadrant, conservative
 //      slack); a ballot gives the step's hit mask;
-//   A. walk: each lane evaluates the hit Gaussians for its pixel in order
-//      (record fields broadcast with readlane), branch-free, w kept in VGPRs;
-//   B. accumulate and scatter, per hit Gaussian with some w > 0:
-//      wide kernel (any number of feature sets, up to 64 channels per wave
-//        plus 4 tail channels): one channel per lane; the rows of 8 pixels
-//        holding a contribution are visited with compile-time lanes and LDS
-//        offsets (features staged pixel-major, 64 words per pixel);
-//        tail channels stay in registers and are reduced across the wave;
-//      small kernel (one set, D <= 32): 64/DG pixel slots of DG channels;
-//      then one global atomic per channel; beta in exact fixed point.
+//   A. walk: a scalar loop over the hit Gaussians in order; each lane
+//      evaluates the Gaussian at its pixel (record fields broadcast with
+//      readlane), every decision in the S32 sequence;
+//   B. a Gaussian with some w > 0 takes the next of 32 LDS rows (its weights
+//      at the 64 pixels).  A full set of rows (and the last, partial one) is
+//      flushed: U_rows += W_rows F on the matrix cores, one global atomic per
+//      (Gaussian, channel); beta (the rows' sums, in exact fixed point) and
+//      the tail channels (the rows' dot products with up to 4 further
+//      channels) by one lane pair per row.
 #include "lv_internal.h"
 
 namespace lv {
@@ -81,23 +80,6 @@ __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
-}
-
-// Sum over the 64 lanes of the wave with DPP (within rows: quad swaps and
-// mirrors; across rows: row broadcasts), returned as a wave-uniform value.
-__device__ __forceinline__ float wave_sum(float x) {
-  x += dpp_f<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
-  x += dpp_f<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
-  x += dpp_f<0x141, 0xF>(x);  // row_half_mirror
-  x += dpp_f<0x140, 0xF>(x);  // row_mirror
-  x += dpp_f<0x142, 0xA>(x);  // row_bcast:15 into rows 1, 3
-  x += dpp_f<0x143, 0xC>(x);  // row_bcast:31 into rows 2, 3
-  return readlane_f(x, 63);
-}
-
 // The quadrant a workgroup handles.  Workgroups go to the 8 XCDs
 // round-robin, so the four quadrant waves of a tile get ids that are equal
 // mod 8 and consecutive within the XCD: they share that XCD's L2 for the
@@ -138,7 +120,6 @@ struct Walk {
   float qx0, qy0;  // the quadrant's first pixel, relative to the tile
   float T;
   bool alive;
-  uint32_t ncontrib;  // this pixel's counted Gaussians (statistics only)
 };
 
 __device__ __forceinline__ void walk_init(const Quad& q, int lane, Walk& s) {
@@ -152,7 +133,6 @@ __device__ __forceinline__ void walk_init(const Quad& q, int lane, Walk& s) {
   s.qy0 = (float)(q.qy - oy);
   s.T = 1.0f;
   s.alive = px < q.g.W && py < q.g.H;
-  s.ncontrib = 0;
 }
 
 // Step 0: records of Gaussians [base, base + cnt) one per lane, centres made
@@ -178,79 +158,34 @@ __device__ __forceinline__ uint64_t step_records(const Rec* __restrict__ vrec,
   return __ballot(hit);
 }
 
-// Step A: the front-to-back walk of the hit Gaussians, branch-free; every
-// decision is the S32 sequence (see lv_internal.h).
-template <int G>
-__device__ __forceinline__ void step_walk(uint64_t hits, float4 q0, float4 q1, Walk& s,
-                                          float (&wv)[G]) {
-#pragma unroll
-  for (int j = 0; j < G; j++) {
-    wv[j] = 0.0f;
-    if ((hits >> j) & 1ull) {
-      const float cx = readlane_f(q0.x, j), cy = readlane_f(q0.y, j);
-      const float L11 = readlane_f(q0.z, j), L12 = readlane_f(q0.w, j);
-      const float L22 = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
-      const float dx = s.pxo - cx, dy = s.pyo - cy;
-      const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
-      const float al = fminf(kAlphaMax, op * exp32(-__builtin_fmaf(u, u, w * w)));
-      const bool ok = s.alive && al >= kAlphaMin;
-      const float Tn = s.T * (1.0f - al);
-      const bool stop = ok && Tn < kTEps;
-      const bool take = ok && !stop;
-      wv[j] = take ? al * s.T : 0.0f;
-      s.T = take ? Tn : s.T;
-      s.alive = s.alive && !stop;
-      s.ncontrib += take ? 1u : 0u;
-    }
-  }
-}
-
-// The same walk, handing each hit Gaussian's weight to fn(j, w) as soon as it
-// is known (no array of the step's weights stays live in registers).
-template <int G, typename Fn>
-__device__ __forceinline__ void step_walk_each(uint64_t hits, float4 q0, float4 q1, Walk& s, Fn&& fn) {
-#pragma unroll
-  for (int j = 0; j < G; j++) {
-    if ((hits >> j) & 1ull) {
-      const float cx = readlane_f(q0.x, j), cy = readlane_f(q0.y, j);
-      const float L11 = readlane_f(q0.z, j), L12 = readlane_f(q0.w, j);
-      const float L22 = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
-      const float dx = s.pxo - cx, dy = s.pyo - cy;
-      const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
-      const float al = fminf(kAlphaMax, op * exp32(-__builtin_fmaf(u, u, w * w)));
-      const bool ok = s.alive && al >= kAlphaMin;
-      const float Tn = s.T * (1.0f - al);
-      const bool stop = ok && Tn < kTEps;
-      const bool take = ok && !stop;
-      const float wj = take ? al * s.T : 0.0f;
-      s.T = take ? Tn : s.T;
-      s.alive = s.alive && !stop;
-      s.ncontrib += take ? 1u : 0u;
-      fn(j, wj);
-    }
-  }
-}
-
-__device__ __forceinline__ void quad_stats(const Walk& s, int lane, unsigned long long* stats) {
-  const uint64_t covered = __ballot(s.ncontrib != 0u);
-  uint64_t c = s.ncontrib;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
-  if (lane == 0) {
-    gatomic_add(&stats[1], (unsigned long long)c);
-    gatomic_add(&stats[0], (unsigned long long)__popcll(covered));
-  }
+// One step of the walk: Gaussian j of the step (lane j's record) at this
+// lane's pixel; returns its weight w = alpha T (0: no contribution).
+__device__ __forceinline__ float walk_one(const float4& q0, const float4& q1, int j, Walk& s) {
+  const float cx = readlane_f(q0.x, j), cy = readlane_f(q0.y, j);
+  const float L11 = readlane_f(q0.z, j), L12 = readlane_f(q0.w, j);
+  const float L22 = readlane_f(q1.x, j), op = readlane_f(q1.y, j);
+  const float dx = s.pxo - cx, dy = s.pyo - cy;
+  const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
+  const float al = fminf(kAlphaMax, op * exp32(-__builtin_fmaf(u, u, w * w)));
+  const bool ok = s.alive && al >= kAlphaMin;
+  const float Tn = s.T * (1.0f - al);
+  const bool stop = ok && Tn < kTEps;
+  const bool take = ok && !stop;
+  const float wj = take ? al * s.T : 0.0f;
+  s.T = take ? Tn : s.T;
+  s.alive = s.alive && !stop;
+  return wj;
 }
 
 // ---------------------------------------------------------------- wide kernel
 // Any number of feature sets; the workgroup's channel group has up to 64
-// channels made of segments of the sets plus up to 4 tail channels (lane =
-// pixel, reduced across the wave).
+// channels made of segments of the sets plus up to 4 tail channels (summed
+// per LDS row at each flush).
 //
-// Accumulation on the matrix cores.  After the walk of a step, the weights
-// of its 32 Gaussians at the quadrant's 64 pixels form W_s (32 x 64), and
-// the contribution of the step to the group's channels is the dense product
-// U_s = W_s F (F: 64 pixels x 64 channels).  It runs as 32x32x16 BF16 MFMAs
+// Accumulation on the matrix cores.  The weights of 32 queued Gaussians at
+// the quadrant's 64 pixels form W_s (32 x 64), and their contribution to the
+// group's channels is the dense product U_s = W_s F (F: 64 pixels x 64
+// channels).  It runs as 32x32x16 BF16 MFMAs
 // with FP32 accumulation on split operands: x = hi + lo, hi = bf16(x) and
 // lo = bf16(x - hi) (both round-to-nearest-even), so |x - hi - lo| <=
 // 2^-18 |x|; U_s = W_hi F_hi + W_lo F_hi + W_hi F_lo (the dropped W_lo F_lo
@@ -405,8 +340,8 @@ __device__ __forceinline__ void batch_mfma(bool two, uint32_t rows, const float*
 }
 
 // One atomic per (queued Gaussian, channel): D row m of the batch is ring
-// row head + m, whose Gaussian id lane (head + m) % 64 holds.
-__device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int count, int head,
+// row m, whose Gaussian id lane m holds.
+__device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int count,
                                               uint32_t ring_gid, int lane, const f32x16& acc0,
                                               const f32x16& acc1) {
   const bool upper = lane >= 32;
@@ -414,8 +349,8 @@ __device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int
   for (int r = 0; r < 16; r++) {
     const int m0 = 8 * (r >> 2) + (r & 3), m1 = m0 + 4;
     if (m0 < count) {
-      const uint32_t g0 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m0) & 63);
-      const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, (head + m1) & 63);
+      const uint32_t g0 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, m0);
+      const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, m1);
       const int64_t gid = (int64_t)(upper ? g1 : g0);
       if ((upper ? m1 : m0) < count) {
         if (L.outp[0] && acc0[r] != 0.0f) gatomic_add(L.outp[0] + gid * L.outD[0], acc0[r]);
@@ -430,14 +365,22 @@ __device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int
 // one wave per (view, quadrant) walks once for all groups; each batch runs
 // every group in turn, staging that group's fragments for the K-steps it
 // needs (the walk, the larger part of a group's cost, is shared).
+// Occupancy: waves per SIMD the register allocation must allow (the walk is
+// latency-bound; more resident waves hide it).  BF16 maps need no low
+// operand halves, so their single-group kernel fits four.
 template <lv_dtype DT, bool MULTI>
-__global__ __launch_bounds__(64) void blend_wide_kernel(
+constexpr int wide_waves() {
+  return MULTI ? 2 : (DT == LV_BF16 ? 4 : 3);
+}
+
+template <lv_dtype DT, bool MULTI>
+__global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
     const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
   constexpr int G = kChunk;
   constexpr bool kSplitF = DT != LV_BF16;  // BF16 maps are exact in one BF16 operand
-  __shared__ __align__(16) float Wt[64 * kWtPitch];  // ring of queued Gaussians: [row][pixel]
+  __shared__ __align__(16) float Wt[32 * kWtPitch];  // queued Gaussians: [row][pixel]
   Quad q;
   if (!decode_quad(ranges, geom, tiles_stride, nviews, MULTI ? 1 : ngroups, q)) return;
   const int lane = threadIdx.x;
@@ -463,13 +406,15 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
   }
   const ChanGroup& last = groups[g_hi - 1];
   const int ntail = last.ntail;
-  float ft[kMaxTail];
+  // tail channels: their features per pixel in LDS (Ft[t][pixel]), summed
+  // against the ring rows at each flush
+  __shared__ __align__(16) float Ft[kMaxTail * 64];
   float* tout[kMaxTail];
   int tD[kMaxTail];
   bool any_tail = false;
 #pragma unroll
   for (int t = 0; t < kMaxTail; t++) {
-    ft[t] = 0.0f;
+    float ft = 0.0f;
     tout[t] = nullptr;
     tD[t] = 0;
     if (t < ntail && map_of(sets[last.tset[t]], q.v)) {
@@ -479,17 +424,14 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
       if constexpr (DT == LV_FP8_E4M3) sc = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * sd.D + c];
       const int64_t idx = inside ? ((int64_t)py * q.g.W + px) * sd.stride + c : 0;
       const float x = load_feature<DT>(map_of(sd, q.v), idx, sc);  // no branch around the load
-      ft[t] = inside ? x : 0.0f;
+      ft = inside ? x : 0.0f;
       tout[t] = sd.U + c;
       tD[t] = sd.D;
       any_tail = true;
     }
+    Ft[t * 64 + lane] = ft;
   }
-  // the tail values are taken here, before the walk: a first use inside the
-  // walk would wait there for every atomic in flight as well
-#pragma unroll
-  for (int t = 0; t < kMaxTail; t++) asm volatile("" ::"v"(ft[t]));
-  if (!has_main && !any_tail) return;  // wave-uniform: nothing of this work takes the view
+  if (!has_main && !any_tail && !bsets) return;  // wave-uniform: nothing here takes the view
 
   // single group: its lanes and fragments once, in registers
   GroupLanes L1;
@@ -508,24 +450,28 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     has_main = has_main && takes && __ballot(L1.outp[0] != nullptr || L1.outp[1] != nullptr) != 0ull;
   }
 
-  // Gaussians with a contribution queue up in a ring of 64 LDS rows (row r:
-  // the Gaussian's weights at the 64 pixels, its id in lane r's ring_gid);
-  // every 32 of them, and at the end, one batch of MFMAs (M = 32 rows) and
-  // one round of atomics per group: the matrix products run on full rows
-  // whatever the number of contributing Gaussians per step of the walk.
-  int head = 0, queued = 0;                  // ring rows [head, head + queued)
-  uint64_t pix_cur = 0ull, pix_next = 0ull;  // pixels used by the current batch / the next
-  uint32_t ring_gid = 0u;
+  // Gaussians with a contribution queue up in 32 LDS rows (row r: the
+  // Gaussian's weights at the 64 pixels; its id and its number of
+  // contributing pixels in lane r's ring_gid / ring_cnt).  When the rows are
+  // full, and at the end, one flush: a batch of MFMAs (M = 32 rows) and one
+  // round of atomics per group, so the matrix products run on full rows
+  // whatever the number of contributing Gaussians per step of the walk; and
+  // the rows' sums (beta) and dot products with the tail channels, one row
+  // per lane pair, each lane summing half of the row in a fixed order.
+  int queued = 0;        // rows [0, queued) hold Gaussians
+  uint64_t pix = 0ull;   // pixels used by the queued rows
+  uint32_t ring_gid = 0u, ring_cnt = 0u;
 
-  auto flush = [&](int count, uint64_t pix) {
+  auto flush = [&](int count) {
     __syncthreads();  // ring rows written (one wave per workgroup: orders LDS)
     const uint32_t rows = row_bits(pix);
-    const float* wrow = Wt + ((head + (lane & 31)) & 63) * kWtPitch + 8 * (lane >> 5);
+    const float* wrow = Wt + (lane & 31) * kWtPitch + 8 * (lane >> 5);
     if constexpr (!MULTI) {
-      f32x16 acc0 = {}, acc1 = {};
-      batch_mfma<kSplitF>(two1, rows, wrow, fh, fl, acc0, acc1);
-      __syncthreads();  // rows read before they are written again
-      batch_scatter(L1, two1, count, head, ring_gid, lane, acc0, acc1);
+      if (has_main) {
+        f32x16 acc0 = {}, acc1 = {};
+        batch_mfma<kSplitF>(two1, rows, wrow, fh, fl, acc0, acc1);
+        batch_scatter(L1, two1, count, ring_gid, lane, acc0, acc1);
+      }
     } else {
       for (int cg = g_lo; cg < g_hi; cg++) {
         if (!((gmask >> (cg - g_lo)) & 1u)) continue;
@@ -567,14 +513,53 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
             }
           }
         }
-        batch_scatter(L, two, count, head, ring_gid, lane, acc0, acc1);
+        batch_scatter(L, two, count, ring_gid, lane, acc0, acc1);
       }
-      __syncthreads();  // rows read before they are written again
     }
+    if (bsets || any_tail) {
+      // lane l: row l % 32, pixels [32 (l / 32), 32 (l / 32) + 32)
+      const float* rp = Wt + (lane & 31) * kWtPitch + 32 * (lane >> 5);
+      const float* fp = Ft + 32 * (lane >> 5);
+      float bs = 0.0f, ts[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const float4 a = *reinterpret_cast<const float4*>(rp + 4 * k);
+        bs += a.x;
+        bs += a.y;
+        bs += a.z;
+        bs += a.w;
+#pragma unroll
+        for (int t = 0; t < kMaxTail; t++) {
+          if (t < ntail) {  // wave-uniform
+            const float4 f = *reinterpret_cast<const float4*>(fp + t * 64 + 4 * k);
+            ts[t] = __builtin_fmaf(a.x, f.x, ts[t]);
+            ts[t] = __builtin_fmaf(a.y, f.y, ts[t]);
+            ts[t] = __builtin_fmaf(a.z, f.z, ts[t]);
+            ts[t] = __builtin_fmaf(a.w, f.w, ts[t]);
+          }
+        }
+      }
+      bs += __shfl_xor(bs, 32, 64);
+#pragma unroll
+      for (int t = 0; t < kMaxTail; t++) ts[t] += __shfl_xor(ts[t], 32, 64);
+      if (lane < count) {  // lane r < 32: row r, whose id and count it holds
+        for (int b = bsets; b; b &= b - 1) {
+          const SetDesc& sd = sets[__builtin_ctz(b)];
+          beta_atomic_add(sd.beta + ring_gid, bs);
+          if (sd.counts) gatomic_add(sd.counts + ring_gid, ring_cnt);
+        }
+#pragma unroll
+        for (int t = 0; t < kMaxTail; t++)
+          if (tout[t] && ts[t] != 0.0f) gatomic_add(tout[t] + (int64_t)ring_gid * tD[t], ts[t]);
+      }
+    }
+    __syncthreads();  // rows read before they are written again
   };
 
   Walk s;
   walk_init(q, lane, s);
+  uint64_t covered = 0ull;  // pixels with a contribution (statistics)
+  uint32_t ncontrib = 0u;   // contributions of the quadrant (statistics)
   const Rec* vrec = rec + (int64_t)q.v * n;
   for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
     if (__ballot(s.alive) == 0ull) break;
@@ -583,181 +568,43 @@ __global__ __launch_bounds__(64) void blend_wide_kernel(
     uint32_t my_id;
     const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
 
-    // per Gaussian with a contribution, as the walk reaches it: weight sum
-    // and count (kept by lane j for one round of atomics after the step),
-    // tail channels, a ring row
-    uint32_t anyw = 0u;
-    float my_ws = 0.0f;
-    uint32_t my_cnt = 0u;
-    step_walk_each<G>(hits, q0, q1, s, [&](const int j, const float wj) {
+    // the hit Gaussians in order (a scalar loop over the set bits); each
+    // with a contribution takes the next ring row, a full ring is flushed
+    for (uint64_t h = hits; h; h &= h - 1) {
+      const int j = (int)__builtin_ctzll(h);
+      const float wj = walk_one(q0, q1, j, s);
       const uint64_t msk = __ballot(wj > 0.0f);
       if (msk) {
-        anyw |= 1u << j;
-        const float ws = wave_sum(wj);
-        if (lane == j) {
-          my_ws = ws;
-          my_cnt = (uint32_t)__popcll(msk);
+        covered |= msk;
+        ncontrib += (uint32_t)__popcll(msk);
+        Wt[queued * kWtPitch + lane] = wj;
+        const uint32_t gj = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
+        if (lane == queued) {
+          ring_gid = gj;
+          ring_cnt = (uint32_t)__popcll(msk);
         }
-        if (has_main) {
-          const int row = (head + queued) & 63;
-          Wt[row * kWtPitch + lane] = wj;
-          const uint32_t gj = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-          if (lane == row) ring_gid = gj;
-          if (queued < 32) pix_cur |= msk;
-          else pix_next |= msk;
-          queued++;
-        }
-        if (any_tail) {
-          const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-#pragma unroll
-          for (int t = 0; t < kMaxTail; t++) {
-            if (t < ntail && tout[t]) {
-              const float at = wave_sum(wj * ft[t]);
-              if (lane == 0 && at != 0.0f) gatomic_add(tout[t] + gid * tD[t], at);
-            }
-          }
+        pix |= msk;
+        if (++queued == 32) {
+          flush(32);
+          queued = 0;
+          pix = 0ull;
         }
       }
-    });
-    if (lane < G && ((anyw >> lane) & 1u)) {  // lanes j < 32 whose Gaussian contributed
-      for (int b = bsets; b; b &= b - 1) {
-        const SetDesc& sd = sets[__builtin_ctz(b)];
-        beta_atomic_add(sd.beta + my_id, my_ws);
-        if (sd.counts) gatomic_add(sd.counts + my_id, my_cnt);
-      }
-    }
-    if (queued >= 32) {  // a full batch
-      flush(32, pix_cur);
-      head = (head + 32) & 63;
-      queued -= 32;
-      pix_cur = pix_next;
-      pix_next = 0ull;
     }
   }
-  if (queued > 0) flush(queued, pix_cur);
+  if (queued > 0) flush(queued);
   // statistics go to every set whose beta this work item takes for this view
   for (int b = bsets; b; b &= b - 1) {
     const SetDesc& sd = sets[__builtin_ctz(b)];
-    if (sd.stats) quad_stats(s, lane, sd.stats);
-  }
-}
-
-// --------------------------------------------------------------- small kernel
-// One feature set with D <= 32 channels: 64/DG pixel slots of DG channels.
-template <lv_dtype DT, int DG>
-__global__ __launch_bounds__(64) void blend_small_kernel(
-    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
-    const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
-    const SetDesc* __restrict__ sets) {
-  constexpr int G = kChunk;
-  constexpr int SLOTS = 64 / DG;
-  extern __shared__ float Fs[];  // [64][DG], pixel-major
-  Quad q;
-  if (!decode_quad(ranges, geom, tiles_stride, nviews, 1, q)) return;
-  const int lane = threadIdx.x;
-  const SetDesc& sd = sets[0];
-  const int D = sd.D, ld = sd.stride;
-  const void* map = map_of(sd, q.v);
-  if (!map) return;  // the set does not take this view
-  for (int e = lane; e < 64 * DG; e += 64) {
-    const int p = e / DG, c = e - p * DG;
-    const int gx = q.qx + (p & 7), gy = q.qy + (p >> 3);
-    float val = 0.0f;
-    if (c < D && gx < q.g.W && gy < q.g.H) {
-      float sc = 1.0f;
-      if constexpr (DT == LV_FP8_E4M3) sc = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * D + c];
-      val = load_feature<DT>(map, ((int64_t)gy * q.g.W + gx) * ld + c, sc);
-    }
-    Fs[e] = val;
-  }
-  __syncthreads();
-  const int slot = lane / DG, ch = lane - slot * DG;
-  const float* fbase = Fs + ch;
-  uint64_t sel = 0ull;
-#pragma unroll
-  for (int k = 0; k < 64; k += SLOTS) sel |= 1ull << k;
-  sel <<= slot;  // slot s takes the pixels p = s (mod SLOTS)
-
-  Walk s;
-  walk_init(q, lane, s);
-  const Rec* vrec = rec + (int64_t)q.v * n;
-  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
-    if (__ballot(s.alive) == 0ull) break;
-    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
-    float4 q0, q1;
-    uint32_t my_id;
-    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
-    float wv[G];
-    step_walk<G>(hits, q0, q1, s, wv);
-    float my_ws = 0.0f;
-    uint32_t my_cnt = 0u;
-    bool mine = false;
-
-#pragma unroll
-    for (int j = 0; j < G; j++) {
-      if ((hits >> j) & 1ull) {
-        const uint64_t msk = __ballot(wv[j] > 0.0f);
-        if (msk) {
-          float acc = 0.0f, wsl = 0.0f;
-          uint64_t mm = msk & sel;
-          while (__ballot(mm != 0ull)) {
-            const bool has = mm != 0ull;
-            const int l = has ? (int)__builtin_ctzll(mm) : 0;
-            if (has) mm &= mm - 1ull;
-            const float wl = __shfl(wv[j], l, 64);  // every lane takes part
-            if (has) {
-              acc = __builtin_fmaf(wl, fbase[l * DG], acc);
-              wsl += wl;
-            }
-          }
-#pragma unroll
-          for (int o = DG; o < 64; o <<= 1) {
-            acc += __shfl_down(acc, o, 64);
-            wsl += __shfl_down(wsl, o, 64);
-          }
-          const int64_t gid = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-          if (lane < D && acc != 0.0f) gatomic_add(&sd.U[gid * D + lane], acc);
-          const float ws = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wsl), 0));
-          if (lane == j) {
-            my_ws = ws;
-            my_cnt = (uint32_t)__popcll(msk);
-            mine = true;
-          }
-        }
-      }
-    }
-    // one round of weight-sum atomics per step (lane j: Gaussian j)
-    if (mine) {
-      beta_atomic_add(&sd.beta[my_id], my_ws);
-      if (sd.counts) gatomic_add(&sd.counts[my_id], my_cnt);
+    if (sd.stats && lane == 0) {
+      gatomic_add(&sd.stats[1], (unsigned long long)ncontrib);
+      gatomic_add(&sd.stats[0], (unsigned long long)__popcll(covered));
     }
   }
-  if (sd.stats) quad_stats(s, lane, sd.stats);
-}
-
-template <lv_dtype DT, int DG>
-hipError_t launch_small(const BlendArgs& a, int m, hipStream_t s) {
-  int64_t work = (int64_t)a.tiles_stride * m;
-  int64_t blocks = (work + 7) / 8 * 32;  // 4 quadrants per tile, whole rounds of 8 XCDs
-  hipLaunchKernelGGL((blend_small_kernel<DT, DG>), dim3((unsigned)blocks), dim3(64),
-                     sizeof(float) * 64 * DG, s, a.rec, a.ids, a.ranges, a.geom, a.n,
-                     a.tiles_stride, m, a.sets);
-  return hipGetLastError();
 }
 
 template <lv_dtype DT>
 hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
-  if (a.small_dg > 0) {
-    switch (a.small_dg) {
-      case 1: return launch_small<DT, 1>(a, m, s);
-      case 2: return launch_small<DT, 2>(a, m, s);
-      case 4: return launch_small<DT, 4>(a, m, s);
-      case 8: return launch_small<DT, 8>(a, m, s);
-      case 16: return launch_small<DT, 16>(a, m, s);
-      case 32: return launch_small<DT, 32>(a, m, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
   // one group: one wave per (view, quadrant, group); several: one wave per
   // (view, quadrant) for all groups, sharing the walk
   const bool multi = a.ngroups > 1;
@@ -805,7 +652,9 @@ __global__ __launch_bounds__(64) void render_kernel(
     float4 q0, q1;
     uint32_t my_id;
     const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, q0, q1, my_id);
-    step_walk_each<G>(hits, q0, q1, s, [&](const int j, const float wj) {
+    for (uint64_t h = hits; h; h &= h - 1) {
+      const int j = (int)__builtin_ctzll(h);
+      const float wj = walk_one(q0, q1, j, s);
       if (__ballot(wj > 0.0f)) {
         const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
         const float* fr = g + (int64_t)gid * D + c0;
@@ -816,7 +665,7 @@ __global__ __launch_bounds__(64) void render_kernel(
         }
         asum += wj;
       }
-    });
+    }
   }
   const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
   if (px < q.g.W && py < q.g.H) {

@@ -207,7 +207,6 @@ struct BlendArgs {
   const ChanGroup* groups;     // device (wide kernel)
   int32_t ngroups;
   int32_t max_width;           // widest group (LDS size)
-  int32_t small_dg;            // > 0: one set of D <= small_dg <= 32 on the small kernel
 };
 hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s);
 
