@@ -96,7 +96,8 @@ const char* lv_version(void);
  * opacity [n]: device FP32 arrays, read (not retained) by the call.  The
  * library derives the covariances R diag(s)^2 R^T and keeps its own copy
  * (48 bytes per Gaussian).  n = 0 is valid.  Errors: LV_ERR_INVALID_ARG
- * (null pointers with n > 0, n >= 2^31), LV_ERR_OUT_OF_MEMORY. */
+ * (null pointers with n > 0, n >= 2^28: the sorted tile lists keep a
+ * Gaussian id in 28 bits), LV_ERR_OUT_OF_MEMORY. */
 lv_status lv_scene_create(const float* means, const float* scales, const float* quats,
                           const float* opacity, int64_t n, void* stream, lv_scene** out);
 lv_status lv_scene_destroy(lv_scene* scene);
