@@ -265,6 +265,30 @@ def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
                        "mean": float(err.mean()), "bound": 2.0 ** -8 + 1e-4},
     }
     del enc, absmaps
+    # ---- weight-based filtering (keep the half with the largest beta) and
+    # the count-normalised finalize
+    log("bench: filtering leg")
+    k = n // 2
+    keep = lv.prune_by_weight(b64, k)
+    reps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        keep = lv.prune_by_weight(b64, k)
+    torch.cuda.synchronize()
+    t_prune = (time.perf_counter() - t0) / reps
+    acc = lv.Accum(s, D, counts=True)
+    acc.add(cams, maps)
+    fc = acc.finalize_count()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fc = acc.finalize_count()
+    torch.cuda.synchronize()
+    t_fc = (time.perf_counter() - t0) / reps
+    res["filtering"] = {"n": n, "kept": int(keep.sum()), "prune_ms": round(t_prune * 1e3, 4),
+                        "finalize_count_ms": round(t_fc * 1e3, 4)}
+    del acc, fc, keep
     # ---- diffusion over the 16-NN graph of the scene (graph built on the host)
     log("bench: diffusion leg (building the 16-NN graph on the host)")
     feats = f64.cpu().numpy()

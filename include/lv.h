@@ -171,6 +171,21 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
  * [n] (nullable); raw U into out_sum [n][D] (nullable). */
 lv_status lv_accum_finalize(lv_accum* acc, float* out_feat, float* out_wsum, float* out_sum,
                             void* stream);
+/* Count-normalised features (appendix, comparison with GaussianEditor's
+ * uplifting): f_i = U_i / c_i into out_feat [n][D], c_i the number of counted
+ * (view, pixel) pairs of Gaussian i instead of the sum of their weights; 0
+ * where c_i = 0.  The accumulator must have been created with
+ * LV_ACCUM_COUNTS (else LV_ERR_INVALID_ARG). */
+lv_status lv_accum_finalize_count(lv_accum* acc, float* out_feat, void* stream);
+/* Weight-based filtering (Sec. 3.2, Gaussian filtering): beta_i estimates
+ * the importance of Gaussian i; keep the k Gaussians with the largest
+ * wsum[i] (device FP32 [n], e.g. the out_wsum of lv_accum_finalize), ties to
+ * the lower index.  keep (device uint8 [n]) gets 1 for kept Gaussians and 0
+ * for the others.  Values are ordered as IEEE floats (-0 below +0).  Scratch
+ * (about 16 bytes per Gaussian) comes from the stream-ordered allocator.
+ * Errors: LV_ERR_INVALID_ARG (n < 0 or n >= 2^28, k outside [0, n], null
+ * buffers with n > 0), LV_ERR_DEVICE. */
+lv_status lv_prune_by_weight(const float* wsum, int64_t n, int64_t k, uint8_t* keep, void* stream);
 /* Per-Gaussian contribution counts (device uint32 [n]); the accumulator must
  * have been created with LV_ACCUM_COUNTS. */
 lv_status lv_accum_counts(lv_accum* acc, uint32_t* out_counts, void* stream);

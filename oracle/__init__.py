@@ -7,6 +7,7 @@ code with the GPU library (``paper_2410_14462_amd``) and never imports it.
 * ``lv_oracle.c``  -- uplift (Eq. 3 / Eq. 5) and forward render (Eq. 4), plain C,
   FP64 values, FP32 (S32) decisions; see its header for the conventions.
 * ``diffuse.py``    -- graph diffusion (Eq. 8) in FP64 on a CSR matrix.
+* ``prune.py``      -- weight-based Gaussian filtering (Sec. 3.2).
 """
 import ctypes
 import os
@@ -14,6 +15,8 @@ import subprocess
 from dataclasses import dataclass
 
 import numpy as np
+
+from . import prune  # noqa: F401  (oracle.prune)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lv_oracle.c")
@@ -90,6 +93,14 @@ class UpliftResult:
         b = self.beta[self.rows][:, None]
         with np.errstate(invalid="ignore", divide="ignore"):
             return np.where(b > 0, self.U / np.where(b > 0, b, 1.0), 0.0)
+
+    @property
+    def f_count(self):
+        """Count-normalised features (appendix, GaussianEditor's aggregation):
+        U / count, 0 where count == 0."""
+        c = self.count[self.rows][:, None].astype(np.float64)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            return np.where(c > 0, self.U / np.where(c > 0, c, 1.0), 0.0)
 
     @property
     def a(self):

@@ -96,6 +96,8 @@ def lib():
             "lv_uplift_accumulate": ([P, P, i32, P, i32, P, P], i32),
             "lv_accum_finalize": ([P, P, P, P, P], i32),
             "lv_accum_counts": ([P, P, P], i32),
+            "lv_accum_finalize_count": ([P, P, P], i32),
+            "lv_prune_by_weight": ([P, i64, i64, P, P], i32),
             "lv_accum_destroy": ([P], i32),
             "lv_encode": ([P, i64, i32, i32, P, P, P], i32),
             "lv_graph_create_csr": ([i64, i64, P, P, P, i32, P, ctypes.POINTER(P)], i32),
@@ -130,7 +132,8 @@ def exported_symbols():
             "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view",
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
             "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",
-            "lv_server_drain", "lv_server_stats_get", "lv_server_destroy"]
+            "lv_server_drain", "lv_server_stats_get", "lv_server_destroy", "lv_accum_finalize_count",
+            "lv_prune_by_weight"]
 
 
 def _check(status):
@@ -330,6 +333,24 @@ class Accum:
         c = torch.empty((self.scene.n,), device="cuda", dtype=torch.int32)
         _check(lib().lv_accum_counts(self.handle, _ptr(c), _stream()))
         return c
+
+    def finalize_count(self):
+        """lv_accum_finalize_count: f = U / count (needs counts=True)."""
+        import torch
+        f = torch.empty((self.scene.n, self.D), device="cuda", dtype=torch.float32)
+        _check(lib().lv_accum_finalize_count(self.handle, _ptr(f), _stream()))
+        return f
+
+
+def prune_by_weight(wsum, k):
+    """lv_prune_by_weight: uint8 mask [n] of the k Gaussians with the largest
+    wsum (device FP32 [n]), ties to the lower index."""
+    import torch
+    _dev_f32(wsum)
+    n = wsum.numel()
+    keep = torch.empty((n,), device="cuda", dtype=torch.uint8)
+    _check(lib().lv_prune_by_weight(_ptr(wsum), n, int(k), _ptr(keep), _stream()))
+    return keep
 
 
 def _slice_table(maps, dtype, D):

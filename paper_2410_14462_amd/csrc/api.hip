@@ -590,6 +590,23 @@ lv_status lv_accum_finalize(lv_accum* a, float* out_feat, float* out_wsum, float
   return LV_OK;
 }
 
+lv_status lv_accum_finalize_count(lv_accum* a, float* out_feat, void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");
+  if (a->scene->n > 0 && !out_feat) return fail(LV_ERR_INVALID_ARG, "out_feat is NULL");
+  HIP_TRY(launch_finalize_count(a->U.as<float>(), a->counts.as<uint32_t>(), a->scene->n, a->D,
+                                out_feat, static_cast<hipStream_t>(stream)));
+  return LV_OK;
+}
+
+lv_status lv_prune_by_weight(const float* wsum, int64_t n, int64_t k, uint8_t* keep, void* stream) {
+  if (n < 0 || n >= kMaxGaussians) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (k < 0 || k > n) return fail(LV_ERR_INVALID_ARG, "k = %lld not in [0, n = %lld]", (long long)k, (long long)n);
+  if (n > 0 && (!wsum || !keep)) return fail(LV_ERR_INVALID_ARG, "null buffer");
+  HIP_TRY(launch_prune(wsum, n, k, keep, static_cast<hipStream_t>(stream)));
+  return LV_OK;
+}
+
 lv_status lv_accum_counts(lv_accum* a, uint32_t* out, void* stream) {
   if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
   if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");

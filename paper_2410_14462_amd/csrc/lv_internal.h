@@ -282,6 +282,13 @@ hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s
 // be null); pixels of empty tiles are not written.
 hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float* const* outs,
                          float* const* alphas, hipStream_t s);
+// Keep the k Gaussians with the largest wsum (ties to the lower index):
+// keep[i] = 1 for them, 0 for the others (scratch from the stream-ordered
+// allocator).
+hipError_t launch_prune(const float* wsum, int64_t n, int64_t k, uint8_t* keep, hipStream_t s);
+// f = U / cnt per Gaussian (0 where cnt = 0).
+hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n, int D, float* f,
+                                 hipStream_t s);
 hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,
                            float* wsum, float* usum, hipStream_t s);
 

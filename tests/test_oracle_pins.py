@@ -390,3 +390,72 @@ def test_brute_force_tiny_scenes(seed):
     assert np.array_equal(r.count, cnt)
     assert np.allclose(r.beta, beta, rtol=1e-9, atol=1e-300)
     assert np.allclose(r.U, U, rtol=1e-9, atol=1e-12)
+
+
+# ------------------------------------------- count normalisation, filtering
+def test_count_normalised_single_gaussian():
+    """Appendix (GaussianEditor's aggregation): f = U / count, from the closed
+    form of one Gaussian; for a constant map it is c beta / count, smaller
+    than c because every weight is below 1."""
+    f, z0, s, op = 100.0, 4.0, 0.2, 0.7
+    cam = axis_camera(f, z0=z0)
+    sc = one_scene([0, 0, 0], [s, s, s], opacity=[op])
+    v = (f * float(F32(s)) / z0) ** 2 + float(F32(0.3))
+    tiles = tiles_for((64.5, 64.5), v, 129, 129)
+    F = philox.uniform(12, 1, 129 * 129 * 2).reshape(129, 129, 2).astype(np.float64)
+    beta, U, cnt, margin = single_closed_form(cam, (64.5, 64.5), v, v, op, tiles, F)
+    assert margin > 1e-4 and cnt > 10
+    r = oracle.uplift(sc, [cam], [F.astype(F32)])
+    assert np.allclose(r.f_count[0], U / cnt, rtol=1e-9, atol=0)
+    c = np.array([2.0, -1.0], F32)
+    rc = oracle.uplift(sc, [cam], [np.broadcast_to(c, (129, 129, 2))])
+    assert np.allclose(rc.f_count[0], c * beta / cnt, rtol=1e-9)
+    assert np.all(np.abs(rc.f_count[0]) < np.abs(c))
+
+
+def test_count_normalised_unseen_is_zero(tiny):
+    sc = one_scene([[0, 0, 0], [100, 0, 0]], [[0.2] * 3, [0.2] * 3])  # the second is out of frame
+    r = oracle.uplift(sc, [axis_camera(100.0)], [np.ones((129, 129, 2), F32)])
+    assert r.count[0] > 0 and r.count[1] == 0 and np.all(r.f_count[1] == 0)
+    sc, cams, maps = tiny
+    r = oracle.uplift(sc, cams, maps)
+    seen = r.count > 0
+    assert np.allclose(r.f_count[seen] * r.count[seen][:, None], r.U[seen], rtol=1e-12)
+
+
+def _brute_keep(values, k):
+    """Sorting (key, index) tuples in Python: the plain definition."""
+    import struct
+    def tot(x):  # IEEE totalOrder key of an FP32 value
+        b = struct.unpack("<I", struct.pack("<f", float(x)))[0]
+        return (0xFFFFFFFF - b) if b >> 31 else (b | 0x80000000)
+    order = sorted(range(len(values)), key=lambda i: (-tot(values[i]), i))
+    keep = np.zeros(len(values), np.uint8)
+    keep[order[:k]] = 1
+    return keep
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 64, 300])
+def test_prune_matches_brute_force(n):
+    rng = np.random.default_rng(n)
+    v = rng.choice(np.array([0.0, -0.0, 0.5, 1.5, 1e-30, 3.0, np.inf], F32), size=n).astype(F32)
+    v[: n // 3] = rng.random(n // 3).astype(F32)
+    for k in sorted({0, n // 2, n, min(n, 1), max(0, n - 1)}):
+        assert np.array_equal(oracle.prune.keep_top_k(v, k), _brute_keep(v, k)), (n, k)
+
+
+def test_prune_matches_library_sort_and_orders_signed_zero():
+    rng = np.random.default_rng(5)
+    v = np.round(rng.random(20000) * 300).astype(F32)  # many ties
+    k = 10000
+    order = np.argsort(-v.astype(np.float64), kind="stable")  # ties keep index order
+    ref = np.zeros(v.size, np.uint8)
+    ref[order[:k]] = 1
+    keep = oracle.prune.keep_top_k(v, k)
+    assert np.array_equal(keep, ref) and keep.sum() == k
+    assert v[keep == 1].min() >= v[keep == 0].max()
+    # totalOrder: +0 above -0, whatever their indices
+    z = np.array([-0.0, 0.0, -0.0, 0.0], F32)
+    assert np.array_equal(oracle.prune.keep_top_k(z, 2), np.array([0, 1, 0, 1], np.uint8))
+    with pytest.raises(ValueError):
+        oracle.prune.keep_top_k(z, 5)
