@@ -223,7 +223,6 @@ def measured_traffic():
 def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
     import numpy as np
     import torch
-    from synth import graph
 
     res = {}
     n, m, D = w.n, w.m, w.D
@@ -289,14 +288,18 @@ def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
     res["filtering"] = {"n": n, "kept": int(keep.sum()), "prune_ms": round(t_prune * 1e3, 4),
                         "finalize_count_ms": round(t_fc * 1e3, 4)}
     del acc, fc, keep
-    # ---- diffusion over the 16-NN graph of the scene (graph built on the host)
-    log("bench: diffusion leg (building the 16-NN graph on the host)")
-    feats = f64.cpu().numpy()
-    rp, col, val = graph.knn_graph(sc.means, feats, 16)
-    G = lv.Graph(torch.as_tensor(rp, device="cuda"), torch.as_tensor(col, device="cuda"),
-                 torch.as_tensor(val, device="cuda"))
-    nnz = int(col.shape[0])
-    dres = {"graph_nnz": nnz, "steps": 100}
+    # ---- diffusion over the 16-NN graph of the scene, built on the device
+    # from the uplifted features
+    log("bench: diffusion leg (16-NN graph built on the device)")
+    G = lv.Graph.knn(s, f64, 16)
+    G.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G = lv.Graph.knn(s, f64, 16)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    nnz = int(G.csr()[1].shape[0])
+    dres = {"graph_nnz": nnz, "graph_build_ms": round(t_graph * 1e3, 3), "steps": 100}
     # with the scene: rows in the Morton order of the centres (built on the
     # first call); without: the caller's order
     for name, g0, scene in (("D1", f1.contiguous(), s), ("D64", f64, s),

@@ -228,6 +228,30 @@ lv_status lv_graph_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, co
                               const void* val, lv_dtype val_dtype, void* stream, lv_graph** out);
 lv_status lv_graph_destroy(lv_graph* graph);
 
+/* The diffusion graph built on the device (Sec. 3.3: a weighted graph
+ * joining each Gaussian to its spatial neighbours, symmetrised by the union
+ * of the directed kNN pairs).  Each centre of the scene is joined to its k
+ * nearest other centres, ordered by (squared distance, index) with squared
+ * distances in FP64 as ((dx dx + dy dy) + dz dz) of the FP32 centres; a
+ * pair's weight is exp(-|x_i - x_j|^2 / sigma^2) * max(0, cos(f_i, f_j))
+ * (FP64), sigma the median of the n k directed distances, the larger
+ * directed weight where both directions exist; the union pairs with a
+ * positive weight are stored, columns ascending; rows are normalised to sum
+ * 1 (FP32 values) and a row without any gets a self-loop of weight 1.
+ * feats: device FP32 [n][D] (e.g. uplifted features).  Scratch (about
+ * 60 + 36 k bytes per Gaussian) comes from the stream-ordered allocator; the
+ * call synchronises the stream once (to size the CSR).  Errors:
+ * LV_ERR_INVALID_ARG (k outside [1, 32], D outside [1, 4096], n <= k, null
+ * pointers), LV_ERR_UNSUPPORTED (n (2k + 1) >= 2^31), LV_ERR_OUT_OF_MEMORY,
+ * LV_ERR_DEVICE. */
+lv_status lv_graph_build_knn(lv_scene* scene, const float* feats, int32_t D, int32_t k, void* stream,
+                             lv_graph** out);
+/* Size of a graph (n, nnz: nullable) and, where the pointers are not NULL,
+ * copies of its CSR arrays into caller device buffers (row_ptr [n+1], col
+ * [nnz] int32, val [nnz] of the graph's value dtype), on the stream. */
+lv_status lv_graph_csr(const lv_graph* graph, int64_t* n, int64_t* nnz, int32_t* row_ptr, int32_t* col,
+                       void* val, void* stream);
+
 /* Eq. (8): `steps` diffusion steps g_{t+1} = A (g_t / ||g_t||_2), each of the
  * D channels normalised by its own norm (a zero-norm channel stays 0).
  * g0 and out are device [n][D] of dtype (LV_F32 or LV_BF16; sums and norms

@@ -8,6 +8,7 @@ code with the GPU library (``paper_2410_14462_amd``) and never imports it.
   FP64 values, FP32 (S32) decisions; see its header for the conventions.
 * ``diffuse.py``    -- graph diffusion (Eq. 8) in FP64 on a CSR matrix.
 * ``prune.py``      -- weight-based Gaussian filtering (Sec. 3.2).
+* ``graph.py``      -- the kNN diffusion graph over the centres (Sec. 3.3).
 """
 import ctypes
 import os
@@ -16,7 +17,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import prune  # noqa: F401  (oracle.prune)
+from . import graph, prune  # noqa: F401  (oracle.graph, oracle.prune)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lv_oracle.c")

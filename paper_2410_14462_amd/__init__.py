@@ -98,6 +98,8 @@ def lib():
             "lv_accum_counts": ([P, P, P], i32),
             "lv_accum_finalize_count": ([P, P, P], i32),
             "lv_prune_by_weight": ([P, i64, i64, P, P], i32),
+            "lv_graph_build_knn": ([P, P, i32, i32, P, ctypes.POINTER(P)], i32),
+            "lv_graph_csr": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64), P, P, P, P], i32),
             "lv_accum_destroy": ([P], i32),
             "lv_encode": ([P, i64, i32, i32, P, P, P], i32),
             "lv_graph_create_csr": ([i64, i64, P, P, P, i32, P, ctypes.POINTER(P)], i32),
@@ -133,7 +135,7 @@ def exported_symbols():
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
             "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",
             "lv_server_drain", "lv_server_stats_get", "lv_server_destroy", "lv_accum_finalize_count",
-            "lv_prune_by_weight"]
+            "lv_prune_by_weight", "lv_graph_build_knn", "lv_graph_csr"]
 
 
 def _check(status):
@@ -445,7 +447,31 @@ class Graph:
         h = ctypes.c_void_p()
         _check(lib().lv_graph_create_csr(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), dt, _stream(),
                                          ctypes.byref(h)))
-        self.handle, self.n = h, n
+        self.handle, self.n, self.dtype = h, n, dt
+
+    @classmethod
+    def knn(cls, scene, feats, k=16):
+        """lv_graph_build_knn: the kNN diffusion graph over the scene's centres
+        with feature weights (feats [n, D] float32 on the device)."""
+        _dev_f32(feats)
+        D = 1 if feats.dim() == 1 else feats.shape[1]
+        h = ctypes.c_void_p()
+        _check(lib().lv_graph_build_knn(scene.handle, _ptr(feats), D, int(k), _stream(), ctypes.byref(h)))
+        g = cls.__new__(cls)
+        g.handle, g.n, g.dtype = h, scene.n, LV_F32
+        return g
+
+    def csr(self):
+        """(row_ptr int32 [n+1], col int32 [nnz], val [nnz]) copies on the device."""
+        import torch
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lv_graph_csr(self.handle, ctypes.byref(n), ctypes.byref(nnz), None, None, None, _stream()))
+        rp = torch.empty((n.value + 1,), device="cuda", dtype=torch.int32)
+        col = torch.empty((nnz.value,), device="cuda", dtype=torch.int32)
+        val = torch.empty((nnz.value,), device="cuda",
+                          dtype=torch.bfloat16 if self.dtype == LV_BF16 else torch.float32)
+        _check(lib().lv_graph_csr(self.handle, None, None, _ptr(rp), _ptr(col), _ptr(val), _stream()))
+        return rp, col, val
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

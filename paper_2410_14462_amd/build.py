@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["geometry.hip", "sort.hip", "blend.hip", "codec.hip", "diffuse.hip", "prune.hip", "api.hip",
-           "serve.hip"]
+SOURCES = ["geometry.hip", "sort.hip", "blend.hip", "codec.hip", "diffuse.hip", "prune.hip", "graph.hip",
+           "api.hip", "serve.hip"]
 LIB = os.path.join(HERE, "liblv.so")
 
 FLAGS = [

@@ -781,6 +781,50 @@ lv_status lv_graph_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, co
   return LV_OK;
 }
 
+lv_status lv_graph_build_knn(lv_scene* sc, const float* feats, int32_t D, int32_t k, void* stream,
+                             lv_graph** out) {
+  if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sc || !feats) return fail(LV_ERR_INVALID_ARG, "null argument");
+  if (k < 1 || k > 32) return fail(LV_ERR_INVALID_ARG, "k = %d not in [1, 32]", k);
+  if (D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "D = %d not in [1, 4096]", D);
+  const int64_t n = sc->n;
+  if (n <= k) return fail(LV_ERR_INVALID_ARG, "n = %lld must exceed k = %d", (long long)n, k);
+  if (n * (int64_t)(2 * k + 1) >= ((int64_t)1 << 31))
+    return fail(LV_ERR_UNSUPPORTED, "n (2k + 1) = %lld >= 2^31", (long long)(n * (2 * k + 1)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t *rp = nullptr, *cl = nullptr;
+  float* vl = nullptr;
+  int64_t nnz = 0;
+  HIP_TRY(build_knn_graph(sc->p0.as<float4>(), n, feats, D, k, s, &rp, &cl, &vl, &nnz));
+  lv_graph* g = new (std::nothrow) lv_graph();
+  if (!g) {
+    (void)hipFree(rp); (void)hipFree(cl); (void)hipFree(vl);
+    return fail(LV_ERR_OUT_OF_MEMORY, "host allocation");
+  }
+  g->n = n;
+  g->nnz = nnz;
+  g->val_dtype = LV_F32;
+  g->row_ptr.p = rp; g->row_ptr.cap = 4 * (size_t)(n + 1);
+  g->col.p = cl; g->col.cap = 4 * (size_t)(nnz + 1);
+  g->val.p = vl; g->val.cap = 4 * (size_t)(nnz + 1);
+  *out = g;
+  return LV_OK;
+}
+
+lv_status lv_graph_csr(const lv_graph* g, int64_t* n, int64_t* nnz, int32_t* row_ptr, int32_t* col,
+                       void* val, void* stream) {
+  if (!g) return fail(LV_ERR_INVALID_ARG, "graph is NULL");
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (row_ptr) HIP_TRY(hipMemcpyAsync(row_ptr, g->row_ptr.p, 4 * (size_t)(g->n + 1), hipMemcpyDeviceToDevice, s));
+  if (col && g->nnz) HIP_TRY(hipMemcpyAsync(col, g->col.p, 4 * (size_t)g->nnz, hipMemcpyDeviceToDevice, s));
+  if (val && g->nnz)
+    HIP_TRY(hipMemcpyAsync(val, g->val.p, dtype_size(g->val_dtype) * (size_t)g->nnz, hipMemcpyDeviceToDevice, s));
+  return LV_OK;
+}
+
 lv_status lv_graph_destroy(lv_graph* g) {
   if (!g) return LV_OK;
   (void)hipDeviceSynchronize();

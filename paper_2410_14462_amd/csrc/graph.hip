@@ -1,0 +1,543 @@
+// The diffusion graph over the Gaussian centres, built on the device
+// (Sec. 3.3: diffusion runs on a weighted graph joining each Gaussian to its
+// spatial neighbours; the relation is symmetrised by the union of the
+// directed kNN pairs).  Weight of a pair: exp(-|x_i - x_j|^2 / sigma^2) *
+// max(0, cos(f_i, f_j)), sigma the median directed kNN distance, the larger
+// directed weight where both exist; rows normalised to sum 1, a row whose
+// weights are all 0 gets a self-loop of weight 1.
+//
+// Reproducible structure: squared distances in FP64 as ((dx dx + dy dy) +
+// dz dz) of the FP32 centres, neighbours ordered by (squared distance,
+// index); the union pairs with a positive FP64 weight are stored, columns
+// ascending; a self-loop is the only entry of its row.
+//
+// Steps: bounding box; uniform grid (about two centres per cell), centres
+// sorted by cell; exact kNN by shells of cells around each centre until the
+// k-th distance is below the distance to the next shell; sigma from the two
+// middle order statistics of the n k squared distances (radix select on
+// their bits); per-node feature norms and per-edge weights (one wave per
+// node, lanes over channels); union rows (own k entries plus the reversed
+// edges, placed with atomics, then sorted by column in each row and merged
+// with max), row sums in column order, normalisation into the CSR.
+#include "lv_internal.h"
+
+namespace lv {
+
+namespace {
+
+constexpr int kGraphMaxK = 32;
+
+// ---------------------------------------------------------------- grid
+__global__ void bbox_partial_kernel(const float4* __restrict__ c, int64_t n, float* __restrict__ part) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 p = c[i];
+    lo[0] = fminf(lo[0], p.x); hi[0] = fmaxf(hi[0], p.x);
+    lo[1] = fminf(lo[1], p.y); hi[1] = fmaxf(hi[1], p.y);
+    lo[2] = fminf(lo[2], p.z); hi[2] = fmaxf(hi[2], p.z);
+  }
+  __shared__ float red[6][256];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    red[a][threadIdx.x] = lo[a];
+    red[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + o]);
+        red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// grid parameters: gp[0..2] = box minimum, gp[3..5] = cells per unit length
+// (0 for a flat axis), gp[6..8] = cell edge lengths
+__global__ void grid_params_kernel(const float* __restrict__ part, int nparts, int G, float* __restrict__ gp) {
+  if (threadIdx.x != 0) return;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < nparts; b++)
+    for (int a = 0; a < 3; a++) {
+      lo[a] = fminf(lo[a], part[6 * b + a]);
+      hi[a] = fmaxf(hi[a], part[6 * b + 3 + a]);
+    }
+  for (int a = 0; a < 3; a++) {
+    const float ext = hi[a] - lo[a];
+    gp[a] = lo[a];
+    gp[3 + a] = ext > 0.0f ? (float)G / ext : 0.0f;
+    gp[6 + a] = ext > 0.0f ? ext / (float)G : 0.0f;
+  }
+}
+
+__device__ __forceinline__ int cell_coord(float x, float lo, float inv, int G) {
+  const int c = (int)floorf((x - lo) * inv);
+  return c < 0 ? 0 : (c >= G ? G - 1 : c);
+}
+
+__global__ void cell_keys_kernel(const float4* __restrict__ c, int64_t n, const float* __restrict__ gp,
+                                 int G, uint32_t* __restrict__ key, uint32_t* __restrict__ id) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 p = c[i];
+  const int cx = cell_coord(p.x, gp[0], gp[3], G), cy = cell_coord(p.y, gp[1], gp[4], G),
+            cz = cell_coord(p.z, gp[2], gp[5], G);
+  key[i] = ((uint32_t)cz * (uint32_t)G + (uint32_t)cy) * (uint32_t)G + (uint32_t)cx;
+  id[i] = (uint32_t)i;
+}
+
+// cell ranges [start, end) from the sorted keys (cells without centres keep
+// start = end = 0 from the fill)
+__global__ void cell_ranges_kernel(const uint32_t* __restrict__ key, int64_t n,
+                                   uint32_t* __restrict__ start, uint32_t* __restrict__ end) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = key[i];
+  if (i == 0 || key[i - 1] != k) start[k] = (uint32_t)i;
+  if (i + 1 == n || key[i + 1] != k) end[k] = (uint32_t)(i + 1);
+}
+
+// (d, j) < (bd, bj) in the (squared distance, index) order
+__device__ __forceinline__ bool closer(double d, uint32_t j, double bd, uint32_t bj) {
+  return d < bd || (d == bd && j < bj);
+}
+
+// Exact kNN of the centre at sorted position p: shells of cells at Chebyshev
+// distance r = 0, 1, 2, ... around its cell; after shell r every centre not
+// yet seen is at least (r - 0.001) min(cell edge) away (0.001 of a cell
+// covers the rounding of the cell assignment), so the search stops once K
+// candidates are held and the k-th is strictly closer than that.
+template <int K>
+__global__ __launch_bounds__(256) void knn_kernel(const float4* __restrict__ c, int64_t n,
+                                                  const uint32_t* __restrict__ sorted_id,
+                                                  const uint32_t* __restrict__ cstart,
+                                                  const uint32_t* __restrict__ cend,
+                                                  const float* __restrict__ gp, int G, int k,
+                                                  int32_t* __restrict__ out_idx,
+                                                  double* __restrict__ out_d2) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t i = sorted_id[p];
+  const float4 pi = c[i];
+  const double xi = pi.x, yi = pi.y, zi = pi.z;
+  const int cx = cell_coord(pi.x, gp[0], gp[3], G), cy = cell_coord(pi.y, gp[1], gp[4], G),
+            cz = cell_coord(pi.z, gp[2], gp[5], G);
+  float hmin = INFINITY;
+  for (int a = 0; a < 3; a++)
+    if (gp[6 + a] > 0.0f) hmin = fminf(hmin, gp[6 + a]);
+  if (!(hmin < INFINITY)) hmin = 0.0f;  // all centres equal: every shell is empty but the first
+  double bd[K];
+  uint32_t bj[K];
+#pragma unroll
+  for (int t = 0; t < K; t++) {
+    bd[t] = INFINITY;
+    bj[t] = 0xFFFFFFFFu;
+  }
+  for (int r = 0; r < G; r++) {
+    for (int dz = -r; dz <= r; dz++) {
+      const int z = cz + dz;
+      if (z < 0 || z >= G) continue;
+      for (int dy = -r; dy <= r; dy++) {
+        const int y = cy + dy;
+        if (y < 0 || y >= G) continue;
+        const bool face = dz == -r || dz == r || dy == -r || dy == r;
+        const int step = face ? 1 : (2 * r > 0 ? 2 * r : 1);  // inside: only dx = +-r
+        for (int dx = -r; dx <= r; dx += step) {
+          const int x = cx + dx;
+          if (x < 0 || x >= G) continue;
+          const uint32_t cell = ((uint32_t)z * (uint32_t)G + (uint32_t)y) * (uint32_t)G + (uint32_t)x;
+          const uint32_t q1 = cend[cell];
+          for (uint32_t q = cstart[cell]; q < q1; q++) {
+            const uint32_t j = sorted_id[q];
+            if (j == i) continue;
+            const float4 pj = c[j];
+            const double ex = xi - (double)pj.x, ey = yi - (double)pj.y, ez = zi - (double)pj.z;
+            double d = (ex * ex + ey * ey) + ez * ez;
+            uint32_t jj = j;
+            if (!closer(d, jj, bd[K - 1], bj[K - 1])) continue;
+#pragma unroll
+            for (int t = 0; t < K; t++) {  // insert, keeping the list sorted
+              if (closer(d, jj, bd[t], bj[t])) {
+                const double td = bd[t];
+                const uint32_t tj = bj[t];
+                bd[t] = d;
+                bj[t] = jj;
+                d = td;
+                jj = tj;
+              }
+            }
+          }
+        }
+      }
+    }
+    double kth = INFINITY;
+#pragma unroll
+    for (int t = 0; t < K; t++)
+      if (t == k - 1) kth = bd[t];
+    const double gap = (double)(r - 0.001) * (double)hmin;
+    if (kth < INFINITY && r > 0 && kth < gap * gap) break;
+  }
+#pragma unroll
+  for (int t = 0; t < K; t++)
+    if (t < k) {
+      out_idx[(int64_t)i * k + t] = (int32_t)bj[t];
+      out_d2[(int64_t)i * k + t] = bd[t];
+    }
+}
+
+// ---------------------------------------------------- median (radix select)
+// Two order statistics (ranks rk[0], rk[1]) of N non-negative doubles, by
+// their bits, 11 bits per round from the top.  st: prefix[2], rank[2]
+// (uint64), advanced by the pick kernel after each round.
+constexpr int kSelBins = 2048;
+
+__global__ void select_hist_kernel(const double* __restrict__ v, int64_t N, int shift, int width,
+                                   const unsigned long long* __restrict__ st,
+                                   unsigned int* __restrict__ hist) {
+  __shared__ unsigned int h[2][kSelBins];
+  for (int e = threadIdx.x; e < 2 * kSelBins; e += blockDim.x) (&h[0][0])[e] = 0u;
+  __syncthreads();
+  const int top = shift + width;
+  const unsigned long long p0 = top >= 64 ? 0ull : st[0] >> top, p1 = top >= 64 ? 0ull : st[1] >> top;
+  const unsigned long long mask = (1ull << width) - 1ull;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v[e]);
+    const unsigned long long hb = top >= 64 ? 0ull : b >> top;
+    const unsigned int d = (unsigned int)((b >> shift) & mask);
+    if (hb == p0) atomicAdd(&h[0][d], 1u);
+    if (hb == p1) atomicAdd(&h[1][d], 1u);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * kSelBins; e += blockDim.x) {
+    const unsigned int x = (&h[0][0])[e];
+    if (x) atomicAdd(&hist[e], x);
+  }
+}
+
+// one block of 1024 threads: for each target, the digit whose cumulative
+// count passes the residual rank; the histogram is cleared for the next round
+__global__ __launch_bounds__(1024) void select_pick_kernel(unsigned int* __restrict__ hist, int shift,
+                                                           unsigned long long* __restrict__ st) {
+  __shared__ unsigned long long cum[2][kSelBins + 1];
+  const int t = threadIdx.x;
+  if (t < 2) {
+    unsigned long long run = 0;
+    for (int d = 0; d < kSelBins; d++) {
+      cum[t][d] = run;
+      run += hist[t * kSelBins + d];
+    }
+    cum[t][kSelBins] = run;
+    const unsigned long long rank = st[2 + t];
+    int dd = kSelBins - 1;
+    for (int d = 0; d < kSelBins; d++)
+      if (rank < cum[t][d + 1]) {
+        dd = d;
+        break;
+      }
+    st[t] |= (unsigned long long)dd << shift;
+    st[2 + t] = rank - cum[t][dd];
+  }
+  __syncthreads();
+  for (int e = t; e < 2 * kSelBins; e += blockDim.x) hist[e] = 0u;
+}
+
+__global__ void select_init_kernel(unsigned long long* st, unsigned long long r0, unsigned long long r1,
+                                   unsigned int* hist) {
+  if (threadIdx.x == 0) {
+    st[0] = 0ull;
+    st[1] = 0ull;
+    st[2] = r0;
+    st[3] = r1;
+  }
+  for (int e = threadIdx.x; e < 2 * kSelBins; e += blockDim.x) hist[e] = 0u;
+}
+
+// sigma^2 from the two middle squared distances (their roots averaged)
+__global__ void sigma_kernel(const unsigned long long* st, double* sig2) {
+  if (threadIdx.x != 0) return;
+  const double a = __longlong_as_double((long long)st[0]), b = __longlong_as_double((long long)st[1]);
+  const double s = (sqrt(a) + sqrt(b)) / 2.0;
+  sig2[0] = s * s;
+}
+
+// ------------------------------------------------------------ edge weights
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// one wave per node: norms first (a pass of their own), then each edge's
+// dot product with lanes over channels
+__global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ f, int64_t n, int D,
+                                                    double* __restrict__ nrm) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int ch = lane; ch < D; ch += 64) {
+    const double x = f[i * D + ch];
+    s += x * x;
+  }
+  s = wave_sum_f64(s);
+  if (lane == 0) nrm[i] = sqrt(s);
+}
+
+__global__ __launch_bounds__(256) void edge_weights_kernel(const float* __restrict__ f, int64_t n, int D,
+                                                           int k, const int32_t* __restrict__ idx,
+                                                           const double* __restrict__ d2,
+                                                           const double* __restrict__ nrm,
+                                                           const double* __restrict__ sig2,
+                                                           double* __restrict__ w) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const double s2 = sig2[0];
+  for (int t = 0; t < k; t++) {
+    const int64_t j = idx[i * k + t];
+    double dot = 0.0;
+    for (int ch = lane; ch < D; ch += 64) dot += (double)f[i * D + ch] * (double)f[j * D + ch];
+    dot = wave_sum_f64(dot);
+    if (lane == 0) {
+      const double den = nrm[i] * nrm[j];
+      const double cs = den > 0.0 ? dot / den : 0.0;
+      w[i * k + t] = exp(-d2[i * k + t] / s2) * (cs > 0.0 ? cs : 0.0);
+    }
+  }
+}
+
+// ------------------------------------------------------------ union rows
+__global__ void indeg_kernel(const int32_t* __restrict__ idx, int64_t nk, uint32_t* __restrict__ indeg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nk) atomicAdd(&indeg[idx[e]], 1u);
+}
+
+__global__ void row_cap_kernel(const uint32_t* __restrict__ indeg, int64_t n, int k,
+                               uint32_t* __restrict__ cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cap[i] = (uint32_t)k + indeg[i] + 1u;  // own, reversed, a possible self-loop
+}
+
+// row i: its own k entries first, then the reversed edges of the nodes that
+// chose i (in arrival order; sorted afterwards)
+__global__ void fill_rows_kernel(const int32_t* __restrict__ idx, const double* __restrict__ w,
+                                 int64_t n, int k, const uint32_t* __restrict__ start,
+                                 uint32_t* __restrict__ fillpos, int32_t* __restrict__ ucol,
+                                 double* __restrict__ uw) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t i = e / k;
+  const int t = (int)(e - i * k);
+  const int32_t j = idx[e];
+  ucol[start[i] + t] = j;
+  uw[start[i] + t] = w[e];
+  const uint32_t slot = atomicAdd(&fillpos[j], 1u);
+  ucol[start[j] + (uint32_t)k + slot] = (int32_t)i;
+  uw[start[j] + (uint32_t)k + slot] = w[e];
+}
+
+// per row: sort by column (ties: larger weight first), keep one entry per
+// column with the larger weight if it is positive, sum in column order; a
+// row left empty gets the self-loop (weight 1).  len[i] = entries kept.
+__global__ void merge_rows_kernel(int64_t n, int k, const uint32_t* __restrict__ start,
+                                  const uint32_t* __restrict__ indeg, int32_t* __restrict__ ucol,
+                                  double* __restrict__ uw, uint32_t* __restrict__ len,
+                                  double* __restrict__ rsum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t* cl = ucol + start[i];
+  double* wv = uw + start[i];
+  const int m = k + (int)indeg[i];
+  for (int a = 1; a < m; a++) {  // insertion sort (rows hold tens of entries)
+    const int32_t c = cl[a];
+    const double x = wv[a];
+    int b = a - 1;
+    while (b >= 0 && (cl[b] > c || (cl[b] == c && wv[b] < x))) {
+      cl[b + 1] = cl[b];
+      wv[b + 1] = wv[b];
+      b--;
+    }
+    cl[b + 1] = c;
+    wv[b + 1] = x;
+  }
+  int u = 0;
+  double s = 0.0;
+  int32_t last = -1;
+  for (int a = 0; a < m; a++) {
+    if (cl[a] == last) continue;  // the first of a column has the larger weight
+    last = cl[a];
+    if (!(wv[a] > 0.0)) continue;
+    cl[u] = cl[a];
+    wv[u] = wv[a];
+    s += wv[u];
+    u++;
+  }
+  if (u == 0) {  // self-loop
+    cl[0] = (int32_t)i;
+    wv[0] = 1.0;
+    u = 1;
+    s = 1.0;
+  }
+  len[i] = (uint32_t)u;
+  rsum[i] = s;
+}
+
+__global__ void csr_out_kernel(int64_t n, const uint32_t* __restrict__ start,
+                               const uint32_t* __restrict__ len, const uint32_t* __restrict__ rp,
+                               const int32_t* __restrict__ ucol, const double* __restrict__ uw,
+                               const double* __restrict__ rsum, int32_t* __restrict__ col,
+                               float* __restrict__ val, int32_t* __restrict__ row_ptr, uint64_t nnz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t a = start[i], o = rp[i], m = len[i];
+  const double s = rsum[i];
+  for (uint32_t q = 0; q < m; q++) {
+    col[o + q] = ucol[a + q];
+    val[o + q] = (float)(uw[a + q] / s);
+  }
+  row_ptr[i] = (int32_t)o;
+  if (i == n - 1) row_ptr[n] = (int32_t)nnz;
+}
+
+__global__ void one_segment_kernel(uint32_t* seg, int64_t n) {
+  if (threadIdx.x == 0) {
+    seg[0] = 0u;
+    seg[1] = (uint32_t)n;
+  }
+}
+
+unsigned grid1(int64_t items) { return (unsigned)((items + 255) / 256); }
+
+}  // namespace
+
+hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats, int D, int k,
+                           hipStream_t s, int32_t** row_ptr, int32_t** col, float** val,
+                           int64_t* nnz_out) {
+  *row_ptr = nullptr;
+  *col = nullptr;
+  *val = nullptr;
+  *nnz_out = 0;
+  const int64_t nk = n * (int64_t)k;
+  const int64_t ucap = n * (int64_t)(2 * k + 1);  // union entries before merging
+  // grid: about two centres per cell
+  int G = 1;
+  while ((int64_t)(G + 1) * (G + 1) * (G + 1) * 2 <= n && G < 1024) G++;
+  const int64_t cells = (int64_t)G * G * G;
+  int cell_bits = 0;
+  while (((int64_t)1 << cell_bits) < cells) cell_bits++;
+  const int nparts = (int)std::min<int64_t>(1024, (n + 255) / 256);
+
+  // scratch layout (bytes), from the stream-ordered allocator
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+  const size_t o_part = take(4 * 6 * (size_t)nparts), o_gp = take(4 * 9);
+  const size_t o_k0 = take(4 * (size_t)n), o_v0 = take(4 * (size_t)n), o_k1 = take(4 * (size_t)n),
+               o_v1 = take(4 * (size_t)n), o_seg = take(8), o_hist = take(4 * sort_hist_size(1, n));
+  const size_t o_cs = take(4 * (size_t)cells), o_ce = take(4 * (size_t)cells);
+  const size_t o_idx = take(4 * (size_t)nk), o_d2 = take(8 * (size_t)nk), o_w = take(8 * (size_t)nk);
+  const size_t o_st = take(8 * 4), o_shist = take(4 * 2 * kSelBins), o_sig = take(8),
+               o_nrm = take(8 * (size_t)n);
+  const size_t o_indeg = take(4 * (size_t)n), o_cap = take(4 * (size_t)n), o_start = take(4 * (size_t)n),
+               o_fill = take(4 * (size_t)n), o_len = take(4 * (size_t)n), o_rp = take(4 * (size_t)n),
+               o_rsum = take(8 * (size_t)n);
+  const size_t o_ucol = take(4 * (size_t)ucap), o_uw = take(8 * (size_t)ucap);
+  const size_t o_sseg = take(8), o_tot = take(16), o_stmp = take(4 * scan_tmp_size(n));
+  char* base = nullptr;
+  hipError_t e = hipMallocAsync((void**)&base, off, s);
+  if (e != hipSuccess) return e;
+  auto at = [&](size_t o) { return base + o; };
+  float* part = (float*)at(o_part);
+  float* gp = (float*)at(o_gp);
+  uint32_t *k0 = (uint32_t*)at(o_k0), *v0 = (uint32_t*)at(o_v0), *k1 = (uint32_t*)at(o_k1),
+           *v1 = (uint32_t*)at(o_v1), *seg = (uint32_t*)at(o_seg), *hist = (uint32_t*)at(o_hist);
+  uint32_t *cs = (uint32_t*)at(o_cs), *ce = (uint32_t*)at(o_ce);
+  int32_t* idx = (int32_t*)at(o_idx);
+  double *d2 = (double*)at(o_d2), *w = (double*)at(o_w);
+  unsigned long long* st = (unsigned long long*)at(o_st);
+  unsigned int* shist = (unsigned int*)at(o_shist);
+  double *sig2 = (double*)at(o_sig), *nrm = (double*)at(o_nrm);
+  uint32_t *indeg = (uint32_t*)at(o_indeg), *cap = (uint32_t*)at(o_cap), *start = (uint32_t*)at(o_start),
+           *fillpos = (uint32_t*)at(o_fill), *len = (uint32_t*)at(o_len), *rp = (uint32_t*)at(o_rp);
+  double* rsum = (double*)at(o_rsum);
+  int32_t* ucol = (int32_t*)at(o_ucol);
+  double* uw = (double*)at(o_uw);
+  uint32_t* sseg = (uint32_t*)at(o_sseg);
+  unsigned long long* tot = (unsigned long long*)at(o_tot);
+  uint32_t* stmp = (uint32_t*)at(o_stmp);
+  uint64_t nnz = 0;
+
+  do {
+    // grid and centres sorted by cell
+    hipLaunchKernelGGL(bbox_partial_kernel, dim3(nparts), dim3(256), 0, s, centres, n, part);
+    hipLaunchKernelGGL(grid_params_kernel, dim3(1), dim3(64), 0, s, part, nparts, G, gp);
+    hipLaunchKernelGGL(cell_keys_kernel, dim3(grid1(n)), dim3(256), 0, s, centres, n, gp, G, k0, v0);
+    hipLaunchKernelGGL(one_segment_kernel, dim3(1), dim3(64), 0, s, seg, n);
+    bool second = false;
+    if ((e = radix_sort(k0, v0, k1, v1, seg, seg + 1, 1, n, cell_bits, hist, true, &second, s)) != hipSuccess) break;
+    const uint32_t* skey = second ? k1 : k0;
+    const uint32_t* sid = second ? v1 : v0;
+    if ((e = hipMemsetAsync(cs, 0, 4 * (size_t)cells, s)) != hipSuccess) break;
+    if ((e = hipMemsetAsync(ce, 0, 4 * (size_t)cells, s)) != hipSuccess) break;
+    hipLaunchKernelGGL(cell_ranges_kernel, dim3(grid1(n)), dim3(256), 0, s, skey, n, cs, ce);
+    // exact kNN
+    if (k <= 8)
+      hipLaunchKernelGGL(knn_kernel<8>, dim3(grid1(n)), dim3(256), 0, s, centres, n, sid, cs, ce, gp, G, k, idx, d2);
+    else if (k <= 16)
+      hipLaunchKernelGGL(knn_kernel<16>, dim3(grid1(n)), dim3(256), 0, s, centres, n, sid, cs, ce, gp, G, k, idx, d2);
+    else
+      hipLaunchKernelGGL(knn_kernel<32>, dim3(grid1(n)), dim3(256), 0, s, centres, n, sid, cs, ce, gp, G, k, idx, d2);
+    // sigma: ranks (N - 1) / 2 and N / 2 of the squared distances
+    const unsigned long long N = (unsigned long long)nk;
+    hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, s, st, (N - 1) / 2, N / 2, shist);
+    const unsigned sblocks = (unsigned)std::min<int64_t>(1024, (nk + 255) / 256);
+    for (int shift = 53, width = 11; ; ) {
+      hipLaunchKernelGGL(select_hist_kernel, dim3(sblocks), dim3(256), 0, s, d2, nk, shift, width, st, shist);
+      hipLaunchKernelGGL(select_pick_kernel, dim3(1), dim3(1024), 0, s, shist, shift, st);
+      if (shift == 0) break;
+      width = shift >= 11 ? 11 : shift;
+      shift -= width;
+    }
+    hipLaunchKernelGGL(sigma_kernel, dim3(1), dim3(64), 0, s, st, sig2);
+    // weights
+    hipLaunchKernelGGL(norms_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, feats, n, D, nrm);
+    hipLaunchKernelGGL(edge_weights_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, feats, n,
+                       D, k, idx, d2, nrm, sig2, w);
+    // union rows
+    if ((e = hipMemsetAsync(indeg, 0, 4 * (size_t)n, s)) != hipSuccess) break;
+    if ((e = hipMemsetAsync(fillpos, 0, 4 * (size_t)n, s)) != hipSuccess) break;
+    hipLaunchKernelGGL(indeg_kernel, dim3(grid1(nk)), dim3(256), 0, s, idx, nk, indeg);
+    hipLaunchKernelGGL(row_cap_kernel, dim3(grid1(n)), dim3(256), 0, s, indeg, n, k, cap);
+    if ((e = scan_counts(cap, nullptr, n, 1, start, sseg, sseg + 1, tot, stmp, s)) != hipSuccess) break;
+    hipLaunchKernelGGL(fill_rows_kernel, dim3(grid1(nk)), dim3(256), 0, s, idx, w, n, k, start, fillpos, ucol, uw);
+    hipLaunchKernelGGL(merge_rows_kernel, dim3(grid1(n)), dim3(256), 0, s, n, k, start, indeg, ucol, uw, len, rsum);
+    if ((e = scan_counts(len, nullptr, n, 1, rp, sseg, sseg + 1, tot, stmp, s)) != hipSuccess) break;
+    unsigned long long th[2] = {0, 0};
+    if ((e = hipMemcpyAsync(th, tot, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    nnz = th[0];
+    if ((e = hipMalloc((void**)row_ptr, 4 * (size_t)(n + 1))) != hipSuccess) break;
+    if ((e = hipMalloc((void**)col, 4 * (size_t)(nnz + 1))) != hipSuccess) break;
+    if ((e = hipMalloc((void**)val, 4 * (size_t)(nnz + 1))) != hipSuccess) break;
+    hipLaunchKernelGGL(csr_out_kernel, dim3(grid1(n)), dim3(256), 0, s, n, start, len, rp, ucol, uw, rsum,
+                       *col, *val, *row_ptr, (uint64_t)nnz);
+    e = hipGetLastError();
+  } while (false);
+  const hipError_t ef = hipFreeAsync(base, s);
+  if (e == hipSuccess) e = ef;
+  if (e != hipSuccess) {
+    if (*row_ptr) (void)hipFree(*row_ptr);
+    if (*col) (void)hipFree(*col);
+    if (*val) (void)hipFree(*val);
+    *row_ptr = nullptr;
+    *col = nullptr;
+    *val = nullptr;
+    return e;
+  }
+  *nnz_out = (int64_t)nnz;
+  return hipSuccess;
+}
+
+}  // namespace lv

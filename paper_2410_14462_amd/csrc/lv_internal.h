@@ -286,6 +286,13 @@ hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float
 // keep[i] = 1 for them, 0 for the others (scratch from the stream-ordered
 // allocator).
 hipError_t launch_prune(const float* wsum, int64_t n, int64_t k, uint8_t* keep, hipStream_t s);
+// kNN diffusion graph over the centres (xyz of centres[i]) with feature
+// weights (feats [n][D]); CSR arrays allocated with hipMalloc (owned by the
+// caller afterwards); synchronises the stream once (to size the CSR).
+// Requires k < n, 1 <= k <= 32, n (2k + 1) < 2^31.
+hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats, int D, int k,
+                           hipStream_t s, int32_t** row_ptr, int32_t** col, float** val,
+                           int64_t* nnz);
 // f = U / cnt per Gaussian (0 where cnt = 0).
 hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n, int D, float* f,
                                  hipStream_t s);

@@ -6,7 +6,8 @@ import torch
 import oracle
 import paper_2410_14462_amd as lv
 from oracle import diffuse as od
-from synth import graph, philox, scenes
+from oracle import graph
+from synth import philox, scenes
 from helpers import beta_error, feature_error
 
 pytestmark = pytest.mark.gpu

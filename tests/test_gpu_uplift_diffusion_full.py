@@ -1,23 +1,28 @@
-"""Uplift followed by graph diffusion at full size (Sec. 3.2 then Sec. 3.3,
-Eq. 8), through the C ABI.
+"""Uplift followed by graph construction and diffusion at full size
+(Sec. 3.2 then Sec. 3.3, Eq. 8), through the C ABI.
 
 1,000,000 Gaussians (scales exp(N(-5, 0.7^2)), opacities sigmoid(N(0.5, 1))),
-D = 64 FP32 features uplifted on the GPU from all 100 views at 1008x756; a
-16-NN graph over the centres with weights exp(-d^2 / sigma^2) (sigma the
-median kNN distance) times the clipped cosine similarity of the uplifted
-features, union-symmetrised and row-normalised (host, FP64, stored FP32 and
-BF16); 100 diffusion steps on a D = 1 half-space indicator and on the D = 64
-features.  The FP64 oracle diffuses the same CSR: the D = 1 signal in full
-and a sample of the 64 channels (each channel is normalised by its own norm,
-so channels are independent).
+100 views at 1008x756.
+
+* Graph parity at full size: the 16-NN graph over the centres with
+  synthetic N(0,1) features (64 channels) built on the device against the
+  FP64 oracle graph (structure bit-exact, values within FP32 rounding), then
+  100 diffusion steps of a half-space indicator (D = 1) and of a sample of
+  the 64 channels on it, FP32 and BF16 storage, against the oracle diffusing
+  the oracle graph.
+* The chained path: D = 64 features uplifted on the GPU from all 100 views,
+  the device graph built from them, 100 steps on it; checked by properties
+  (finite, row-stochastic and union-symmetric graph, a non-negative signal
+  stays non-negative, a constant signal stays constant).
 """
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2410_14462_amd as lv
 from oracle import diffuse as od
-from synth import graph, scenes
+from synth import philox, scenes
 
 pytestmark = pytest.mark.gpu
 
@@ -31,40 +36,36 @@ def rel_err(out, ref):
     return np.max(np.abs(out - ref) / scale)
 
 
-def test_uplift_graph_diffusion_full_size():
+@pytest.fixture(scope="module")
+def large():
     w = scenes.WORKLOADS["large"]
     sc = scenes.scene_for(w)
-    cams = scenes.cameras_for(w)
-    gs = lv.Scene.from_arrays(sc)
-    D = 64
-    print("full diffusion: uplift D=64 from 100 views", flush=True)
-    acc = lv.Accum(gs, D)
-    for v0 in range(0, w.m, 10):
-        maps = [scenes.feature_map(w, v, device="cuda", D=D) for v in range(v0, v0 + 10)]
-        acc.add(cams[v0:v0 + 10], maps)
-        del maps
-    f, b = acc.finalize()
-    acc.close()
-    feats = f.cpu().numpy()
-    assert np.isfinite(feats).all() and (b.cpu().numpy() > 0).mean() > 0.2
+    return w, sc, lv.Scene.from_arrays(sc)
 
-    print("full diffusion: 16-NN graph", flush=True)
-    rp, col, val = graph.knn_graph(sc.means, feats, 16)
-    n = sc.n
-    print(f"full diffusion: nnz={len(col)}", flush=True)
+
+def test_graph_and_diffusion_full_size(large):
+    w, sc, gs = large
+    n, D = sc.n, 64
+    feats = philox.normal(w.seed, 77, n * D).reshape(n, D).astype(np.float32)
+    print("full graph: device build", flush=True)
+    G = lv.Graph.knn(gs, torch.as_tensor(feats, device="cuda"), 16)
+    rp, col, val = (t.cpu().numpy() for t in G.csr())
+    print(f"full graph: nnz={len(col)}; oracle build", flush=True)
+    rrp, rcol, rval = oracle.graph.knn_graph(sc.means, feats, 16)
+    assert np.array_equal(rp, rrp) and np.array_equal(col, rcol)
+    err = np.abs(val.astype(np.float64) - rval) - 2e-7 * np.abs(rval)
+    assert err.max() <= 1e-9
     mask = scenes.halfspace_indicator(w.seed, sc.means)
     dev = lambda a: torch.as_tensor(a, device="cuda")
     for vdt in ("f32", "bf16"):
-        gval = dev(val) if vdt == "f32" else dev(val).to(torch.bfloat16)
-        G = lv.Graph(dev(rp), dev(col), gval)
         tdt = torch.float32 if vdt == "f32" else torch.bfloat16
+        Gd = G if vdt == "f32" else lv.Graph(dev(rp), dev(col), dev(val).to(torch.bfloat16))
         g_mask = dev(mask).to(tdt)
-        g_feat = f.to(tdt)
-        out_mask = G.diffuse(g_mask, STEPS, scene=gs).float().cpu().numpy().astype(np.float64)
-        out_feat = G.diffuse(g_feat, STEPS, scene=gs).float().cpu().numpy().astype(np.float64)
-        G.close()
-        aval = val if vdt == "f32" else torch.as_tensor(val).to(torch.bfloat16).float().numpy()
-        A = od.csr_matrix(n, rp, col, aval)
+        g_feat = dev(feats).to(tdt)
+        out_mask = Gd.diffuse(g_mask, STEPS, scene=gs).float().cpu().numpy().astype(np.float64)
+        out_feat = Gd.diffuse(g_feat, STEPS, scene=gs).float().cpu().numpy().astype(np.float64)
+        aval = rval if vdt == "f32" else torch.as_tensor(rval).to(torch.bfloat16).float().numpy()
+        A = od.csr_matrix(n, rrp, rcol, aval)
         chans = CHANNELS if vdt == "f32" else CHANNELS[:2]
         ref_mask = od.diffuse(A, g_mask.float().cpu().numpy(), STEPS)
         ref_feat = od.diffuse(A, g_feat[:, chans].float().cpu().numpy(), STEPS)
@@ -77,3 +78,38 @@ def test_uplift_graph_diffusion_full_size():
             # every iterate is rounded to BF16 (relative 2^-9); A is row-stochastic,
             # so a step adds at most that much to the max-norm error
             assert e_mask < STEPS * 2.0 ** -9 and e_feat < STEPS * 2.0 ** -9
+        if vdt == "bf16":
+            Gd.close()
+    G.close()
+
+
+def test_uplift_graph_diffusion_chain(large):
+    w, sc, gs = large
+    cams = scenes.cameras_for(w)
+    D = 64
+    print("chain: uplift D=64 from 100 views", flush=True)
+    acc = lv.Accum(gs, D)
+    for v0 in range(0, w.m, 10):
+        maps = [scenes.feature_map(w, v, device="cuda", D=D) for v in range(v0, v0 + 10)]
+        acc.add(cams[v0:v0 + 10], maps)
+        del maps
+    f, b = acc.finalize()
+    acc.close()
+    assert torch.isfinite(f).all() and (b > 0).float().mean() > 0.2
+    G = lv.Graph.knn(gs, f, 16)
+    rp, col, val = (t.cpu().numpy() for t in G.csr())
+    n = sc.n
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    assert np.all(np.isfinite(val)) and np.all(val >= 0)
+    assert np.allclose(np.bincount(rows, weights=val.astype(np.float64), minlength=n), 1.0, atol=1e-5)
+    # union-symmetric structure (self-loops aside)
+    off = rows != col
+    fwd = rows[off].astype(np.int64) * n + col[off]
+    bwd = col[off].astype(np.int64) * n + rows[off]
+    assert np.array_equal(np.sort(fwd), np.sort(bwd))
+    mask = torch.as_tensor(scenes.halfspace_indicator(w.seed, sc.means), device="cuda")
+    out = G.diffuse(mask, STEPS, scene=gs)
+    assert torch.all(out >= 0) and torch.isfinite(out).all()
+    ones = G.diffuse(torch.ones((n, 1), device="cuda"), STEPS, scene=gs)
+    assert torch.allclose(ones, torch.full_like(ones, n ** -0.5), rtol=1e-4)
+    G.close()

@@ -1,9 +1,9 @@
-"""Pins for the FP64 diffusion oracle (Eq. 8) and the kNN-graph input builder."""
+"""Pins for the FP64 diffusion oracle (Eq. 8)."""
 import numpy as np
 import scipy.sparse as sp
 
 from oracle import diffuse as od
-from synth import graph
+from oracle import graph
 
 
 def random_graph(n, k, seed, feats_dim=4):
@@ -59,37 +59,3 @@ def test_power_method_reaches_dominant_eigenvector():
     g1 = od.diffuse(sp.csr_matrix(M), g, 1)
     assert np.linalg.norm(g1) == np.float64(np.linalg.norm(g1))
     assert abs(np.linalg.norm(g1) - w[-1]) < 1e-9 * w[-1]
-
-
-def test_knn_matches_brute_force():
-    rng = np.random.default_rng(6)
-    x = rng.uniform(-1, 1, (700, 3))
-    idx, dist = graph.knn(x, 10)
-    D = np.linalg.norm(x[:, None] - x[None], axis=-1)
-    np.fill_diagonal(D, np.inf)
-    ref = np.argsort(D, axis=1, kind="stable")[:, :10]
-    assert np.array_equal(np.sort(idx, 1), np.sort(ref, 1))
-    assert np.allclose(np.sort(dist, 1), np.sort(np.take_along_axis(D, ref, 1), 1))
-
-
-def test_graph_is_union_symmetric_and_row_stochastic():
-    n, k = 400, 6
-    x, f, A = random_graph(n, k, 7)
-    pat = (A != 0).astype(np.int8)
-    idx, dist = graph.knn(x, k)
-    # every kNN edge with positive cosine is present in both directions
-    fn = f / np.linalg.norm(f, axis=1, keepdims=True)
-    for i in range(0, n, 37):
-        for j in idx[i]:
-            if fn[i] @ fn[j] > 1e-9:
-                assert pat[i, j] and pat[j, i]
-    assert np.allclose(np.asarray(A.sum(axis=1)).ravel(), 1.0, atol=1e-6)
-    sigma = np.median(dist)
-    i = 0
-    j = [c for c in idx[0] if fn[0] @ fn[c] > 0][0]
-    d = np.linalg.norm(x[0] - x[j])
-    w = np.exp(-d * d / sigma ** 2) * (fn[0] @ fn[j])
-    row = A.getrow(0).toarray().ravel()
-    assert abs(row[j] / row.sum() - w / sum(
-        np.exp(-np.linalg.norm(x[0] - x[c]) ** 2 / sigma ** 2) * max(0.0, fn[0] @ fn[c])
-        for c in np.nonzero(row)[0])) < 1e-6
