@@ -186,6 +186,16 @@ lv_status lv_accum_finalize_count(lv_accum* acc, float* out_feat, void* stream);
  * Errors: LV_ERR_INVALID_ARG (n < 0 or n >= 2^28, k outside [0, n], null
  * buffers with n > 0), LV_ERR_DEVICE. */
 lv_status lv_prune_by_weight(const float* wsum, int64_t n, int64_t k, uint8_t* keep, void* stream);
+/* Anchor initialisation of a diffusion (appendix on diffusion for
+ * segmentation): of the n values g (device FP32, e.g. an uplifted mask),
+ * the ceil(fraction * npos) largest of the npos positive ones (ties to the
+ * lower index) are copied to g0 (device FP32 [n]), every other entry of g0
+ * is 0.  0 < fraction <= 1.  Scratch from the stream-ordered allocator. */
+lv_status lv_anchor_init(const float* g, int64_t n, float fraction, float* g0, void* stream);
+/* Reachability after diffusion (same appendix): h[i][c] = unary[i] where
+ * gT[i][c] > 0, else 0 (gT, h: device FP32 [n][D]; unary: device FP32 [n]). */
+lv_status lv_reach_unary(const float* gT, const float* unary, int64_t n, int32_t D, float* h,
+                         void* stream);
 /* Per-Gaussian contribution counts (device uint32 [n]); the accumulator must
  * have been created with LV_ACCUM_COUNTS. */
 lv_status lv_accum_counts(lv_accum* acc, uint32_t* out_counts, void* stream);
@@ -244,8 +254,27 @@ lv_status lv_graph_destroy(lv_graph* graph);
  * LV_ERR_INVALID_ARG (k outside [1, 32], D outside [1, 4096], n <= k, null
  * pointers), LV_ERR_UNSUPPORTED (n (2k + 1) >= 2^31), LV_ERR_OUT_OF_MEMORY,
  * LV_ERR_DEVICE. */
-lv_status lv_graph_build_knn(lv_scene* scene, const float* feats, int32_t D, int32_t k, void* stream,
-                             lv_graph** out);
+typedef enum lv_graph_kind {
+    LV_GRAPH_SPATIAL_COSINE = 0,  /* the weights above */
+    LV_GRAPH_FEATURE_RBF = 1      /* Eq. 7 with Eq. 9, see lv_graph_opts */
+} lv_graph_kind;
+/* opts NULL: LV_GRAPH_SPATIAL_COSINE.  LV_GRAPH_FEATURE_RBF (the paper's
+ * weights, Eq. 7 with the feature kernel of Eq. 9, appendix on diffusion
+ * for segmentation): A_ij = exp(-|g_i - g_j|^2 / (b s_f^2)) (sqrt(P_i)
+ * sqrt(P_j)) on the same union pairs, g the l2-normalised features (a zero
+ * feature stays 0), s_f the median of |g_i - g_j| over the n k directed
+ * kNN pairs, b = bandwidth > 0, P = unary (device FP32 [n], >= 0; NULL: 1);
+ * FP64, stored FP32, no row normalisation, no self-loops (a row may be
+ * empty); pairs with weight 0 are not stored, and with binarize > 0 only the
+ * pairs whose weight exceeds binarize are stored, with value 1. */
+typedef struct lv_graph_opts {
+    int32_t kind;
+    float bandwidth;
+    const float* unary;
+    float binarize;
+} lv_graph_opts;
+lv_status lv_graph_build_knn(lv_scene* scene, const float* feats, int32_t D, int32_t k,
+                             const lv_graph_opts* opts, void* stream, lv_graph** out);
 /* Size of a graph (n, nnz: nullable) and, where the pointers are not NULL,
  * copies of its CSR arrays into caller device buffers (row_ptr [n+1], col
  * [nnz] int32, val [nnz] of the graph's value dtype), on the stream. */

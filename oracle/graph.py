@@ -109,3 +109,45 @@ def knn_graph(points, feats, k=16):
     row_ptr = np.zeros(n + 1, np.int64)
     np.cumsum(np.bincount(r2, minlength=n), out=row_ptr[1:])
     return row_ptr.astype(np.int32), c2.astype(np.int32), val.astype(np.float32)
+
+
+def feature_rbf_graph(points, feats, k, bandwidth, unary=None, binarize=0.0):
+    """The paper's weights (Eq. 7 with the feature kernel of Eq. 9, appendix
+    on diffusion for segmentation) on the same union pairs:
+    A_ij = exp(-|g_i - g_j|^2 / (b s_f^2)) (sqrt(P_i) sqrt(P_j)), g the
+    l2-normalised features (a zero feature stays 0), s_f the median of
+    |g_i - g_j| over the directed kNN pairs, P = unary (1 if None).  No row
+    normalisation and no self-loops; pairs with weight 0 are not stored;
+    binarize > 0 keeps the pairs whose weight exceeds it, with value 1.
+    Returns (row_ptr int32 [n+1], col int32 [nnz], val float32 [nnz])."""
+    x = np.asarray(points, np.float32).astype(np.float64)
+    n = x.shape[0]
+    idx, _ = knn(x, k)
+    f = np.asarray(feats, np.float32).astype(np.float64)
+    if f.ndim == 1:
+        f = f[:, None]
+    nrm = np.sqrt(np.sum(f * f, axis=1))
+    g = np.where(nrm[:, None] > 0, f / np.where(nrm > 0, nrm, 1.0)[:, None], 0.0)
+    rows = np.repeat(np.arange(n), k)
+    cols = idx.reshape(-1)
+    fd2 = np.concatenate([np.sum((g[rows[a:a + (1 << 20)]] - g[cols[a:a + (1 << 20)]]) ** 2, axis=1)
+                          for a in range(0, n * k, 1 << 20)])
+    sf = float(np.median(np.sqrt(fd2)))
+    p = np.ones(n) if unary is None else np.asarray(unary, np.float32).astype(np.float64)
+    w = np.exp(-fd2 / (float(np.float32(bandwidth)) * (sf * sf))) * (np.sqrt(p[rows]) * np.sqrt(p[cols]))
+    r2 = np.concatenate([rows, cols])
+    c2 = np.concatenate([cols, rows])
+    w2 = np.concatenate([w, w])
+    o = np.lexsort((-w2, c2, r2))
+    r2, c2, w2 = r2[o], c2[o], w2[o]
+    first = np.ones(r2.size, bool)
+    first[1:] = (r2[1:] != r2[:-1]) | (c2[1:] != c2[:-1])
+    r2, c2, w2 = r2[first], c2[first], w2[first]
+    thr = float(np.float32(binarize))
+    keep = w2 > thr
+    r2, c2, w2 = r2[keep], c2[keep], w2[keep]
+    if thr > 0:
+        w2 = np.ones_like(w2)
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(r2, minlength=n), out=row_ptr[1:])
+    return row_ptr.astype(np.int32), c2.astype(np.int32), w2.astype(np.float32)

@@ -30,3 +30,21 @@ def keep_top_k(values, k):
     keep = np.zeros(n, np.uint8)
     keep[order[:k]] = 1
     return keep
+
+
+def anchor_init(g, fraction):
+    """Anchors of a diffusion (appendix on diffusion for segmentation): the
+    ceil(fraction * npos) largest of the npos positive values of g keep their
+    value (ties to the lower index), every other entry is 0."""
+    import math
+    g = np.asarray(g, dtype=np.float32)
+    npos = int(np.sum(g > 0))
+    k = int(math.ceil(float(np.float32(fraction)) * npos))
+    return np.where(keep_top_k(g, k) == 1, g, np.float32(0.0)).astype(np.float32)
+
+
+def reach_unary(gT, unary):
+    """h = P where the diffused signal is positive (the nodes reached), else 0."""
+    gT = np.asarray(gT, dtype=np.float32)
+    p = np.asarray(unary, dtype=np.float32)
+    return np.where(gT > 0, p.reshape((-1,) + (1,) * (gT.ndim - 1)), np.float32(0.0)).astype(np.float32)

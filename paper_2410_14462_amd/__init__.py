@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblv.so")
 
 LV_F32, LV_BF16, LV_FP8_E4M3 = 0, 1, 2
 LV_ACCUM_COUNTS = 1
+LV_GRAPH_SPATIAL_COSINE, LV_GRAPH_FEATURE_RBF = 0, 1
 _DTYPES = {"f32": LV_F32, "bf16": LV_BF16, "fp8": LV_FP8_E4M3}
 
 
@@ -37,6 +38,11 @@ class lv_view_debug(ctypes.Structure):
 class lv_feature_set(ctypes.Structure):
     _fields_ = [("acc", ctypes.c_void_p), ("maps", ctypes.c_void_p), ("scales", ctypes.c_void_p),
                 ("stride", ctypes.c_int32)]
+
+
+class lv_graph_opts(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("bandwidth", ctypes.c_float), ("unary", ctypes.c_void_p),
+                ("binarize", ctypes.c_float)]
 
 
 class lv_server_opts(ctypes.Structure):
@@ -98,7 +104,9 @@ def lib():
             "lv_accum_counts": ([P, P, P], i32),
             "lv_accum_finalize_count": ([P, P, P], i32),
             "lv_prune_by_weight": ([P, i64, i64, P, P], i32),
-            "lv_graph_build_knn": ([P, P, i32, i32, P, ctypes.POINTER(P)], i32),
+            "lv_graph_build_knn": ([P, P, i32, i32, ctypes.POINTER(lv_graph_opts), P, ctypes.POINTER(P)], i32),
+            "lv_anchor_init": ([P, i64, ctypes.c_float, P, P], i32),
+            "lv_reach_unary": ([P, P, i64, i32, P, P], i32),
             "lv_graph_csr": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64), P, P, P, P], i32),
             "lv_accum_destroy": ([P], i32),
             "lv_encode": ([P, i64, i32, i32, P, P, P], i32),
@@ -135,7 +143,7 @@ def exported_symbols():
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
             "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",
             "lv_server_drain", "lv_server_stats_get", "lv_server_destroy", "lv_accum_finalize_count",
-            "lv_prune_by_weight", "lv_graph_build_knn", "lv_graph_csr"]
+            "lv_prune_by_weight", "lv_graph_build_knn", "lv_graph_csr", "lv_anchor_init", "lv_reach_unary"]
 
 
 def _check(status):
@@ -344,6 +352,28 @@ class Accum:
         return f
 
 
+def anchor_init(g, fraction=0.1):
+    """lv_anchor_init: g0 keeps the ceil(fraction npos) largest positive
+    entries of g (float32 [n] on the device), 0 elsewhere."""
+    import torch
+    _dev_f32(g)
+    g0 = torch.empty_like(g)
+    _check(lib().lv_anchor_init(_ptr(g), g.numel(), float(fraction), _ptr(g0), _stream()))
+    return g0
+
+
+def reach_unary(gT, unary):
+    """lv_reach_unary: h = unary where gT > 0, else 0 (gT [n] or [n, D])."""
+    import torch
+    _dev_f32(gT)
+    _dev_f32(unary)
+    n = unary.numel()
+    D = 1 if gT.dim() == 1 else gT.shape[1]
+    h = torch.empty_like(gT)
+    _check(lib().lv_reach_unary(_ptr(gT), _ptr(unary), n, D, _ptr(h), _stream()))
+    return h
+
+
 def prune_by_weight(wsum, k):
     """lv_prune_by_weight: uint8 mask [n] of the k Gaussians with the largest
     wsum (device FP32 [n]), ties to the lower index."""
@@ -450,13 +480,21 @@ class Graph:
         self.handle, self.n, self.dtype = h, n, dt
 
     @classmethod
-    def knn(cls, scene, feats, k=16):
+    def knn(cls, scene, feats, k=16, kind="spatial_cosine", bandwidth=1.0, unary=None, binarize=0.0):
         """lv_graph_build_knn: the kNN diffusion graph over the scene's centres
-        with feature weights (feats [n, D] float32 on the device)."""
+        with feature weights (feats [n, D] float32 on the device); kind
+        "feature_rbf" gives the paper's Eq. 7 / Eq. 9 weights (bandwidth,
+        unary P [n] float32 on the device or None, binarize threshold)."""
         _dev_f32(feats)
+        if unary is not None:
+            _dev_f32(unary)
         D = 1 if feats.dim() == 1 else feats.shape[1]
+        kinds = {"spatial_cosine": LV_GRAPH_SPATIAL_COSINE, "feature_rbf": LV_GRAPH_FEATURE_RBF}
+        o = lv_graph_opts(kinds[kind], float(bandwidth), None if unary is None else unary.data_ptr(),
+                          float(binarize))
         h = ctypes.c_void_p()
-        _check(lib().lv_graph_build_knn(scene.handle, _ptr(feats), D, int(k), _stream(), ctypes.byref(h)))
+        _check(lib().lv_graph_build_knn(scene.handle, _ptr(feats), D, int(k), ctypes.byref(o), _stream(),
+                                        ctypes.byref(h)))
         g = cls.__new__(cls)
         g.handle, g.n, g.dtype = h, scene.n, LV_F32
         return g

@@ -607,6 +607,22 @@ lv_status lv_prune_by_weight(const float* wsum, int64_t n, int64_t k, uint8_t* k
   return LV_OK;
 }
 
+lv_status lv_anchor_init(const float* g, int64_t n, float fraction, float* g0, void* stream) {
+  if (n < 0 || n >= kMaxGaussians) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (!(fraction > 0.0f && fraction <= 1.0f)) return fail(LV_ERR_INVALID_ARG, "fraction must be in (0, 1]");
+  if (n > 0 && (!g || !g0)) return fail(LV_ERR_INVALID_ARG, "null buffer");
+  HIP_TRY(launch_anchor_init(g, n, fraction, g0, static_cast<hipStream_t>(stream)));
+  return LV_OK;
+}
+
+lv_status lv_reach_unary(const float* gT, const float* unary, int64_t n, int32_t D, float* h,
+                         void* stream) {
+  if (n < 0 || D < 1) return fail(LV_ERR_INVALID_ARG, "bad size");
+  if (n > 0 && (!gT || !unary || !h)) return fail(LV_ERR_INVALID_ARG, "null buffer");
+  HIP_TRY(launch_reach_unary(gT, unary, n, D, h, static_cast<hipStream_t>(stream)));
+  return LV_OK;
+}
+
 lv_status lv_accum_counts(lv_accum* a, uint32_t* out, void* stream) {
   if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
   if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");
@@ -781,8 +797,8 @@ lv_status lv_graph_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, co
   return LV_OK;
 }
 
-lv_status lv_graph_build_knn(lv_scene* sc, const float* feats, int32_t D, int32_t k, void* stream,
-                             lv_graph** out) {
+lv_status lv_graph_build_knn(lv_scene* sc, const float* feats, int32_t D, int32_t k,
+                             const lv_graph_opts* opts, void* stream, lv_graph** out) {
   if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!sc || !feats) return fail(LV_ERR_INVALID_ARG, "null argument");
@@ -792,11 +808,24 @@ lv_status lv_graph_build_knn(lv_scene* sc, const float* feats, int32_t D, int32_
   if (n <= k) return fail(LV_ERR_INVALID_ARG, "n = %lld must exceed k = %d", (long long)n, k);
   if (n * (int64_t)(2 * k + 1) >= ((int64_t)1 << 31))
     return fail(LV_ERR_UNSUPPORTED, "n (2k + 1) = %lld >= 2^31", (long long)(n * (2 * k + 1)));
+  GraphWeights gw;
+  if (opts) {
+    if (opts->kind != LV_GRAPH_SPATIAL_COSINE && opts->kind != LV_GRAPH_FEATURE_RBF)
+      return fail(LV_ERR_INVALID_ARG, "unknown graph kind %d", opts->kind);
+    gw.kind = opts->kind;
+    if (gw.kind == LV_GRAPH_FEATURE_RBF) {
+      if (!(opts->bandwidth > 0.0f)) return fail(LV_ERR_INVALID_ARG, "bandwidth must be > 0");
+      if (!(opts->binarize >= 0.0f)) return fail(LV_ERR_INVALID_ARG, "binarize must be >= 0");
+      gw.bandwidth = opts->bandwidth;
+      gw.unary = opts->unary;
+      gw.binarize = opts->binarize;
+    }
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   int32_t *rp = nullptr, *cl = nullptr;
   float* vl = nullptr;
   int64_t nnz = 0;
-  HIP_TRY(build_knn_graph(sc->p0.as<float4>(), n, feats, D, k, s, &rp, &cl, &vl, &nnz));
+  HIP_TRY(build_knn_graph(sc->p0.as<float4>(), n, feats, D, k, gw, s, &rp, &cl, &vl, &nnz));
   lv_graph* g = new (std::nothrow) lv_graph();
   if (!g) {
     (void)hipFree(rp); (void)hipFree(cl); (void)hipFree(vl);

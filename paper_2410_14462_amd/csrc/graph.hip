@@ -11,6 +11,14 @@
 // index); the union pairs with a positive FP64 weight are stored, columns
 // ascending; a self-loop is the only entry of its row.
 //
+// The paper's own weights (Eq. 7 with the feature kernel of Eq. 9, the
+// appendix on diffusion for segmentation) are the other kind: A_ij =
+// exp(-|g_i - g_j|^2 / (b s_f^2)) (sqrt(P_i) sqrt(P_j)) with g the
+// l2-normalised features, s_f the median feature distance over the directed
+// kNN pairs, b a bandwidth and P a caller-given unary term (1 if absent); no
+// row normalisation, no self-loops; optionally binarised (1 where the weight
+// exceeds a threshold).
+//
 // Steps: bounding box; uniform grid (about two centres per cell), centres
 // sorted by cell; exact kNN by shells of cells around each centre until the
 // k-th distance is below the distance to the next shell; sigma from the two
@@ -255,7 +263,8 @@ __global__ void select_init_kernel(unsigned long long* st, unsigned long long r0
   for (int e = threadIdx.x; e < 2 * kSelBins; e += blockDim.x) hist[e] = 0u;
 }
 
-// sigma^2 from the two middle squared distances (their roots averaged)
+// sig2 = (median of the roots)^2, from the two middle squared values (their
+// roots averaged)
 __global__ void sigma_kernel(const unsigned long long* st, double* sig2) {
   if (threadIdx.x != 0) return;
   const double a = __longlong_as_double((long long)st[0]), b = __longlong_as_double((long long)st[1]);
@@ -309,6 +318,42 @@ __global__ __launch_bounds__(256) void edge_weights_kernel(const float* __restri
   }
 }
 
+// squared distances of the l2-normalised features of each directed pair
+// (a zero feature stays zero), one wave per node
+__global__ __launch_bounds__(256) void feature_d2_kernel(const float* __restrict__ f, int64_t n, int D,
+                                                         int k, const int32_t* __restrict__ idx,
+                                                         const double* __restrict__ nrm,
+                                                         double* __restrict__ fd2) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const double ni = nrm[i];
+  for (int t = 0; t < k; t++) {
+    const int64_t j = idx[i * k + t];
+    const double nj = nrm[j];
+    double acc = 0.0;
+    for (int ch = lane; ch < D; ch += 64) {
+      const double a = ni > 0.0 ? (double)f[i * D + ch] / ni : 0.0;
+      const double b = nj > 0.0 ? (double)f[j * D + ch] / nj : 0.0;
+      acc += (a - b) * (a - b);
+    }
+    acc = wave_sum_f64(acc);
+    if (lane == 0) fd2[i * k + t] = acc;
+  }
+}
+
+// Eq. 7 / Eq. 9 weight of each directed pair
+__global__ void rbf_weights_kernel(int64_t nk, int k, const int32_t* __restrict__ idx,
+                                   const double* __restrict__ fd2, const double* __restrict__ s2,
+                                   double bandwidth, const float* __restrict__ unary,
+                                   double* __restrict__ w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nk) return;
+  const int64_t i = e / k, j = idx[e];
+  const double pp = unary ? sqrt((double)unary[i]) * sqrt((double)unary[j]) : 1.0;
+  w[e] = exp(-fd2[e] / (bandwidth * s2[0])) * pp;
+}
+
 // ------------------------------------------------------------ union rows
 __global__ void indeg_kernel(const int32_t* __restrict__ idx, int64_t nk, uint32_t* __restrict__ indeg) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -345,7 +390,8 @@ __global__ void fill_rows_kernel(const int32_t* __restrict__ idx, const double* 
 __global__ void merge_rows_kernel(int64_t n, int k, const uint32_t* __restrict__ start,
                                   const uint32_t* __restrict__ indeg, int32_t* __restrict__ ucol,
                                   double* __restrict__ uw, uint32_t* __restrict__ len,
-                                  double* __restrict__ rsum) {
+                                  double* __restrict__ rsum, double thresh, bool binarize,
+                                  bool self_loops) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int32_t* cl = ucol + start[i];
@@ -369,13 +415,13 @@ __global__ void merge_rows_kernel(int64_t n, int k, const uint32_t* __restrict__
   for (int a = 0; a < m; a++) {
     if (cl[a] == last) continue;  // the first of a column has the larger weight
     last = cl[a];
-    if (!(wv[a] > 0.0)) continue;
+    if (!(wv[a] > thresh)) continue;
     cl[u] = cl[a];
-    wv[u] = wv[a];
+    wv[u] = binarize ? 1.0 : wv[a];
     s += wv[u];
     u++;
   }
-  if (u == 0) {  // self-loop
+  if (u == 0 && self_loops) {  // self-loop
     cl[0] = (int32_t)i;
     wv[0] = 1.0;
     u = 1;
@@ -389,14 +435,15 @@ __global__ void csr_out_kernel(int64_t n, const uint32_t* __restrict__ start,
                                const uint32_t* __restrict__ len, const uint32_t* __restrict__ rp,
                                const int32_t* __restrict__ ucol, const double* __restrict__ uw,
                                const double* __restrict__ rsum, int32_t* __restrict__ col,
-                               float* __restrict__ val, int32_t* __restrict__ row_ptr, uint64_t nnz) {
+                               float* __restrict__ val, int32_t* __restrict__ row_ptr, uint64_t nnz,
+                               bool normalise) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t a = start[i], o = rp[i], m = len[i];
   const double s = rsum[i];
   for (uint32_t q = 0; q < m; q++) {
     col[o + q] = ucol[a + q];
-    val[o + q] = (float)(uw[a + q] / s);
+    val[o + q] = normalise ? (float)(uw[a + q] / s) : (float)uw[a + q];
   }
   row_ptr[i] = (int32_t)o;
   if (i == n - 1) row_ptr[n] = (int32_t)nnz;
@@ -414,8 +461,9 @@ unsigned grid1(int64_t items) { return (unsigned)((items + 255) / 256); }
 }  // namespace
 
 hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats, int D, int k,
-                           hipStream_t s, int32_t** row_ptr, int32_t** col, float** val,
-                           int64_t* nnz_out) {
+                           const GraphWeights& gw, hipStream_t s, int32_t** row_ptr, int32_t** col,
+                           float** val, int64_t* nnz_out) {
+  const bool rbf = gw.kind == LV_GRAPH_FEATURE_RBF;
   *row_ptr = nullptr;
   *col = nullptr;
   *val = nullptr;
@@ -503,8 +551,29 @@ hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats,
     hipLaunchKernelGGL(sigma_kernel, dim3(1), dim3(64), 0, s, st, sig2);
     // weights
     hipLaunchKernelGGL(norms_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, feats, n, D, nrm);
-    hipLaunchKernelGGL(edge_weights_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, feats, n,
-                       D, k, idx, d2, nrm, sig2, w);
+    if (!rbf) {
+      hipLaunchKernelGGL(edge_weights_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, feats,
+                         n, D, k, idx, d2, nrm, sig2, w);
+    } else {
+      // s_f: median feature distance over the directed pairs (d2 is reused
+      // for the feature distances; sigma above is not needed)
+      hipLaunchKernelGGL(feature_d2_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, feats, n,
+                         D, k, idx, nrm, w);
+      hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, s, st, (N - 1) / 2, N / 2, shist);
+      for (int shift = 53, width = 11; ; ) {
+        hipLaunchKernelGGL(select_hist_kernel, dim3(sblocks), dim3(256), 0, s, w, nk, shift, width, st, shist);
+        hipLaunchKernelGGL(select_pick_kernel, dim3(1), dim3(1024), 0, s, shist, shift, st);
+        if (shift == 0) break;
+        width = shift >= 11 ? 11 : shift;
+        shift -= width;
+      }
+      hipLaunchKernelGGL(sigma_kernel, dim3(1), dim3(64), 0, s, st, sig2);
+      hipLaunchKernelGGL(rbf_weights_kernel, dim3(grid1(nk)), dim3(256), 0, s, nk, k, idx, w, sig2,
+                         (double)gw.bandwidth, gw.unary, d2);
+      double* t = w;  // the weights are in d2's buffer
+      w = d2;
+      d2 = t;
+    }
     // union rows
     if ((e = hipMemsetAsync(indeg, 0, 4 * (size_t)n, s)) != hipSuccess) break;
     if ((e = hipMemsetAsync(fillpos, 0, 4 * (size_t)n, s)) != hipSuccess) break;
@@ -512,7 +581,9 @@ hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats,
     hipLaunchKernelGGL(row_cap_kernel, dim3(grid1(n)), dim3(256), 0, s, indeg, n, k, cap);
     if ((e = scan_counts(cap, nullptr, n, 1, start, sseg, sseg + 1, tot, stmp, s)) != hipSuccess) break;
     hipLaunchKernelGGL(fill_rows_kernel, dim3(grid1(nk)), dim3(256), 0, s, idx, w, n, k, start, fillpos, ucol, uw);
-    hipLaunchKernelGGL(merge_rows_kernel, dim3(grid1(n)), dim3(256), 0, s, n, k, start, indeg, ucol, uw, len, rsum);
+    const bool bin = rbf && gw.binarize > 0.0f;
+    hipLaunchKernelGGL(merge_rows_kernel, dim3(grid1(n)), dim3(256), 0, s, n, k, start, indeg, ucol, uw, len,
+                       rsum, bin ? (double)gw.binarize : 0.0, bin, !rbf);
     if ((e = scan_counts(len, nullptr, n, 1, rp, sseg, sseg + 1, tot, stmp, s)) != hipSuccess) break;
     unsigned long long th[2] = {0, 0};
     if ((e = hipMemcpyAsync(th, tot, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) break;
@@ -522,7 +593,7 @@ hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats,
     if ((e = hipMalloc((void**)col, 4 * (size_t)(nnz + 1))) != hipSuccess) break;
     if ((e = hipMalloc((void**)val, 4 * (size_t)(nnz + 1))) != hipSuccess) break;
     hipLaunchKernelGGL(csr_out_kernel, dim3(grid1(n)), dim3(256), 0, s, n, start, len, rp, ucol, uw, rsum,
-                       *col, *val, *row_ptr, (uint64_t)nnz);
+                       *col, *val, *row_ptr, (uint64_t)nnz, !rbf);
     e = hipGetLastError();
   } while (false);
   const hipError_t ef = hipFreeAsync(base, s);

@@ -290,9 +290,21 @@ hipError_t launch_prune(const float* wsum, int64_t n, int64_t k, uint8_t* keep, 
 // weights (feats [n][D]); CSR arrays allocated with hipMalloc (owned by the
 // caller afterwards); synchronises the stream once (to size the CSR).
 // Requires k < n, 1 <= k <= 32, n (2k + 1) < 2^31.
+struct GraphWeights {
+  int32_t kind = LV_GRAPH_SPATIAL_COSINE;
+  float bandwidth = 1.0f;        // b (feature kernel)
+  const float* unary = nullptr;  // P [n] (feature kernel), NULL: 1
+  float binarize = 0.0f;         // > 0 (feature kernel): 1 where the weight exceeds it
+};
 hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats, int D, int k,
-                           hipStream_t s, int32_t** row_ptr, int32_t** col, float** val,
-                           int64_t* nnz);
+                           const GraphWeights& gw, hipStream_t s, int32_t** row_ptr, int32_t** col,
+                           float** val, int64_t* nnz);
+// g0 = g on the ceil(fraction npos) largest positive entries (ties to the
+// lower index), 0 elsewhere.
+hipError_t launch_anchor_init(const float* g, int64_t n, float fraction, float* g0, hipStream_t s);
+// h[i][c] = unary[i] where gT[i][c] > 0, else 0.
+hipError_t launch_reach_unary(const float* gT, const float* unary, int64_t n, int D, float* h,
+                              hipStream_t s);
 // f = U / cnt per Gaussian (0 where cnt = 0).
 hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n, int D, float* f,
                                  hipStream_t s);

@@ -6,7 +6,9 @@
 //
 // Filtering keeps the k Gaussians with the largest beta, ties to the lower
 // index: a stable radix sort of (descending-order key, index) over all n,
-// then the first k are marked.
+// then the first k are marked.  The same order gives the anchors of a
+// diffusion (appendix on diffusion for segmentation: the largest fraction
+// of the positive uplifted mask values) and the reachability output h.
 #include "lv_internal.h"
 
 namespace lv {
@@ -39,6 +41,42 @@ __global__ void prune_mark_kernel(const uint32_t* __restrict__ sorted_idx, int64
                                   uint8_t* __restrict__ keep) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < k) keep[sorted_idx[r]] = 1;
+}
+
+// anchor initialisation: keys as for filtering, g0 cleared, positives counted
+__global__ void anchor_keys_kernel(const float* __restrict__ g, int64_t n, uint32_t* __restrict__ key,
+                                   uint32_t* __restrict__ idx, float* __restrict__ g0,
+                                   uint32_t* __restrict__ seg, unsigned long long* __restrict__ npos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    seg[0] = 0u;
+    seg[1] = (uint32_t)n;
+  }
+  const bool pos = i < n && g[i] > 0.0f;
+  const uint64_t b = __ballot(pos);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(npos, (unsigned long long)__popcll(b));
+  if (i >= n) return;
+  key[i] = descending_key(g[i]);
+  idx[i] = (uint32_t)i;
+  g0[i] = 0.0f;
+}
+
+__global__ void anchor_mark_kernel(const uint32_t* __restrict__ sorted_idx, int64_t n, float fraction,
+                                   const unsigned long long* __restrict__ npos,
+                                   const float* __restrict__ g, float* __restrict__ g0) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = (int64_t)ceil((double)fraction * (double)npos[0]);
+  if (r < k && r < n) {
+    const uint32_t i = sorted_idx[r];
+    g0[i] = g[i];
+  }
+}
+
+__global__ void reach_unary_kernel(const float* __restrict__ gT, const float* __restrict__ unary,
+                                   int64_t n, int D, float* __restrict__ h) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * D) return;
+  h[e] = gT[e] > 0.0f ? unary[e / D] : 0.0f;
 }
 
 __global__ void finalize_count_kernel(const float* __restrict__ U, const uint32_t* __restrict__ cnt,
@@ -75,6 +113,44 @@ hipError_t launch_prune(const float* wsum, int64_t n, int64_t k, uint8_t* keep, 
   }
   const hipError_t ef = hipFreeAsync(mem, s);
   return e != hipSuccess ? e : ef;
+}
+
+hipError_t launch_anchor_init(const float* g, int64_t n, float fraction, float* g0, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t words = 4 * (size_t)n + 2 + 2 + sort_hist_size(1, n);
+  void* mem = nullptr;
+  hipError_t e = hipMallocAsync(&mem, 4 * words, s);
+  if (e != hipSuccess) return e;
+  uint32_t* k0 = static_cast<uint32_t*>(mem);
+  uint32_t* v0 = k0 + n;
+  uint32_t* k1 = v0 + n;
+  uint32_t* v1 = k1 + n;
+  uint32_t* seg = v1 + n;
+  unsigned long long* npos = reinterpret_cast<unsigned long long*>(seg + 2);  // 8-byte aligned: 4n + 2 even
+  uint32_t* hist = seg + 4;
+  e = hipMemsetAsync(npos, 0, 8, s);
+  if (e == hipSuccess) {
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(anchor_keys_kernel, dim3(nb), dim3(256), 0, s, g, n, k0, v0, g0, seg, npos);
+    bool second = false;
+    e = radix_sort(k0, v0, k1, v1, seg, seg + 1, 1, n, 32, hist, false, &second, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(anchor_mark_kernel, dim3(nb), dim3(256), 0, s, second ? v1 : v0, n, fraction, npos,
+                         g, g0);
+      e = hipGetLastError();
+    }
+  }
+  const hipError_t ef = hipFreeAsync(mem, s);
+  return e != hipSuccess ? e : ef;
+}
+
+hipError_t launch_reach_unary(const float* gT, const float* unary, int64_t n, int D, float* h,
+                              hipStream_t s) {
+  const int64_t total = n * (int64_t)D;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(reach_unary_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, gT, unary,
+                     n, D, h);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n, int D, float* f,

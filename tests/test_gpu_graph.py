@@ -92,3 +92,74 @@ def test_diffusion_on_device_graph():
     err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
     print(f"diffusion on the device graph: err {err:.3e}")
     assert err < 1e-5
+
+
+# ------------------------------------------- the paper's Eq. 7 / Eq. 9 graph
+def compare_rbf(x, f, k, b, unary=None, binarize=0.0):
+    gs = lv.Scene.from_arrays(scene_at(x))
+    P = None if unary is None else torch.as_tensor(unary, device="cuda")
+    G = lv.Graph.knn(gs, torch.as_tensor(f, device="cuda"), k, kind="feature_rbf", bandwidth=b, unary=P,
+                     binarize=binarize)
+    rp, col, val = (t.cpu().numpy() for t in G.csr())
+    rrp, rcol, rval = oracle.graph.feature_rbf_graph(x, f, k, b, unary=unary, binarize=binarize)
+    assert np.array_equal(rp, rrp)
+    assert np.array_equal(col, rcol)
+    err = np.abs(val.astype(np.float64) - rval) - 2e-7 * np.abs(rval)
+    assert err.max(initial=0.0) <= 1e-9
+    return G, gs, (rp, col, val)
+
+
+@pytest.mark.parametrize("n,k,D,b,with_unary", [(300, 8, 4, 1.0, False), (5000, 16, 32, 0.3, True),
+                                                 (20000, 16, 64, 2.0, True)])
+def test_feature_rbf_graph(n, k, D, b, with_unary):
+    x = uniform_points(n, 70 + n)
+    f = features(n, D, 71 + n)
+    p = philox.uniform(72, n, n).astype(np.float32) if with_unary else None
+    compare_rbf(x, f, k, b, p)
+
+
+def test_feature_rbf_graph_binarised_and_reachability():
+    """The segmentation diffusion of the appendix on synthetic inputs: anchors
+    from a mask (the largest 10 % of its positive values), the binarised
+    Eq. 7 graph with a unary term, T steps, h = P on the reached nodes.  The
+    reached set is a graph property (A >= 0, g0 >= 0), so h is compared
+    exactly."""
+    n, k, T = 20000, 16, 4
+    x = uniform_points(n, 81)
+    f = features(n, 16, 82)
+    p = philox.uniform(83, 0, n).astype(np.float32)
+    G, gs, (rp, col, val) = compare_rbf(x, f, k, 0.5, p, binarize=1e-5)
+    assert np.all(val == 1.0)
+    # a mask that is positive only in a slab of the scene
+    mask = np.where(x[:, 0] > 0.8, philox.uniform(84, 0, n) + 0.1, -1.0).astype(np.float32)
+    g0 = lv.anchor_init(torch.as_tensor(mask, device="cuda"), 0.1)
+    ref_g0 = oracle.prune.anchor_init(mask, 0.1)
+    assert np.array_equal(g0.cpu().numpy(), ref_g0)
+    gT = G.diffuse(g0, T)
+    h = lv.reach_unary(gT, torch.as_tensor(p, device="cuda")).cpu().numpy()
+    ref_gT = od.diffuse(od.csr_matrix(n, rp, col, val), ref_g0.astype(np.float64), T)
+    ref_h = oracle.prune.reach_unary(ref_gT, p)
+    reached = int(np.count_nonzero(ref_h))
+    print(f"reached {reached} of {n} nodes from {np.count_nonzero(ref_g0)} anchors in {T} steps")
+    assert 0 < reached < n
+    assert np.array_equal(h, ref_h)
+
+
+@pytest.mark.parametrize("n", [0, 1, 9, 4097, 300001])
+def test_anchor_init_matches_oracle(n):
+    g = (philox.normal(90, n % 7, max(n, 1))[:n]).astype(np.float32)
+    if n > 8:
+        g[:4] = 0.0
+        g[4:8] = g[8]  # ties
+    for frac in (0.1, 0.5, 1.0):
+        got = lv.anchor_init(torch.as_tensor(g, device="cuda"), frac).cpu().numpy()
+        assert np.array_equal(got, oracle.prune.anchor_init(g, frac)), (n, frac)
+
+
+def test_graph_opts_bad_arguments():
+    gs = lv.Scene.from_arrays(scene_at(uniform_points(50, 1)))
+    f = torch.ones((50, 2), device="cuda")
+    with pytest.raises(lv.LvError):
+        lv.Graph.knn(gs, f, 4, kind="feature_rbf", bandwidth=0.0)
+    with pytest.raises(lv.LvError):
+        lv.anchor_init(torch.ones(5, device="cuda"), 0.0)

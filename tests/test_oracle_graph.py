@@ -89,3 +89,61 @@ def test_zero_row_gets_self_loop():
     cs, vs = col[rp[7]:rp[8]], val[rp[7]:rp[8]]
     assert list(cs) == [7] and vs[0] == 1.0
     assert np.all(val > 0)
+
+
+# ------------------------------------------------- the paper's Eq. 7 / Eq. 9
+def test_feature_rbf_graph_definition():
+    n, k, b = 500, 8, 0.7
+    x = rand_points(n, 31)
+    f = np.random.default_rng(32).normal(size=(n, 6)).astype(F32)
+    p = np.random.default_rng(33).uniform(0, 1, n).astype(F32)
+    rp, col, val = graph.feature_rbf_graph(x, f, k, b, unary=p)
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    assert np.array_equal(A, A.T)  # symmetric bit for bit
+    idx, _ = graph.knn(x, k)
+    g = f.astype(np.float64) / np.linalg.norm(f.astype(np.float64), axis=1, keepdims=True)
+    D = cdist(g, g)
+    sf = np.median(D[np.arange(n)[:, None], idx])
+    for i in range(0, n, 23):
+        for j in idx[i]:
+            ref = np.exp(-D[i, j] ** 2 / (float(F32(b)) * sf ** 2)) * np.sqrt(float(p[i]) * float(p[j]))
+            assert abs(A[i, j] - ref) <= 1e-6 * ref + 1e-12
+    # no self-loops, no row normalisation; unary 1 is the plain kernel
+    assert np.all(np.diag(A) == 0)
+    rp1, col1, val1 = graph.feature_rbf_graph(x, f, k, b)
+    A1 = np.zeros((n, n))
+    for i in range(n):
+        A1[i, col1[rp1[i]:rp1[i + 1]]] = val1[rp1[i]:rp1[i + 1]]
+    sq = np.sqrt(p.astype(np.float64))
+    assert np.allclose(A, A1 * sq[:, None] * sq[None, :], rtol=2e-7, atol=1e-12)
+
+
+def test_feature_rbf_graph_binarised():
+    n, k = 400, 10
+    x = rand_points(n, 41)
+    f = np.random.default_rng(42).normal(size=(n, 3)).astype(F32)
+    rp, col, val = graph.feature_rbf_graph(x, f, k, 0.05, binarize=1e-5)
+    rpw, colw, valw = graph.feature_rbf_graph(x, f, k, 0.05)
+    assert np.all(val == 1.0)
+    kept = {(i, int(c)) for i in range(n) for c in col[rp[i]:rp[i + 1]]}
+    ref = {(i, int(c)) for i in range(n) for c, v in zip(colw[rpw[i]:rpw[i + 1]], valw[rpw[i]:rpw[i + 1]])
+           if float(v) > float(F32(1e-5)) * (1 + 1e-6)}
+    assert ref <= kept and len(kept) < len(colw)
+
+
+def test_anchor_init_and_reach():
+    from oracle import prune
+    rng = np.random.default_rng(51)
+    g = rng.normal(size=1000).astype(F32)
+    g0 = prune.anchor_init(g, 0.1)
+    npos = int(np.sum(g > 0))
+    k = int(np.ceil(0.1 * npos))
+    assert np.count_nonzero(g0) == k
+    top = np.sort(g[g > 0])[::-1][:k]
+    assert np.array_equal(np.sort(g0[g0 != 0])[::-1], top)
+    gt = rng.normal(size=(1000, 2)).astype(F32)
+    p = rng.uniform(size=1000).astype(F32)
+    h = prune.reach_unary(gt, p)
+    assert np.array_equal(h[:, 1], np.where(gt[:, 1] > 0, p, 0).astype(F32))
