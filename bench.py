@@ -314,8 +314,34 @@ def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
         byts = 4 * (n + 1) + nnz * 8 + 2 * n * Dg * 4
         dres[name] = {"ms_per_step": round(t * 1e3, 4), "GBs": round(byts / t / 1e9, 1),
                       "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4)}
-    res["diffuse"] = dres
     G.close()
+    # the paper's segmentation diffusion: binarised Eq. 7 / Eq. 9 graph with a
+    # unary term, anchors from the uplifted mask, 10 steps, reached nodes
+    log("bench: segmentation diffusion (Eq. 7 / Eq. 9 graph)")
+    unary = torch.rand(n, device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    kw = dict(kind="feature_rbf", bandwidth=0.5, unary=unary, binarize=1e-5)
+    Gs = lv.Graph.knn(s, f64, 16, **kw)
+    Gs.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Gs = lv.Graph.knn(s, f64, 16, **kw)
+    torch.cuda.synchronize()
+    t_sg = time.perf_counter() - t0
+    g0 = lv.anchor_init(f1.reshape(-1).contiguous(), 0.1)
+    gT = Gs.diffuse(g0, 10, scene=s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g0 = lv.anchor_init(f1.reshape(-1).contiguous(), 0.1)
+    gT = Gs.diffuse(g0, 10, scene=s, out=gT)
+    h = lv.reach_unary(gT, unary)
+    torch.cuda.synchronize()
+    t_seg = time.perf_counter() - t0
+    dres["segmentation"] = {"graph_build_ms": round(t_sg * 1e3, 3), "graph_nnz": int(Gs.csr()[1].shape[0]),
+                            "anchors": int((g0 > 0).sum()), "steps": 10,
+                            "anchors_diffuse_reach_ms": round(t_seg * 1e3, 3),
+                            "reached": int((h > 0).sum())}
+    Gs.close()
+    res["diffuse"] = dres
     s.close()
     return res
 
