@@ -96,8 +96,7 @@ const char* lv_version(void);
  * opacity [n]: device FP32 arrays, read (not retained) by the call.  The
  * library derives the covariances R diag(s)^2 R^T and keeps its own copy
  * (48 bytes per Gaussian).  n = 0 is valid.  Errors: LV_ERR_INVALID_ARG
- * (null pointers with n > 0, n >= 2^28: the sorted tile lists keep a
- * Gaussian id in 28 bits), LV_ERR_OUT_OF_MEMORY. */
+ * (null pointers with n > 0, n >= 2^31), LV_ERR_OUT_OF_MEMORY. */
 lv_status lv_scene_create(const float* means, const float* scales, const float* quats,
                           const float* opacity, int64_t n, void* stream, lv_scene** out);
 lv_status lv_scene_destroy(lv_scene* scene);
@@ -183,7 +182,7 @@ lv_status lv_accum_finalize_count(lv_accum* acc, float* out_feat, void* stream);
  * the lower index.  keep (device uint8 [n]) gets 1 for kept Gaussians and 0
  * for the others.  Values are ordered as IEEE floats (-0 below +0).  Scratch
  * (about 16 bytes per Gaussian) comes from the stream-ordered allocator.
- * Errors: LV_ERR_INVALID_ARG (n < 0 or n >= 2^28, k outside [0, n], null
+ * Errors: LV_ERR_INVALID_ARG (n < 0 or n >= 2^31, k outside [0, n], null
  * buffers with n > 0), LV_ERR_DEVICE. */
 lv_status lv_prune_by_weight(const float* wsum, int64_t n, int64_t k, uint8_t* keep, void* stream);
 /* Anchor initialisation of a diffusion (appendix on diffusion for

@@ -191,7 +191,7 @@ int ceil_log2(int64_t x) {
 }
 
 // Structure of one chunk of views: everything up to the tile ranges.  On
-// return, the sorted pair values (Gaussian ids with quadrant bits) are in *ids, the ranges in
+// return, the sorted pair values (Gaussian ids) are in *ids, the ranges in
 // ws.ranges with row stride *stride, and the pair count in *P.
 lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, int mv,
                           hipStream_t s, const uint32_t** ids, int* stride,
@@ -281,7 +281,6 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   HIP_TRY(ws.pv1.ensure(4 * total + 4, s));
   HIP_TRY(ws.hist2.ensure(4 * sort_hist_size(mv, max_len), s));
   HIP_TRY(launch_duplicate(sval, ws.off.as<uint32_t>(), ws.srect.as<uint2>(), ws.scnt.as<uint32_t>(),
-                           ws.rec.as<Rec>(),
                            ws.geom.as<ViewGeom>(), n, mv, ws.pk0.as<uint32_t>(),
                            ws.pv0.as<uint32_t>(), s));
   // one pass (up to 2048 tiles): the tile ranges come from the pass's scanned
@@ -327,8 +326,7 @@ lv_status lv_scene_create(const float* means, const float* scales, const float* 
                           const float* opacity, int64_t n, void* stream, lv_scene** out) {
   if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (n < 0 || n >= kMaxGaussians)
-    return fail(LV_ERR_INVALID_ARG, "n = %lld out of range [0, 2^28)", (long long)n);
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if (n > 0 && (!means || !scales || !quats || !opacity))
     return fail(LV_ERR_INVALID_ARG, "null scene array");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -600,7 +598,7 @@ lv_status lv_accum_finalize_count(lv_accum* a, float* out_feat, void* stream) {
 }
 
 lv_status lv_prune_by_weight(const float* wsum, int64_t n, int64_t k, uint8_t* keep, void* stream) {
-  if (n < 0 || n >= kMaxGaussians) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if (k < 0 || k > n) return fail(LV_ERR_INVALID_ARG, "k = %lld not in [0, n = %lld]", (long long)k, (long long)n);
   if (n > 0 && (!wsum || !keep)) return fail(LV_ERR_INVALID_ARG, "null buffer");
   HIP_TRY(launch_prune(wsum, n, k, keep, static_cast<hipStream_t>(stream)));
@@ -608,7 +606,7 @@ lv_status lv_prune_by_weight(const float* wsum, int64_t n, int64_t k, uint8_t* k
 }
 
 lv_status lv_anchor_init(const float* g, int64_t n, float fraction, float* g0, void* stream) {
-  if (n < 0 || n >= kMaxGaussians) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if (!(fraction > 0.0f && fraction <= 1.0f)) return fail(LV_ERR_INVALID_ARG, "fraction must be in (0, 1]");
   if (n > 0 && (!g || !g0)) return fail(LV_ERR_INVALID_ARG, "null buffer");
   HIP_TRY(launch_anchor_init(g, n, fraction, g0, static_cast<hipStream_t>(stream)));
@@ -1041,10 +1039,8 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
     }
     out->tile_start[max_tiles] = run;
   }
-  if (out->ids && out->ids_capacity >= P && P > 0) {
+  if (out->ids && out->ids_capacity >= P && P > 0)
     HIP_TRY(hipMemcpy(out->ids, ids, 4 * (size_t)P, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < P; i++) out->ids[i] &= kIdMask;  // without the quadrant bits
-  }
   return LV_OK;
 }
 

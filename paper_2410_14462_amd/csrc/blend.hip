@@ -9,12 +9,12 @@
 // all of them).  Waves never wait for each other.  Per step of 64 Gaussians
 // of the tile's list:
 //   0. lane j loads Gaussian j's record (vector loads, all in flight
-//      together) and tests whether its alpha >= 1/255 region can touch the
-//      quadrant (exact minimum of the conic over the quadrant, conservative
-//      slack); a ballot gives the step's hit mask;
+//      together), leaves it in LDS and tests whether its alpha >= 1/255
+//      region can touch the quadrant (exact minimum of the conic over the
+//      quadrant, conservative slack); a ballot gives the step's hit mask;
 //   A. walk: a scalar loop over the hit Gaussians in order; each lane
-//      evaluates the Gaussian at its pixel (record fields broadcast with
-//      readlane), every decision in the S32 sequence;
+//      evaluates the Gaussian at its pixel (the record read from LDS at one
+//      address, a broadcast), every decision in the S32 sequence;
 //   B. a Gaussian with some w > 0 takes the next of 32 LDS rows (its weights
 //      at the 64 pixels).  A full set of rows (and the last, partial one) is
 //      flushed: U_rows += W_rows F on the matrix cores, one global atomic per
@@ -48,12 +48,40 @@ __device__ __forceinline__ float load_feature(const void* map, int64_t idx, floa
 // Map of set sd for view v (NULL: the set does not take the view).
 __device__ __forceinline__ const void* map_of(const SetDesc& sd, int v) { return gptr(sd.maps)[v]; }
 
+// Can -power(d) <= tau hold for some d in the rectangle [X0,X1] x [Y0,Y1]
+// (offsets from the Gaussian's centre)?  -power = (L11 dx + L12 dy)^2 +
+// (L22 dy)^2 is convex with its minimum at 0, so outside the rectangle its
+// minimum over the rectangle lies on an edge; along each edge it is a 1D
+// quadratic with a clamped vertex.  Evaluated in the factored form, which
+// stays accurate for thin Gaussians.
+__device__ __forceinline__ float neg_power(float L11, float L12, float L22, float dx, float dy) {
+  const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
+  return __builtin_fmaf(u, u, w * w);
+}
+
+__device__ __forceinline__ bool region_hits(float4 r0, float4 r1, float X0, float X1, float Y0,
+                                            float Y1) {
+  const float tau = r1.z;
+  if (!(tau >= 0.0f)) return false;
+  if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
+  const float L11 = r0.z, L12 = r0.w, L22 = r1.x;
+  const float ky = -(L11 * L12) / __builtin_fmaf(L12, L12, L22 * L22);  // edge dx = X: dy* = ky X
+  const float kx = -L12 / L11;                                          // edge dy = Y: dx* = kx Y
+  const float dy0 = fminf(fmaxf(ky * X0, Y0), Y1);
+  const float dy1 = fminf(fmaxf(ky * X1, Y0), Y1);
+  const float dx0 = fminf(fmaxf(kx * Y0, X0), X1);
+  const float dx1 = fminf(fmaxf(kx * Y1, X0), X1);
+  const float m0 = fminf(neg_power(L11, L12, L22, X0, dy0), neg_power(L11, L12, L22, X1, dy1));
+  const float m1 = fminf(neg_power(L11, L12, L22, dx0, Y0), neg_power(L11, L12, L22, dx1, Y1));
+  return fminf(m0, m1) <= tau;
+}
+
 // The quadrant a workgroup handles.  Workgroups go to the 8 XCDs
 // round-robin, so the four quadrant waves of a tile get ids that are equal
 // mod 8 and consecutive within the XCD: they share that XCD's L2 for the
 // tile's records.
 struct Quad {
-  int v, tile, cg, qx, qy, quad;  // quad: 2 (y / 8) + (x / 8) within the tile
+  int v, tile, cg, qx, qy;
   uint2 rg;
   ViewGeom g;
 };
@@ -73,7 +101,6 @@ __device__ __forceinline__ bool decode_quad(const uint2* __restrict__ ranges,
   if (q.tile >= q.g.TX * q.g.TY) return false;
   q.rg = ranges[(int64_t)q.v * tiles_stride + q.tile];
   if (q.rg.y <= q.rg.x) return false;
-  q.quad = quad;
   const int tx = q.tile % q.g.TX, ty = q.tile / q.g.TX;
   q.qx = tx * kTile + (quad & 1) * 8;
   q.qy = ty * kTile + (quad >> 1) * 8;
@@ -104,22 +131,30 @@ __device__ __forceinline__ void walk_init(const Quad& q, int lane, Walk& s) {
   s.alive = px < q.g.W && py < q.g.H;
 }
 
-// Step 0: the next G entries of the tile's list, one per lane; the entries
-// whose quadrant bit is set (the hit mask) load their records, centres made
-// tile-relative, into rs[lane] = {(cx, cy, L11, L12), (L22, opacity, -, -)}.
-// pv: this lane's list entry; my_id gets its Gaussian id.
-__device__ __forceinline__ uint64_t step_hits(const Rec* __restrict__ vrec, uint32_t pv, int quad,
-                                              const Walk& s, int lane, float4 (*rs)[2],
-                                              uint32_t& my_id) {
-  const bool hit = (pv >> (kIdBits + quad)) & 1u;
-  my_id = pv & kIdMask;
-  if (hit) {
-    float4 r0 = vrec[my_id].r0;
-    const float4 r1 = vrec[my_id].r1;
-    tile_centre(r0, r1, s.ocx, s.ocy, r0.x, r0.y);
-    rs[lane][0] = r0;
-    rs[lane][1] = r1;
+// Step 0: records of Gaussians [base, base + cnt) one per lane, centres made
+// tile-relative and left in rs[lane] = {(cx, cy, L11, L12), (L22, opacity,
+// tau, -)} for the walk; the hit mask (the alpha >= 1/255 region can touch
+// the quadrant).
+__device__ __forceinline__ uint64_t step_records(const Rec* __restrict__ vrec,
+                                                 const uint32_t* __restrict__ ids, uint32_t base,
+                                                 int cnt, int lane, const Walk& s, uint32_t& my_id,
+                                                 float4 (*rs)[2]) {
+  float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float4 q1 = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+  my_id = 0;
+  if (lane < cnt) {
+    my_id = ids[base + lane];
+    q0 = vrec[my_id].r0;
+    q1 = vrec[my_id].r1;
+    // centre relative to the tile (see Rec)
+    const uint32_t lo = __float_as_uint(q1.w);
+    q0.x = (q0.x - s.ocx) + __uint_as_float(lo << 16);
+    q0.y = (q0.y - s.ocy) + __uint_as_float(lo & 0xFFFF0000u);
   }
+  rs[lane][0] = q0;
+  rs[lane][1] = q1;
+  const float X0 = s.qx0 - q0.x, Y0 = s.qy0 - q0.y;
+  const bool hit = lane < cnt && region_hits(q0, q1, X0, X0 + 7.0f, Y0, Y0 + 7.0f);
   return __ballot(hit);
 }
 
@@ -525,15 +560,11 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   uint64_t covered = 0ull;  // pixels with a contribution (statistics)
   uint32_t ncontrib = 0u;   // contributions of the quadrant (statistics)
   const Rec* vrec = rec + (int64_t)q.v * n;
-  const uint32_t end = q.rg.y;
-  // list entries one step ahead: the next step's are in flight during a step
-  uint32_t pv = q.rg.x + lane < end ? ids[q.rg.x + lane] : 0u;
-  for (uint32_t base = q.rg.x; base < end; base += G) {
+  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
     if (__ballot(s.alive) == 0ull) break;
-    const uint32_t pvn = base + G + lane < end ? ids[base + G + lane] : 0u;
+    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
     uint32_t my_id;
-    const uint64_t hits = step_hits(vrec, pv, q.quad, s, lane, Rs, my_id);
-    pv = pvn;
+    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, my_id, Rs);
     if (!hits) continue;
     __syncthreads();  // records in LDS (one wave per workgroup: orders LDS)
 
@@ -626,15 +657,11 @@ __global__ __launch_bounds__(64) void render_kernel(
   Walk s;
   walk_init(q, lane, s);
   const Rec* vrec = rec + (int64_t)q.v * n;
-  const uint32_t end = q.rg.y;
-  // list entries one step ahead: the next step's are in flight during a step
-  uint32_t pv = q.rg.x + lane < end ? ids[q.rg.x + lane] : 0u;
-  for (uint32_t base = q.rg.x; base < end; base += G) {
+  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
     if (__ballot(s.alive) == 0ull) break;
-    const uint32_t pvn = base + G + lane < end ? ids[base + G + lane] : 0u;
+    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
     uint32_t my_id;
-    const uint64_t hits = step_hits(vrec, pv, q.quad, s, lane, Rs, my_id);
-    pv = pvn;
+    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, my_id, Rs);
     if (!hits) continue;
     __syncthreads();  // records in LDS (one wave per workgroup: orders LDS)
     for (uint64_t h = hits; h; h &= h - 1) {

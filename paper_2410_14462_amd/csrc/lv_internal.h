@@ -46,66 +46,6 @@ struct Rec {
   float4 r0, r1;
 };
 
-// Values of the sorted tile lists: the Gaussian id in the low kIdBits bits
-// and, in bit kIdBits + k, whether the Gaussian's alpha >= 1/255 region can
-// reach quadrant k = 2 (y / 8) + (x / 8) of the tile (its 8x8 pixel quarters,
-// x, y relative to the tile).
-constexpr int kIdBits = 28;
-constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
-constexpr int64_t kMaxGaussians = (int64_t)1 << kIdBits;
-
-// Can -power(d) <= tau hold for some d in the rectangle [X0,X1] x [Y0,Y1]
-// (offsets from the Gaussian's centre)?  -power = (L11 dx + L12 dy)^2 +
-// (L22 dy)^2 is convex with its minimum at 0, so outside the rectangle its
-// minimum over the rectangle lies on an edge; along each edge it is a 1D
-// quadratic with a clamped vertex.  Evaluated in the factored form, which
-// stays accurate for thin Gaussians.
-__device__ __forceinline__ float neg_power(float L11, float L12, float L22, float dx, float dy) {
-  const float u = __builtin_fmaf(L12, dy, L11 * dx), w = L22 * dy;
-  return __builtin_fmaf(u, u, w * w);
-}
-
-__device__ __forceinline__ bool region_hits(float4 r0, float4 r1, float X0, float X1, float Y0,
-                                            float Y1) {
-  const float tau = r1.z;
-  if (!(tau >= 0.0f)) return false;
-  if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
-  const float L11 = r0.z, L12 = r0.w, L22 = r1.x;
-  const float ky = -(L11 * L12) / __builtin_fmaf(L12, L12, L22 * L22);  // edge dx = X: dy* = ky X
-  const float kx = -L12 / L11;                                          // edge dy = Y: dx* = kx Y
-  const float dy0 = fminf(fmaxf(ky * X0, Y0), Y1);
-  const float dy1 = fminf(fmaxf(ky * X1, Y0), Y1);
-  const float dx0 = fminf(fmaxf(kx * Y0, X0), X1);
-  const float dx1 = fminf(fmaxf(kx * Y1, X0), X1);
-  const float m0 = fminf(neg_power(L11, L12, L22, X0, dy0), neg_power(L11, L12, L22, X1, dy1));
-  const float m1 = fminf(neg_power(L11, L12, L22, dx0, Y0), neg_power(L11, L12, L22, dx1, Y1));
-  return fminf(m0, m1) <= tau;
-}
-
-// Centre of record (r0, r1) relative to the first pixel centre (ox + 0.5,
-// oy + 0.5) of its tile, with the low parts added (see Rec).
-__device__ __forceinline__ void tile_centre(const float4& r0, const float4& r1, float ocx, float ocy,
-                                            float& cx, float& cy) {
-  const uint32_t lo = __float_as_uint(r1.w);
-  cx = (r0.x - ocx) + __uint_as_float(lo << 16);
-  cy = (r0.y - ocy) + __uint_as_float(lo & 0xFFFF0000u);
-}
-
-// Quadrant bits (kIdBits + k) of a Gaussian for the tile with pixel origin
-// (ox, oy): quadrant k spans pixel offsets [8 (k & 1), 8 (k & 1) + 7] x
-// [8 (k >> 1), 8 (k >> 1) + 7] from the tile's first pixel centre.
-__device__ __forceinline__ uint32_t quad_bits(float4 r0, const float4& r1, int ox, int oy) {
-  float cx, cy;
-  tile_centre(r0, r1, (float)ox + 0.5f, (float)oy + 0.5f, cx, cy);
-  uint32_t m = 0u;
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const float X0 = (float)(8 * (k & 1)) - cx, Y0 = (float)(8 * (k >> 1)) - cy;
-    if (region_hits(r0, r1, X0, X0 + 7.0f, Y0, Y0 + 7.0f)) m |= 1u << (kIdBits + k);
-  }
-  return m;
-}
-
 // S32 exponential for x <= 0: Cody-Waite reduction to |r| <= ln2/2, degree-7
 // Taylor polynomial in Horner form with fmaf, scaling by 2^k; 0 below -80.
 // Branch-free: the polynomial runs on max(x, -80) and the result is selected.
@@ -222,10 +162,9 @@ hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t 
                        unsigned long long* totals, uint32_t* tmp, hipStream_t s);
 
 // (tile, Gaussian) pairs of the depth-sorted items, given their ids, pair
-// offsets, rects and counts in the same sorted order; pair values carry the
-// quadrant bits (records rec [m][n]).
+// offsets, rects and counts in the same sorted order.
 hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off,
-                            const uint2* sorted_rect, const uint32_t* sorted_cnt, const Rec* rec,
+                            const uint2* sorted_rect, const uint32_t* sorted_cnt,
                             const ViewGeom* geom, int64_t n, int m, uint32_t* pair_key,
                             uint32_t* pair_val, hipStream_t s);
 

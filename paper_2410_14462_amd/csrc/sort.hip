@@ -428,17 +428,13 @@ __global__ void seg_kernel(const uint32_t* __restrict__ off, int64_t n, int m,
 // exclusive scan of the counts in this order), so the wave walks them 64 at a
 // time, each lane finding the item that owns its pair by a binary search over
 // the wave's inclusive count prefix.  Within an item, tiles go row by row.
-// The pair value is the Gaussian id with the tile's quadrant bits; the
-// items' records wait in LDS for the lanes that need them.
 __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restrict__ sval,
                                                         const uint32_t* __restrict__ off,
                                                         const uint2* __restrict__ srect,
                                                         const uint32_t* __restrict__ scnt,
-                                                        const Rec* __restrict__ rec,
                                                         const ViewGeom* __restrict__ geom, int64_t n,
                                                         uint32_t* __restrict__ pkey,
                                                         uint32_t* __restrict__ pval) {
-  __shared__ float4 rl[256][2];  // records of the block's items
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   const int lane = threadIdx.x & 63;
@@ -454,13 +450,8 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
       x0 = r.x & 0xFFFFu;
       y0 = r.x >> 16;
       w = (r.y & 0xFFFFu) - x0;
-      const Rec& rc = rec[(int64_t)v * n + gi];
-      rl[threadIdx.x][0] = rc.r0;
-      rl[threadIdx.x][1] = rc.r1;
     }
   }
-  __builtin_amdgcn_wave_barrier();  // rl is written and read by this wave only
-  const float4(*wrl)[2] = rl + (threadIdx.x - lane);
   uint32_t incl = c;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -484,9 +475,8 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
     const uint32_t og = __shfl(gi, pos, 64);
     if (slot < total) {
       const uint32_t dy = kk / ow;
-      const uint32_t tx = ox + (kk - dy * ow), ty = oy + dy;
-      pkey[p0 + slot] = hv | (ty * TX + tx);
-      pval[p0 + slot] = og | quad_bits(wrl[pos][0], wrl[pos][1], (int)tx * kTile, (int)ty * kTile);
+      pkey[p0 + slot] = hv | ((oy + dy) * TX + ox + (kk - dy * ow));
+      pval[p0 + slot] = og;
     }
   }
 }
@@ -576,12 +566,12 @@ hipError_t scan_counts(const uint32_t* cnt, const uint32_t* sorted_val, int64_t 
 }
 
 hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off,
-                            const uint2* sorted_rect, const uint32_t* sorted_cnt, const Rec* rec,
+                            const uint2* sorted_rect, const uint32_t* sorted_cnt,
                             const ViewGeom* geom, int64_t n, int m, uint32_t* pair_key,
                             uint32_t* pair_val, hipStream_t s) {
   if (n == 0 || m == 0) return hipSuccess;
   hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
-                     s, sorted_val, off, sorted_rect, sorted_cnt, rec, geom, n, pair_key, pair_val);
+                     s, sorted_val, off, sorted_rect, sorted_cnt, geom, n, pair_key, pair_val);
   return hipGetLastError();
 }
 
