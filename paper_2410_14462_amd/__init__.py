@@ -184,11 +184,21 @@ def camera_struct(cam):
     return c
 
 
+_CAM_DTYPE = np.dtype([("R", np.float32, 9), ("t", np.float32, 3), ("f", np.float32, 5),
+                       ("wh", np.int32, 3)])
+assert _CAM_DTYPE.itemsize == ctypes.sizeof(lv_camera)
+
+
 def camera_array(cams):
-    arr = (lv_camera * max(1, len(cams)))()
-    for i, cam in enumerate(cams):
-        arr[i] = camera_struct(cam)
-    return arr
+    """lv_camera[m] (same layout as the C struct), filled column-wise."""
+    m = len(cams)
+    a = np.zeros(max(1, m), _CAM_DTYPE)
+    if m:
+        a["R"][:m] = np.asarray([c.R for c in cams], np.float32).reshape(m, 9)
+        a["t"][:m] = np.asarray([c.t for c in cams], np.float32).reshape(m, 3)
+        a["f"][:m] = np.asarray([(c.fx, c.fy, c.cx, c.cy, c.znear) for c in cams], np.float32)
+        a["wh"][:m, :2] = np.asarray([(c.width, c.height) for c in cams], np.int64)
+    return (lv_camera * max(1, m)).from_buffer(a)
 
 
 def _map_table(maps, dtype):
