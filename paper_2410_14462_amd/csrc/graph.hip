@@ -66,13 +66,19 @@ __global__ void bbox_partial_kernel(const float4* __restrict__ c, int64_t n, flo
 // grid parameters: gp[0..2] = box minimum, gp[3..5] = cells per unit length
 // (0 for a flat axis), gp[6..8] = cell edge lengths
 __global__ void grid_params_kernel(const float* __restrict__ part, int nparts, int G, float* __restrict__ gp) {
-  if (threadIdx.x != 0) return;
+  // one wave: lanes stride over the partials, then a wave reduction
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nparts; b++)
+  for (int b = threadIdx.x; b < nparts; b += 64)
     for (int a = 0; a < 3; a++) {
       lo[a] = fminf(lo[a], part[6 * b + a]);
       hi[a] = fmaxf(hi[a], part[6 * b + 3 + a]);
     }
+  for (int a = 0; a < 3; a++)
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+    }
+  if (threadIdx.x != 0) return;
   for (int a = 0; a < 3; a++) {
     const float ext = hi[a] - lo[a];
     gp[a] = lo[a];
@@ -229,24 +235,37 @@ __global__ void select_hist_kernel(const double* __restrict__ v, int64_t N, int 
 // count passes the residual rank; the histogram is cleared for the next round
 __global__ __launch_bounds__(1024) void select_pick_kernel(unsigned int* __restrict__ hist, int shift,
                                                            unsigned long long* __restrict__ st) {
-  __shared__ unsigned long long cum[2][kSelBins + 1];
-  const int t = threadIdx.x;
-  if (t < 2) {
-    unsigned long long run = 0;
-    for (int d = 0; d < kSelBins; d++) {
-      cum[t][d] = run;
-      run += hist[t * kSelBins + d];
+  // thread t owns bins 2t, 2t + 1 of each target; block-wide exclusive scan
+  __shared__ unsigned long long wsum[2][16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  unsigned long long rank[2], part[2], c0[2], c1[2];
+#pragma unroll
+  for (int g = 0; g < 2; g++) {
+    rank[g] = st[2 + g];
+    c0[g] = hist[g * kSelBins + 2 * t];
+    c1[g] = hist[g * kSelBins + 2 * t + 1];
+    unsigned long long incl = c0[g] + c1[g];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
     }
-    cum[t][kSelBins] = run;
-    const unsigned long long rank = st[2 + t];
-    int dd = kSelBins - 1;
-    for (int d = 0; d < kSelBins; d++)
-      if (rank < cum[t][d + 1]) {
-        dd = d;
-        break;
-      }
-    st[t] |= (unsigned long long)dd << shift;
-    st[2 + t] = rank - cum[t][dd];
+    part[g] = incl - (c0[g] + c1[g]);  // exclusive within the wave
+    if (lane == 63) wsum[g][w] = incl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < 2; g++) {
+    unsigned long long base = part[g];
+    for (int q = 0; q < w; q++) base += wsum[g][q];
+    // the bin whose [cum, cum + count) holds the rank (exactly one thread)
+    if (rank[g] >= base && rank[g] < base + c0[g]) {
+      st[g] |= (unsigned long long)(2 * t) << shift;
+      st[2 + g] = rank[g] - base;
+    } else if (rank[g] >= base + c0[g] && rank[g] < base + c0[g] + c1[g]) {
+      st[g] |= (unsigned long long)(2 * t + 1) << shift;
+      st[2 + g] = rank[g] - base - c0[g];
+    }
   }
   __syncthreads();
   for (int e = t; e < 2 * kSelBins; e += blockDim.x) hist[e] = 0u;
@@ -384,20 +403,21 @@ __global__ void fill_rows_kernel(const int32_t* __restrict__ idx, const double* 
   uw[start[j] + (uint32_t)k + slot] = w[e];
 }
 
-// per row: sort by column (ties: larger weight first), keep one entry per
-// column with the larger weight if it is positive, sum in column order; a
-// row left empty gets the self-loop (weight 1).  len[i] = entries kept.
+// per row of more than 64 entries (the others are merged by one wave each,
+// below): sort by column (ties: larger weight first), keep one entry per
+// column with the larger weight if it passes, sum in column order; a row
+// left empty gets the self-loop (weight 1).  len[i] = entries kept.
 __global__ void merge_rows_kernel(int64_t n, int k, const uint32_t* __restrict__ start,
                                   const uint32_t* __restrict__ indeg, int32_t* __restrict__ ucol,
                                   double* __restrict__ uw, uint32_t* __restrict__ len,
                                   double* __restrict__ rsum, double thresh, bool binarize,
                                   bool self_loops) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || len[i] != 0xFFFFFFFFu) return;  // rows of more than 64 entries only
   int32_t* cl = ucol + start[i];
   double* wv = uw + start[i];
   const int m = k + (int)indeg[i];
-  for (int a = 1; a < m; a++) {  // insertion sort (rows hold tens of entries)
+  for (int a = 1; a < m; a++) {  // insertion sort
     const int32_t c = cl[a];
     const double x = wv[a];
     int b = a - 1;
@@ -429,6 +449,70 @@ __global__ void merge_rows_kernel(int64_t n, int k, const uint32_t* __restrict__
   }
   len[i] = (uint32_t)u;
   rsum[i] = s;
+}
+
+// The same for rows of at most 64 entries, one wave per row: a bitonic sort
+// of (column ascending, weight descending) across the lanes, the first of
+// each column kept if its weight passes, compaction by ballot.  Rows with
+// more entries are left to merge_rows_kernel (flagged with len = ~0).
+__device__ __forceinline__ bool before(int32_t c1, double x1, int32_t c2, double x2) {
+  return c1 < c2 || (c1 == c2 && x1 > x2);
+}
+
+__global__ __launch_bounds__(256) void merge_rows_wave_kernel(int64_t n, int k, const uint32_t* __restrict__ start,
+                                                              const uint32_t* __restrict__ indeg,
+                                                              int32_t* __restrict__ ucol, double* __restrict__ uw,
+                                                              uint32_t* __restrict__ len,
+                                                              double* __restrict__ rsum, double thresh,
+                                                              bool binarize, bool self_loops) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int m = k + (int)indeg[i];
+  if (m > 64) {  // wave-uniform
+    if (lane == 0) len[i] = 0xFFFFFFFFu;
+    return;
+  }
+  int32_t* cl = ucol + start[i];
+  double* wv = uw + start[i];
+  int32_t c = lane < m ? cl[lane] : 0x7FFFFFFF;
+  double x = lane < m ? wv[lane] : -INFINITY;
+  for (int kk = 2; kk <= 64; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      const int32_t pc = __shfl_xor(c, j, 64);
+      const double px = __shfl_xor(x, j, 64);
+      const bool up = (lane & kk) == 0;
+      const bool low = (lane & j) == 0;
+      // the lower lane of an ascending pair keeps the earlier element
+      const bool take = (low == up) ? before(pc, px, c, x) : before(c, x, pc, px);
+      if (take) {
+        c = pc;
+        x = px;
+      }
+    }
+  const int32_t prev = __shfl_up(c, 1, 64);
+  const bool keep = lane < m && (lane == 0 || prev != c) && x > thresh;
+  const uint64_t kb = __ballot(keep);
+  const uint32_t pos = (uint32_t)__popcll(kb & (lane ? (~0ull >> (64 - lane)) : 0ull));
+  const double v = keep ? (binarize ? 1.0 : x) : 0.0;
+  if (keep) {
+    cl[pos] = c;
+    wv[pos] = v;
+  }
+  double sum = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  uint32_t u = (uint32_t)__popcll(kb);
+  if (lane == 0) {
+    if (u == 0 && self_loops) {  // self-loop
+      cl[0] = (int32_t)i;
+      wv[0] = 1.0;
+      u = 1;
+      sum = 1.0;
+    }
+    len[i] = u;
+    rsum[i] = sum;
+  }
 }
 
 __global__ void csr_out_kernel(int64_t n, const uint32_t* __restrict__ start,
@@ -582,6 +666,8 @@ hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats,
     if ((e = scan_counts(cap, nullptr, n, 1, start, sseg, sseg + 1, tot, stmp, s)) != hipSuccess) break;
     hipLaunchKernelGGL(fill_rows_kernel, dim3(grid1(nk)), dim3(256), 0, s, idx, w, n, k, start, fillpos, ucol, uw);
     const bool bin = rbf && gw.binarize > 0.0f;
+    hipLaunchKernelGGL(merge_rows_wave_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, n, k,
+                       start, indeg, ucol, uw, len, rsum, bin ? (double)gw.binarize : 0.0, bin, !rbf);
     hipLaunchKernelGGL(merge_rows_kernel, dim3(grid1(n)), dim3(256), 0, s, n, k, start, indeg, ucol, uw, len,
                        rsum, bin ? (double)gw.binarize : 0.0, bin, !rbf);
     if ((e = scan_counts(len, nullptr, n, 1, rp, sseg, sseg + 1, tot, stmp, s)) != hipSuccess) break;
