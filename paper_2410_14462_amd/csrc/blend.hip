@@ -450,8 +450,9 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   }
 
   // Gaussians with a contribution queue up in 32 LDS rows (row r: the
-  // Gaussian's weights at the 64 pixels; its id and its number of
-  // contributing pixels in lane r's ring_gid / ring_cnt).  When the rows are
+  // Gaussian's weights at the 64 pixels in Wt, its id and its number of
+  // contributing pixels in Rg[r] / Rc[r], read into lane r's ring_gid /
+  // ring_cnt when the rows are flushed).  When the rows are
   // full, and at the end, one flush: a batch of MFMAs (M = 32 rows) and one
   // round of atomics per group, so the matrix products run on full rows
   // whatever the number of contributing Gaussians per step of the walk; and
@@ -459,10 +460,13 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   // per lane pair, each lane summing half of the row in a fixed order.
   int queued = 0;        // rows [0, queued) hold Gaussians
   uint64_t pix = 0ull;   // pixels used by the queued rows
+  __shared__ uint32_t Rg[32], Rc[32];
   uint32_t ring_gid = 0u, ring_cnt = 0u;
 
   auto flush = [&](int count) {
     __syncthreads();  // ring rows written (one wave per workgroup: orders LDS)
+    ring_gid = Rg[lane & 31];
+    ring_cnt = Rc[lane & 31];
     const uint32_t rows = row_bits(pix);
     const float* wrow = Wt + (lane & 31) * kWtPitch + 8 * (lane >> 5);
     if constexpr (!MULTI) {
@@ -577,18 +581,29 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
     while (h) {
       h &= h - 1;
       const int jn = h ? (int)__builtin_ctzll(h) : j;
-      const float4 na = Rs[jn][0], nb = Rs[jn][1];
-      bool take;
-      const float wj = walk_rec(ra, rb, s, take);
-      const uint64_t msk = __ballot(take);
+      // wj: this lane's weight (0 where it takes no part), msk: the lanes
+      // with a contribution
+      const float dx = s.pxo - ra.x, dy = s.pyo - ra.y;
+      const float u = __builtin_fmaf(ra.w, dy, ra.z * dx), w = rb.x * dy;
+      const float al = fminf(kAlphaMax, rb.y * exp32_clamped(-__builtin_fmaf(u, u, w * w)));
+      // the next record into the same registers (no copies between hits)
+      ra = Rs[jn][0];
+      rb = Rs[jn][1];
+      const float Tn = s.T * (1.0f - al);
+      const bool ok = s.alive && al >= kAlphaMin;
+      const bool stop = ok && Tn < kTEps;
+      const bool take = ok && !stop;
+      const uint64_t msk = __builtin_amdgcn_ballot_w64(take);
+      const float wj = take ? al * s.T : 0.0f;
+      s.T = take ? Tn : s.T;
+      s.alive = s.alive && !stop;
       if (msk) {
         covered |= msk;
         ncontrib += (uint32_t)__popcll(msk);
         Wt[queued * kWtPitch + lane] = wj;
-        const uint32_t gj = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-        if (lane == queued) {
-          ring_gid = gj;
-          ring_cnt = (uint32_t)__popcll(msk);
+        if (lane == j) {  // lane j holds the Gaussian's id
+          Rg[queued] = my_id;
+          Rc[queued] = (uint32_t)__popcll(msk);
         }
         pix |= msk;
         if (++queued == 32) {
@@ -598,8 +613,6 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
         }
       }
       j = jn;
-      ra = na;
-      rb = nb;
     }
   }
   if (queued > 0) flush(queued);
