@@ -36,6 +36,9 @@ HBM_PEAK_GBS = 8000.0
 # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 ALU_PEAK_TFLOPS = 78.6
 ALU_PEAK_PACKED_TFLOPS = 157.3
+# Device-scope atomic updates in the L2: one 4-byte update per L2 channel per
+# clock, 8 XCDs x 16 channels x 2.4 GHz
+ATOMIC_PEAK_GPS = 307.2
 
 
 def log(*a):
@@ -156,6 +159,13 @@ def main():
                 "frac_of_packed_peak": round(alu_tflops / ALU_PEAK_PACKED_TFLOPS, 4),
                 "alg_flops": flops64},
     })
+    # the resource that binds this kernel: one atomic update per channel and
+    # one for beta per (Gaussian, view, 8x8 block) partial sum
+    if st64.get("partial_sums", -1) > 0:
+        upd = st64["partial_sums"] * (C + 1)
+        roof["l2_atomics"] = {"achieved_Gps": round(upd / t64 / 1e9, 1), "peak_Gps": ATOMIC_PEAK_GPS,
+                              "frac": round(upd / t64 / 1e9 / ATOMIC_PEAK_GPS, 4),
+                              "updates": int(upd), "partial_sums": int(st64["partial_sums"])}
 
     out = {
         "metric": METRIC,

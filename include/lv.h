@@ -203,10 +203,12 @@ lv_status lv_accum_destroy(lv_accum* acc);
 /* Work statistics of an accumulator since its creation or last reset
  * (synchronous): views processed, (tile, Gaussian) pairs, visible
  * (view, Gaussian) items, and -- only with LV_ACCUM_COUNTS, else -1 --
- * pixels with at least one counted Gaussian and counted (Gaussian, view,
- * pixel) contributions (the non-zeros of W). */
+ * pixels with at least one counted Gaussian, counted (Gaussian, view,
+ * pixel) contributions (the non-zeros of W) and partial sums: (Gaussian,
+ * view, 8x8 pixel block) triples with a contribution, each of which the
+ * blend adds to U, beta (and counts) with one atomic update per channel. */
 typedef struct lv_uplift_stats {
-    int64_t views, pairs, visible, covered_pixels, contributions;
+    int64_t views, pairs, visible, covered_pixels, contributions, partial_sums;
 } lv_uplift_stats;
 lv_status lv_accum_stats(lv_accum* acc, lv_uplift_stats* out);
 

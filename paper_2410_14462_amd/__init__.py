@@ -74,7 +74,8 @@ class lv_uplift_set(ctypes.Structure):
 
 class lv_uplift_stats(ctypes.Structure):
     _fields_ = [("views", ctypes.c_int64), ("pairs", ctypes.c_int64), ("visible", ctypes.c_int64),
-                ("covered_pixels", ctypes.c_int64), ("contributions", ctypes.c_int64)]
+                ("covered_pixels", ctypes.c_int64), ("contributions", ctypes.c_int64),
+                ("partial_sums", ctypes.c_int64)]
 
 
 assert ctypes.sizeof(lv_camera) == 80

@@ -377,7 +377,7 @@ lv_status lv_accum_create(lv_scene* sc, int32_t D, uint32_t flags, void* stream,
   hipError_t e = a->U.ensure(sizeof(float) * n1 * D, s);
   if (e == hipSuccess) e = a->beta.ensure(sizeof(beta_t) * n1, s);
   if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->counts.ensure(4 * n1, s);
-  if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->dstats.ensure(16, s);
+  if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->dstats.ensure(24, s);
   if (e != hipSuccess) {
     a->U.release(); a->beta.release(); a->counts.release(); a->dstats.release();
     delete a;
@@ -397,7 +397,7 @@ lv_status lv_accum_reset(lv_accum* a, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   size_t n = (size_t)a->scene->n;
   a->views = a->pairs = a->visible = 0;
-  if (a->dstats.p) HIP_TRY(hipMemsetAsync(a->dstats.p, 0, 16, s));
+  if (a->dstats.p) HIP_TRY(hipMemsetAsync(a->dstats.p, 0, 24, s));
   if (n == 0) return LV_OK;
   HIP_TRY(hipMemsetAsync(a->U.p, 0, sizeof(float) * n * a->D, s));
   HIP_TRY(hipMemsetAsync(a->beta.p, 0, sizeof(beta_t) * n, s));
@@ -638,11 +638,13 @@ lv_status lv_accum_stats(lv_accum* a, lv_uplift_stats* out) {
   out->visible = a->visible;
   out->covered_pixels = -1;
   out->contributions = -1;
+  out->partial_sums = -1;
   if (a->dstats.p) {
-    unsigned long long h[2];
-    HIP_TRY(hipMemcpy(h, a->dstats.p, 16, hipMemcpyDeviceToHost));
+    unsigned long long h[3];
+    HIP_TRY(hipMemcpy(h, a->dstats.p, 24, hipMemcpyDeviceToHost));
     out->covered_pixels = (int64_t)h[0];
     out->contributions = (int64_t)h[1];
+    out->partial_sums = (int64_t)h[2];
   }
   return LV_OK;
 }

@@ -563,6 +563,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   walk_init(q, lane, s);
   uint64_t covered = 0ull;  // pixels with a contribution (statistics)
   uint32_t ncontrib = 0u;   // contributions of the quadrant (statistics)
+  uint32_t nrows = 0u;      // Gaussians queued (statistics)
   const Rec* vrec = rec + (int64_t)q.v * n;
   for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
     if (__ballot(s.alive) == 0ull) break;
@@ -600,6 +601,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
       if (msk) {
         covered |= msk;
         ncontrib += (uint32_t)__popcll(msk);
+        nrows++;
         Wt[queued * kWtPitch + lane] = wj;
         if (lane == j) {  // lane j holds the Gaussian's id
           Rg[queued] = my_id;
@@ -622,6 +624,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
     if (sd.stats && lane == 0) {
       gatomic_add(&sd.stats[1], (unsigned long long)ncontrib);
       gatomic_add(&sd.stats[0], (unsigned long long)__popcll(covered));
+      gatomic_add(&sd.stats[2], (unsigned long long)nrows);
     }
   }
 }

@@ -182,7 +182,7 @@ struct SetDesc {
   float* U;                   // [n][D]
   beta_t* beta;               // [n] fixed point, units of 2^-35
   uint32_t* counts;           // [n] or null
-  unsigned long long* stats;  // [2] covered pixels, contributions; or null
+  unsigned long long* stats;  // [3] covered pixels, contributions, partial sums; or null
   int32_t D;
   int32_t stride;             // elements between consecutive pixels (>= D)
   int32_t view_base;          // index of the launch's first view in scales
