@@ -202,6 +202,53 @@ def camera_array(cams):
     return (lv_camera * max(1, m)).from_buffer(a)
 
 
+class Cameras:
+    """A camera rig marshalled once into lv_camera[m]; accepted wherever a
+    list of cameras is (saves the per-call marshalling of the rig)."""
+
+    def __init__(self, cams):
+        self.cams = list(cams)
+        self.array = camera_array(self.cams)
+
+    def __len__(self):
+        return len(self.cams)
+
+    def __getitem__(self, i):
+        return self.cams[i]
+
+    def __iter__(self):
+        return iter(self.cams)
+
+
+class Maps:
+    """Contiguous maps [H, W, D] of one dtype, validated and marshalled once
+    into a device-pointer table (the tensors are kept alive); accepted
+    wherever a list of maps is."""
+
+    def __init__(self, maps, dtype="f32"):
+        self.maps = list(maps)
+        self.dtype = _DTYPES[dtype]
+        self.table = _map_table(self.maps, self.dtype)
+
+    def __len__(self):
+        return len(self.maps)
+
+    def __getitem__(self, i):
+        return self.maps[i]
+
+
+def _cams(cams):
+    return cams.array if isinstance(cams, Cameras) else camera_array(cams)
+
+
+def _maps(maps, dtype):
+    if isinstance(maps, Maps):
+        if maps.dtype != dtype:
+            raise LvError("map table built for another dtype")
+        return maps.table
+    return _map_table(maps, dtype)
+
+
 def _map_table(maps, dtype):
     import torch
     want = {LV_F32: (torch.float32,), LV_BF16: (torch.bfloat16,),
@@ -247,8 +294,8 @@ class Scene:
             out = torch.empty((self.n, D), device="cuda", dtype=torch.float32)
         if wsum is None:
             wsum = torch.empty((self.n,), device="cuda", dtype=torch.float32)
-        ca = camera_array(cams)
-        tab = _map_table(maps, dt)
+        ca = _cams(cams)
+        tab = _maps(maps, dt)
         _check(lib().lv_uplift(self.handle, ca, len(cams), tab, dt, _ptr(scales), D, _ptr(out),
                                _ptr(wsum), _stream()))
         return out, wsum
@@ -264,7 +311,7 @@ class Scene:
         alps = [torch.empty((c.height, c.width), device="cuda") for c in cams] if alpha else []
         to = (ctypes.c_void_p * max(1, len(cams)))(*[o.data_ptr() for o in outs])
         ta = (ctypes.c_void_p * max(1, len(cams)))(*[a.data_ptr() for a in alps]) if alpha else None
-        _check(lib().lv_render(self.handle, camera_array(cams), len(cams), _ptr(g), D, to, ta, _stream()))
+        _check(lib().lv_render(self.handle, _cams(cams), len(cams), _ptr(g), D, to, ta, _stream()))
         return outs, alps
 
     def uplift_sets(self, cams, sets, dtype="f32", outs=None):
@@ -280,13 +327,13 @@ class Scene:
             f, b = outs[k] if outs is not None else (
                 torch.empty((self.n, D), device="cuda", dtype=torch.float32),
                 torch.empty((self.n,), device="cuda", dtype=torch.float32))
-            tab = _map_table(maps, dt)
+            tab = _maps(maps, dt)
             keep.append(tab)
             arr[k] = lv_uplift_set(ctypes.cast(tab, ctypes.c_void_p),
                                    None if scales is None else scales.data_ptr(), D,
                                    f.data_ptr(), b.data_ptr())
             res.append((f, b))
-        _check(lib().lv_uplift_sets(self.handle, camera_array(cams), len(cams), arr, len(sets), dt,
+        _check(lib().lv_uplift_sets(self.handle, _cams(cams), len(cams), arr, len(sets), dt,
                                     _stream()))
         return res
 
@@ -332,8 +379,8 @@ class Accum:
 
     def add(self, cams, maps, dtype="f32", scales=None):
         dt = _DTYPES[dtype]
-        _check(lib().lv_uplift_accumulate(self.handle, camera_array(cams), len(cams),
-                                          _map_table(maps, dt), dt, _ptr(scales), _stream()))
+        _check(lib().lv_uplift_accumulate(self.handle, _cams(cams), len(cams),
+                                          _maps(maps, dt), dt, _ptr(scales), _stream()))
 
     def finalize(self, want_sum=False):
         import torch
@@ -439,7 +486,7 @@ def accumulate_sets(cams, sets, dtype="f32"):
         keep.append(tab)
         arr[k] = lv_feature_set(acc.handle.value, ctypes.cast(tab, ctypes.c_void_p),
                                 None if scales is None else scales.data_ptr(), stride)
-    _check(lib().lv_uplift_accumulate_sets(camera_array(cams), len(cams), arr, len(sets), dt,
+    _check(lib().lv_uplift_accumulate_sets(_cams(cams), len(cams), arr, len(sets), dt,
                                            _stream()))
 
 

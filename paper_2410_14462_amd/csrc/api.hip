@@ -322,6 +322,57 @@ const char* lv_last_error(void) { return g_err.c_str(); }
 
 const char* lv_version(void) { return "lv 0.1 gfx950"; }
 
+namespace {
+// Device buffers of destroyed scenes, kept for the next scenes of a similar
+// size (a scene that is created and destroyed per request then costs no
+// allocation); bounded in count and bytes, buffers above kSceneCacheMaxBuf
+// are freed at once.
+std::mutex g_scene_cache_mu;
+std::vector<std::pair<int, Buf>> g_scene_cache;
+constexpr size_t kSceneCacheBufs = 12;
+constexpr size_t kSceneCacheMaxBuf = (size_t)256 << 20;
+constexpr size_t kSceneCacheBytes = (size_t)1 << 30;
+
+hipError_t scene_buf(Buf& out, int dev, size_t bytes, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_scene_cache_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_scene_cache.size(); i++) {
+      const Buf& b = g_scene_cache[i].second;
+      if (g_scene_cache[i].first == dev && b.cap >= bytes && b.cap <= 2 * bytes + 4096 &&
+          (best < 0 || b.cap < g_scene_cache[best].second.cap))
+        best = (int)i;
+    }
+    if (best >= 0) {
+      out = g_scene_cache[best].second;
+      g_scene_cache.erase(g_scene_cache.begin() + best);
+      return hipSuccess;
+    }
+  }
+  return out.ensure(bytes, s);
+}
+
+// After the device has finished with the buffer (the caller synchronised).
+void scene_buf_release(int dev, Buf& b) {
+  if (!b.p) return;
+  if (b.cap > kSceneCacheMaxBuf) {
+    b.release();
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_scene_cache_mu);
+  g_scene_cache.emplace_back(dev, b);
+  b.p = nullptr;
+  b.cap = 0;
+  size_t total = 0;
+  for (const auto& e : g_scene_cache) total += e.second.cap;
+  while (!g_scene_cache.empty() && (g_scene_cache.size() > kSceneCacheBufs || total > kSceneCacheBytes)) {
+    total -= g_scene_cache.front().second.cap;
+    g_scene_cache.front().second.release();
+    g_scene_cache.erase(g_scene_cache.begin());
+  }
+}
+}  // namespace
+
 lv_status lv_scene_create(const float* means, const float* scales, const float* quats,
                           const float* opacity, int64_t n, void* stream, lv_scene** out) {
   if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
@@ -335,9 +386,9 @@ lv_status lv_scene_create(const float* means, const float* scales, const float* 
   sc->n = n;
   (void)hipGetDevice(&sc->device);
   size_t b = sizeof(float4) * (size_t)(n > 0 ? n : 1);
-  hipError_t e = sc->p0.ensure(b, s);
-  if (e == hipSuccess) e = sc->p1.ensure(b, s);
-  if (e == hipSuccess) e = sc->p2.ensure(b, s);
+  hipError_t e = scene_buf(sc->p0, sc->device, b, s);
+  if (e == hipSuccess) e = scene_buf(sc->p1, sc->device, b, s);
+  if (e == hipSuccess) e = scene_buf(sc->p2, sc->device, b, s);
   if (e == hipSuccess)
     e = launch_scene_derive(means, scales, quats, opacity, n, sc->p0.as<float4>(), sc->p1.as<float4>(),
                             sc->p2.as<float4>(), s);
@@ -353,8 +404,14 @@ lv_status lv_scene_create(const float* means, const float* scales, const float* 
 
 lv_status lv_scene_destroy(lv_scene* sc) {
   if (!sc) return LV_OK;
+  int cur = sc->device;
+  (void)hipGetDevice(&cur);
+  if (cur != sc->device) (void)hipSetDevice(sc->device);
   (void)hipDeviceSynchronize();
-  sc->p0.release(); sc->p1.release(); sc->p2.release();
+  if (cur != sc->device) (void)hipSetDevice(cur);
+  scene_buf_release(sc->device, sc->p0);
+  scene_buf_release(sc->device, sc->p1);
+  scene_buf_release(sc->device, sc->p2);
   delete sc;
   return LV_OK;
 }

@@ -213,3 +213,28 @@ def test_mid_full_size_sampled():
     print(f"mid D=64: max err {e.max():.3e} mean {e.mean():.3e}")
     assert e.max() < TOL
     assert feature_error(fm[rows], refm).max() < TOL
+
+
+def test_prebuilt_rig_and_maps_and_scene_reuse(tiny):
+    """A rig and map tables marshalled once give the list result; scenes
+    created and destroyed in turn (the library reuses their buffers, also
+    across scene sizes) give the same result each time."""
+    w, sc, cams, maps, gs = tiny
+    dm = [dev(m) for m in maps]
+    f_ref, b_ref = gs.uplift(cams, dm)
+    rig, tab = lv.Cameras(cams), lv.Maps(dm)
+    half = Scene(sc.means[:4000], sc.scales[:4000], sc.quats[:4000], sc.opacity[:4000])
+    for k in range(3):
+        small = lv.Scene.from_arrays(half)
+        fs, _ = small.uplift(rig, tab)
+        small.close()
+        assert fs.shape == (4000, w.D)
+        s2 = lv.Scene.from_arrays(sc)
+        f, b = s2.uplift(rig, tab)
+        s2.close()
+        torch.cuda.synchronize()
+        scale = f_ref.abs().max().clamp_min(1e-30)
+        assert float((f - f_ref).abs().max() / scale) < 1e-5, k
+        assert float((b - b_ref).abs().max() / b_ref.abs().max()) < 1e-6, k
+    with pytest.raises(lv.LvError):  # a table built for BF16 maps
+        gs.uplift(rig, lv.Maps([m.to(torch.bfloat16) for m in dm], "bf16"))
