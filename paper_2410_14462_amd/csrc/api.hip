@@ -129,6 +129,14 @@ std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
 // two key/value buffers, rect and count (Gaussian and depth order), offset.
 constexpr int64_t kItemBytes = sizeof(Rec) + 4 * 4 + 2 * (8 + 4) + 4;
 
+// Digit width of the depth sort's passes (tile sort: kRadixBits).  With
+// kSortItems items per block, narrower digits give longer runs of one digit
+// and so better coalesced writes, at the cost of more passes.
+#ifndef LV_DEPTH_PASS_BITS
+#define LV_DEPTH_PASS_BITS 8
+#endif
+constexpr int kDepthPassBits = LV_DEPTH_PASS_BITS;
+
 int64_t chunk_budget_bytes() {
   const char* e = getenv("LV_CHUNK_BYTES");
   if (e) {
@@ -255,7 +263,8 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   HIP_TRY(radix_sort(ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.key1.as<uint32_t>(),
                      ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, 32, ws.hist.as<uint32_t>(),
                      true, &second, s,
-                     SortPayload{ws.rect.as<uint2>(), ws.scnt.as<uint32_t>(), ws.srect.as<uint2>()}));
+                     SortPayload{ws.rect.as<uint2>(), ws.scnt.as<uint32_t>(), ws.srect.as<uint2>()},
+                     kDepthPassBits));
   const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
   ws.dkey = second ? ws.key1.as<uint32_t>() : ws.key0.as<uint32_t>();
   ws.dval = sval;

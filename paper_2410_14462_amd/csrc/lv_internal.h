@@ -139,12 +139,15 @@ struct SortPayload {
   uint32_t* ocnt = nullptr;
   uint2* orect = nullptr;
 };
-inline int radix_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
+inline int radix_passes(int bits, int pass_bits = kRadixBits) {
+  return (bits + pass_bits - 1) / pass_bits;
+}
 size_t sort_hist_size(int nseg, int64_t max_len);
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
                       int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
-                      hipStream_t s, SortPayload payload = SortPayload{});
+                      hipStream_t s, SortPayload payload = SortPayload{},
+                      int pass_bits = kRadixBits);
 // Tile ranges (absolute [start, end) per view and tile, tiles_stride per view)
 // after a one-pass radix_sort by tile over the same segments, from its hist.
 hipError_t launch_hist_ranges(const uint32_t* hist, const uint32_t* seg_start,

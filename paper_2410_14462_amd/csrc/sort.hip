@@ -503,13 +503,14 @@ size_t sort_hist_size(int nseg, int64_t max_len) {
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
                       int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
-                      hipStream_t s, SortPayload payload) {
+                      hipStream_t s, SortPayload payload, int pass_bits) {
   *in_second = false;
   if (nseg == 0 || max_len == 0 || bits == 0) return hipSuccess;
   int nb = (int)((max_len + kSortItems - 1) / kSortItems);
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   // fewest passes of at most kRadixBits bits, widths balanced
-  const int passes = radix_passes(bits);
+  pass_bits = pass_bits < 1 ? 1 : (pass_bits > kRadixBits ? kRadixBits : pass_bits);
+  const int passes = radix_passes(bits, pass_bits);
   for (int p = 0, shift = 0; p < passes; p++) {
     const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
     hipLaunchKernelGGL(radix_hist_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, seg_start,
