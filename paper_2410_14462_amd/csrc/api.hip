@@ -105,6 +105,7 @@ struct Workspace {
   const uint32_t* dval = nullptr;
   Buf rec, key0, val0, key1, val1, rect, cnt, scnt, srect, off, scan_tmp, hist, seg, pseg, total;
   Buf pk0, pv0, pk1, pv1, hist2, ranges, cams, geom, maps;
+  Buf cls;  // beta and count increments of classes of sets taking the same views
   HostBuf up, down;
 };
 
@@ -506,6 +507,25 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
   const int64_t n = sc->n;
   if (n == 0 || m == 0) return LV_OK;
 
+  // Sets that take exactly the same views receive the same weights, hence the
+  // same beta and count increments: the blend adds those once per class (into
+  // class accumulators, by the first member) and a small kernel adds them to
+  // every member.  cls[k] = first set of k's class.
+  int cls[kMaxSets], members[kMaxSets] = {0};
+  for (int k = 0; k < nsets; k++) {
+    cls[k] = k;
+    for (int q = 0; q < k && cls[k] == k; q++) {
+      if (cls[q] != q) continue;
+      bool same = true;
+      for (int v = 0; v < m && same; v++)
+        same = (fsets[q].maps[v] == nullptr) == (fsets[k].maps[v] == nullptr);
+      if (same) cls[k] = q;
+    }
+    members[cls[k]]++;
+  }
+  int slot[kMaxSets], nslots = 0;  // class accumulator slot of each shared class
+  for (int k = 0; k < nsets; k++) slot[k] = (cls[k] == k && members[k] > 1) ? nslots++ : -1;
+
   // channel groups: the sets' channels concatenated and cut into groups of
   // 64, a last part of <= kMaxTail channels joining the previous group as its
   // tail
@@ -547,7 +567,10 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
           g.tc[g.ntail] = c - off;
           g.ntail++;
         }
-        if (off >= lo && off < thi) g.beta_sets |= 1 << k;
+        if (off >= lo && off < thi) {
+          g.stats_sets |= 1 << k;
+          if (cls[k] == k) g.beta_sets |= 1 << k;
+        }
         off += D;
       }
       groups.push_back(g);
@@ -559,6 +582,7 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
+  if (nslots) HIP_TRY(ws.cls.ensure((size_t)nslots * n * 12, s));
   int64_t per_view = n * kItemBytes;
   int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
   mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
@@ -598,9 +622,17 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
       sd[k].D = a->D;
       sd[k].stride = fsets[k].stride ? fsets[k].stride : a->D;
       sd[k].view_base = v0;
+      if (slot[k] >= 0) {  // shared class: its increments go to the class accumulators
+        char* c = ws.cls.as<char>() + (size_t)slot[k] * n * 12;
+        sd[k].beta = reinterpret_cast<beta_t*>(c);
+        bool any_counts = false;
+        for (int q = 0; q < nsets; q++) any_counts = any_counts || (cls[q] == k && fsets[q].acc->counts.p);
+        sd[k].counts = any_counts ? reinterpret_cast<uint32_t*>(c + (size_t)n * 8) : nullptr;
+      }
     }
     if (b_groups) memcpy(up + b_sets, groups.data(), b_groups);
     HIP_TRY(hipMemcpyAsync(dev, up, bytes, hipMemcpyHostToDevice, s));
+    if (nslots) HIP_TRY(hipMemsetAsync(ws.cls.p, 0, (size_t)nslots * n * 12, s));
     BlendArgs ba;
     ba.rec = ws.rec.as<Rec>();
     ba.ids = ids;
@@ -625,6 +657,19 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
       } else {
         HIP_TRY(launch_blend(ba, dtype, mv, s));
       }
+    }
+    for (int k = 0; k < nsets; k++) {
+      if (slot[k] < 0) continue;
+      ClassAdd dst;
+      memset(&dst, 0, sizeof(dst));
+      for (int q = 0; q < nsets; q++) {
+        if (cls[q] != k) continue;
+        dst.beta[dst.nd] = fsets[q].acc->beta.as<beta_t>();
+        dst.counts[dst.nd] = fsets[q].acc->counts.as<uint32_t>();
+        dst.nd++;
+      }
+      const char* c = ws.cls.as<char>() + (size_t)slot[k] * n * 12;
+      HIP_TRY(launch_class_add(reinterpret_cast<const beta_t*>(c), sd[k].counts ? reinterpret_cast<const uint32_t*>(c + (size_t)n * 8) : nullptr, dst, n, s));
     }
     if (v0 + mc < m) HIP_TRY(hipStreamSynchronize(s));  // staging buffers are reused
   }

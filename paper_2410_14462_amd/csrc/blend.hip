@@ -21,6 +21,8 @@
 //      (Gaussian, channel); beta (the rows' sums, in exact fixed point) and
 //      the tail channels (the rows' dot products with up to 4 further
 //      channels) by one lane pair per row.
+#include <algorithm>
+
 #include "lv_internal.h"
 
 namespace lv {
@@ -390,12 +392,14 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   // groups taking the view, sets whose beta (and counts) are added here;
   // tail channels (only the last group has them)
   bool has_main = false;
-  int bsets = 0;
+  int bsets = 0, ssets = 0;
   uint32_t gmask = 0u;  // groups (relative to g_lo) with a segment taking the view
   for (int cg = g_lo; cg < g_hi; cg++) {
     const ChanGroup& grp = groups[cg];
     for (int b = grp.beta_sets; b; b &= b - 1)
       if (map_of(sets[__builtin_ctz(b)], q.v)) bsets |= b & -b;
+    for (int b = grp.stats_sets; b; b &= b - 1)
+      if (map_of(sets[__builtin_ctz(b)], q.v)) ssets |= b & -b;
     bool any = false;
     for (int k = 0; k < grp.nseg; k++) any = any || map_of(sets[grp.set[k]], q.v) != nullptr;
     if (any) {
@@ -430,7 +434,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
     }
     Ft[t * 64 + lane] = ft;
   }
-  if (!has_main && !any_tail && !bsets) return;  // wave-uniform: nothing here takes the view
+  if (!has_main && !any_tail && !bsets && !ssets) return;  // wave-uniform: nothing here takes the view
 
   // single group: its lanes and fragments once, in registers
   GroupLanes L1;
@@ -618,8 +622,8 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
     }
   }
   if (queued > 0) flush(queued);
-  // statistics go to every set whose beta this work item takes for this view
-  for (int b = bsets; b; b &= b - 1) {
+  // statistics go to every set whose statistics this work item takes
+  for (int b = ssets; b; b &= b - 1) {
     const SetDesc& sd = sets[__builtin_ctz(b)];
     if (sd.stats && lane == 0) {
       gatomic_add(&sd.stats[1], (unsigned long long)ncontrib);
@@ -721,6 +725,29 @@ __global__ void finalize_kernel(const float* __restrict__ U, const beta_t* __res
 }
 
 }  // namespace
+
+namespace {
+__global__ __launch_bounds__(256) void class_add_kernel(const beta_t* __restrict__ beta,
+                                                        const uint32_t* __restrict__ counts,
+                                                        ClassAdd dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const beta_t b = beta[i];
+    const uint32_t c = counts ? counts[i] : 0u;
+    for (int k = 0; k < dst.nd; k++) {
+      if (dst.beta[k]) dst.beta[k][i] += b;
+      if (dst.counts[k]) dst.counts[k][i] += c;
+    }
+  }
+}
+}  // namespace
+
+hipError_t launch_class_add(const beta_t* beta, const uint32_t* counts, const ClassAdd& dst,
+                            int64_t n, hipStream_t s) {
+  if (n == 0 || dst.nd == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(class_add_kernel, dim3((unsigned)blocks), dim3(256), 0, s, beta, counts, dst, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s) {
   if (m == 0 || a.tiles_stride == 0) return hipSuccess;

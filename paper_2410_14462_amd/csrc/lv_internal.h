@@ -197,10 +197,10 @@ constexpr int kMaxTail = 4;   // channels of a group kept in registers
 // of the group's (<= 64) channels taken from set `set`, channels
 // [c0, c0 + cnt), vc0 ascending from 0, one channel per lane.  Tail: up to 4
 // further single channels (set tset[t], channel tc[t]) reduced across the
-// wave.  beta_sets: bit s set if this group adds beta (and counts and
-// statistics) of set s.
+// wave.  beta_sets: bit s set if this group adds beta (and counts) of set
+// s; stats_sets: bit s set if it adds the statistics of set s.
 struct ChanGroup {
-  int32_t width, nseg, ntail, beta_sets;
+  int32_t width, nseg, ntail, beta_sets, stats_sets;
   int32_t set[kMaxSegs], c0[kMaxSegs], vc0[kMaxSegs], cnt[kMaxSegs];
   int32_t tset[kMaxTail], tc[kMaxTail];
 };
@@ -218,6 +218,16 @@ struct BlendArgs {
   int32_t max_width;           // widest group (LDS size)
 };
 hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s);
+// dst_beta[k][i] += beta[i], dst_counts[k][i] += counts[i] (entries may be
+// NULL) for the k < nd members of a class of feature sets that take the same
+// views (their increments are equal and are accumulated once).
+struct ClassAdd {
+  beta_t* beta[kMaxSets];
+  uint32_t* counts[kMaxSets];
+  int32_t nd;
+};
+hipError_t launch_class_add(const beta_t* beta, const uint32_t* counts, const ClassAdd& dst,
+                            int64_t n, hipStream_t s);
 
 // Eq. (4) forward render of g [n][D] into outs[v] [H][W][D] (device table of
 // m pointers) and the accumulated opacity into alphas[v] [H][W] (entries may

@@ -238,3 +238,32 @@ def test_prebuilt_rig_and_maps_and_scene_reuse(tiny):
         assert float((b - b_ref).abs().max() / b_ref.abs().max()) < 1e-6, k
     with pytest.raises(lv.LvError):  # a table built for BF16 maps
         gs.uplift(rig, lv.Maps([m.to(torch.bfloat16) for m in dm], "bf16"))
+
+
+def test_sets_taking_the_same_views_share_beta():
+    """Sets that take the same views get their beta and counts from one class
+    accumulator: members with and without counts, a set with another view
+    pattern, and a member with earlier content of its own."""
+    sc = scenes.make_scene(9, 3000, -3.8, 0.5, 0.0, 1.0)
+    cams = [scenes.look_at(e, 80, 64, 60.0) for e in scenes.fibonacci_eyes(3, 4.0)]
+    gs = lv.Scene.from_arrays(sc)
+    Ds = (3, 5, 2, 1)
+    host = [[philox.normal(90 + k, v, 64 * 80 * D).reshape(64, 80, D) for v in range(3)]
+            for k, D in enumerate(Ds)]
+    maps = [[dev(m) for m in hm] for hm in host]
+    A, B, C, E = (lv.Accum(gs, Ds[0], counts=True), lv.Accum(gs, Ds[1]),
+                  lv.Accum(gs, Ds[2], counts=True), lv.Accum(gs, Ds[3], counts=True))
+    A.add(cams[:1], maps[0][:1])  # earlier content of A alone
+    lv.accumulate_sets(cams, [(A, maps[0]), (B, maps[1]), (C, [maps[2][0], None, None]),
+                              (E, maps[3])])
+    refs = [oracle.uplift(sc, cams[:1] + cams, host[0][:1] + host[0]),
+            oracle.uplift(sc, cams, host[1]),
+            oracle.uplift(sc, cams[:1], host[2][:1]),
+            oracle.uplift(sc, cams, host[3])]
+    for k, (acc, ref) in enumerate(zip((A, B, C, E), refs)):
+        f, b = acc.finalize()
+        torch.cuda.synchronize()
+        if k != 1:
+            assert np.array_equal(acc.counts().cpu().numpy().astype(np.int64), ref.count), k
+        assert feature_error(f.cpu().numpy(), ref).max() < TOL, k
+        assert beta_error(b.cpu().numpy(), ref).max() < TOL, k
