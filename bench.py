@@ -18,7 +18,12 @@ Also reported, measured in the same run outside the timed steps:
                 HIP events around each launch during the timed steps;
   bf16          BF16 storage of the D = 64 maps (encode + uplift) and its error
                 against the FP32 result;
-  diffuse       100 steps of Eq. (8) on a 16-NN graph of the scene (D = 1 and 64);
+  filtering     pruning by weight sum and the count-normalised finalize;
+  render        the forward render (Eq. 4) of the uplifted D = 64 features into
+                all 50 views, with opacity;
+  diffuse       100 steps of Eq. (8) on a 16-NN graph of the scene (D = 1 and 64),
+                the graph build, and the segmentation diffusion (Eq. 7 / 9);
+  serving       a synthetic request trace through the server;
   cpu_baseline  the FP64 oracle on a sample of the same workload, host cores.
 """
 import argparse
@@ -302,6 +307,24 @@ def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
     res["filtering"] = {"n": n, "kept": int(keep.sum()), "prune_ms": round(t_prune * 1e3, 4),
                         "finalize_count_ms": round(t_fc * 1e3, 4)}
     del acc, fc, keep
+    # ---- forward render (Eq. 4) of the uplifted D=64 features into all views
+    log("bench: render leg")
+    outs, alps = s.render(cams, f64)  # warm (and output allocation)
+    del outs, alps
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        outs, alps = s.render(cams, f64)
+    torch.cuda.synchronize()
+    t_r = (time.perf_counter() - t0) / reps
+    H, W = w.height, w.width
+    out_bytes = m * H * W * (D + 1) * 4  # rendered features and opacity, written once
+    res["render"] = {"ms": round(t_r * 1e3, 3), "ms_per_view_channel": round(t_r * 1e3 / (m * D), 7),
+                     "output_GB": round(out_bytes / 1e9, 3),
+                     "output_GBs": round(out_bytes / t_r / 1e9, 1),
+                     "hbm_frac_of_output_bytes": round(out_bytes / t_r / 1e9 / HBM_PEAK_GBS, 4)}
+    del outs, alps
     # ---- diffusion over the 16-NN graph of the scene, built on the device
     # from the uplifted features
     log("bench: diffusion leg (16-NN graph built on the device)")

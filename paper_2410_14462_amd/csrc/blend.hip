@@ -652,28 +652,75 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ forward render
-// Eq. (4): F^(p) = sum_i w_i(p) g_i.  Each quadrant wave walks its tile's
-// list exactly as the uplift does and accumulates, per pixel, up to
-// kRenderCh channels of g in registers; the row of g of a Gaussian is the
-// same for the whole wave (its id comes from readlane), so it is read once
-// per wave.  The accumulated opacity sum_i w_i(p) goes to alpha[v] (group 0).
-constexpr int kRenderCh = 32;
+// Eq. (4): F^(p) = sum_i w_i(p) g_i, the adjoint of the uplift.  One wave per
+// (view, quadrant, group of 64 channels) walks its tile's list exactly as the
+// uplift does; a Gaussian with some contribution queues its weights at the
+// 64 pixels in one of 32 LDS rows (its id beside it).  A full queue (and the
+// last, partial one) is flushed on the matrix cores: out (64 pixels x 64
+// channels) += W^T (64 x 32 rows) G (32 rows x 64 channels), split BF16
+// operands as in the uplift, the four 32x32 output blocks held in registers
+// until the walk ends; each (pixel, channel) is then written once.  The
+// opacity sum_i w_i(p) goes to alpha[v] (group 0).
+constexpr int kRenderCh = 64;
 
-__global__ __launch_bounds__(64) void render_kernel(
+__global__ __launch_bounds__(64, 3) void render_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews, int ngroups,
     const float* __restrict__ g, int D, float* const* __restrict__ outs,
     float* const* __restrict__ alphas) {
   constexpr int G = kChunk;
-  __shared__ float4 Rs[kChunk][2];  // the step's records
+  __shared__ __align__(16) float Wt[32 * kWtPitch];  // queued Gaussians: [row][pixel]
+  __shared__ float4 Rs[kChunk][2];                   // the step's records
+  __shared__ uint32_t Rg[32];                        // queued Gaussians' ids
   Quad q;
   if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
   const int lane = threadIdx.x;
   const int c0 = q.cg * kRenderCh;
-  float acc[kRenderCh];
-#pragma unroll
-  for (int k = 0; k < kRenderCh; k++) acc[k] = 0.0f;
+  // this lane's channel in each 32-channel block (a readable one where it has none)
+  const int ch0 = c0 + (lane & 31), ch1 = c0 + 32 + (lane & 31);
+  const bool own0 = ch0 < D, own1 = ch1 < D;
+  f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};  // [pixel block][channel block]
   float asum = 0.0f;
+  int queued = 0;
+
+  // K-step t: queue rows 16 t + 8 (l / 32) + i, i < 8
+  auto flush = [&](int count) {
+    __syncthreads();  // rows written (one wave per workgroup: orders LDS)
+    for (int t = 0; t < 2 && 16 * t < count; t++) {
+      float w0[8], w1[8], g0[8], g1[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const int row = 16 * t + 8 * (lane >> 5) + i;
+        const bool ok = row < count;
+        const int64_t gid = ok ? (int64_t)Rg[row] : 0;
+        w0[i] = ok ? Wt[row * kWtPitch + (lane & 31)] : 0.0f;
+        w1[i] = ok ? Wt[row * kWtPitch + 32 + (lane & 31)] : 0.0f;
+        const float x0 = g[gid * D + (own0 ? ch0 : 0)];  // no branch around the loads
+        const float x1 = g[gid * D + (own1 ? ch1 : 0)];
+        g0[i] = ok && own0 ? x0 : 0.0f;
+        g1[i] = ok && own1 ? x1 : 0.0f;
+      }
+      bf16x8 a0h, a0l, a1h, a1l, b0h, b0l, b1h, b1l;
+      split8(w0, a0h, a0l);
+      split8(w1, a1h, a1l);
+      split8(g0, b0h, b0l);
+      split8(g1, b1h, b1l);
+      acc00 = mfma(a0h, b0h, acc00);
+      acc01 = mfma(a0h, b1h, acc01);
+      acc10 = mfma(a1h, b0h, acc10);
+      acc11 = mfma(a1h, b1h, acc11);
+      acc00 = mfma(a0l, b0h, acc00);
+      acc01 = mfma(a0l, b1h, acc01);
+      acc10 = mfma(a1l, b0h, acc10);
+      acc11 = mfma(a1l, b1h, acc11);
+      acc00 = mfma(a0h, b0l, acc00);
+      acc01 = mfma(a0h, b1l, acc01);
+      acc10 = mfma(a1h, b0l, acc10);
+      acc11 = mfma(a1h, b1l, acc11);
+    }
+    __syncthreads();  // rows read before they are written again
+  };
+
   Walk s;
   walk_init(q, lane, s);
   const Rec* vrec = rec + (int64_t)q.v * n;
@@ -689,26 +736,37 @@ __global__ __launch_bounds__(64) void render_kernel(
       bool take;
       const float wj = walk_rec(Rs[j][0], Rs[j][1], s, take);
       if (__ballot(take)) {
-        const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)my_id, j);
-        const float* fr = g + (int64_t)gid * D + c0;
-#pragma unroll
-        for (int k = 0; k < kRenderCh; k++) {
-          const float fv = c0 + k < D ? fr[k] : 0.0f;
-          acc[k] = __builtin_fmaf(wj, fv, acc[k]);
-        }
+        Wt[queued * kWtPitch + lane] = wj;
+        if (lane == j) Rg[queued] = my_id;  // lane j holds the Gaussian's id
         asum += wj;
+        if (++queued == 32) {
+          flush(32);
+          queued = 0;
+        }
+      }
+    }
+  }
+  if (queued > 0) flush(queued);
+
+  // D row m of a block: pixel 32 pb + 8 (r / 4) + 4 (l / 32) + r % 4, column
+  // (channel) l % 32
+  float* const out = outs[q.v];
+#pragma unroll
+  for (int pb = 0; pb < 2; pb++) {
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int m = 32 * pb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int px = q.qx + (m & 7), py = q.qy + (m >> 3);
+      if (px < q.g.W && py < q.g.H) {
+        const int64_t pix = (int64_t)py * q.g.W + px;
+        if (own0) gptr(out)[pix * D + ch0] = pb ? acc10[r] : acc00[r];
+        if (own1) gptr(out)[pix * D + ch1] = pb ? acc11[r] : acc01[r];
       }
     }
   }
   const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
-  if (px < q.g.W && py < q.g.H) {
-    const int64_t pix = (int64_t)py * q.g.W + px;
-    LV_GLOBAL float* o = gptr(outs[q.v] + pix * D + c0);
-#pragma unroll
-    for (int k = 0; k < kRenderCh; k++)
-      if (c0 + k < D) o[k] = acc[k];
-    if (q.cg == 0 && alphas[q.v]) gptr(alphas[q.v])[pix] = asum;
-  }
+  if (q.cg == 0 && alphas[q.v] && px < q.g.W && py < q.g.H)
+    gptr(alphas[q.v])[(int64_t)py * q.g.W + px] = asum;
 }
 
 __global__ void finalize_kernel(const float* __restrict__ U, const beta_t* __restrict__ beta,
