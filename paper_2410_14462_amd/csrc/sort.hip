@@ -40,10 +40,13 @@ static_assert(kSortThreads == 256 && kWaveItems % 64 == 0, "four waves per block
 // Digit counts of one block's items (LDS atomics: the order of counting does
 // not matter), written as the block's row hist[segment][block][digit].  All
 // of the block's keys are loaded before any is counted.
+// kB: digit values the LDS arrays hold (passes of at most 8 bits use the
+// small size, so more blocks fit on a CU).
+template <int kB>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t hs[kBins];
+  __shared__ uint32_t hs[kB];
   const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
   const int nbins = 1 << bits;
   const uint32_t mask = (uint32_t)nbins - 1u;
@@ -144,14 +147,15 @@ __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__
 // are consecutive in LDS and go to consecutive global positions.  kout may
 // be NULL (keys not needed after this pass).  With a payload, each item also
 // takes rect[s0 + val] (and its area, the count) to its output position.
+template <int kB>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb,
     const uint32_t* __restrict__ hist, SortPayload pl) {
-  constexpr int kPer = kBins / kSortThreads;       // digits per thread in the scan
-  __shared__ uint16_t wc[4][kBins];                 // per-wave counts, then local cursors
-  __shared__ uint32_t gdelta[kBins];                // global minus local position, per digit
+  constexpr int kPer = kB / kSortThreads;          // digits per thread in the scan
+  __shared__ uint16_t wc[4][kB];                    // per-wave counts, then local cursors
+  __shared__ uint32_t gdelta[kB];                   // global minus local position, per digit
   __shared__ uint32_t lk[kSortItems], lval[kSortItems];
   __shared__ uint32_t wsum[kSortThreads / 64];
   const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     key[r] = i < hi ? kin[s0 + i] : 0u;
     val[r] = i < hi ? vin[s0 + i] : 0u;
   }
-  for (int e = t; e < 4 * kBins; e += kSortThreads) (&wc[0][0])[e] = 0;
+  for (int e = t; e < 4 * kB; e += kSortThreads) (&wc[0][0])[e] = 0;
   __syncthreads();
 
   // count per (wave, digit): the lowest lane of each group of equal digits
@@ -513,12 +517,23 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
   const int passes = radix_passes(bits, pass_bits);
   for (int p = 0, shift = 0; p < passes; p++) {
     const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, seg_start,
-                       seg_len, shift, pb, nb, hist);
+    uint32_t* const kout = (p + 1 < passes || keys_last) ? ko : nullptr;
+    const SortPayload pl = p + 1 < passes ? SortPayload{} : payload;
+    if (pb <= 8) {
+      hipLaunchKernelGGL((radix_hist_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+                         seg_start, seg_len, shift, pb, nb, hist);
+    } else {
+      hipLaunchKernelGGL((radix_hist_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+                         seg_start, seg_len, shift, pb, nb, hist);
+    }
     hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb, nseg), dim3(kSortThreads), 0, s, ki, vi,
-                       (p + 1 < passes || keys_last) ? ko : nullptr, vo, seg_start, seg_len, shift,
-                       pb, nb, hist, p + 1 < passes ? SortPayload{} : payload);
+    if (pb <= 8) {
+      hipLaunchKernelGGL((radix_scatter_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+                         vi, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
+    } else {
+      hipLaunchKernelGGL((radix_scatter_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+                         vi, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
+    }
     shift += pb;
     uint32_t* t;
     t = ki; ki = ko; ko = t;
