@@ -40,8 +40,8 @@ static_assert(kSortThreads == 256 && kWaveItems % 64 == 0, "four waves per block
 // Digit counts of one block's items (LDS atomics: the order of counting does
 // not matter), written as the block's row hist[segment][block][digit].  All
 // of the block's keys are loaded before any is counted.
-// kB: digit values the LDS arrays hold (passes of at most 8 bits use the
-// small size, so more blocks fit on a CU).
+// kB: digit values the LDS arrays hold (passes of at most 8 or 10 bits use
+// smaller arrays, so more blocks fit on a CU).
 template <int kB>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ seg_start,
@@ -522,6 +522,9 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
     if (pb <= 8) {
       hipLaunchKernelGGL((radix_hist_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          seg_start, seg_len, shift, pb, nb, hist);
+    } else if (pb <= 10) {
+      hipLaunchKernelGGL((radix_hist_kernel<1024>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+                         seg_start, seg_len, shift, pb, nb, hist);
     } else {
       hipLaunchKernelGGL((radix_hist_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          seg_start, seg_len, shift, pb, nb, hist);
@@ -529,6 +532,9 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
     hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
     if (pb <= 8) {
       hipLaunchKernelGGL((radix_scatter_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+                         vi, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
+    } else if (pb <= 10) {
+      hipLaunchKernelGGL((radix_scatter_kernel<1024>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          vi, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     } else {
       hipLaunchKernelGGL((radix_scatter_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
