@@ -380,23 +380,33 @@ __global__ __launch_bounds__(256) void count_scan_kernel(const uint32_t* __restr
                                                          int64_t n, int64_t items,
                                                          const unsigned long long* __restrict__ bsum,
                                                          uint32_t* __restrict__ off) {
-  // 256 threads x 16 consecutive items
+  // the block's 4096 counts go through LDS (one pad word per 16, so that a
+  // thread's 16 consecutive items are read without bank conflicts): loads
+  // and stores are coalesced, thread t scans items [16 t, 16 t + 16)
+  __shared__ uint32_t buf[kScanItems + kScanItems / 16];
   __shared__ uint32_t part[4];
-  int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)t * 16;
-  uint32_t x[16];
-  uint32_t s = 0;
-  int64_t vs = (base / n) * n;  // start of the view of item base (one division)
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanItems;
+  int64_t i = base + t;
+  int64_t vs = (i / n) * n;  // start of i's view (one division, then moved along)
 #pragma unroll
-  for (int k = 0; k < 16; k++) {
-    const int64_t i = base + k;
+  for (int r = 0; r < kScanItems / 256; r++, i += 256) {
     while (i >= vs + n) vs += n;
     uint32_t c = 0;
     if (i < items) c = sval ? cnt[vs + sval[i]] : cnt[i];
-    x[k] = c;
-    s += c;
+    const int e = t + 256 * r;
+    buf[e + (e >> 4)] = c;
   }
-  uint32_t incl = s;
+  __syncthreads();
+  uint32_t x[16];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int e = 16 * t + k;
+    x[k] = buf[e + (e >> 4)];
+    sum += x[k];
+  }
+  uint32_t incl = sum;
   for (int o = 1; o < 64; o <<= 1) {
     uint32_t y = __shfl_up(incl, o, 64);
     if (lane >= o) incl += y;
@@ -405,12 +415,19 @@ __global__ __launch_bounds__(256) void count_scan_kernel(const uint32_t* __restr
   __syncthreads();
   uint32_t wo = 0;
   for (int q = 0; q < w; q++) wo += part[q];
-  uint32_t run = (uint32_t)bsum[blockIdx.x] + wo + incl - s;
+  uint32_t run = (uint32_t)bsum[blockIdx.x] + wo + incl - sum;
 #pragma unroll
   for (int k = 0; k < 16; k++) {
-    int64_t i = base + k;
-    if (i < items) off[i] = run;
+    const int e = 16 * t + k;
+    buf[e + (e >> 4)] = run;
     run += x[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kScanItems / 256; r++) {
+    const int e = t + 256 * r;
+    const int64_t j = base + e;
+    if (j < items) off[j] = buf[e + (e >> 4)];
   }
 }
 
