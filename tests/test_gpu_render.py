@@ -19,7 +19,7 @@ def setup():
     return sc, cams, lv.Scene.from_arrays(sc)
 
 
-@pytest.mark.parametrize("D", [1, 5, 40])
+@pytest.mark.parametrize("D", [1, 5, 40, 64, 70])
 def test_render_matches_oracle(setup, D):
     sc, cams, gs = setup
     g = philox.normal(40 + D, 0, sc.n * D).reshape(sc.n, D)
