@@ -18,9 +18,10 @@
 //   B. a Gaussian with some w > 0 takes the next of 32 LDS rows (its weights
 //      at the 64 pixels).  A full set of rows (and the last, partial one) is
 //      flushed: U_rows += W_rows F on the matrix cores, one global atomic per
-//      (Gaussian, channel); beta (the rows' sums, in exact fixed point) and
-//      the tail channels (the rows' dot products with up to 4 further
-//      channels) by one lane pair per row.
+//      (Gaussian, channel); beta (the rows' sums, in exact fixed point, once
+//      for all feature sets that take the same views) and the tail channels
+//      (the rows' dot products with up to 4 further channels) by one lane
+//      pair per row.
 #include <algorithm>
 
 #include "lv_internal.h"
