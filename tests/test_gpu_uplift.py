@@ -267,3 +267,31 @@ def test_sets_taking_the_same_views_share_beta():
             assert np.array_equal(acc.counts().cpu().numpy().astype(np.int64), ref.count), k
         assert feature_error(f.cpu().numpy(), ref).max() < TOL, k
         assert beta_error(b.cpu().numpy(), ref).max() < TOL, k
+
+
+def test_views_in_several_chunks(monkeypatch):
+    """A scratch budget of two views per structure build: the views run in
+    three chunks (the staging and the class accumulators reused between
+    them) and the result equals the oracle over all views."""
+    sc = scenes.make_scene(12, 3000, -3.8, 0.5, 0.0, 1.0)
+    cams = [scenes.look_at(e, 80, 64, 60.0) for e in scenes.fibonacci_eyes(5, 4.0)]
+    gs = lv.Scene.from_arrays(sc)
+    item_bytes = 32 + 4 * 4 + 2 * (8 + 4) + 4  # scratch bytes per (view, Gaussian)
+    monkeypatch.setenv("LV_CHUNK_BYTES", str(2 * sc.n * item_bytes + 64))
+    host = [[philox.normal(110 + k, v, 64 * 80 * D).reshape(64, 80, D) for v in range(5)]
+            for k, D in enumerate((4, 1))]
+    maps = [[dev(m) for m in hm] for hm in host]
+    A, B = lv.Accum(gs, 4, counts=True), lv.Accum(gs, 1, counts=True)
+    lv.accumulate_sets(cams, [(A, maps[0]), (B, maps[1])])
+    f1, b1 = gs.uplift(cams, maps[0])
+    for acc, hm in ((A, host[0]), (B, host[1])):
+        ref = oracle.uplift(sc, cams, hm)
+        f, b = acc.finalize()
+        torch.cuda.synchronize()
+        assert np.array_equal(acc.counts().cpu().numpy().astype(np.int64), ref.count)
+        assert feature_error(f.cpu().numpy(), ref).max() < TOL
+        assert beta_error(b.cpu().numpy(), ref).max() < TOL
+    ref = oracle.uplift(sc, cams, host[0])
+    assert feature_error(f1.cpu().numpy(), ref).max() < TOL
+    assert beta_error(b1.cpu().numpy(), ref).max() < TOL
+    assert A.stats()["views"] == 5
