@@ -103,7 +103,7 @@ struct Workspace {
   Buf accUs[kMaxSets], accBs[kMaxSets];
   const uint32_t* dkey = nullptr;  // depth-sorted keys / ids of the last structure build
   const uint32_t* dval = nullptr;
-  Buf rec, key0, val0, key1, val1, rect, cnt, scnt, srect, off, scan_tmp, hist, seg, pseg, total;
+  Buf rec, key0, val0, key1, val1, rect, scnt, srect, off, scan_tmp, hist, seg, pseg, total;
   Buf pk0, pv0, pk1, pv1, hist2, ranges, cams, geom, maps;
   Buf cls;  // beta and count increments of classes of sets taking the same views
   HostBuf up, down;
@@ -127,8 +127,9 @@ bool g_prof_on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
 
 // Workspace bytes per (view, Gaussian) item of a structure build: record,
-// two key/value buffers, rect and count (Gaussian and depth order), offset.
-constexpr int64_t kItemBytes = sizeof(Rec) + 4 * 4 + 2 * (8 + 4) + 4;
+// two key/value buffers, rect (Gaussian and depth order), count (depth
+// order), offset.
+constexpr int64_t kItemBytes = sizeof(Rec) + 4 * 4 + 2 * 8 + 4 + 4;
 
 // Digit width of the depth sort's passes (tile sort: kRadixBits).  With
 // kSortItems items per block, narrower digits give longer runs of one digit
@@ -224,7 +225,6 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   HIP_TRY(ws.key1.ensure(4 * items, s));
   HIP_TRY(ws.val1.ensure(4 * items, s));
   HIP_TRY(ws.rect.ensure(8 * items, s));
-  HIP_TRY(ws.cnt.ensure(4 * items, s));
   HIP_TRY(ws.scnt.ensure(4 * items, s));
   HIP_TRY(ws.srect.ensure(8 * items, s));
   HIP_TRY(ws.off.ensure(4 * items, s));
@@ -257,15 +257,14 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
 
   HIP_TRY(launch_preprocess(sc->p0.as<float4>(), sc->p1.as<float4>(), sc->p2.as<float4>(), n,
                             ws.cams.as<Cam>(), ws.geom.as<ViewGeom>(), mv, ws.rec.as<Rec>(),
-                            ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.rect.as<uint2>(),
-                            ws.cnt.as<uint32_t>(), s));
+                            ws.key0.as<uint32_t>(), ws.rect.as<uint2>(), s));
   bool second = false;
   const uint32_t* seg = ws.seg.as<uint32_t>();
   HIP_TRY(radix_sort(ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.key1.as<uint32_t>(),
                      ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, 32, ws.hist.as<uint32_t>(),
                      true, &second, s,
                      SortPayload{ws.rect.as<uint2>(), ws.scnt.as<uint32_t>(), ws.srect.as<uint2>()},
-                     kDepthPassBits));
+                     kDepthPassBits, true));
   const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
   ws.dkey = second ? ws.key1.as<uint32_t>() : ws.key0.as<uint32_t>();
   ws.dval = sval;
@@ -1111,10 +1110,8 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
   std::vector<uint32_t> key(n);
   std::vector<Rec> rec(n);
   std::vector<uint2> rect(n);
-  std::vector<uint32_t> cnt(n);
   HIP_TRY(hipMemcpy(rec.data(), ws.rec.p, sizeof(Rec) * n, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(rect.data(), ws.rect.p, 8 * n, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(cnt.data(), ws.cnt.p, 4 * n, hipMemcpyDeviceToHost));
   // depth keys in Gaussian order: scatter the depth-sorted (key, id) pairs
   // back by id
   std::vector<uint32_t> sk(n), sv(n);
@@ -1122,7 +1119,8 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
   HIP_TRY(hipMemcpy(sv.data(), ws.dval, 4 * n, hipMemcpyDeviceToHost));
   for (int64_t k = 0; k < n; k++) key[sv[k]] = sk[k];
   for (int64_t i = 0; i < n; i++) {
-    bool vis = cnt[i] != 0;
+    // visible: a non-empty tile rectangle (culled items keep the empty one)
+    const bool vis = (rect[i].y & 0xFFFFu) > (rect[i].x & 0xFFFFu) && (rect[i].y >> 16) > (rect[i].x >> 16);
     if (out->visible) out->visible[i] = vis ? 1 : 0;
     if (out->depth) out->depth[i] = key[i];
     if (out->rect) {

@@ -111,8 +111,7 @@ __global__ void preprocess_kernel(const float4* __restrict__ p0, const float4* _
                                   const float4* __restrict__ p2, int64_t n,
                                   const Cam* __restrict__ cams, const ViewGeom* __restrict__ geom,
                                   Rec* __restrict__ rec, uint32_t* __restrict__ key,
-                                  uint32_t* __restrict__ val, uint2* __restrict__ rect,
-                                  uint32_t* __restrict__ cnt) {
+                                  uint2* __restrict__ rect) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int v = blockIdx.y;
   if (i >= n) return;
@@ -120,9 +119,7 @@ __global__ void preprocess_kernel(const float4* __restrict__ p0, const float4* _
   const Cam& c = cams[v];
   const ViewGeom g = geom[v];
   float4 a0 = p0[i], a1 = p1[i], a2 = p2[i];
-  val[o] = (uint32_t)i;
   key[o] = 0xFFFFFFFFu;
-  cnt[o] = 0u;
   rect[o] = make_uint2(0u, 0u);
   rec[o].r1 = make_float4(0.0f, 0.0f, -1.0f, -1.0f);
 
@@ -204,7 +201,6 @@ __global__ void preprocess_kernel(const float4* __restrict__ p0, const float4* _
   // exponent can never make a skipped pixel count.  -1: never reachable.
   float tau = op >= kAlphaMin ? (logf(op / kAlphaMin) + 0.01f) * 1.01f : -1.0f;
   key[o] = __float_as_uint(zc);
-  cnt[o] = (uint32_t)((x1 - x0) * (y1 - y0));
   rect[o] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
   rec[o].r0 = make_float4(ux, uy, L11, L12);
   rec[o].r1 = make_float4(L22, op, tau, __uint_as_float(uxl | (uyl << 16)));
@@ -212,12 +208,11 @@ __global__ void preprocess_kernel(const float4* __restrict__ p0, const float4* _
 
 hipError_t launch_preprocess(const float4* p0, const float4* p1, const float4* p2, int64_t n,
                              const Cam* cams, const ViewGeom* geom, int m, Rec* rec,
-                             uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt,
-                             hipStream_t s) {
+                             uint32_t* key, uint2* rect, hipStream_t s) {
   if (n == 0 || m == 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks, (unsigned)m), dim3(256), 0, s, p0,
-                     p1, p2, n, cams, geom, rec, key, val, rect, cnt);
+                     p1, p2, n, cams, geom, rec, key, rect);
   return hipGetLastError();
 }
 

@@ -121,8 +121,7 @@ struct ViewGeom {      // per view of a chunk (device array)
 
 hipError_t launch_preprocess(const float4* p0, const float4* p1, const float4* p2, int64_t n,
                              const Cam* cams, const ViewGeom* geom, int m, Rec* rec,
-                             uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt,
-                             hipStream_t s);
+                             uint32_t* key, uint2* rect, hipStream_t s);
 
 // Segmented stable LSD radix sort of (key, val) pairs on key bits [0, bits),
 // in radix_passes(bits) passes.  Segment g occupies [seg_start[g],
@@ -147,7 +146,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
                       int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
                       hipStream_t s, SortPayload payload = SortPayload{},
-                      int pass_bits = kRadixBits);
+                      int pass_bits = kRadixBits, bool iota_values = false);
 // Tile ranges (absolute [start, end) per view and tile, tiles_stride per view)
 // after a one-pass radix_sort by tile over the same segments, from its hist.
 hipError_t launch_hist_ranges(const uint32_t* hist, const uint32_t* seg_start,

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   for (int r = 0; r < kPerLane; r++) {
     const uint32_t i = lo + 64u * r + lane;
     key[r] = i < hi ? kin[s0 + i] : 0u;
-    val[r] = i < hi ? vin[s0 + i] : 0u;
+    val[r] = i < hi ? (vin ? vin[s0 + i] : i) : 0u;  // no vin: the item's index in its segment
   }
   for (int e = t; e < 4 * kB; e += kSortThreads) (&wc[0][0])[e] = 0;
   __syncthreads();
@@ -524,7 +524,7 @@ size_t sort_hist_size(int nseg, int64_t max_len) {
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                       const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
                       int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
-                      hipStream_t s, SortPayload payload, int pass_bits) {
+                      hipStream_t s, SortPayload payload, int pass_bits, bool iota_values) {
   *in_second = false;
   if (nseg == 0 || max_len == 0 || bits == 0) return hipSuccess;
   int nb = (int)((max_len + kSortItems - 1) / kSortItems);
@@ -535,6 +535,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
   for (int p = 0, shift = 0; p < passes; p++) {
     const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
     uint32_t* const kout = (p + 1 < passes || keys_last) ? ko : nullptr;
+    const uint32_t* const vin = p == 0 && iota_values ? nullptr : vi;
     const SortPayload pl = p + 1 < passes ? SortPayload{} : payload;
     if (pb <= 8) {
       hipLaunchKernelGGL((radix_hist_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
@@ -549,13 +550,13 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
     hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
     if (pb <= 8) {
       hipLaunchKernelGGL((radix_scatter_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
-                         vi, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
+                         vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     } else if (pb <= 10) {
       hipLaunchKernelGGL((radix_scatter_kernel<1024>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
-                         vi, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
+                         vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     } else {
       hipLaunchKernelGGL((radix_scatter_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
-                         vi, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
+                         vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     }
     shift += pb;
     uint32_t* t;

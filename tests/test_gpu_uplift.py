@@ -276,7 +276,7 @@ def test_views_in_several_chunks(monkeypatch):
     sc = scenes.make_scene(12, 3000, -3.8, 0.5, 0.0, 1.0)
     cams = [scenes.look_at(e, 80, 64, 60.0) for e in scenes.fibonacci_eyes(5, 4.0)]
     gs = lv.Scene.from_arrays(sc)
-    item_bytes = 32 + 4 * 4 + 2 * (8 + 4) + 4  # scratch bytes per (view, Gaussian)
+    item_bytes = 32 + 4 * 4 + 2 * 8 + 4 + 4  # scratch bytes per (view, Gaussian)
     monkeypatch.setenv("LV_CHUNK_BYTES", str(2 * sc.n * item_bytes + 64))
     host = [[philox.normal(110 + k, v, 64 * 80 * D).reshape(64, 80, D) for v in range(5)]
             for k, D in enumerate((4, 1))]
