@@ -9,6 +9,8 @@
 // Within a block, each wave ranks its items in rounds of 64 in index order;
 // lanes holding the same digit are found with one wave ballot per digit bit,
 // so ranking needs no atomics and keeps input order among equal digits.
+#include <type_traits>
+
 #include "lv_internal.h"
 
 namespace lv {
@@ -147,7 +149,9 @@ __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__
 // are consecutive in LDS and go to consecutive global positions.  kout may
 // be NULL (keys not needed after this pass).  With a payload, each item also
 // takes rect[s0 + val] (and its area, the count) to its output position.
-template <int kB>
+// kKeys false: the keys are not written (kout NULL), so LDS holds each
+// item's digit instead of its key (a smaller block footprint).
+template <int kB, bool kKeys = true>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
@@ -156,7 +160,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   constexpr int kPer = kB / kSortThreads;          // digits per thread in the scan
   __shared__ uint16_t wc[4][kB];                    // per-wave counts, then local cursors
   __shared__ uint32_t gdelta[kB];                   // global minus local position, per digit
-  __shared__ uint32_t lk[kSortItems], lval[kSortItems];
+  typedef typename std::conditional<kKeys, uint32_t, uint16_t>::type lk_t;
+  __shared__ lk_t lk[kSortItems];
+  __shared__ uint32_t lval[kSortItems];
   __shared__ uint32_t wsum[kSortThreads / 64];
   const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint32_t s0 = seg_start[g];
@@ -238,7 +244,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
       const uint32_t rank = (uint32_t)__popcll(peers[r] & lt);
       if (valid) {
         const uint32_t pos = (uint32_t)cur[d] + rank;
-        lk[pos] = key[r];
+        lk[pos] = (lk_t)(kKeys ? key[r] : d);
         lval[pos] = val[r];
       }
       __builtin_amdgcn_wave_barrier();  // every lane has read cur[d]
@@ -252,8 +258,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   if (!pl.orect) {
     for (uint32_t p = t; p < items; p += kSortThreads) {
       const uint32_t k = lk[p];
-      const uint32_t pos = gdelta[(k >> shift) & mask] + p;
-      if (kout) kout[pos] = k;
+      const uint32_t pos = gdelta[kKeys ? (k >> shift) & mask : k] + p;
+      if (kKeys && kout) kout[pos] = k;
       vout[pos] = lval[p];
     }
     return;
@@ -270,10 +276,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     rr[r] = make_uint2(0u, 0u);
     if (p < items) {
       const uint32_t k = lk[p];
-      pos[r] = gdelta[(k >> shift) & mask] + p;
+      pos[r] = gdelta[kKeys ? (k >> shift) & mask : k] + p;
       vv[r] = lval[p];
       rr[r] = pl.rect[s0 + vv[r]];
-      if (kout) kout[pos[r]] = k;
+      if (kKeys && kout) kout[pos[r]] = k;
     }
   }
 #pragma unroll
@@ -551,6 +557,9 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
     if (pb <= 8) {
       hipLaunchKernelGGL((radix_scatter_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
+    } else if (pb <= 10 && !kout) {
+      hipLaunchKernelGGL((radix_scatter_kernel<1024, false>), dim3(nb, nseg), dim3(kSortThreads), 0,
+                         s, ki, vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     } else if (pb <= 10) {
       hipLaunchKernelGGL((radix_scatter_kernel<1024>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
