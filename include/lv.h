@@ -42,7 +42,9 @@
  * (thread-local).  No C++ exception crosses this interface.
  *
  * Threads: distinct handles may be used from different threads.  One handle
- * must not be used by two threads at once.
+ * must not be used by two threads at once, and an accumulator must not be
+ * the target of work in flight on two streams at once (calls on one stream
+ * are ordered by the stream).
  */
 #ifndef LV_H
 #define LV_H
