@@ -222,8 +222,9 @@ class Cameras:
 
 class Maps:
     """Contiguous maps [H, W, D] of one dtype, validated and marshalled once
-    into a device-pointer table (the tensors are kept alive); accepted
-    wherever a list of maps is."""
+    into a device-pointer table (the tensors are kept alive; they must keep
+    their storage, not be resized or re-allocated in place, while the table
+    is in use); accepted wherever a list of maps is."""
 
     def __init__(self, maps, dtype="f32"):
         self.maps = list(maps)
