@@ -140,6 +140,67 @@ __global__ __launch_bounds__(1024) void radix_scan_kernel(uint32_t* __restrict__
     }
 }
 
+// The same scan split over row chunks, for segments with many blocks and at
+// most 1024 digits (the scan above runs one block per segment, so a few
+// segments of many rows leave the chip mostly idle).  part[segment][chunk]
+// [digit] holds first the chunk's column sums, then each chunk's starting
+// offset per digit.
+__global__ __launch_bounds__(1024) void radix_chunk_sum_kernel(const uint32_t* __restrict__ hist,
+                                                               int nb, int bits, int chunks,
+                                                               uint32_t* __restrict__ part) {
+  const int g = blockIdx.y, c = blockIdx.x, t = threadIdx.x;
+  const int nbins = 1 << bits;
+  const int r0 = (int)((int64_t)nb * c / chunks), r1 = (int)((int64_t)nb * (c + 1) / chunks);
+  if (t >= nbins) return;
+  const uint32_t* h = hist + (size_t)g * nb * nbins + t;
+  uint32_t sum = 0u;
+  for (int b = r0; b < r1; b++) sum += h[(size_t)b * nbins];
+  part[((size_t)g * chunks + c) * nbins + t] = sum;
+}
+
+__global__ __launch_bounds__(1024) void radix_chunk_scan_kernel(uint32_t* __restrict__ part,
+                                                                int bits, int chunks) {
+  __shared__ uint32_t wsum[1024 / 64];
+  const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nbins = 1 << bits;
+  uint32_t* pg = part + (size_t)g * chunks * nbins;
+  uint32_t tot = 0u;
+  if (t < nbins)
+    for (int c = 0; c < chunks; c++) tot += pg[(size_t)c * nbins + t];
+  uint32_t incl = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t run = incl - tot;
+  for (int q = 0; q < w; q++) run += wsum[q];
+  if (t >= nbins) return;
+  for (int c = 0; c < chunks; c++) {
+    const uint32_t x = pg[(size_t)c * nbins + t];
+    pg[(size_t)c * nbins + t] = run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(1024) void radix_chunk_write_kernel(uint32_t* __restrict__ hist,
+                                                                 int nb, int bits, int chunks,
+                                                                 const uint32_t* __restrict__ part) {
+  const int g = blockIdx.y, c = blockIdx.x, t = threadIdx.x;
+  const int nbins = 1 << bits;
+  const int r0 = (int)((int64_t)nb * c / chunks), r1 = (int)((int64_t)nb * (c + 1) / chunks);
+  if (t >= nbins) return;
+  uint32_t* h = hist + (size_t)g * nb * nbins + t;
+  uint32_t run = part[((size_t)g * chunks + c) * nbins + t];
+  for (int b = r0; b < r1; b++) {
+    const uint32_t x = h[(size_t)b * nbins];
+    h[(size_t)b * nbins] = run;
+    run += x;
+  }
+}
+
 // Stable scatter through LDS.  Each wave takes a contiguous quarter of the
 // block's items into registers (item lo + 64 r + lane), finds for each round
 // of 64 the lanes sharing its digit (kept for both uses below), and counts
@@ -553,7 +614,19 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
       hipLaunchKernelGGL((radix_hist_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          seg_start, seg_len, shift, pb, nb, hist);
     }
-    hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
+    if (pb <= 10 && nb >= 64) {
+      // chunks of rows; their sums live in the unused upper half of hist
+      // (sized for kBins >= 2 x 1024 digits per row)
+      const int chunks = 16;
+      uint32_t* part = hist + (size_t)nseg * nb * ((size_t)1 << pb);
+      hipLaunchKernelGGL(radix_chunk_sum_kernel, dim3(chunks, nseg), dim3(1024), 0, s, hist, nb, pb,
+                         chunks, part);
+      hipLaunchKernelGGL(radix_chunk_scan_kernel, dim3(nseg), dim3(1024), 0, s, part, pb, chunks);
+      hipLaunchKernelGGL(radix_chunk_write_kernel, dim3(chunks, nseg), dim3(1024), 0, s, hist, nb,
+                         pb, chunks, part);
+    } else {
+      hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
+    }
     if (pb <= 8) {
       hipLaunchKernelGGL((radix_scatter_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
