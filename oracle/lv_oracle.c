@@ -18,11 +18,24 @@
  * paper relies on (Sec. 5); every choice is spelled out below.
  *
  * Evaluation is brute force: every pixel of every view walks, in order, every
- * Gaussian whose tile rectangle contains the pixel's tile.  Which Gaussians a
- * pixel counts (the alpha >= 1/255 skip and the T < 1e-4 stop) is a discrete
- * outcome decided by floating point, so it is decided in FP32 by a fixed
- * sequence of IEEE operations ("S32") that the GPU library follows too; the
- * VALUES (alpha, T, w, every sum) are computed in FP64 from the FP32 inputs.
+ * Gaussian whose tile rectangle contains the pixel's tile.
+ *
+ *   - Structure (visibility, depth key, tile rectangle, hence each tile's
+ *     ordered list) is discrete and decided by a fixed sequence of IEEE FP32
+ *     operations ("S32") from the FP32 inputs, so that any two correct
+ *     implementations of the convention agree bit for bit.
+ *   - Everything else is FP64 from the same FP32 inputs: the projected centre
+ *     and conic, alpha, the transmittance, the alpha >= 1/255 skip, the
+ *     T < 1e-4 stop and every sum.  The skip and the stop are decided on the
+ *     FP64 values, straight from the definition.
+ *   - Decision margins: every skip decision has the relative margin
+ *     |alpha - 1/255| / (1/255), every stop decision |T' - 1e-4| / 1e-4.  A
+ *     pixel with a margin below a threshold (1e-5 by default) is ambiguous:
+ *     an FP32 evaluation of the same definition may decide it the other way.
+ *     Its Gaussians whose weight at the pixel depends on that decision (from
+ *     the first ambiguous decision on: every candidate with alpha within the
+ *     threshold of 1/255 or above, up to the stop and two beyond it) are
+ *     flagged, so that comparisons can exclude them and count them.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -fPIC -shared
  */
@@ -44,31 +57,6 @@ static const float K_DILATE = 0x1.333334p-2f;      /* 0.3f    */
 static const float K_CLAMP = 0x1.4cccccp+0f;       /* 1.3f    */
 
 /* ----------------------------------------------------------------------- */
-/* S32 exponential (decision path only): exp(x) for x <= 0 by Cody-Waite
- * reduction x = k ln2 + r, |r| <= ln2/2, and the degree-7 Taylor polynomial
- * of e^r in Horner form with fmaf; 0 below -80.                              */
-static float orc_exp32(float x)
-{
-    if (x < -80.0f) return 0.0f;
-    float kf = rintf(x * 0x1.715476p+0f);
-    float r = fmaf(kf, -0x1.62e4p-1f, x);
-    r = fmaf(kf, -0x1.7f7d1cp-20f, r);
-    float p = 0x1.a01a02p-13f;
-    p = fmaf(p, r, 0x1.6c16c2p-10f);
-    p = fmaf(p, r, 0x1.111112p-7f);
-    p = fmaf(p, r, 0x1.555556p-5f);
-    p = fmaf(p, r, 0x1.555556p-3f);
-    p = fmaf(p, r, 0x1.0p-1f);
-    p = fmaf(p, r, 1.0f);
-    p = fmaf(p, r, 1.0f);
-    int k = (int)kf;
-    uint32_t sb = (uint32_t)(k + 127) << 23;
-    float s;
-    memcpy(&s, &sb, 4);
-    return p * s;
-}
-
-/* ----------------------------------------------------------------------- */
 /* Camera: 17 floats = R[9] (world->camera, row-major), t[3], fx, fy, cx, cy,
  * znear; x_c = R x_w + t; x right, y down, z forward; pixel (i,j) is the unit
  * square [i,i+1) x [j,j+1), its centre (i+0.5, j+0.5).                       */
@@ -79,9 +67,9 @@ typedef struct {
     int vis;
     uint32_t depth;                 /* bits of FP32 z_c (z_c > 0 orders as unsigned) */
     int x0, y0, x1, y1;             /* tile rectangle [x0,x1) x [y0,y1)              */
-    float ux, uy, L11, L12, L22, op; /* S32: power = -((L11 dx + L12 dy)^2 + (L22 dy)^2) */
-    float uxl, uyl;                 /* S32: low parts of the centre (see below)      */
-    double ux64, uy64, A64, B64, C64, op64;
+    float ux, uy;                   /* S32 projected centre (decides the rectangle)   */
+    double ux64, uy64;              /* FP64 projected centre                          */
+    double A64, B64, C64, op64;     /* power = A dx^2 + B dx dy + C dy^2 (FP64)       */
 } orc_proj;
 
 /* Sec. 3.1: covariance from scale and rotation, Sigma = R diag(s)^2 R^T =
@@ -139,15 +127,14 @@ static void orc_cov64(const float* s, const float* q, double out[6])
     }
 }
 
-/* S32 centre.  Pixel coordinates reach ~10^3, where one FP32 ulp (6e-5 px)
- * already moves the exponent of a compact Gaussian by ~1e-4; so the centre
- * is carried as an unevaluated sum hi + lo of two floats, built with
- * error-free transformations: Knuth's TwoSum, TwoProduct by fmaf, the
- * compensated dot product Dot2 of Ogita, Rump and Oishi (SIAM J. Sci.
- * Comput. 26(6), 2005) for x_c = R x_w + t, one Newton-style correction of
- * the quotient x_c / z_c, and a compensated affine map u = f i + c.  lo is
- * then kept to its 8 leading significand bits (its low 16 bits cleared), so
- * that both halves fit a 32-bit word.                                      */
+/* S32 centre, which places the tile rectangle: the centre u = f x_c / z_c + c
+ * is formed as the correctly rounded value of an unevaluated sum of two
+ * floats, built with error-free transformations: Knuth's TwoSum, TwoProduct
+ * by fmaf, the compensated dot product Dot2 of Ogita, Rump and Oishi (SIAM
+ * J. Sci. Comput. 26(6), 2005) for x_c = R x_w + t, one Newton-style
+ * correction of the quotient x_c / z_c, and a compensated affine map
+ * u = f i + c.  The FP32 result is therefore (almost always) the FP32 value
+ * nearest the exact centre, whichever implementation computes it.          */
 static void orc_two_sum(float a, float b, float* s, float* e)
 {
     float x = a + b, bb = x - a;
@@ -179,9 +166,8 @@ static void orc_dot3(const float* r, const float* m, float t, float* hi, float* 
     *lo = s - (*hi - p);
 }
 
-/* hi + lo = f (xh + xl) / (zh + zl) + c */
-static void orc_center(float f, float c, float xh, float xl, float zh, float zl, float* hi,
-                       float* lo)
+/* hi = fl(f (xh + xl) / (zh + zl) + c) */
+static float orc_center(float f, float c, float xh, float xl, float zh, float zl)
 {
     float q = xh / zh;
     float r = fmaf(-q, zh, xh);
@@ -192,22 +178,7 @@ static void orc_center(float f, float c, float xh, float xl, float zh, float zl,
     e = fmaf(f, ql, e);
     orc_two_sum(p, c, &s, &g);
     g = g + e;
-    *hi = s + g;
-    float l = g - (*hi - s);
-    uint32_t b;
-    memcpy(&b, &l, 4);
-    b &= 0xFFFF0000u;
-    memcpy(lo, &b, 4);
-}
-
-/* Offset of pixel column (or row) px from a centre hi + lo, in S32: relative
- * to the centre of the first pixel of px's 16-pixel tile, so that the
- * rounding is that of numbers of the size of the Gaussian, not of the image. */
-static float orc_offset(int px, float hi, float lo)
-{
-    int o = px - px % ORC_TILE;
-    float c = (hi - ((float)o + 0.5f)) + lo;
-    return (float)(px - o) - c;
+    return s + g;
 }
 
 /* Projection of one Gaussian into one view: EWA local-affine approximation
@@ -215,13 +186,11 @@ static float orc_offset(int px, float hi, float lo)
  * tangent), 2D covariance plus 0.3 px^2, conic = inverse, radius
  * ceil(3 sqrt(lambda_max)), 16x16 tile rectangle.  Values in FP64 from the
  * same FP32 inputs, as the textbook formulas.  Structure in S32: x_c, y_c,
- * z_c and the centre compensated as above (the depth key is the high part of
- * z_c); the 2D covariance [[a, b], [b, c]] = V V^T + 0.3 I from V = T M, its
- * determinant by Lagrange's identity |v0|^2 |v1|^2 - (v0.v1)^2 = |v0 x v1|^2
- * (a sum of squares), and the exponent -d^T Sigma2^-1 d / 2 in the Cholesky
- * form -((L11 dx + L12 dy)^2 + (L22 dy)^2) with L22 = sqrt(1 / (2c)),
- * L11 = sqrt(c / (2 det)), L12 = -(b / c) L11: conditional variance of x
- * given y, then the marginal of y.  Neither step cancels.                    */
+ * z_c by Dot2 and the centre as above (the depth key is the FP32 z_c); the
+ * 2D covariance [[a, b], [b, c]] = V V^T + 0.3 I from V = T M (T = J R_cam),
+ * its determinant by Lagrange's identity |v0|^2 |v1|^2 - (v0.v1)^2 =
+ * |v0 x v1|^2 (a sum of squares, no cancellation), lambda_max, the radius
+ * and the rectangle.                                                        */
 static void orc_project(const float* mu, const float* M, const double* cov64, float op,
                         const orc_cam* cam, orc_proj* g)
 {
@@ -238,9 +207,8 @@ static void orc_project(const float* mu, const float* M, const double* cov64, fl
     orc_dot3(Rc + 6, mu, t[2], &zc, &zl);
     if (!(zc > zn)) return;
     float ix = xc / zc, iy = yc / zc;
-    float ux, uxl, uy, uyl;
-    orc_center(fx, cx, xc, xl, zc, zl, &ux, &uxl);
-    orc_center(fy, cy, yc, yl, zc, zl, &uy, &uyl);
+    float ux = orc_center(fx, cx, xc, xl, zc, zl);
+    float uy = orc_center(fy, cy, yc, yl, zc, zl);
     float limx = K_CLAMP * ((0.5f * (float)cam->W) / fx);
     float limy = K_CLAMP * ((0.5f * (float)cam->H) / fy);
     float tx = fminf(limx, fmaxf(-limx, ix));
@@ -279,11 +247,6 @@ static void orc_project(const float* mu, const float* M, const double* cov64, fl
     memcpy(&g->depth, &zc, 4);
     g->x0 = x0; g->x1 = x1; g->y0 = y0; g->y1 = y1;
     g->ux = ux; g->uy = uy;
-    g->uxl = uxl; g->uyl = uyl;
-    g->L11 = sqrtf((0.5f * cc) / det);
-    g->L12 = -((b / cc) * g->L11);
-    g->L22 = sqrtf(0.5f / cc);
-    g->op = op;
 
     /* ---- FP64 values ---- */
     double X = (double)Rc[0] * mu[0] + (double)Rc[1] * mu[1] + (double)Rc[2] * mu[2] + t[0];
@@ -403,38 +366,79 @@ static int orc_view_build(const orc_scene* sc, const orc_cam* cam, orc_view* v)
 
 static void orc_view_free(orc_view* v) { free(v->g); free(v->start); free(v->ids); }
 
-/* One pixel's front-to-back walk.  Calls `emit(i, w64)` for every Gaussian the
- * pixel counts, in order; returns the final transmittance (FP64), writes the
- * FP32 one to *t32 when non-NULL.                                            */
+/* alpha_i(p) of Sec. 3.1 in FP64: min(0.99, opacity * exp(power)), power =
+ * -d^T Sigma2^-1 d / 2 clamped to <= 0 (it is <= 0 in exact arithmetic). */
+static double orc_alpha(const orc_proj* g, double pxd, double pyd)
+{
+    double ex = pxd - g->ux64, ey = pyd - g->uy64;
+    double p = fmin(0.0, g->A64 * ex * ex + g->B64 * ex * ey + g->C64 * ey * ey);
+    return fmin((double)K_ALPHA_MAX, g->op64 * exp(p));
+}
+
+/* Decision log of one thread: smallest relative margins seen, ambiguous
+ * pixels, and per Gaussian the number of ambiguous pixels at which it is
+ * flagged (nullable). */
+typedef struct {
+    double thr;
+    double min_skip, min_stop;
+    int64_t amb_px;
+    int32_t* flag;
+} orc_dec;
+
+/* One pixel's front-to-back walk (Eq. 1), every decision in FP64: a Gaussian
+ * with alpha < 1/255 is skipped; the walk stops at the Gaussian that would
+ * take T below 1e-4, which is not counted.  Calls `emit(i, w)` for every
+ * counted Gaussian, in order, and returns the final transmittance.  With a
+ * decision log, logs the margins and, if the pixel is ambiguous, flags the
+ * Gaussians whose weight here depends on the ambiguous decision: a
+ * different skip changes T for everything behind it, a different stop adds
+ * or removes the stopping Gaussian, and a transmittance off by a factor
+ * (1 - alpha) of a Gaussian near 1/255 can move the stop by at most the next
+ * two candidates (each of which multiplies T by at most 1 - 1/255).       */
 typedef void (*orc_emit_fn)(void* ctx, int32_t i, double w);
 
 static double orc_walk(const orc_view* v, int64_t tile, int px, int py, orc_emit_fn emit,
-                       void* ctx, float* t32)
+                       void* ctx, orc_dec* dec, int* ambiguous)
 {
-    double pxd = px + 0.5, pyd = py + 0.5;
-    float T = 1.0f;
-    double T64 = 1.0;
-    for (int64_t k = v->start[tile]; k < v->start[tile + 1]; k++) {
-        int32_t i = v->ids[k];
-        const orc_proj* g = v->g + i;
-        /* decision path (S32) */
-        float dx = orc_offset(px, g->ux, g->uxl), dy = orc_offset(py, g->uy, g->uyl);
-        float u = fmaf(g->L12, dy, g->L11 * dx), w = g->L22 * dy;
-        float q = fmaf(u, u, w * w);
-        float al = fminf(K_ALPHA_MAX, g->op * orc_exp32(-q));
-        if (al < K_ALPHA_MIN) continue;
-        float Tn = T * (1.0f - al);
-        if (Tn < K_T_EPS) break;
-        /* values (FP64) */
-        double ex = pxd - g->ux64, ey = pyd - g->uy64;
-        double p64 = fmin(0.0, g->A64 * ex * ex + g->B64 * ex * ey + g->C64 * ey * ey);
-        double a64 = fmin((double)K_ALPHA_MAX, g->op64 * exp(p64));
-        emit(ctx, i, a64 * T64);
+    const double pxd = px + 0.5, pyd = py + 0.5;
+    const double amin = K_ALPHA_MIN, teps = K_T_EPS;
+    const int64_t k0 = v->start[tile], k1 = v->start[tile + 1];
+    const double thr = dec ? dec->thr : -1.0;
+    double T = 1.0;
+    int64_t first = -1, k;
+    for (k = k0; k < k1; k++) {
+        const int32_t i = v->ids[k];
+        const double a = orc_alpha(v->g + i, pxd, pyd);
+        if (dec) {
+            const double ms = fabs(a - amin) / amin;
+            if (ms < dec->min_skip) dec->min_skip = ms;
+            if (ms < thr && first < 0) first = k;
+        }
+        if (a < amin) continue;
+        const double Tn = T * (1.0 - a);
+        if (dec) {
+            const double mt = fabs(Tn - teps) / teps;
+            if (mt < dec->min_stop) dec->min_stop = mt;
+            if (mt < thr && first < 0) first = k;
+        }
+        if (Tn < teps) break;
+        emit(ctx, i, a * T);
         T = Tn;
-        T64 *= 1.0 - a64;
     }
-    if (t32) *t32 = T;
-    return T64;
+    if (ambiguous) *ambiguous = first >= 0;
+    if (first >= 0) {
+        dec->amb_px++;
+        if (dec->flag) {
+            int beyond = 0;
+            for (int64_t j = first; j < k1; j++) {
+                const int32_t i = v->ids[j];
+                if (orc_alpha(v->g + i, pxd, pyd) < amin * (1.0 - thr)) continue;
+                if (j > k && beyond++ == 2) break;
+                dec->flag[i]++;
+            }
+        }
+    }
+    return T;
 }
 
 /* ----------------------------------------------------------------------- */
@@ -482,12 +486,18 @@ static int orc_threads(int req)
  *   beta[n] += sum_p w_i(p),           cnt[n] += #{p : i counted at p}.
  * F is [H][W][D] FP32 (HWC).  row[n] maps Gaussian -> accumulated row (or -1);
  * NULL means every Gaussian, nrows = n.  tfinal (nullable) gets the FP64 final
- * transmittance per pixel [H][W].  stats[0..2] += nnz, P, n_visible.
+ * transmittance per pixel [H][W].
+ * Decision log (see the header): amb_thr is the margin threshold; amb_px
+ * (nullable, [H][W]) gets 1 at ambiguous pixels, 0 elsewhere; amb_flag
+ * (nullable, [n]) += the number of ambiguous pixels at which each Gaussian is
+ * flagged; margins[0..1] = min(margins, smallest skip / stop margin).
+ * stats[0..3] += nnz, P, n_visible, ambiguous pixels.
  * Returns 0, or -1 on allocation failure.                                    */
 int orc_uplift_view(int64_t n, const float* mu, const float* s, const float* q, const float* op,
                     const float* cam17, int W, int H, const float* F, int D, const int32_t* row,
                     int64_t nrows, double* U, double* A, double* beta, int64_t* cnt,
-                    double* tfinal, int64_t* stats, int nthreads)
+                    double* tfinal, uint8_t* amb_px, int32_t* amb_flag, double amb_thr,
+                    double* margins, int64_t* stats, int nthreads)
 {
     orc_scene sc;
     orc_view v;
@@ -500,18 +510,23 @@ int orc_uplift_view(int64_t n, const float* mu, const float* s, const float* q, 
     int nth = orc_threads(nthreads);
     int64_t nt = (int64_t)v.TX * v.TY;
     size_t rs = (size_t)nrows * (size_t)D;
+    size_t nn = (size_t)(n ? n : 1);
     double** pu = (double**)calloc((size_t)nth, sizeof(double*));
     double** pa = (double**)calloc((size_t)nth, sizeof(double*));
     double** pb = (double**)calloc((size_t)nth, sizeof(double*));
     int64_t** pc = (int64_t**)calloc((size_t)nth, sizeof(int64_t*));
     int64_t* pn = (int64_t*)calloc((size_t)nth, sizeof(int64_t));
-    int fail = !pu || !pa || !pb || !pc || !pn;
+    orc_dec* pd = (orc_dec*)calloc((size_t)nth, sizeof(orc_dec));
+    int fail = !pu || !pa || !pb || !pc || !pn || !pd;
     for (int t = 0; t < nth && !fail; t++) {
         pu[t] = (double*)calloc(rs ? rs : 1, sizeof(double));
         pa[t] = (double*)calloc(rs ? rs : 1, sizeof(double));
-        pb[t] = (double*)calloc((size_t)(n ? n : 1), sizeof(double));
-        pc[t] = (int64_t*)calloc((size_t)(n ? n : 1), sizeof(int64_t));
-        fail |= !pu[t] || !pa[t] || !pb[t] || !pc[t];
+        pb[t] = (double*)calloc(nn, sizeof(double));
+        pc[t] = (int64_t*)calloc(nn, sizeof(int64_t));
+        pd[t].thr = amb_thr;
+        pd[t].min_skip = pd[t].min_stop = INFINITY;
+        pd[t].flag = amb_flag ? (int32_t*)calloc(nn, sizeof(int32_t)) : NULL;
+        fail |= !pu[t] || !pa[t] || !pb[t] || !pc[t] || (amb_flag && !pd[t].flag);
     }
     if (!fail) {
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
@@ -525,16 +540,25 @@ int orc_uplift_view(int64_t n, const float* mu, const float* s, const float* q, 
             int tx = (int)(tile % v.TX), ty = (int)(tile / v.TX);
             for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < H; py++)
                 for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < W; px++) {
+                    int amb = 0;
                     ctx.F = F + ((int64_t)py * W + px) * D;
-                    double T = orc_walk(&v, tile, px, py, orc_emit_acc, &ctx, NULL);
+                    double T = orc_walk(&v, tile, px, py, orc_emit_acc, &ctx, pd + th, &amb);
                     if (tfinal) tfinal[(int64_t)py * W + px] = T;
+                    if (amb_px) amb_px[(int64_t)py * W + px] = (uint8_t)amb;
                 }
             pn[th] += ctx.nnz;
         }
         for (int t = 0; t < nth; t++) {
             for (size_t k = 0; k < rs; k++) { U[k] += pu[t][k]; A[k] += pa[t][k]; }
             for (int64_t i = 0; i < n; i++) { beta[i] += pb[t][i]; cnt[i] += pc[t][i]; }
+            if (amb_flag)
+                for (int64_t i = 0; i < n; i++) amb_flag[i] += pd[t].flag[i];
+            if (margins) {
+                margins[0] = fmin(margins[0], pd[t].min_skip);
+                margins[1] = fmin(margins[1], pd[t].min_stop);
+            }
             stats[0] += pn[t];
+            stats[3] += pd[t].amb_px;
         }
         stats[1] += v.P;
         stats[2] += v.nvis;
@@ -544,8 +568,9 @@ int orc_uplift_view(int64_t n, const float* mu, const float* s, const float* q, 
         if (pa) free(pa[t]);
         if (pb) free(pb[t]);
         if (pc) free(pc[t]);
+        if (pd) free(pd[t].flag);
     }
-    free(pu); free(pa); free(pb); free(pc); free(pn);
+    free(pu); free(pa); free(pb); free(pc); free(pn); free(pd);
     orc_view_free(&v);
     orc_scene_free(&sc);
     return fail ? -1 : 0;
@@ -553,7 +578,8 @@ int orc_uplift_view(int64_t n, const float* mu, const float* s, const float* q, 
 
 /* ----------------------------------------------------------------------- */
 /* Forward render of one view, Eq. (4): out[H][W][D] = sum_i w_i(p) g_i
- * (FP64 g [n][D]); alpha[H][W] (nullable) = sum_i w_i(p).                   */
+ * (FP64 g [n][D]); alpha[H][W] (nullable) = sum_i w_i(p); amb_px[H][W]
+ * (nullable) = 1 where the pixel is ambiguous at threshold amb_thr.       */
 typedef struct { const double* g; double* out; double asum; int D; } orc_rctx;
 
 static void orc_emit_render(void* vctx, int32_t i, double w)
@@ -565,7 +591,7 @@ static void orc_emit_render(void* vctx, int32_t i, double w)
 
 int orc_render_view(int64_t n, const float* mu, const float* s, const float* q, const float* op,
                     const float* cam17, int W, int H, const double* g, int D, double* out,
-                    double* alpha, int nthreads)
+                    double* alpha, uint8_t* amb_px, double amb_thr, int nthreads)
 {
     orc_scene sc;
     orc_view v;
@@ -579,13 +605,16 @@ int orc_render_view(int64_t n, const float* mu, const float* s, const float* q, 
     int64_t nt = (int64_t)v.TX * v.TY;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
     for (int64_t tile = 0; tile < nt; tile++) {
+        orc_dec dec = {amb_thr, INFINITY, INFINITY, 0, NULL};
         int tx = (int)(tile % v.TX), ty = (int)(tile / v.TX);
         for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < H; py++)
             for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < W; px++) {
+                int amb = 0;
                 orc_rctx c = {g, out + ((int64_t)py * W + px) * D, 0.0, D};
                 for (int k = 0; k < D; k++) c.out[k] = 0.0;
-                orc_walk(&v, tile, px, py, orc_emit_render, &c, NULL);
+                orc_walk(&v, tile, px, py, orc_emit_render, &c, &dec, &amb);
                 if (alpha) alpha[(int64_t)py * W + px] = c.asum;
+                if (amb_px) amb_px[(int64_t)py * W + px] = (uint8_t)amb;
             }
     }
     orc_view_free(&v);
@@ -596,12 +625,12 @@ int orc_render_view(int64_t n, const float* mu, const float* s, const float* q, 
 /* ----------------------------------------------------------------------- */
 /* Structure of one view, for bit-exact comparison.  Call with ids == NULL to
  * get P (returned); then with ids[P] and tile_start[TX*TY+1].  visible[n],
- * depth[n], rect[n][4] = (x0,y0,x1,y1), rec32[n][8] = (ux,uy,uxl,uyl,L11,L12,L22,
- * opacity)
- * are filled when non-NULL.  Returns P, or -1 on allocation failure.         */
+ * depth[n], rect[n][4] = (x0,y0,x1,y1) and center[n][2] (the S32 centre that
+ * places the rectangle) are filled when non-NULL.  Returns P, or -1 on
+ * allocation failure.                                                       */
 int64_t orc_view_structure(int64_t n, const float* mu, const float* s, const float* q,
                            const float* op, const float* cam17, int W, int H, uint8_t* visible,
-                           uint32_t* depth, int32_t* rect, float* rec32, int64_t* tile_start,
+                           uint32_t* depth, int32_t* rect, float* center, int64_t* tile_start,
                            int32_t* ids)
 {
     orc_scene sc;
@@ -617,11 +646,7 @@ int64_t orc_view_structure(int64_t n, const float* mu, const float* s, const flo
         if (visible) visible[i] = (uint8_t)g->vis;
         if (depth) depth[i] = g->depth;
         if (rect) { rect[4 * i] = g->x0; rect[4 * i + 1] = g->y0; rect[4 * i + 2] = g->x1; rect[4 * i + 3] = g->y1; }
-        if (rec32) {
-            float* r = rec32 + 8 * i;
-            r[0] = g->ux; r[1] = g->uy; r[2] = g->uxl; r[3] = g->uyl;
-            r[4] = g->L11; r[5] = g->L12; r[6] = g->L22; r[7] = g->op;
-        }
+        if (center) { center[2 * i] = g->ux; center[2 * i + 1] = g->uy; }
     }
     int64_t nt = (int64_t)v.TX * v.TY;
     if (tile_start) memcpy(tile_start, v.start, sizeof(int64_t) * (size_t)(nt + 1));
@@ -640,9 +665,3 @@ void orc_factor32_array(int64_t n, const float* s, const float* q, float* out)
 
 /* Threads an oracle call uses by default. */
 int orc_num_threads(void) { return orc_threads(0); }
-
-/* The S32 exponential, exposed for its own pins. */
-void orc_exp32_array(int64_t n, const float* x, float* y)
-{
-    for (int64_t i = 0; i < n; i++) y[i] = orc_exp32(x[i]);
-}

@@ -8,7 +8,7 @@ import paper_2410_14462_amd as lv
 from oracle import diffuse as od
 from oracle import graph
 from synth import philox, scenes
-from helpers import beta_error, feature_error
+from helpers import beta_error, counts_match, feature_error
 
 pytestmark = pytest.mark.gpu
 
@@ -138,13 +138,23 @@ def test_diffuse_bf16_storage_and_constant_signal():
     assert np.allclose(c, 1.0 / np.sqrt(n), rtol=2e-2)
     g0 = philox.uniform(50, 0, n * D).reshape(n, D)
     g0b = torch.as_tensor(g0, device="cuda").to(torch.bfloat16)
-    out = G.diffuse(g0b, steps).float().cpu().numpy()
     Ab = od.csr_matrix(n, rp, col, torch.as_tensor(val).to(torch.bfloat16).float().numpy())
-    ref = od.diffuse(Ab, g0b.float().cpu().numpy(), steps)
-    # BF16 storage of each iterate: relative error grows at most ~2^-8 per step
-    err = np.max(np.abs(out - ref) / np.max(np.abs(ref), axis=0))
-    print(f"diffuse bf16: max err {err:.3e}")
-    assert err < steps * 2.0 ** -8
+    for T in (1, 3, 5, steps):
+        out = G.diffuse(g0b, T).float().cpu().numpy()
+        # the FP64 oracle with each iterate stored in BF16, as the path stores
+        # it: the GPU's FP32 sums and norms round to the other neighbour only
+        # near BF16 ties, one BF16 ulp (2^-8 relative) of that element, and a
+        # row-stochastic A averages such flips instead of growing them
+        ref = od.diffuse(Ab, g0b.float().cpu().numpy(), T, store="bf16")
+        err = np.max(np.abs(out - ref) / np.max(np.abs(ref), axis=0))
+        exact = np.mean(out == ref)
+        # and the FP64 iterates without storage rounding: at most 2^-9 per step
+        ref64 = od.diffuse(Ab, g0b.float().cpu().numpy(), T)
+        err64 = np.max(np.abs(out - ref64) / np.max(np.abs(ref64), axis=0))
+        print(f"diffuse bf16 T={T}: max err {err:.3e} vs BF16-stored oracle "
+              f"({exact:.4f} of the values equal), {err64:.3e} vs FP64 iterates")
+        assert err <= 2.0 ** -7
+        assert err64 <= T * 2.0 ** -9 + 2.0 ** -7
 
 
 def test_large_full_size_precision_sampled():
@@ -193,7 +203,7 @@ def test_large_full_size_precision_sampled():
             up.add_view(cam, dec[k].cpu().numpy())
         ref = up.result()
         del dec
-        assert np.array_equal(c, ref.count)
+        assert counts_match(c, ref)
         assert beta_error(b, ref).max() < 1e-4
         e = feature_error(f, ref)
         print(f"large {dtype} vs decoded maps: max {e.max():.3e}", flush=True)

@@ -25,13 +25,17 @@ def test_render_matches_oracle(setup, D):
     g = philox.normal(40 + D, 0, sc.n * D).reshape(sc.n, D)
     outs, alphas = gs.render(cams, torch.as_tensor(g, device="cuda"))
     for v, cam in enumerate(cams):
-        ref, ref_a = oracle.render(sc, cam, g)
+        # pixels with an ambiguous skip/stop decision (relative margin below
+        # 1e-5) are excluded and counted
+        ref, ref_a, amb = oracle.render(sc, cam, g, amb_px=True)
         scale, _ = oracle.render(sc, cam, np.abs(g))  # sum_i w_i(p) |g_i|
         got = outs[v].cpu().numpy().astype(np.float64)
         err = np.abs(got - ref) / np.maximum(scale, 1e-30)
-        print(f"render D={D} view {v}: max err {err.max():.3e}")
-        assert err.max() < 1e-4
-        assert np.abs(alphas[v].cpu().numpy() - ref_a).max() < 1e-5
+        ok = ~amb
+        print(f"render D={D} view {v}: max err {err[ok].max():.3e}, ambiguous pixels {int(amb.sum())}")
+        assert amb.sum() <= 0.001 * amb.size
+        assert err[ok].max() < 1e-4
+        assert np.abs(alphas[v].cpu().numpy() - ref_a)[ok].max() < 1e-5
         assert np.all(ref_a <= 1.0 + 1e-12)
 
 

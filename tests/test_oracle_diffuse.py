@@ -59,3 +59,30 @@ def test_power_method_reaches_dominant_eigenvector():
     g1 = od.diffuse(sp.csr_matrix(M), g, 1)
     assert np.linalg.norm(g1) == np.float64(np.linalg.norm(g1))
     assert abs(np.linalg.norm(g1) - w[-1]) < 1e-9 * w[-1]
+
+
+def test_bf16_rounding_matches_library_conversion():
+    """On FP32 inputs (where no double rounding can occur) the BF16 rounding
+    of the storage option equals torch's float32 -> bfloat16 conversion
+    (round to nearest, ties to even), ties and subnormals included."""
+    import torch
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.normal(size=20000), rng.normal(size=2000) * 1e-38,
+                        rng.uniform(-1, 1, 2000) * 1e30]).astype(np.float32)
+    bits = x.view(np.uint32)
+    ties = ((bits & ~np.uint32(0xFFFF)) | np.uint32(0x8000)).view(np.float32)  # exact halfway cases
+    x = np.concatenate([x, ties, np.float32([0.0, -0.0, 1.0, 2.0 ** -133, 3 * 2.0 ** -134])])
+    ref = torch.from_numpy(x).to(torch.bfloat16).float().numpy().astype(np.float64)
+    assert np.array_equal(od.round_bf16(x.astype(np.float64)), ref)
+
+
+def test_bf16_storage_diffusion_stays_on_the_bf16_grid():
+    n = 200
+    _, _, A = random_graph(n, 8, 6)
+    g0 = np.random.default_rng(7).uniform(0, 1, (n, 2))
+    g = od.diffuse(A, od.round_bf16(g0), 3, store="bf16")
+    assert np.array_equal(g, od.round_bf16(g))
+    ref = od.diffuse(A, od.round_bf16(g0), 3)
+    # each step: one relative rounding of at most 2^-9, averaged by a
+    # row-stochastic A
+    assert np.max(np.abs(g - ref) / np.max(np.abs(ref), axis=0)) <= 3 * 2.0 ** -9

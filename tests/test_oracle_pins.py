@@ -18,6 +18,7 @@ from synth.scenes import Camera, Scene
 F32 = np.float32
 ALPHA_MAX = float(F32(0.99))
 ALPHA_MIN = float(F32(1.0) / F32(255.0))
+T_EPS = float(F32(1e-4))
 
 
 def one_scene(means, scales, quats=None, opacity=None):
@@ -54,16 +55,6 @@ def test_generators_are_counter_based():
 
 
 # ------------------------------------------------------------ S32 helpers
-def test_exp32_accuracy_and_exact_points():
-    x = np.concatenate([np.linspace(-80, 0, 200001), -np.logspace(-8, 1.9, 5000), [0.0, -0.0]]).astype(F32)
-    y = oracle.exp32(x).astype(np.float64)
-    ref = np.exp(x.astype(np.float64))
-    ulp = np.spacing(ref.astype(F32)).astype(np.float64)
-    assert np.max(np.abs(y - ref) / ulp) <= 2.0
-    assert oracle.exp32(np.array([0.0], F32))[0] == 1.0
-    assert oracle.exp32(np.array([-81.0], F32))[0] == 0.0
-
-
 def test_covariance_factor_matches_library_rotation():
     """M = R diag(s) against scipy's quaternion rotation, and M M^T against the
     covariance R diag(s)^2 R^T (Sec. 3.1)."""
@@ -202,12 +193,83 @@ def test_termination_at_T_eps():
 
 def test_alpha_clamp_uses_fp32_constants():
     """Two opaque Gaussians: alpha = 0.99f, then T' = (1 - 0.99f)^2 = 9.99998e-5
-    < 1e-4f, so the second is excluded (with decimal 0.99 it would count)."""
+    < 1e-4f, so the second is excluded (with decimal 0.99 it would count).  The
+    margin, 1.9e-6 relative, is below the ambiguity threshold: the pixel is
+    reported ambiguous, and the second Gaussian flagged, the first not."""
     means = np.array([[0, 0, 0], [0, 0, 0.1]], F32)
     sc = one_scene(means, np.full((2, 3), 0.5), opacity=np.ones(2))
-    out, alpha = oracle.render(sc, axis_camera(100.0), np.eye(2))
+    cam = axis_camera(100.0)
+    out, alpha, amb = oracle.render(sc, cam, np.eye(2), amb_px=True)
     assert alpha[64, 64] == ALPHA_MAX
     assert out[64, 64, 1] == 0.0
+    assert amb[64, 64]
+    r = oracle.uplift(sc, [cam], [np.ones((129, 129, 1), F32)])
+    t_next = (1.0 - ALPHA_MAX) ** 2
+    assert r.margin_stop == pytest.approx(abs(t_next - T_EPS) / T_EPS, rel=1e-9)
+    assert r.margin_stop < oracle.AMB_THR and r.amb[1] >= 1
+
+
+# ------------------------------------------------------ decision margins
+def _centre_counts(sc, cam):
+    up = oracle.Uplifter(sc, 1)
+    amb = up.add_view(cam, np.ones((cam.height, cam.width, 1), F32), amb_px=True)
+    return up.result(), amb
+
+
+def test_alpha_next_to_skip_threshold_is_flagged():
+    """A Gaussian centred on pixel (64, 64) has alpha = opacity there (power 0).
+    With the opacity one FP32 ulp above 1/255 (4.7e-10 above it, relative
+    margin 1.2e-7) it counts
+    and the pixel is ambiguous; one ulp below, it is skipped and the pixel is
+    still ambiguous; 1e-3 above, nothing is ambiguous.  A wide Gaussian in
+    front keeps its weight and is not flagged; one behind is flagged (its T
+    depends on the decision)."""
+    amin32 = F32(1.0) / F32(255.0)
+    up1 = float(np.nextafter(amin32, F32(1)))
+    dn1 = float(np.nextafter(amin32, F32(0)))
+    cam = axis_camera(100.0)
+    means = np.array([[0, 0, -0.2], [0, 0, 0], [0, 0, 0.2]], F32)
+    scales = np.array([[0.2] * 3, [0.01] * 3, [0.2] * 3], F32)
+    for op, counted, ambiguous in ((up1, 1, True), (dn1, 0, True),
+                                   (float(amin32) * 1.001, 1, False)):
+        sc = one_scene(means, scales, opacity=[0.5, op, 0.5])
+        r, amb = _centre_counts(sc, cam)
+        # the small Gaussian counts at the centre pixel only (its neighbours
+        # see a quarter of the opacity, far below 1/255)
+        assert r.count[1] == counted
+        assert bool(amb[64, 64]) == ambiguous and amb.sum() == int(ambiguous)
+        assert r.amb_px == int(ambiguous)
+        if ambiguous:
+            assert r.margin_skip == pytest.approx(abs(op - ALPHA_MIN) / ALPHA_MIN, rel=1e-9)
+            assert abs(op - ALPHA_MIN) < 1e-9 and r.margin_skip < 2e-7
+            assert list(r.amb) == [0, 1, 1]
+        else:
+            assert r.margin_skip > 1e-4 and not r.amb.any()
+
+
+def test_transmittance_next_to_stop_threshold_is_flagged():
+    """13 stacked wide Gaussians with opacity 0.5 leave T = 2^-13 at the centre
+    pixel; a 14th with opacity fl32(1 - 1e-4f 2^13) gives T' within 1e-7 of
+    1e-4: the pixel is ambiguous and only the 14th is flagged there."""
+    n = 14
+    means = np.array([[0, 0, 0.05 * k] for k in range(n)], F32)
+    op14 = F32(1.0 - T_EPS * 2.0 ** 13)
+    sc = one_scene(means, np.full((n, 3), 0.5), opacity=[0.5] * 13 + [float(op14)])
+    cam = axis_camera(100.0)
+    r, amb = _centre_counts(sc, cam)
+    t_next = 2.0 ** -13 * (1.0 - float(op14))
+    assert abs(t_next - T_EPS) / T_EPS < 1e-7
+    assert amb[64, 64]
+    assert r.margin_stop == pytest.approx(abs(t_next - T_EPS) / T_EPS, rel=1e-6)
+    # flags at the centre pixel alone: from the 14th on (the first 13 keep
+    # their weights whatever the stop decides)
+    _, _, amb_r = oracle.render(sc, cam, np.eye(n), amb_px=True)
+    assert np.array_equal(amb_r, amb.astype(bool))
+    only = one_scene(means, np.full((n, 3), 0.5), opacity=[0.5] * 13 + [float(op14)])
+    ro = oracle.uplift(only, [cam], [np.ones((129, 129, 1), F32)])
+    assert ro.amb[13] >= 1
+    if amb.sum() == 1:
+        assert not ro.amb[:13].any()
 
 
 def test_depth_order_front_to_back():
@@ -386,6 +448,7 @@ def test_brute_force_tiny_scenes(seed):
     beta, U, cnt, margin = brute_force(sc, cams, maps)
     assert margin > 1e-4
     r = oracle.uplift(sc, cams, maps)
+    assert r.amb_px == 0 and min(r.margin_skip, r.margin_stop) == pytest.approx(margin, rel=1e-6)
     assert cnt.sum() > 100
     assert np.array_equal(r.count, cnt)
     assert np.allclose(r.beta, beta, rtol=1e-9, atol=1e-300)
