@@ -63,7 +63,7 @@ def test_low_precision_storage_within_stated_bounds(dtype):
     ref32 = oracle.uplift(sc, cams, [m.cpu().numpy() for m in maps32])
     refq = oracle.uplift(sc, cams, [m.cpu().numpy() for m in dec])
     assert feature_error(f, refq).max() < 1e-4
-    seen = ref32.beta > 0
+    seen = (ref32.beta > 0) & ref32.strict  # no ambiguous decision
     d = np.abs(f[seen] - ref32.f[seen])
     a = ref32.a[seen]
     if dtype == "bf16":
@@ -214,7 +214,7 @@ def test_large_full_size_precision_sampled():
     for k, cam in enumerate(cams):
         up.add_view(cam, maps32[k].cpu().numpy())
     ref32 = up.result()
-    seen = ref32.beta[rows] > 0
+    seen = (ref32.beta[rows] > 0) & ref32.strict[rows]  # no ambiguous decision
     a = ref32.a[seen]
     for dtype, (f, smax) in results.items():
         d = np.abs(f[seen] - ref32.f[seen])
