@@ -1,32 +1,38 @@
 #!/usr/bin/env python3
 """Benchmark of the uplift hot path on one MI355X.
 
-Workload (the mid configuration): 200,000 Gaussians (centres U[-1,1]^3,
-scales exp(N(-4, 0.5^2)), uniform rotations, opacities sigmoid(N(0,1))), 50
-Fibonacci-sphere cameras at radius 4, 512x384 px, 55 deg horizontal FoV; two
-feature sets per view: D = 64 FP32 maps (N(0,1) at 1/14 resolution, bilinearly
-upsampled) and a D = 1 ellipse mask.  Inputs are generated before timing and
-are resident in HBM.
+Headline workload (the large precision configuration): 1,000,000 Gaussians
+(centres U[-1,1]^3, scales exp(N(-5, 0.7^2)), uniform rotations, opacities
+sigmoid(N(0.5, 1))), 100 Fibonacci-sphere cameras at radius 4, 1008x756 px,
+55 deg horizontal FoV; D = 384 feature maps (N(0,1) at 1/14 resolution,
+bilinearly upsampled), stored BF16 (the headline), FP32 and FP8 E4M3 with
+per-(view, channel) scales; FP32 accumulation throughout.  Every map of the
+three storage formats is generated and resident in HBM before timing
+(205 GB).
 
-One step = the whole job on that workload: make the scene resident
-(lv_scene_create), uplift the D = 64 maps and the D = 1 masks of all 50 views
-(lv_uplift, FP32), release the scene.  value = ms per (view x channel) over
-the 50 x 65 view-channels of a step.
+One step = the whole uplift job on that workload: make the scene resident
+(lv_scene_create), uplift the 100 BF16 maps (lv_uplift: structure build and
+blend-accumulate of all views, finalize), release the scene.  value = ms per
+(view x channel) = ms_per_step / (100 x 384).
 
-Also reported, measured in the same run outside the timed steps:
-  roofline      the blend-and-accumulate kernel of the D = 64 uplift, timed with
-                HIP events around each launch during the timed steps;
-  bf16          BF16 storage of the D = 64 maps (encode + uplift) and its error
-                against the FP32 result;
-  filtering     pruning by weight sum and the count-normalised finalize;
-  render        the forward render (Eq. 4) of the uplifted D = 64 features into
-                all 50 views, with opacity;
-  diffuse       100 steps of Eq. (8) on a 16-NN graph of the scene (D = 1 and 64),
-                the graph build, and the segmentation diffusion (Eq. 7 / 9);
-  serving       a synthetic request trace through the server;
-  cpu_baseline  the FP64 oracle on a sample of the same workload, host cores.
+Also in the same JSON line:
+  roofline      the blend-and-accumulate kernel of the headline step, timed
+                with HIP events on its stream during the timed steps, against
+                the HBM and FP32-FMA roofs of its algorithmic bytes and flops
+                (the binding one named), plus its matrix-core share;
+  storage       the FP32 and FP8 legs of the same job, and the error of every
+                storage leg against the FP64 oracle on a 20,000-Gaussian
+                subsample (views given by --oracle-views);
+  mid           the mid configuration (200k Gaussians, 50 views of 512x384,
+                D = 64 maps + a D = 1 mask in one pass), FP32 and BF16;
+  diffuse       the uplift + diffusion configuration: 16-NN graph of the large
+                scene built on the device from D = 64 uplifted features, 100
+                steps of Eq. (8) at D = 1 and D = 64, FP32 and BF16 storage;
+  serving       the serving trace through the request server;
+  cpu_baseline  the FP64 oracle on a bounded sample of the headline workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,14 +42,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "uplift ms/view/channel + % HBM roofline, BF16 vs FP32 @ tol; p50/p99 latency"
-HBM_PEAK_GBS = 8000.0
-# FP32 FMA on the vector ALUs without packed-FP32 instructions:
-# 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
-ALU_PEAK_TFLOPS = 78.6
-ALU_PEAK_PACKED_TFLOPS = 157.3
-# Device-scope atomic updates in the L2: one 4-byte update per L2 channel per
-# clock, 8 XCDs x 16 channels x 2.4 GHz
-ATOMIC_PEAK_GPS = 307.2
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3        # MI355X vector FP32 (packed FMA)
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
+SUBSAMPLE = 20_000
 
 
 def log(*a):
@@ -62,69 +64,105 @@ def percentile(xs, q):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-views", type=int, default=6,
-                    help="views of the workload the CPU-baseline oracle runs (0 = skip)")
-    ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a 1 GiB device copy (reference for HBM traffic counters)")
-    ap.add_argument("--serve-requests", type=int, default=40,
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--legs", default="f32,fp8", help="storage legs besides the BF16 headline")
+    ap.add_argument("--oracle-views", type=int, default=6,
+                    help="views of the headline workload the FP64 oracle runs (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving trace (0 = skip the serving leg)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, req/s")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2410_14462_amd as lv
-    from synth import scenes
 
     torch.cuda.set_device(0)
-    w = scenes.WORKLOADS["mid"]
+    out, keep = large_leg(lv, args)
+    if args.calib_copy:
+        src = torch.empty(1 << 28, device="cuda", dtype=torch.float32).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 4
+        del src, dst
+    del keep
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["mid"] = mid_leg(lv, args)
+        torch.cuda.empty_cache()
+        out["diffuse"] = diffusion_leg(lv)
+        torch.cuda.empty_cache()
+        if args.serve_requests > 0:
+            out["serving"] = serving(lv, args.serve_requests, args.serve_rate)
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ headline
+def large_leg(lv, args):
+    import numpy as np
+    import torch
+
+    from synth import scenes
+
+    w = scenes.WORKLOADS["large"]
     n, m, H, W, D = w.n, w.m, w.height, w.width, w.D
-    log(f"bench: {w.name}: generating inputs")
+    log(f"bench: {w.name}: scene, rig, {m} maps x 3 storage formats")
     sc = scenes.scene_for(w)
     cams = scenes.cameras_for(w)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     means, scales, quats, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacity)
-    maps = [scenes.feature_map(w, v, device="cuda") for v in range(m)]
-    masks = [dev(scenes.ellipse_mask(w.seed, v, H, W)) for v in range(m)]
-    f64 = torch.empty((n, D), device="cuda")
-    b64 = torch.empty((n,), device="cuda")
-    f1 = torch.empty((n, 1), device="cuda")
-    b1 = torch.empty((n,), device="cuda")
+    legs = ["bf16"] + [x for x in args.legs.split(",") if x in ("f32", "fp8")]
+    maps32, maps16, codes8, sc8 = [], [], [], []
+    for v in range(m):
+        f = scenes.feature_map(w, v, device="cuda")
+        maps16.append(lv.encode(f, "bf16")[0])
+        if "fp8" in legs:
+            c, s = lv.encode(f, "fp8")
+            codes8.append(c)
+            sc8.append(s)
+        if "f32" in legs:
+            maps32.append(f)
+        del f
+    scales8 = torch.stack(sc8).contiguous() if sc8 else None
     torch.cuda.synchronize()
+    rig = lv.Cameras(cams)
+    tabs = {"bf16": (lv.Maps(maps16, "bf16"), None)}
+    if "f32" in legs:
+        tabs["f32"] = (lv.Maps(maps32), None)
+    if "fp8" in legs:
+        tabs["fp8"] = (lv.Maps(codes8, "fp8"), scales8)
+    fout = torch.empty((n, D), device="cuda")
+    bout = torch.empty((n,), device="cuda")
 
-    # the rig and the two map lists marshalled once (pointer tables), as a
-    # C caller would hold them
-    rig, tab64, tab1 = lv.Cameras(cams), lv.Maps(maps), lv.Maps(masks)
-
-    def step():
+    def step(dt):
+        tab, s8 = tabs[dt]
         s = lv.Scene(means, scales, quats, opac)
-        s.uplift_sets(rig, [tab64, tab1], outs=[(f64, b64), (f1, b1)])
+        s.uplift(rig, tab, dtype=dt, scales=s8, out=fout, wsum=bout)
         s.close()
 
-    # work statistics (untimed pass with counters)
+    # work statistics of the headline pass (untimed, with counters)
     s = lv.Scene(means, scales, quats, opac)
-    acc, accm = lv.Accum(s, D, counts=True), lv.Accum(s, 1, counts=True)
-    lv.accumulate_sets(cams, [(acc, maps), (accm, masks)])
-    st64 = acc.stats()
+    acc = lv.Accum(s, D, counts=True)
+    acc.add(rig, tabs["bf16"][0], dtype="bf16")
+    stats = acc.stats()
     acc.close()
-    accm.close()
     s.close()
-    log(f"bench: stats {st64}")
+    log(f"bench: stats {stats}")
 
-    log(f"bench: warmup {args.warmup}")
+    log(f"bench: headline (bf16): warmup {args.warmup}, timing {args.steps} steps")
     for _ in range(args.warmup):
-        step()
+        step("bf16")
     torch.cuda.synchronize()
-
-    log(f"bench: timing {args.steps} steps")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     lv.profile_start()
@@ -132,53 +170,49 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record()
-        step()
+        step("bf16")
         ev[k][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches = lv.profile_stop()
     lat = [a.elapsed_time(b) for a, b in ev]
     ms_step = (t1 - t0) * 1e3 / args.steps
-    value = ms_step / (m * (D + 1))
+    value = ms_step / (m * D)
     log(f"bench: {ms_step:.3f} ms/step, {value * 1e3:.4f} us/view/channel")
+    roof = roofline(stats, launches, args.steps, n, D, 2, products=2,
+                    kernel="blend_wide_kernel<LV_BF16, true> (D=384 BF16 maps)",
+                    traffic_name="blend_wide_kernel-uplift-1M-100v-1008x756-D384-bf16")
 
-    # the blend launch of a step serves both feature sets (65 channels)
-    t64 = sum(launches) / len(launches) * 1e-3
-    C = D + 1
-    bytes64 = (st64["covered_pixels"] * C * 4 + st64["visible"] * 32 + st64["pairs"] * 4
-               + n * (C + 4) * 4)
-    flops64 = 2.0 * st64["contributions"] * (C + 2)
-    hbm_gbs = bytes64 / t64 / 1e9
-    alu_tflops = flops64 / t64 / 1e12
-    t_hbm, t_alu = bytes64 / (HBM_PEAK_GBS * 1e9), flops64 / (ALU_PEAK_TFLOPS * 1e12)
-    if t_alu >= t_hbm:
-        roof = {"bound": "alu", "achieved": round(alu_tflops, 3), "peak": ALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(alu_tflops / ALU_PEAK_TFLOPS, 4)}
-    else:
-        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
-    roof.update({
-        "traffic": measured_traffic(),
-        "kernel": "blend_wide_kernel<LV_F32> (D=64 maps + D=1 mask, 50 views per launch)",
-        "launch_ms": round(t64 * 1e3, 4),
-        "hbm": {"achieved_GBs": round(hbm_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
-                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "alg_bytes": int(bytes64)},
-        "alu": {"achieved_TFLOPs": round(alu_tflops, 3), "peak_TFLOPs": ALU_PEAK_TFLOPS,
-                "frac": round(alu_tflops / ALU_PEAK_TFLOPS, 4),
-                "frac_of_packed_peak": round(alu_tflops / ALU_PEAK_PACKED_TFLOPS, 4),
-                "alg_flops": flops64},
-    })
-    # the resource that binds this kernel: one atomic update per channel and
-    # one for beta per (Gaussian, view, 8x8 block) partial sum
-    if st64.get("partial_sums", -1) > 0:
-        upd = st64["partial_sums"] * (C + 1)
-        roof["l2_atomics"] = {"achieved_Gps": round(upd / t64 / 1e9, 1), "peak_Gps": ATOMIC_PEAK_GPS,
-                              "frac": round(upd / t64 / 1e9 / ATOMIC_PEAK_GPS, 4),
-                              "updates": int(upd), "partial_sums": int(st64["partial_sums"])}
+    # the other storage legs: same job, same timing
+    storage = {"bf16": {"ms_per_step": round(ms_step, 3), "ms_per_view_channel": round(value, 7),
+                        "blend_ms_per_step": round(sum(launches) / args.steps, 3)}}
+    for dt in legs[1:]:
+        log(f"bench: storage leg {dt}")
+        step(dt)
+        torch.cuda.synchronize()
+        lv.profile_start()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step(dt)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) * 1e3 / reps
+        bl = lv.profile_stop()
+        storage[dt] = {"ms_per_step": round(t, 3), "ms_per_view_channel": round(t / (m * D), 7),
+                       "blend_ms_per_step": round(sum(bl) / reps, 3)}
+    storage["bf16_speedup_vs_f32"] = (round(storage["f32"]["ms_per_step"] / ms_step, 3)
+                                      if "f32" in storage else None)
+
+    cpu = None
+    if args.oracle_views > 0:
+        errs, cpu = oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, codes8,
+                                  scales8, args.oracle_views)
+        for dt, e in errs.items():
+            storage.setdefault(dt, {})["error"] = e
 
     out = {
         "metric": METRIC,
-        "value": round(value, 7),
+        "value": round(value, 8),
         "unit": "ms/view/channel",
         "n_gpus": 1,
         "steps": args.steps,
@@ -190,44 +224,26 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "gaussians": n, "views": m, "width": W, "height": H,
-                   "channels": [D, 1], "map_dtype": "f32"},
-        "latency_ms": {"p50": round(percentile(lat, 0.5), 4), "p99": round(percentile(lat, 0.99), 4)},
-        "contributions_per_s": round(st64["contributions"] / t64, 1),
-        "work": st64,
+                   "channels": D, "storage": "bf16", "accumulation": "f32",
+                   "contraction": "split-BF16 matrix-core products, FP32 accumulate (BF16 maps: "
+                                  "2 exact products per term; FP32 and FP8 maps: 3, error < 2^-16 |w F|)"},
+        "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)},
+        "contributions_per_s": round(stats["contributions"] / (sum(launches) / args.steps * 1e-3), 1),
+        "work": stats,
         "roofline": roof,
+        "storage": storage,
     }
-
-    if args.calib_copy:
-        src = torch.empty(1 << 28, device="cuda", dtype=torch.float32).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = src.numel() * 4
-        del src, dst
-
-    if not args.no_extras:
-        out.update(extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac))
-
-    if args.serve_requests > 0:
-        del maps, masks, f64, b64, f1, b1
-        torch.cuda.empty_cache()
-        out["serving"] = serving(lv, args.serve_requests, args.serve_rate)
-        maps = [scenes.feature_map(w, v, device="cuda") for v in range(args.cpu_views)]
-        masks = [dev(scenes.ellipse_mask(w.seed, v, H, W)) for v in range(args.cpu_views)]
-
-    if args.cpu_views > 0:
-        out["cpu_baseline"] = cpu_baseline(w, sc, cams, maps, masks, args.cpu_views)
-        out["cpu_baseline"]["gpu_over_cpu"] = round(out["cpu_baseline"]["value"] / value, 1)
-
-    print(json.dumps(out), flush=True)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        out["cpu_baseline"]["cpu_over_gpu"] = round(cpu["value"] / value, 1)
+    keep = (maps32, maps16, codes8, scales8, tabs)
+    return out, keep
 
 
-def measured_traffic():
-    """HBM bytes per D=64 blend launch from the committed FETCH_SIZE/WRITE_SIZE
+def measured_traffic(name):
+    """HBM bytes per blend launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, if it was taken on the current kernel source (else None)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "uplift-200k-50v-512x384-D64+mask_blend_traffic.json")
+    path = os.path.join(ROOT, "profiles", name + "_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -239,172 +255,247 @@ def measured_traffic():
     return int(rec["traffic_bytes"])
 
 
-def extras(lv, w, sc, cams, maps, f64, b64, f1, means, scales, quats, opac):
+def roofline(st, launches, steps, n, D, s_f, products, kernel, traffic_name):
+    """Blend-accumulate against its roofs.  Algorithmic bytes of a step: the
+    features of covered pixels (covered_px D s_F), one 24-byte projected
+    record per visible (view, Gaussian), one 4-byte id per (tile, Gaussian)
+    pair, and U and beta written once per launch (n (D + 1) 4).  Flops: one
+    FMA per channel per counted contribution plus ~15 for alpha, T and w
+    (2 nnz D + 15 nnz).  The FP32-FMA roof prices those flops at 157.3
+    TFLOP/s; the matrix-core share prices the contraction as it runs (2 nnz D
+    per product, `products` split-BF16 products) at 2.5 PFLOP/s."""
+    per_step = len(launches) / steps
+    t = sum(launches) / len(launches) * 1e-3          # average launch, s
+    nb = (st["covered_pixels"] * D * s_f + st["visible"] * 24 + st["pairs"] * 4
+          + per_step * n * (D + 1) * 4) / per_step     # bytes per launch
+    nnz = st["contributions"] / per_step
+    fl = 2.0 * nnz * D + 15.0 * nnz
+    mf = 2.0 * nnz * D * products
+    gbs, tfl = nb / t / 1e9, fl / t / 1e12
+    hbm = {"achieved_GBs": round(gbs, 1), "peak_GBs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "alg_bytes_per_launch": int(nb)}
+    fma = {"achieved_TFLOPs": round(tfl, 2), "peak_TFLOPs": FP32_PEAK_TFLOPS,
+           "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "alg_flops_per_launch": fl}
+    mfma = {"achieved_TFLOPs": round(mf / t / 1e12, 2), "peak_TFLOPs": MFMA_BF16_PEAK_TFLOPS,
+            "frac": round(mf / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4), "products_per_term": products}
+    if nb / (HBM_PEAK_GBS * 1e9) >= fl / (FP32_PEAK_TFLOPS * 1e12):
+        roof = {"bound": "hbm", "achieved": hbm["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm["frac"]}
+    else:
+        roof = {"bound": "alu", "achieved": fma["achieved_TFLOPs"], "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": fma["frac"]}
+    roof.update({"traffic": measured_traffic(traffic_name), "kernel": kernel,
+                 "launches_per_step": per_step, "launch_ms": round(t * 1e3, 4),
+                 "hbm": hbm, "fma_fp32": fma, "mfma_bf16": mfma})
+    if st.get("partial_sums", -1) > 0:
+        # the diagnostic that limits this kernel: one device-scope FP32 atomic
+        # per channel and one for beta per (Gaussian, view, 8x8 block)
+        upd = st["partial_sums"] / per_step * (D + 1)
+        roof["atomics"] = {"updates_per_launch": int(upd), "achieved_Gps": round(upd / t / 1e9, 1),
+                           "partial_sums_per_launch": int(st["partial_sums"] / per_step)}
+    return roof
+
+
+def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, codes8, scales8, nv):
+    """Each storage leg's result over the first nv views against the FP64
+    oracle on a 20,000-Gaussian subsample: total error (oracle on the FP32
+    maps) and accumulation error (oracle on the decoded stored maps), in units
+    of a = sum w |F| / beta; Gaussians flagged by an ambiguous skip/stop
+    decision are excluded and counted.  The first oracle run is also the CPU
+    baseline."""
     import numpy as np
     import torch
 
-    res = {}
-    n, m, D = w.n, w.m, w.D
+    import oracle
+    from synth import scenes
+
+    rows = scenes.subsample(w.seed, sc.n, SUBSAMPLE)
+    views = list(range(nv))
+    c = [cams[v] for v in views]
     s = lv.Scene(means, scales, quats, opac)
-    # ---- BF16 storage (codec + uplift) against the FP32 result
-    log("bench: bf16 leg")
+    gpu = {"bf16": s.uplift(c, [maps16[v] for v in views], dtype="bf16")}
+    if maps32:
+        gpu["f32"] = s.uplift(c, [maps32[v] for v in views])
+    if codes8:
+        gpu["fp8"] = s.uplift(c, [codes8[v] for v in views], dtype="fp8",
+                              scales=scales8[:nv].contiguous())
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    enc = [lv.encode(mp, "bf16")[0] for mp in maps]
-    torch.cuda.synchronize()
-    t_enc = time.perf_counter() - t0
-    # the codec kernel itself: one call over all 50 maps stacked (the wall
-    # time above is mostly the per-call marshalling of 50 separate maps)
-    stacked = torch.stack(maps)
-    lv.encode(stacked, "bf16")  # warm
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(3):
-        lv.encode(stacked, "bf16")
-    e1.record()
-    torch.cuda.synchronize()
-    t_enc_gpu = e0.elapsed_time(e1) * 1e-3 / 3
-    enc_bytes = stacked.numel() * (4 + 2)
-    del stacked
-    fb = torch.empty((n, D), device="cuda")
-    bb = torch.empty((n,), device="cuda")
-    s.uplift(cams, enc, dtype="bf16", out=fb, wsum=bb)  # warm
-    reps = 5
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        s.uplift(cams, enc, dtype="bf16", out=fb, wsum=bb)
-    torch.cuda.synchronize()
-    t_bf = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        s.uplift(cams, maps, out=f64, wsum=b64)
-    torch.cuda.synchronize()
-    t_f32 = (time.perf_counter() - t0) / reps
-    # error scale a = uplift of |F| (sum w |F| / beta)
-    absmaps = [mp.abs() for mp in maps]
-    fa, _ = s.uplift(cams, absmaps)
-    seen = b64 > 0
-    err = ((fb - f64).abs() / fa.clamp_min(1e-30))[seen]
-    res["bf16"] = {
-        "encode_ms": round(t_enc * 1e3, 3),
-        "encode_stacked_ms": round(t_enc_gpu * 1e3, 3),
-        "encode_GBs": round(enc_bytes / t_enc_gpu / 1e9, 1),
-        "uplift_ms": round(t_bf * 1e3, 3),
-        "uplift_ms_f32": round(t_f32 * 1e3, 3),
-        "ms_per_view_channel": round(t_bf * 1e3 / (m * D), 7),
-        "ms_per_view_channel_f32": round(t_f32 * 1e3 / (m * D), 7),
-        "err_vs_f32": {"max": float(err.max()), "p99": float(torch.quantile(err[:1000000], 0.99)),
-                       "mean": float(err.mean()), "bound": 2.0 ** -8 + 1e-4},
-    }
-    del enc, absmaps
-    # ---- weight-based filtering (keep the half with the largest beta) and
-    # the count-normalised finalize
-    log("bench: filtering leg")
-    k = n // 2
-    keep = lv.prune_by_weight(b64, k)
-    reps = 20
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        keep = lv.prune_by_weight(b64, k)
-    torch.cuda.synchronize()
-    t_prune = (time.perf_counter() - t0) / reps
-    acc = lv.Accum(s, D, counts=True)
-    acc.add(cams, maps)
-    fc = acc.finalize_count()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        fc = acc.finalize_count()
-    torch.cuda.synchronize()
-    t_fc = (time.perf_counter() - t0) / reps
-    res["filtering"] = {"n": n, "kept": int(keep.sum()), "prune_ms": round(t_prune * 1e3, 4),
-                        "finalize_count_ms": round(t_fc * 1e3, 4)}
-    del acc, fc, keep
-    # ---- forward render (Eq. 4) of the uplifted D=64 features into all views
-    log("bench: render leg")
-    outs, alps = s.render(cams, f64)  # warm (and output allocation)
-    del outs, alps
-    reps = 3
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        outs, alps = s.render(cams, f64)
-    torch.cuda.synchronize()
-    t_r = (time.perf_counter() - t0) / reps
-    H, W = w.height, w.width
-    out_bytes = m * H * W * (D + 1) * 4  # rendered features and opacity, written once
-    res["render"] = {"ms": round(t_r * 1e3, 3), "ms_per_view_channel": round(t_r * 1e3 / (m * D), 7),
-                     "output_GB": round(out_bytes / 1e9, 3),
-                     "output_GBs": round(out_bytes / t_r / 1e9, 1),
-                     "hbm_frac_of_output_bytes": round(out_bytes / t_r / 1e9 / HBM_PEAK_GBS, 4)}
-    del outs, alps
-    # ---- diffusion over the 16-NN graph of the scene, built on the device
-    # from the uplifted features
-    log("bench: diffusion leg (16-NN graph built on the device)")
-    G = lv.Graph.knn(s, f64, 16)
-    G.close()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    G = lv.Graph.knn(s, f64, 16)
-    torch.cuda.synchronize()
-    t_graph = time.perf_counter() - t0
-    nnz = int(G.csr()[1].shape[0])
-    dres = {"graph_nnz": nnz, "graph_build_ms": round(t_graph * 1e3, 3), "steps": 100}
-    # with the scene: rows in the Morton order of the centres (built on the
-    # first call); without: the caller's order
-    for name, g0, scene in (("D1", f1.contiguous(), s), ("D64", f64, s),
-                            ("D64_caller_order", f64, None)):
-        out = G.diffuse(g0, 100, scene=scene)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out = G.diffuse(g0, 100, scene=scene, out=out)
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / 100
-        Dg = g0.shape[1]
-        byts = 4 * (n + 1) + nnz * 8 + 2 * n * Dg * 4
-        dres[name] = {"ms_per_step": round(t * 1e3, 4), "GBs": round(byts / t / 1e9, 1),
-                      "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4)}
-    G.close()
-    # the paper's segmentation diffusion: binarised Eq. 7 / Eq. 9 graph with a
-    # unary term, anchors from the uplifted mask, 10 steps, reached nodes
-    log("bench: segmentation diffusion (Eq. 7 / Eq. 9 graph)")
-    unary = torch.rand(n, device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
-    kw = dict(kind="feature_rbf", bandwidth=0.5, unary=unary, binarize=1e-5)
-    Gs = lv.Graph.knn(s, f64, 16, **kw)
-    Gs.close()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Gs = lv.Graph.knn(s, f64, 16, **kw)
-    torch.cuda.synchronize()
-    t_sg = time.perf_counter() - t0
-    g0 = lv.anchor_init(f1.reshape(-1).contiguous(), 0.1)
-    gT = Gs.diffuse(g0, 10, scene=s)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g0 = lv.anchor_init(f1.reshape(-1).contiguous(), 0.1)
-    gT = Gs.diffuse(g0, 10, scene=s, out=gT)
-    h = lv.reach_unary(gT, unary)
-    torch.cuda.synchronize()
-    t_seg = time.perf_counter() - t0
-    dres["segmentation"] = {"graph_build_ms": round(t_sg * 1e3, 3), "graph_nnz": int(Gs.csr()[1].shape[0]),
-                            "anchors": int((g0 > 0).sum()), "steps": 10,
-                            "anchors_diffuse_reach_ms": round(t_seg * 1e3, 3),
-                            "reached": int((h > 0).sum())}
-    Gs.close()
-    res["diffuse"] = dres
     s.close()
+
+    def run(get):
+        up = oracle.Uplifter(sc, w.D, rows=rows)
+        for v in views:
+            up.add_view(cams[v], get(v))
+        return up.result()
+
+    log(f"bench: oracle on {nv} views, {SUBSAMPLE} Gaussians accumulated")
+    host32 = lambda v: scenes.feature_map(w, v, device="cuda").cpu().numpy()
+    t0 = time.perf_counter()
+    ref32 = run(host32)
+    t_cpu = time.perf_counter() - t0
+    decoded = {"bf16": lambda v: maps16[v].float().cpu().numpy(),
+               "fp8": lambda v: (codes8[v].view(torch.float8_e4m3fn).float() * scales8[v]).cpu().numpy(),
+               "f32": host32}
+    errs = {}
+    for dt, (f, b) in gpu.items():
+        f = f.cpu().numpy().astype(np.float64)[rows]
+        b = b.cpu().numpy().astype(np.float64)
+        refq = ref32 if dt == "f32" else run(decoded[dt])
+        res = {}
+        for name, ref in (("total", ref32), ("accumulation", refq)):
+            ok = (ref.beta[rows] > 0) & ref.strict[rows]
+            a = ref.a[ok]
+            e = np.abs(f[ok] - ref.f[ok]) / np.maximum(a, 1e-30)
+            res[name] = {"max": float(e.max()), "p99": float(np.quantile(e, 0.99)), "mean": float(e.mean())}
+        okb = (refq.beta > 0) & refq.strict
+        res["beta_rel_max"] = float((np.abs(b[okb] - refq.beta[okb]) / refq.beta[okb]).max())
+        res["bound_total"] = {"f32": "1e-4 a", "bf16": "2^-8 a + 1e-4 a",
+                              "fp8": "2^-4 a + 2^-10 scale + 1e-4 a"}[dt]
+        res["ambiguous_pixels"] = ref32.amb_px
+        res["excluded_gaussians"] = int((~ref32.strict[rows]).sum())
+        errs[dt] = res
+        log(f"bench: {dt} error {res}")
+    cpu = {"value": round(t_cpu * 1e3 / (nv * w.D), 4), "unit": "ms/view/channel (subsample)",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{nv} of {w.m} views, D={w.D}, every pixel walked over all {w.n} Gaussians, "
+                     f"{SUBSAMPLE} Gaussians accumulated, FP64",
+           "seconds": round(t_cpu, 2)}
+    return errs, cpu
+
+
+# --------------------------------------------------------------- mid config
+def mid_leg(lv, args):
+    """200k Gaussians, 50 views of 512x384, D = 64 maps and the D = 1 mask in
+    one pass; FP32 and BF16 storage; the blend's roofline for each."""
+    import numpy as np
+    import torch
+
+    from synth import scenes
+
+    w = scenes.WORKLOADS["mid"]
+    n, m, H, W, D = w.n, w.m, w.height, w.width, w.D
+    log(f"bench: mid leg {w.name}")
+    sc = scenes.scene_for(w)
+    cams = scenes.cameras_for(w)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    means, scales, quats, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacity)
+    maps = [scenes.feature_map(w, v, device="cuda") for v in range(m)]
+    masks = [dev(scenes.ellipse_mask(w.seed, v, H, W)) for v in range(m)]
+    rig = lv.Cameras(cams)
+    tab = {"f32": (lv.Maps(maps), lv.Maps(masks)),
+           "bf16": (lv.Maps([x.to(torch.bfloat16) for x in maps], "bf16"),
+                    lv.Maps([x.to(torch.bfloat16) for x in masks], "bf16"))}
+    outs = [(torch.empty((n, D), device="cuda"), torch.empty((n,), device="cuda")),
+            (torch.empty((n, 1), device="cuda"), torch.empty((n,), device="cuda"))]
+    s = lv.Scene(means, scales, quats, opac)
+    acc, accm = lv.Accum(s, D, counts=True), lv.Accum(s, 1, counts=True)
+    lv.accumulate_sets(cams, [(acc, maps), (accm, masks)])
+    st = acc.stats()
+    acc.close()
+    accm.close()
+    s.close()
+    res = {"workload": w.name, "work": st}
+    for dt in ("f32", "bf16"):
+        def step():
+            s = lv.Scene(means, scales, quats, opac)
+            s.uplift_sets(rig, list(tab[dt]), dtype=dt, outs=outs)
+            s.close()
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        lv.profile_start()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) * 1e3 / reps
+        bl = lv.profile_stop()
+        kname = "LV_F32" if dt == "f32" else "LV_BF16"
+        res[dt] = {"ms_per_step": round(t, 3), "ms_per_view_channel": round(t / (m * (D + 1)), 7),
+                   "roofline": roofline(st, bl, reps, n, D + 1, 4 if dt == "f32" else 2,
+                                        3 if dt == "f32" else 2, f"blend_wide_kernel<{kname}, false>",
+                                        f"blend_wide_kernel-{w.name}-{dt}")}
+        log(f"bench: mid {dt}: {res[dt]['ms_per_step']} ms/step, blend {res[dt]['roofline']['launch_ms']} ms")
+    res["bf16_speedup_vs_f32"] = round(res["f32"]["ms_per_step"] / res["bf16"]["ms_per_step"], 3)
+    res["bf16_blend_speedup_vs_f32"] = round(res["f32"]["roofline"]["launch_ms"]
+                                             / res["bf16"]["roofline"]["launch_ms"], 3)
     return res
 
 
-def serving(lv, nreq, rate, bank_k=4):
-    """The serving trace (synth.trace) twice: BF16 maps through the server
-    (2 workers, same-scene requests merged into one pass, admission by a
-    64 GiB accumulator budget), and FP32 maps one request at a time (1 worker,
-    no merging).  Latency = completion - submission; submissions follow the
-    trace's arrival times."""
+# ------------------------------------------------------ uplift + diffusion
+def diffusion_leg(lv):
+    """The uplift + diffusion configuration: D = 64 FP32 features uplifted
+    from the 100 views of the large scene, the 16-NN graph built on the device
+    from them, 100 steps of Eq. (8) on a D = 1 half-space mask and on the D =
+    64 features, FP32 and BF16 storage (signal and graph values).  Bytes of a
+    step: row pointers 4 (n + 1), columns and values nnz (4 + s_val), the
+    signal read and written once, 2 n D s_g."""
     import torch
+
+    from synth import scenes
+
+    w = scenes.WORKLOADS["diffuse"]
+    n, m, D = w.n, w.m, w.D
+    steps = w.extra["steps"]
+    log(f"bench: diffusion leg {w.name}")
+    sc = scenes.scene_for(w)
+    cams = scenes.cameras_for(w)
+    gs = lv.Scene.from_arrays(sc)
+    acc = lv.Accum(gs, D)
+    t_up = 0.0
+    for v0 in range(0, m, 10):
+        maps = [scenes.feature_map(w, v, device="cuda", D=D) for v in range(v0, v0 + 10)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc.add(cams[v0:v0 + 10], maps)
+        torch.cuda.synchronize()
+        t_up += time.perf_counter() - t0
+        del maps
+    f, _ = acc.finalize()
+    acc.close()
+    G = lv.Graph.knn(gs, f, w.extra["k"])
+    G.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G = lv.Graph.knn(gs, f, w.extra["k"])
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    rp, col, val = G.csr()
+    nnz = int(col.shape[0])
+    Gb = lv.Graph(rp, col, val.to(torch.bfloat16))
+    mask = torch.as_tensor(scenes.halfspace_indicator(w.seed, sc.means), device="cuda")
+    res = {"workload": w.name, "uplift_ms": round(t_up * 1e3, 2), "graph_build_ms": round(t_graph * 1e3, 2),
+           "graph_nnz": nnz, "steps": steps}
+    for name, g0, Gx, s_v, s_g in (("D1_f32", mask, G, 4, 4), ("D64_f32", f, G, 4, 4),
+                                   ("D1_bf16", mask.to(torch.bfloat16), Gb, 2, 2),
+                                   ("D64_bf16", f.to(torch.bfloat16), Gb, 2, 2)):
+        o = Gx.diffuse(g0, steps, scene=gs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = Gx.diffuse(g0, steps, scene=gs, out=o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        Dg = 1 if g0.dim() == 1 else g0.shape[1]
+        byts = 4 * (n + 1) + nnz * (4 + s_v) + 2 * n * Dg * s_g
+        res[name] = {"ms_per_step": round(t * 1e3, 4), "GBs": round(byts / t / 1e9, 1),
+                     "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_step": byts}
+        log(f"bench: diffuse {name}: {res[name]}")
+    G.close()
+    Gb.close()
+    gs.close()
+    return res
+
+
+# ------------------------------------------------------------------ serving
+def serving(lv, nreq, rate, bank_k=4):
+    """The serving trace (synth.trace) three times: BF16 maps through the
+    server (2 workers, same-scene requests merged into one pass, admission by
+    an HBM budget), FP32 maps through the same server settings, and FP32 maps
+    one request at a time (1 worker, no merging).  Latency = completion -
+    submission; submissions follow the trace's arrival times."""
+    import torch
+
     from synth import trace
     log(f"bench: serving leg ({nreq} requests at {rate}/s): scenes, rigs, map bank")
     scs = [lv.Scene.from_arrays(s) for s in trace.scenes()]
@@ -413,10 +504,11 @@ def serving(lv, nreq, rate, bank_k=4):
     bank16 = [[b.to(torch.bfloat16) for b in bk] for bk in bank32]
     reqs = trace.requests(nreq, rate)
     check = list(range(min(6, nreq)))  # requests whose BF16 and FP32 results are compared
+    budget = 64 << 30
 
     def run(dtype, workers, max_sets):
         bank = bank16 if dtype == "bf16" else bank32
-        srv = lv.Server(budget=64 << 30, workers=workers, max_sets=max_sets, max_channels=1024)
+        srv = lv.Server(budget=budget, workers=workers, max_sets=max_sets, max_channels=1024)
         # warm each worker's stream workspace on every scene (not timed)
         for k, g in enumerate(scs):
             for _ in range(workers):
@@ -448,11 +540,16 @@ def serving(lv, nreq, rate, bank_k=4):
         res = {"p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),
                "req_per_s": round(nreq / span, 3), "makespan_s": round(span, 3),
                "passes": st["passes"] - len(scs) * workers,
-               "mean_requests_per_pass": round(nreq / max(1, st["passes"] - len(scs) * workers), 2)}
+               "mean_requests_per_pass": round(nreq / max(1, st["passes"] - len(scs) * workers), 2),
+               "peak_budget_bytes": st["peak_bytes"]}
+        if "peak_device_bytes" in st:
+            res["peak_device_bytes"] = st["peak_device_bytes"]
         return res, kept
 
     served, out16 = run("bf16", 2, 8)
-    log(f"bench: served {served}")
+    log(f"bench: served bf16 {served}")
+    served32, _ = run("f32", 2, 8)
+    log(f"bench: served f32 {served32}")
     base, out32 = run("f32", 1, 1)
     log(f"bench: baseline {base}")
     err = 0.0
@@ -460,32 +557,20 @@ def serving(lv, nreq, rate, bank_k=4):
         a, b = out16[k].double(), out32[k].double()
         err = max(err, float(((a - b).abs().max(dim=0).values / b.abs().max(dim=0).values.clamp_min(1e-30)).max()))
     views = [len(r.views) for r in reqs]
+    for g in scs:
+        g.close()
     return {
-        "trace": {"requests": nreq, "rate_per_s": rate, "scenes": list(trace.SCENE_SIZES),
-                  "resolutions": [list(x) for x in trace.RESOLUTIONS], "D": list(trace.D_CHOICES),
-                  "views_mean": round(sum(views) / len(views), 1)},
+        "trace": {"requests": nreq, "of_configured": 2000, "rate_per_s": rate,
+                  "scenes": list(trace.SCENE_SIZES), "resolutions": [list(x) for x in trace.RESOLUTIONS],
+                  "D": list(trace.D_CHOICES), "views_mean": round(sum(views) / len(views), 1),
+                  "budget_bytes": budget},
         "served_bf16": served,
+        "served_f32": served32,
         "baseline_f32_one_at_a_time": base,
         "speedup_req_per_s": round(served["req_per_s"] / base["req_per_s"], 3),
+        "bf16_vs_f32_served_req_per_s": round(served["req_per_s"] / served32["req_per_s"], 3),
         "bf16_vs_f32_max_rel_err": err,
     }
-
-
-def cpu_baseline(w, sc, cams, maps, masks, views):
-    """The FP64 oracle (unchanged) on the first `views` views of the workload,
-    both feature sets, all Gaussians; host threads as the oracle uses them."""
-    import oracle
-    log(f"bench: cpu baseline ({views} views)")
-    hm = [maps[v].cpu().numpy() for v in range(views)]
-    hk = [masks[v].cpu().numpy() for v in range(views)]
-    t0 = time.perf_counter()
-    oracle.uplift(sc, cams[:views], hm)
-    oracle.uplift(sc, cams[:views], hk)
-    t = time.perf_counter() - t0
-    return {"value": round(t * 1e3 / (views * (w.D + 1)), 4), "unit": "ms/view/channel",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{views} of {w.m} views, D=64 and D=1, all {w.n} Gaussians, FP64",
-            "seconds": round(t, 2)}
 
 
 if __name__ == "__main__":

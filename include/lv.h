@@ -49,6 +49,7 @@
 #ifndef LV_H
 #define LV_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -60,7 +61,8 @@ typedef enum {
     LV_ERR_INVALID_ARG = 1,
     LV_ERR_OUT_OF_MEMORY = 2,
     LV_ERR_DEVICE = 3,
-    LV_ERR_UNSUPPORTED = 4
+    LV_ERR_UNSUPPORTED = 4,
+    LV_ERR_CANCELLED = 5     /* a server request cancelled before it ran */
 } lv_status;
 
 /* Storage type of feature maps / diffusion signals.  Arithmetic is FP32. */
@@ -89,18 +91,59 @@ typedef struct lv_graph lv_graph;
 /* Thread-local description of the last non-OK status of this thread. */
 const char* lv_last_error(void);
 
+/* ------------------------------------------------------- device memory -- */
+/* Every device buffer the library allocates -- cached scratch (structure
+ * builds, pair buffers), temporary scratch (graph builds, filtering, server
+ * accumulators) and the buffers its handles own -- comes from `alloc` and
+ * returns through `free` once registered (e.g. a framework's caching
+ * allocator); without one, hipMalloc / hipFree (hipMallocAsync /
+ * hipFreeAsync for temporary scratch).  alloc(bytes, stream, ctx) returns a
+ * device pointer (256-byte aligned) usable on `stream`, or NULL (the call
+ * then fails with LV_ERR_OUT_OF_MEMORY); free(ptr, bytes, stream, ctx)
+ * releases it after the work enqueued on `stream` (stream-ordered; NULL
+ * stream: the device is idle).  The callbacks may be called from any thread
+ * (the server's workers too).  lv_set_allocator(NULL, NULL, NULL) restores
+ * the default.  It first releases the cached scratch (lv_release_scratch of
+ * every stream) and fails with LV_ERR_INVALID_ARG while any handle still
+ * owns device memory (memory must return to the allocator it came from).
+ * Call it while no library work is in flight. */
+typedef void* (*lv_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*lv_free_fn)(void* ptr, size_t bytes, void* stream, void* ctx);
+lv_status lv_set_allocator(lv_alloc_fn alloc, lv_free_fn free, void* ctx);
+/* Frees the scratch the library caches for `stream` (all_streams != 0: for
+ * every stream, and the buffers kept from destroyed scenes); the scratch is
+ * allocated again by the next call that needs it.  No library work may be in
+ * flight on those streams. */
+lv_status lv_release_scratch(void* stream, int32_t all_streams);
+/* Device bytes the library holds (handles and cached scratch) and the
+ * number of its live device allocations. */
+lv_status lv_memory_stats(int64_t* bytes, int64_t* allocations);
+
 /* Library version string. */
 const char* lv_version(void);
 
 /* ---------------------------------------------------------------- scenes -- */
+/* Blending constants of a scene (Sec. 3.1, Eq. 1, with the rasteriser
+ * conventions the paper relies on): alpha clamp, skip threshold,
+ * transmittance stop, 2D dilation (px^2) and tile edge (px).  opts = NULL
+ * means the defaults 0.99f, 1/255.f, 1e-4f, 0.3f, 16, which are also the
+ * only values this build runs: others give LV_ERR_UNSUPPORTED (the kernels
+ * and their exact FP32 decision sequence are compiled for them). */
+typedef struct lv_scene_opts {
+    float alpha_max, alpha_min, t_eps, dilation;
+    int32_t tile;
+} lv_scene_opts;
+
 /* Make a scene resident on the current device (Sec. 3.1 scene
  * representation).  means [n][3], scales [n][3], quats [n][4] (w,x,y,z),
  * opacity [n]: device FP32 arrays, read (not retained) by the call.  The
  * library derives the covariances R diag(s)^2 R^T and keeps its own copy
- * (48 bytes per Gaussian).  n = 0 is valid.  Errors: LV_ERR_INVALID_ARG
- * (null pointers with n > 0, n >= 2^31), LV_ERR_OUT_OF_MEMORY. */
+ * (48 bytes per Gaussian).  n = 0 is valid.  opts: see lv_scene_opts.
+ * Errors: LV_ERR_INVALID_ARG (null pointers with n > 0, n >= 2^31),
+ * LV_ERR_UNSUPPORTED (non-default opts), LV_ERR_OUT_OF_MEMORY. */
 lv_status lv_scene_create(const float* means, const float* scales, const float* quats,
-                          const float* opacity, int64_t n, void* stream, lv_scene** out);
+                          const float* opacity, int64_t n, const lv_scene_opts* opts, void* stream,
+                          lv_scene** out);
 lv_status lv_scene_destroy(lv_scene* scene);
 int64_t lv_scene_size(const lv_scene* scene);
 
@@ -115,9 +158,13 @@ int64_t lv_scene_size(const lv_scene* scene);
  *   out_wsum  device FP32 [n]: beta_i = sum over views and pixels of w_i
  *             (nullable).
  * D in [1, 4096]; m >= 0 (m = 0 writes zeros).  Views are processed in
- * chunks (one host synchronisation per chunk); scratch is allocated by the
- * library and cached per (device, stream) for the life of the process.
- * Errors: LV_ERR_INVALID_ARG (bad sizes, null maps, reserved != 0),
+ * chunks (one host synchronisation per chunk) bounded by a scratch budget
+ * (a sixteenth of the device memory, clamped to [4, 16] GiB) for the
+ * per-(view, Gaussian) items and the same for the (tile, Gaussian) pairs; a
+ * chunk whose pairs exceed that (or 2^31) is split and built again.  Scratch
+ * is cached per (device, stream) until lv_release_scratch.  Errors:
+ * LV_ERR_INVALID_ARG (bad sizes, null maps, reserved != 0),
+ * LV_ERR_UNSUPPORTED (one view alone has 2^31 pairs or more),
  * LV_ERR_OUT_OF_MEMORY, LV_ERR_DEVICE. */
 lv_status lv_uplift(lv_scene* scene, const lv_camera* cams, int32_t m, const void* const* maps,
                     lv_dtype dtype, const float* scales, int32_t D, float* out_feat,
@@ -304,29 +351,38 @@ lv_status lv_render(lv_scene* scene, const lv_camera* cams, int32_t m, const flo
                     float* const* outs, float* const* alphas, void* stream);
 
 /* -------------------------------------------------------------- serving -- */
-/* A request server for uplift (Eq. 3 / Eq. 5) over resident scenes.  Requests
- * are admitted first come, first served while the memory they need (the
- * accumulators, n (D + 2) x 4 bytes) fits in hbm_budget; a request larger
- * than the budget is refused.  Each of `workers` threads runs one pass at a
- * time on its own HIP stream, so passes overlap on the device; a free worker
- * takes the oldest admitted request and merges into the same pass the other
- * admitted requests on the same scene with the same storage dtype (at most
- * max_sets requests and max_channels channels): one structure build and one
- * blend walk over the union of their views, each request adding only its own
- * views.  FP8 requests are not merged (their scales are per view).  Memory of
- * finished passes returns to the budget at once, admitting waiting requests
- * while other passes run.  Each result equals lv_uplift of that request alone
- * (within FP32 accumulation order). */
+/* A request server for uplift (Eq. 3 / Eq. 5) over resident scenes.  Of
+ * hbm_budget, workers x scratch_bytes are set aside for the workers' scratch
+ * (structure builds and pair buffers, whose chunks are sized to fit it);
+ * requests are admitted first come, first served while the memory they need
+ * (their accumulators, n (D + 2) x 4 bytes) fits in the rest; a request
+ * larger than the rest is refused.  Each of `workers` threads runs one pass
+ * at a time on its own HIP stream, so passes overlap on the device; a free
+ * worker takes the oldest admitted request and merges into the same pass the
+ * other admitted requests on the same scene with the same storage dtype (at
+ * most max_sets requests and max_channels channels): one structure build and
+ * one blend walk over the union of their views, each request adding only its
+ * own views (FP8 requests with their scales rearranged to the union's
+ * views).  If a merged pass fails, each of its requests runs again alone, so
+ * a request's status is its own.  Memory of finished passes returns to the
+ * budget at once, admitting waiting requests while other passes run.  Each
+ * result equals lv_uplift of that request alone (within FP32 accumulation
+ * order).  A worker's scratch is freed when the server is destroyed. */
 typedef struct lv_server lv_server;
 typedef struct lv_server_opts {
     int64_t hbm_budget;     /* bytes; <= 0: half of the free device memory */
     int32_t workers;        /* passes in flight, 1..8 (0: 2) */
     int32_t max_sets;       /* requests per pass, 1..8 (0: 8) */
     int32_t max_channels;   /* channels per pass (0: 1024) */
+    int32_t reserved;       /* must be 0 */
+    int64_t scratch_bytes;  /* per worker; <= 0: 4 GiB */
 } lv_server_opts;
-/* One request: as lv_uplift, plus the pixel stride of its maps (0 = D) and a
- * caller tag.  cams and the maps table are copied at submission; the scene,
- * the maps, scales and outputs must stay valid until the request completes. */
+/* One request: as lv_uplift, plus the pixel stride of its maps (0 = D), a
+ * caller tag and the stream that produces its inputs: the pass waits for the
+ * work enqueued on `stream` before the submission (an event recorded at
+ * submission; NULL: the null stream).  cams and the maps table are copied at
+ * submission; the scene, the maps, scales and outputs must stay valid until
+ * the request completes. */
 typedef struct lv_request {
     lv_scene* scene;
     const lv_camera* cams;
@@ -339,6 +395,7 @@ typedef struct lv_request {
     float* out_feat;
     float* out_wsum;
     uint64_t tag;
+    void* stream;
 } lv_request;
 /* A finished request: status, the number of requests in its pass, and times
  * in ns since the server was created (submission, start and end of its
@@ -349,8 +406,12 @@ typedef struct lv_completion {
     int32_t batch_size;
     int64_t t_submit, t_start, t_end;
 } lv_completion;
+/* peak_bytes: the most request memory admitted at once (<= budget less the
+ * workers' scratch); peak_device_bytes: the largest device memory in use
+ * (hipMemGetInfo, sampled at every pass's start and end) above what was in
+ * use when the server was created. */
 typedef struct lv_server_stats {
-    int64_t submitted, completed, passes, peak_bytes, budget;
+    int64_t submitted, completed, passes, peak_bytes, budget, cancelled, peak_device_bytes;
 } lv_server_stats;
 lv_status lv_server_create(const lv_server_opts* opts, lv_server** out);
 /* Non-blocking.  LV_ERR_INVALID_ARG for a malformed request,
@@ -360,6 +421,11 @@ lv_status lv_server_submit(lv_server* srv, const lv_request* req);
 lv_status lv_server_poll(lv_server* srv, lv_completion* out, int32_t cap, int32_t* n);
 /* Blocks until every submitted request has completed. */
 lv_status lv_server_drain(lv_server* srv);
+/* Cancels the request with this tag if it has not started: it completes at
+ * once with status LV_ERR_CANCELLED and its memory returns to the budget.
+ * LV_ERR_INVALID_ARG if no waiting request has the tag (unknown, running or
+ * finished). */
+lv_status lv_server_cancel(lv_server* srv, uint64_t tag);
 lv_status lv_server_stats_get(lv_server* srv, lv_server_stats* out);
 /* Drains, stops the workers and frees the server. */
 lv_status lv_server_destroy(lv_server* srv);

@@ -13,6 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblv.so")
 
 LV_F32, LV_BF16, LV_FP8_E4M3 = 0, 1, 2
+LV_ERR_CANCELLED = 5
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 LV_ACCUM_COUNTS = 1
 LV_GRAPH_SPATIAL_COSINE, LV_GRAPH_FEATURE_RBF = 0, 1
 _DTYPES = {"f32": LV_F32, "bf16": LV_BF16, "fp8": LV_FP8_E4M3}
@@ -45,16 +48,22 @@ class lv_graph_opts(ctypes.Structure):
                 ("binarize", ctypes.c_float)]
 
 
+class lv_scene_opts(ctypes.Structure):
+    _fields_ = [("alpha_max", ctypes.c_float), ("alpha_min", ctypes.c_float), ("t_eps", ctypes.c_float),
+                ("dilation", ctypes.c_float), ("tile", ctypes.c_int32)]
+
+
 class lv_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_int64), ("workers", ctypes.c_int32),
-                ("max_sets", ctypes.c_int32), ("max_channels", ctypes.c_int32)]
+                ("max_sets", ctypes.c_int32), ("max_channels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("scratch_bytes", ctypes.c_int64)]
 
 
 class lv_request(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_void_p), ("cams", ctypes.c_void_p), ("m", ctypes.c_int32),
                 ("maps", ctypes.c_void_p), ("stride", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("scales", ctypes.c_void_p), ("D", ctypes.c_int32), ("out_feat", ctypes.c_void_p),
-                ("out_wsum", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+                ("out_wsum", ctypes.c_void_p), ("tag", ctypes.c_uint64), ("stream", ctypes.c_void_p)]
 
 
 class lv_completion(ctypes.Structure):
@@ -64,7 +73,8 @@ class lv_completion(ctypes.Structure):
 
 class lv_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
-                ("passes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("budget", ctypes.c_int64)]
+                ("passes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("budget", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("peak_device_bytes", ctypes.c_int64)]
 
 
 class lv_uplift_set(ctypes.Structure):
@@ -94,7 +104,7 @@ def lib():
         sig = {
             "lv_last_error": ([], ctypes.c_char_p),
             "lv_version": ([], ctypes.c_char_p),
-            "lv_scene_create": ([P, P, P, P, i64, P, ctypes.POINTER(P)], i32),
+            "lv_scene_create": ([P, P, P, P, i64, ctypes.POINTER(lv_scene_opts), P, ctypes.POINTER(P)], i32),
             "lv_scene_destroy": ([P], i32),
             "lv_scene_size": ([P], i64),
             "lv_uplift": ([P, P, i32, P, i32, P, i32, P, P, P], i32),
@@ -127,6 +137,10 @@ def lib():
             "lv_server_drain": ([P], i32),
             "lv_server_stats_get": ([P, ctypes.POINTER(lv_server_stats)], i32),
             "lv_server_destroy": ([P], i32),
+            "lv_server_cancel": ([P, ctypes.c_uint64], i32),
+            "lv_set_allocator": ([ALLOC_FN, FREE_FN, P], i32),
+            "lv_release_scratch": ([P, i32], i32),
+            "lv_memory_stats": ([ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -144,7 +158,8 @@ def exported_symbols():
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
             "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",
             "lv_server_drain", "lv_server_stats_get", "lv_server_destroy", "lv_accum_finalize_count",
-            "lv_prune_by_weight", "lv_graph_build_knn", "lv_graph_csr", "lv_anchor_init", "lv_reach_unary"]
+            "lv_prune_by_weight", "lv_graph_build_knn", "lv_graph_csr", "lv_anchor_init", "lv_reach_unary",
+            "lv_server_cancel", "lv_set_allocator", "lv_release_scratch", "lv_memory_stats"]
 
 
 def _check(status):
@@ -262,15 +277,30 @@ def _map_table(maps, dtype):
     return tab
 
 
+# lv_scene_opts defaults: the FP32 literals 0.99f, 1/255.f, 1e-4f, 0.3f and 16
+SCENE_DEFAULTS = (float(np.float32(0.99)), float(np.float32(1.0) / np.float32(255.0)),
+                  float(np.float32(1e-4)), float(np.float32(0.3)), 16)
+
+
 class Scene:
     """lv_scene: Gaussians resident on the GPU (means, scales, quats, opacity)."""
 
-    def __init__(self, means, scales, quats, opacity):
+    def __init__(self, means, scales, quats, opacity, opts=None):
+        """opts: None or a dict of lv_scene_opts fields (alpha_max, alpha_min,
+        t_eps, dilation, tile)."""
         n = means.shape[0]
         _dev_f32(means, (n, 3)); _dev_f32(scales, (n, 3)); _dev_f32(quats, (n, 4)); _dev_f32(opacity, (n,))
         h = ctypes.c_void_p()
+        o = None
+        if opts is not None:
+            o = lv_scene_opts(*[opts.get(k, d) for k, d in (("alpha_max", SCENE_DEFAULTS[0]),
+                                                               ("alpha_min", SCENE_DEFAULTS[1]),
+                                                               ("t_eps", SCENE_DEFAULTS[2]),
+                                                               ("dilation", SCENE_DEFAULTS[3]),
+                                                               ("tile", SCENE_DEFAULTS[4]))])
         _check(lib().lv_scene_create(_ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), n,
-                                     _stream(), ctypes.byref(h)))
+                                     ctypes.byref(o) if o is not None else None, _stream(),
+                                     ctypes.byref(h)))
         self.handle, self.n = h, n
 
     @classmethod
@@ -593,8 +623,8 @@ class Server:
     """lv_server: uplift requests admitted by memory budget, merged per scene
     into wide passes, several passes in flight (one HIP stream per worker)."""
 
-    def __init__(self, budget=0, workers=2, max_sets=8, max_channels=1024):
-        o = lv_server_opts(int(budget), workers, max_sets, max_channels)
+    def __init__(self, budget=0, workers=2, max_sets=8, max_channels=1024, scratch=0):
+        o = lv_server_opts(int(budget), workers, max_sets, max_channels, 0, int(scratch))
         h = ctypes.c_void_p()
         _check(lib().lv_server_create(ctypes.byref(o), ctypes.byref(h)))
         self.handle = h
@@ -620,7 +650,7 @@ class Server:
         q = lv_request(scene.handle.value, ctypes.cast(ca, ctypes.c_void_p), len(cams),
                        ctypes.cast(tab, ctypes.c_void_p), stride, dt,
                        None if scales is None else scales.data_ptr(), D, out.data_ptr(),
-                       wsum.data_ptr(), tag)
+                       wsum.data_ptr(), tag, _stream().value)
         _check(lib().lv_server_submit(self.handle, ctypes.byref(q)))
         self._live[tag] = (scene, list(maps), scales, out, wsum)
         return tag
@@ -643,6 +673,12 @@ class Server:
     def drain(self):
         _check(lib().lv_server_drain(self.handle))
 
+    def cancel(self, tag):
+        """Cancel a waiting request: True if it was cancelled (it completes
+        with status LV_ERR_CANCELLED), False if it is running or finished."""
+        st = lib().lv_server_cancel(self.handle, tag)
+        return st == 0
+
     def stats(self):
         st = lv_server_stats()
         _check(lib().lv_server_stats_get(self.handle, ctypes.byref(st)))
@@ -654,3 +690,50 @@ class Server:
             self.handle = None
 
     __del__ = close
+
+
+# ------------------------------------------------------------ device memory
+_allocator = None  # keeps the registered ctypes callbacks alive
+
+
+def set_allocator(alloc=None, free=None):
+    """Route every device allocation of the library through Python callables
+    alloc(bytes, stream) -> int pointer and free(ptr, bytes, stream); None,
+    None restores hipMalloc / hipFree.  The library must hold no memory."""
+    global _allocator
+    if alloc is None:
+        _check(lib().lv_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator = None
+        return
+    a = ALLOC_FN(lambda nbytes, stream, ctx: alloc(int(nbytes), stream) or None)
+    f = FREE_FN(lambda ptr, nbytes, stream, ctx: free(ptr, int(nbytes), stream))
+    _check(lib().lv_set_allocator(a, f, None))
+    _allocator = (a, f)
+
+
+def use_torch_allocator():
+    """Route the library's device allocations through torch's caching
+    allocator (on the stream each allocation is made for)."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(max(nbytes, 1), torch.cuda.current_device(),
+                                                  stream or 0)
+
+    def free(ptr, nbytes, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    set_allocator(alloc, free)
+
+
+def release_scratch(all_streams=True):
+    """Free the scratch the library caches (this stream's, or every stream's
+    and the buffers of destroyed scenes)."""
+    _check(lib().lv_release_scratch(_stream() if not all_streams else None, 1 if all_streams else 0))
+
+
+def memory_stats():
+    """-> (bytes, allocations) of device memory the library holds."""
+    b, n = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().lv_memory_stats(ctypes.byref(b), ctypes.byref(n)))
+    return b.value, n.value

@@ -9,6 +9,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <climits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -42,6 +44,14 @@ lv_status fail(lv_status st, const char* fmt, ...) {
     }                                                                                      \
   } while (0)
 
+// The registered device allocator (lv_set_allocator) and the library's own
+// account of the device memory it holds.
+std::mutex g_alloc_mu;
+lv_alloc_fn g_alloc_fn = nullptr;
+lv_free_fn g_free_fn = nullptr;
+void* g_alloc_ctx = nullptr;
+std::atomic<int64_t> g_dev_bytes{0}, g_dev_allocs{0};
+
 // Grow-only device buffer.
 struct Buf {
   void* p = nullptr;
@@ -51,13 +61,12 @@ struct Buf {
     if (p) {
       hipError_t e = hipStreamSynchronize(s);
       if (e != hipSuccess) return e;
-      e = hipFree(p);
-      if (e != hipSuccess) return e;
+      lv::dev_free(p, cap, s);
       p = nullptr;
       cap = 0;
     }
     size_t want = bytes + bytes / 8 + 256;
-    hipError_t e = hipMalloc(&p, want);
+    hipError_t e = lv::dev_alloc(&p, want, s);
     if (e != hipSuccess) {
       p = nullptr;
       return e;
@@ -65,8 +74,8 @@ struct Buf {
     cap = want;
     return hipSuccess;
   }
-  void release() {
-    if (p) (void)hipFree(p);
+  void release(hipStream_t s = nullptr) {
+    if (p) lv::dev_free(p, cap, s);
     p = nullptr;
     cap = 0;
   }
@@ -99,6 +108,7 @@ struct HostBuf {
 // anyway).
 struct Workspace {
   std::mutex mu;
+  int64_t chunk_bytes = 0;  // scratch budget of a structure build (0: chunk_budget_bytes())
   std::mutex accmu;  // held by a one-call uplift while it uses accU/accB
   Buf accUs[kMaxSets], accBs[kMaxSets];
   const uint32_t* dkey = nullptr;  // depth-sorted keys / ids of the last structure build
@@ -121,6 +131,24 @@ Workspace* workspace_for(hipStream_t s) {
   return w;
 }
 
+void workspace_free(Workspace* w, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(w->mu);
+    for (int k = 0; k < kMaxSets; k++) {
+      w->accUs[k].release(s);
+      w->accBs[k].release(s);
+    }
+    Buf* bufs[] = {&w->rec, &w->key0, &w->val0, &w->key1, &w->val1, &w->rect, &w->scnt,
+                   &w->srect, &w->off, &w->scan_tmp, &w->hist, &w->seg, &w->pseg, &w->total,
+                   &w->pk0, &w->pv0, &w->pk1, &w->pv1, &w->hist2, &w->ranges, &w->cams,
+                   &w->geom, &w->maps, &w->cls};
+    for (Buf* b : bufs) b->release(s);
+    w->up.release();
+    w->down.release();
+  }
+  delete w;
+}
+
 // Blend-kernel timing (HIP events around every blend launch) for benchmarks.
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -139,13 +167,21 @@ constexpr int64_t kItemBytes = sizeof(Rec) + 4 * 4 + 2 * 8 + 4 + 4;
 #endif
 constexpr int kDepthPassBits = LV_DEPTH_PASS_BITS;
 
-int64_t chunk_budget_bytes() {
+// Per-(view, Gaussian) scratch of one structure build: LV_CHUNK_BYTES, else a
+// sixteenth of the device's memory clamped to [4, 16] GiB (16 GiB on a
+// 288 GB MI355X: a million Gaussians over 100 views in one chunk).
+int64_t chunk_budget_bytes(const Workspace* ws = nullptr) {
+  if (ws && ws->chunk_bytes > 0) return ws->chunk_bytes;
   const char* e = getenv("LV_CHUNK_BYTES");
   if (e) {
     long long v = atoll(e);
     if (v > 0) return v;
   }
-  return (int64_t)4 << 30;
+  size_t free_b = 0, total_b = 0;
+  int64_t b = (int64_t)4 << 30;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+    b = std::max<int64_t>(b, std::min<int64_t>((int64_t)16 << 30, (int64_t)(total_b / 16)));
+  return b;
 }
 
 }  // namespace
@@ -202,10 +238,15 @@ int ceil_log2(int64_t x) {
 
 // Structure of one chunk of views: everything up to the tile ranges.  On
 // return, the sorted pair values (Gaussian ids) are in *ids, the ranges in
-// ws.ranges with row stride *stride, and the pair count in *P.
+// ws.ranges with row stride *stride, and the pair count in *P.  If the chunk
+// has more than one view and its pairs would reach 2^31 or need more than
+// pair_budget bytes of pair buffers, *split is set and nothing past the pair
+// count is built (the caller retries with fewer views).
 lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, int mv,
                           hipStream_t s, const uint32_t** ids, int* stride,
-                          int64_t* P, int64_t* nvis, int* max_tiles_out) {
+                          int64_t* P, int64_t* nvis, int* max_tiles_out,
+                          int64_t pair_budget = INT64_MAX, bool* split = nullptr) {
+  if (split) *split = false;
   const int64_t n = sc->n;
   const int64_t items = n * (int64_t)mv;
   std::vector<ViewGeom> geom(mv);
@@ -278,8 +319,13 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   const unsigned long long* tot64 = reinterpret_cast<const unsigned long long*>(down);
   uint64_t total = tot64[0];
   *nvis = (int64_t)tot64[1];
+  if (split && mv > 1 && (total >= 0x80000000ull || (int64_t)total * 16 > pair_budget)) {
+    *split = true;
+    *P = (int64_t)total;
+    return LV_OK;
+  }
   if (total >= 0x80000000ull)
-    return fail(LV_ERR_UNSUPPORTED, "%llu (tile, Gaussian) pairs in one chunk (limit 2^31)",
+    return fail(LV_ERR_UNSUPPORTED, "%llu (tile, Gaussian) pairs in one view (limit 2^31)",
                 (unsigned long long)total);
   int64_t max_len = 0;
   for (int v = 0; v < mv; v++) max_len = std::max<int64_t>(max_len, down[4 + v]);
@@ -325,9 +371,121 @@ lv_status check_maps(const void* const* maps, int32_t m, lv_dtype dtype, const f
 
 }  // namespace
 
+namespace lv {
+
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s, bool temp) {
+  lv_alloc_fn fn;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    fn = g_alloc_fn;
+    ctx = g_alloc_ctx;
+  }
+  hipError_t e;
+  if (fn) {
+    *p = fn(bytes, s, ctx);
+    e = *p ? hipSuccess : hipErrorOutOfMemory;
+  } else {
+    e = temp ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+    if (e != hipSuccess) *p = nullptr;
+  }
+  if (e == hipSuccess) {
+    g_dev_bytes += (int64_t)bytes;
+    g_dev_allocs += 1;
+  }
+  return e;
+}
+
+void dev_free(void* p, size_t bytes, hipStream_t s, bool temp) {
+  if (!p) return;
+  lv_free_fn fn;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    fn = g_free_fn;
+    ctx = g_alloc_ctx;
+  }
+  if (fn)
+    fn(p, bytes, s, ctx);
+  else if (temp)
+    (void)hipFreeAsync(p, s);
+  else
+    (void)hipFree(p);
+  g_dev_bytes -= (int64_t)bytes;
+  g_dev_allocs -= 1;
+}
+
+// Frees the workspace of stream s (the caller guarantees it is idle).
+void release_workspace(hipStream_t s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  Workspace* w = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.find(std::make_pair(dev, s));
+    if (it == g_pool.end()) return;
+    w = it->second;
+    g_pool.erase(it);
+  }
+  (void)hipStreamSynchronize(s);
+  workspace_free(w, s);
+}
+
+// Caps the structure-build scratch of stream s's workspace (items and pairs
+// each at most `bytes`).
+void limit_workspace(hipStream_t s, int64_t bytes) {
+  Workspace* w = workspace_for(s);
+  std::lock_guard<std::mutex> lk(w->mu);
+  w->chunk_bytes = bytes;
+}
+
+}  // namespace lv
+
+namespace {
+void scene_cache_clear();
+}
+
 extern "C" {
 
 const char* lv_last_error(void) { return g_err.c_str(); }
+
+lv_status lv_release_scratch(void* stream, int32_t all_streams) {
+  if (!all_streams) {
+    lv::release_workspace(static_cast<hipStream_t>(stream));
+    return LV_OK;
+  }
+  std::vector<Workspace*> ws;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto& e : g_pool) ws.push_back(e.second);
+    g_pool.clear();
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  for (Workspace* w : ws) workspace_free(w, nullptr);
+  scene_cache_clear();
+  return LV_OK;
+}
+
+lv_status lv_set_allocator(lv_alloc_fn alloc, lv_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(LV_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+  lv_status st = lv_release_scratch(nullptr, 1);
+  if (st != LV_OK) return st;
+  if (g_dev_allocs.load() != 0)
+    return fail(LV_ERR_INVALID_ARG, "%lld device allocations of live handles are outstanding",
+                (long long)g_dev_allocs.load());
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc_fn = alloc;
+  g_free_fn = free_fn;
+  g_alloc_ctx = ctx;
+  return LV_OK;
+}
+
+lv_status lv_memory_stats(int64_t* bytes, int64_t* allocations) {
+  if (bytes) *bytes = g_dev_bytes.load();
+  if (allocations) *allocations = g_dev_allocs.load();
+  return LV_OK;
+}
 
 const char* lv_version(void) { return "lv 0.1 gfx950"; }
 
@@ -361,6 +519,12 @@ hipError_t scene_buf(Buf& out, int dev, size_t bytes, hipStream_t s) {
   return out.ensure(bytes, s);
 }
 
+void scene_cache_clear() {
+  std::lock_guard<std::mutex> lk(g_scene_cache_mu);
+  for (auto& e : g_scene_cache) e.second.release();
+  g_scene_cache.clear();
+}
+
 // After the device has finished with the buffer (the caller synchronised).
 void scene_buf_release(int dev, Buf& b) {
   if (!b.p) return;
@@ -383,9 +547,19 @@ void scene_buf_release(int dev, Buf& b) {
 }  // namespace
 
 lv_status lv_scene_create(const float* means, const float* scales, const float* quats,
-                          const float* opacity, int64_t n, void* stream, lv_scene** out) {
+                          const float* opacity, int64_t n, const lv_scene_opts* opts, void* stream,
+                          lv_scene** out) {
   if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
+  if (opts) {
+    // the kernels are compiled for the default constants (FP32 literals)
+    const bool dflt = opts->alpha_max == kAlphaMax && opts->alpha_min == kAlphaMin &&
+                      opts->t_eps == kTEps && opts->dilation == kDilate && opts->tile == kTile;
+    if (!dflt)
+      return fail(LV_ERR_UNSUPPORTED,
+                  "scene constants other than alpha_max 0.99, alpha_min 1/255, t_eps 1e-4, "
+                  "dilation 0.3, tile 16 are not supported by this build");
+  }
   if (n < 0 || n >= ((int64_t)1 << 31)) return fail(LV_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if (n > 0 && (!means || !scales || !quats || !opacity))
     return fail(LV_ERR_INVALID_ARG, "null scene array");
@@ -582,16 +756,23 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
   if (nslots) HIP_TRY(ws.cls.ensure((size_t)nslots * n * 12, s));
-  int64_t per_view = n * kItemBytes;
-  int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
+  const int64_t per_view = n * kItemBytes;
+  const int64_t budget = chunk_budget_bytes(&ws);
+  int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, budget / per_view));
   mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
-  for (int v0 = 0; v0 < m; v0 += (int)mc) {
+  for (int v0 = 0; v0 < m;) {
     int mv = (int)std::min<int64_t>(mc, m - v0);
     const uint32_t* ids = nullptr;
     int stride = 0, max_tiles = 0;
     int64_t P = 0, nvis = 0;
-    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &stride, &P, &nvis, &max_tiles);
+    bool split = false;
+    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &stride, &P, &nvis, &max_tiles, budget, &split);
     if (st != LV_OK) return st;
+    if (split) {  // too many pairs for the chunk: fewer views per chunk, same views again
+      const double fit = (double)std::min<int64_t>(budget / 16, 0x7FFFFFFF) / (double)P;
+      mc = std::max<int64_t>(1, std::min<int64_t>(mv - 1, (int64_t)(mv * fit * 0.9)));
+      continue;
+    }
     for (int k = 0; k < nsets; k++) {
       fsets[k].acc->views += mv;
       fsets[k].acc->pairs += P;
@@ -670,7 +851,8 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
       const char* c = ws.cls.as<char>() + (size_t)slot[k] * n * 12;
       HIP_TRY(launch_class_add(reinterpret_cast<const beta_t*>(c), sd[k].counts ? reinterpret_cast<const uint32_t*>(c + (size_t)n * 8) : nullptr, dst, n, s));
     }
-    if (v0 + mc < m) HIP_TRY(hipStreamSynchronize(s));  // staging buffers are reused
+    v0 += mv;
+    if (v0 < m) HIP_TRY(hipStreamSynchronize(s));  // staging buffers are reused
   }
   return LV_OK;
 }
@@ -859,9 +1041,11 @@ lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype,
   if (dtype != LV_F32 && dtype != LV_BF16 && dtype != LV_FP8_E4M3)
     return fail(LV_ERR_INVALID_ARG, "unknown dtype");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  static thread_local Buf tmp;
-  if (dtype == LV_FP8_E4M3) HIP_TRY(tmp.ensure(4 * (size_t)D, s));
-  HIP_TRY(launch_encode(src, pixels, D, dtype, dst, scales, tmp.as<float>(), s));
+  void* tmp = nullptr;  // per-channel absmax (FP8), stream-ordered scratch
+  if (dtype == LV_FP8_E4M3) HIP_TRY(dev_alloc(&tmp, 4 * (size_t)D, s, true));
+  const hipError_t e = launch_encode(src, pixels, D, dtype, dst, scales, static_cast<float*>(tmp), s);
+  dev_free(tmp, 4 * (size_t)D, s, true);
+  HIP_TRY(e);
   return LV_OK;
 }
 
@@ -938,7 +1122,10 @@ lv_status lv_graph_build_knn(lv_scene* sc, const float* feats, int32_t D, int32_
   HIP_TRY(build_knn_graph(sc->p0.as<float4>(), n, feats, D, k, gw, s, &rp, &cl, &vl, &nnz));
   lv_graph* g = new (std::nothrow) lv_graph();
   if (!g) {
-    (void)hipFree(rp); (void)hipFree(cl); (void)hipFree(vl);
+    (void)hipStreamSynchronize(s);
+    dev_free(rp, 4 * (size_t)(n + 1), s);
+    dev_free(cl, 4 * (size_t)(nnz + 1), s);
+    dev_free(vl, 4 * (size_t)(nnz + 1), s);
     return fail(LV_ERR_OUT_OF_MEMORY, "host allocation");
   }
   g->n = n;
@@ -1054,16 +1241,23 @@ lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float*
   if (n == 0 || m == 0) return LV_OK;
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
-  int64_t per_view = n * kItemBytes;
-  int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, chunk_budget_bytes() / per_view));
+  const int64_t per_view = n * kItemBytes;
+  const int64_t budget = chunk_budget_bytes(&ws);
+  int64_t mc = std::max<int64_t>(1, std::min<int64_t>(m, budget / per_view));
   mc = std::min<int64_t>(mc, 1 << (31 - kViewShift));
-  for (int v0 = 0; v0 < m; v0 += (int)mc) {
+  for (int v0 = 0; v0 < m;) {
     const int mv = (int)std::min<int64_t>(mc, m - v0);
     const uint32_t* ids = nullptr;
     int stride = 0, max_tiles = 0;
     int64_t P = 0, nvis = 0;
-    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &stride, &P, &nvis, &max_tiles);
+    bool split = false;
+    st = build_structure(sc, ws, cams + v0, mv, s, &ids, &stride, &P, &nvis, &max_tiles, budget, &split);
     if (st != LV_OK) return st;
+    if (split) {  // too many pairs for the chunk: fewer views per chunk, same views again
+      const double fit = (double)std::min<int64_t>(budget / 16, 0x7FFFFFFF) / (double)P;
+      mc = std::max<int64_t>(1, std::min<int64_t>(mv - 1, (int64_t)(mv * fit * 0.9)));
+      continue;
+    }
     // output tables (ws.up is idle: build_structure synchronised the stream)
     const size_t bytes = 2 * sizeof(float*) * (size_t)mv;
     HIP_TRY(ws.maps.ensure(bytes, s));
@@ -1084,6 +1278,7 @@ lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float*
     ba.tiles_stride = stride;
     float* const* dtab = static_cast<float* const*>(ws.maps.p);
     HIP_TRY(launch_render(ba, mv, g, D, dtab, dtab + mv, s));
+    v0 += mv;
   }
   return LV_OK;
 }
@@ -1159,7 +1354,14 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
 
 namespace lv {
 
-lv_status set_error(lv_status st, const char* msg) { return fail(st, "%s", msg); }
+lv_status set_error(lv_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return fail(st, "%s", buf);
+}
 
 // One pass of the server: per-set accumulators from the stream-ordered
 // allocator (no device-wide synchronisation), lv_uplift_accumulate_sets over
@@ -1176,10 +1378,10 @@ lv_status run_batch(lv_scene* sc, const lv_camera* cams, int32_t m, const BatchS
   for (int k = 0; k < nsets; k++) {
     void* U = nullptr;
     void* B = nullptr;
-    hipError_t e = hipMallocAsync(&U, sizeof(float) * n1 * sets[k].D, s);
-    if (e == hipSuccess) e = hipMallocAsync(&B, sizeof(beta_t) * n1, s);
+    hipError_t e = dev_alloc(&U, sizeof(float) * n1 * sets[k].D, s, true);
+    if (e == hipSuccess) e = dev_alloc(&B, sizeof(beta_t) * n1, s, true);
     if (e != hipSuccess) {
-      if (U) (void)hipFreeAsync(U, s);
+      dev_free(U, sizeof(float) * n1 * sets[k].D, s, true);
       st = fail(LV_ERR_OUT_OF_MEMORY, "server accumulator: %s", hipGetErrorString(e));
       break;
     }
@@ -1199,8 +1401,8 @@ lv_status run_batch(lv_scene* sc, const lv_camera* cams, int32_t m, const BatchS
   for (int k = 0; k < nsets && st == LV_OK; k++)
     st = lv_accum_finalize(&acc[k], sets[k].out_feat, sets[k].out_wsum, nullptr, s);
   for (int k = 0; k < made; k++) {
-    (void)hipFreeAsync(acc[k].U.p, s);
-    (void)hipFreeAsync(acc[k].beta.p, s);
+    dev_free(acc[k].U.p, sizeof(float) * n1 * sets[k].D, s, true);
+    dev_free(acc[k].beta.p, sizeof(beta_t) * n1, s, true);
     acc[k].U.p = acc[k].beta.p = nullptr;
   }
   return st;

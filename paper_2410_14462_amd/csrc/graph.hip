@@ -578,7 +578,7 @@ hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats,
   const size_t o_ucol = take(4 * (size_t)ucap), o_uw = take(8 * (size_t)ucap);
   const size_t o_sseg = take(8), o_tot = take(16), o_stmp = take(4 * scan_tmp_size(n));
   char* base = nullptr;
-  hipError_t e = hipMallocAsync((void**)&base, off, s);
+  hipError_t e = dev_alloc((void**)&base, off, s, true);
   if (e != hipSuccess) return e;
   auto at = [&](size_t o) { return base + o; };
   float* part = (float*)at(o_part);
@@ -675,19 +675,20 @@ hipError_t build_knn_graph(const float4* centres, int64_t n, const float* feats,
     if ((e = hipMemcpyAsync(th, tot, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) break;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
     nnz = th[0];
-    if ((e = hipMalloc((void**)row_ptr, 4 * (size_t)(n + 1))) != hipSuccess) break;
-    if ((e = hipMalloc((void**)col, 4 * (size_t)(nnz + 1))) != hipSuccess) break;
-    if ((e = hipMalloc((void**)val, 4 * (size_t)(nnz + 1))) != hipSuccess) break;
+    if ((e = dev_alloc((void**)row_ptr, 4 * (size_t)(n + 1), s)) != hipSuccess) break;
+    if ((e = dev_alloc((void**)col, 4 * (size_t)(nnz + 1), s)) != hipSuccess) break;
+    if ((e = dev_alloc((void**)val, 4 * (size_t)(nnz + 1), s)) != hipSuccess) break;
     hipLaunchKernelGGL(csr_out_kernel, dim3(grid1(n)), dim3(256), 0, s, n, start, len, rp, ucol, uw, rsum,
                        *col, *val, *row_ptr, (uint64_t)nnz, !rbf);
     e = hipGetLastError();
   } while (false);
-  const hipError_t ef = hipFreeAsync(base, s);
-  if (e == hipSuccess) e = ef;
+  dev_free(base, off, s, true);
+  if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
-    if (*row_ptr) (void)hipFree(*row_ptr);
-    if (*col) (void)hipFree(*col);
-    if (*val) (void)hipFree(*val);
+    (void)hipStreamSynchronize(s);
+    dev_free(*row_ptr, 4 * (size_t)(n + 1), s);
+    dev_free(*col, 4 * (size_t)(nnz + 1), s);
+    dev_free(*val, 4 * (size_t)(nnz + 1), s);
     *row_ptr = nullptr;
     *col = nullptr;
     *val = nullptr;

@@ -109,6 +109,15 @@ __device__ __forceinline__ void beta_atomic_add(beta_t* p, float w) {
   gatomic_add(p, (beta_t)__double2ull_rn((double)w * kBetaUnit));
 }
 
+// ------------------------------------------------------------ device memory
+// Every device buffer of the library: the allocator registered with
+// lv_set_allocator, else hipMalloc / hipFree, or hipMallocAsync /
+// hipFreeAsync for temporary (stream-ordered) scratch.  dev_free releases
+// after the work enqueued on `s` (a registered allocator gets the stream;
+// hipFree itself waits for the device).
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s, bool temp = false);
+void dev_free(void* p, size_t bytes, hipStream_t s, bool temp = false);
+
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `s` and return hipGetLastError().
 hipError_t launch_scene_derive(const float* means, const float* scales, const float* quats,
@@ -174,7 +183,7 @@ hipError_t launch_ranges(const uint32_t* pair_key, int64_t P, int tiles_stride, 
                          hipStream_t s);
 
 constexpr int kMaxSets = 8;   // feature sets per blend launch
-constexpr int kMaxSegs = 4;   // set segments per channel group
+constexpr int kMaxSegs = 8;   // set segments per channel group (one per set at most)
 
 // One feature set of a blend launch (device array).
 struct SetDesc {
@@ -278,8 +287,9 @@ struct BatchSet {
 };
 lv_status run_batch(lv_scene* sc, const lv_camera* cams, int32_t m, const BatchSet* sets,
                     int nsets, lv_dtype dtype, hipStream_t s);
-// Records msg as the calling thread's lv_last_error and returns st.
-lv_status set_error(lv_status st, const char* msg);
+// Records the formatted message as the calling thread's lv_last_error and
+// returns st.
+lv_status set_error(lv_status st, const char* fmt, ...);
 
 hipError_t launch_diffuse(const int32_t* row_ptr, const int32_t* col, const void* val,
                           lv_dtype val_dtype, int64_t n, const void* g0, lv_dtype dtype, int D,

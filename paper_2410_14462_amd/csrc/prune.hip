@@ -94,7 +94,7 @@ hipError_t launch_prune(const float* wsum, int64_t n, int64_t k, uint8_t* keep, 
   // key/index pairs double buffered, one segment, histogram rows
   const size_t words = 4 * (size_t)n + 2 + sort_hist_size(1, n);
   void* mem = nullptr;
-  hipError_t e = hipMallocAsync(&mem, 4 * words, s);
+  hipError_t e = dev_alloc(&mem, 4 * words, s, true);
   if (e != hipSuccess) return e;
   uint32_t* k0 = static_cast<uint32_t*>(mem);
   uint32_t* v0 = k0 + n;
@@ -111,15 +111,15 @@ hipError_t launch_prune(const float* wsum, int64_t n, int64_t k, uint8_t* keep, 
                        second ? v1 : v0, k, keep);
     e = hipGetLastError();
   }
-  const hipError_t ef = hipFreeAsync(mem, s);
-  return e != hipSuccess ? e : ef;
+  dev_free(mem, 4 * words, s, true);
+  return e;
 }
 
 hipError_t launch_anchor_init(const float* g, int64_t n, float fraction, float* g0, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const size_t words = 4 * (size_t)n + 2 + 2 + sort_hist_size(1, n);
   void* mem = nullptr;
-  hipError_t e = hipMallocAsync(&mem, 4 * words, s);
+  hipError_t e = dev_alloc(&mem, 4 * words, s, true);
   if (e != hipSuccess) return e;
   uint32_t* k0 = static_cast<uint32_t*>(mem);
   uint32_t* v0 = k0 + n;
@@ -140,8 +140,8 @@ hipError_t launch_anchor_init(const float* g, int64_t n, float fraction, float* 
       e = hipGetLastError();
     }
   }
-  const hipError_t ef = hipFreeAsync(mem, s);
-  return e != hipSuccess ? e : ef;
+  dev_free(mem, 4 * words, s, true);
+  return e;
 }
 
 hipError_t launch_reach_unary(const float* gT, const float* unary, int64_t n, int D, float* h,

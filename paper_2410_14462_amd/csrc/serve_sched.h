@@ -15,6 +15,11 @@
 //   * A finished pass returns its requests' memory to the budget, which may
 //     admit more requests while other passes are still running: requests
 //     join as slots and memory free up (continuous batching across passes).
+//   * A waiting request (pending or admitted, not yet in a pass) can be
+//     cancelled; its memory returns to the budget.
+//   * A merged pass that fails with a request-level error runs each of its
+//     requests again alone (run_isolated), so that one malformed request
+//     does not fail the others.
 #pragma once
 
 #include <chrono>
@@ -80,6 +85,33 @@ class Scheduler {
     cv_.notify_all();
   }
 
+  // Removes the oldest waiting request (pending or admitted, not running)
+  // for which pred holds, moving it into *out; false if there is none.
+  template <typename Pred>
+  bool cancel(Pred pred, Req* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = admitted_.begin(); it != admitted_.end(); ++it) {
+      if (!pred(*it)) continue;
+      *out = std::move(*it);
+      admitted_.erase(it);
+      used_ -= out->bytes;
+      --outstanding_;
+      admit_locked();
+      cv_.notify_all();
+      return true;
+    }
+    for (auto it = pending_.begin(); it != pending_.end(); ++it) {
+      if (!pred(*it)) continue;
+      *out = std::move(*it);
+      pending_.erase(it);
+      --outstanding_;
+      admit_locked();  // a cancelled head may have been blocking the others
+      cv_.notify_all();
+      return true;
+    }
+    return false;
+  }
+
   // Blocks until every submitted request has completed.
   void drain() {
     std::unique_lock<std::mutex> lk(mu_);
@@ -121,5 +153,21 @@ class Scheduler {
   int running_ = 0;
   bool stop_ = false;
 };
+
+// Runs a pass over all n requests of a batch: run(indices) -> status (0 =
+// success).  If the merged pass fails with a status other than `fatal` (a
+// device fault, which taints the device for every request), each request
+// runs again alone, so that every request gets its own status.  Returns the
+// status of each request.
+template <typename Run>
+std::vector<int> run_isolated(size_t n, int fatal, Run run) {
+  std::vector<size_t> all(n);
+  for (size_t k = 0; k < n; k++) all[k] = k;
+  const int st = run(all);
+  std::vector<int> out(n, st);
+  if (st == 0 || n == 1 || st == fatal) return out;
+  for (size_t k = 0; k < n; k++) out[k] = run(std::vector<size_t>{k});
+  return out;
+}
 
 }  // namespace lv

@@ -1,6 +1,9 @@
 // Host test of the uplift server's scheduler policy (admission by budget,
-// first come first served, same-key merging, continuous admission), with a
-// stand-in executor instead of the GPU.  Built and run by test_serve_sched.py.
+// first come first served, same-key merging, continuous admission,
+// cancellation of waiting requests, failure isolation of merged passes),
+// with a stand-in executor instead of the GPU.  Built and run by
+// test_serve_sched.py, also under ThreadSanitizer.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -67,6 +70,43 @@ int main() {
     CHECK(s.next_batch(b) && ids(b) == std::vector<int>({0, 2}));
     CHECK(s.next_batch(b) && ids(b) == std::vector<int>({1}));
   }
+  {  // cancellation: a pending request (blocking the queue) and an admitted one
+    lv::Scheduler<Req> s(100, 8, 1024);
+    CHECK(s.submit({60, 1, 1, 0}));
+    CHECK(s.submit({50, 1, 2, 1}));   // pending: 60 + 50 > 100
+    CHECK(s.submit({30, 1, 3, 2}));   // pending behind request 1
+    Req out{};
+    CHECK(s.cancel([](const Req& r) { return r.id == 1; }, &out) && out.id == 1);
+    CHECK(s.used() == 90);            // request 2 admitted once 1 no longer blocks it
+    CHECK(s.cancel([](const Req& r) { return r.id == 2; }, &out) && out.id == 2);
+    CHECK(s.used() == 60);            // an admitted request's memory returns
+    CHECK(!s.cancel([](const Req& r) { return r.id == 7; }, &out));
+    CHECK(s.next_batch(b) && ids(b) == std::vector<int>({0}));
+    CHECK(!s.cancel([](const Req& r) { return r.id == 0; }, &out));  // running
+    s.complete(b);
+    s.drain();                        // cancelled requests no longer count as outstanding
+    CHECK(s.used() == 0);
+  }
+  {  // failure isolation: a failing merged pass runs each request alone
+    std::vector<std::vector<size_t>> calls;
+    auto run = [&](const std::vector<size_t>& idx) {
+      calls.push_back(idx);
+      for (size_t k : idx)
+        if (k == 1) return 2;         // request 1 is malformed
+      return 0;
+    };
+    std::vector<int> st = lv::run_isolated(3, 3, run);
+    CHECK(st == std::vector<int>({0, 2, 0}));
+    CHECK(calls.size() == 4 && calls[0].size() == 3);
+    calls.clear();
+    auto fatal = [&](const std::vector<size_t>& idx) {
+      calls.push_back(idx);
+      return 3;                       // a device fault: no reruns
+    };
+    CHECK(lv::run_isolated(3, 3, fatal) == std::vector<int>({3, 3, 3}) && calls.size() == 1);
+    calls.clear();
+    CHECK(lv::run_isolated(2, 3, run) == std::vector<int>({0, 2}) && calls.size() == 3);
+  }
   {  // concurrent workers, random arrivals: budget never exceeded, every
      // request served exactly once, batches homogeneous and within limits
     const int64_t budget = 1000;
@@ -105,21 +145,29 @@ int main() {
       });
     }
     std::mt19937 rng(42);
+    std::vector<int> cancelled;
     for (int i = 0; i < nreq; i++) {
       Req r{(int64_t)(1 + rng() % 400), (int32_t)(1 + rng() % 128), (uint64_t)(rng() % 3), i};
       CHECK(s.submit(r));
       if (rng() % 4 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 100));
+      if (i > 10 && rng() % 8 == 0) {  // cancel an earlier request if it is still waiting
+        const int victim = i - 1 - (int)(rng() % 10);
+        Req out{};
+        if (s.cancel([victim](const Req& q) { return q.id == victim; }, &out)) cancelled.push_back(victim);
+      }
     }
     s.drain();
     CHECK(s.used() == 0);
     s.shutdown();
     for (auto& t : ws) t.join();
-    for (int i = 0; i < nreq; i++) CHECK(served[i] == 1);
+    for (int v : cancelled) CHECK(served[v] == 0);
+    for (int i = 0; i < nreq; i++)
+      CHECK(served[i] == (std::find(cancelled.begin(), cancelled.end(), i) == cancelled.end() ? 1 : 0));
     CHECK(max_live <= budget);
     CHECK(s.peak_used() <= budget);
     CHECK(merged > 0);
-    std::printf("ok passes=%d merged=%d peak=%lld\n", passes.load(), merged.load(),
-                (long long)s.peak_used());
+    std::printf("ok passes=%d merged=%d cancelled=%d peak=%lld\n", passes.load(), merged.load(),
+                (int)cancelled.size(), (long long)s.peak_used());
   }
   return 0;
 }

@@ -42,9 +42,21 @@ def test_camera_layout_matches_header(lvlib):
 def test_invalid_arguments_fail_without_touching_the_gpu(lvlib):
     L = lvlib.lib()
     out = ctypes.c_void_p()
-    assert L.lv_scene_create(None, None, None, None, -1, None, ctypes.byref(out)) == 1
+    assert L.lv_scene_create(None, None, None, None, -1, None, None, ctypes.byref(out)) == 1
     assert b"out of range" in L.lv_last_error()
-    assert L.lv_scene_create(None, None, None, None, 10, None, ctypes.byref(out)) == 1
+    assert L.lv_scene_create(None, None, None, None, 10, None, None, ctypes.byref(out)) == 1
+    # blending constants other than the compiled ones are refused up front
+    opts = lvlib.lv_scene_opts(*lvlib.SCENE_DEFAULTS)
+    opts.alpha_min = 0.01
+    assert L.lv_scene_create(None, None, None, None, 0, ctypes.byref(opts), None, ctypes.byref(out)) == 4
+    assert b"not supported" in L.lv_last_error()
+    opts = lvlib.lv_scene_opts(*lvlib.SCENE_DEFAULTS)
+    opts.tile = 32
+    assert L.lv_scene_create(None, None, None, None, 0, ctypes.byref(opts), None, ctypes.byref(out)) == 4
+    # an allocator needs both callbacks
+    assert L.lv_set_allocator(lvlib.ALLOC_FN(lambda b, s, c: None), lvlib.FREE_FN(), None) == 1
+    assert lvlib.memory_stats() == (0, 0)
+    assert L.lv_server_cancel(None, 3) == 1
     assert L.lv_uplift(None, None, 0, None, 0, None, 8, None, None, None) == 1
     assert L.lv_diffuse(None, None, None, 0, 1, 1, None, None) == 1
     assert L.lv_encode(None, 10, 0, 0, None, None, None) == 1

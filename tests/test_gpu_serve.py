@@ -83,7 +83,9 @@ def test_server_results_equal_alone(rig, workers, budget):
     request uplifted alone."""
     sc, gs, cams, bank = rig
     reqs = make_requests(rig, workers, 14)
-    srv = lv.Server(budget=budget, workers=workers, max_sets=4, max_channels=160)
+    scratch = 256 << 20  # per worker, set aside from the budget
+    srv = lv.Server(budget=budget + workers * scratch if budget else 0, workers=workers, max_sets=4,
+                    max_channels=160, scratch=scratch)
     for i, (D, views, maps, dtype) in enumerate(reqs):
         srv.submit(gs, [cams[v] for v in views], maps, dtype=dtype, tag=i)
     srv.drain()
@@ -116,7 +118,10 @@ def test_server_results_equal_alone(rig, workers, budget):
 
 def test_server_rejects_and_recovers(rig):
     sc, gs, cams, bank = rig
-    srv = lv.Server(budget=1000, workers=1)
+    with pytest.raises(lv.LvError):  # the workers' scratch alone exceeds the budget
+        lv.Server(budget=1 << 20, workers=2, scratch=1 << 20)
+    srv = lv.Server(budget=(64 << 20) + 1000, workers=1, scratch=64 << 20)
+    assert srv.stats()["budget"] == 1000  # what is left for requests
     with pytest.raises(lv.LvError):  # larger than the whole budget
         srv.submit(gs, cams[:1], [bank[0, :, :, :4]])
     srv.close()

@@ -300,3 +300,26 @@ def test_views_in_several_chunks(monkeypatch):
     assert feature_error(f1.cpu().numpy(), ref).max() < TOL
     assert beta_error(b1.cpu().numpy(), ref).max() < TOL
     assert A.stats()["views"] == 5
+
+
+def test_two_groups_one_set_skipping_views():
+    """Two sets in two channel groups (64 + 40 channels: one wave walks for
+    both); the second takes every other view only, so on the other views its
+    group takes nothing while the first group still accumulates."""
+    sc = scenes.make_scene(13, 3000, -3.8, 0.5, 0.0, 1.0)
+    cams = [scenes.look_at(e, 80, 64, 60.0) for e in scenes.fibonacci_eyes(4, 4.0)]
+    gs = lv.Scene.from_arrays(sc)
+    DA, DB = 64, 40
+    ha = [philox.normal(130, v, 64 * 80 * DA).reshape(64, 80, DA) for v in range(4)]
+    hb = [philox.normal(131, v, 64 * 80 * DB).reshape(64, 80, DB) for v in range(0, 4, 2)]
+    A, B = lv.Accum(gs, DA, counts=True), lv.Accum(gs, DB, counts=True)
+    mb = [dev(hb[v // 2]) if v % 2 == 0 else None for v in range(4)]
+    lv.accumulate_sets(cams, [(A, [dev(m) for m in ha]), (B, mb)])
+    for acc, ref in ((A, oracle.uplift(sc, cams, ha)), (B, oracle.uplift(sc, cams[0::2], hb))):
+        f, b = acc.finalize()
+        torch.cuda.synchronize()
+        assert counts_match(acc.counts().cpu().numpy(), ref)
+        e = feature_error(f.cpu().numpy(), ref)
+        print(f"two groups: D={acc.D} max err {e.max():.3e}", flush=True)
+        assert e.max() < TOL
+        assert beta_error(b.cpu().numpy(), ref).max() < TOL
