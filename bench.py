@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--oracle-views", type=int, default=6,
                     help="views of the headline workload the FP64 oracle runs (0 = skip)")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--only", choices=["mid", "diffuse", "serving"],
+                    help="run one secondary leg alone (no headline; for profiles)")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving trace (0 = skip the serving leg)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, req/s")
@@ -86,6 +88,11 @@ def main():
     import paper_2410_14462_amd as lv
 
     torch.cuda.set_device(0)
+    if args.only:
+        leg = {"mid": lambda: mid_leg(lv, args), "diffuse": lambda: diffusion_leg(lv),
+               "serving": lambda: serving(lv, args.serve_requests, args.serve_rate)}[args.only]
+        print(json.dumps({args.only: leg()}), flush=True)
+        return
     out, keep = large_leg(lv, args)
     if args.calib_copy:
         src = torch.empty(1 << 28, device="cuda", dtype=torch.float32).fill_(1.0)
@@ -180,8 +187,8 @@ def large_leg(lv, args):
     value = ms_step / (m * D)
     log(f"bench: {ms_step:.3f} ms/step, {value * 1e3:.4f} us/view/channel")
     roof = roofline(stats, launches, args.steps, n, D, 2, products=2,
-                    kernel="blend_wide_kernel<LV_BF16, true> (D=384 BF16 maps)",
-                    traffic_name="blend_wide_kernel-uplift-1M-100v-1008x756-D384-bf16")
+                    kernel="blend_pair_kernel<LV_BF16> (D=384 BF16 maps, 100 views per launch)",
+                    traffic_name="blend_pair_kernel-uplift-1M-100v-1008x756-D384-bf16")
 
     # the other storage legs: same job, same timing
     storage = {"bf16": {"ms_per_step": round(ms_step, 3), "ms_per_view_channel": round(value, 7),
@@ -414,7 +421,7 @@ def mid_leg(lv, args):
         kname = "LV_F32" if dt == "f32" else "LV_BF16"
         res[dt] = {"ms_per_step": round(t, 3), "ms_per_view_channel": round(t / (m * (D + 1)), 7),
                    "roofline": roofline(st, bl, reps, n, D + 1, 4 if dt == "f32" else 2,
-                                        3 if dt == "f32" else 2, f"blend_wide_kernel<{kname}, false>",
+                                        3 if dt == "f32" else 2, f"blend_wide_kernel<{kname}>",
                                         f"blend_wide_kernel-{w.name}-{dt}")}
         log(f"bench: mid {dt}: {res[dt]['ms_per_step']} ms/step, blend {res[dt]['roofline']['launch_ms']} ms")
     res["bf16_speedup_vs_f32"] = round(res["f32"]["ms_per_step"] / res["bf16"]["ms_per_step"], 3)

@@ -5,9 +5,10 @@
 // accumulators U_i and beta_i.  W is never materialised.
 //
 // One workgroup = one wave64 = one 8x8 quadrant of a 16x16 tile (one pixel
-// per lane), for one group of up to 64 channels (or, with several groups,
-// all of them).  Waves never wait for each other.  Per step of 64 Gaussians
-// of the tile's list:
+// per lane) for one group of up to 64 channels; with several groups, one
+// wave per 16x8 half tile for all of them (blend_pair_kernel, two pixels per
+// lane).  Waves never wait for each other.  Per step of 64 Gaussians of the
+// tile's list:
 //   0. lane j loads Gaussian j's record (vector loads, all in flight
 //      together), leaves it in LDS and tests whether its alpha >= 1/255
 //      region can touch the quadrant (exact minimum of the conic over the
@@ -361,21 +362,18 @@ __device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int
   }
 }
 
-// MULTI = false: one wave per (view, quadrant, channel group); the group's F
-// fragments are staged once in registers.  MULTI = true (several groups):
-// one wave per (view, quadrant) walks once for all groups; each batch runs
-// every group in turn, staging that group's fragments for the K-steps it
-// needs (the walk, the larger part of a group's cost, is shared).
-// Occupancy: waves per SIMD the register allocation must allow (the walk is
-// latency-bound; more resident waves hide it).  BF16 maps need no low
-// operand halves, so their single-group kernel fits four.
-template <lv_dtype DT, bool MULTI>
+// One channel group (at most 64 + 4 channels): one wave per (view,
+// quadrant); the group's F fragments are staged once in registers.  Several
+// groups run on blend_pair_kernel below.  Occupancy: waves per SIMD the
+// register allocation must allow (the walk is latency-bound; more resident
+// waves hide it).  BF16 maps need no low operand halves, so they fit four.
+template <lv_dtype DT>
 constexpr int wide_waves() {
-  return MULTI ? 2 : (DT == LV_BF16 ? 4 : 3);
+  return DT == LV_BF16 ? 4 : 3;
 }
 
-template <lv_dtype DT, bool MULTI>
-__global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kernel(
+template <lv_dtype DT>
+__global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
     const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
@@ -384,31 +382,24 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   __shared__ __align__(16) float Wt[32 * kWtPitch];  // queued Gaussians: [row][pixel]
   __shared__ float4 Rs[kChunk][2];                   // the step's records
   Quad q;
-  if (!decode_quad(ranges, geom, tiles_stride, nviews, MULTI ? 1 : ngroups, q)) return;
+  if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
   const int lane = threadIdx.x;
-  const int g_lo = MULTI ? 0 : q.cg, g_hi = MULTI ? ngroups : q.cg + 1;
   const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
   const bool inside = px < q.g.W && py < q.g.H;
 
-  // groups taking the view, sets whose beta (and counts) are added here;
-  // tail channels (only the last group has them)
+  // whether the group takes the view, sets whose beta (and counts) are added
+  // here; its tail channels
   bool has_main = false;
   int bsets = 0, ssets = 0;
-  uint32_t gmask = 0u;  // groups (relative to g_lo) with a segment taking the view
-  for (int cg = g_lo; cg < g_hi; cg++) {
-    const ChanGroup& grp = groups[cg];
+  {
+    const ChanGroup& grp = groups[q.cg];
     for (int b = grp.beta_sets; b; b &= b - 1)
       if (map_of(sets[__builtin_ctz(b)], q.v)) bsets |= b & -b;
     for (int b = grp.stats_sets; b; b &= b - 1)
       if (map_of(sets[__builtin_ctz(b)], q.v)) ssets |= b & -b;
-    bool any = false;
-    for (int k = 0; k < grp.nseg; k++) any = any || map_of(sets[grp.set[k]], q.v) != nullptr;
-    if (any) {
-      gmask |= 1u << (cg - g_lo);
-      has_main = true;
-    }
+    for (int k = 0; k < grp.nseg; k++) has_main = has_main || map_of(sets[grp.set[k]], q.v) != nullptr;
   }
-  const ChanGroup& last = groups[g_hi - 1];
+  const ChanGroup& last = groups[q.cg];
   const int ntail = last.ntail;
   // tail channels: their features per pixel in LDS (Ft[t][pixel]), summed
   // against the ring rows at each flush
@@ -437,11 +428,11 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   }
   if (!has_main && !any_tail && !bsets && !ssets) return;  // wave-uniform: nothing here takes the view
 
-  // single group: its lanes and fragments once, in registers
+  // the group's lanes and fragments once, in registers
   GroupLanes L1;
   bf16x8 fh[2][4], fl[2][4];
   bool two1 = false;
-  if constexpr (!MULTI) {
+  {
     const ChanGroup& grp = groups[q.cg];
     const bool takes = group_lanes<DT>(grp, sets, q, lane, L1);
     two1 = grp.width > 32;
@@ -474,55 +465,10 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
     ring_cnt = Rc[lane & 31];
     const uint32_t rows = row_bits(pix);
     const float* wrow = Wt + (lane & 31) * kWtPitch + 8 * (lane >> 5);
-    if constexpr (!MULTI) {
-      if (has_main) {
-        f32x16 acc0 = {}, acc1 = {};
-        batch_mfma<kSplitF>(two1, rows, wrow, fh, fl, acc0, acc1);
-        batch_scatter(L1, two1, count, ring_gid, lane, acc0, acc1);
-      }
-    } else {
-      for (int cg = g_lo; cg < g_hi; cg++) {
-        if (!((gmask >> (cg - g_lo)) & 1u)) continue;
-        const ChanGroup& grp = groups[cg];
-        GroupLanes L;
-        if (!group_lanes<DT>(grp, sets, q, lane, L)) continue;
-        const bool two = grp.width > 32;
-        // fragments staged K-step by K-step, right before their MFMAs (only
-        // one K-step's operands live at a time)
-        f32x16 acc0 = {}, acc1 = {};
-        if (two) {
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            if ((rows >> (2 * t)) & 3u) {
-              bf16x8 h0, l0, h1, l1, ah, al;
-              stage_fragment<DT>(L, q, lane, t, 0, h0, l0);
-              stage_fragment<DT>(L, q, lane, t, 1, h1, l1);
-              load_split_w(wrow + 16 * t, ah, al);
-              acc0 = mfma(ah, h0, acc0);
-              acc1 = mfma(ah, h1, acc1);
-              acc0 = mfma(al, h0, acc0);
-              acc1 = mfma(al, h1, acc1);
-              if constexpr (kSplitF) {
-                acc0 = mfma(ah, l0, acc0);
-                acc1 = mfma(ah, l1, acc1);
-              }
-            }
-          }
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            if ((rows >> (2 * t)) & 3u) {
-              bf16x8 h0, l0, ah, al;
-              stage_fragment<DT>(L, q, lane, t, 0, h0, l0);
-              load_split_w(wrow + 16 * t, ah, al);
-              acc0 = mfma(ah, h0, acc0);
-              acc0 = mfma(al, h0, acc0);
-              if constexpr (kSplitF) acc0 = mfma(ah, l0, acc0);
-            }
-          }
-        }
-        batch_scatter(L, two, count, ring_gid, lane, acc0, acc1);
-      }
+    if (has_main) {
+      f32x16 acc0 = {}, acc1 = {};
+      batch_mfma<kSplitF>(two1, rows, wrow, fh, fl, acc0, acc1);
+      batch_scatter(L1, two1, count, ring_gid, lane, acc0, acc1);
     }
     if (bsets || any_tail) {
       // lane l: row l % 32, pixels [32 (l / 32), 32 (l / 32) + 32)
@@ -634,6 +580,323 @@ __global__ __launch_bounds__(64, (wide_waves<DT, MULTI>())) void blend_wide_kern
   }
 }
 
+// ------------------------------------------------------------- pair kernel
+// Several channel groups (wide D): one wave per (view, tile, half tile), the
+// two 8x8 quadrants of a 16x8 half tile, two pixels per lane (lane l covers
+// pixel (l % 8, l / 8) of each quadrant).  A Gaussian that reaches both
+// quadrants queues one row of 128 weights instead of two rows of 64, so a
+// (Gaussian, view) adds about 0.7 times as many partial sums to U as with one
+// wave per quadrant -- each partial sum is D atomic adds, the binding cost at
+// large D.  The walk evaluates a Gaussian only at the quadrants its
+// alpha >= 1/255 region reaches.  Pixel p of a queued row: quadrant p / 64,
+// pixel p % 64 of it (row-major 8x8); K-step t of the products (16 pixels)
+// is pixel rows 2 (t % 4), 2 (t % 4) + 1 of quadrant t / 4.
+constexpr int kPairPitch = 132;  // LDS row pitch (floats) of the 128 queued weights
+
+struct Pair {
+  int v, tile, qx, qy;  // qx, qy: the half tile's first pixel
+  uint2 rg;
+  ViewGeom g;
+};
+
+// The two halves of a tile get consecutive ids on the same XCD (ids equal
+// mod 8), so they share that XCD's L2 for the tile's records.
+__device__ __forceinline__ bool decode_pair(const uint2* __restrict__ ranges,
+                                            const ViewGeom* __restrict__ geom, int tiles_stride,
+                                            int nviews, Pair& q) {
+  const uint32_t L = blockIdx.x;
+  const uint32_t kx = L >> 3;
+  const uint32_t work = ((kx >> 1) << 3) | (L & 7u);
+  if (work >= (uint32_t)tiles_stride * (uint32_t)nviews) return false;
+  const int half = (int)(kx & 1u);
+  q.tile = (int)(work % (uint32_t)tiles_stride);
+  q.v = (int)(work / (uint32_t)tiles_stride);
+  q.g = geom[q.v];
+  if (q.tile >= q.g.TX * q.g.TY) return false;
+  q.rg = ranges[(int64_t)q.v * tiles_stride + q.tile];
+  if (q.rg.y <= q.rg.x) return false;
+  const int tx = q.tile % q.g.TX, ty = q.tile / q.g.TX;
+  q.qx = tx * kTile;
+  q.qy = ty * kTile + half * 8;
+  return q.qx < q.g.W && q.qy < q.g.H;
+}
+
+// Alpha-blending step at one pixel (offsets relative to the tile), as
+// walk_rec: take = the Gaussian contributes here, w = alpha T.
+__device__ __forceinline__ float blend_at(const float4& a, const float4& b, float pxo, float pyo,
+                                          float& T, bool& alive, bool& take) {
+  const float dx = pxo - a.x, dy = pyo - a.y;
+  const float u = __builtin_fmaf(a.w, dy, a.z * dx), w = b.x * dy;
+  const float al = fminf(kAlphaMax, b.y * exp32_clamped(-__builtin_fmaf(u, u, w * w)));
+  const bool ok = alive && al >= kAlphaMin;
+  const float Tn = T * (1.0f - al);
+  const bool stop = ok && Tn < kTEps;
+  take = ok && !stop;
+  const float wj = take ? al * T : 0.0f;
+  T = take ? Tn : T;
+  alive = alive && !stop;
+  return wj;
+}
+
+// B operands of K-step t of a half tile (see above) for block b.
+template <lv_dtype DT>
+__device__ __forceinline__ void stage_fragment_pair(const GroupLanes& L, const Pair& q, int lane,
+                                                    int t, int b, bf16x8& fh, bf16x8& fl) {
+  float v[8];
+  const int gy = q.qy + 2 * (t & 3) + (lane >> 5);
+  const int gx0 = q.qx + 8 * (t >> 2);
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const int gx = gx0 + i;
+    const bool ok = L.own[b] && gx < q.g.W && gy < q.g.H;
+    const int64_t idx = ok ? ((int64_t)gy * q.g.W + gx) * L.srcld[b] + L.srcc[b] : 0;
+    const float x = load_feature<DT>(L.src[b], idx, L.srcsc[b]);
+    v[i] = ok ? x : 0.0f;
+  }
+  split8(v, fh, fl);
+}
+
+// group_lanes for a half tile (only the view matters)
+template <lv_dtype DT>
+__device__ __forceinline__ bool group_lanes_pair(const ChanGroup& grp, const SetDesc* __restrict__ sets,
+                                                 const Pair& p, int lane, GroupLanes& L) {
+  Quad q;
+  q.v = p.v;
+  return group_lanes<DT>(grp, sets, q, lane, L);
+}
+
+template <lv_dtype DT>
+__global__ __launch_bounds__(64, 2) void blend_pair_kernel(
+    const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
+    const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
+    const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
+  constexpr int G = kChunk;
+  constexpr bool kSplitF = DT != LV_BF16;
+  __shared__ __align__(16) float Wt[32 * kPairPitch];  // queued Gaussians: [row][128 pixels]
+  __shared__ float4 Rs[kChunk][2];                     // the step's records
+  __shared__ __align__(16) float Ft[kMaxTail * 128];   // tail channels per pixel
+  __shared__ uint32_t Rg[32], Rc[32];
+  Pair q;
+  if (!decode_pair(ranges, geom, tiles_stride, nviews, q)) return;
+  const int lane = threadIdx.x;
+  const int ox = q.qx, oy = q.qy & ~(kTile - 1);
+  const float ocx = (float)ox + 0.5f, ocy = (float)oy + 0.5f;
+  const float pyo = (float)(q.qy - oy + (lane >> 3));
+  const float pxo0 = (float)(lane & 7), pxo1 = pxo0 + 8.0f;
+  const float qy0 = (float)(q.qy - oy);
+  const int py = q.qy + (lane >> 3);
+  const bool in0 = q.qx + (lane & 7) < q.g.W && py < q.g.H;
+  const bool in1 = q.qx + 8 + (lane & 7) < q.g.W && py < q.g.H;
+
+  bool has_main = false;
+  int bsets = 0, ssets = 0;
+  uint32_t gmask = 0u;
+  for (int cg = 0; cg < ngroups; cg++) {
+    const ChanGroup& grp = groups[cg];
+    for (int b = grp.beta_sets; b; b &= b - 1)
+      if (map_of(sets[__builtin_ctz(b)], q.v)) bsets |= b & -b;
+    for (int b = grp.stats_sets; b; b &= b - 1)
+      if (map_of(sets[__builtin_ctz(b)], q.v)) ssets |= b & -b;
+    bool any = false;
+    for (int k = 0; k < grp.nseg; k++) any = any || map_of(sets[grp.set[k]], q.v) != nullptr;
+    if (any) {
+      gmask |= 1u << cg;
+      has_main = true;
+    }
+  }
+  const ChanGroup& last = groups[ngroups - 1];
+  const int ntail = last.ntail;
+  float* tout[kMaxTail];
+  int tD[kMaxTail];
+  bool any_tail = false;
+#pragma unroll
+  for (int t = 0; t < kMaxTail; t++) {
+    float ft0 = 0.0f, ft1 = 0.0f;
+    tout[t] = nullptr;
+    tD[t] = 0;
+    if (t < ntail && map_of(sets[last.tset[t]], q.v)) {
+      const SetDesc& sd = sets[last.tset[t]];
+      const int c = last.tc[t];
+      float sc = 1.0f;
+      if constexpr (DT == LV_FP8_E4M3) sc = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * sd.D + c];
+      const int64_t i0 = in0 ? ((int64_t)py * q.g.W + q.qx + (lane & 7)) * sd.stride + c : 0;
+      const int64_t i1 = in1 ? ((int64_t)py * q.g.W + q.qx + 8 + (lane & 7)) * sd.stride + c : 0;
+      const float x0 = load_feature<DT>(map_of(sd, q.v), i0, sc);  // no branch around the loads
+      const float x1 = load_feature<DT>(map_of(sd, q.v), i1, sc);
+      ft0 = in0 ? x0 : 0.0f;
+      ft1 = in1 ? x1 : 0.0f;
+      tout[t] = sd.U + c;
+      tD[t] = sd.D;
+      any_tail = true;
+    }
+    Ft[t * 128 + lane] = ft0;
+    Ft[t * 128 + 64 + lane] = ft1;
+  }
+  if (!has_main && !any_tail && !bsets && !ssets) return;  // wave-uniform
+
+  int queued = 0;
+  uint64_t pix0 = 0ull, pix1 = 0ull;  // pixels of each quadrant used by the queued rows
+  uint32_t ring_gid = 0u, ring_cnt = 0u;
+
+  auto flush = [&](int count) {
+    __syncthreads();  // ring rows written (one wave per workgroup: orders LDS)
+    ring_gid = Rg[lane & 31];
+    ring_cnt = Rc[lane & 31];
+    // bit r: pixel row r % 8 of quadrant r / 8; K-step t covers bits 2t, 2t + 1
+    const uint32_t rows = row_bits(pix0) | (row_bits(pix1) << 8);
+    const float* wrow = Wt + (lane & 31) * kPairPitch + 8 * (lane >> 5);
+    for (int cg = 0; cg < ngroups; cg++) {
+      if (!((gmask >> cg) & 1u)) continue;
+      const ChanGroup& grp = groups[cg];
+      GroupLanes L;
+      if (!group_lanes_pair<DT>(grp, sets, q, lane, L)) continue;
+      const bool two = grp.width > 32;
+      f32x16 acc0 = {}, acc1 = {};
+      if (two) {
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          if ((rows >> (2 * t)) & 3u) {
+            bf16x8 h0, l0, h1, l1, ah, al;
+            stage_fragment_pair<DT>(L, q, lane, t, 0, h0, l0);
+            stage_fragment_pair<DT>(L, q, lane, t, 1, h1, l1);
+            load_split_w(wrow + 16 * t, ah, al);
+            acc0 = mfma(ah, h0, acc0);
+            acc1 = mfma(ah, h1, acc1);
+            acc0 = mfma(al, h0, acc0);
+            acc1 = mfma(al, h1, acc1);
+            if constexpr (kSplitF) {
+              acc0 = mfma(ah, l0, acc0);
+              acc1 = mfma(ah, l1, acc1);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          if ((rows >> (2 * t)) & 3u) {
+            bf16x8 h0, l0, ah, al;
+            stage_fragment_pair<DT>(L, q, lane, t, 0, h0, l0);
+            load_split_w(wrow + 16 * t, ah, al);
+            acc0 = mfma(ah, h0, acc0);
+            acc0 = mfma(al, h0, acc0);
+            if constexpr (kSplitF) acc0 = mfma(ah, l0, acc0);
+          }
+        }
+      }
+      batch_scatter(L, two, count, ring_gid, lane, acc0, acc1);
+    }
+    if (bsets || any_tail) {
+      // lane l: row l % 32, the pixels of quadrant l / 32
+      const float* rp = Wt + (lane & 31) * kPairPitch + 64 * (lane >> 5);
+      const float* fp = Ft + 64 * (lane >> 5);
+      float bs = 0.0f, ts[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < 16; k++) {
+        const float4 a = *reinterpret_cast<const float4*>(rp + 4 * k);
+        bs += a.x;
+        bs += a.y;
+        bs += a.z;
+        bs += a.w;
+#pragma unroll
+        for (int t = 0; t < kMaxTail; t++) {
+          if (t < ntail) {  // wave-uniform
+            const float4 f = *reinterpret_cast<const float4*>(fp + t * 128 + 4 * k);
+            ts[t] = __builtin_fmaf(a.x, f.x, ts[t]);
+            ts[t] = __builtin_fmaf(a.y, f.y, ts[t]);
+            ts[t] = __builtin_fmaf(a.z, f.z, ts[t]);
+            ts[t] = __builtin_fmaf(a.w, f.w, ts[t]);
+          }
+        }
+      }
+      bs += __shfl_xor(bs, 32, 64);
+#pragma unroll
+      for (int t = 0; t < kMaxTail; t++) ts[t] += __shfl_xor(ts[t], 32, 64);
+      if (lane < count) {
+        for (int b = bsets; b; b &= b - 1) {
+          const SetDesc& sd = sets[__builtin_ctz(b)];
+          beta_atomic_add(sd.beta + ring_gid, bs);
+          if (sd.counts) gatomic_add(sd.counts + ring_gid, ring_cnt);
+        }
+#pragma unroll
+        for (int t = 0; t < kMaxTail; t++)
+          if (tout[t] && ts[t] != 0.0f) gatomic_add(tout[t] + (int64_t)ring_gid * tD[t], ts[t]);
+      }
+    }
+    __syncthreads();  // rows read before they are written again
+  };
+
+  float T0 = 1.0f, T1 = 1.0f;
+  bool alive0 = in0, alive1 = in1;
+  uint64_t cov0 = 0ull, cov1 = 0ull;
+  uint32_t ncontrib = 0u, nrows = 0u;
+  const Rec* vrec = rec + (int64_t)q.v * n;
+  for (uint32_t base = q.rg.x; base < q.rg.y; base += G) {
+    if (__ballot(alive0 || alive1) == 0ull) break;
+    const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
+    // lane j: record j, centre made tile-relative, left in LDS; hit masks of
+    // the two quadrants
+    float4 r0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float4 r1 = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+    uint32_t my_id = 0;
+    if (lane < cnt) {
+      my_id = ids[base + lane];
+      r0 = vrec[my_id].r0;
+      r1 = vrec[my_id].r1;
+      const uint32_t lo = __float_as_uint(r1.w);
+      r0.x = (r0.x - ocx) + __uint_as_float(lo << 16);
+      r0.y = (r0.y - ocy) + __uint_as_float(lo & 0xFFFF0000u);
+    }
+    Rs[lane][0] = r0;
+    Rs[lane][1] = r1;
+    const float X0 = -r0.x, Y0 = qy0 - r0.y;
+    const bool h0 = lane < cnt && region_hits(r0, r1, X0, X0 + 7.0f, Y0, Y0 + 7.0f);
+    const bool h1 = lane < cnt && region_hits(r0, r1, X0 + 8.0f, X0 + 15.0f, Y0, Y0 + 7.0f);
+    const uint64_t hits0 = __ballot(h0), hits1 = __ballot(h1);
+    uint64_t h = hits0 | hits1;
+    if (!h) continue;
+    __syncthreads();  // records in LDS
+    while (h) {
+      const int j = (int)__builtin_ctzll(h);
+      h &= h - 1;
+      const float4 a = Rs[j][0], b = Rs[j][1];
+      bool t0 = false, t1 = false;
+      float w0 = 0.0f, w1 = 0.0f;
+      if ((hits0 >> j) & 1ull) w0 = blend_at(a, b, pxo0, pyo, T0, alive0, t0);
+      if ((hits1 >> j) & 1ull) w1 = blend_at(a, b, pxo1, pyo, T1, alive1, t1);
+      const uint64_t m0 = __builtin_amdgcn_ballot_w64(t0), m1 = __builtin_amdgcn_ballot_w64(t1);
+      if (m0 | m1) {
+        cov0 |= m0;
+        cov1 |= m1;
+        const uint32_t c = (uint32_t)(__popcll(m0) + __popcll(m1));
+        ncontrib += c;
+        nrows++;
+        Wt[queued * kPairPitch + lane] = w0;
+        Wt[queued * kPairPitch + 64 + lane] = w1;
+        if (lane == j) {  // lane j holds the Gaussian's id
+          Rg[queued] = my_id;
+          Rc[queued] = c;
+        }
+        pix0 |= m0;
+        pix1 |= m1;
+        if (++queued == 32) {
+          flush(32);
+          queued = 0;
+          pix0 = pix1 = 0ull;
+        }
+      }
+    }
+  }
+  if (queued > 0) flush(queued);
+  for (int b = ssets; b; b &= b - 1) {
+    const SetDesc& sd = sets[__builtin_ctz(b)];
+    if (sd.stats && lane == 0) {
+      gatomic_add(&sd.stats[1], (unsigned long long)ncontrib);
+      gatomic_add(&sd.stats[0], (unsigned long long)(__popcll(cov0) + __popcll(cov1)));
+      gatomic_add(&sd.stats[2], (unsigned long long)nrows);
+    }
+  }
+}
+
 template <lv_dtype DT>
 hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   // one group: one wave per (view, quadrant, group); several: one wave per
@@ -641,12 +904,14 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   const bool multi = a.ngroups > 1;
   int64_t work = (int64_t)a.tiles_stride * m * (multi ? 1 : a.ngroups);
   int64_t blocks = (work + 7) / 8 * 32;
-  if (multi)
-    hipLaunchKernelGGL((blend_wide_kernel<DT, true>), dim3((unsigned)blocks), dim3(64), 0, s, a.rec,
+  if (multi) {
+    // one wave per half tile: two per tile, whole rounds of 8 XCDs
+    const int64_t pblocks = ((int64_t)a.tiles_stride * m + 7) / 8 * 16;
+    hipLaunchKernelGGL((blend_pair_kernel<DT>), dim3((unsigned)pblocks), dim3(64), 0, s, a.rec,
                        a.ids, a.ranges, a.geom, a.n, a.tiles_stride, m, a.sets, a.groups,
                        a.ngroups);
-  else
-    hipLaunchKernelGGL((blend_wide_kernel<DT, false>), dim3((unsigned)blocks), dim3(64), 0, s,
+  } else
+    hipLaunchKernelGGL((blend_wide_kernel<DT>), dim3((unsigned)blocks), dim3(64), 0, s,
                        a.rec, a.ids, a.ranges, a.geom, a.n, a.tiles_stride, m, a.sets, a.groups,
                        a.ngroups);
   return hipGetLastError();
