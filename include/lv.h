@@ -280,6 +280,19 @@ lv_status lv_profile_stop(int64_t* launches, double* total_ms, double* per_launc
 lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,
                     float* scales, void* stream);
 
+/* lv_encode without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as lv_encode, except that the
+ * FP8 per-channel absmax lives in a static device array of 4096 uint32 (16 KiB,
+ * held by each GPU the library runs on until the process ends): D must be in
+ * [1, 4096], else LV_ERR_INVALID_ARG.  Every call on one GPU shares that array
+ * (it is cleared at the start of each FP8 call, on the caller's stream), so
+ * FP8 calls that overlap on one GPU (different streams, no ordering) race;
+ * calls on one stream are ordered and safe.  LV_BF16 and LV_F32 use no
+ * scratch. */
+lv_status lv_encode_noalloc(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,
+                            float* scales, void* stream);
+
 /* -------------------------------------------------------------- diffusion -- */
 /* Sec. 3.3: a graph A over the n Gaussians as CSR (row_ptr [n+1], col [nnz]
  * int32, val [nnz] of val_dtype = LV_F32 or LV_BF16), device arrays copied by

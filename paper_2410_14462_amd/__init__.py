@@ -121,6 +121,7 @@ def lib():
             "lv_graph_csr": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64), P, P, P, P], i32),
             "lv_accum_destroy": ([P], i32),
             "lv_encode": ([P, i64, i32, i32, P, P, P], i32),
+            "lv_encode_noalloc": ([P, i64, i32, i32, P, P, P], i32),
             "lv_graph_create_csr": ([i64, i64, P, P, P, i32, P, ctypes.POINTER(P)], i32),
             "lv_graph_destroy": ([P], i32),
             "lv_diffuse": ([P, P, P, i32, i32, i32, P, P], i32),
@@ -153,7 +154,7 @@ def lib():
 def exported_symbols():
     return ["lv_last_error", "lv_version", "lv_scene_create", "lv_scene_destroy", "lv_scene_size",
             "lv_uplift", "lv_accum_create", "lv_accum_reset", "lv_uplift_accumulate",
-            "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode",
+            "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode", "lv_encode_noalloc",
             "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view",
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
             "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",

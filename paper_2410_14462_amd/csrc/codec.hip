@@ -4,6 +4,7 @@
 // round-to-nearest-even of x / scale).  Decoding happens inside the blend
 // kernel's tile staging.
 #include <algorithm>
+#include <mutex>
 
 #include "lv_internal.h"
 
@@ -82,6 +83,11 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ s
   }
 }
 
+__global__ void zero_kernel(uint32_t* __restrict__ p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 __global__ void scale_kernel(const uint32_t* __restrict__ amax, int D, float* __restrict__ scales) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= D) return;
@@ -145,9 +151,10 @@ hipError_t launch_encode(const float* src, int64_t pixels, int D, lv_dtype dtype
                          static_cast<uint16_t*>(dst));
     return hipGetLastError();
   }
+  // the per-channel absmax starts at zero (a kernel, not a memset: callers
+  // may capture the launches in a graph)
   uint32_t* amax = reinterpret_cast<uint32_t*>(tmp_absmax);
-  hipError_t e = hipMemsetAsync(amax, 0, sizeof(uint32_t) * (size_t)D, s);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(zero_kernel, dim3((D + 255) / 256), dim3(256), 0, s, amax, D);
   int rows = 512;
   hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)((pixels + rows - 1) / rows), (D + 63) / 64),
                      dim3(256), 0, s, src, pixels, D, rows, amax);
@@ -163,3 +170,53 @@ hipError_t launch_encode(const float* src, int64_t pixels, int D, lv_dtype dtype
 }
 
 }  // namespace lv
+
+// ------------------------------------------------------------ no allocation
+// Scratch of lv_encode_noalloc: the per-channel absmax of an FP8 encode, in
+// device memory the library never allocates (each GPU holds its own copy of
+// the array until the process ends).  Host code uses the per-device address
+// from hipGetSymbolAddress, never the array's name.
+constexpr int kNoAllocMaxD = 4096;
+static __device__ __align__(256) uint32_t scratch[kNoAllocMaxD];
+
+namespace {
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up once per device).
+hipError_t scratch_ptr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" lv_status lv_encode_noalloc(const float* src, int64_t pixels, int32_t D, lv_dtype dtype,
+                                       void* dst, float* scales, void* stream) {
+  if (pixels < 0) return lv::set_error(LV_ERR_INVALID_ARG, "pixels = %lld < 0", (long long)pixels);
+  if (D < 1 || D > kNoAllocMaxD)
+    return lv::set_error(LV_ERR_INVALID_ARG, "D = %d outside [1, %d], the size of the static scratch", D,
+                         kNoAllocMaxD);
+  if (pixels > 0 && (!src || !dst)) return lv::set_error(LV_ERR_INVALID_ARG, "null buffer");
+  if (dtype != LV_F32 && dtype != LV_BF16 && dtype != LV_FP8_E4M3)
+    return lv::set_error(LV_ERR_INVALID_ARG, "unknown dtype");
+  if (dtype == LV_FP8_E4M3 && !scales) return lv::set_error(LV_ERR_INVALID_ARG, "FP8 needs scales");
+  void* amax = nullptr;
+  hipError_t e = scratch_ptr(&amax);
+  if (e != hipSuccess) return lv::set_error(LV_ERR_DEVICE, "scratch address: %s", hipGetErrorString(e));
+  e = lv::launch_encode(src, pixels, D, dtype, dst, scales, static_cast<float*>(amax),
+                        static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return lv::set_error(LV_ERR_DEVICE, "encode: %s", hipGetErrorString(e));
+  return LV_OK;
+}
