@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--legs", default="f32,fp8", help="storage legs besides the BF16 headline")
+    ap.add_argument("--layout", choices=["px8", "hwc"], default="px8",
+                    help="stored-map layout of the large configuration's legs: pixel blocks "
+                         "(lv_encode_map) or HWC")
     ap.add_argument("--oracle-views", type=int, default=6,
                     help="views of the headline workload the FP64 oracle runs (0 = skip)")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
@@ -129,38 +132,40 @@ def large_leg(lv, args):
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     means, scales, quats, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacity)
     legs = ["bf16"] + [x for x in args.legs.split(",") if x in ("f32", "fp8")]
+    # storage format of each leg (lv dtype): pixel blocks, or HWC (FP32: the maps as generated)
+    fmt = {k: (k + "_px8" if args.layout == "px8" else k) for k in ("bf16", "f32", "fp8")}
     maps32, maps16, codes8, sc8 = [], [], [], []
     for v in range(m):
         f = scenes.feature_map(w, v, device="cuda")
-        maps16.append(lv.encode(f, "bf16")[0])
+        maps16.append(lv.encode(f, fmt["bf16"])[0])
         if "fp8" in legs:
-            c, s = lv.encode(f, "fp8")
+            c, s = lv.encode(f, fmt["fp8"])
             codes8.append(c)
             sc8.append(s)
         if "f32" in legs:
-            maps32.append(f)
+            maps32.append(lv.encode(f, fmt["f32"])[0] if args.layout == "px8" else f)
         del f
     scales8 = torch.stack(sc8).contiguous() if sc8 else None
     torch.cuda.synchronize()
     rig = lv.Cameras(cams)
-    tabs = {"bf16": (lv.Maps(maps16, "bf16"), None)}
+    tabs = {"bf16": (lv.Maps(maps16, fmt["bf16"]), None)}
     if "f32" in legs:
-        tabs["f32"] = (lv.Maps(maps32), None)
+        tabs["f32"] = (lv.Maps(maps32, fmt["f32"]), None)
     if "fp8" in legs:
-        tabs["fp8"] = (lv.Maps(codes8, "fp8"), scales8)
+        tabs["fp8"] = (lv.Maps(codes8, fmt["fp8"]), scales8)
     fout = torch.empty((n, D), device="cuda")
     bout = torch.empty((n,), device="cuda")
 
     def step(dt):
         tab, s8 = tabs[dt]
         s = lv.Scene(means, scales, quats, opac)
-        s.uplift(rig, tab, dtype=dt, scales=s8, out=fout, wsum=bout)
+        s.uplift(rig, tab, dtype=fmt[dt], scales=s8, out=fout, wsum=bout)
         s.close()
 
     # work statistics of the headline pass (untimed, with counters)
     s = lv.Scene(means, scales, quats, opac)
     acc = lv.Accum(s, D, counts=True)
-    acc.add(rig, tabs["bf16"][0], dtype="bf16")
+    acc.add(rig, tabs["bf16"][0], dtype=fmt["bf16"])
     stats = acc.stats()
     acc.close()
     s.close()
@@ -187,8 +192,9 @@ def large_leg(lv, args):
     value = ms_step / (m * D)
     log(f"bench: {ms_step:.3f} ms/step, {value * 1e3:.4f} us/view/channel")
     roof = roofline(stats, launches, args.steps, n, D, 2, products=2,
-                    kernel="blend_pair_kernel<LV_BF16> (D=384 BF16 maps, 100 views per launch)",
-                    traffic_name="blend_pair_kernel-uplift-1M-100v-1008x756-D384-bf16")
+                    kernel=f"blend_pair_kernel<LV_BF16, {args.layout == 'px8'}> "
+                           f"(D=384 BF16 maps, {args.layout.upper()} layout, 100 views per launch)",
+                    traffic_name=f"blend_pair_kernel-uplift-1M-100v-1008x756-D384-{fmt['bf16']}")
 
     # the other storage legs: same job, same timing
     storage = {"bf16": {"ms_per_step": round(ms_step, 3), "ms_per_view_channel": round(value, 7),
@@ -213,7 +219,7 @@ def large_leg(lv, args):
     cpu = None
     if args.oracle_views > 0:
         errs, cpu = oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, codes8,
-                                  scales8, args.oracle_views)
+                                  scales8, args.oracle_views, fmt)
         for dt, e in errs.items():
             storage.setdefault(dt, {})["error"] = e
 
@@ -231,7 +237,7 @@ def large_leg(lv, args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "gaussians": n, "views": m, "width": W, "height": H,
-                   "channels": D, "storage": "bf16", "accumulation": "f32",
+                   "channels": D, "storage": fmt["bf16"], "accumulation": "f32",
                    "contraction": "split-BF16 matrix-core products, FP32 accumulate (BF16 maps: "
                                   "2 exact products per term; FP32 and FP8 maps: 3, error < 2^-16 |w F|)"},
         "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)},
@@ -303,7 +309,15 @@ def roofline(st, launches, steps, n, D, s_f, products, kernel, traffic_name):
     return roof
 
 
-def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, codes8, scales8, nv):
+def unblock(t, W):
+    """A pixel-block map [H, ceil(W/8), D, 8] back to HWC [H, W, D] (HWC maps pass)."""
+    if t.dim() == 3:
+        return t
+    H, W8, D, _ = t.shape
+    return t.permute(0, 1, 3, 2).reshape(H, W8 * 8, D)[:, :W]
+
+
+def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, codes8, scales8, nv, fmt):
     """Each storage leg's result over the first nv views against the FP64
     oracle on a 20,000-Gaussian subsample: total error (oracle on the FP32
     maps) and accumulation error (oracle on the decoded stored maps), in units
@@ -320,11 +334,11 @@ def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, c
     views = list(range(nv))
     c = [cams[v] for v in views]
     s = lv.Scene(means, scales, quats, opac)
-    gpu = {"bf16": s.uplift(c, [maps16[v] for v in views], dtype="bf16")}
+    gpu = {"bf16": s.uplift(c, [maps16[v] for v in views], dtype=fmt["bf16"])}
     if maps32:
-        gpu["f32"] = s.uplift(c, [maps32[v] for v in views])
+        gpu["f32"] = s.uplift(c, [maps32[v] for v in views], dtype=fmt["f32"])
     if codes8:
-        gpu["fp8"] = s.uplift(c, [codes8[v] for v in views], dtype="fp8",
+        gpu["fp8"] = s.uplift(c, [codes8[v] for v in views], dtype=fmt["fp8"],
                               scales=scales8[:nv].contiguous())
     torch.cuda.synchronize()
     s.close()
@@ -340,8 +354,10 @@ def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, c
     t0 = time.perf_counter()
     ref32 = run(host32)
     t_cpu = time.perf_counter() - t0
-    decoded = {"bf16": lambda v: maps16[v].float().cpu().numpy(),
-               "fp8": lambda v: (codes8[v].view(torch.float8_e4m3fn).float() * scales8[v]).cpu().numpy(),
+    W = w.width
+    decoded = {"bf16": lambda v: unblock(maps16[v], W).float().cpu().numpy(),
+               "fp8": lambda v: (unblock(codes8[v], W).view(torch.float8_e4m3fn).float()
+                                 * scales8[v]).cpu().numpy(),
                "f32": host32}
     errs = {}
     for dt, (f, b) in gpu.items():
@@ -391,7 +407,9 @@ def mid_leg(lv, args):
     rig = lv.Cameras(cams)
     tab = {"f32": (lv.Maps(maps), lv.Maps(masks)),
            "bf16": (lv.Maps([x.to(torch.bfloat16) for x in maps], "bf16"),
-                    lv.Maps([x.to(torch.bfloat16) for x in masks], "bf16"))}
+                    lv.Maps([x.to(torch.bfloat16) for x in masks], "bf16")),
+           "bf16_px8": (lv.Maps([lv.encode(x, "bf16_px8")[0] for x in maps], "bf16_px8"),
+                        lv.Maps([lv.encode(x, "bf16_px8")[0] for x in masks], "bf16_px8"))}
     outs = [(torch.empty((n, D), device="cuda"), torch.empty((n,), device="cuda")),
             (torch.empty((n, 1), device="cuda"), torch.empty((n,), device="cuda"))]
     s = lv.Scene(means, scales, quats, opac)
@@ -402,7 +420,7 @@ def mid_leg(lv, args):
     accm.close()
     s.close()
     res = {"workload": w.name, "work": st}
-    for dt in ("f32", "bf16"):
+    for dt in ("f32", "bf16", "bf16_px8"):
         def step():
             s = lv.Scene(means, scales, quats, opac)
             s.uplift_sets(rig, list(tab[dt]), dtype=dt, outs=outs)
@@ -418,7 +436,7 @@ def mid_leg(lv, args):
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) * 1e3 / reps
         bl = lv.profile_stop()
-        kname = "LV_F32" if dt == "f32" else "LV_BF16"
+        kname = "LV_F32, false" if dt == "f32" else "LV_BF16, false" if dt == "bf16" else "LV_BF16, true"
         res[dt] = {"ms_per_step": round(t, 3), "ms_per_view_channel": round(t / (m * (D + 1)), 7),
                    "roofline": roofline(st, bl, reps, n, D + 1, 4 if dt == "f32" else 2,
                                         3 if dt == "f32" else 2, f"blend_wide_kernel<{kname}>",
@@ -427,6 +445,7 @@ def mid_leg(lv, args):
     res["bf16_speedup_vs_f32"] = round(res["f32"]["ms_per_step"] / res["bf16"]["ms_per_step"], 3)
     res["bf16_blend_speedup_vs_f32"] = round(res["f32"]["roofline"]["launch_ms"]
                                              / res["bf16"]["roofline"]["launch_ms"], 3)
+    res["bf16_px8_speedup_vs_f32"] = round(res["f32"]["ms_per_step"] / res["bf16_px8"]["ms_per_step"], 3)
     return res
 
 

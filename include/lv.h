@@ -65,11 +65,23 @@ typedef enum {
     LV_ERR_CANCELLED = 5     /* a server request cancelled before it ran */
 } lv_status;
 
-/* Storage type of feature maps / diffusion signals.  Arithmetic is FP32. */
+/* Storage type of feature maps / diffusion signals.  Arithmetic is FP32.
+ * The _PX8 types are feature maps (uplift inputs only) of the same element
+ * types in the pixel-block layout that lv_encode_map writes: element
+ * (y, x, c) of a W-pixel-wide map whose pixels hold ld channels (ld = D
+ * unless a channel slice of a wider map is read) is at
+ * ((y ceil(W/8) + floor(x/8)) ld + c) 8 + (x mod 8), pixels past W are 0.
+ * The 8 pixels of one channel that an 8-pixel row of a tile quadrant needs
+ * are then contiguous: one 16-byte read per matrix-product operand for
+ * BF16 (the blend, Sec. 3.2).  Maps must be aligned to their 8-pixel
+ * blocks (32, 16 or 8 bytes). */
 typedef enum {
     LV_F32 = 0,
     LV_BF16 = 1,       /* bfloat16, round-to-nearest-even                     */
-    LV_FP8_E4M3 = 2    /* OCP E4M3FN with a per-(view, channel) FP32 scale     */
+    LV_FP8_E4M3 = 2,   /* OCP E4M3FN with a per-(view, channel) FP32 scale     */
+    LV_F32_PX8 = 3,
+    LV_BF16_PX8 = 4,
+    LV_FP8_E4M3_PX8 = 5
 } lv_dtype;
 
 /* Pinhole camera, 80 bytes. */
@@ -279,6 +291,16 @@ lv_status lv_profile_stop(int64_t* launches, double* total_ms, double* per_launc
  * of x / scale.  LV_F32 copies. */
 lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,
                     float* scales, void* stream);
+/* Encode one FP32 map src [H][W][D] (device, HWC) into dst (device) in
+ * `dtype`: the element types and FP8 scales of lv_encode, in the HWC layout
+ * (then the same as lv_encode with pixels = H W) or in the pixel-block
+ * layout of the _PX8 types (dst then holds H ceil(W/8) D 8 elements, the
+ * pixels past W zero, and must be aligned to 16 bytes (8 for FP8)).  The
+ * blend reads a pixel-block map with one vector load per 8 pixels of a
+ * channel instead of eight element loads.  Same errors as lv_encode, plus
+ * H or W outside [0, 16384]. */
+lv_status lv_encode_map(const float* src, int32_t H, int32_t W, int32_t D, lv_dtype dtype, void* dst,
+                        float* scales, void* stream);
 
 /* lv_encode without any device allocation, for callers that cannot allocate:
  * code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -13,12 +13,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblv.so")
 
 LV_F32, LV_BF16, LV_FP8_E4M3 = 0, 1, 2
+# the same element types in the pixel-block layout of lv_encode_map
+LV_F32_PX8, LV_BF16_PX8, LV_FP8_E4M3_PX8 = 3, 4, 5
 LV_ERR_CANCELLED = 5
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 LV_ACCUM_COUNTS = 1
 LV_GRAPH_SPATIAL_COSINE, LV_GRAPH_FEATURE_RBF = 0, 1
-_DTYPES = {"f32": LV_F32, "bf16": LV_BF16, "fp8": LV_FP8_E4M3}
+_DTYPES = {"f32": LV_F32, "bf16": LV_BF16, "fp8": LV_FP8_E4M3,
+           "f32_px8": LV_F32_PX8, "bf16_px8": LV_BF16_PX8, "fp8_px8": LV_FP8_E4M3_PX8}
 
 
 class LvError(RuntimeError):
@@ -122,6 +125,7 @@ def lib():
             "lv_accum_destroy": ([P], i32),
             "lv_encode": ([P, i64, i32, i32, P, P, P], i32),
             "lv_encode_noalloc": ([P, i64, i32, i32, P, P, P], i32),
+            "lv_encode_map": ([P, i32, i32, i32, i32, P, P, P], i32),
             "lv_graph_create_csr": ([i64, i64, P, P, P, i32, P, ctypes.POINTER(P)], i32),
             "lv_graph_destroy": ([P], i32),
             "lv_diffuse": ([P, P, P, i32, i32, i32, P, P], i32),
@@ -155,6 +159,7 @@ def exported_symbols():
     return ["lv_last_error", "lv_version", "lv_scene_create", "lv_scene_destroy", "lv_scene_size",
             "lv_uplift", "lv_accum_create", "lv_accum_reset", "lv_uplift_accumulate",
             "lv_accum_finalize", "lv_accum_counts", "lv_accum_destroy", "lv_encode", "lv_encode_noalloc",
+            "lv_encode_map",
             "lv_graph_create_csr", "lv_graph_destroy", "lv_diffuse", "lv_debug_view",
             "lv_accum_stats", "lv_profile_start", "lv_profile_stop", "lv_uplift_sets",
             "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",
@@ -266,10 +271,20 @@ def _maps(maps, dtype):
     return _map_table(maps, dtype)
 
 
-def _map_table(maps, dtype):
+def _elem_torch(dtype):
+    """torch dtypes accepted for maps of an lv dtype (either layout)."""
     import torch
-    want = {LV_F32: (torch.float32,), LV_BF16: (torch.bfloat16,),
-            LV_FP8_E4M3: (torch.uint8, getattr(torch, "float8_e4m3fn", torch.uint8))}[dtype]
+    return {LV_F32: (torch.float32,), LV_BF16: (torch.bfloat16,),
+            LV_FP8_E4M3: (torch.uint8, getattr(torch, "float8_e4m3fn", torch.uint8))}[dtype % 3]
+
+
+def _map_channels(mp, dtype):
+    """D of a map: [H, W, D] (HWC) or [H, ceil(W/8), D, 8] (pixel blocks)."""
+    return int(mp.shape[2]) if dtype >= LV_F32_PX8 else int(mp.shape[-1])
+
+
+def _map_table(maps, dtype):
+    want = _elem_torch(dtype)
     tab = (ctypes.c_void_p * max(1, len(maps)))()
     for i, mp in enumerate(maps):
         if not (mp.is_cuda and mp.is_contiguous() and mp.dtype in want):
@@ -321,7 +336,7 @@ class Scene:
         """Eq. (3): returns (f [n,D] f32, beta [n] f32)."""
         import torch
         dt = _DTYPES[dtype]
-        D = maps[0].shape[-1] if maps else (out.shape[1] if out is not None else 1)
+        D = _map_channels(maps[0], dt) if maps else (out.shape[1] if out is not None else 1)
         if out is None:
             out = torch.empty((self.n, D), device="cuda", dtype=torch.float32)
         if wsum is None:
@@ -355,7 +370,7 @@ class Scene:
         keep, res = [], []
         for k, st in enumerate(sets):
             maps, scales = st if isinstance(st, tuple) else (st, None)
-            D = maps[0].shape[-1]
+            D = _map_channels(maps[0], dt)
             f, b = outs[k] if outs is not None else (
                 torch.empty((self.n, D), device="cuda", dtype=torch.float32),
                 torch.empty((self.n,), device="cuda", dtype=torch.float32))
@@ -480,19 +495,24 @@ def _slice_table(maps, dtype, D):
     not take that view), channels contiguous, pixels `stride` elements apart
     (a channel slice [..., :D] of a wider map is accepted).  Returns (table,
     stride)."""
-    import torch
-    want = {LV_F32: (torch.float32,), LV_BF16: (torch.bfloat16,),
-            LV_FP8_E4M3: (torch.uint8, getattr(torch, "float8_e4m3fn", torch.uint8))}[dtype]
+    want = _elem_torch(dtype)
+    px8 = dtype >= LV_F32_PX8
     tab = (ctypes.c_void_p * max(1, len(maps)))()
     stride = None
     for i, mp in enumerate(maps):
         if mp is None:
             tab[i] = None
             continue
-        ok = mp.is_cuda and mp.dtype in want and mp.dim() == 3 and mp.shape[2] == D
-        if ok and mp.is_contiguous():
-            px = D
+        if px8:  # [H, ceil(W/8), D, 8], or a channel slice [..., :D, :] of a wider map
+            ok = mp.is_cuda and mp.dtype in want and mp.dim() == 4 and mp.shape[2] == D and mp.shape[3] == 8
+            st = mp.stride() if ok else (0, 0, 0, 0)
+            px = st[1] // 8 if ok else 0
+            ok = ok and st[3] == 1 and (st[2] == 8 or D == 1) and st[1] == 8 * px and px >= D \
+                and st[0] == st[1] * mp.shape[1]
+        elif mp.is_cuda and mp.dtype in want and mp.dim() == 3 and mp.shape[2] == D and mp.is_contiguous():
+            ok, px = True, D
         else:  # a channel slice: channels adjacent, rows of W pixels
+            ok = mp.is_cuda and mp.dtype in want and mp.dim() == 3 and mp.shape[2] == D
             st = mp.stride() if ok else (0, 0, 0)
             px = st[1]
             ok = ok and (st[2] == 1 or D == 1) and px >= D and st[0] == px * mp.shape[1]
@@ -535,12 +555,24 @@ def profile_stop(capacity=4096):
 
 
 def encode(src, dtype):
-    """Encode an FP32 map [..., D] to 'bf16' or 'fp8' (+ per-channel scales)."""
+    """Encode an FP32 map [..., D] to 'bf16' or 'fp8' (+ per-channel scales);
+    the '_px8' types take one map [H, W, D] and return it in the pixel-block
+    layout, shape [H, ceil(W/8), D, 8]."""
     import torch
     _dev_f32(src)
     D = src.shape[-1]
     pixels = src.numel() // D
     dt = _DTYPES[dtype]
+    if dt >= LV_F32_PX8:
+        if src.dim() != 3:
+            raise LvError("pixel-block encoding takes one map [H, W, D]")
+        H, W = src.shape[0], src.shape[1]
+        el = _elem_torch(dt)
+        dst = torch.empty((H, (W + 7) // 8, D, 8), device="cuda",
+                          dtype=torch.uint8 if el[0] == torch.uint8 else el[0])
+        scales = torch.empty((D,), device="cuda", dtype=torch.float32) if dt == LV_FP8_E4M3_PX8 else None
+        _check(lib().lv_encode_map(_ptr(src), H, W, D, dt, _ptr(dst), _ptr(scales), _stream()))
+        return dst, scales
     if dt == LV_BF16:
         dst = torch.empty(src.shape, device="cuda", dtype=torch.bfloat16)
         scales = None

@@ -359,13 +359,18 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
 
 lv_status check_maps(const void* const* maps, int32_t m, lv_dtype dtype, const float* scales,
                      bool allow_null = false) {
-  if (dtype != LV_F32 && dtype != LV_BF16 && dtype != LV_FP8_E4M3)
-    return fail(LV_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+  if (!map_format_valid(dtype)) return fail(LV_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
   if (m > 0 && !maps) return fail(LV_ERR_INVALID_ARG, "maps is NULL");
   for (int v = 0; v < m && !allow_null; v++)
     if (!maps[v]) return fail(LV_ERR_INVALID_ARG, "maps[%d] is NULL", v);
-  if (dtype == LV_FP8_E4M3 && m > 0 && !scales)
+  if (map_elem(dtype) == LV_FP8_E4M3 && m > 0 && !scales)
     return fail(LV_ERR_INVALID_ARG, "FP8 maps need scales");
+  if (map_px8(dtype)) {  // the blocks are read whole
+    const uintptr_t align = map_elem(dtype) == LV_F32 ? 16 : map_elem(dtype) == LV_BF16 ? 16 : 8;
+    for (int v = 0; v < m; v++)
+      if (maps[v] && (uintptr_t)maps[v] % align)
+        return fail(LV_ERR_INVALID_ARG, "maps[%d] is not %d-byte aligned", v, (int)align);
+  }
   return LV_OK;
 }
 
@@ -1033,20 +1038,39 @@ lv_status lv_uplift(lv_scene* sc, const lv_camera* cams, int32_t m, const void* 
   return lv_uplift_sets(sc, cams, m, &set, 1, dtype, stream);
 }
 
-lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,
-                    float* scales, void* stream) {
+namespace {
+// pixels = H W; W only matters for the pixel-block formats
+lv_status encode_impl(const float* src, int64_t pixels, int32_t W, int32_t D, lv_dtype dtype, void* dst,
+                      float* scales, void* stream) {
   if (pixels < 0 || D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "bad size");
+  if (!map_format_valid(dtype)) return fail(LV_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
   if (pixels > 0 && (!src || !dst)) return fail(LV_ERR_INVALID_ARG, "null buffer");
-  if (dtype == LV_FP8_E4M3 && !scales) return fail(LV_ERR_INVALID_ARG, "FP8 needs scales");
-  if (dtype != LV_F32 && dtype != LV_BF16 && dtype != LV_FP8_E4M3)
-    return fail(LV_ERR_INVALID_ARG, "unknown dtype");
+  const lv_dtype el = map_elem(dtype);
+  if (el == LV_FP8_E4M3 && !scales) return fail(LV_ERR_INVALID_ARG, "FP8 needs scales");
+  if (map_px8(dtype) && (uintptr_t)dst % (el == LV_FP8_E4M3 ? 8 : 16))
+    return fail(LV_ERR_INVALID_ARG, "dst is not aligned to the 8-pixel blocks");
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* tmp = nullptr;  // per-channel absmax (FP8), stream-ordered scratch
-  if (dtype == LV_FP8_E4M3) HIP_TRY(dev_alloc(&tmp, 4 * (size_t)D, s, true));
-  const hipError_t e = launch_encode(src, pixels, D, dtype, dst, scales, static_cast<float*>(tmp), s);
+  if (el == LV_FP8_E4M3) HIP_TRY(dev_alloc(&tmp, 4 * (size_t)D, s, true));
+  const hipError_t e = launch_encode(src, pixels, D, dtype, dst, scales, static_cast<float*>(tmp), s, W);
   dev_free(tmp, 4 * (size_t)D, s, true);
   HIP_TRY(e);
   return LV_OK;
+}
+}  // namespace
+
+lv_status lv_encode(const float* src, int64_t pixels, int32_t D, lv_dtype dtype, void* dst,
+                    float* scales, void* stream) {
+  if (map_px8(dtype))
+    return fail(LV_ERR_INVALID_ARG, "pixel-block formats need the image width: lv_encode_map");
+  return encode_impl(src, pixels, 0, D, dtype, dst, scales, stream);
+}
+
+lv_status lv_encode_map(const float* src, int32_t H, int32_t W, int32_t D, lv_dtype dtype, void* dst,
+                        float* scales, void* stream) {
+  if (H < 0 || W < 0 || H > 16384 || W > 16384)
+    return fail(LV_ERR_INVALID_ARG, "map size %dx%d out of [0, 16384]", W, H);
+  return encode_impl(src, (int64_t)H * W, W, D, dtype, dst, scales, stream);
 }
 
 lv_status lv_graph_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,

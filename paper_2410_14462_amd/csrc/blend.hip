@@ -168,7 +168,7 @@ __device__ __forceinline__ uint64_t step_records(const Rec* __restrict__ vrec,
 __device__ __forceinline__ float walk_rec(const float4& a, const float4& b, Walk& s, bool& take) {
   const float dx = s.pxo - a.x, dy = s.pyo - a.y;
   const float u = __builtin_fmaf(a.w, dy, a.z * dx), w = b.x * dy;
-  const float al = fminf(kAlphaMax, b.y * exp32_clamped(-__builtin_fmaf(u, u, w * w)));
+  const float al = fminf(kAlphaMax, b.y * exp_neg(-__builtin_fmaf(u, u, w * w)));
   const bool ok = s.alive && al >= kAlphaMin;
   const float Tn = s.T * (1.0f - al);
   const bool stop = ok && Tn < kTEps;
@@ -199,6 +199,9 @@ __device__ __forceinline__ float walk_rec(const float4& a, const float4& b, Walk
 // [l % 32] in accumulator r.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWtPitch = 68;  // LDS row pitch (floats) of the transposed weights
 
@@ -284,25 +287,92 @@ __device__ __forceinline__ bool group_lanes(const ChanGroup& grp, const SetDesc*
   return active;
 }
 
-// B operands of K-step t (pixel rows 2t, 2t + 1) for both blocks: F[pixel (row
-// 2t + l / 32, column i)][channel], split into hi and lo.  Only for a group
-// that takes the view (group_lanes true: L.src holds a map for every lane).
-template <lv_dtype DT>
-__device__ __forceinline__ void stage_fragment(const GroupLanes& L, const Quad& q, int lane, int t,
-                                               int b, bf16x8& fh, bf16x8& fl) {
-  // every lane loads (a safe index where it has nothing to load), then selects:
-  // no branch around the loads, so they are all in flight together
-  float v[8];
-  const int gy = q.qy + 2 * t + (lane >> 5);
+// Element (y, x, channel c) of a map with pixel stride ld: HWC at
+// (y W + x) ld + c; pixel-block layout (PX8) at ((y W8 + x / 8) ld + c) 8 +
+// x % 8 with W8 = ceil(W / 8) (pixels past W are zeros).
+template <bool PX>
+__device__ __forceinline__ int64_t map_index(int y, int x, int W, int ld, int64_t c) {
+  if constexpr (PX)
+    return (((int64_t)y * ((W + 7) >> 3) + (x >> 3)) * ld + c) * 8 + (x & 7);
+  else
+    return ((int64_t)y * W + x) * ld + c;
+}
+
+// OCP E4M3FN code -> the same value in BF16 bits (exact: 3 mantissa bits).
+// Normal codes move their exponent and mantissa; subnormals m 2^-9 go
+// through an exact FP32 product.
+__device__ __forceinline__ uint32_t e4m3_bf16(uint32_t b) {
+  const uint32_t e = (b >> 3) & 0xFu, m = b & 7u;
+  const uint32_t nrm = ((e + 120u) << 7) | (m << 4);
+  const uint32_t sub = __float_as_uint((float)m * 0x1.0p-9f) >> 16;
+  return (e ? nrm : sub) | ((b & 0x80u) << 8);
+}
+
+__device__ __forceinline__ bf16x8 bf16x8_of(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+  return __builtin_bit_cast(bf16x8, (u32x4{w0, w1, w2, w3}));
+}
+
+// The B operand of one K-step for block b: this lane's channel at the 8
+// pixels (gx0 .. gx0 + 7, gx0 a multiple of 8) of pixel row gy, as BF16
+// (hi; lo = the FP32 remainder, FP32 maps only).  BF16 maps are exact in hi;
+// FP8 codes too (their per-channel scale multiplies the products, see
+// batch_scatter).  Zeros outside the image and for lanes without a channel.
+// Every lane loads (a safe index where it has nothing to load), then
+// selects: no branch around the loads, so they are all in flight together.
+template <lv_dtype DT, bool PX>
+__device__ __forceinline__ void load_row8(const GroupLanes& L, int b, int gy, int gx0,
+                                          const ViewGeom& g, bf16x8& fh, bf16x8& fl) {
+  const bool okr = L.own[b] && gy < g.H;
+  if constexpr (PX) {
+    // one block of 8 pixels of one channel: 32, 16 or 8 contiguous bytes
+    const int64_t blk = okr ? ((int64_t)gy * ((g.W + 7) >> 3) + (gx0 >> 3)) * L.srcld[b] + L.srcc[b] : 0;
+    if constexpr (DT == LV_BF16) {
+      const u32x4 q = gptr(static_cast<const u32x4*>(L.src[b]))[blk];
+      fh = okr ? bf16x8_of(q.x, q.y, q.z, q.w) : bf16x8_of(0u, 0u, 0u, 0u);
+    } else if constexpr (DT == LV_FP8_E4M3) {
+      const u32x2 q = gptr(static_cast<const u32x2*>(L.src[b]))[blk];
+      const uint32_t w[2] = {okr ? q.x : 0u, okr ? q.y : 0u};
+      uint32_t h[4];
 #pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const int gx = q.qx + i;
-    const bool ok = L.own[b] && gx < q.g.W && gy < q.g.H;
-    const int64_t idx = ok ? ((int64_t)gy * q.g.W + gx) * L.srcld[b] + L.srcc[b] : 0;
-    const float x = load_feature<DT>(L.src[b], idx, L.srcsc[b]);
-    v[i] = ok ? x : 0.0f;
+      for (int k = 0; k < 4; k++) {
+        const uint32_t x = w[k >> 1] >> (16 * (k & 1));
+        h[k] = e4m3_bf16(x & 0xFFu) | (e4m3_bf16((x >> 8) & 0xFFu) << 16);
+      }
+      fh = bf16x8_of(h[0], h[1], h[2], h[3]);
+    } else {
+      const f32x4 qa = gptr(static_cast<const f32x4*>(L.src[b]))[2 * blk];
+      const f32x4 qb = gptr(static_cast<const f32x4*>(L.src[b]))[2 * blk + 1];
+      const float v[8] = {okr ? qa.x : 0.0f, okr ? qa.y : 0.0f, okr ? qa.z : 0.0f, okr ? qa.w : 0.0f,
+                          okr ? qb.x : 0.0f, okr ? qb.y : 0.0f, okr ? qb.z : 0.0f, okr ? qb.w : 0.0f};
+      split8(v, fh, fl);
+    }
+  } else {
+    if constexpr (DT == LV_F32) {
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const bool ok = okr && gx0 + i < g.W;
+        const int64_t idx = ok ? ((int64_t)gy * g.W + gx0 + i) * L.srcld[b] + L.srcc[b] : 0;
+        const float x = gptr(static_cast<const float*>(L.src[b]))[idx];
+        v[i] = ok ? x : 0.0f;
+      }
+      split8(v, fh, fl);
+    } else {
+      uint32_t h[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const bool ok = okr && gx0 + i < g.W;
+        const int64_t idx = ok ? ((int64_t)gy * g.W + gx0 + i) * L.srcld[b] + L.srcc[b] : 0;
+        uint32_t x;
+        if constexpr (DT == LV_BF16)
+          x = gptr(static_cast<const uint16_t*>(L.src[b]))[idx];
+        else
+          x = e4m3_bf16(gptr(static_cast<const uint8_t*>(L.src[b]))[idx]);
+        h[i] = ok ? x : 0u;
+      }
+      fh = bf16x8_of(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+    }
   }
-  split8(v, fh, fl);
 }
 
 // U_b = W_b F for a batch of queued rows, one or two blocks of 32 channels.
@@ -342,10 +412,16 @@ __device__ __forceinline__ void batch_mfma(bool two, uint32_t rows, const float*
 }
 
 // One atomic per (queued Gaussian, channel): D row m of the batch is ring
-// row m, whose Gaussian id lane m holds.
+// row m, whose Gaussian id lane m holds.  FP8 maps: the products were formed
+// on the codes, the channel's scale multiplies them here.
+template <lv_dtype DT>
 __device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int count,
-                                              uint32_t ring_gid, int lane, const f32x16& acc0,
-                                              const f32x16& acc1) {
+                                              uint32_t ring_gid, int lane, f32x16 acc0,
+                                              f32x16 acc1) {
+  if constexpr (DT == LV_FP8_E4M3) {
+    acc0 *= L.srcsc[0];
+    acc1 *= L.srcsc[1];
+  }
   const bool upper = lane >= 32;
 #pragma unroll
   for (int r = 0; r < 16; r++) {
@@ -372,13 +448,13 @@ constexpr int wide_waves() {
   return DT == LV_BF16 ? 4 : 3;
 }
 
-template <lv_dtype DT>
+template <lv_dtype DT, bool PX>
 __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
     const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
   constexpr int G = kChunk;
-  constexpr bool kSplitF = DT != LV_BF16;  // BF16 maps are exact in one BF16 operand
+  constexpr bool kSplitF = DT == LV_F32;  // BF16 maps and FP8 codes are exact in one BF16 operand
   __shared__ __align__(16) float Wt[32 * kWtPitch];  // queued Gaussians: [row][pixel]
   __shared__ float4 Rs[kChunk][2];                   // the step's records
   Quad q;
@@ -417,7 +493,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
       const int c = last.tc[t];
       float sc = 1.0f;
       if constexpr (DT == LV_FP8_E4M3) sc = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * sd.D + c];
-      const int64_t idx = inside ? ((int64_t)py * q.g.W + px) * sd.stride + c : 0;
+      const int64_t idx = inside ? map_index<PX>(py, px, q.g.W, sd.stride, c) : 0;
       const float x = load_feature<DT>(map_of(sd, q.v), idx, sc);  // no branch around the load
       ft = inside ? x : 0.0f;
       tout[t] = sd.U + c;
@@ -440,7 +516,8 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
 #pragma unroll
       for (int b = 0; b < 2; b++)
 #pragma unroll
-        for (int t = 0; t < 4; t++) stage_fragment<DT>(L1, q, lane, t, b, fh[b][t], fl[b][t]);
+        for (int t = 0; t < 4; t++)
+          load_row8<DT, PX>(L1, b, q.qy + 2 * t + (lane >> 5), q.qx, q.g, fh[b][t], fl[b][t]);
     }
     has_main = has_main && takes && __ballot(L1.outp[0] != nullptr || L1.outp[1] != nullptr) != 0ull;
   }
@@ -468,7 +545,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
     if (has_main) {
       f32x16 acc0 = {}, acc1 = {};
       batch_mfma<kSplitF>(two1, rows, wrow, fh, fl, acc0, acc1);
-      batch_scatter(L1, two1, count, ring_gid, lane, acc0, acc1);
+      batch_scatter<DT>(L1, two1, count, ring_gid, lane, acc0, acc1);
     }
     if (bsets || any_tail) {
       // lane l: row l % 32, pixels [32 (l / 32), 32 (l / 32) + 32)
@@ -537,7 +614,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
       // with a contribution
       const float dx = s.pxo - ra.x, dy = s.pyo - ra.y;
       const float u = __builtin_fmaf(ra.w, dy, ra.z * dx), w = rb.x * dy;
-      const float al = fminf(kAlphaMax, rb.y * exp32_clamped(-__builtin_fmaf(u, u, w * w)));
+      const float al = fminf(kAlphaMax, rb.y * exp_neg(-__builtin_fmaf(u, u, w * w)));
       // the next record into the same registers (no copies between hits)
       ra = Rs[jn][0];
       rb = Rs[jn][1];
@@ -627,7 +704,7 @@ __device__ __forceinline__ float blend_at(const float4& a, const float4& b, floa
                                           float& T, bool& alive, bool& take) {
   const float dx = pxo - a.x, dy = pyo - a.y;
   const float u = __builtin_fmaf(a.w, dy, a.z * dx), w = b.x * dy;
-  const float al = fminf(kAlphaMax, b.y * exp32_clamped(-__builtin_fmaf(u, u, w * w)));
+  const float al = fminf(kAlphaMax, b.y * exp_neg(-__builtin_fmaf(u, u, w * w)));
   const bool ok = alive && al >= kAlphaMin;
   const float Tn = T * (1.0f - al);
   const bool stop = ok && Tn < kTEps;
@@ -636,24 +713,6 @@ __device__ __forceinline__ float blend_at(const float4& a, const float4& b, floa
   T = take ? Tn : T;
   alive = alive && !stop;
   return wj;
-}
-
-// B operands of K-step t of a half tile (see above) for block b.
-template <lv_dtype DT>
-__device__ __forceinline__ void stage_fragment_pair(const GroupLanes& L, const Pair& q, int lane,
-                                                    int t, int b, bf16x8& fh, bf16x8& fl) {
-  float v[8];
-  const int gy = q.qy + 2 * (t & 3) + (lane >> 5);
-  const int gx0 = q.qx + 8 * (t >> 2);
-#pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const int gx = gx0 + i;
-    const bool ok = L.own[b] && gx < q.g.W && gy < q.g.H;
-    const int64_t idx = ok ? ((int64_t)gy * q.g.W + gx) * L.srcld[b] + L.srcc[b] : 0;
-    const float x = load_feature<DT>(L.src[b], idx, L.srcsc[b]);
-    v[i] = ok ? x : 0.0f;
-  }
-  split8(v, fh, fl);
 }
 
 // group_lanes for a half tile (only the view matters)
@@ -665,13 +724,13 @@ __device__ __forceinline__ bool group_lanes_pair(const ChanGroup& grp, const Set
   return group_lanes<DT>(grp, sets, q, lane, L);
 }
 
-template <lv_dtype DT>
+template <lv_dtype DT, bool PX>
 __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews,
     const SetDesc* __restrict__ sets, const ChanGroup* __restrict__ groups, int ngroups) {
   constexpr int G = kChunk;
-  constexpr bool kSplitF = DT != LV_BF16;
+  constexpr bool kSplitF = DT == LV_F32;
   __shared__ __align__(16) float Wt[32 * kPairPitch];  // queued Gaussians: [row][128 pixels]
   __shared__ float4 Rs[kChunk][2];                     // the step's records
   __shared__ __align__(16) float Ft[kMaxTail * 128];   // tail channels per pixel
@@ -719,8 +778,8 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
       const int c = last.tc[t];
       float sc = 1.0f;
       if constexpr (DT == LV_FP8_E4M3) sc = gptr(sd.scales)[(int64_t)(sd.view_base + q.v) * sd.D + c];
-      const int64_t i0 = in0 ? ((int64_t)py * q.g.W + q.qx + (lane & 7)) * sd.stride + c : 0;
-      const int64_t i1 = in1 ? ((int64_t)py * q.g.W + q.qx + 8 + (lane & 7)) * sd.stride + c : 0;
+      const int64_t i0 = in0 ? map_index<PX>(py, q.qx + (lane & 7), q.g.W, sd.stride, c) : 0;
+      const int64_t i1 = in1 ? map_index<PX>(py, q.qx + 8 + (lane & 7), q.g.W, sd.stride, c) : 0;
       const float x0 = load_feature<DT>(map_of(sd, q.v), i0, sc);  // no branch around the loads
       const float x1 = load_feature<DT>(map_of(sd, q.v), i1, sc);
       ft0 = in0 ? x0 : 0.0f;
@@ -757,8 +816,9 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
         for (int t = 0; t < 8; t++) {
           if ((rows >> (2 * t)) & 3u) {
             bf16x8 h0, l0, h1, l1, ah, al;
-            stage_fragment_pair<DT>(L, q, lane, t, 0, h0, l0);
-            stage_fragment_pair<DT>(L, q, lane, t, 1, h1, l1);
+            const int gy = q.qy + 2 * (t & 3) + (lane >> 5), gx0 = q.qx + 8 * (t >> 2);
+            load_row8<DT, PX>(L, 0, gy, gx0, q.g, h0, l0);
+            load_row8<DT, PX>(L, 1, gy, gx0, q.g, h1, l1);
             load_split_w(wrow + 16 * t, ah, al);
             acc0 = mfma(ah, h0, acc0);
             acc1 = mfma(ah, h1, acc1);
@@ -775,7 +835,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
         for (int t = 0; t < 8; t++) {
           if ((rows >> (2 * t)) & 3u) {
             bf16x8 h0, l0, ah, al;
-            stage_fragment_pair<DT>(L, q, lane, t, 0, h0, l0);
+            load_row8<DT, PX>(L, 0, q.qy + 2 * (t & 3) + (lane >> 5), q.qx + 8 * (t >> 2), q.g, h0, l0);
             load_split_w(wrow + 16 * t, ah, al);
             acc0 = mfma(ah, h0, acc0);
             acc0 = mfma(al, h0, acc0);
@@ -783,7 +843,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
           }
         }
       }
-      batch_scatter(L, two, count, ring_gid, lane, acc0, acc1);
+      batch_scatter<DT>(L, two, count, ring_gid, lane, acc0, acc1);
     }
     if (bsets || any_tail) {
       // lane l: row l % 32, the pixels of quadrant l / 32
@@ -897,7 +957,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
   }
 }
 
-template <lv_dtype DT>
+template <lv_dtype DT, bool PX>
 hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   // one group: one wave per (view, quadrant, group); several: one wave per
   // (view, quadrant) for all groups, sharing the walk
@@ -907,11 +967,11 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   if (multi) {
     // one wave per half tile: two per tile, whole rounds of 8 XCDs
     const int64_t pblocks = ((int64_t)a.tiles_stride * m + 7) / 8 * 16;
-    hipLaunchKernelGGL((blend_pair_kernel<DT>), dim3((unsigned)pblocks), dim3(64), 0, s, a.rec,
+    hipLaunchKernelGGL((blend_pair_kernel<DT, PX>), dim3((unsigned)pblocks), dim3(64), 0, s, a.rec,
                        a.ids, a.ranges, a.geom, a.n, a.tiles_stride, m, a.sets, a.groups,
                        a.ngroups);
   } else
-    hipLaunchKernelGGL((blend_wide_kernel<DT>), dim3((unsigned)blocks), dim3(64), 0, s,
+    hipLaunchKernelGGL((blend_wide_kernel<DT, PX>), dim3((unsigned)blocks), dim3(64), 0, s,
                        a.rec, a.ids, a.ranges, a.geom, a.n, a.tiles_stride, m, a.sets, a.groups,
                        a.ngroups);
   return hipGetLastError();
@@ -1076,9 +1136,12 @@ hipError_t launch_class_add(const beta_t* beta, const uint32_t* counts, const Cl
 hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s) {
   if (m == 0 || a.tiles_stride == 0) return hipSuccess;
   switch (dtype) {
-    case LV_F32: return launch_blend_t<LV_F32>(a, m, s);
-    case LV_BF16: return launch_blend_t<LV_BF16>(a, m, s);
-    case LV_FP8_E4M3: return launch_blend_t<LV_FP8_E4M3>(a, m, s);
+    case LV_F32: return launch_blend_t<LV_F32, false>(a, m, s);
+    case LV_BF16: return launch_blend_t<LV_BF16, false>(a, m, s);
+    case LV_FP8_E4M3: return launch_blend_t<LV_FP8_E4M3, false>(a, m, s);
+    case LV_F32_PX8: return launch_blend_t<LV_F32, true>(a, m, s);
+    case LV_BF16_PX8: return launch_blend_t<LV_BF16, true>(a, m, s);
+    case LV_FP8_E4M3_PX8: return launch_blend_t<LV_FP8_E4M3, true>(a, m, s);
   }
   return hipErrorInvalidValue;
 }

@@ -125,12 +125,77 @@ __global__ __launch_bounds__(256) void encode_fp8_vec_kernel(const float4* __res
   }
 }
 
+// Pixel-block layout: thread k writes element (block k / D, channel k % D):
+// the 8 pixels of its block of an image row, read from the HWC source (for
+// each pixel, consecutive threads read consecutive channels) and written as
+// one contiguous run (consecutive threads, consecutive runs).  Pixels past W
+// are zeros.  E: element type; scales for FP8.
+template <lv_dtype E>
+__global__ __launch_bounds__(256) void encode_px8_kernel(const float* __restrict__ src, int W, int D,
+                                                         int64_t runs,
+                                                         const float* __restrict__ scales,
+                                                         void* __restrict__ dst) {
+  const int W8 = (W + 7) >> 3;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < runs;
+       k += (int64_t)gridDim.x * 256) {
+    const int c = (int)(k % D);
+    const int64_t blk = k / D;
+    const int64_t y = blk / W8;
+    const int x0 = (int)(blk - y * W8) * 8;
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = x0 + i < W ? src[(y * W + x0 + i) * D + c] : 0.0f;
+    if constexpr (E == LV_F32) {
+      float4* o = static_cast<float4*>(dst) + 2 * k;
+      o[0] = make_float4(v[0], v[1], v[2], v[3]);
+      o[1] = make_float4(v[4], v[5], v[6], v[7]);
+    } else if constexpr (E == LV_BF16) {
+      uint4 o;
+      o.x = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+      o.y = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+      o.z = (uint32_t)to_bf16(v[4]) | ((uint32_t)to_bf16(v[5]) << 16);
+      o.w = (uint32_t)to_bf16(v[6]) | ((uint32_t)to_bf16(v[7]) << 16);
+      static_cast<uint4*>(dst)[k] = o;
+    } else {
+      const float sc = scales[c];
+      uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        lo |= (uint32_t)to_e4m3(v[i] / sc) << (8 * i);
+        hi |= (uint32_t)to_e4m3(v[4 + i] / sc) << (8 * i);
+      }
+      static_cast<uint2*>(dst)[k] = make_uint2(lo, hi);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_encode(const float* src, int64_t pixels, int D, lv_dtype dtype, void* dst,
-                         float* scales, float* tmp_absmax, hipStream_t s) {
+                         float* scales, float* tmp_absmax, hipStream_t s, int W) {
   int64_t total = pixels * (int64_t)D;
   if (total == 0) return hipSuccess;
+  if (map_px8(dtype)) {
+    const lv_dtype el = map_elem(dtype);
+    if (el == LV_FP8_E4M3) {
+      uint32_t* amax = reinterpret_cast<uint32_t*>(tmp_absmax);
+      hipLaunchKernelGGL(zero_kernel, dim3((D + 255) / 256), dim3(256), 0, s, amax, D);
+      int rows = 512;
+      hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)((pixels + rows - 1) / rows), (D + 63) / 64),
+                         dim3(256), 0, s, src, pixels, D, rows, amax);
+      hipLaunchKernelGGL(scale_kernel, dim3((D + 255) / 256), dim3(256), 0, s, amax, D, scales);
+    }
+    const int64_t runs = pixels / W * ((W + 7) / 8) * (int64_t)D;
+    const unsigned nb = (unsigned)std::min<int64_t>((runs + 255) / 256, 65536);
+    if (el == LV_F32)
+      hipLaunchKernelGGL(encode_px8_kernel<LV_F32>, dim3(nb), dim3(256), 0, s, src, W, D, runs, scales, dst);
+    else if (el == LV_BF16)
+      hipLaunchKernelGGL(encode_px8_kernel<LV_BF16>, dim3(nb), dim3(256), 0, s, src, W, D, runs, scales, dst);
+    else
+      hipLaunchKernelGGL(encode_px8_kernel<LV_FP8_E4M3>, dim3(nb), dim3(256), 0, s, src, W, D, runs, scales,
+                         dst);
+    return hipGetLastError();
+  }
   if (dtype == LV_F32) {
     return hipMemcpyAsync(dst, src, (size_t)total * sizeof(float), hipMemcpyDeviceToDevice, s);
   }

@@ -46,32 +46,14 @@ struct Rec {
   float4 r0, r1;
 };
 
-// S32 exponential for x <= 0: Cody-Waite reduction to |r| <= ln2/2, degree-7
-// Taylor polynomial in Horner form with fmaf, scaling by 2^k; 0 below -80.
-// Branch-free: the polynomial runs on max(x, -80) and the result is selected.
-__device__ __forceinline__ float exp32_clamped(float x0);
-__device__ __forceinline__ float exp32(float x0) {
-  return x0 < -80.0f ? 0.0f : exp32_clamped(x0);
-}
-
-// The same without the final select: below -80 it returns exp32(-80), about
-// 1.8e-35.  Where the result only decides whether opacity * exp >= 1/255
-// (opacity <= 1), the two cannot differ in any decision.
-__device__ __forceinline__ float exp32_clamped(float x0) {
-  const float x = fmaxf(x0, -80.0f);
-  float kf = rintf(x * 0x1.715476p+0f);
-  float r = __builtin_fmaf(kf, -0x1.62e4p-1f, x);
-  r = __builtin_fmaf(kf, -0x1.7f7d1cp-20f, r);
-  float p = 0x1.a01a02p-13f;
-  p = __builtin_fmaf(p, r, 0x1.6c16c2p-10f);
-  p = __builtin_fmaf(p, r, 0x1.111112p-7f);
-  p = __builtin_fmaf(p, r, 0x1.555556p-5f);
-  p = __builtin_fmaf(p, r, 0x1.555556p-3f);
-  p = __builtin_fmaf(p, r, 0x1.0p-1f);
-  p = __builtin_fmaf(p, r, 1.0f);
-  p = __builtin_fmaf(p, r, 1.0f);
-  int k = (int)kf;
-  return p * __uint_as_float((uint32_t)(k + 127) << 23);
+// e^x for x <= 0 on the hardware base-2 exponential, 2^(x log2 e): the
+// product is rounded once (relative error of the result about |x| 2^-24)
+// and v_exp_f32 adds about one ulp, so alpha = opacity e^x is within 1e-6
+// (relative) of its exact value wherever it can reach 1/255 (x >= -6).
+// The skip and stop decisions therefore agree with the FP64 definition
+// except where its own margin is below that.
+__device__ __forceinline__ float exp_neg(float x) {
+  return __builtin_amdgcn_exp2f(x * 0x1.715476p+0f);
 }
 
 // Global-memory accesses through pointers held in structures: the compiler
@@ -271,8 +253,15 @@ hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n,
 hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,
                            float* wsum, float* usum, hipStream_t s);
 
+// Feature-map formats: valid uplift input, element type, pixel-block layout.
+inline bool map_format_valid(lv_dtype d) { return d >= LV_F32 && d <= LV_FP8_E4M3_PX8; }
+inline lv_dtype map_elem(lv_dtype d) { return d >= LV_F32_PX8 ? (lv_dtype)(d - LV_F32_PX8) : d; }
+inline bool map_px8(lv_dtype d) { return d >= LV_F32_PX8; }
+
+// Encode src [pixels][D] (HWC; pixels = H W) in format dtype; the pixel-block
+// formats need the image width W.
 hipError_t launch_encode(const float* src, int64_t pixels, int D, lv_dtype dtype, void* dst,
-                         float* scales, float* tmp_absmax, hipStream_t s);
+                         float* scales, float* tmp_absmax, hipStream_t s, int W = 0);
 
 // One merged pass of the uplift server (see serve.hip): set k takes maps[k]
 // (host array [m], NULL where the set lacks the view) and writes f and beta

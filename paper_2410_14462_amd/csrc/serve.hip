@@ -132,7 +132,7 @@ lv_status lv_server::run_pass(std::vector<ServeReq*>& reqs, hipStream_t s) {
     }
   }
   const int um = (int)ucams.size();
-  const bool fp8 = reqs[0]->dtype == LV_FP8_E4M3;
+  const bool fp8 = lv::map_elem(reqs[0]->dtype) == LV_FP8_E4M3;
   std::vector<void*> scl(nb, nullptr);
   std::vector<size_t> scl_bytes(nb, 0);
   lv_status st = LV_OK;
@@ -263,10 +263,11 @@ lv_status lv_server_submit(lv_server* srv, const lv_request* q) {
   const lv_status bad = LV_ERR_INVALID_ARG;
   if (!srv || !q || !q->scene) return lv::set_error(bad, "server, request or scene is NULL");
   if (q->D < 1 || q->D > 4096 || q->m < 0) return lv::set_error(bad, "D or m out of range");
-  if (q->dtype != LV_F32 && q->dtype != LV_BF16 && q->dtype != LV_FP8_E4M3)
+  if (!lv::map_format_valid(q->dtype))
     return lv::set_error(bad, "unknown dtype");
   if (q->m > 0 && (!q->cams || !q->maps)) return lv::set_error(bad, "cams or maps is NULL");
-  if (q->dtype == LV_FP8_E4M3 && q->m > 0 && !q->scales) return lv::set_error(bad, "FP8 maps need scales");
+  if (lv::map_elem(q->dtype) == LV_FP8_E4M3 && q->m > 0 && !q->scales)
+    return lv::set_error(bad, "FP8 maps need scales");
   if (q->stride != 0 && q->stride < q->D) return lv::set_error(bad, "pixel stride < D");
   const int64_t n = lv_scene_size(q->scene);
   if (n > 0 && !q->out_feat) return lv::set_error(bad, "out_feat is NULL");

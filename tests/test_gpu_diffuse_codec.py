@@ -222,3 +222,77 @@ def test_large_full_size_precision_sampled():
                  "fp8": 2.0 ** -4 * a + 2.0 ** -10 * smax + 1e-4 * a}[dtype]
         print(f"large {dtype} vs FP32 maps: max |df|/a {np.max(d / np.maximum(a, 1e-30)):.3e}")
         assert np.all(d <= bound)
+
+
+def px8_reference(a):
+    """[H, W, D] -> [H, ceil(W/8), D, 8] (pixels past W zero), on the CPU."""
+    H, W, D = a.shape
+    W8 = (W + 7) // 8
+    p = torch.zeros((H, W8 * 8, D), dtype=a.dtype)
+    p[:, :W] = a
+    return p.reshape(H, W8, 8, D).permute(0, 1, 3, 2).contiguous()
+
+
+@pytest.mark.parametrize("dtype", ["f32_px8", "bf16_px8", "fp8_px8"])
+def test_pixel_block_encode_bit_exact(dtype):
+    """lv_encode_map's pixel-block layout: the HWC encoding's values (BF16
+    round to nearest even, FP8 E4M3FN with per-channel absmax scales, FP32
+    copied) moved to [H][ceil(W/8)][D][8] with zero padding, bit for bit, on a
+    width that is not a multiple of 8."""
+    H, W, D = 13, 37, 20
+    x = torch.as_tensor(philox.normal(32, 0, H * W * D).reshape(H, W, D), device="cuda")
+    x[0, 0, :3] = torch.tensor([0.0, -0.0, 1e-40], device="cuda")
+    y, sc = lv.encode(x, dtype)
+    assert tuple(y.shape) == (H, (W + 7) // 8, D, 8)
+    if dtype == "f32_px8":
+        ref = px8_reference(x.cpu())
+        assert torch.equal(y.cpu().view(torch.int32), ref.view(torch.int32))
+    elif dtype == "bf16_px8":
+        ref = px8_reference(x.cpu().to(torch.bfloat16))
+        assert torch.equal(y.cpu().view(torch.int16), ref.view(torch.int16))
+    else:
+        hwc, sc_hwc = lv.encode(x.reshape(H * W, D), "fp8")
+        assert torch.equal(sc.cpu(), sc_hwc.cpu())
+        ref = px8_reference(hwc.reshape(H, W, D).cpu())
+        assert torch.equal(y.cpu(), ref)
+
+
+@pytest.mark.parametrize("D", [64, 130])
+@pytest.mark.parametrize("elem", ["f32", "bf16", "fp8"])
+def test_pixel_block_uplift_parity(elem, D):
+    """The uplift from pixel-block maps (one vector load per 8 pixels of a
+    channel) against the oracle on the decoded maps (counts exact, 1e-4), and
+    against the HWC maps of the same values; D = 64 runs the one-group
+    quadrant kernel, D = 130 the several-group half-tile kernel.  Ragged
+    image (97 x 83).  A channel slice of wider pixel-block maps too."""
+    sc = scenes.make_scene(15, 3000, -3.8, 0.5, 0.0, 1.0)
+    cams = [scenes.look_at(e, 97, 83, 60.0) for e in scenes.fibonacci_eyes(2, 4.0)]
+    gs = lv.Scene.from_arrays(sc)
+    Dw = D + 6  # the stored maps hold D + 6 channels; the uplift reads the first D
+    src = [torch.as_tensor(philox.normal(150 + D, v, 83 * 97 * Dw).reshape(83, 97, Dw), device="cuda")
+           for v in range(2)]
+    hwc = [lv.encode(m[..., :D].contiguous(), elem) for m in src]
+    px = [lv.encode(m, elem + "_px8") for m in src]
+    if elem == "fp8":
+        # the scales of the wider map's first D channels are those of the narrower map
+        assert all(torch.equal(a[1], b[1][:D]) for a, b in zip(hwc, px))
+        scales = torch.stack([e[1] for e in hwc]).contiguous()
+        dec = [e[0].view(torch.float8_e4m3fn).float() * e[1] for e in hwc]
+    else:
+        scales = None
+        dec = [e[0].float() for e in hwc]
+    ref = oracle.uplift(sc, cams, [d.cpu().numpy() for d in dec])
+    outs = {}
+    for name, maps, dt in (("hwc", [e[0] for e in hwc], elem),
+                           ("px8", [e[0][:, :, :D, :] for e in px], elem + "_px8")):
+        acc = lv.Accum(gs, D, counts=True)
+        lv.accumulate_sets(cams, [(acc, maps, scales)], dtype=dt)
+        f, b = acc.finalize()
+        torch.cuda.synchronize()
+        assert counts_match(acc.counts().cpu().numpy(), ref), name
+        e = feature_error(f.cpu().numpy(), ref)
+        print(f"px8 parity {elem} D={D} {name}: max err {e.max():.3e}", flush=True)
+        assert e.max() < 1e-4, name
+        assert beta_error(b.cpu().numpy(), ref).max() < 1e-4, name
+        outs[name] = f.cpu().numpy()
+    assert np.abs(outs["hwc"] - outs["px8"]).max() <= 1e-5 * max(1.0, np.abs(outs["hwc"]).max())
