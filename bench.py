@@ -126,131 +126,142 @@ def large_leg(lv, args):
 
     w = scenes.WORKLOADS["large"]
     n, m, H, W, D = w.n, w.m, w.height, w.width, w.D
-    log(f"bench: {w.name}: scene, rig, {m} maps x 3 storage formats")
+    log(f"bench: {w.name}: scene, rig")
     sc = scenes.scene_for(w)
     cams = scenes.cameras_for(w)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     means, scales, quats, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacity)
     legs = ["bf16"] + [x for x in args.legs.split(",") if x in ("f32", "fp8")]
-    # storage format of each leg (lv dtype): pixel blocks, or HWC (FP32: the maps as generated)
-    fmt = {k: (k + "_px8" if args.layout == "px8" else k) for k in ("bf16", "f32", "fp8")}
-    maps32, maps16, codes8, sc8 = [], [], [], []
-    for v in range(m):
-        f = scenes.feature_map(w, v, device="cuda")
-        maps16.append(lv.encode(f, fmt["bf16"])[0])
-        if "fp8" in legs:
-            c, s = lv.encode(f, fmt["fp8"])
-            codes8.append(c)
-            sc8.append(s)
-        if "f32" in legs:
-            maps32.append(lv.encode(f, fmt["f32"])[0] if args.layout == "px8" else f)
-        del f
-    scales8 = torch.stack(sc8).contiguous() if sc8 else None
-    torch.cuda.synchronize()
+    # storage format of each leg (lv dtype): the encoded legs in pixel blocks
+    # (or HWC), the FP32 leg the maps as generated (HWC: the faster FP32 path)
+    fmt = {k: (k + "_px8" if args.layout == "px8" else k) for k in ("bf16", "fp8")}
+    fmt["f32"] = "f32"
     rig = lv.Cameras(cams)
-    tabs = {"bf16": (lv.Maps(maps16, fmt["bf16"]), None)}
-    if "f32" in legs:
-        tabs["f32"] = (lv.Maps(maps32, fmt["f32"]), None)
-    if "fp8" in legs:
-        tabs["fp8"] = (lv.Maps(codes8, fmt["fp8"]), scales8)
     fout = torch.empty((n, D), device="cuda")
     bout = torch.empty((n,), device="cuda")
+    nv = args.oracle_views
 
-    def step(dt):
-        tab, s8 = tabs[dt]
-        s = lv.Scene(means, scales, quats, opac)
-        s.uplift(rig, tab, dtype=fmt[dt], scales=s8, out=fout, wsum=bout)
-        s.close()
-
-    # work statistics of the headline pass (untimed, with counters)
-    s = lv.Scene(means, scales, quats, opac)
-    acc = lv.Accum(s, D, counts=True)
-    acc.add(rig, tabs["bf16"][0], dtype=fmt["bf16"])
-    stats = acc.stats()
-    acc.close()
-    s.close()
-    log(f"bench: stats {stats}")
-
-    log(f"bench: headline (bf16): warmup {args.warmup}, timing {args.steps} steps")
-    for _ in range(args.warmup):
-        step("bf16")
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    lv.profile_start()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record()
-        step("bf16")
-        ev[k][1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches = lv.profile_stop()
-    lat = [a.elapsed_time(b) for a, b in ev]
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = ms_step / (m * D)
-    log(f"bench: {ms_step:.3f} ms/step, {value * 1e3:.4f} us/view/channel")
-    roof = roofline(stats, launches, args.steps, n, D, 2, products=2,
-                    kernel=f"blend_pair_kernel<LV_BF16, {args.layout == 'px8'}> "
-                           f"(D=384 BF16 maps, {args.layout.upper()} layout, 100 views per launch)",
-                    traffic_name=f"blend_pair_kernel-uplift-1M-100v-1008x756-D384-{fmt['bf16']}")
-
-    # the other storage legs: same job, same timing
-    storage = {"bf16": {"ms_per_step": round(ms_step, 3), "ms_per_view_channel": round(value, 7),
-                        "blend_ms_per_step": round(sum(launches) / args.steps, 3)}}
-    for dt in legs[1:]:
-        log(f"bench: storage leg {dt}")
-        step(dt)
+    def generate(leg):
+        """The leg's 100 stored maps (all resident in HBM) and FP8 scales; one
+        leg's maps at a time."""
+        maps, sc8 = [], []
+        for v in range(m):
+            f = scenes.feature_map(w, v, device="cuda")
+            if leg == "f32":
+                maps.append(f)
+            else:
+                e, s8 = lv.encode(f, fmt[leg])
+                maps.append(e)
+                if s8 is not None:
+                    sc8.append(s8)
+            del f
         torch.cuda.synchronize()
-        lv.profile_start()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            step(dt)
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) * 1e3 / reps
-        bl = lv.profile_stop()
-        storage[dt] = {"ms_per_step": round(t, 3), "ms_per_view_channel": round(t / (m * D), 7),
-                       "blend_ms_per_step": round(sum(bl) / reps, 3)}
-    storage["bf16_speedup_vs_f32"] = (round(storage["f32"]["ms_per_step"] / ms_step, 3)
+        return maps, (torch.stack(sc8).contiguous() if sc8 else None)
+
+    storage, kept, gpu_sub = {}, {}, {}
+    out = None
+    for leg in legs:
+        log(f"bench: {leg} leg: {m} maps ({fmt[leg]})")
+        maps, scales8 = generate(leg)
+        tab = lv.Maps(maps, fmt[leg])
+
+        def step():
+            s = lv.Scene(means, scales, quats, opac)
+            s.uplift(rig, tab, dtype=fmt[leg], scales=scales8, out=fout, wsum=bout)
+            s.close()
+
+        if leg == "bf16":
+            # work statistics of the headline pass (untimed, with counters)
+            s = lv.Scene(means, scales, quats, opac)
+            acc = lv.Accum(s, D, counts=True)
+            acc.add(rig, tab, dtype=fmt[leg], scales=scales8)
+            stats = acc.stats()
+            acc.close()
+            s.close()
+            log(f"bench: stats {stats}")
+            log(f"bench: headline (bf16): warmup {args.warmup}, timing {args.steps} steps")
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+            lv.profile_start()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                ev[k][0].record()
+                step()
+                ev[k][1].record()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            launches = lv.profile_stop()
+            lat = [a.elapsed_time(b) for a, b in ev]
+            ms_step = (t1 - t0) * 1e3 / args.steps
+            value = ms_step / (m * D)
+            log(f"bench: {ms_step:.3f} ms/step, {value * 1e3:.4f} us/view/channel, "
+                f"blend {sum(launches) / args.steps:.2f} ms in {len(launches) / args.steps:.0f} launches")
+            roof = roofline(stats, launches, args.steps, n, D, 2, products=2,
+                            kernel=f"blend_pair_kernel<LV_BF16, {args.layout == 'px8'}> "
+                                   f"(D=384 BF16 maps, {args.layout.upper()} layout)",
+                            traffic_name=f"blend_pair_kernel-uplift-1M-100v-1008x756-D384-{fmt['bf16']}")
+            storage[leg] = {"ms_per_step": round(ms_step, 3), "ms_per_view_channel": round(value, 7),
+                            "blend_ms_per_step": round(sum(launches) / args.steps, 3)}
+            out = {
+                "metric": METRIC,
+                "value": round(value, 8),
+                "unit": "ms/view/channel",
+                "n_gpus": 1,
+                "steps": args.steps,
+                "warmup": args.warmup,
+                "ms_per_step": round(ms_step, 4),
+                "higher_is_better": False,
+                "scaling": "weak",
+                "vs_baseline": None,
+                "dtype": "f32",
+                "data": "synthetic",
+                "config": {"workload": w.name, "gaussians": n, "views": m, "width": W, "height": H,
+                           "channels": D, "storage": fmt["bf16"], "accumulation": "f32",
+                           "contraction": "split-BF16 matrix-core products, FP32 accumulate (BF16 maps "
+                                          "and FP8 codes: 2 exact products per term; FP32 maps: 3, "
+                                          "error < 2^-16 |w F|)"},
+                "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)},
+                "contributions_per_s": round(stats["contributions"] / (ms_step * 1e-3), 1),
+                "work": stats,
+                "roofline": roof,
+            }
+        else:
+            step()
+            torch.cuda.synchronize()
+            lv.profile_start()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                step()
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) * 1e3 / reps
+            bl = lv.profile_stop()
+            storage[leg] = {"ms_per_step": round(t, 3), "ms_per_view_channel": round(t / (m * D), 7),
+                            "blend_ms_per_step": round(sum(bl) / reps, 3)}
+            log(f"bench: {leg}: {storage[leg]}")
+        if nv > 0:  # this leg's result over the first nv views, for the oracle comparison
+            s = lv.Scene(means, scales, quats, opac)
+            gpu_sub[leg] = s.uplift(cams[:nv], maps[:nv], dtype=fmt[leg],
+                                    scales=None if scales8 is None else scales8[:nv].contiguous())
+            torch.cuda.synchronize()
+            s.close()
+            kept[leg] = ([t.clone() for t in maps[:nv]], None if scales8 is None else scales8[:nv].clone())
+        del tab, maps, scales8
+        torch.cuda.empty_cache()
+    storage["bf16_speedup_vs_f32"] = (round(storage["f32"]["ms_per_step"] / storage["bf16"]["ms_per_step"], 3)
                                       if "f32" in storage else None)
-
-    cpu = None
-    if args.oracle_views > 0:
-        errs, cpu = oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, codes8,
-                                  scales8, args.oracle_views, fmt)
+    if nv > 0:
+        errs, cpu = oracle_errors(w, sc, cams, gpu_sub, kept, nv)
         for dt, e in errs.items():
-            storage.setdefault(dt, {})["error"] = e
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 8),
-        "unit": "ms/view/channel",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "gaussians": n, "views": m, "width": W, "height": H,
-                   "channels": D, "storage": fmt["bf16"], "accumulation": "f32",
-                   "contraction": "split-BF16 matrix-core products, FP32 accumulate (BF16 maps: "
-                                  "2 exact products per term; FP32 and FP8 maps: 3, error < 2^-16 |w F|)"},
-        "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)},
-        "contributions_per_s": round(stats["contributions"] / (sum(launches) / args.steps * 1e-3), 1),
-        "work": stats,
-        "roofline": roof,
-        "storage": storage,
-    }
-    if cpu is not None:
+            storage[dt]["error"] = e
         out["cpu_baseline"] = cpu
-        out["cpu_baseline"]["cpu_over_gpu"] = round(cpu["value"] / value, 1)
-    keep = (maps32, maps16, codes8, scales8, tabs)
-    return out, keep
+        out["cpu_baseline"]["cpu_over_gpu"] = round(cpu["value"] / out["value"], 1)
+    out["storage"] = storage
+    return out, None
 
 
 def measured_traffic(name):
@@ -301,11 +312,12 @@ def roofline(st, launches, steps, n, D, s_f, products, kernel, traffic_name):
                  "launches_per_step": per_step, "launch_ms": round(t * 1e3, 4),
                  "hbm": hbm, "fma_fp32": fma, "mfma_bf16": mfma})
     if st.get("partial_sums", -1) > 0:
-        # the diagnostic that limits this kernel: one device-scope FP32 atomic
-        # per channel and one for beta per (Gaussian, view, 8x8 block)
-        upd = st["partial_sums"] / per_step * (D + 1)
+        # one device-scope FP32 atomic per channel and one for beta per
+        # (Gaussian, view, pixel block) partial sum
+        ps = st["partial_sums"] / per_step
+        upd = ps * (D + 1)
         roof["atomics"] = {"updates_per_launch": int(upd), "achieved_Gps": round(upd / t / 1e9, 1),
-                           "partial_sums_per_launch": int(st["partial_sums"] / per_step)}
+                           "partial_sums_per_launch": int(ps)}
     return roof
 
 
@@ -317,7 +329,7 @@ def unblock(t, W):
     return t.permute(0, 1, 3, 2).reshape(H, W8 * 8, D)[:, :W]
 
 
-def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, codes8, scales8, nv, fmt):
+def oracle_errors(w, sc, cams, gpu_sub, kept, nv):
     """Each storage leg's result over the first nv views against the FP64
     oracle on a 20,000-Gaussian subsample: total error (oracle on the FP32
     maps) and accumulation error (oracle on the decoded stored maps), in units
@@ -331,21 +343,10 @@ def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, c
     from synth import scenes
 
     rows = scenes.subsample(w.seed, sc.n, SUBSAMPLE)
-    views = list(range(nv))
-    c = [cams[v] for v in views]
-    s = lv.Scene(means, scales, quats, opac)
-    gpu = {"bf16": s.uplift(c, [maps16[v] for v in views], dtype=fmt["bf16"])}
-    if maps32:
-        gpu["f32"] = s.uplift(c, [maps32[v] for v in views], dtype=fmt["f32"])
-    if codes8:
-        gpu["fp8"] = s.uplift(c, [codes8[v] for v in views], dtype=fmt["fp8"],
-                              scales=scales8[:nv].contiguous())
-    torch.cuda.synchronize()
-    s.close()
 
     def run(get):
         up = oracle.Uplifter(sc, w.D, rows=rows)
-        for v in views:
+        for v in range(nv):
             up.add_view(cams[v], get(v))
         return up.result()
 
@@ -354,16 +355,20 @@ def oracle_errors(lv, w, sc, means, scales, quats, opac, cams, maps32, maps16, c
     t0 = time.perf_counter()
     ref32 = run(host32)
     t_cpu = time.perf_counter() - t0
-    W = w.width
-    decoded = {"bf16": lambda v: unblock(maps16[v], W).float().cpu().numpy(),
-               "fp8": lambda v: (unblock(codes8[v], W).view(torch.float8_e4m3fn).float()
-                                 * scales8[v]).cpu().numpy(),
-               "f32": host32}
+
+    def decoded(dt):
+        maps, s8 = kept[dt]
+        if dt == "f32":
+            return host32
+        if dt == "bf16":
+            return lambda v: unblock(maps[v], w.width).float().cpu().numpy()
+        return lambda v: (unblock(maps[v], w.width).view(torch.float8_e4m3fn).float() * s8[v]).cpu().numpy()
+
     errs = {}
-    for dt, (f, b) in gpu.items():
+    for dt, (f, b) in gpu_sub.items():
         f = f.cpu().numpy().astype(np.float64)[rows]
         b = b.cpu().numpy().astype(np.float64)
-        refq = ref32 if dt == "f32" else run(decoded[dt])
+        refq = ref32 if dt == "f32" else run(decoded(dt))
         res = {}
         for name, ref in (("total", ref32), ("accumulation", refq)):
             ok = (ref.beta[rows] > 0) & ref.strict[rows]

@@ -804,46 +804,107 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
     // bit r: pixel row r % 8 of quadrant r / 8; K-step t covers bits 2t, 2t + 1
     const uint32_t rows = row_bits(pix0) | (row_bits(pix1) << 8);
     const float* wrow = Wt + (lane & 31) * kPairPitch + 8 * (lane >> 5);
-    for (int cg = 0; cg < ngroups; cg++) {
-      if (!((gmask >> cg) & 1u)) continue;
-      const ChanGroup& grp = groups[cg];
-      GroupLanes L;
-      if (!group_lanes_pair<DT>(grp, sets, q, lane, L)) continue;
-      const bool two = grp.width > 32;
+    if constexpr (!kSplitF && PX) {
+      // BF16 / FP8 pixel-block maps: one operand load per K-step and block
+      // (the HWC layout's eight loads per operand leave no registers for
+      // this).  A group's products go out (one atomic per channel) only
+      // after the next group's operand loads have been issued: the vector
+      // memory counter completes in order, so waiting for those loads does
+      // not wait for the atomics.
+      GroupLanes Lp;  // the group whose products are pending
+      bool pend = false, twop = false;
       f32x16 acc0 = {}, acc1 = {};
-      if (two) {
+      for (int cg = 0; cg < ngroups; cg++) {
+        GroupLanes L;
+        const bool ok = ((gmask >> cg) & 1u) && group_lanes_pair<DT>(groups[cg], sets, q, lane, L);
+        const bool two = groups[cg].width > 32;
+        bf16x8 F[2][8];
+        if (ok) {
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
-          if ((rows >> (2 * t)) & 3u) {
-            bf16x8 h0, l0, h1, l1, ah, al;
-            const int gy = q.qy + 2 * (t & 3) + (lane >> 5), gx0 = q.qx + 8 * (t >> 2);
-            load_row8<DT, PX>(L, 0, gy, gx0, q.g, h0, l0);
-            load_row8<DT, PX>(L, 1, gy, gx0, q.g, h1, l1);
-            load_split_w(wrow + 16 * t, ah, al);
-            acc0 = mfma(ah, h0, acc0);
-            acc1 = mfma(ah, h1, acc1);
-            acc0 = mfma(al, h0, acc0);
-            acc1 = mfma(al, h1, acc1);
-            if constexpr (kSplitF) {
-              acc0 = mfma(ah, l0, acc0);
-              acc1 = mfma(ah, l1, acc1);
+          for (int t = 0; t < 8; t++) {
+            if ((rows >> (2 * t)) & 3u) {
+              bf16x8 lo;
+              const int gy = q.qy + 2 * (t & 3) + (lane >> 5), gx0 = q.qx + 8 * (t >> 2);
+              load_row8<DT, PX>(L, 0, gy, gx0, q.g, F[0][t], lo);
+              if (two) load_row8<DT, PX>(L, 1, gy, gx0, q.g, F[1][t], lo);
             }
           }
         }
-      } else {
+        if (pend) batch_scatter<DT>(Lp, twop, count, ring_gid, lane, acc0, acc1);
+        pend = false;
+        if (!ok) continue;
+        acc0 = f32x16{};
+        acc1 = f32x16{};
+        if (two) {
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
-          if ((rows >> (2 * t)) & 3u) {
-            bf16x8 h0, l0, ah, al;
-            load_row8<DT, PX>(L, 0, q.qy + 2 * (t & 3) + (lane >> 5), q.qx + 8 * (t >> 2), q.g, h0, l0);
-            load_split_w(wrow + 16 * t, ah, al);
-            acc0 = mfma(ah, h0, acc0);
-            acc0 = mfma(al, h0, acc0);
-            if constexpr (kSplitF) acc0 = mfma(ah, l0, acc0);
+          for (int t = 0; t < 8; t++) {
+            if ((rows >> (2 * t)) & 3u) {
+              bf16x8 ah, al;
+              load_split_w(wrow + 16 * t, ah, al);
+              acc0 = mfma(ah, F[0][t], acc0);
+              acc1 = mfma(ah, F[1][t], acc1);
+              acc0 = mfma(al, F[0][t], acc0);
+              acc1 = mfma(al, F[1][t], acc1);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; t++) {
+            if ((rows >> (2 * t)) & 3u) {
+              bf16x8 ah, al;
+              load_split_w(wrow + 16 * t, ah, al);
+              acc0 = mfma(ah, F[0][t], acc0);
+              acc0 = mfma(al, F[0][t], acc0);
+            }
           }
         }
+        Lp = L;
+        twop = two;
+        pend = true;
       }
-      batch_scatter<DT>(L, two, count, ring_gid, lane, acc0, acc1);
+      if (pend) batch_scatter<DT>(Lp, twop, count, ring_gid, lane, acc0, acc1);
+    } else {
+      for (int cg = 0; cg < ngroups; cg++) {
+        if (!((gmask >> cg) & 1u)) continue;
+        const ChanGroup& grp = groups[cg];
+        GroupLanes L;
+        if (!group_lanes_pair<DT>(grp, sets, q, lane, L)) continue;
+        const bool two = grp.width > 32;
+        f32x16 acc0 = {}, acc1 = {};
+        if (two) {
+  #pragma unroll
+          for (int t = 0; t < 8; t++) {
+            if ((rows >> (2 * t)) & 3u) {
+              bf16x8 h0, l0, h1, l1, ah, al;
+              const int gy = q.qy + 2 * (t & 3) + (lane >> 5), gx0 = q.qx + 8 * (t >> 2);
+              load_row8<DT, PX>(L, 0, gy, gx0, q.g, h0, l0);
+              load_row8<DT, PX>(L, 1, gy, gx0, q.g, h1, l1);
+              load_split_w(wrow + 16 * t, ah, al);
+              acc0 = mfma(ah, h0, acc0);
+              acc1 = mfma(ah, h1, acc1);
+              acc0 = mfma(al, h0, acc0);
+              acc1 = mfma(al, h1, acc1);
+              if constexpr (kSplitF) {
+                acc0 = mfma(ah, l0, acc0);
+                acc1 = mfma(ah, l1, acc1);
+              }
+            }
+          }
+        } else {
+  #pragma unroll
+          for (int t = 0; t < 8; t++) {
+            if ((rows >> (2 * t)) & 3u) {
+              bf16x8 h0, l0, ah, al;
+              load_row8<DT, PX>(L, 0, q.qy + 2 * (t & 3) + (lane >> 5), q.qx + 8 * (t >> 2), q.g, h0, l0);
+              load_split_w(wrow + 16 * t, ah, al);
+              acc0 = mfma(ah, h0, acc0);
+              acc0 = mfma(al, h0, acc0);
+              if constexpr (kSplitF) acc0 = mfma(ah, l0, acc0);
+            }
+          }
+        }
+        batch_scatter<DT>(L, two, count, ring_gid, lane, acc0, acc1);
+      }
     }
     if (bsets || any_tail) {
       // lane l: row l % 32, the pixels of quadrant l / 32

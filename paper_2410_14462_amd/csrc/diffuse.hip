@@ -126,6 +126,165 @@ __global__ __launch_bounds__(256) void spmm_kernel(const int32_t* __restrict__ r
   }
 }
 
+// The value a signal element holds once stored (BF16 storage rounds).
+template <lv_dtype DT>
+__device__ __forceinline__ float stored(float x) {
+  if constexpr (DT == LV_F32) {
+    return x;
+  } else {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+  }
+}
+
+// One channel (D = 1): one row per lane.  A row's edges go 8 at a time: the
+// 8 column indices and weights are loaded together, then the 8 gathers, so
+// each lane has 8 loads in flight instead of walking its edges one by one.
+// Sums in edge order, as spmm_kernel.
+template <lv_dtype GT, lv_dtype VT>
+__global__ __launch_bounds__(256) void spmm1_kernel(const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const void* __restrict__ val, int64_t n,
+                                                    const void* __restrict__ g,
+                                                    const float* __restrict__ nrm_in,
+                                                    void* __restrict__ y, float* __restrict__ nrm_out) {
+  constexpr int U = 8;
+  __shared__ float sq[4];
+  const float n2 = nrm_in[0];
+  const float scl = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+  float ss = 0.0f;
+  // XCD x (= blockIdx mod 8) takes the x-th eighth of the rows (locality order)
+  const int64_t tiles = (n + 255) / 256;
+  const int64_t xcd = blockIdx.x & 7, nloc = gridDim.x >> 3;
+  const int64_t t0 = tiles * xcd / 8, t1 = tiles * (xcd + 1) / 8;
+  for (int64_t tile = t0 + (blockIdx.x >> 3); tile < t1; tile += nloc) {
+    const int64_t row = tile * 256 + threadIdx.x;
+    if (row >= n) continue;
+    const int32_t a = row_ptr[row], b = row_ptr[row + 1];
+    float acc = 0.0f;
+    for (int32_t e = a; e < b; e += U) {
+      int32_t cj[U];
+      float w[U], x[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const bool ok = e + u < b;
+        cj[u] = ok ? col[e + u] : 0;
+        w[u] = ok ? ld<VT>(val, e + u) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) x[u] = ld<GT>(g, cj[u]);
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (e + u < b) acc = __builtin_fmaf(w[u], x[u], acc);
+    }
+    const float out = scl * acc;
+    st<GT>(y, row, out);
+    const float o = stored<GT>(out);  // the norm of what is stored
+    ss = __builtin_fmaf(o, o, ss);
+  }
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+  if ((threadIdx.x & 63) == 0) sq[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float t = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+    if (t != 0.0f) atomicAdd(&nrm_out[0], t);
+  }
+}
+
+// Four consecutive channels per lane (D = 4 L, L lanes per row, 64 / L rows
+// per wave): the gathers are 16-byte (FP32) or 8-byte (BF16) loads of a
+// neighbour's channels and a wave keeps several rows in flight.  A row's
+// edges are fetched L at a time, one per lane, and broadcast with shuffles;
+// 8 gathers in flight per lane.  Sums in edge order, as spmm_kernel.
+template <int L, lv_dtype GT, lv_dtype VT>
+__global__ __launch_bounds__(256) void spmm4_kernel(const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const void* __restrict__ val, int64_t n,
+                                                    const void* __restrict__ g,
+                                                    const float* __restrict__ nrm_in,
+                                                    void* __restrict__ y, float* __restrict__ nrm_out) {
+  constexpr int D = 4 * L, R = 64 / L, U = 8;
+  __shared__ float sq[256 * 4];
+  const int t = threadIdx.x, lane = t & 63;
+  const int sub = lane / L, c4 = lane % L, gbase = sub * L;
+  float scl[4], ss[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const float n2 = nrm_in[4 * c4 + k];
+    scl[k] = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+  }
+  const int64_t tiles = (n + 4 * R - 1) / (4 * R);
+  const int64_t xcd = blockIdx.x & 7, nloc = gridDim.x >> 3;
+  const int64_t t0 = tiles * xcd / 8, t1 = tiles * (xcd + 1) / 8;
+  for (int64_t tile = t0 + (blockIdx.x >> 3); tile < t1; tile += nloc) {
+    const int64_t row = (tile * 4 + (t >> 6)) * R + sub;
+    const bool valid = row < n;
+    const int32_t a = valid ? row_ptr[row] : 0, b = valid ? row_ptr[row + 1] : 0;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int32_t e0 = a; e0 < b; e0 += L) {
+      const int32_t my = e0 + c4;
+      const int32_t cv = my < b ? col[my] : 0;
+      const float wv = my < b ? ld<VT>(val, my) : 0.0f;
+      const int cnt = b - e0 < L ? b - e0 : L;
+      for (int j = 0; j < cnt; j += U) {
+        float w[U], x[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int src = gbase + ((j + u) < L ? (j + u) : 0);
+          const int32_t cj = __shfl(cv, src, 64);
+          const float wj = __shfl(wv, src, 64);
+          w[u] = (j + u) < cnt ? wj : 0.0f;
+          const int64_t off = (int64_t)cj * D + 4 * c4;
+          if constexpr (GT == LV_F32) {
+            const float4 q = *reinterpret_cast<const float4*>(static_cast<const float*>(g) + off);
+            x[u][0] = q.x;
+            x[u][1] = q.y;
+            x[u][2] = q.z;
+            x[u][3] = q.w;
+          } else {
+            const uint2 q = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(g) + off);
+            x[u][0] = __uint_as_float(q.x << 16);
+            x[u][1] = __uint_as_float(q.x & 0xFFFF0000u);
+            x[u][2] = __uint_as_float(q.y << 16);
+            x[u][3] = __uint_as_float(q.y & 0xFFFF0000u);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+          for (int k = 0; k < 4; k++) acc[k] = __builtin_fmaf(w[u], x[u][k], acc[k]);
+      }
+    }
+    if (valid) {
+      float o[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        o[k] = stored<GT>(scl[k] * acc[k]);
+        ss[k] = __builtin_fmaf(o[k], o[k], ss[k]);
+      }
+      const int64_t off = row * D + 4 * c4;
+      if constexpr (GT == LV_F32) {
+        *reinterpret_cast<float4*>(static_cast<float*>(y) + off) = make_float4(o[0], o[1], o[2], o[3]);
+      } else {
+        const uint2 q = make_uint2((__float_as_uint(o[0]) >> 16) | (__float_as_uint(o[1]) & 0xFFFF0000u),
+                                   (__float_as_uint(o[2]) >> 16) | (__float_as_uint(o[3]) & 0xFFFF0000u));
+        *reinterpret_cast<uint2*>(static_cast<uint16_t*>(y) + off) = q;
+      }
+    }
+  }
+  // per-channel sums over the block: threads t = c4 (mod L) hold channels 4 c4 .. 4 c4 + 3
+#pragma unroll
+  for (int k = 0; k < 4; k++) sq[k * 256 + t] = ss[k];
+  __syncthreads();
+  if (t < D) {
+    const int k = t & 3, cc = t >> 2;
+    float s2 = 0.0f;
+    for (int q = cc; q < 256; q += L) s2 += sq[k * 256 + q];
+    if (s2 != 0.0f) atomicAdd(&nrm_out[t], s2);
+  }
+}
+
 template <lv_dtype GT>
 __global__ void copy_kernel(const void* __restrict__ src, void* __restrict__ dst, int64_t total) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -147,9 +306,38 @@ hipError_t spmm_launch(const int32_t* rp, const int32_t* col, const void* val, i
   return hipGetLastError();
 }
 
+template <int L, lv_dtype GT, lv_dtype VT>
+hipError_t spmm4_launch(const int32_t* rp, const int32_t* col, const void* val, int64_t n,
+                        const void* g, const float* nin, void* y, float* nout, hipStream_t s) {
+  constexpr int R = 64 / L;
+  const int64_t tiles = (n + 4 * R - 1) / (4 * R);
+  const int64_t want = (tiles + 7) / 8 * 8;
+  const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL((spmm4_kernel<L, GT, VT>), dim3(blocks), dim3(256), 0, s, rp, col, val, n, g, nin,
+                     y, nout);
+  return hipGetLastError();
+}
+
 template <lv_dtype GT, lv_dtype VT>
 hipError_t spmm_dispatch(const int32_t* rp, const int32_t* col, const void* val, int64_t n, int D,
                          const void* g, const float* nin, void* y, float* nout, hipStream_t s) {
+  if (D == 1) {
+    const int64_t tiles = (n + 255) / 256;
+    const int64_t want = (tiles + 7) / 8 * 8;
+    const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL((spmm1_kernel<GT, VT>), dim3(blocks), dim3(256), 0, s, rp, col, val, n, g, nin, y,
+                       nout);
+    return hipGetLastError();
+  }
+  // four channels per lane where D = 4 L, L a power of two up to 16 and the
+  // rows are 16-byte (FP32) or 8-byte (BF16) aligned
+  if (((uintptr_t)g % 16 == 0) && ((uintptr_t)y % 16 == 0)) {
+    if (D == 64) return spmm4_launch<16, GT, VT>(rp, col, val, n, g, nin, y, nout, s);
+    if (D == 32) return spmm4_launch<8, GT, VT>(rp, col, val, n, g, nin, y, nout, s);
+    if (D == 16) return spmm4_launch<4, GT, VT>(rp, col, val, n, g, nin, y, nout, s);
+    if (D == 8) return spmm4_launch<2, GT, VT>(rp, col, val, n, g, nin, y, nout, s);
+    if (D == 4) return spmm4_launch<1, GT, VT>(rp, col, val, n, g, nin, y, nout, s);
+  }
   if (D >= 64) return spmm_launch<64, GT, VT>(rp, col, val, n, D, g, nin, y, nout, s);
   if (D > 16) return spmm_launch<32, GT, VT>(rp, col, val, n, D, g, nin, y, nout, s);
   if (D > 4) return spmm_launch<8, GT, VT>(rp, col, val, n, D, g, nin, y, nout, s);

@@ -83,7 +83,8 @@ def gpu_graph(n, k, seed, D):
     return rp, col, val
 
 
-@pytest.mark.parametrize("D,steps", [(1, 10), (3, 5), (64, 20), (70, 3), (8, 0), (12, 4), (384, 3)])
+@pytest.mark.parametrize("D,steps", [(1, 10), (3, 5), (64, 20), (70, 3), (8, 0), (8, 6), (12, 4), (4, 6), (16, 5),
+                                     (32, 4), (384, 3)])
 def test_diffuse_fp32_parity(D, steps):
     n = 5000
     rp, col, val = gpu_graph(n, 16, D, D)
