@@ -298,14 +298,16 @@ __device__ __forceinline__ int64_t map_index(int y, int x, int W, int ld, int64_
     return ((int64_t)y * W + x) * ld + c;
 }
 
-// OCP E4M3FN code -> the same value in BF16 bits (exact: 3 mantissa bits).
-// Normal codes move their exponent and mantissa; subnormals m 2^-9 go
-// through an exact FP32 product.
-__device__ __forceinline__ uint32_t e4m3_bf16(uint32_t b) {
-  const uint32_t e = (b >> 3) & 0xFu, m = b & 7u;
-  const uint32_t nrm = ((e + 120u) << 7) | (m << 4);
-  const uint32_t sub = __float_as_uint((float)m * 0x1.0p-9f) >> 16;
-  return (e ? nrm : sub) | ((b & 0x80u) << 8);
+// Four OCP E4M3FN codes (the bytes of w) -> their values as BF16 bits, two
+// per word: the hardware FP8 -> FP32 conversion (two codes per
+// instruction), then FP32 -> BF16 (exact: 3 mantissa bits).
+__device__ __forceinline__ void e4m3x4_bf16(uint32_t w, uint32_t& h01, uint32_t& h23) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  h01 = __builtin_bit_cast(uint32_t, (bf16x2{(__bf16)a.x, (__bf16)a.y}));
+  h23 = __builtin_bit_cast(uint32_t, (bf16x2{(__bf16)b.x, (__bf16)b.y}));
 }
 
 __device__ __forceinline__ bf16x8 bf16x8_of(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
@@ -331,13 +333,9 @@ __device__ __forceinline__ void load_row8(const GroupLanes& L, int b, int gy, in
       fh = okr ? bf16x8_of(q.x, q.y, q.z, q.w) : bf16x8_of(0u, 0u, 0u, 0u);
     } else if constexpr (DT == LV_FP8_E4M3) {
       const u32x2 q = gptr(static_cast<const u32x2*>(L.src[b]))[blk];
-      const uint32_t w[2] = {okr ? q.x : 0u, okr ? q.y : 0u};
       uint32_t h[4];
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const uint32_t x = w[k >> 1] >> (16 * (k & 1));
-        h[k] = e4m3_bf16(x & 0xFFu) | (e4m3_bf16((x >> 8) & 0xFFu) << 16);
-      }
+      e4m3x4_bf16(okr ? q.x : 0u, h[0], h[1]);
+      e4m3x4_bf16(okr ? q.y : 0u, h[2], h[3]);
       fh = bf16x8_of(h[0], h[1], h[2], h[3]);
     } else {
       const f32x4 qa = gptr(static_cast<const f32x4*>(L.src[b]))[2 * blk];
@@ -367,10 +365,17 @@ __device__ __forceinline__ void load_row8(const GroupLanes& L, int b, int gy, in
         if constexpr (DT == LV_BF16)
           x = gptr(static_cast<const uint16_t*>(L.src[b]))[idx];
         else
-          x = e4m3_bf16(gptr(static_cast<const uint8_t*>(L.src[b]))[idx]);
+          x = gptr(static_cast<const uint8_t*>(L.src[b]))[idx];
         h[i] = ok ? x : 0u;
       }
-      fh = bf16x8_of(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+      if constexpr (DT == LV_BF16) {
+        fh = bf16x8_of(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+      } else {
+        uint32_t o[4];
+        e4m3x4_bf16(h[0] | (h[1] << 8) | (h[2] << 16) | (h[3] << 24), o[0], o[1]);
+        e4m3x4_bf16(h[4] | (h[5] << 8) | (h[6] << 16) | (h[7] << 24), o[2], o[3]);
+        fh = bf16x8_of(o[0], o[1], o[2], o[3]);
+      }
     }
   }
 }
