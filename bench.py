@@ -548,21 +548,28 @@ def serving(lv, nreq, rate, bank_k=4):
         srv.poll()
         torch.cuda.synchronize()
         kept, comps = {}, []
+
+        def collect(cs):
+            # a finished request's outputs are dropped at once (kept only for the
+            # requests compared below), as a client that consumes them would
+            for c in cs:
+                if c["tag"] in check:
+                    kept[c["tag"]] = c["out"]
+                c.pop("out", None)
+                c.pop("wsum", None)
+                comps.append(c)
+
         t0 = time.perf_counter()
         for i, r in enumerate(reqs):
             while time.perf_counter() - t0 < r.arrival:
                 time.sleep(0.0005)
             maps = [bank[r.res][v % bank_k][..., :r.D] for v in r.views]
             srv.submit(scs[r.scene], [rigs[r.res][v] for v in r.views], maps, dtype=dtype, tag=i)
-            for c in srv.poll():
-                comps.append(c)
+            collect(srv.poll())
         srv.drain()
-        comps += srv.poll()
+        collect(srv.poll())
         st = srv.stats()
         srv.close()
-        for c in comps:
-            if c["tag"] in check:
-                kept[c["tag"]] = c["out"]
         bad = [(c["tag"], c["status"]) for c in comps if c["status"] != 0]
         if len(comps) != nreq or bad:
             raise RuntimeError(f"serving: {len(comps)} of {nreq} completed, failed: {bad[:8]}")
@@ -574,7 +581,10 @@ def serving(lv, nreq, rate, bank_k=4):
                "mean_requests_per_pass": round(nreq / max(1, st["passes"] - len(scs) * workers), 2),
                "peak_budget_bytes": st["peak_bytes"]}
         if "peak_device_bytes" in st:
+            # device memory in use above the level at the server's creation
+            # (hipMemGetInfo), the in-flight requests' output tensors included
             res["peak_device_bytes"] = st["peak_device_bytes"]
+            res["peak_device_within_budget"] = st["peak_device_bytes"] <= budget
         return res, kept
 
     served, out16 = run("bf16", 2, 8)

@@ -1161,6 +1161,31 @@ __global__ __launch_bounds__(64, 3) void render_kernel(
     gptr(alphas[q.v])[(int64_t)py * q.g.W + px] = asum;
 }
 
+// D a multiple of 4, 16-byte aligned arrays: a block takes 64 Gaussians,
+// each thread four channels at a time (16-byte accesses, no 64-bit division
+// per element).
+constexpr int kFinRows = 64;
+__global__ __launch_bounds__(256) void finalize4_kernel(const float4* __restrict__ U,
+                                                        const beta_t* __restrict__ beta, int64_t n,
+                                                        int Q, float4* __restrict__ f,
+                                                        float* __restrict__ wsum,
+                                                        float4* __restrict__ usum) {
+  const int64_t r0 = (int64_t)blockIdx.x * kFinRows;
+  const int rows = (int)(n - r0 < kFinRows ? n - r0 : kFinRows);
+  for (int k = threadIdx.x; k < rows * Q; k += 256) {
+    const int r = k / Q, q = k - r * Q;
+    const int64_t i = r0 + r;
+    const float bs = (float)((double)beta[i] * (1.0 / kBetaUnit));
+    const int64_t e = i * Q + q;
+    const float4 u = U[e];
+    if (f)
+      f[e] = bs > 0.0f ? make_float4(u.x / bs, u.y / bs, u.z / bs, u.w / bs)
+                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (usum) usum[e] = u;
+    if (wsum && q == 0) wsum[i] = bs;
+  }
+}
+
 __global__ void finalize_kernel(const float* __restrict__ U, const beta_t* __restrict__ beta,
                                 int64_t n, int D, float* __restrict__ f, float* __restrict__ wsum,
                                 float* __restrict__ usum) {
@@ -1227,6 +1252,13 @@ hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D,
                            float* wsum, float* usum, hipStream_t s) {
   int64_t total = n * (int64_t)D;
   if (total == 0) return hipSuccess;
+  const auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  if (D % 4 == 0 && a16(U) && a16(f) && a16(usum)) {
+    hipLaunchKernelGGL(finalize4_kernel, dim3((unsigned)((n + kFinRows - 1) / kFinRows)), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(U), beta, n, D / 4, reinterpret_cast<float4*>(f),
+                       wsum, reinterpret_cast<float4*>(usum));
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, U,
                      beta, n, D, f, wsum, usum);
   return hipGetLastError();
