@@ -537,9 +537,12 @@ def serving(lv, nreq, rate, bank_k=4):
     check = list(range(min(6, nreq)))  # requests whose BF16 and FP32 results are compared
     budget = 64 << 30
 
+    scratch = 4 << 30  # per worker (the server's default)
+
     def run(dtype, workers, max_sets):
         bank = bank16 if dtype == "bf16" else bank32
-        srv = lv.Server(budget=budget, workers=workers, max_sets=max_sets, max_channels=1024)
+        srv = lv.Server(budget=budget, workers=workers, max_sets=max_sets, max_channels=1024,
+                        scratch=scratch)
         # warm each worker's stream workspace on every scene (not timed)
         for k, g in enumerate(scs):
             for _ in range(workers):
@@ -548,6 +551,8 @@ def serving(lv, nreq, rate, bank_k=4):
         srv.poll()
         torch.cuda.synchronize()
         kept, comps = {}, []
+        out_bytes = {}            # the client's output tensors of submitted, unfinished requests
+        live = [0, 0]             # bytes in flight, peak
 
         def collect(cs):
             # a finished request's outputs are dropped at once (kept only for the
@@ -557,6 +562,7 @@ def serving(lv, nreq, rate, bank_k=4):
                     kept[c["tag"]] = c["out"]
                 c.pop("out", None)
                 c.pop("wsum", None)
+                live[0] -= out_bytes.pop(c["tag"], 0)
                 comps.append(c)
 
         t0 = time.perf_counter()
@@ -565,6 +571,9 @@ def serving(lv, nreq, rate, bank_k=4):
                 time.sleep(0.0005)
             maps = [bank[r.res][v % bank_k][..., :r.D] for v in r.views]
             srv.submit(scs[r.scene], [rigs[r.res][v] for v in r.views], maps, dtype=dtype, tag=i)
+            out_bytes[i] = scs[r.scene].n * (r.D + 1) * 4
+            live[0] += out_bytes[i]
+            live[1] = max(live[1], live[0])
             collect(srv.poll())
         srv.drain()
         collect(srv.poll())
@@ -580,11 +589,17 @@ def serving(lv, nreq, rate, bank_k=4):
                "passes": st["passes"] - len(scs) * workers,
                "mean_requests_per_pass": round(nreq / max(1, st["passes"] - len(scs) * workers), 2),
                "peak_budget_bytes": st["peak_bytes"]}
+        # the server's memory: accumulators (within the budget by admission) and
+        # the workers' scratch, set aside from the budget at creation
+        res["server_peak_bytes"] = st["peak_bytes"] + workers * scratch
+        res["server_within_budget"] = res["server_peak_bytes"] <= budget
         if "peak_device_bytes" in st:
             # device memory in use above the level at the server's creation
-            # (hipMemGetInfo), the in-flight requests' output tensors included
+            # (hipMemGetInfo): the server's, plus the client's output tensors of the
+            # submitted, unfinished requests (caller-owned; peak of those below)
             res["peak_device_bytes"] = st["peak_device_bytes"]
-            res["peak_device_within_budget"] = st["peak_device_bytes"] <= budget
+            res["client_outputs_peak_bytes"] = live[1]
+            res["peak_device_within_budget_plus_client_outputs"] = st["peak_device_bytes"] <= budget + live[1]
         return res, kept
 
     served, out16 = run("bf16", 2, 8)
