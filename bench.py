@@ -520,7 +520,7 @@ def diffusion_leg(lv):
 
 # ------------------------------------------------------------------ serving
 def serving(lv, nreq, rate, bank_k=4):
-    """The serving trace (synth.trace) three times: BF16 maps through the
+    """The serving trace (synth.trace) three times: BF16 pixel-block maps through the
     server (2 workers, same-scene requests merged into one pass, admission by
     an HBM budget), FP32 maps through the same server settings, and FP32 maps
     one request at a time (1 worker, no merging).  Latency = completion -
@@ -532,21 +532,26 @@ def serving(lv, nreq, rate, bank_k=4):
     scs = [lv.Scene.from_arrays(s) for s in trace.scenes()]
     rigs = [trace.rig(r) for r in range(len(trace.RESOLUTIONS))]
     bank32 = [trace.bank(r, bank_k) for r in range(len(trace.RESOLUTIONS))]
-    bank16 = [[b.to(torch.bfloat16) for b in bk] for bk in bank32]
+    # BF16 maps in the pixel-block layout (requests read channel slices of them)
+    bank16 = [[lv.encode(b, "bf16_px8")[0] for b in bk] for bk in bank32]
     reqs = trace.requests(nreq, rate)
     check = list(range(min(6, nreq)))  # requests whose BF16 and FP32 results are compared
     budget = 64 << 30
 
     scratch = 4 << 30  # per worker (the server's default)
 
+    def take(t, D):  # channels [0, D) of a bank map, HWC or pixel blocks
+        return t[..., :D] if t.dim() == 3 else t[:, :, :D, :]
+
     def run(dtype, workers, max_sets):
         bank = bank16 if dtype == "bf16" else bank32
+        dtype = "bf16_px8" if dtype == "bf16" else dtype
         srv = lv.Server(budget=budget, workers=workers, max_sets=max_sets, max_channels=1024,
                         scratch=scratch)
         # warm each worker's stream workspace on every scene (not timed)
         for k, g in enumerate(scs):
             for _ in range(workers):
-                srv.submit(g, rigs[2][:1], [bank[2][0][..., :4]], dtype=dtype, tag=1_000_000 + k)
+                srv.submit(g, rigs[2][:1], [take(bank[2][0], 4)], dtype=dtype, tag=1_000_000 + k)
         srv.drain()
         srv.poll()
         torch.cuda.synchronize()
@@ -569,7 +574,7 @@ def serving(lv, nreq, rate, bank_k=4):
         for i, r in enumerate(reqs):
             while time.perf_counter() - t0 < r.arrival:
                 time.sleep(0.0005)
-            maps = [bank[r.res][v % bank_k][..., :r.D] for v in r.views]
+            maps = [take(bank[r.res][v % bank_k], r.D) for v in r.views]
             srv.submit(scs[r.scene], [rigs[r.res][v] for v in r.views], maps, dtype=dtype, tag=i)
             out_bytes[i] = scs[r.scene].n * (r.D + 1) * 4
             live[0] += out_bytes[i]
