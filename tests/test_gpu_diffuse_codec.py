@@ -161,8 +161,8 @@ def test_diffuse_bf16_storage_and_constant_signal():
 def test_large_full_size_precision_sampled():
     """The large configuration at full size: 1,000,000 Gaussians (scales
     exp(N(-5, 0.7^2)), opacities sigmoid(N(0.5, 1))), 1008x756 views, D = 384
-    maps (N(0,1) at 1/14 resolution, upsampled), stored FP32, BF16 and FP8 with
-    FP32 accumulation, 5 of the 100 rig views.  The oracle walks every pixel and
+    maps (N(0,1) at 1/14 resolution, upsampled), stored FP32 (HWC), BF16 and
+    FP8 (pixel blocks) with FP32 accumulation, 5 of the 100 rig views.  The oracle walks every pixel and
     accumulates a 20,000-Gaussian sample (drawn without replacement); counts
     and weight sums are compared for all Gaussians."""
     w = scenes.WORKLOADS["large"]
@@ -182,14 +182,16 @@ def test_large_full_size_precision_sampled():
             acc.add(cams, maps32)
             dec = maps32
         else:
-            enc = [lv.encode(m, dtype) for m in maps32]
+            # pixel-block storage, the layout the headline bench times
+            enc = [lv.encode(m, dtype + "_px8") for m in maps32]
+            Wd = maps32[0].shape[1]
             if dtype == "bf16":
-                acc.add(cams, [e[0] for e in enc], dtype="bf16")
-                dec = [e[0].float() for e in enc]
+                acc.add(cams, [e[0] for e in enc], dtype="bf16_px8")
+                dec = [px8_to_hwc(e[0].float(), Wd) for e in enc]
             else:
                 scales = torch.stack([e[1] for e in enc]).contiguous()
-                acc.add(cams, [e[0] for e in enc], dtype="fp8", scales=scales)
-                dec = [e[0].view(torch.float8_e4m3fn).float() * e[1] for e in enc]
+                acc.add(cams, [e[0] for e in enc], dtype="fp8_px8", scales=scales)
+                dec = [px8_to_hwc(e[0].view(torch.float8_e4m3fn).float(), Wd) * e[1] for e in enc]
             if dtype == "fp8":
                 smax = max(float(e[1].max()) for e in enc)
             del enc
@@ -223,6 +225,12 @@ def test_large_full_size_precision_sampled():
                  "fp8": 2.0 ** -4 * a + 2.0 ** -10 * smax + 1e-4 * a}[dtype]
         print(f"large {dtype} vs FP32 maps: max |df|/a {np.max(d / np.maximum(a, 1e-30)):.3e}")
         assert np.all(d <= bound)
+
+
+def px8_to_hwc(t, W):
+    """[H, ceil(W/8), D, 8] -> [H, W, D] (the inverse of px8_reference)."""
+    H, W8, D, _ = t.shape
+    return t.permute(0, 1, 3, 2).reshape(H, W8 * 8, D)[:, :W]
 
 
 def px8_reference(a):
