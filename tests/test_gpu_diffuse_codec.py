@@ -101,6 +101,45 @@ def test_diffuse_fp32_parity(D, steps):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("D,gdt", [(64, "f32"), (32, "f32"), (64, "bf16"), (32, "bf16"), (16, "f32")])
+def test_diffuse_ragged_degrees(D, gdt):
+    """Rows of very different degrees in one wave: empty rows (also at the
+    start and end), rows of 1-20 edges and hubs of 100-300 edges (several
+    64-edge chunks of a wave's edge range), n not a multiple of any row
+    tile; FP32 against the FP64 oracle, BF16 storage against the oracle that
+    rounds every iterate to BF16."""
+    n, steps = 3001, 4
+    rng = np.random.default_rng(7 + D)
+    deg = rng.integers(1, 21, n)
+    deg[rng.random(n) < 0.3] = 0
+    hubs = rng.choice(n, 12, replace=False)
+    deg[hubs] = rng.integers(100, 301, 12)
+    deg[:3] = 0
+    deg[-2:] = 0
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum(deg)
+    col = rng.integers(0, n, rp[-1]).astype(np.int32)
+    val = rng.uniform(0.1, 1.0, rp[-1]).astype(np.float32)
+    g0 = philox.uniform(60 + D, 1, n * D).reshape(n, D)
+    dt = torch.float32 if gdt == "f32" else torch.bfloat16
+    G = lv.Graph(torch.as_tensor(rp, device="cuda"), torch.as_tensor(col, device="cuda"),
+                 torch.as_tensor(val, device="cuda"))
+    gin = torch.as_tensor(g0, device="cuda").to(dt)
+    out = G.diffuse(gin, steps).float().cpu().numpy().astype(np.float64)
+    A = od.csr_matrix(n, rp, col, val)
+    if gdt == "f32":
+        ref = od.diffuse(A, g0.astype(np.float64), steps)
+        tol = 1e-5
+    else:
+        ref = od.diffuse(A, gin.float().cpu().numpy().astype(np.float64), steps, store="bf16")
+        tol = 2.0 ** -7
+    assert np.all(out[deg == 0] == 0)
+    scale = np.maximum(np.max(np.abs(ref), axis=0), 1e-30)
+    err = np.max(np.abs(out - ref) / scale)
+    print(f"ragged degrees D={D} {gdt}: max err {err:.3e}")
+    assert err < tol
+
+
 @pytest.mark.parametrize("D,vdt", [(1, "f32"), (64, "f32"), (5, "bf16")])
 def test_diffuse_locality_order(D, vdt):
     """With the scene given, rows run in the Morton order of the centres
