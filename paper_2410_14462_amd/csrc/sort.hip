@@ -569,15 +569,38 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
   }
 }
 
-__global__ void ranges_kernel(const uint32_t* __restrict__ key, int64_t P, int stride,
-                              uint2* __restrict__ ranges) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  uint32_t k = key[i];
-  uint32_t v = k >> kViewShift, tile = k & ((1u << kViewShift) - 1u);
-  uint2* r = ranges + (int64_t)v * stride + tile;
-  if (i == 0 || key[i - 1] != k) r->x = (uint32_t)i;
-  if (i + 1 == P || key[i + 1] != k) r->y = (uint32_t)(i + 1);
+// Four consecutive sorted keys per thread (one 16-byte load where the key
+// array is 16-byte aligned): a key that differs from its predecessor starts
+// its tile's range, one that differs from its successor ends it.
+__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict__ key, int64_t P,
+                                                     int stride, bool aligned, uint2* __restrict__ ranges) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i0 = 4 * q;
+  if (i0 >= P) return;
+  uint32_t k[4];
+  if (aligned && i0 + 4 <= P) {
+    const uint4 v = reinterpret_cast<const uint4*>(key)[q];
+    k[0] = v.x;
+    k[1] = v.y;
+    k[2] = v.z;
+    k[3] = v.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; j++) k[j] = i0 + j < P ? key[i0 + j] : 0u;
+  }
+  const uint32_t before = i0 > 0 ? key[i0 - 1] : 0u;
+  const uint32_t after = i0 + 4 < P ? key[i0 + 4] : 0u;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int64_t i = i0 + j;
+    if (i >= P) break;
+    const uint32_t v = k[j] >> kViewShift, tile = k[j] & ((1u << kViewShift) - 1u);
+    uint2* r = ranges + (int64_t)v * stride + tile;
+    const uint32_t prev = j > 0 ? k[j - 1] : before;
+    const uint32_t next = j < 3 ? k[j + 1] : after;
+    if (i == 0 || prev != k[j]) r->x = (uint32_t)i;
+    if (i + 1 == P || next != k[j]) r->y = (uint32_t)(i + 1);
+  }
 }
 
 }  // namespace
@@ -700,8 +723,10 @@ hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off,
 hipError_t launch_ranges(const uint32_t* pair_key, int64_t P, int tiles_stride, uint2* ranges,
                          hipStream_t s) {
   if (P == 0) return hipSuccess;
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, pair_key, P,
-                     tiles_stride, ranges);
+  const int64_t quads = (P + 3) / 4;
+  const bool aligned = ((uintptr_t)pair_key & 15) == 0;
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, pair_key, P,
+                     tiles_stride, aligned, ranges);
   return hipGetLastError();
 }
 

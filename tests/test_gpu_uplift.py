@@ -52,6 +52,17 @@ def check_structure(gs, sc, cam):
     return len(o.ids)
 
 
+def test_structure_bit_exact_two_pass_tile_sort():
+    """More than 2048 tiles (1009x757: 64 x 48 tiles, 12-bit tile ids): the
+    tile sort takes two passes and the tile ranges come from the sorted keys
+    (four keys per thread, ragged pair counts)."""
+    sc = scenes.make_scene(8, 30000, -4.5, 0.6, 0.0, 1.0)
+    gs = lv.Scene.from_arrays(sc)
+    for k, e in enumerate(scenes.fibonacci_eyes(3, 3.0)):
+        cam = scenes.look_at(e, 1009 - 2 * k, 757 + k, 60.0)
+        assert check_structure(gs, sc, cam) > 10000
+
+
 @pytest.fixture(scope="module")
 def tiny():
     w = scenes.WORKLOADS["tiny"]
