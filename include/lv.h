@@ -140,10 +140,22 @@ const char* lv_version(void);
  * transmittance stop, 2D dilation (px^2) and tile edge (px).  opts = NULL
  * means the defaults 0.99f, 1/255.f, 1e-4f, 0.3f, 16, which are also the
  * only values this build runs: others give LV_ERR_UNSUPPORTED (the kernels
- * and their exact FP32 decision sequence are compiled for them). */
+ * and their exact FP32 decision sequence are compiled for them).
+ * flags: by default the library stores the Gaussians in the Morton order
+ * of their centres (10 bits per axis over the scene's bounding box, equal
+ * codes in the caller's order), which gives the blend's reads of projected
+ * records and its accumulator updates spatial locality.  The order is
+ * internal: every per-Gaussian input and output (features, weight sums,
+ * counts, render inputs, graph nodes, debug views) stays in the caller's
+ * order, and Gaussians at exactly equal depth still blend in the order of
+ * their caller index, so results equal those of the caller's order up to
+ * the summation order of the accumulators.  LV_SCENE_CALLER_ORDER stores
+ * them in the caller's order instead. */
+#define LV_SCENE_CALLER_ORDER 1u
 typedef struct lv_scene_opts {
     float alpha_max, alpha_min, t_eps, dilation;
     int32_t tile;
+    uint32_t flags;
 } lv_scene_opts;
 
 /* Make a scene resident on the current device (Sec. 3.1 scene

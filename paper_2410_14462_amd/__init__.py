@@ -53,7 +53,10 @@ class lv_graph_opts(ctypes.Structure):
 
 class lv_scene_opts(ctypes.Structure):
     _fields_ = [("alpha_max", ctypes.c_float), ("alpha_min", ctypes.c_float), ("t_eps", ctypes.c_float),
-                ("dilation", ctypes.c_float), ("tile", ctypes.c_int32)]
+                ("dilation", ctypes.c_float), ("tile", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+LV_SCENE_CALLER_ORDER = 1
 
 
 class lv_server_opts(ctypes.Structure):
@@ -301,29 +304,34 @@ SCENE_DEFAULTS = (float(np.float32(0.99)), float(np.float32(1.0) / np.float32(25
 class Scene:
     """lv_scene: Gaussians resident on the GPU (means, scales, quats, opacity)."""
 
-    def __init__(self, means, scales, quats, opacity, opts=None):
+    def __init__(self, means, scales, quats, opacity, opts=None, order="morton"):
         """opts: None or a dict of lv_scene_opts fields (alpha_max, alpha_min,
-        t_eps, dilation, tile)."""
+        t_eps, dilation, tile).  order: "morton" (the library's default
+        storage order) or "caller" (LV_SCENE_CALLER_ORDER)."""
         n = means.shape[0]
         _dev_f32(means, (n, 3)); _dev_f32(scales, (n, 3)); _dev_f32(quats, (n, 4)); _dev_f32(opacity, (n,))
+        if order not in ("morton", "caller"):
+            raise ValueError(f"order must be 'morton' or 'caller', not {order!r}")
         h = ctypes.c_void_p()
         o = None
-        if opts is not None:
+        if opts is not None or order == "caller":
+            opts = opts or {}
             o = lv_scene_opts(*[opts.get(k, d) for k, d in (("alpha_max", SCENE_DEFAULTS[0]),
                                                                ("alpha_min", SCENE_DEFAULTS[1]),
                                                                ("t_eps", SCENE_DEFAULTS[2]),
                                                                ("dilation", SCENE_DEFAULTS[3]),
-                                                               ("tile", SCENE_DEFAULTS[4]))])
+                                                               ("tile", SCENE_DEFAULTS[4]))],
+                              LV_SCENE_CALLER_ORDER if order == "caller" else 0)
         _check(lib().lv_scene_create(_ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), n,
                                      ctypes.byref(o) if o is not None else None, _stream(),
                                      ctypes.byref(h)))
         self.handle, self.n = h, n
 
     @classmethod
-    def from_arrays(cls, scene, device="cuda"):
+    def from_arrays(cls, scene, device="cuda", order="morton"):
         import torch
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
-        return cls(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacity))
+        return cls(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacity), order=order)
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -18,6 +18,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+    # roctx ranges around the phases of a call (rocprofv3 --marker-trace)
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

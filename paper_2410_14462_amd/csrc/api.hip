@@ -189,7 +189,14 @@ int64_t chunk_budget_bytes(const Workspace* ws = nullptr) {
 struct lv_scene {
   int64_t n = 0;
   int device = 0;
-  Buf p0, p1, p2;
+  Buf p0, p1, p2;  // derived parameters, in storage order
+  // Morton storage order (unless LV_SCENE_CALLER_ORDER): perm maps a
+  // storage index to the caller's index, inv the reverse; p0c is p0 in the
+  // caller's order (the graph builder and the diffusion's own order read it)
+  bool morton = false;
+  Buf perm, inv, p0c;
+  const uint32_t* out_perm() const { return morton ? perm.as<uint32_t>() : nullptr; }
+  const float4* caller_p0() const { return morton ? p0c.as<float4>() : p0.as<float4>(); }
 };
 
 struct lv_accum {
@@ -246,6 +253,7 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
                           hipStream_t s, const uint32_t** ids, int* stride,
                           int64_t* P, int64_t* nvis, int* max_tiles_out,
                           int64_t pair_budget = INT64_MAX, bool* split = nullptr) {
+  TraceRange tr("lv.structure");
   if (split) *split = false;
   const int64_t n = sc->n;
   const int64_t items = n * (int64_t)mv;
@@ -309,6 +317,9 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   const uint32_t* sval = second ? ws.val1.as<uint32_t>() : ws.val0.as<uint32_t>();
   ws.dkey = second ? ws.key1.as<uint32_t>() : ws.key0.as<uint32_t>();
   ws.dval = sval;
+  if (sc->morton)  // equal depths blend in the caller's index order, as without the reorder
+    HIP_TRY(launch_depth_ties(ws.dkey, const_cast<uint32_t*>(sval), ws.srect.as<uint2>(),
+                              ws.scnt.as<uint32_t>(), n, mv, sc->perm.as<uint32_t>(), s));
   uint32_t* pseg = ws.pseg.as<uint32_t>();
   HIP_TRY(scan_counts(ws.scnt.as<uint32_t>(), nullptr, n, mv, ws.off.as<uint32_t>(), pseg, pseg + mv,
                       ws.total.as<unsigned long long>(), ws.scan_tmp.as<uint32_t>(), s));
@@ -573,15 +584,41 @@ lv_status lv_scene_create(const float* means, const float* scales, const float* 
   if (!sc) return fail(LV_ERR_OUT_OF_MEMORY, "host allocation");
   sc->n = n;
   (void)hipGetDevice(&sc->device);
+  sc->morton = n > 1 && !(opts && (opts->flags & LV_SCENE_CALLER_ORDER));
   size_t b = sizeof(float4) * (size_t)(n > 0 ? n : 1);
   hipError_t e = scene_buf(sc->p0, sc->device, b, s);
   if (e == hipSuccess) e = scene_buf(sc->p1, sc->device, b, s);
   if (e == hipSuccess) e = scene_buf(sc->p2, sc->device, b, s);
-  if (e == hipSuccess)
+  if (e == hipSuccess && !sc->morton)
     e = launch_scene_derive(means, scales, quats, opacity, n, sc->p0.as<float4>(), sc->p1.as<float4>(),
                             sc->p2.as<float4>(), s);
+  if (e == hipSuccess && sc->morton) {
+    // derive in the caller's order, order by the Morton code of the
+    // centres (stable: equal codes keep the caller's order), gather
+    void* c12 = nullptr;
+    void* scratch = nullptr;
+    const size_t scratch_bytes = 4 * reorder_scratch_words(n);
+    e = scene_buf(sc->p0c, sc->device, b, s);
+    if (e == hipSuccess) e = scene_buf(sc->perm, sc->device, 4 * (size_t)n, s);
+    if (e == hipSuccess) e = scene_buf(sc->inv, sc->device, 4 * (size_t)n, s);
+    if (e == hipSuccess) e = dev_alloc(&c12, 2 * b, s, true);
+    if (e == hipSuccess) e = dev_alloc(&scratch, scratch_bytes, s, true);
+    float4* c1 = static_cast<float4*>(c12);
+    if (e == hipSuccess)
+      e = launch_scene_derive(means, scales, quats, opacity, n, sc->p0c.as<float4>(), c1, c1 + n, s);
+    if (e == hipSuccess)
+      e = launch_morton_order(sc->p0c.as<float4>(), n, static_cast<uint32_t*>(scratch),
+                              sc->perm.as<uint32_t>(), sc->inv.as<uint32_t>(), s);
+    if (e == hipSuccess)
+      e = launch_gather_scene(sc->p0c.as<float4>(), c1, c1 + n, sc->perm.as<uint32_t>(), n,
+                              sc->p0.as<float4>(), sc->p1.as<float4>(), sc->p2.as<float4>(), s);
+    dev_free(scratch, scratch_bytes, s, true);
+    dev_free(c12, 2 * b, s, true);
+  }
   if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
     sc->p0.release(); sc->p1.release(); sc->p2.release();
+    sc->p0c.release(); sc->perm.release(); sc->inv.release();
     delete sc;
     return fail(e == hipErrorOutOfMemory ? LV_ERR_OUT_OF_MEMORY : LV_ERR_DEVICE, "scene: %s",
                 hipGetErrorString(e));
@@ -600,6 +637,9 @@ lv_status lv_scene_destroy(lv_scene* sc) {
   scene_buf_release(sc->device, sc->p0);
   scene_buf_release(sc->device, sc->p1);
   scene_buf_release(sc->device, sc->p2);
+  scene_buf_release(sc->device, sc->p0c);
+  scene_buf_release(sc->device, sc->perm);
+  scene_buf_release(sc->device, sc->inv);
   delete sc;
   return LV_OK;
 }
@@ -660,6 +700,7 @@ lv_status lv_accum_destroy(lv_accum* a) {
 
 lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_feature_set* fsets,
                                    int32_t nsets, lv_dtype dtype, void* stream) {
+  TraceRange tr("lv.uplift_accumulate");
   if (nsets < 1 || nsets > kMaxSets)
     return fail(LV_ERR_INVALID_ARG, "nsets = %d out of [1, %d]", nsets, kMaxSets);
   if (!fsets) return fail(LV_ERR_INVALID_ARG, "sets is NULL");
@@ -830,6 +871,7 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
     ba.ngroups = (int32_t)groups.size();
     ba.max_width = max_width;
     {
+      TraceRange tb("lv.blend");
       std::lock_guard<std::mutex> pk(g_prof_mu);
       if (g_prof_on) {
         hipEvent_t e0, e1;
@@ -880,8 +922,9 @@ lv_status lv_accum_finalize(lv_accum* a, float* out_feat, float* out_wsum, float
   if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
   if (a->scene->n > 0 && !out_feat && !out_wsum && !out_sum)
     return fail(LV_ERR_INVALID_ARG, "no output requested");
+  TraceRange tr("lv.finalize");
   HIP_TRY(launch_finalize(a->U.as<float>(), a->beta.as<beta_t>(), a->scene->n, a->D, out_feat,
-                          out_wsum, out_sum, static_cast<hipStream_t>(stream)));
+                          out_wsum, out_sum, a->scene->out_perm(), static_cast<hipStream_t>(stream)));
   return LV_OK;
 }
 
@@ -890,7 +933,7 @@ lv_status lv_accum_finalize_count(lv_accum* a, float* out_feat, void* stream) {
   if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");
   if (a->scene->n > 0 && !out_feat) return fail(LV_ERR_INVALID_ARG, "out_feat is NULL");
   HIP_TRY(launch_finalize_count(a->U.as<float>(), a->counts.as<uint32_t>(), a->scene->n, a->D,
-                                out_feat, static_cast<hipStream_t>(stream)));
+                                out_feat, a->scene->out_perm(), static_cast<hipStream_t>(stream)));
   return LV_OK;
 }
 
@@ -923,8 +966,12 @@ lv_status lv_accum_counts(lv_accum* a, uint32_t* out, void* stream) {
   if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");
   if (!out && a->scene->n > 0) return fail(LV_ERR_INVALID_ARG, "out is NULL");
   if (a->scene->n == 0) return LV_OK;
-  HIP_TRY(hipMemcpyAsync(out, a->counts.p, 4 * (size_t)a->scene->n, hipMemcpyDeviceToDevice,
-                         static_cast<hipStream_t>(stream)));
+  if (a->scene->morton)  // back to the caller's order
+    HIP_TRY(launch_permute_rows(a->counts.p, out, a->scene->perm.as<uint32_t>(), a->scene->n, 1, LV_F32,
+                                true, static_cast<hipStream_t>(stream)));
+  else
+    HIP_TRY(hipMemcpyAsync(out, a->counts.p, 4 * (size_t)a->scene->n, hipMemcpyDeviceToDevice,
+                           static_cast<hipStream_t>(stream)));
   return LV_OK;
 }
 
@@ -1117,6 +1164,7 @@ lv_status lv_graph_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, co
 
 lv_status lv_graph_build_knn(lv_scene* sc, const float* feats, int32_t D, int32_t k,
                              const lv_graph_opts* opts, void* stream, lv_graph** out) {
+  TraceRange tr("lv.graph_build_knn");
   if (!out) return fail(LV_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!sc || !feats) return fail(LV_ERR_INVALID_ARG, "null argument");
@@ -1143,7 +1191,7 @@ lv_status lv_graph_build_knn(lv_scene* sc, const float* feats, int32_t D, int32_
   int32_t *rp = nullptr, *cl = nullptr;
   float* vl = nullptr;
   int64_t nnz = 0;
-  HIP_TRY(build_knn_graph(sc->p0.as<float4>(), n, feats, D, k, gw, s, &rp, &cl, &vl, &nnz));
+  HIP_TRY(build_knn_graph(sc->caller_p0(), n, feats, D, k, gw, s, &rp, &cl, &vl, &nnz));
   lv_graph* g = new (std::nothrow) lv_graph();
   if (!g) {
     (void)hipStreamSynchronize(s);
@@ -1189,6 +1237,7 @@ lv_status lv_graph_destroy(lv_graph* g) {
 
 lv_status lv_diffuse(const lv_scene* sc, const lv_graph* gc, const void* g0, lv_dtype dtype, int32_t D,
                      int32_t steps, void* out, void* stream) {
+  TraceRange tr("lv.diffuse");
   if (!gc) return fail(LV_ERR_INVALID_ARG, "graph is NULL");
   if (sc && sc->n != gc->n) return fail(LV_ERR_INVALID_ARG, "scene and graph sizes differ");
   if (D < 1 || D > 4096 || steps < 0) return fail(LV_ERR_INVALID_ARG, "bad D or steps");
@@ -1217,7 +1266,7 @@ lv_status lv_diffuse(const lv_scene* sc, const lv_graph* gc, const void* g0, lv_
     if (e == hipSuccess) e = g->col2.ensure(4 * (size_t)(nnz + 1), s);
     if (e == hipSuccess) e = g->val2.ensure(dtype_size(g->val_dtype) * (size_t)(nnz + 1), s);
     if (e == hipSuccess)
-      e = launch_graph_reorder(sc->p0.as<float4>(), n, g->row_ptr.as<int32_t>(), g->col.as<int32_t>(),
+      e = launch_graph_reorder(sc->caller_p0(), n, g->row_ptr.as<int32_t>(), g->col.as<int32_t>(),
                                g->val.p, g->val_dtype, nnz, scratch.as<uint32_t>(),
                                g->perm.as<uint32_t>(), g->inv.as<uint32_t>(), g->rp2.as<int32_t>(),
                                g->col2.as<int32_t>(), g->val2.p, s);
@@ -1246,6 +1295,7 @@ lv_status lv_diffuse(const lv_scene* sc, const lv_graph* gc, const void* g0, lv_
 
 lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float* g, int32_t D,
                     float* const* outs, float* const* alphas, void* stream) {
+  TraceRange tr("lv.render");
   if (!sc) return fail(LV_ERR_INVALID_ARG, "scene is NULL");
   if (D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "D = %d out of [1, 4096]", D);
   lv_status st = check_cams(cams, m);
@@ -1263,6 +1313,24 @@ lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float*
     if (alphas && alphas[v]) HIP_TRY(hipMemsetAsync(alphas[v], 0, sizeof(float) * px, s));
   }
   if (n == 0 || m == 0) return LV_OK;
+  // g in the scene's storage order
+  void* gs = nullptr;
+  const size_t gs_bytes = sizeof(float) * (size_t)n * D;
+  if (sc->morton) {
+    HIP_TRY(dev_alloc(&gs, gs_bytes, s, true));
+    const hipError_t e = launch_permute_rows(g, gs, sc->perm.as<uint32_t>(), n, D, LV_F32, false, s);
+    if (e != hipSuccess) {
+      dev_free(gs, gs_bytes, s, true);
+      return fail(LV_ERR_DEVICE, "render: %s", hipGetErrorString(e));
+    }
+    g = static_cast<const float*>(gs);
+  }
+  struct TempFree {  // returned to the allocator on the stream, whatever the exit
+    void* p;
+    size_t bytes;
+    hipStream_t s;
+    ~TempFree() { dev_free(p, bytes, s, true); }
+  } gs_free{gs, gs_bytes, s};
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
   const int64_t per_view = n * kItemBytes;
@@ -1337,26 +1405,35 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
   HIP_TRY(hipMemcpy(sk.data(), ws.dkey, 4 * n, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(sv.data(), ws.dval, 4 * n, hipMemcpyDeviceToHost));
   for (int64_t k = 0; k < n; k++) key[sv[k]] = sk[k];
-  for (int64_t i = 0; i < n; i++) {
+  // storage index -> the caller's index (the identity without the Morton order)
+  std::vector<uint32_t> perm(n);
+  if (sc->morton)
+    HIP_TRY(hipMemcpy(perm.data(), sc->perm.p, 4 * n, hipMemcpyDeviceToHost));
+  else
+    for (int64_t i = 0; i < n; i++) perm[i] = (uint32_t)i;
+  for (int64_t si = 0; si < n; si++) {
+    const int64_t i = perm[si];  // outputs at the caller's index
+    const Rec& rc = rec[si];
+    const uint2& rt = rect[si];
     // visible: a non-empty tile rectangle (culled items keep the empty one)
-    const bool vis = (rect[i].y & 0xFFFFu) > (rect[i].x & 0xFFFFu) && (rect[i].y >> 16) > (rect[i].x >> 16);
+    const bool vis = (rt.y & 0xFFFFu) > (rt.x & 0xFFFFu) && (rt.y >> 16) > (rt.x >> 16);
     if (out->visible) out->visible[i] = vis ? 1 : 0;
-    if (out->depth) out->depth[i] = key[i];
+    if (out->depth) out->depth[i] = key[si];
     if (out->rect) {
-      out->rect[4 * i] = (int32_t)(rect[i].x & 0xFFFF);
-      out->rect[4 * i + 1] = (int32_t)(rect[i].x >> 16);
-      out->rect[4 * i + 2] = (int32_t)(rect[i].y & 0xFFFF);
-      out->rect[4 * i + 3] = (int32_t)(rect[i].y >> 16);
+      out->rect[4 * i] = (int32_t)(rt.x & 0xFFFF);
+      out->rect[4 * i + 1] = (int32_t)(rt.x >> 16);
+      out->rect[4 * i + 2] = (int32_t)(rt.y & 0xFFFF);
+      out->rect[4 * i + 3] = (int32_t)(rt.y >> 16);
     }
     if (out->rec) {
       float* r = out->rec + 8 * i;
       uint32_t lo;
-      memcpy(&lo, &rec[i].r1.w, 4);
+      memcpy(&lo, &rc.r1.w, 4);
       const uint32_t lx = lo << 16, ly = lo & 0xFFFF0000u;
-      r[0] = rec[i].r0.x; r[1] = rec[i].r0.y;
+      r[0] = rc.r0.x; r[1] = rc.r0.y;
       memcpy(&r[2], &lx, 4);
       memcpy(&r[3], &ly, 4);
-      r[4] = rec[i].r0.z; r[5] = rec[i].r0.w; r[6] = rec[i].r1.x; r[7] = rec[i].r1.y;
+      r[4] = rc.r0.z; r[5] = rc.r0.w; r[6] = rc.r1.x; r[7] = rc.r1.y;
     }
   }
   if (out->tile_start) {
@@ -1369,8 +1446,11 @@ lv_status lv_debug_view(lv_scene* sc, const lv_camera* cam, lv_view_debug* out, 
     }
     out->tile_start[max_tiles] = run;
   }
-  if (out->ids && out->ids_capacity >= P && P > 0)
+  if (out->ids && out->ids_capacity >= P && P > 0) {
     HIP_TRY(hipMemcpy(out->ids, ids, 4 * (size_t)P, hipMemcpyDeviceToHost));
+    if (sc->morton)
+      for (int64_t k = 0; k < P; k++) out->ids[k] = perm[out->ids[k]];
+  }
   return LV_OK;
 }
 

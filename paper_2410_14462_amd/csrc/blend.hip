@@ -1169,34 +1169,38 @@ __global__ __launch_bounds__(256) void finalize4_kernel(const float4* __restrict
                                                         const beta_t* __restrict__ beta, int64_t n,
                                                         int Q, float4* __restrict__ f,
                                                         float* __restrict__ wsum,
-                                                        float4* __restrict__ usum) {
+                                                        float4* __restrict__ usum,
+                                                        const uint32_t* __restrict__ perm) {
   const int64_t r0 = (int64_t)blockIdx.x * kFinRows;
   const int rows = (int)(n - r0 < kFinRows ? n - r0 : kFinRows);
   for (int k = threadIdx.x; k < rows * Q; k += 256) {
     const int r = k / Q, q = k - r * Q;
     const int64_t i = r0 + r;
+    const int64_t o = perm ? (int64_t)perm[i] : i;  // the output row
     const float bs = (float)((double)beta[i] * (1.0 / kBetaUnit));
-    const int64_t e = i * Q + q;
-    const float4 u = U[e];
+    const float4 u = U[i * Q + q];
+    const int64_t e = o * Q + q;
     if (f)
       f[e] = bs > 0.0f ? make_float4(u.x / bs, u.y / bs, u.z / bs, u.w / bs)
                        : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (usum) usum[e] = u;
-    if (wsum && q == 0) wsum[i] = bs;
+    if (wsum && q == 0) wsum[o] = bs;
   }
 }
 
 __global__ void finalize_kernel(const float* __restrict__ U, const beta_t* __restrict__ beta,
                                 int64_t n, int D, float* __restrict__ f, float* __restrict__ wsum,
-                                float* __restrict__ usum) {
+                                float* __restrict__ usum, const uint32_t* __restrict__ perm) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * D) return;
   int64_t i = e / D;
+  const int64_t c = e - i * D;
+  const int64_t o = perm ? (int64_t)perm[i] : i;  // the output row
   const float bs = (float)((double)beta[i] * (1.0 / kBetaUnit));
   float u = U[e];
-  if (f) f[e] = bs > 0.0f ? u / bs : 0.0f;
-  if (usum) usum[e] = u;
-  if (wsum && e - i * D == 0) wsum[i] = bs;
+  if (f) f[o * D + c] = bs > 0.0f ? u / bs : 0.0f;
+  if (usum) usum[o * D + c] = u;
+  if (wsum && c == 0) wsum[o] = bs;
 }
 
 }  // namespace
@@ -1249,18 +1253,18 @@ hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float
 }
 
 hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,
-                           float* wsum, float* usum, hipStream_t s) {
+                           float* wsum, float* usum, const uint32_t* perm, hipStream_t s) {
   int64_t total = n * (int64_t)D;
   if (total == 0) return hipSuccess;
   const auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   if (D % 4 == 0 && a16(U) && a16(f) && a16(usum)) {
     hipLaunchKernelGGL(finalize4_kernel, dim3((unsigned)((n + kFinRows - 1) / kFinRows)), dim3(256), 0, s,
                        reinterpret_cast<const float4*>(U), beta, n, D / 4, reinterpret_cast<float4*>(f),
-                       wsum, reinterpret_cast<float4*>(usum));
+                       wsum, reinterpret_cast<float4*>(usum), perm);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, U,
-                     beta, n, D, f, wsum, usum);
+                     beta, n, D, f, wsum, usum, perm);
   return hipGetLastError();
 }
 

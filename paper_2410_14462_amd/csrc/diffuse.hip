@@ -417,12 +417,24 @@ __global__ __launch_bounds__(256) void box_kernel(const float4* __restrict__ p0,
       hi[k] = h > hi[k] ? h : hi[k];
     }
   }
+  // the block's four waves through LDS, then one atomic per bound and block
+  // (few blocks: the six words would serialise thousands of wave atomics)
+  __shared__ uint32_t wb[4][6];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      atomicMin(&box[k], lo[k]);
-      atomicMax(&box[3 + k], hi[k]);
+      wb[w][k] = lo[k];
+      wb[w][3 + k] = hi[k];
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    uint32_t r = wb[0][k];
+    for (int q = 1; q < (int)(blockDim.x >> 6); q++) r = k < 3 ? (wb[q][k] < r ? wb[q][k] : r) : (wb[q][k] > r ? wb[q][k] : r);
+    if (k < 3) atomicMin(&box[k], r);
+    else atomicMax(&box[k], r);
   }
 }
 
@@ -454,7 +466,7 @@ __global__ void morton_kernel(const float4* __restrict__ p0, int64_t n,
   }
   key[i] = code;
   val[i] = (uint32_t)i;
-  deg[i] = (uint32_t)(row_ptr[i + 1] - row_ptr[i]);
+  if (row_ptr) deg[i] = (uint32_t)(row_ptr[i + 1] - row_ptr[i]);
 }
 
 // One sort segment covering all n items.
@@ -528,6 +540,29 @@ size_t reorder_scratch_words(int64_t n) {
   return (size_t)n * 6 + 16 + sort_hist_size(1, n) + scan_tmp_size(n);
 }
 
+hipError_t launch_morton_order(const float4* p0, int64_t n, uint32_t* scratch, uint32_t* perm,
+                               uint32_t* inv, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint32_t* k0 = scratch;
+  uint32_t* v0 = k0 + n;
+  uint32_t* k1 = v0 + n;
+  uint32_t* v1 = k1 + n;
+  uint32_t* box = v1 + n;  // within reorder_scratch_words(n)
+  uint32_t* seg = box + 6;
+  uint32_t* hist = box + 16;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(box_init_kernel, dim3(1), dim3(64), 0, s, box);
+  hipLaunchKernelGGL(box_kernel, dim3(nb < 256 ? nb : 256), dim3(256), 0, s, p0, n, box);
+  hipLaunchKernelGGL(morton_kernel, dim3(nb), dim3(256), 0, s, p0, n, box, k0, v0, nullptr, nullptr);
+  hipLaunchKernelGGL(seg_init_kernel, dim3(1), dim3(64), 0, s, seg, n);
+  bool second = false;
+  hipError_t e = radix_sort(k0, v0, k1, v1, seg, seg + 1, 1, n, 30, hist, false, &second, s);
+  if (e != hipSuccess) return e;
+  const uint32_t* sorted = second ? v1 : v0;
+  hipLaunchKernelGGL(invert_kernel, dim3(nb), dim3(256), 0, s, sorted, n, inv);
+  return hipMemcpyAsync(perm, sorted, 4 * (size_t)n, hipMemcpyDeviceToDevice, s);
+}
+
 hipError_t launch_graph_reorder(const float4* p0, int64_t n, const int32_t* rp, const int32_t* col,
                                 const void* val, lv_dtype vt, int64_t nnz, uint32_t* scratch,
                                 uint32_t* perm, uint32_t* inv, int32_t* rp2, int32_t* col2,
@@ -546,7 +581,7 @@ hipError_t launch_graph_reorder(const float4* p0, int64_t n, const int32_t* rp, 
   uint32_t* tmp = hist + sort_hist_size(1, n);
   const unsigned nb = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(box_init_kernel, dim3(1), dim3(64), 0, s, box);
-  hipLaunchKernelGGL(box_kernel, dim3(nb < 1024 ? nb : 1024), dim3(256), 0, s, p0, n, box);
+  hipLaunchKernelGGL(box_kernel, dim3(nb < 256 ? nb : 256), dim3(256), 0, s, p0, n, box);
   hipLaunchKernelGGL(morton_kernel, dim3(nb), dim3(256), 0, s, p0, n, box, k0, v0, deg, rp);
   hipLaunchKernelGGL(seg_init_kernel, dim3(1), dim3(64), 0, s, seg, n);
   bool second = false;

@@ -44,6 +44,27 @@ hipError_t launch_scene_derive(const float* means, const float* scales, const fl
   return hipGetLastError();
 }
 
+__global__ void gather_scene_kernel(const float4* __restrict__ c0, const float4* __restrict__ c1,
+                                    const float4* __restrict__ c2, const uint32_t* __restrict__ perm,
+                                    int64_t n, float4* __restrict__ p0, float4* __restrict__ p1,
+                                    float4* __restrict__ p2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = perm[i];
+  p0[i] = c0[j];
+  p1[i] = c1[j];
+  p2[i] = c2[j];
+}
+
+hipError_t launch_gather_scene(const float4* c0, const float4* c1, const float4* c2,
+                               const uint32_t* perm, int64_t n, float4* p0, float4* p1, float4* p2,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_scene_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c0, c1, c2,
+                     perm, n, p0, p1, p2);
+  return hipGetLastError();
+}
+
 // Error-free transformations for the projected centre.  Pixel coordinates
 // reach ~10^3 px, where one FP32 ulp (6e-5 px) already shifts the exponent of
 // a compact Gaussian by ~1e-4, so the centre is carried as hi + lo: TwoSum

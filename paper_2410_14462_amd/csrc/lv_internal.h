@@ -4,11 +4,22 @@
 // structure and the blend decisions reproducible bit for bit.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include "lv.h"
 
 namespace lv {
+
+// A named roctx range over a host scope (the phases of a call, the
+// server's passes): visible in `rocprofv3 --marker-trace`, free without a
+// tool attached.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 constexpr int kTile = 16;           // tile edge in pixels
 constexpr int kChunk = 64;          // Gaussians per blend step (one per lane)
@@ -247,11 +258,12 @@ hipError_t launch_anchor_init(const float* g, int64_t n, float fraction, float* 
 // h[i][c] = unary[i] where gT[i][c] > 0, else 0.
 hipError_t launch_reach_unary(const float* gT, const float* unary, int64_t n, int D, float* h,
                               hipStream_t s);
-// f = U / cnt per Gaussian (0 where cnt = 0).
+// f = U / cnt per Gaussian (0 where cnt = 0).  Outputs of row i go to row
+// perm[i] when perm is given (a scene stored in Morton order), else to i.
 hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n, int D, float* f,
-                                 hipStream_t s);
+                                 const uint32_t* perm, hipStream_t s);
 hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,
-                           float* wsum, float* usum, hipStream_t s);
+                           float* wsum, float* usum, const uint32_t* perm, hipStream_t s);
 
 // Feature-map formats: valid uplift input, element type, pixel-block layout.
 inline bool map_format_valid(lv_dtype d) { return d >= LV_F32 && d <= LV_FP8_E4M3_PX8; }
@@ -294,6 +306,20 @@ hipError_t launch_graph_reorder(const float4* p0, int64_t n, const int32_t* rp, 
                                 const void* val, lv_dtype vt, int64_t nnz, uint32_t* scratch,
                                 uint32_t* perm, uint32_t* inv, int32_t* rp2, int32_t* col2,
                                 void* val2, hipStream_t s);
+// The same Morton order without a graph: perm (position -> index) and its
+// inverse; scratch holds reorder_scratch_words(n) uint32.
+hipError_t launch_morton_order(const float4* p0, int64_t n, uint32_t* scratch, uint32_t* perm,
+                               uint32_t* inv, hipStream_t s);
+// Scene storage in that order: dst_k[i] = src_k[perm[i]] for the three
+// derived arrays.
+hipError_t launch_gather_scene(const float4* c0, const float4* c1, const float4* c2,
+                               const uint32_t* perm, int64_t n, float4* p0, float4* p1, float4* p2,
+                               hipStream_t s);
+// Gaussians at exactly equal depth, stored in Morton order, back in the
+// order of their caller index: within each run of equal (visible) depth keys
+// of the depth-sorted views, (id, rect, count) sorted by perm[id].
+hipError_t launch_depth_ties(const uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt, int64_t n,
+                             int mv, const uint32_t* perm, hipStream_t s);
 // dst[r] = src[perm[r]] (gather) or dst[perm[r]] = src[r] (scatter), rows of D.
 hipError_t launch_permute_rows(const void* src, void* dst, const uint32_t* perm, int64_t n, int D,
                                lv_dtype dt, bool scatter, hipStream_t s);

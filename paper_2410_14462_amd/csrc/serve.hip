@@ -168,6 +168,7 @@ lv_status lv_server::run_pass(std::vector<ServeReq*>& reqs, hipStream_t s) {
       sets[k].out_feat = reqs[k]->out_feat;
       sets[k].out_wsum = reqs[k]->out_wsum;
     }
+    lv::TraceRange tr("lv.server_pass");
     st = lv::run_batch(reqs[0]->scene, ucams.data(), (int32_t)um, sets.data(), nb, reqs[0]->dtype, s);
   }
   for (int k = 0; k < nb; k++) lv::dev_free(scl[k], scl_bytes[k], s, true);

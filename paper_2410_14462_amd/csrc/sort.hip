@@ -603,7 +603,115 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict_
   }
 }
 
+// Exact depth ties of a scene stored in Morton order, back in the caller's
+// index order.  Four consecutive depth-sorted items per thread (one 16-byte
+// load where the keys are 16-byte aligned) over the mv views' segments of n
+// items.  A lane first finds the runs (two or more equal visible keys
+// within a view) that start among its items, at most two, then handles them
+// together: a pair (by far the commonest tie) is one compare of the two
+// caller indices and a swap, with the loads of both runs in flight at once;
+// longer runs are insertion-sorted by caller index.
+__global__ __launch_bounds__(256) void depth_ties_kernel(const uint32_t* __restrict__ key,
+                                                         uint32_t* __restrict__ val,
+                                                         uint2* __restrict__ rect,
+                                                         uint32_t* __restrict__ cnt, int64_t n,
+                                                         int64_t total, bool aligned,
+                                                         const uint32_t* __restrict__ perm) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e0 = 4 * q;
+  if (e0 >= total) return;
+  uint32_t k[4];
+  if (aligned && e0 + 4 <= total) {
+    const uint4 v = reinterpret_cast<const uint4*>(key)[q];
+    k[0] = v.x;
+    k[1] = v.y;
+    k[2] = v.z;
+    k[3] = v.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; j++) k[j] = e0 + j < total ? key[e0 + j] : 0xFFFFFFFFu;
+  }
+  if (k[0] == 0xFFFFFFFFu && k[1] == 0xFFFFFFFFu && k[2] == 0xFFFFFFFFu && k[3] == 0xFFFFFFFFu)
+    return;  // culled items (they sort last in their view)
+  const uint32_t before = e0 > 0 ? key[e0 - 1] : 0xFFFFFFFFu;
+  const uint32_t after = e0 + 4 < total ? key[e0 + 4] : 0xFFFFFFFFu;
+  int64_t st[2] = {0, 0}, ve[2] = {0, 0};  // run starts and the end of their view
+  int ns = 0;
+  int64_t vs = e0 / n * n;  // the segment of the view item e0 is in
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int64_t e = e0 + j;
+    if (e >= total) break;
+    while (e >= vs + n) vs += n;  // views of fewer than four items
+    const uint32_t kk = k[j];
+    if (kk == 0xFFFFFFFFu || e + 1 >= vs + n) continue;               // culled, or the view's last item
+    if ((j < 3 ? k[j + 1] : after) != kk) continue;                     // no tie after it
+    if (e > vs && (j > 0 ? k[j - 1] : before) == kk) continue;         // not the run's first item
+    st[ns < 2 ? ns : 1] = e;  // at most two starts among four items
+    ve[ns < 2 ? ns : 1] = vs + n;
+    ns++;
+  }
+  if (ns == 0) return;
+  uint32_t a[2], b[2];
+  bool longer[2];
+#pragma unroll
+  for (int t = 0; t < 2; t++) {
+    const int64_t e = st[t];
+    const bool on = t < ns;
+    a[t] = on ? val[e] : 0u;
+    b[t] = on ? val[e + 1] : 0u;
+    longer[t] = on && e + 2 < ve[t] && key[e + 2] == key[e];
+  }
+#pragma unroll
+  for (int t = 0; t < 2; t++) {
+    const int64_t e = st[t];
+    if (t < ns && !longer[t] && perm[a[t]] > perm[b[t]]) {
+      const uint2 r0 = rect[e], r1 = rect[e + 1];
+      const uint32_t c0 = cnt[e], c1 = cnt[e + 1];
+      val[e] = b[t];
+      val[e + 1] = a[t];
+      rect[e] = r1;
+      rect[e + 1] = r0;
+      cnt[e] = c1;
+      cnt[e + 1] = c0;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; t++) {
+    if (t >= ns || !longer[t]) continue;
+    const int64_t e = st[t];
+    const uint32_t kk = key[e];
+    int64_t r = e + 3;
+    while (r < ve[t] && key[r] == kk) r++;
+    for (int64_t i = e + 1; i < r; i++) {
+      const uint32_t v = val[i], pv = perm[v];
+      const uint2 rc = rect[i];
+      const uint32_t c = cnt[i];
+      int64_t u = i;
+      while (u > e && perm[val[u - 1]] > pv) {
+        val[u] = val[u - 1];
+        rect[u] = rect[u - 1];
+        cnt[u] = cnt[u - 1];
+        u--;
+      }
+      val[u] = v;
+      rect[u] = rc;
+      cnt[u] = c;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_depth_ties(const uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt, int64_t n,
+                             int mv, const uint32_t* perm, hipStream_t s) {
+  if (n < 2 || mv == 0) return hipSuccess;
+  const int64_t total = n * (int64_t)mv, quads = (total + 3) / 4;
+  const bool aligned = ((uintptr_t)key & 15) == 0;
+  hipLaunchKernelGGL(depth_ties_kernel, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, key, val,
+                     rect, cnt, n, total, aligned, perm);
+  return hipGetLastError();
+}
 
 size_t sort_hist_size(int nseg, int64_t max_len) {
   int64_t nb = (max_len + kSortItems - 1) / kSortItems;

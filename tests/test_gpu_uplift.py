@@ -63,6 +63,63 @@ def test_structure_bit_exact_two_pass_tile_sort():
         assert check_structure(gs, sc, cam) > 10000
 
 
+def tie_scene():
+    """3,000 Gaussians on two planes z = 0 and z = 0.1 (positions shuffled, so
+    the Morton order of the centres is far from the index order) and 2,000
+    in the volume: a camera on the z axis sees each plane at one exact FP32
+    depth, i.e. runs of ~1,500 equal depth keys."""
+    rng = np.random.default_rng(11)
+    base = scenes.make_scene(21, 5000, -3.6, 0.4, 0.5, 1.0)
+    means = base.means.copy()
+    means[:3000, 2] = np.where(rng.random(3000) < 0.5, 0.0, 0.1).astype(np.float32)
+    return Scene(means, base.scales, base.quats, base.opacity)
+
+
+def test_morton_storage_order_is_internal():
+    """The default Morton storage order against LV_SCENE_CALLER_ORDER and the
+    oracle: structure bit-exact (exact depth ties blend in the caller's index
+    order), weight sums (fixed point) and counts equal, features and renders
+    equal up to the summation order, outputs in the caller's order."""
+    sc = tie_scene()
+    cams = [scenes.look_at((0.0, 0.0, 4.0), 160, 120, 60.0)]
+    cams += [scenes.look_at(e, 150, 110, 60.0) for e in scenes.fibonacci_eyes(2, 4.0)]
+    gm = lv.Scene.from_arrays(sc)
+    gc = lv.Scene.from_arrays(sc, order="caller")
+    for cam in cams:
+        check_structure(gm, sc, cam)
+        a, b = gm.debug_view(cam), gc.debug_view(cam)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    D = 6
+    maps = [torch.as_tensor(philox.normal(31, v, c.height * c.width * D).reshape(c.height, c.width, D),
+                            device="cuda") for v, c in enumerate(cams)]
+    res = {}
+    for name, g in (("morton", gm), ("caller", gc)):
+        acc = lv.Accum(g, D, counts=True)
+        acc.add(cams, maps)
+        f, b, u = acc.finalize(want_sum=True)
+        res[name] = (f.cpu().numpy(), b.cpu().numpy(), u.cpu().numpy(), acc.counts().cpu().numpy(),
+                     acc.finalize_count().cpu().numpy())
+        acc.close()
+    fm, bm, um, cm, qm = res["morton"]
+    fc, bc, uc, cc, qc = res["caller"]
+    assert np.array_equal(bm, bc) and np.array_equal(cm, cc)
+    scale = max(1.0, float(np.abs(fc).max()))
+    assert np.abs(fm - fc).max() <= 1e-5 * scale
+    assert np.abs(um - uc).max() <= 1e-5 * max(1.0, float(np.abs(uc).max()))
+    assert np.abs(qm - qc).max() <= 1e-5 * max(1.0, float(np.abs(qc).max()))
+    ref = oracle.uplift(sc, cams, [m.cpu().numpy() for m in maps])
+    assert counts_match(cm, ref)
+    assert feature_error(fm, ref).max() < 1e-4 and beta_error(bm, ref).max() < 1e-4
+    # the forward render reads g in the caller's order
+    g = torch.as_tensor(philox.uniform(32, 0, sc.n * 3).reshape(sc.n, 3), device="cuda")
+    (om, am), (oc, ac) = gm.render(cams, g), gc.render(cams, g)
+    for x, y in zip(om + am, oc + ac):
+        assert torch.allclose(x, y, rtol=1e-5, atol=1e-6)
+    gm.close()
+    gc.close()
+
+
 @pytest.fixture(scope="module")
 def tiny():
     w = scenes.WORKLOADS["tiny"]
