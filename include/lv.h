@@ -213,8 +213,18 @@ lv_status lv_uplift_sets(lv_scene* scene, const lv_camera* cams, int32_t m, cons
  * weight per Gaussian), to which views are added in any grouping
  * (accumulating views [0,k) then [k,m) equals all m).  With
  * LV_ACCUM_COUNTS it also counts, per Gaussian, the (view, pixel) pairs
- * that contribute (exact integers). */
+ * that contribute (exact integers).
+ * LV_ACCUM_DETERMINISTIC: U too is 64-bit fixed point (units of 2^-35: each
+ * partial sum is rounded to the nearest unit and added with an integer
+ * atomic), so U, beta and the features are the same bit for bit from run to
+ * run and for any grouping of the views, and a comparison with the FP32
+ * accumulator exposes lost updates.  Limits: |U_ic| < 2^28, absolute
+ * rounding up to 2^-36 per partial sum (against the FP32 accumulator's
+ * relative 2^-24), twice the accumulator memory and the integer atomics'
+ * traffic.  All accumulators of one call take the same mode (else
+ * LV_ERR_INVALID_ARG). */
 #define LV_ACCUM_COUNTS 1u
+#define LV_ACCUM_DETERMINISTIC 2u
 lv_status lv_accum_create(lv_scene* scene, int32_t D, uint32_t flags, void* stream, lv_accum** out);
 lv_status lv_accum_reset(lv_accum* acc, void* stream);
 lv_status lv_uplift_accumulate(lv_accum* acc, const lv_camera* cams, int32_t m,

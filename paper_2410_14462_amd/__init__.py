@@ -19,6 +19,7 @@ LV_ERR_CANCELLED = 5
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 LV_ACCUM_COUNTS = 1
+LV_ACCUM_DETERMINISTIC = 2
 LV_GRAPH_SPATIAL_COSINE, LV_GRAPH_FEATURE_RBF = 0, 1
 _DTYPES = {"f32": LV_F32, "bf16": LV_BF16, "fp8": LV_FP8_E4M3,
            "f32_px8": LV_F32_PX8, "bf16_px8": LV_BF16_PX8, "fp8_px8": LV_FP8_E4M3_PX8}
@@ -416,10 +417,12 @@ class Scene:
 class Accum:
     """lv_accum: streaming accumulator U = W^T F, beta (and counts)."""
 
-    def __init__(self, scene, D, counts=False):
+    def __init__(self, scene, D, counts=False, deterministic=False):
+        """deterministic: U in 64-bit fixed point (LV_ACCUM_DETERMINISTIC),
+        the same bit for bit whatever the order of the updates."""
         h = ctypes.c_void_p()
-        _check(lib().lv_accum_create(scene.handle, D, LV_ACCUM_COUNTS if counts else 0, _stream(),
-                                     ctypes.byref(h)))
+        flags = (LV_ACCUM_COUNTS if counts else 0) | (LV_ACCUM_DETERMINISTIC if deterministic else 0)
+        _check(lib().lv_accum_create(scene.handle, D, flags, _stream(), ctypes.byref(h)))
         self.handle, self.scene, self.D = h, scene, D
 
     def close(self):

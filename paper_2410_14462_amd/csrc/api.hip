@@ -203,6 +203,8 @@ struct lv_accum {
   lv_scene* scene = nullptr;
   int32_t D = 0;
   uint32_t flags = 0;
+  bool fixed() const { return (flags & LV_ACCUM_DETERMINISTIC) != 0; }
+  size_t u_elem_bytes() const { return fixed() ? 8 : 4; }
   Buf U, beta, counts, dstats;
   int64_t views = 0, pairs = 0, visible = 0;
 };
@@ -651,7 +653,8 @@ lv_status lv_accum_create(lv_scene* sc, int32_t D, uint32_t flags, void* stream,
   *out = nullptr;
   if (!sc) return fail(LV_ERR_INVALID_ARG, "scene is NULL");
   if (D < 1 || D > 4096) return fail(LV_ERR_INVALID_ARG, "D = %d out of [1, 4096]", D);
-  if (flags & ~LV_ACCUM_COUNTS) return fail(LV_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(LV_ACCUM_COUNTS | LV_ACCUM_DETERMINISTIC))
+    return fail(LV_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   hipStream_t s = static_cast<hipStream_t>(stream);
   lv_accum* a = new (std::nothrow) lv_accum();
   if (!a) return fail(LV_ERR_OUT_OF_MEMORY, "host allocation");
@@ -659,7 +662,7 @@ lv_status lv_accum_create(lv_scene* sc, int32_t D, uint32_t flags, void* stream,
   a->D = D;
   a->flags = flags;
   size_t n1 = (size_t)(sc->n > 0 ? sc->n : 1);
-  hipError_t e = a->U.ensure(sizeof(float) * n1 * D, s);
+  hipError_t e = a->U.ensure(a->u_elem_bytes() * n1 * D, s);
   if (e == hipSuccess) e = a->beta.ensure(sizeof(beta_t) * n1, s);
   if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->counts.ensure(4 * n1, s);
   if (e == hipSuccess && (flags & LV_ACCUM_COUNTS)) e = a->dstats.ensure(24, s);
@@ -684,7 +687,7 @@ lv_status lv_accum_reset(lv_accum* a, void* stream) {
   a->views = a->pairs = a->visible = 0;
   if (a->dstats.p) HIP_TRY(hipMemsetAsync(a->dstats.p, 0, 24, s));
   if (n == 0) return LV_OK;
-  HIP_TRY(hipMemsetAsync(a->U.p, 0, sizeof(float) * n * a->D, s));
+  HIP_TRY(hipMemsetAsync(a->U.p, 0, a->u_elem_bytes() * n * a->D, s));
   HIP_TRY(hipMemsetAsync(a->beta.p, 0, sizeof(beta_t) * n, s));
   if (a->counts.p) HIP_TRY(hipMemsetAsync(a->counts.p, 0, 4 * n, s));
   return LV_OK;
@@ -715,6 +718,8 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
     for (int q = 0; q < k; q++)
       if (fsets[q].acc == fsets[k].acc)
         return fail(LV_ERR_INVALID_ARG, "set %d repeats the accumulator of set %d", k, q);
+    if (fsets[k].acc->fixed() != fsets[0].acc->fixed())
+      return fail(LV_ERR_INVALID_ARG, "set %d: deterministic and FP32 accumulators in one call", k);
     sc = fsets[k].acc->scene;
     st = check_maps(fsets[k].maps, m, dtype, fsets[k].scales, true);
     if (st != LV_OK) return st;
@@ -842,6 +847,7 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
       sd[k].maps = reinterpret_cast<const void* const*>(dev + b_sets + b_groups) + (size_t)k * mv;
       sd[k].scales = fsets[k].scales;
       sd[k].U = a->U.as<float>();
+      sd[k].fixed = a->fixed() ? 1 : 0;
       sd[k].beta = a->beta.as<beta_t>();
       sd[k].counts = a->counts.as<uint32_t>();
       sd[k].stats = a->dstats.as<unsigned long long>();
@@ -923,8 +929,12 @@ lv_status lv_accum_finalize(lv_accum* a, float* out_feat, float* out_wsum, float
   if (a->scene->n > 0 && !out_feat && !out_wsum && !out_sum)
     return fail(LV_ERR_INVALID_ARG, "no output requested");
   TraceRange tr("lv.finalize");
-  HIP_TRY(launch_finalize(a->U.as<float>(), a->beta.as<beta_t>(), a->scene->n, a->D, out_feat,
-                          out_wsum, out_sum, a->scene->out_perm(), static_cast<hipStream_t>(stream)));
+  if (a->fixed())
+    HIP_TRY(launch_finalize_fixed(a->U.as<long long>(), a->beta.as<beta_t>(), a->scene->n, a->D, out_feat,
+                                  out_wsum, out_sum, a->scene->out_perm(), static_cast<hipStream_t>(stream)));
+  else
+    HIP_TRY(launch_finalize(a->U.as<float>(), a->beta.as<beta_t>(), a->scene->n, a->D, out_feat,
+                            out_wsum, out_sum, a->scene->out_perm(), static_cast<hipStream_t>(stream)));
   return LV_OK;
 }
 
@@ -933,7 +943,7 @@ lv_status lv_accum_finalize_count(lv_accum* a, float* out_feat, void* stream) {
   if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");
   if (a->scene->n > 0 && !out_feat) return fail(LV_ERR_INVALID_ARG, "out_feat is NULL");
   HIP_TRY(launch_finalize_count(a->U.as<float>(), a->counts.as<uint32_t>(), a->scene->n, a->D,
-                                out_feat, a->scene->out_perm(), static_cast<hipStream_t>(stream)));
+                                out_feat, a->scene->out_perm(), a->fixed(), static_cast<hipStream_t>(stream)));
   return LV_OK;
 }
 

@@ -274,7 +274,7 @@ __device__ __forceinline__ bool group_lanes(const ChanGroup& grp, const SetDesc*
       if (!L.src[b]) L.src[b] = map;  // readable, for lanes without a channel
       if (ch >= vc0 && ch < vc0 + cnt) {
         const int c = grp.c0[k] + (ch - vc0);
-        L.outp[b] = sd.U + c;
+        L.outp[b] = u_elem(sd.U, c, sd.fixed != 0);
         L.outD[b] = sd.D;
         L.src[b] = map;
         L.own[b] = true;
@@ -419,10 +419,10 @@ __device__ __forceinline__ void batch_mfma(bool two, uint32_t rows, const float*
 // One atomic per (queued Gaussian, channel): D row m of the batch is ring
 // row m, whose Gaussian id lane m holds.  FP8 maps: the products were formed
 // on the codes, the channel's scale multiplies them here.
-template <lv_dtype DT>
-__device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int count,
-                                              uint32_t ring_gid, int lane, f32x16 acc0,
-                                              f32x16 acc1) {
+template <lv_dtype DT, bool FIX>
+__device__ __forceinline__ void batch_scatter_t(const GroupLanes& L, bool two, int count,
+                                                uint32_t ring_gid, int lane, f32x16 acc0,
+                                                f32x16 acc1) {
   if constexpr (DT == LV_FP8_E4M3) {
     acc0 *= L.srcsc[0];
     acc1 *= L.srcsc[1];
@@ -436,11 +436,23 @@ __device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int
       const uint32_t g1 = (uint32_t)__builtin_amdgcn_readlane((int)ring_gid, m1);
       const int64_t gid = (int64_t)(upper ? g1 : g0);
       if ((upper ? m1 : m0) < count) {
-        if (L.outp[0] && acc0[r] != 0.0f) gatomic_add(L.outp[0] + gid * L.outD[0], acc0[r]);
-        if (two && L.outp[1] && acc1[r] != 0.0f) gatomic_add(L.outp[1] + gid * L.outD[1], acc1[r]);
+        if (L.outp[0] && acc0[r] != 0.0f) u_atomic_add(L.outp[0], gid * L.outD[0], acc0[r], FIX);
+        if (two && L.outp[1] && acc1[r] != 0.0f) u_atomic_add(L.outp[1], gid * L.outD[1], acc1[r], FIX);
       }
     }
   }
+}
+
+// fixed (a deterministic accumulator) is wave-uniform: one branch per
+// flush, each side a straight run of atomics
+template <lv_dtype DT>
+__device__ __forceinline__ void batch_scatter(const GroupLanes& L, bool two, int count,
+                                              uint32_t ring_gid, int lane, f32x16 acc0,
+                                              f32x16 acc1, bool fixed) {
+  if (fixed)
+    batch_scatter_t<DT, true>(L, two, count, ring_gid, lane, acc0, acc1);
+  else
+    batch_scatter_t<DT, false>(L, two, count, ring_gid, lane, acc0, acc1);
 }
 
 // One channel group (at most 64 + 4 channels): one wave per (view,
@@ -465,6 +477,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
   Quad q;
   if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
   const int lane = threadIdx.x;
+  const bool fixedU = sets[0].fixed != 0;  // one accumulation mode per launch (wave-uniform)
   const int px = q.qx + (lane & 7), py = q.qy + (lane >> 3);
   const bool inside = px < q.g.W && py < q.g.H;
 
@@ -501,7 +514,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
       const int64_t idx = inside ? map_index<PX>(py, px, q.g.W, sd.stride, c) : 0;
       const float x = load_feature<DT>(map_of(sd, q.v), idx, sc);  // no branch around the load
       ft = inside ? x : 0.0f;
-      tout[t] = sd.U + c;
+      tout[t] = u_elem(sd.U, c, fixedU);
       tD[t] = sd.D;
       any_tail = true;
     }
@@ -550,7 +563,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
     if (has_main) {
       f32x16 acc0 = {}, acc1 = {};
       batch_mfma<kSplitF>(two1, rows, wrow, fh, fl, acc0, acc1);
-      batch_scatter<DT>(L1, two1, count, ring_gid, lane, acc0, acc1);
+      batch_scatter<DT>(L1, two1, count, ring_gid, lane, acc0, acc1, fixedU);
     }
     if (bsets || any_tail) {
       // lane l: row l % 32, pixels [32 (l / 32), 32 (l / 32) + 32)
@@ -586,7 +599,7 @@ __global__ __launch_bounds__(64, (wide_waves<DT>())) void blend_wide_kernel(
         }
 #pragma unroll
         for (int t = 0; t < kMaxTail; t++)
-          if (tout[t] && ts[t] != 0.0f) gatomic_add(tout[t] + (int64_t)ring_gid * tD[t], ts[t]);
+          if (tout[t] && ts[t] != 0.0f) u_atomic_add(tout[t], (int64_t)ring_gid * tD[t], ts[t], fixedU);
       }
     }
     __syncthreads();  // rows read before they are written again
@@ -743,6 +756,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
   Pair q;
   if (!decode_pair(ranges, geom, tiles_stride, nviews, q)) return;
   const int lane = threadIdx.x;
+  const bool fixedU = sets[0].fixed != 0;  // one accumulation mode per launch (wave-uniform)
   const int ox = q.qx, oy = q.qy & ~(kTile - 1);
   const float ocx = (float)ox + 0.5f, ocy = (float)oy + 0.5f;
   const float pyo = (float)(q.qy - oy + (lane >> 3));
@@ -789,7 +803,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
       const float x1 = load_feature<DT>(map_of(sd, q.v), i1, sc);
       ft0 = in0 ? x0 : 0.0f;
       ft1 = in1 ? x1 : 0.0f;
-      tout[t] = sd.U + c;
+      tout[t] = u_elem(sd.U, c, fixedU);
       tD[t] = sd.D;
       any_tail = true;
     }
@@ -835,7 +849,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
             }
           }
         }
-        if (pend) batch_scatter<DT>(Lp, twop, count, ring_gid, lane, acc0, acc1);
+        if (pend) batch_scatter<DT>(Lp, twop, count, ring_gid, lane, acc0, acc1, fixedU);
         pend = false;
         if (!ok) continue;
         acc0 = f32x16{};
@@ -867,7 +881,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
         twop = two;
         pend = true;
       }
-      if (pend) batch_scatter<DT>(Lp, twop, count, ring_gid, lane, acc0, acc1);
+      if (pend) batch_scatter<DT>(Lp, twop, count, ring_gid, lane, acc0, acc1, fixedU);
     } else {
       for (int cg = 0; cg < ngroups; cg++) {
         if (!((gmask >> cg) & 1u)) continue;
@@ -908,7 +922,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
             }
           }
         }
-        batch_scatter<DT>(L, two, count, ring_gid, lane, acc0, acc1);
+        batch_scatter<DT>(L, two, count, ring_gid, lane, acc0, acc1, fixedU);
       }
     }
     if (bsets || any_tail) {
@@ -945,7 +959,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
         }
 #pragma unroll
         for (int t = 0; t < kMaxTail; t++)
-          if (tout[t] && ts[t] != 0.0f) gatomic_add(tout[t] + (int64_t)ring_gid * tD[t], ts[t]);
+          if (tout[t] && ts[t] != 0.0f) u_atomic_add(tout[t], (int64_t)ring_gid * tD[t], ts[t], fixedU);
       }
     }
     __syncthreads();  // rows read before they are written again
@@ -1203,6 +1217,20 @@ __global__ void finalize_kernel(const float* __restrict__ U, const beta_t* __res
   if (wsum && c == 0) wsum[o] = bs;
 }
 
+__global__ void finalize_fixed_kernel(const long long* __restrict__ U, const beta_t* __restrict__ beta,
+                                      int64_t n, int D, float* __restrict__ f, float* __restrict__ wsum,
+                                      float* __restrict__ usum, const uint32_t* __restrict__ perm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * D) return;
+  const int64_t i = e / D, c = e - i * D;
+  const int64_t o = perm ? (int64_t)perm[i] : i;  // the output row
+  const double b = (double)beta[i] * (1.0 / kBetaUnit);
+  const double u = (double)U[e] * (1.0 / kBetaUnit);
+  if (f) f[o * D + c] = b > 0.0 ? (float)(u / b) : 0.0f;
+  if (usum) usum[o * D + c] = (float)u;
+  if (wsum && c == 0) wsum[o] = (float)b;
+}
+
 }  // namespace
 
 namespace {
@@ -1249,6 +1277,15 @@ hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float
   const int64_t blocks = (work + 7) / 8 * 32;  // 4 quadrants per tile, whole rounds of 8 XCDs
   hipLaunchKernelGGL(render_kernel, dim3((unsigned)blocks), dim3(64), 0, s, a.rec, a.ids, a.ranges,
                      a.geom, a.n, a.tiles_stride, m, ngroups, g, D, outs, alphas);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_fixed(const long long* U, const beta_t* beta, int64_t n, int D, float* f,
+                                 float* wsum, float* usum, const uint32_t* perm, hipStream_t s) {
+  const int64_t total = n * (int64_t)D;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_fixed_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, U, beta,
+                     n, D, f, wsum, usum, perm);
   return hipGetLastError();
 }
 

@@ -102,6 +102,24 @@ __device__ __forceinline__ void beta_atomic_add(beta_t* p, float w) {
   gatomic_add(p, (beta_t)__double2ull_rn((double)w * kBetaUnit));
 }
 
+// U += v at p[off]: an FP32 atomic, or, for a deterministic accumulator, v
+// rounded to the nearest 2^-35 and added to a signed 64-bit fixed-point word
+// (two's complement: the unsigned add wraps correctly).  Integer adds
+// commute, so a deterministic U is the same bit for bit whatever the order
+// of the atomics; |U| must stay below 2^28.  p points at element 0 of the
+// lane's channel in either element type (fixed: the word address as float*).
+__device__ __forceinline__ void u_atomic_add(float* p, int64_t off, float v, bool fixed) {
+  if (fixed)
+    gatomic_add(reinterpret_cast<unsigned long long*>(p) + off,
+                (unsigned long long)__double2ll_rn((double)v * kBetaUnit));
+  else
+    gatomic_add(p + off, v);
+}
+// Element c of a set's U row 0 as a float* (either element type).
+__device__ __forceinline__ float* u_elem(float* U, int64_t c, bool fixed) {
+  return fixed ? reinterpret_cast<float*>(reinterpret_cast<long long*>(U) + c) : U + c;
+}
+
 // ------------------------------------------------------------ device memory
 // Every device buffer of the library: the allocator registered with
 // lv_set_allocator, else hipMalloc / hipFree, or hipMallocAsync /
@@ -183,7 +201,8 @@ struct SetDesc {
   const void* const* maps;    // [views] device pointers, HWC [H][W][stride];
                               // NULL: the set does not take that view
   const float* scales;        // FP8: [all views][D] scales, else null
-  float* U;                   // [n][D]
+  float* U;                   // [n][D] FP32, or int64 fixed point (units of 2^-35) if fixed
+  int32_t fixed;              // the same for every set of a launch
   beta_t* beta;               // [n] fixed point, units of 2^-35
   uint32_t* counts;           // [n] or null
   unsigned long long* stats;  // [3] covered pixels, contributions, partial sums; or null
@@ -261,9 +280,12 @@ hipError_t launch_reach_unary(const float* gT, const float* unary, int64_t n, in
 // f = U / cnt per Gaussian (0 where cnt = 0).  Outputs of row i go to row
 // perm[i] when perm is given (a scene stored in Morton order), else to i.
 hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n, int D, float* f,
-                                 const uint32_t* perm, hipStream_t s);
+                                 const uint32_t* perm, bool fixed, hipStream_t s);
 hipError_t launch_finalize(const float* U, const beta_t* beta, int64_t n, int D, float* f,
                            float* wsum, float* usum, const uint32_t* perm, hipStream_t s);
+// The same for a fixed-point U (units of 2^-35): f = U / beta in FP64, rounded.
+hipError_t launch_finalize_fixed(const long long* U, const beta_t* beta, int64_t n, int D, float* f,
+                                 float* wsum, float* usum, const uint32_t* perm, hipStream_t s);
 
 // Feature-map formats: valid uplift input, element type, pixel-block layout.
 inline bool map_format_valid(lv_dtype d) { return d >= LV_F32 && d <= LV_FP8_E4M3_PX8; }

@@ -81,13 +81,18 @@ __global__ void reach_unary_kernel(const float* __restrict__ gT, const float* __
 
 __global__ void finalize_count_kernel(const float* __restrict__ U, const uint32_t* __restrict__ cnt,
                                       int64_t n, int D, float* __restrict__ f,
-                                      const uint32_t* __restrict__ perm) {
+                                      const uint32_t* __restrict__ perm, bool fixed) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * D) return;
   const int64_t i = e / D;
   const uint32_t c = cnt[i];
   const int64_t o = perm ? (int64_t)perm[i] : i;  // the output row
-  f[o * D + (e - i * D)] = c ? U[e] / (float)c : 0.0f;
+  float r = 0.0f;
+  if (c && fixed)  // fixed-point U (units of 2^-35)
+    r = (float)((double)reinterpret_cast<const long long*>(U)[e] * (1.0 / kBetaUnit) / (double)c);
+  else if (c)
+    r = U[e] / (float)c;
+  f[o * D + (e - i * D)] = r;
 }
 
 }  // namespace
@@ -157,11 +162,11 @@ hipError_t launch_reach_unary(const float* gT, const float* unary, int64_t n, in
 }
 
 hipError_t launch_finalize_count(const float* U, const uint32_t* cnt, int64_t n, int D, float* f,
-                                 const uint32_t* perm, hipStream_t s) {
+                                 const uint32_t* perm, bool fixed, hipStream_t s) {
   const int64_t total = n * (int64_t)D;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_count_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     U, cnt, n, D, f, perm);
+                     U, cnt, n, D, f, perm, fixed);
   return hipGetLastError();
 }
 

@@ -120,6 +120,62 @@ def test_morton_storage_order_is_internal():
     gc.close()
 
 
+def test_deterministic_accumulator():
+    """LV_ACCUM_DETERMINISTIC (U in 64-bit fixed point): U, beta and f the
+    same bit for bit on a second run and for any grouping of the views;
+    against the FP32 accumulator within its rounding (a lost update would
+    stand out); against the oracle within 1e-4.  A D = 130 set (three channel
+    groups, tail channels) and a D = 3 set sharing one walk run the
+    several-group kernel; a D = 3 accumulator on its own runs the one-group
+    kernel."""
+    sc = scenes.make_scene(17, 12000, -3.9, 0.5, 0.0, 1.0)
+    gs = lv.Scene.from_arrays(sc)
+    cams = [scenes.look_at(e, 131, 97, 60.0) for e in scenes.fibonacci_eyes(3, 4.0)]
+    maps = [torch.as_tensor(philox.normal(41, v, 97 * 131 * 130).reshape(97, 131, 130), device="cuda")
+            for v in range(3)]
+    small = [m[..., :3].contiguous() for m in maps]
+
+    def run(det, groups):
+        a = lv.Accum(gs, 130, counts=True, deterministic=det)
+        b = lv.Accum(gs, 3, deterministic=det)
+        for g in groups:
+            lv.accumulate_sets([cams[v] for v in g], [(a, [maps[v] for v in g], None),
+                                                      (b, [small[v] for v in g], None)])
+        c = lv.Accum(gs, 3, deterministic=det)
+        for g in groups:
+            c.add([cams[v] for v in g], [small[v] for v in g])
+        fa, ba, ua = a.finalize(want_sum=True)
+        fb, bb = b.finalize()
+        fc, bc = c.finalize()
+        out = [x.cpu().numpy() for x in (fa, ba, ua, fb, bb, a.counts(), a.finalize_count(), fc, bc)]
+        a.close()
+        b.close()
+        c.close()
+        return out
+
+    d1 = run(True, [[0, 1, 2]])
+    d2 = run(True, [[0, 1, 2]])
+    d3 = run(True, [[2], [0, 1]])
+    for x, y, z in zip(d1, d2, d3):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    a = run(False, [[0, 1, 2]])
+    assert np.array_equal(d1[1], a[1]) and np.array_equal(d1[5], a[5])  # beta, counts: exact in both
+    assert np.array_equal(d1[8], a[8])
+    for k in (0, 2, 3, 6, 7):
+        scale = max(1.0, float(np.abs(a[k]).max()))
+        assert np.abs(d1[k] - a[k]).max() <= 1e-5 * scale, k
+    ref = oracle.uplift(sc, cams, [m.cpu().numpy() for m in maps])
+    assert counts_match(d1[5], ref)
+    assert feature_error(d1[0], ref).max() < 1e-4 and beta_error(d1[1], ref).max() < 1e-4
+    # one mode per call
+    det, fp = lv.Accum(gs, 3, deterministic=True), lv.Accum(gs, 3)
+    with pytest.raises(lv.LvError, match="status 1"):
+        lv.accumulate_sets(cams, [(det, small, None), (fp, small, None)])
+    det.close()
+    fp.close()
+    gs.close()
+
+
 @pytest.fixture(scope="module")
 def tiny():
     w = scenes.WORKLOADS["tiny"]
