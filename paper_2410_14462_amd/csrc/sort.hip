@@ -604,74 +604,78 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict_
 }
 
 // Exact depth ties of a scene stored in Morton order, back in the caller's
-// index order.  Four consecutive depth-sorted items per thread (one 16-byte
-// load where the keys are 16-byte aligned) over the mv views' segments of n
-// items.  A lane first finds the runs (two or more equal visible keys
-// within a view) that start among its items, at most two, then handles them
-// together: a pair (by far the commonest tie) is one compare of the two
-// caller indices and a swap, with the loads of both runs in flight at once;
-// longer runs are insertion-sorted by caller index.
+// index order.  Grid row blockIdx.y is a view (its n depth-sorted items);
+// four consecutive items per thread (one 16-byte load where aligned).  A
+// lane first finds the runs (two or more equal visible keys) that start
+// among its items, at most two, then handles them together: a pair (by far
+// the commonest tie) is, where the two tile rectangles overlap (else no
+// tile list holds both), one compare of the two caller indices and a swap,
+// with the loads of both runs in flight at once; longer runs are
+// insertion-sorted by caller index.
 __global__ __launch_bounds__(256) void depth_ties_kernel(const uint32_t* __restrict__ key,
                                                          uint32_t* __restrict__ val,
                                                          uint2* __restrict__ rect,
                                                          uint32_t* __restrict__ cnt, int64_t n,
-                                                         int64_t total, bool aligned,
+                                                         bool aligned,
                                                          const uint32_t* __restrict__ perm) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t e0 = 4 * q;
-  if (e0 >= total) return;
+  const int64_t e0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);  // in the view
+  if (e0 >= n) return;
+  const int64_t base = (int64_t)blockIdx.y * n;
+  const uint32_t* kv = key + base;
   uint32_t k[4];
-  if (aligned && e0 + 4 <= total) {
-    const uint4 v = reinterpret_cast<const uint4*>(key)[q];
+  if (aligned && e0 + 4 <= n) {
+    const uint4 v = *reinterpret_cast<const uint4*>(kv + e0);
     k[0] = v.x;
     k[1] = v.y;
     k[2] = v.z;
     k[3] = v.w;
   } else {
 #pragma unroll
-    for (int j = 0; j < 4; j++) k[j] = e0 + j < total ? key[e0 + j] : 0xFFFFFFFFu;
+    for (int j = 0; j < 4; j++) k[j] = e0 + j < n ? kv[e0 + j] : 0xFFFFFFFFu;
   }
-  if (k[0] == 0xFFFFFFFFu && k[1] == 0xFFFFFFFFu && k[2] == 0xFFFFFFFFu && k[3] == 0xFFFFFFFFu)
-    return;  // culled items (they sort last in their view)
-  const uint32_t before = e0 > 0 ? key[e0 - 1] : 0xFFFFFFFFu;
-  const uint32_t after = e0 + 4 < total ? key[e0 + 4] : 0xFFFFFFFFu;
-  int64_t st[2] = {0, 0}, ve[2] = {0, 0};  // run starts and the end of their view
+  if (k[0] == 0xFFFFFFFFu) return;  // culled items sort last: so are the lane's others
+  const uint32_t before = e0 > 0 ? kv[e0 - 1] : 0xFFFFFFFFu;
+  const uint32_t after = e0 + 4 < n ? kv[e0 + 4] : 0xFFFFFFFFu;
+  int64_t st[2] = {0, 0};  // run starts (in the view)
   int ns = 0;
-  int64_t vs = e0 / n * n;  // the segment of the view item e0 is in
 #pragma unroll
   for (int j = 0; j < 4; j++) {
     const int64_t e = e0 + j;
-    if (e >= total) break;
-    while (e >= vs + n) vs += n;  // views of fewer than four items
     const uint32_t kk = k[j];
-    if (kk == 0xFFFFFFFFu || e + 1 >= vs + n) continue;               // culled, or the view's last item
+    if (kk == 0xFFFFFFFFu || e + 1 >= n) continue;                     // culled, or the view's last item
     if ((j < 3 ? k[j + 1] : after) != kk) continue;                     // no tie after it
-    if (e > vs && (j > 0 ? k[j - 1] : before) == kk) continue;         // not the run's first item
+    if (e > 0 && (j > 0 ? k[j - 1] : before) == kk) continue;          // not the run's first item
     st[ns < 2 ? ns : 1] = e;  // at most two starts among four items
-    ve[ns < 2 ? ns : 1] = vs + n;
     ns++;
   }
   if (ns == 0) return;
   uint32_t a[2], b[2];
+  uint2 ra[2], rb[2];
   bool longer[2];
 #pragma unroll
   for (int t = 0; t < 2; t++) {
-    const int64_t e = st[t];
+    const int64_t e = base + st[t];
     const bool on = t < ns;
     a[t] = on ? val[e] : 0u;
     b[t] = on ? val[e + 1] : 0u;
-    longer[t] = on && e + 2 < ve[t] && key[e + 2] == key[e];
+    ra[t] = on ? rect[e] : make_uint2(0u, 0u);
+    rb[t] = on ? rect[e + 1] : make_uint2(0u, 0u);
+    longer[t] = on && st[t] + 2 < n && key[e + 2] == key[e];
   }
 #pragma unroll
   for (int t = 0; t < 2; t++) {
-    const int64_t e = st[t];
-    if (t < ns && !longer[t] && perm[a[t]] > perm[b[t]]) {
-      const uint2 r0 = rect[e], r1 = rect[e + 1];
+    const int64_t e = base + st[t];
+    // two Gaussians whose tile rectangles [x0, x1) x [y0, y1) are disjoint
+    // share no tile list: their relative order changes nothing
+    const uint2 p = ra[t], q = rb[t];
+    const bool overlap = (p.x & 0xFFFFu) < (q.y & 0xFFFFu) && (q.x & 0xFFFFu) < (p.y & 0xFFFFu) &&
+                         (p.x >> 16) < (q.y >> 16) && (q.x >> 16) < (p.y >> 16);
+    if (t < ns && !longer[t] && overlap && perm[a[t]] > perm[b[t]]) {
       const uint32_t c0 = cnt[e], c1 = cnt[e + 1];
       val[e] = b[t];
       val[e + 1] = a[t];
-      rect[e] = r1;
-      rect[e + 1] = r0;
+      rect[e] = q;
+      rect[e + 1] = p;
       cnt[e] = c1;
       cnt[e + 1] = c0;
     }
@@ -679,10 +683,10 @@ __global__ __launch_bounds__(256) void depth_ties_kernel(const uint32_t* __restr
 #pragma unroll
   for (int t = 0; t < 2; t++) {
     if (t >= ns || !longer[t]) continue;
-    const int64_t e = st[t];
+    const int64_t e = base + st[t], end = base + n;
     const uint32_t kk = key[e];
     int64_t r = e + 3;
-    while (r < ve[t] && key[r] == kk) r++;
+    while (r < end && key[r] == kk) r++;
     for (int64_t i = e + 1; i < r; i++) {
       const uint32_t v = val[i], pv = perm[v];
       const uint2 rc = rect[i];
@@ -706,10 +710,10 @@ __global__ __launch_bounds__(256) void depth_ties_kernel(const uint32_t* __restr
 hipError_t launch_depth_ties(const uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt, int64_t n,
                              int mv, const uint32_t* perm, hipStream_t s) {
   if (n < 2 || mv == 0) return hipSuccess;
-  const int64_t total = n * (int64_t)mv, quads = (total + 3) / 4;
-  const bool aligned = ((uintptr_t)key & 15) == 0;
-  hipLaunchKernelGGL(depth_ties_kernel, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, key, val,
-                     rect, cnt, n, total, aligned, perm);
+  const int64_t quads = (n + 3) / 4;
+  const bool aligned = ((uintptr_t)key & 15) == 0 && n % 4 == 0;  // every view's start too
+  hipLaunchKernelGGL(depth_ties_kernel, dim3((unsigned)((quads + 255) / 256), mv), dim3(256), 0, s, key, val,
+                     rect, cnt, n, aligned, perm);
   return hipGetLastError();
 }
 

@@ -64,22 +64,31 @@ def test_structure_bit_exact_two_pass_tile_sort():
 
 
 def tie_scene():
-    """3,000 Gaussians on two planes z = 0 and z = 0.1 (positions shuffled, so
-    the Morton order of the centres is far from the index order) and 2,000
-    in the volume: a camera on the z axis sees each plane at one exact FP32
-    depth, i.e. runs of ~1,500 equal depth keys."""
+    """Seen by a camera on the z axis (depth 4 - z exactly in FP32):
+    3,000 Gaussians on the planes z = 0 and z = 0.1 (positions shuffled, so
+    the Morton order of the centres is far from the index order): runs of
+    ~1,500 equal depth keys; 1,000 pairs (Gaussians 3000 + k and 4000 + k) at
+    one depth per pair, 0.01 apart in x with overlapping tile rectangles, the
+    pair's first index at the larger x (so the Morton order reverses the
+    pair); 2,000 Gaussians in the volume."""
     rng = np.random.default_rng(11)
-    base = scenes.make_scene(21, 5000, -3.6, 0.4, 0.5, 1.0)
+    base = scenes.make_scene(21, 7000, -3.6, 0.4, 0.5, 1.0)
     means = base.means.copy()
     means[:3000, 2] = np.where(rng.random(3000) < 0.5, 0.0, 0.1).astype(np.float32)
+    k = np.arange(1000)
+    xy = rng.uniform(-0.9, 0.9, (1000, 2)).astype(np.float32)
+    z = (-0.45 + 0.0009 * k).astype(np.float32)  # distinct per pair
+    means[3000 + k] = np.stack([xy[:, 0] + np.float32(0.01), xy[:, 1], z], axis=1)
+    means[4000 + k] = np.stack([xy[:, 0], xy[:, 1], z], axis=1)
     return Scene(means, base.scales, base.quats, base.opacity)
 
 
 def test_morton_storage_order_is_internal():
     """The default Morton storage order against LV_SCENE_CALLER_ORDER and the
     oracle: structure bit-exact (exact depth ties blend in the caller's index
-    order), weight sums (fixed point) and counts equal, features and renders
-    equal up to the summation order, outputs in the caller's order."""
+    order: long runs, and pairs whose tile rectangles overlap), weight sums
+    (fixed point) and counts equal, features and renders equal up to the
+    summation order, outputs in the caller's order."""
     sc = tie_scene()
     cams = [scenes.look_at((0.0, 0.0, 4.0), 160, 120, 60.0)]
     cams += [scenes.look_at(e, 150, 110, 60.0) for e in scenes.fibonacci_eyes(2, 4.0)]
