@@ -221,6 +221,7 @@ def large_leg(lv, args):
                 "data": "synthetic",
                 "config": {"workload": w.name, "gaussians": n, "views": m, "width": W, "height": H,
                            "channels": D, "storage": fmt["bf16"], "accumulation": "f32",
+                           "scene_order": "morton (library default; outputs in the caller's order)",
                            "contraction": "split-BF16 matrix-core products, FP32 accumulate (BF16 maps "
                                           "and FP8 codes: 2 exact products per term; FP32 maps: 3, "
                                           "error < 2^-16 |w F|)"},
