@@ -253,6 +253,19 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
  * [n] (nullable); raw U into out_sum [n][D] (nullable). */
 lv_status lv_accum_finalize(lv_accum* acc, float* out_feat, float* out_wsum, float* out_sum,
                             void* stream);
+/* Checkpoint / resume of an accumulator: its raw state, in the caller's
+ * Gaussian order, to or from caller device buffers.  U [n][D]: FP32, or
+ * int64 (units of 2^-35) for an LV_ACCUM_DETERMINISTIC accumulator; beta [n]
+ * uint64 (units of 2^-35); counts [n] uint32 (accumulators with
+ * LV_ACCUM_COUNTS; NULL skips them, and on import NULL zeroes them).
+ * Importing what another accumulator of the same scene, D and flags
+ * exported, then adding the remaining views, equals adding all views to one
+ * accumulator (bit for bit for beta, counts and a deterministic U).
+ * Errors: LV_ERR_INVALID_ARG (null accumulator, U or beta with n > 0;
+ * counts given without LV_ACCUM_COUNTS), LV_ERR_DEVICE. */
+lv_status lv_accum_export(lv_accum* acc, void* U, uint64_t* beta, uint32_t* counts, void* stream);
+lv_status lv_accum_import(lv_accum* acc, const void* U, const uint64_t* beta, const uint32_t* counts,
+                          void* stream);
 /* Count-normalised features (appendix, comparison with GaussianEditor's
  * uplifting): f_i = U_i / c_i into out_feat [n][D], c_i the number of counted
  * (view, pixel) pairs of Gaussian i instead of the sum of their weights; 0

@@ -112,6 +112,8 @@ def lib():
             "lv_last_error": ([], ctypes.c_char_p),
             "lv_version": ([], ctypes.c_char_p),
             "lv_scene_create": ([P, P, P, P, i64, ctypes.POINTER(lv_scene_opts), P, ctypes.POINTER(P)], i32),
+            "lv_accum_export": ([P, P, P, P, P], i32),
+            "lv_accum_import": ([P, P, P, P, P], i32),
             "lv_scene_destroy": ([P], i32),
             "lv_scene_size": ([P], i64),
             "lv_uplift": ([P, P, i32, P, i32, P, i32, P, P, P], i32),
@@ -169,7 +171,8 @@ def exported_symbols():
             "lv_uplift_accumulate_sets", "lv_render", "lv_server_create", "lv_server_submit", "lv_server_poll",
             "lv_server_drain", "lv_server_stats_get", "lv_server_destroy", "lv_accum_finalize_count",
             "lv_prune_by_weight", "lv_graph_build_knn", "lv_graph_csr", "lv_anchor_init", "lv_reach_unary",
-            "lv_server_cancel", "lv_set_allocator", "lv_release_scratch", "lv_memory_stats"]
+            "lv_server_cancel", "lv_set_allocator", "lv_release_scratch", "lv_memory_stats",
+            "lv_accum_export", "lv_accum_import"]
 
 
 def _check(status):
@@ -423,7 +426,7 @@ class Accum:
         h = ctypes.c_void_p()
         flags = (LV_ACCUM_COUNTS if counts else 0) | (LV_ACCUM_DETERMINISTIC if deterministic else 0)
         _check(lib().lv_accum_create(scene.handle, D, flags, _stream(), ctypes.byref(h)))
-        self.handle, self.scene, self.D = h, scene, D
+        self.handle, self.scene, self.D, self.flags = h, scene, D, flags
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -459,6 +462,23 @@ class Accum:
         c = torch.empty((self.scene.n,), device="cuda", dtype=torch.int32)
         _check(lib().lv_accum_counts(self.handle, _ptr(c), _stream()))
         return c
+
+    def export(self):
+        """Checkpoint: (U [n, D] float32, or int64 fixed point for a
+        deterministic accumulator; beta [n] int64 holding the uint64 fixed
+        point; counts [n] int32 or None), in the caller's Gaussian order."""
+        import torch
+        n = self.scene.n
+        det = bool(self.flags & LV_ACCUM_DETERMINISTIC)
+        U = torch.empty((n, self.D), device="cuda", dtype=torch.int64 if det else torch.float32)
+        beta = torch.empty((n,), device="cuda", dtype=torch.int64)
+        counts = torch.empty((n,), device="cuda", dtype=torch.int32) if self.flags & LV_ACCUM_COUNTS else None
+        _check(lib().lv_accum_export(self.handle, _ptr(U), _ptr(beta), _ptr(counts), _stream()))
+        return U, beta, counts
+
+    def load(self, U, beta, counts=None):
+        """Resume from export()'s tensors (same scene, D and flags)."""
+        _check(lib().lv_accum_import(self.handle, _ptr(U), _ptr(beta), _ptr(counts), _stream()))
 
     def finalize_count(self):
         """lv_accum_finalize_count: f = U / count (needs counts=True)."""

@@ -938,6 +938,51 @@ lv_status lv_accum_finalize(lv_accum* a, float* out_feat, float* out_wsum, float
   return LV_OK;
 }
 
+namespace {
+// rows of `words` 32-bit words, storage order <-> the caller's order
+hipError_t move_rows(const void* src, void* dst, int64_t n, int words, const lv_scene* sc, bool to_caller,
+                     hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (!sc->morton)
+    return hipMemcpyAsync(dst, src, 4 * (size_t)n * words, hipMemcpyDeviceToDevice, s);
+  return launch_permute_rows(src, dst, sc->perm.as<uint32_t>(), n, words, LV_F32, to_caller, s);
+}
+}  // namespace
+
+lv_status lv_accum_export(lv_accum* a, void* U, uint64_t* beta, uint32_t* counts, void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  const int64_t n = a->scene->n;
+  if (n > 0 && (!U || !beta)) return fail(LV_ERR_INVALID_ARG, "U or beta is NULL");
+  if (counts && !(a->flags & LV_ACCUM_COUNTS))
+    return fail(LV_ERR_INVALID_ARG, "counts requested from an accumulator without LV_ACCUM_COUNTS");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int uw = (int)(a->u_elem_bytes() / 4) * a->D;
+  HIP_TRY(move_rows(a->U.p, U, n, uw, a->scene, true, s));
+  HIP_TRY(move_rows(a->beta.p, beta, n, 2, a->scene, true, s));
+  if (counts) HIP_TRY(move_rows(a->counts.p, counts, n, 1, a->scene, true, s));
+  return LV_OK;
+}
+
+lv_status lv_accum_import(lv_accum* a, const void* U, const uint64_t* beta, const uint32_t* counts,
+                          void* stream) {
+  if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
+  const int64_t n = a->scene->n;
+  if (n > 0 && (!U || !beta)) return fail(LV_ERR_INVALID_ARG, "U or beta is NULL");
+  if (counts && !(a->flags & LV_ACCUM_COUNTS))
+    return fail(LV_ERR_INVALID_ARG, "counts given to an accumulator without LV_ACCUM_COUNTS");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int uw = (int)(a->u_elem_bytes() / 4) * a->D;
+  HIP_TRY(move_rows(U, a->U.p, n, uw, a->scene, false, s));
+  HIP_TRY(move_rows(beta, a->beta.p, n, 2, a->scene, false, s));
+  if (a->counts.p && n > 0) {
+    if (counts)
+      HIP_TRY(move_rows(counts, a->counts.p, n, 1, a->scene, false, s));
+    else
+      HIP_TRY(hipMemsetAsync(a->counts.p, 0, 4 * (size_t)n, s));
+  }
+  return LV_OK;
+}
+
 lv_status lv_accum_finalize_count(lv_accum* a, float* out_feat, void* stream) {
   if (!a) return fail(LV_ERR_INVALID_ARG, "accumulator is NULL");
   if (!(a->flags & LV_ACCUM_COUNTS)) return fail(LV_ERR_INVALID_ARG, "created without LV_ACCUM_COUNTS");

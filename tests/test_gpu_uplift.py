@@ -185,6 +185,56 @@ def test_deterministic_accumulator():
     gs.close()
 
 
+def test_accumulator_checkpoint_resume():
+    """Checkpoint after two of four views, resume in a new accumulator, add
+    the other two: equals all four views in one accumulator (beta, counts
+    and a deterministic U bit for bit; an FP32 U within its rounding).  The
+    checkpoint is in the caller's Gaussian order: the same for a scene
+    stored in Morton order and one in the caller's order."""
+    sc = scenes.make_scene(19, 8000, -3.9, 0.5, 0.0, 1.0)
+    gs = lv.Scene.from_arrays(sc)
+    gc = lv.Scene.from_arrays(sc, order="caller")
+    cams = [scenes.look_at(e, 120, 90, 60.0) for e in scenes.fibonacci_eyes(4, 4.0)]
+    D = 10
+    maps = [torch.as_tensor(philox.normal(51, v, 90 * 120 * D).reshape(90, 120, D), device="cuda")
+            for v in range(4)]
+    for det in (False, True):
+        full = lv.Accum(gs, D, counts=True, deterministic=det)
+        full.add(cams, maps)
+        Uf, bf, cf = full.export()
+        ff, wf = full.finalize()
+        full.close()
+        first = lv.Accum(gs, D, counts=True, deterministic=det)
+        first.add(cams[:2], maps[:2])
+        U1, b1, c1 = first.export()
+        first.close()
+        other = lv.Accum(gc, D, counts=True, deterministic=det)
+        other.add(cams[:2], maps[:2])
+        Uo, bo, co = other.export()
+        other.close()
+        assert torch.equal(bo, b1) and torch.equal(co, c1)
+        if det:
+            assert torch.equal(Uo, U1)
+        else:
+            assert torch.allclose(Uo, U1, rtol=1e-5, atol=1e-6)
+        second = lv.Accum(gs, D, counts=True, deterministic=det)
+        second.load(U1, b1, c1)
+        _, w1 = second.finalize()
+        assert torch.equal(w1, (b1.double() * 2.0 ** -35).float())
+        second.add(cams[2:], maps[2:])
+        U2, b2, c2 = second.export()
+        f2, w2 = second.finalize()
+        second.close()
+        assert torch.equal(b2, bf) and torch.equal(c2, cf) and torch.equal(w2, wf)
+        if det:
+            assert torch.equal(U2, Uf) and torch.equal(f2, ff)
+        else:
+            assert torch.allclose(U2, Uf, rtol=1e-5, atol=1e-6)
+            assert torch.allclose(f2, ff, rtol=1e-5, atol=1e-6)
+    gs.close()
+    gc.close()
+
+
 @pytest.fixture(scope="module")
 def tiny():
     w = scenes.WORKLOADS["tiny"]
