@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving trace (0 = skip the serving leg)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, req/s")
+    ap.add_argument("--serve-log", default=None,
+                    help="write each served request's metrics as JSON lines to PATH.<dtype>.w<workers>.jsonl")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -93,7 +95,7 @@ def main():
     torch.cuda.set_device(0)
     if args.only:
         leg = {"mid": lambda: mid_leg(lv, args), "diffuse": lambda: diffusion_leg(lv),
-               "serving": lambda: serving(lv, args.serve_requests, args.serve_rate)}[args.only]
+               "serving": lambda: serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log)}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     out, keep = large_leg(lv, args)
@@ -113,7 +115,7 @@ def main():
         out["diffuse"] = diffusion_leg(lv)
         torch.cuda.empty_cache()
         if args.serve_requests > 0:
-            out["serving"] = serving(lv, args.serve_requests, args.serve_rate)
+            out["serving"] = serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log)
     print(json.dumps(out), flush=True)
 
 
@@ -520,7 +522,7 @@ def diffusion_leg(lv):
 
 
 # ------------------------------------------------------------------ serving
-def serving(lv, nreq, rate, bank_k=4):
+def serving(lv, nreq, rate, bank_k=4, log_path=None):
     """The serving trace (synth.trace) three times: BF16 pixel-block maps through the
     server (2 workers, same-scene requests merged into one pass, admission by
     an HBM budget), FP32 maps through the same server settings, and FP32 maps
@@ -589,8 +591,18 @@ def serving(lv, nreq, rate, bank_k=4):
         if len(comps) != nreq or bad:
             raise RuntimeError(f"serving: {len(comps)} of {nreq} completed, failed: {bad[:8]}")
         lat = [(c["t_end"] - c["t_submit"]) * 1e3 for c in comps]
+        wait_admit = [(c["t_admit"] - c["t_submit"]) * 1e3 for c in comps]  # memory budget
+        wait_pass = [(c["t_start"] - c["t_admit"]) * 1e3 for c in comps]    # admitted, waiting for a worker
         span = max(c["t_end"] for c in comps) - min(c["t_submit"] for c in comps)
+        if log_path:
+            with open(f"{log_path}.{dtype}.w{workers}.jsonl", "w") as fh:
+                for c in comps:
+                    fh.write(json.dumps(lv.completion_record(c)) + "\n")
         res = {"p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),
+               "admission_wait_ms_p50_p99": [round(percentile(wait_admit, 0.5), 2),
+                                             round(percentile(wait_admit, 0.99), 2)],
+               "worker_wait_ms_p50_p99": [round(percentile(wait_pass, 0.5), 2),
+                                          round(percentile(wait_pass, 0.99), 2)],
                "req_per_s": round(nreq / span, 3), "makespan_s": round(span, 3),
                "passes": st["passes"] - len(scs) * workers,
                "mean_requests_per_pass": round(nreq / max(1, st["passes"] - len(scs) * workers), 2),

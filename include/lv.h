@@ -467,14 +467,19 @@ typedef struct lv_request {
     uint64_t tag;
     void* stream;
 } lv_request;
-/* A finished request: status, the number of requests in its pass, and times
- * in ns since the server was created (submission, start and end of its
- * pass; the outputs are complete at t_end). */
+/* A finished request: status, the number of requests in its pass, times in
+ * ns since the server was created (submission, admission within the
+ * budget, start and end of its pass; the outputs are complete at t_end;
+ * t_admit is 0 for a request cancelled before admission, t_start and t_end
+ * its cancellation), the memory it was admitted with, D and its number of
+ * views. */
 typedef struct lv_completion {
     uint64_t tag;
     int32_t status;
     int32_t batch_size;
     int64_t t_submit, t_start, t_end;
+    int64_t t_admit, bytes;
+    int32_t D, views;
 } lv_completion;
 /* peak_bytes: the most request memory admitted at once (<= budget less the
  * workers' scratch); peak_device_bytes: the largest device memory in use

@@ -75,7 +75,9 @@ class lv_request(ctypes.Structure):
 
 class lv_completion(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
-                ("t_submit", ctypes.c_int64), ("t_start", ctypes.c_int64), ("t_end", ctypes.c_int64)]
+                ("t_submit", ctypes.c_int64), ("t_start", ctypes.c_int64), ("t_end", ctypes.c_int64),
+                ("t_admit", ctypes.c_int64), ("bytes", ctypes.c_int64), ("D", ctypes.c_int32),
+                ("views", ctypes.c_int32)]
 
 
 class lv_server_stats(ctypes.Structure):
@@ -683,6 +685,13 @@ class Graph:
         return out
 
 
+def completion_record(c):
+    """One finished request (a dict of Server.poll) as a JSON-ready dict: the
+    per-request metrics (arrival, admission, start, done, D, views, bytes)."""
+    return {k: c[k] for k in ("tag", "status", "batch_size", "t_submit", "t_admit", "t_start", "t_end",
+                              "bytes", "D", "views")}
+
+
 class Server:
     """lv_server: uplift requests admitted by memory budget, merged per scene
     into wide passes, several passes in flight (one HIP stream per worker)."""
@@ -720,8 +729,10 @@ class Server:
         return tag
 
     def poll(self, cap=4096):
-        """Finished requests: dicts with tag, status, batch_size, times (s) and
-        the outputs (features, weight sums)."""
+        """Finished requests: dicts with tag, status, batch_size, times (s:
+        submission, admission, start and end of the pass), admitted bytes, D,
+        views and the outputs (features, weight sums).  completion_record()
+        makes one JSON-ready line of a result."""
         buf = (lv_completion * cap)()
         n = ctypes.c_int32()
         _check(lib().lv_server_poll(self.handle, buf, cap, ctypes.byref(n)))
@@ -729,8 +740,9 @@ class Server:
         for c in buf[:n.value]:
             live = self._live.pop(c.tag, None)
             res.append({"tag": c.tag, "status": c.status, "batch_size": c.batch_size,
-                        "t_submit": c.t_submit * 1e-9, "t_start": c.t_start * 1e-9,
-                        "t_end": c.t_end * 1e-9,
+                        "t_submit": c.t_submit * 1e-9, "t_admit": c.t_admit * 1e-9,
+                        "t_start": c.t_start * 1e-9, "t_end": c.t_end * 1e-9, "bytes": c.bytes,
+                        "D": c.D, "views": c.views,
                         "out": live[3] if live else None, "wsum": live[4] if live else None})
         return res
 

@@ -37,7 +37,7 @@ struct ServeReq {
   float* out_feat = nullptr;
   float* out_wsum = nullptr;
   uint64_t tag = 0;
-  int64_t t_submit = 0;
+  int64_t t_submit = 0, t_admit = 0;
   hipEvent_t ready = nullptr;  // inputs produced (recorded on the caller's stream)
 };
 
@@ -72,7 +72,8 @@ struct lv_server {
   int device = 0;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
-  lv_server(int64_t b, int max_sets, int max_channels) : sched(b, max_sets, max_channels), budget(b) {}
+  lv_server(int64_t b, int max_sets, int max_channels)
+      : sched(b, max_sets, max_channels, [this](ServeReq& r) { r.t_admit = now_ns(t0); }), budget(b) {}
 
   void run_worker();
   void execute(std::vector<ServeReq>& batch, hipStream_t s);
@@ -97,6 +98,10 @@ void lv_server::finish(const ServeReq& r, int32_t status, int32_t nb, int64_t t_
   c.t_submit = r.t_submit;
   c.t_start = t_start;
   c.t_end = t_end;
+  c.t_admit = r.t_admit;
+  c.bytes = r.bytes;
+  c.D = r.D;
+  c.views = (int32_t)r.cams.size();
   std::lock_guard<std::mutex> lk(mu);
   done.push_back(c);
   completed += 1;

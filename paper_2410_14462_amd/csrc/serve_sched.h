@@ -27,6 +27,7 @@
 #include <cstdint>
 #include <deque>
 #include <mutex>
+#include <functional>
 #include <vector>
 
 namespace lv {
@@ -35,8 +36,11 @@ template <typename Req>
 class Scheduler {
  public:
   // Req must provide: int64_t bytes; int32_t D; uint64_t key; and is moved.
-  Scheduler(int64_t budget, int max_sets, int max_channels)
-      : budget_(budget), max_sets_(max_sets), max_channels_(max_channels) {}
+  // on_admit (optional) sees each request as it is admitted, in admission
+  // order, under the scheduler's lock.
+  Scheduler(int64_t budget, int max_sets, int max_channels,
+            std::function<void(Req&)> on_admit = std::function<void(Req&)>())
+      : budget_(budget), max_sets_(max_sets), max_channels_(max_channels), on_admit_(std::move(on_admit)) {}
 
   // false: the request can never be admitted (larger than the budget)
   bool submit(Req r) {
@@ -138,6 +142,7 @@ class Scheduler {
     while (!pending_.empty() && used_ + pending_.front().bytes <= budget_) {
       used_ += pending_.front().bytes;
       if (used_ > peak_) peak_ = used_;
+      if (on_admit_) on_admit_(pending_.front());
       admitted_.push_back(std::move(pending_.front()));
       pending_.pop_front();
     }
@@ -145,6 +150,7 @@ class Scheduler {
 
   const int64_t budget_;
   const int max_sets_, max_channels_;
+  std::function<void(Req&)> on_admit_;
   std::mutex mu_;
   std::condition_variable cv_;
   std::deque<Req> pending_, admitted_;

@@ -38,6 +38,21 @@ static std::vector<int> ids(const std::vector<Req>& b) {
 
 int main() {
   std::vector<Req> b;
+  {  // the admission hook sees requests in admission order, when the budget allows
+    std::vector<int> order;
+    lv::Scheduler<Req> s(100, 8, 1024, [&](Req& r) { order.push_back(r.id); });
+    CHECK(s.submit({60, 1, 1, 1}));
+    CHECK(s.submit({50, 1, 2, 2}));
+    CHECK(s.submit({30, 1, 3, 3}));
+    CHECK(order == std::vector<int>({1}));
+    CHECK(s.next_batch(b) && ids(b) == std::vector<int>({1}));
+    s.complete(b);
+    CHECK(order == std::vector<int>({1, 2, 3}));
+    CHECK(s.next_batch(b));
+    s.complete(b);
+    CHECK(s.next_batch(b));
+    s.complete(b);
+  }
   {  // refusal, FIFO admission blocking behind a request that does not fit
     lv::Scheduler<Req> s(100, 8, 1024);
     CHECK(!s.submit({101, 1, 1, 0}));

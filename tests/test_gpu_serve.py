@@ -1,6 +1,8 @@
 """The uplift server and the pieces it relies on, through the C ABI: sets that
 skip views, maps that are channel slices of wider maps, and requests served
 in merged passes (each result equal to the request run alone)."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -101,7 +103,9 @@ def test_server_results_equal_alone(rig, workers, budget):
         f_alone, b_alone = gs.uplift([cams[v] for v in views], [m.contiguous() for m in maps],
                                      dtype=dtype)
         c = done[i]
-        assert c["t_submit"] <= c["t_start"] <= c["t_end"]
+        assert c["t_submit"] <= c["t_admit"] <= c["t_start"] <= c["t_end"]
+        assert (c["D"], c["views"]) == (D, len(views)) and c["bytes"] > 0
+        assert json.loads(json.dumps(lv.completion_record(c)))["tag"] == i
         assert rel_diff(c["out"], f_alone) < TOL_F, (i, D, views, dtype, c["batch_size"])
         assert rel_diff(c["wsum"][:, None], b_alone[:, None]) < TOL_B
         if i % 3 == 0 or dtype == "bf16":
