@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving trace (0 = skip the serving leg)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, req/s")
+    ap.add_argument("--serve-workers", type=int, default=2, help="server workers (passes in flight)")
     ap.add_argument("--serve-log", default=None,
                     help="write each served request's metrics as JSON lines to PATH.<dtype>.w<workers>.jsonl")
     ap.add_argument("--calib-copy", action="store_true",
@@ -95,7 +96,7 @@ def main():
     torch.cuda.set_device(0)
     if args.only:
         leg = {"mid": lambda: mid_leg(lv, args), "diffuse": lambda: diffusion_leg(lv),
-               "serving": lambda: serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log)}[args.only]
+               "serving": lambda: serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log, workers=args.serve_workers)}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     out, keep = large_leg(lv, args)
@@ -115,7 +116,7 @@ def main():
         out["diffuse"] = diffusion_leg(lv)
         torch.cuda.empty_cache()
         if args.serve_requests > 0:
-            out["serving"] = serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log)
+            out["serving"] = serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log, workers=args.serve_workers)
     print(json.dumps(out), flush=True)
 
 
@@ -522,7 +523,7 @@ def diffusion_leg(lv):
 
 
 # ------------------------------------------------------------------ serving
-def serving(lv, nreq, rate, bank_k=4, log_path=None):
+def serving(lv, nreq, rate, bank_k=4, log_path=None, workers=2):
     """The serving trace (synth.trace) three times: BF16 pixel-block maps through the
     server (2 workers, same-scene requests merged into one pass, admission by
     an HBM budget), FP32 maps through the same server settings, and FP32 maps
@@ -620,9 +621,9 @@ def serving(lv, nreq, rate, bank_k=4, log_path=None):
             res["peak_device_within_budget_plus_client_outputs"] = st["peak_device_bytes"] <= budget + live[1]
         return res, kept
 
-    served, out16 = run("bf16", 2, 8)
+    served, out16 = run("bf16", workers, 8)
     log(f"bench: served bf16 {served}")
-    served32, _ = run("f32", 2, 8)
+    served32, _ = run("f32", workers, 8)
     log(f"bench: served f32 {served32}")
     base, out32 = run("f32", 1, 1)
     log(f"bench: baseline {base}")
