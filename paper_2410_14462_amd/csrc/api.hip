@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "lv_internal.h"
+#include <cmath>
 
 using namespace lv;
 
@@ -195,6 +196,10 @@ struct lv_scene {
   // caller's order (the graph builder and the diffusion's own order read it)
   bool morton = false;
   Buf perm, inv, p0c;
+  // bounding box of the centres (min x, y, z, max x, y, z), for the depth
+  // keys' range
+  bool has_box = false;
+  double box[6] = {0, 0, 0, 0, 0, 0};
   const uint32_t* out_perm() const { return morton ? perm.as<uint32_t>() : nullptr; }
   const float4* caller_p0() const { return morton ? p0c.as<float4>() : p0.as<float4>(); }
 };
@@ -251,6 +256,47 @@ int ceil_log2(int64_t x) {
 // has more than one view and its pairs would reach 2^31 or need more than
 // pair_budget bytes of pair buffers, *split is set and nothing past the pair
 // count is built (the caller retries with fewer views).
+// Bits of the depth keys the depth sort has to order.  A visible Gaussian's
+// key is the FP32 bits of its view depth z_c > znear, which grow with z_c;
+// over a chunk's views, z_c of a centre in the scene's box lies in
+// [zlo, zhi] (the extremes of the box corners, in FP64), widened for the
+// FP32 evaluation.  Keys whose bits above h are those of every key in that
+// range sort on their h low bits; culled items (0xFFFFFFFF) still sort
+// after them as long as the largest key's low h bits are not all ones.
+int depth_key_bits(const lv_scene* sc, const lv_camera* cams, int mv) {
+  if (!sc->has_box) return 32;
+  double zlo = 1e300, zhi = -1e300, amax = 0.0;
+  float znear = 3.4e38f;
+  for (int v = 0; v < mv; v++) {
+    const float* R = cams[v].R;
+    for (int c = 0; c < 8; c++) {
+      const double x = sc->box[(c & 1) ? 3 : 0], y = sc->box[(c & 2) ? 4 : 1], z = sc->box[(c & 4) ? 5 : 2];
+      const double zc = (double)R[6] * x + (double)R[7] * y + (double)R[8] * z + (double)cams[v].t[2];
+      zlo = std::min(zlo, zc);
+      zhi = std::max(zhi, zc);
+      amax = std::max(amax, std::fabs((double)R[6] * x) + std::fabs((double)R[7] * y) +
+                                std::fabs((double)R[8] * z) + std::fabs((double)cams[v].t[2]));
+    }
+    znear = std::min(znear, cams[v].znear);
+  }
+  const double slack = 1e-5 * (amax + std::fabs(zlo) + std::fabs(zhi));  // far above FP32 rounding
+  zlo -= slack;
+  zhi += slack;
+  if (!(zhi > (double)znear) || !(znear >= 0.0f) || !std::isfinite(zhi)) return 32;
+  const float flo = zlo > (double)znear ? std::nextafter((float)zlo, 0.0f) : znear;
+  const float fhi = std::nextafter((float)zhi, 3.4e38f);
+  uint32_t klo, khi;
+  memcpy(&klo, &flo, 4);
+  memcpy(&khi, &fhi, 4);
+  if (klo > khi) return 32;
+  const uint32_t diff = klo ^ khi;
+  const int h = diff ? 32 - __builtin_clz(diff) : 1;
+  if (h >= 32) return 32;
+  const uint32_t low = (1u << h) - 1u;
+  if ((khi & low) == low) return 32;
+  return h;
+}
+
 lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, int mv,
                           hipStream_t s, const uint32_t** ids, int* stride,
                           int64_t* P, int64_t* nvis, int* max_tiles_out,
@@ -312,7 +358,8 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   bool second = false;
   const uint32_t* seg = ws.seg.as<uint32_t>();
   HIP_TRY(radix_sort(ws.key0.as<uint32_t>(), ws.val0.as<uint32_t>(), ws.key1.as<uint32_t>(),
-                     ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, 32, ws.hist.as<uint32_t>(),
+                     ws.val1.as<uint32_t>(), seg, seg + mv, mv, n, depth_key_bits(sc, cams, mv),
+                     ws.hist.as<uint32_t>(),
                      true, &second, s,
                      SortPayload{ws.rect.as<uint2>(), ws.scnt.as<uint32_t>(), ws.srect.as<uint2>()},
                      kDepthPassBits, true));
@@ -616,6 +663,26 @@ lv_status lv_scene_create(const float* means, const float* scales, const float* 
                               sc->p0.as<float4>(), sc->p1.as<float4>(), sc->p2.as<float4>(), s);
     dev_free(scratch, scratch_bytes, s, true);
     dev_free(c12, 2 * b, s, true);
+  }
+  if (e == hipSuccess && n > 0) {
+    // the box on the host (one small read back): bounds of the depth keys
+    void* bx = nullptr;
+    uint32_t hb[6];
+    e = dev_alloc(&bx, 32, s, true);
+    if (e == hipSuccess) e = launch_scene_box(sc->p0.as<float4>(), n, static_cast<uint32_t*>(bx), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hb, bx, 24, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(bx, 32, s, true);
+    if (e == hipSuccess) {
+      for (int k = 0; k < 6; k++) {
+        const uint32_t u = (hb[k] & 0x80000000u) ? (hb[k] & 0x7FFFFFFFu) : ~hb[k];
+        float f;
+        memcpy(&f, &u, 4);
+        sc->box[k] = (double)f;
+      }
+      sc->has_box = std::isfinite(sc->box[0]) && std::isfinite(sc->box[1]) && std::isfinite(sc->box[2]) &&
+                    std::isfinite(sc->box[3]) && std::isfinite(sc->box[4]) && std::isfinite(sc->box[5]);
+    }
   }
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(s);

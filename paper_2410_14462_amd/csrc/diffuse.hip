@@ -540,6 +540,14 @@ size_t reorder_scratch_words(int64_t n) {
   return (size_t)n * 6 + 16 + sort_hist_size(1, n) + scan_tmp_size(n);
 }
 
+hipError_t launch_scene_box(const float4* p0, int64_t n, uint32_t* box, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(box_init_kernel, dim3(1), dim3(64), 0, s, box);
+  hipLaunchKernelGGL(box_kernel, dim3(nb < 256 ? nb : 256), dim3(256), 0, s, p0, n, box);
+  return hipGetLastError();
+}
+
 hipError_t launch_morton_order(const float4* p0, int64_t n, uint32_t* scratch, uint32_t* perm,
                                uint32_t* inv, hipStream_t s) {
   if (n == 0) return hipSuccess;

@@ -328,6 +328,10 @@ hipError_t launch_graph_reorder(const float4* p0, int64_t n, const int32_t* rp, 
                                 const void* val, lv_dtype vt, int64_t nnz, uint32_t* scratch,
                                 uint32_t* perm, uint32_t* inv, int32_t* rp2, int32_t* col2,
                                 void* val2, hipStream_t s);
+// Bounding box of the centres: box[0..2] the minima, box[3..5] the maxima,
+// as order-preserving unsigned encodings of the FP32 values (sign bit
+// flipped for non-negative values, all bits for negative ones).
+hipError_t launch_scene_box(const float4* p0, int64_t n, uint32_t* box, hipStream_t s);
 // The same Morton order without a graph: perm (position -> index) and its
 // inverse; scratch holds reorder_scratch_words(n) uint32.
 hipError_t launch_morton_order(const float4* p0, int64_t n, uint32_t* scratch, uint32_t* perm,
