@@ -390,29 +390,45 @@ lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, in
   int64_t max_len = 0;
   for (int v = 0; v < mv; v++) max_len = std::max<int64_t>(max_len, down[4 + v]);
   *P = (int64_t)total;
-  HIP_TRY(ws.pk0.ensure(4 * total + 4, s));
+  // pair keys: the tile alone (16 bits; the sort is segmented by view) where
+  // the tile ids fit, else view << 20 | tile
+  const bool k16 = max_tiles <= 65536;
+  const size_t kbytes = k16 ? 2 : 4;
+  HIP_TRY(ws.pk0.ensure(kbytes * total + 16, s));
   HIP_TRY(ws.pv0.ensure(4 * total + 4, s));
-  HIP_TRY(ws.pk1.ensure(4 * total + 4, s));
+  HIP_TRY(ws.pk1.ensure(kbytes * total + 16, s));
   HIP_TRY(ws.pv1.ensure(4 * total + 4, s));
   HIP_TRY(ws.hist2.ensure(4 * sort_hist_size(mv, max_len), s));
-  HIP_TRY(launch_duplicate(sval, ws.off.as<uint32_t>(), ws.srect.as<uint2>(), ws.scnt.as<uint32_t>(),
-                           ws.geom.as<ViewGeom>(), n, mv, ws.pk0.as<uint32_t>(),
-                           ws.pv0.as<uint32_t>(), s));
+  if (k16)
+    HIP_TRY(launch_duplicate16(sval, ws.off.as<uint32_t>(), ws.srect.as<uint2>(), ws.scnt.as<uint32_t>(),
+                               ws.geom.as<ViewGeom>(), n, mv, ws.pk0.as<uint16_t>(), ws.pv0.as<uint32_t>(), s));
+  else
+    HIP_TRY(launch_duplicate(sval, ws.off.as<uint32_t>(), ws.srect.as<uint2>(), ws.scnt.as<uint32_t>(),
+                             ws.geom.as<ViewGeom>(), n, mv, ws.pk0.as<uint32_t>(), ws.pv0.as<uint32_t>(), s));
   // one pass (up to 2048 tiles): the tile ranges come from the pass's scanned
   // counts and the sorted keys are not written; else from the sorted keys
   const int tile_bits = ceil_log2(max_tiles);
   const bool one_pass = total > 0 && radix_passes(tile_bits) == 1;
-  HIP_TRY(radix_sort(ws.pk0.as<uint32_t>(), ws.pv0.as<uint32_t>(), ws.pk1.as<uint32_t>(),
-                     ws.pv1.as<uint32_t>(), pseg, pseg + mv, mv, max_len, tile_bits,
-                     ws.hist2.as<uint32_t>(), !one_pass, &second, s));
-  const uint32_t* pk = second ? ws.pk1.as<uint32_t>() : ws.pk0.as<uint32_t>();
+  if (k16)
+    HIP_TRY(radix_sort16(ws.pk0.as<uint16_t>(), ws.pv0.as<uint32_t>(), ws.pk1.as<uint16_t>(),
+                         ws.pv1.as<uint32_t>(), pseg, pseg + mv, mv, max_len, tile_bits,
+                         ws.hist2.as<uint32_t>(), !one_pass, &second, s));
+  else
+    HIP_TRY(radix_sort(ws.pk0.as<uint32_t>(), ws.pv0.as<uint32_t>(), ws.pk1.as<uint32_t>(),
+                       ws.pv1.as<uint32_t>(), pseg, pseg + mv, mv, max_len, tile_bits,
+                       ws.hist2.as<uint32_t>(), !one_pass, &second, s));
   *ids = second ? ws.pv1.as<uint32_t>() : ws.pv0.as<uint32_t>();
   if (one_pass) {
     HIP_TRY(launch_hist_ranges(ws.hist2.as<uint32_t>(), pseg, pseg + mv, mv, max_len, tile_bits,
                                max_tiles, ws.ranges.as<uint2>(), s));
   } else {
     HIP_TRY(hipMemsetAsync(ws.ranges.p, 0, sizeof(uint2) * (size_t)mv * max_tiles, s));
-    HIP_TRY(launch_ranges(pk, (int64_t)total, max_tiles, ws.ranges.as<uint2>(), s));
+    if (k16)
+      HIP_TRY(launch_ranges16(second ? ws.pk1.as<uint16_t>() : ws.pk0.as<uint16_t>(), pseg, pseg + mv, mv,
+                              max_len, max_tiles, ws.ranges.as<uint2>(), s));
+    else
+      HIP_TRY(launch_ranges(second ? ws.pk1.as<uint32_t>() : ws.pk0.as<uint32_t>(), (int64_t)total, max_tiles,
+                            ws.ranges.as<uint2>(), s));
   }
   return LV_OK;
 }

@@ -190,6 +190,17 @@ hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off,
                             const ViewGeom* geom, int64_t n, int m, uint32_t* pair_key,
                             uint32_t* pair_val, hipStream_t s);
 
+// The same with 16-bit tile keys (tiles_stride <= 65536): the view of a pair
+// is its sort segment.
+hipError_t radix_sort16(uint16_t* k0, uint32_t* v0, uint16_t* k1, uint32_t* v1,
+                        const uint32_t* seg_start, const uint32_t* seg_len, int nseg, int64_t max_len,
+                        int bits, uint32_t* hist, bool keys_last, bool* in_second, hipStream_t s);
+hipError_t launch_duplicate16(const uint32_t* sorted_val, const uint32_t* off,
+                              const uint2* sorted_rect, const uint32_t* sorted_cnt,
+                              const ViewGeom* geom, int64_t n, int m, uint16_t* pair_key,
+                              uint32_t* pair_val, hipStream_t s);
+hipError_t launch_ranges16(const uint16_t* pair_key, const uint32_t* seg_start, const uint32_t* seg_len,
+                           int nseg, int64_t max_len, int tiles_stride, uint2* ranges, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* pair_key, int64_t P, int tiles_stride, uint2* ranges,
                          hipStream_t s);
 

@@ -44,9 +44,9 @@ static_assert(kSortThreads == 256 && kWaveItems % 64 == 0, "four waves per block
 // of the block's keys are loaded before any is counted.
 // kB: digit values the LDS arrays hold (passes of at most 8 or 10 bits use
 // smaller arrays, so more blocks fit on a CU).
-template <int kB>
+template <int kB, typename K = uint32_t>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ seg_start,
+    const K* __restrict__ keys, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb, uint32_t* __restrict__ hist) {
   __shared__ uint32_t hs[kB];
   const int g = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
   const uint32_t mask = (uint32_t)nbins - 1u;
   const uint32_t len = seg_len[g];
   const uint32_t base = (uint32_t)b * kSortItems;
-  const uint32_t* k = keys + seg_start[g];
+  const K* k = keys + seg_start[g];
   uint32_t d[kPerThread];
 #pragma unroll
   for (int r = 0; r < kPerThread; r++) {
@@ -212,16 +212,18 @@ __global__ __launch_bounds__(1024) void radix_chunk_write_kernel(uint32_t* __res
 // takes rect[s0 + val] (and its area, the count) to its output position.
 // kKeys false: the keys are not written (kout NULL), so LDS holds each
 // item's digit instead of its key (a smaller block footprint).
-template <int kB, bool kKeys = true>
+template <int kB, bool kKeys = true, typename K = uint32_t>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_len, int shift, int bits, int nb,
     const uint32_t* __restrict__ hist, SortPayload pl) {
   constexpr int kPer = kB / kSortThreads;          // digits per thread in the scan
   __shared__ uint16_t wc[4][kB];                    // per-wave counts, then local cursors
   __shared__ uint32_t gdelta[kB];                   // global minus local position, per digit
-  typedef typename std::conditional<kKeys, uint32_t, uint16_t>::type lk_t;
+  // LDS keeps each item's key (16-bit keys, or 32-bit ones that are written
+  // out) or only its digit
+  typedef typename std::conditional<kKeys && sizeof(K) == 4, uint32_t, uint16_t>::type lk_t;
   __shared__ lk_t lk[kSortItems];
   __shared__ uint32_t lval[kSortItems];
   __shared__ uint32_t wsum[kSortThreads / 64];
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     for (uint32_t p = t; p < items; p += kSortThreads) {
       const uint32_t k = lk[p];
       const uint32_t pos = gdelta[kKeys ? (k >> shift) & mask : k] + p;
-      if (kKeys && kout) kout[pos] = k;
+      if (kKeys && kout) kout[pos] = (K)k;
       vout[pos] = lval[p];
     }
     return;
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
       pos[r] = gdelta[kKeys ? (k >> shift) & mask : k] + p;
       vv[r] = lval[p];
       rr[r] = pl.rect[s0 + vv[r]];
-      if (kKeys && kout) kout[pos[r]] = k;
+      if (kKeys && kout) kout[pos[r]] = (K)k;
     }
   }
 #pragma unroll
@@ -516,12 +518,15 @@ __global__ void seg_kernel(const uint32_t* __restrict__ off, int64_t n, int m,
 // exclusive scan of the counts in this order), so the wave walks them 64 at a
 // time, each lane finding the item that owns its pair by a binary search over
 // the wave's inclusive count prefix.  Within an item, tiles go row by row.
+// K = uint32_t: key view << 20 | tile; K = uint16_t: the tile alone (the
+// sort is segmented by view, so the view is its segment)
+template <typename K>
 __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restrict__ sval,
                                                         const uint32_t* __restrict__ off,
                                                         const uint2* __restrict__ srect,
                                                         const uint32_t* __restrict__ scnt,
                                                         const ViewGeom* __restrict__ geom, int64_t n,
-                                                        uint32_t* __restrict__ pkey,
+                                                        K* __restrict__ pkey,
                                                         uint32_t* __restrict__ pval) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
   const uint32_t p0 = __shfl(p, 0, 64);  // lane 0 is inside the view
   const uint32_t excl = incl - c;
   const uint32_t TX = (uint32_t)geom[v].TX;
-  const uint32_t hv = (uint32_t)v << kViewShift;
+  const uint32_t hv = sizeof(K) == 4 ? (uint32_t)v << kViewShift : 0u;
   for (uint32_t j = 0; j < total; j += 64) {
     const uint32_t slot = j + lane;
     // owner: the number of lanes whose inclusive prefix is <= slot
@@ -563,7 +568,7 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
     const uint32_t og = __shfl(gi, pos, 64);
     if (slot < total) {
       const uint32_t dy = kk / ow;
-      pkey[p0 + slot] = hv | ((oy + dy) * TX + ox + (kk - dy * ow));
+      pkey[p0 + slot] = (K)(hv | ((oy + dy) * TX + ox + (kk - dy * ow)));
       pval[p0 + slot] = og;
     }
   }
@@ -705,6 +710,46 @@ __global__ __launch_bounds__(256) void depth_ties_kernel(const uint32_t* __restr
   }
 }
 
+// Tile ranges from 16-bit sorted tile keys: grid row blockIdx.y is a view
+// (its segment [s0, s0 + len) of the pairs); each thread takes eight keys
+// at an absolute position that is a multiple of 8 (one aligned 16-byte
+// load; keys of the neighbouring segments in it are skipped, and the key
+// buffer has 16 bytes of slack past the last pair).
+__global__ __launch_bounds__(256) void ranges16_kernel(const uint16_t* __restrict__ key,
+                                                       const uint32_t* __restrict__ seg_start,
+                                                       const uint32_t* __restrict__ seg_len, int stride,
+                                                       bool aligned, uint2* __restrict__ ranges) {
+  const int v = blockIdx.y;
+  const int64_t s0 = seg_start[v], e = s0 + (int64_t)seg_len[v];
+  const int64_t p0 = (s0 & ~(int64_t)7) + 8 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (p0 >= e) return;
+  uint32_t k[8];
+  if (aligned) {
+    const uint4 w = *reinterpret_cast<const uint4*>(key + p0);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      k[2 * j] = ws[j] & 0xFFFFu;
+      k[2 * j + 1] = ws[j] >> 16;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; j++) k[j] = p0 + j >= s0 && p0 + j < e ? key[p0 + j] : 0u;
+  }
+  const uint32_t before = p0 > s0 ? key[p0 - 1] : 0u;
+  const uint32_t after = p0 + 8 < e ? key[p0 + 8] : 0u;
+  uint2* rv = ranges + (int64_t)v * stride;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const int64_t i = p0 + j;
+    if (i < s0 || i >= e) continue;
+    const uint32_t prev = j > 0 ? k[j - 1] : before;
+    const uint32_t next = j < 7 ? k[j + 1] : after;
+    if (i == s0 || prev != k[j]) rv[k[j]].x = (uint32_t)i;
+    if (i + 1 == e || next != k[j]) rv[k[j]].y = (uint32_t)(i + 1);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_depth_ties(const uint32_t* key, uint32_t* val, uint2* rect, uint32_t* cnt, int64_t n,
@@ -723,30 +768,33 @@ size_t sort_hist_size(int nseg, int64_t max_len) {
   return (size_t)nseg * kBins * (size_t)nb;
 }
 
-hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
-                      const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
-                      int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
-                      hipStream_t s, SortPayload payload, int pass_bits, bool iota_values) {
+namespace {
+template <typename K>
+hipError_t radix_sort_t(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* seg_start,
+                        const uint32_t* seg_len, int nseg, int64_t max_len, int bits, uint32_t* hist,
+                        bool keys_last, bool* in_second, hipStream_t s, SortPayload payload, int pass_bits,
+                        bool iota_values) {
   *in_second = false;
   if (nseg == 0 || max_len == 0 || bits == 0) return hipSuccess;
   int nb = (int)((max_len + kSortItems - 1) / kSortItems);
-  uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  K *ki = k0, *ko = k1;
+  uint32_t *vi = v0, *vo = v1;
   // fewest passes of at most kRadixBits bits, widths balanced
   pass_bits = pass_bits < 1 ? 1 : (pass_bits > kRadixBits ? kRadixBits : pass_bits);
   const int passes = radix_passes(bits, pass_bits);
   for (int p = 0, shift = 0; p < passes; p++) {
     const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
-    uint32_t* const kout = (p + 1 < passes || keys_last) ? ko : nullptr;
+    K* const kout = (p + 1 < passes || keys_last) ? ko : nullptr;
     const uint32_t* const vin = p == 0 && iota_values ? nullptr : vi;
     const SortPayload pl = p + 1 < passes ? SortPayload{} : payload;
     if (pb <= 8) {
-      hipLaunchKernelGGL((radix_hist_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+      hipLaunchKernelGGL((radix_hist_kernel<256, K>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          seg_start, seg_len, shift, pb, nb, hist);
     } else if (pb <= 10) {
-      hipLaunchKernelGGL((radix_hist_kernel<1024>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+      hipLaunchKernelGGL((radix_hist_kernel<1024, K>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          seg_start, seg_len, shift, pb, nb, hist);
     } else {
-      hipLaunchKernelGGL((radix_hist_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+      hipLaunchKernelGGL((radix_hist_kernel<kBins, K>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          seg_start, seg_len, shift, pb, nb, hist);
     }
     if (pb <= 10 && nb >= 64) {
@@ -763,26 +811,46 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
       hipLaunchKernelGGL(radix_scan_kernel, dim3(nseg), dim3(1024), 0, s, hist, nb, pb);
     }
     if (pb <= 8) {
-      hipLaunchKernelGGL((radix_scatter_kernel<256>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+      hipLaunchKernelGGL((radix_scatter_kernel<256, true, K>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     } else if (pb <= 10 && !kout) {
-      hipLaunchKernelGGL((radix_scatter_kernel<1024, false>), dim3(nb, nseg), dim3(kSortThreads), 0,
+      hipLaunchKernelGGL((radix_scatter_kernel<1024, false, K>), dim3(nb, nseg), dim3(kSortThreads), 0,
                          s, ki, vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     } else if (pb <= 10) {
-      hipLaunchKernelGGL((radix_scatter_kernel<1024>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+      hipLaunchKernelGGL((radix_scatter_kernel<1024, true, K>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     } else {
-      hipLaunchKernelGGL((radix_scatter_kernel<kBins>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
+      hipLaunchKernelGGL((radix_scatter_kernel<kBins, true, K>), dim3(nb, nseg), dim3(kSortThreads), 0, s, ki,
                          vin, kout, vo, seg_start, seg_len, shift, pb, nb, hist, pl);
     }
     shift += pb;
-    uint32_t* t;
-    t = ki; ki = ko; ko = t;
-    t = vi; vi = vo; vo = t;
+    K* tk = ki;
+    ki = ko;
+    ko = tk;
+    uint32_t* tv = vi;
+    vi = vo;
+    vo = tv;
     *in_second = !*in_second;
   }
   return hipGetLastError();
 }
+}  // namespace
+
+hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                      const uint32_t* seg_start, const uint32_t* seg_len, int nseg,
+                      int64_t max_len, int bits, uint32_t* hist, bool keys_last, bool* in_second,
+                      hipStream_t s, SortPayload payload, int pass_bits, bool iota_values) {
+  return radix_sort_t(k0, v0, k1, v1, seg_start, seg_len, nseg, max_len, bits, hist, keys_last, in_second, s,
+                      payload, pass_bits, iota_values);
+}
+
+hipError_t radix_sort16(uint16_t* k0, uint32_t* v0, uint16_t* k1, uint32_t* v1,
+                        const uint32_t* seg_start, const uint32_t* seg_len, int nseg, int64_t max_len,
+                        int bits, uint32_t* hist, bool keys_last, bool* in_second, hipStream_t s) {
+  return radix_sort_t(k0, v0, k1, v1, seg_start, seg_len, nseg, max_len, bits, hist, keys_last, in_second, s,
+                      SortPayload{}, kRadixBits, false);
+}
+
 
 hipError_t launch_hist_ranges(const uint32_t* hist, const uint32_t* seg_start,
                               const uint32_t* seg_len, int nseg, int64_t max_len, int bits,
@@ -827,8 +895,28 @@ hipError_t launch_duplicate(const uint32_t* sorted_val, const uint32_t* off,
                             const ViewGeom* geom, int64_t n, int m, uint32_t* pair_key,
                             uint32_t* pair_val, hipStream_t s) {
   if (n == 0 || m == 0) return hipSuccess;
-  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
+  hipLaunchKernelGGL(duplicate_kernel<uint32_t>, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
                      s, sorted_val, off, sorted_rect, sorted_cnt, geom, n, pair_key, pair_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_duplicate16(const uint32_t* sorted_val, const uint32_t* off,
+                              const uint2* sorted_rect, const uint32_t* sorted_cnt,
+                              const ViewGeom* geom, int64_t n, int m, uint16_t* pair_key,
+                              uint32_t* pair_val, hipStream_t s) {
+  if (n == 0 || m == 0) return hipSuccess;
+  hipLaunchKernelGGL(duplicate_kernel<uint16_t>, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
+                     s, sorted_val, off, sorted_rect, sorted_cnt, geom, n, pair_key, pair_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges16(const uint16_t* pair_key, const uint32_t* seg_start, const uint32_t* seg_len,
+                           int nseg, int64_t max_len, int tiles_stride, uint2* ranges, hipStream_t s) {
+  if (nseg == 0 || max_len == 0) return hipSuccess;
+  const int64_t octs = (max_len + 15) / 8;  // the segment's start rounded down to a multiple of 8
+  const bool aligned = ((uintptr_t)pair_key & 15) == 0;
+  hipLaunchKernelGGL(ranges16_kernel, dim3((unsigned)((octs + 255) / 256), (unsigned)nseg), dim3(256), 0, s,
+                     pair_key, seg_start, seg_len, tiles_stride, aligned, ranges);
   return hipGetLastError();
 }
 
