@@ -63,6 +63,16 @@ def test_structure_bit_exact_two_pass_tile_sort():
         assert check_structure(gs, sc, cam) > 10000
 
 
+def test_structure_bit_exact_32bit_tile_keys():
+    """More than 65,536 tiles (4112x4112: 257 x 257 tiles, 17-bit tile ids):
+    pair keys carry view << 20 | tile in 32 bits instead of the 16-bit tile
+    alone; two tile-sort passes and the ranges from the 32-bit keys."""
+    sc = scenes.make_scene(9, 20000, -4.5, 0.6, 0.0, 1.0)
+    gs = lv.Scene.from_arrays(sc)
+    cam = scenes.look_at(scenes.fibonacci_eyes(1, 3.0)[0], 4112, 4112, 60.0)
+    assert check_structure(gs, sc, cam) > 10000
+
+
 def tie_scene():
     """Seen by a camera on the z axis (depth 4 - z exactly in FP32):
     3,000 Gaussians on the planes z = 0 and z = 0.1 (positions shuffled, so
