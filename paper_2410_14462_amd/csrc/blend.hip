@@ -318,9 +318,16 @@ __device__ __forceinline__ bf16x8 bf16x8_of(uint32_t w0, uint32_t w1, uint32_t w
 // pixels (gx0 .. gx0 + 7, gx0 a multiple of 8) of pixel row gy, as BF16
 // (hi; lo = the FP32 remainder, FP32 maps only).  BF16 maps are exact in hi;
 // FP8 codes too (their per-channel scale multiplies the products, see
-// batch_scatter).  Zeros outside the image and for lanes without a channel.
-// Every lane loads (a safe index where it has nothing to load), then
-// selects: no branch around the loads, so they are all in flight together.
+// batch_scatter).  Every lane loads, from a safe index (block or pixel 0 of
+// the map) where it has nothing to load.  Pixel blocks: the data is used as
+// loaded -- a lane without a channel feeds only its own output column, which
+// is never scattered, and a pixel outside the image has weight 0 in every
+// queued row.  (A select of zeros there becomes a zero fill of the
+// destination registers plus a masked load, and the fill waits for every
+// memory operation in flight: a group's K-steps would load one round trip at
+// a time.)  HWC: eight gathers per row, selected (zeros outside the image
+// and for lanes without a channel), which keeps them from all being in
+// flight at once.
 template <lv_dtype DT, bool PX>
 __device__ __forceinline__ void load_row8(const GroupLanes& L, int b, int gy, int gx0,
                                           const ViewGeom& g, bf16x8& fh, bf16x8& fl) {
@@ -330,18 +337,17 @@ __device__ __forceinline__ void load_row8(const GroupLanes& L, int b, int gy, in
     const int64_t blk = okr ? ((int64_t)gy * ((g.W + 7) >> 3) + (gx0 >> 3)) * L.srcld[b] + L.srcc[b] : 0;
     if constexpr (DT == LV_BF16) {
       const u32x4 q = gptr(static_cast<const u32x4*>(L.src[b]))[blk];
-      fh = okr ? bf16x8_of(q.x, q.y, q.z, q.w) : bf16x8_of(0u, 0u, 0u, 0u);
+      fh = bf16x8_of(q.x, q.y, q.z, q.w);
     } else if constexpr (DT == LV_FP8_E4M3) {
       const u32x2 q = gptr(static_cast<const u32x2*>(L.src[b]))[blk];
       uint32_t h[4];
-      e4m3x4_bf16(okr ? q.x : 0u, h[0], h[1]);
-      e4m3x4_bf16(okr ? q.y : 0u, h[2], h[3]);
+      e4m3x4_bf16(q.x, h[0], h[1]);
+      e4m3x4_bf16(q.y, h[2], h[3]);
       fh = bf16x8_of(h[0], h[1], h[2], h[3]);
     } else {
       const f32x4 qa = gptr(static_cast<const f32x4*>(L.src[b]))[2 * blk];
       const f32x4 qb = gptr(static_cast<const f32x4*>(L.src[b]))[2 * blk + 1];
-      const float v[8] = {okr ? qa.x : 0.0f, okr ? qa.y : 0.0f, okr ? qa.z : 0.0f, okr ? qa.w : 0.0f,
-                          okr ? qb.x : 0.0f, okr ? qb.y : 0.0f, okr ? qb.z : 0.0f, okr ? qb.w : 0.0f};
+      const float v[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
       split8(v, fh, fl);
     }
   } else {
