@@ -222,6 +222,20 @@ __device__ __forceinline__ void load_split_w(const float* w, bf16x8& hi, bf16x8&
   split8(w8, hi, lo);
 }
 
+// The same chunk after split_w_in_place: BF16 hi in its first 16 bytes, lo
+// in the next 16.
+__device__ __forceinline__ void load_w(const float* w, bf16x8& hi, bf16x8& lo) {
+  hi = *reinterpret_cast<const bf16x8*>(w);
+  lo = *reinterpret_cast<const bf16x8*>(w + 4);
+}
+
+__device__ __forceinline__ void split_w_in_place(float* w) {
+  bf16x8 hi, lo;
+  load_split_w(w, hi, lo);
+  *reinterpret_cast<bf16x8*>(w) = hi;
+  *reinterpret_cast<bf16x8*>(w + 4) = lo;
+}
+
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
@@ -829,6 +843,51 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
     // bit r: pixel row r % 8 of quadrant r / 8; K-step t covers bits 2t, 2t + 1
     const uint32_t rows = row_bits(pix0) | (row_bits(pix1) << 8);
     const float* wrow = Wt + (lane & 31) * kPairPitch + 8 * (lane >> 5);
+    if (bsets || any_tail) {
+      // lane l: row l % 32, the pixels of quadrant l / 32
+      const float* rp = Wt + (lane & 31) * kPairPitch + 64 * (lane >> 5);
+      const float* fp = Ft + 64 * (lane >> 5);
+      float bs = 0.0f, ts[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < 16; k++) {
+        const float4 a = *reinterpret_cast<const float4*>(rp + 4 * k);
+        bs += a.x;
+        bs += a.y;
+        bs += a.z;
+        bs += a.w;
+#pragma unroll
+        for (int t = 0; t < kMaxTail; t++) {
+          if (t < ntail) {  // wave-uniform
+            const float4 f = *reinterpret_cast<const float4*>(fp + t * 128 + 4 * k);
+            ts[t] = __builtin_fmaf(a.x, f.x, ts[t]);
+            ts[t] = __builtin_fmaf(a.y, f.y, ts[t]);
+            ts[t] = __builtin_fmaf(a.z, f.z, ts[t]);
+            ts[t] = __builtin_fmaf(a.w, f.w, ts[t]);
+          }
+        }
+      }
+      bs += __shfl_xor(bs, 32, 64);
+#pragma unroll
+      for (int t = 0; t < kMaxTail; t++) ts[t] += __shfl_xor(ts[t], 32, 64);
+      if (lane < count) {
+        for (int b = bsets; b; b &= b - 1) {
+          const SetDesc& sd = sets[__builtin_ctz(b)];
+          beta_atomic_add(sd.beta + ring_gid, bs);
+          if (sd.counts) gatomic_add(sd.counts + ring_gid, ring_cnt);
+        }
+#pragma unroll
+        for (int t = 0; t < kMaxTail; t++)
+          if (tout[t] && ts[t] != 0.0f) u_atomic_add(tout[t], (int64_t)ring_gid * tD[t], ts[t], fixedU);
+      }
+      __syncthreads();  // the FP32 weights read before they are split
+    }
+    // the weights of this lane's operand chunks (row l % 32, pixels
+    // 16 t + 8 (l / 32) + [0, 8)) split once into BF16 hi and lo in place,
+    // for all groups; each lane splits exactly the chunks it reads (the FP32
+    // weights' other reader, the beta and tail sums above, is done)
+#pragma unroll
+    for (int t = 0; t < 8; t++)
+      if ((rows >> (2 * t)) & 3u) split_w_in_place(Wt + (lane & 31) * kPairPitch + 8 * (lane >> 5) + 16 * t);
     if constexpr (!kSplitF && PX) {
       // BF16 / FP8 pixel-block maps: one operand load per K-step and block
       // (the HWC layout's eight loads per operand leave no registers for
@@ -865,7 +924,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
           for (int t = 0; t < 8; t++) {
             if ((rows >> (2 * t)) & 3u) {
               bf16x8 ah, al;
-              load_split_w(wrow + 16 * t, ah, al);
+              load_w(wrow + 16 * t, ah, al);
               acc0 = mfma(ah, F[0][t], acc0);
               acc1 = mfma(ah, F[1][t], acc1);
               acc0 = mfma(al, F[0][t], acc0);
@@ -877,7 +936,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
           for (int t = 0; t < 8; t++) {
             if ((rows >> (2 * t)) & 3u) {
               bf16x8 ah, al;
-              load_split_w(wrow + 16 * t, ah, al);
+              load_w(wrow + 16 * t, ah, al);
               acc0 = mfma(ah, F[0][t], acc0);
               acc0 = mfma(al, F[0][t], acc0);
             }
@@ -904,7 +963,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
               const int gy = q.qy + 2 * (t & 3) + (lane >> 5), gx0 = q.qx + 8 * (t >> 2);
               load_row8<DT, PX>(L, 0, gy, gx0, q.g, h0, l0);
               load_row8<DT, PX>(L, 1, gy, gx0, q.g, h1, l1);
-              load_split_w(wrow + 16 * t, ah, al);
+              load_w(wrow + 16 * t, ah, al);
               acc0 = mfma(ah, h0, acc0);
               acc1 = mfma(ah, h1, acc1);
               acc0 = mfma(al, h0, acc0);
@@ -921,7 +980,7 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
             if ((rows >> (2 * t)) & 3u) {
               bf16x8 h0, l0, ah, al;
               load_row8<DT, PX>(L, 0, q.qy + 2 * (t & 3) + (lane >> 5), q.qx + 8 * (t >> 2), q.g, h0, l0);
-              load_split_w(wrow + 16 * t, ah, al);
+              load_w(wrow + 16 * t, ah, al);
               acc0 = mfma(ah, h0, acc0);
               acc0 = mfma(al, h0, acc0);
               if constexpr (kSplitF) acc0 = mfma(ah, l0, acc0);
@@ -929,43 +988,6 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
           }
         }
         batch_scatter<DT>(L, two, count, ring_gid, lane, acc0, acc1, fixedU);
-      }
-    }
-    if (bsets || any_tail) {
-      // lane l: row l % 32, the pixels of quadrant l / 32
-      const float* rp = Wt + (lane & 31) * kPairPitch + 64 * (lane >> 5);
-      const float* fp = Ft + 64 * (lane >> 5);
-      float bs = 0.0f, ts[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int k = 0; k < 16; k++) {
-        const float4 a = *reinterpret_cast<const float4*>(rp + 4 * k);
-        bs += a.x;
-        bs += a.y;
-        bs += a.z;
-        bs += a.w;
-#pragma unroll
-        for (int t = 0; t < kMaxTail; t++) {
-          if (t < ntail) {  // wave-uniform
-            const float4 f = *reinterpret_cast<const float4*>(fp + t * 128 + 4 * k);
-            ts[t] = __builtin_fmaf(a.x, f.x, ts[t]);
-            ts[t] = __builtin_fmaf(a.y, f.y, ts[t]);
-            ts[t] = __builtin_fmaf(a.z, f.z, ts[t]);
-            ts[t] = __builtin_fmaf(a.w, f.w, ts[t]);
-          }
-        }
-      }
-      bs += __shfl_xor(bs, 32, 64);
-#pragma unroll
-      for (int t = 0; t < kMaxTail; t++) ts[t] += __shfl_xor(ts[t], 32, 64);
-      if (lane < count) {
-        for (int b = bsets; b; b &= b - 1) {
-          const SetDesc& sd = sets[__builtin_ctz(b)];
-          beta_atomic_add(sd.beta + ring_gid, bs);
-          if (sd.counts) gatomic_add(sd.counts + ring_gid, ring_cnt);
-        }
-#pragma unroll
-        for (int t = 0; t < kMaxTail; t++)
-          if (tout[t] && ts[t] != 0.0f) u_atomic_add(tout[t], (int64_t)ring_gid * tD[t], ts[t], fixedU);
       }
     }
     __syncthreads();  // rows read before they are written again
