@@ -959,6 +959,7 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
     ba.groups = reinterpret_cast<const ChanGroup*>(dev + b_sets);
     ba.ngroups = (int32_t)groups.size();
     ba.max_width = max_width;
+    ba.has_tail = !groups.empty() && groups.back().ntail > 0 ? 1 : 0;
     {
       TraceRange tb("lv.blend");
       std::lock_guard<std::mutex> pk(g_prof_mu);

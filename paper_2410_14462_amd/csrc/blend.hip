@@ -771,7 +771,10 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
   constexpr bool kSplitF = DT == LV_F32;
   __shared__ __align__(16) float Wt[32 * kPairPitch];  // queued Gaussians: [row][128 pixels]
   __shared__ float4 Rs[kChunk][2];                     // the step's records
-  __shared__ __align__(16) float Ft[kMaxTail * 128];   // tail channels per pixel
+  // tail channels per pixel [kMaxTail][128]: dynamic, allocated only when the
+  // last group has a tail (without it the workgroup's 19.2 KB of LDS lets 8
+  // workgroups share a CU instead of 7)
+  extern __shared__ __align__(16) float Ft[];
   __shared__ uint32_t Rg[32], Rc[32];
   Pair q;
   if (!decode_pair(ranges, geom, tiles_stride, nviews, q)) return;
@@ -827,8 +830,10 @@ __global__ __launch_bounds__(64, 2) void blend_pair_kernel(
       tD[t] = sd.D;
       any_tail = true;
     }
-    Ft[t * 128 + lane] = ft0;
-    Ft[t * 128 + 64 + lane] = ft1;
+    if (t < ntail) {  // wave-uniform
+      Ft[t * 128 + lane] = ft0;
+      Ft[t * 128 + 64 + lane] = ft1;
+    }
   }
   if (!has_main && !any_tail && !bsets && !ssets) return;  // wave-uniform
 
@@ -1075,7 +1080,8 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
   if (multi) {
     // one wave per half tile: two per tile, whole rounds of 8 XCDs
     const int64_t pblocks = ((int64_t)a.tiles_stride * m + 7) / 8 * 16;
-    hipLaunchKernelGGL((blend_pair_kernel<DT, PX>), dim3((unsigned)pblocks), dim3(64), 0, s, a.rec,
+    const size_t tail_lds = a.has_tail ? sizeof(float) * kMaxTail * 128 : 0;
+    hipLaunchKernelGGL((blend_pair_kernel<DT, PX>), dim3((unsigned)pblocks), dim3(64), tail_lds, s, a.rec,
                        a.ids, a.ranges, a.geom, a.n, a.tiles_stride, m, a.sets, a.groups,
                        a.ngroups);
   } else

@@ -247,6 +247,7 @@ struct BlendArgs {
   const ChanGroup* groups;     // device (wide kernel)
   int32_t ngroups;
   int32_t max_width;           // widest group (LDS size)
+  int32_t has_tail;            // the last group has tail channels
 };
 hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s);
 // dst_beta[k][i] += beta[i], dst_counts[k][i] += counts[i] (entries may be
