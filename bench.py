@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--oracle-views", type=int, default=6,
                     help="views of the headline workload the FP64 oracle runs (0 = skip)")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
-    ap.add_argument("--only", choices=["mid", "diffuse", "serving"],
+    ap.add_argument("--only", choices=["mid", "diffuse", "render", "serving"],
                     help="run one secondary leg alone (no headline; for profiles)")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving trace (0 = skip the serving leg)")
@@ -96,6 +96,7 @@ def main():
     torch.cuda.set_device(0)
     if args.only:
         leg = {"mid": lambda: mid_leg(lv, args), "diffuse": lambda: diffusion_leg(lv),
+               "render": lambda: render_leg(lv),
                "serving": lambda: serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log, workers=args.serve_workers)}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
@@ -114,6 +115,8 @@ def main():
         out["mid"] = mid_leg(lv, args)
         torch.cuda.empty_cache()
         out["diffuse"] = diffusion_leg(lv)
+        torch.cuda.empty_cache()
+        out["render"] = render_leg(lv)
         torch.cuda.empty_cache()
         if args.serve_requests > 0:
             out["serving"] = serving(lv, args.serve_requests, args.serve_rate, log_path=args.serve_log, workers=args.serve_workers)
@@ -519,6 +522,60 @@ def diffusion_leg(lv):
     G.close()
     Gb.close()
     gs.close()
+    return res
+
+
+# ------------------------------------------------------------ forward render
+RENDER_VIEWS = 20
+
+
+def render_leg(lv):
+    """Eq. (4) on the large scene: D = 384 FP32 features (seeded normal draws)
+    rendered with opacity into the first RENDER_VIEWS of its 1008x756 views,
+    into preallocated outputs.  Algorithmic bytes per view: every output
+    written once, H W (D + 1) 4, and the features of the Gaussians the view
+    sees read once, taken as n D 4 (the rig sees all but 0.03 % of the scene
+    in every view); the render kernel's own time from HIP events around its
+    launches."""
+    import torch
+
+    from synth import scenes
+
+    w = scenes.WORKLOADS["large"]
+    n, H, W, D = w.n, w.height, w.width, w.D
+    m = RENDER_VIEWS
+    log(f"bench: render leg {w.name}: {m} views, D={D}")
+    sc = scenes.scene_for(w)
+    cams = scenes.cameras_for(w)[:m]
+    gs = lv.Scene.from_arrays(sc)
+    gen = torch.Generator().manual_seed(w.seed + 4)
+    g = torch.randn((n, D), generator=gen).to("cuda")
+    outs = ([torch.empty((H, W, D), device="cuda") for _ in range(m)],
+            [torch.empty((H, W), device="cuda") for _ in range(m)])
+    gs.render(cams, g, outs=outs)  # warmup
+    torch.cuda.synchronize()
+    reps = 3
+    lv.profile_start()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        gs.render(cams, g, outs=outs)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) * 1e3 / reps
+    bl = lv.profile_stop()
+    gs.close()
+    launch_ms = float(sum(bl)) / reps
+    byts = m * (H * W * (D + 1) * 4 + n * D * 4)
+    gbs = byts / (launch_ms * 1e-3) / 1e9
+    res = {"workload": f"render-1M-{m}v-{W}x{H}-D{D}", "views": m, "D": D,
+           "ms_per_call": round(t, 3), "ms_per_view": round(t / m, 4),
+           "ms_per_view_channel": round(t / (m * D), 7),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "render_kernel",
+                        "launches_per_call": len(bl) / reps, "launch_ms": round(launch_ms, 4),
+                        "alg_bytes_per_call": byts}}
+    log(f"bench: render: {t:.2f} ms per call of {m} views, render kernel {launch_ms:.2f} ms "
+        f"({gbs:.0f} GB/s, {gbs / HBM_PEAK_GBS:.3f} of HBM)")
+    del outs
     return res
 
 

@@ -308,9 +308,9 @@ typedef struct lv_uplift_stats {
 } lv_uplift_stats;
 lv_status lv_accum_stats(lv_accum* acc, lv_uplift_stats* out);
 
-/* Benchmark timing of the blend-and-accumulate kernel: after
- * lv_profile_start, every blend launch is bracketed by HIP events on its
- * stream; lv_profile_stop waits for them and returns the number of launches,
+/* Benchmark timing of the blend-and-accumulate and forward-render kernels:
+ * after lv_profile_start, every blend launch (uplift) and render launch
+ * (lv_render) is bracketed by HIP events on its stream; lv_profile_stop waits for them and returns the number of launches,
  * their summed duration in milliseconds and, in per_launch_ms (host, nullable,
  * `capacity` entries), each launch's duration in launch order.
  * Process-wide. */

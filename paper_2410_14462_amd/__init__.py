@@ -361,15 +361,27 @@ class Scene:
                                _ptr(wsum), _stream()))
         return out, wsum
 
-    def render(self, cams, g, alpha=True):
-        """Eq. (4): g [n, D] f32 -> ([H, W, D] per camera, [H, W] opacity per camera)."""
+    def render(self, cams, g, alpha=True, outs=None):
+        """Eq. (4): g [n, D] f32 -> ([H, W, D] per camera, [H, W] opacity per camera).
+        outs: optional (maps, opacities) to write into (opacities [] when alpha
+        is False), each shaped as above."""
         import torch
         if g.dim() == 1:
             g = g[:, None]
         _dev_f32(g, (self.n, g.shape[1]))
         D = g.shape[1]
-        outs = [torch.empty((c.height, c.width, D), device="cuda") for c in cams]
-        alps = [torch.empty((c.height, c.width), device="cuda") for c in cams] if alpha else []
+        if outs is not None:
+            outs, alps = outs
+            if len(outs) != len(cams) or (alpha and len(alps) != len(cams)):
+                raise LvError("render: one output (and opacity) per camera")
+            for c, o in zip(cams, outs):
+                _dev_f32(o, (c.height, c.width, D))
+            if alpha:
+                for c, a in zip(cams, alps):
+                    _dev_f32(a, (c.height, c.width))
+        else:
+            outs = [torch.empty((c.height, c.width, D), device="cuda") for c in cams]
+            alps = [torch.empty((c.height, c.width), device="cuda") for c in cams] if alpha else []
         to = (ctypes.c_void_p * max(1, len(cams)))(*[o.data_ptr() for o in outs])
         ta = (ctypes.c_void_p * max(1, len(cams)))(*[a.data_ptr() for a in alps]) if alpha else None
         _check(lib().lv_render(self.handle, _cams(cams), len(cams), _ptr(g), D, to, ta, _stream()))

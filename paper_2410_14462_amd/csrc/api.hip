@@ -297,6 +297,26 @@ int depth_key_bits(const lv_scene* sc, const lv_camera* cams, int mv) {
   return h;
 }
 
+
+// Runs launch() (a kernel launch on s); while profiling is on (lv_profile_start)
+// it is bracketed by HIP events on s.
+template <typename F>
+static lv_status profiled_launch(hipStream_t s, F&& launch) {
+  std::lock_guard<std::mutex> pk(g_prof_mu);
+  if (g_prof_on) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    HIP_TRY(launch());
+    HIP_TRY(hipEventRecord(e1, s));
+    g_prof_events.emplace_back(e0, e1);
+  } else {
+    HIP_TRY(launch());
+  }
+  return LV_OK;
+}
+
 lv_status build_structure(lv_scene* sc, Workspace& ws, const lv_camera* cams, int mv,
                           hipStream_t s, const uint32_t** ids, int* stride,
                           int64_t* P, int64_t* nvis, int* max_tiles_out,
@@ -962,18 +982,8 @@ lv_status lv_uplift_accumulate_sets(const lv_camera* cams, int32_t m, const lv_f
     ba.has_tail = !groups.empty() && groups.back().ntail > 0 ? 1 : 0;
     {
       TraceRange tb("lv.blend");
-      std::lock_guard<std::mutex> pk(g_prof_mu);
-      if (g_prof_on) {
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        HIP_TRY(hipEventRecord(e0, s));
-        HIP_TRY(launch_blend(ba, dtype, mv, s));
-        HIP_TRY(hipEventRecord(e1, s));
-        g_prof_events.emplace_back(e0, e1);
-      } else {
-        HIP_TRY(launch_blend(ba, dtype, mv, s));
-      }
+      st = profiled_launch(s, [&] { return launch_blend(ba, dtype, mv, s); });
+      if (st != LV_OK) return st;
     }
     for (int k = 0; k < nsets; k++) {
       if (slot[k] < 0) continue;
@@ -1445,31 +1455,17 @@ lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float*
   const int64_t n = sc->n;
   if (n > 0 && !g) return fail(LV_ERR_INVALID_ARG, "g is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // pixels no Gaussian reaches stay 0
-  for (int v = 0; v < m; v++) {
-    const size_t px = (size_t)cams[v].width * cams[v].height;
-    HIP_TRY(hipMemsetAsync(outs[v], 0, sizeof(float) * px * D, s));
-    if (alphas && alphas[v]) HIP_TRY(hipMemsetAsync(alphas[v], 0, sizeof(float) * px, s));
+  if (n == 0) {  // no Gaussian: every output is 0 (with Gaussians the kernel writes every pixel)
+    for (int v = 0; v < m; v++) {
+      const size_t px = (size_t)cams[v].width * cams[v].height;
+      HIP_TRY(hipMemsetAsync(outs[v], 0, sizeof(float) * px * D, s));
+      if (alphas && alphas[v]) HIP_TRY(hipMemsetAsync(alphas[v], 0, sizeof(float) * px, s));
+    }
   }
   if (n == 0 || m == 0) return LV_OK;
-  // g in the scene's storage order
-  void* gs = nullptr;
-  const size_t gs_bytes = sizeof(float) * (size_t)n * D;
-  if (sc->morton) {
-    HIP_TRY(dev_alloc(&gs, gs_bytes, s, true));
-    const hipError_t e = launch_permute_rows(g, gs, sc->perm.as<uint32_t>(), n, D, LV_F32, false, s);
-    if (e != hipSuccess) {
-      dev_free(gs, gs_bytes, s, true);
-      return fail(LV_ERR_DEVICE, "render: %s", hipGetErrorString(e));
-    }
-    g = static_cast<const float*>(gs);
-  }
-  struct TempFree {  // returned to the allocator on the stream, whatever the exit
-    void* p;
-    size_t bytes;
-    hipStream_t s;
-    ~TempFree() { dev_free(p, bytes, s, true); }
-  } gs_free{gs, gs_bytes, s};
+  // g stays in the caller's order: the kernel reads row perm[i] for the
+  // scene's storage index i
+  const uint32_t* perm = sc->morton ? sc->perm.as<uint32_t>() : nullptr;
   Workspace& ws = *workspace_for(s);
   std::lock_guard<std::mutex> lk(ws.mu);
   const int64_t per_view = n * kItemBytes;
@@ -1508,7 +1504,8 @@ lv_status lv_render(lv_scene* sc, const lv_camera* cams, int32_t m, const float*
     ba.n = n;
     ba.tiles_stride = stride;
     float* const* dtab = static_cast<float* const*>(ws.maps.p);
-    HIP_TRY(launch_render(ba, mv, g, D, dtab, dtab + mv, s));
+    st = profiled_launch(s, [&] { return launch_render(ba, mv, g, D, dtab, dtab + mv, perm, s); });
+    if (st != LV_OK) return st;
     v0 += mv;
   }
   return LV_OK;

@@ -90,9 +90,11 @@ struct Quad {
   ViewGeom g;
 };
 
+// empty_ok: a tile without Gaussians is kept (the render writes its zeros).
 __device__ __forceinline__ bool decode_quad(const uint2* __restrict__ ranges,
                                             const ViewGeom* __restrict__ geom, int tiles_stride,
-                                            int nviews, int ngroups, Quad& q) {
+                                            int nviews, int ngroups, Quad& q,
+                                            bool empty_ok = false) {
   const uint32_t L = blockIdx.x;
   const uint32_t kx = L >> 3;
   const uint32_t work = ((kx >> 2) << 3) | (L & 7u);
@@ -104,7 +106,7 @@ __device__ __forceinline__ bool decode_quad(const uint2* __restrict__ ranges,
   q.g = geom[q.v];
   if (q.tile >= q.g.TX * q.g.TY) return false;
   q.rg = ranges[(int64_t)q.v * tiles_stride + q.tile];
-  if (q.rg.y <= q.rg.x) return false;
+  if (q.rg.y <= q.rg.x && !empty_ok) return false;
   const int tx = q.tile % q.g.TX, ty = q.tile / q.g.TX;
   q.qx = tx * kTile + (quad & 1) * 8;
   q.qy = ty * kTile + (quad >> 1) * 8;
@@ -139,17 +141,21 @@ __device__ __forceinline__ void walk_init(const Quad& q, int lane, Walk& s) {
 // tile-relative and left in rs[lane] = {(cx, cy, L11, L12), (L22, opacity,
 // tau, -)} for the walk; the hit mask (the alpha >= 1/255 region can touch
 // the quadrant).
+// perm (nullable): storage -> caller order; my_id is then the caller's index
+// (loaded beside the records).
 __device__ __forceinline__ uint64_t step_records(const Rec* __restrict__ vrec,
                                                  const uint32_t* __restrict__ ids, uint32_t base,
                                                  int cnt, int lane, const Walk& s, uint32_t& my_id,
-                                                 float4 (*rs)[2]) {
+                                                 float4 (*rs)[2],
+                                                 const uint32_t* __restrict__ perm = nullptr) {
   float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   float4 q1 = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
   my_id = 0;
   if (lane < cnt) {
-    my_id = ids[base + lane];
-    q0 = vrec[my_id].r0;
-    q1 = vrec[my_id].r1;
+    const uint32_t id = ids[base + lane];
+    my_id = perm ? perm[id] : id;
+    q0 = vrec[id].r0;
+    q1 = vrec[id].r1;
     // centre relative to the tile (see Rec)
     const uint32_t lo = __float_as_uint(q1.w);
     q0.x = (q0.x - s.ocx) + __uint_as_float(lo << 16);
@@ -1107,13 +1113,15 @@ __global__ __launch_bounds__(64, 3) void render_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews, int ngroups,
     const float* __restrict__ g, int D, float* const* __restrict__ outs,
-    float* const* __restrict__ alphas) {
+    float* const* __restrict__ alphas, const uint32_t* __restrict__ perm) {
   constexpr int G = kChunk;
   __shared__ __align__(16) float Wt[32 * kWtPitch];  // queued Gaussians: [row][pixel]
   __shared__ float4 Rs[kChunk][2];                   // the step's records
   __shared__ uint32_t Rg[32];                        // queued Gaussians' ids
   Quad q;
-  if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q)) return;
+  // every in-image (pixel, channel) of every view is written, zeros where no
+  // Gaussian reaches (a tile without Gaussians walks nothing)
+  if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q, true)) return;
   const int lane = threadIdx.x;
   const int c0 = q.cg * kRenderCh;
   // this lane's channel in each 32-channel block (a readable one where it has none)
@@ -1168,7 +1176,7 @@ __global__ __launch_bounds__(64, 3) void render_kernel(
     if (__ballot(s.alive) == 0ull) break;
     const int cnt = (int)(q.rg.y - base < (uint32_t)G ? q.rg.y - base : (uint32_t)G);
     uint32_t my_id;
-    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, my_id, Rs);
+    const uint64_t hits = step_records(vrec, ids, base, cnt, lane, s, my_id, Rs, perm);
     if (!hits) continue;
     __syncthreads();  // records in LDS (one wave per workgroup: orders LDS)
     for (uint64_t h = hits; h; h &= h - 1) {
@@ -1177,7 +1185,7 @@ __global__ __launch_bounds__(64, 3) void render_kernel(
       const float wj = walk_rec(Rs[j][0], Rs[j][1], s, take);
       if (__ballot(take)) {
         Wt[queued * kWtPitch + lane] = wj;
-        if (lane == j) Rg[queued] = my_id;  // lane j holds the Gaussian's id
+        if (lane == j) Rg[queued] = my_id;  // lane j holds the Gaussian's (caller) index
         asum += wj;
         if (++queued == 32) {
           flush(32);
@@ -1304,13 +1312,13 @@ hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s
 }
 
 hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float* const* outs,
-                         float* const* alphas, hipStream_t s) {
+                         float* const* alphas, const uint32_t* perm, hipStream_t s) {
   if (m == 0 || a.tiles_stride == 0) return hipSuccess;
   const int ngroups = (D + kRenderCh - 1) / kRenderCh;
   const int64_t work = (int64_t)a.tiles_stride * m * ngroups;
   const int64_t blocks = (work + 7) / 8 * 32;  // 4 quadrants per tile, whole rounds of 8 XCDs
   hipLaunchKernelGGL(render_kernel, dim3((unsigned)blocks), dim3(64), 0, s, a.rec, a.ids, a.ranges,
-                     a.geom, a.n, a.tiles_stride, m, ngroups, g, D, outs, alphas);
+                     a.geom, a.n, a.tiles_stride, m, ngroups, g, D, outs, alphas, perm);
   return hipGetLastError();
 }
 

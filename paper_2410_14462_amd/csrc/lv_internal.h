@@ -263,9 +263,11 @@ hipError_t launch_class_add(const beta_t* beta, const uint32_t* counts, const Cl
 
 // Eq. (4) forward render of g [n][D] into outs[v] [H][W][D] (device table of
 // m pointers) and the accumulated opacity into alphas[v] [H][W] (entries may
-// be null); pixels of empty tiles are not written.
+// be null); every in-image pixel is written (zeros where no Gaussian
+// reaches).  perm (nullable): storage -> caller order of the scene; g is in
+// the caller's order.
 hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float* const* outs,
-                         float* const* alphas, hipStream_t s);
+                         float* const* alphas, const uint32_t* perm, hipStream_t s);
 // Keep the k Gaussians with the largest wsum (ties to the lower index):
 // keep[i] = 1 for them, 0 for the others (scratch from the stream-ordered
 // allocator).

@@ -61,8 +61,41 @@ def test_render_empty_view_and_bad_args(setup):
     sc, cams, gs = setup
     away = scenes.look_at([0, 0, 40.0], 64, 48, 60.0)
     away.t = -away.t  # the cloud is behind this camera
-    outs, alphas = gs.render([away], torch.ones((sc.n, 3), device="cuda"))
+    # outputs filled with NaN first: the render writes every pixel, zeros
+    # where no Gaussian reaches
+    out = torch.full((48, 64, 3), float("nan"), device="cuda")
+    alpha = torch.full((48, 64), float("nan"), device="cuda")
+    outs, alphas = gs.render([away], torch.ones((sc.n, 3), device="cuda"), outs=([out], [alpha]))
     torch.cuda.synchronize()
     assert torch.all(outs[0] == 0) and torch.all(alphas[0] == 0)
     with pytest.raises(lv.LvError):
         gs.render(cams[:1], torch.ones((sc.n + 1, 3), device="cuda"))
+
+
+def test_render_full_size_view():
+    """The render benchmark's configuration on one view: the 1M-Gaussian
+    scene, a 1008 x 756 camera of its rig, D = 384 FP32 features, written into
+    caller-provided outputs; every pixel against the oracle's render (pixels
+    with an ambiguous skip/stop decision excluded and counted)."""
+    w = scenes.WORKLOADS["large"]
+    sc = scenes.scene_for(w)
+    cam = scenes.cameras_for(w)[0]
+    gs = lv.Scene.from_arrays(sc)
+    D = w.D
+    g = np.random.default_rng(2024).standard_normal((sc.n, D), dtype=np.float32)
+    out = torch.full((cam.height, cam.width, D), float("nan"), device="cuda")
+    alpha = torch.full((cam.height, cam.width), float("nan"), device="cuda")
+    outs, alphas = gs.render([cam], torch.as_tensor(g, device="cuda"), outs=([out], [alpha]))
+    assert outs[0] is out and alphas[0] is alpha
+    got = out.cpu().numpy().astype(np.float64)
+    got_a = alpha.cpu().numpy()
+    gs.close()
+    print("render full-size view: oracle", flush=True)
+    ref, ref_a, amb = oracle.render(sc, cam, g, amb_px=True)
+    scale, _ = oracle.render(sc, cam, np.abs(g))
+    err = np.abs(got - ref) / np.maximum(scale, 1e-30)
+    ok = ~amb
+    print(f"render full-size view: max err {err[ok].max():.3e}, ambiguous pixels {int(amb.sum())}", flush=True)
+    assert amb.sum() <= 0.001 * amb.size
+    assert err[ok].max() < 1e-4
+    assert np.abs(got_a - ref_a)[ok].max() < 1e-5
