@@ -1099,17 +1099,19 @@ hipError_t launch_blend_t(const BlendArgs& a, int m, hipStream_t s) {
 
 // ------------------------------------------------------------ forward render
 // Eq. (4): F^(p) = sum_i w_i(p) g_i, the adjoint of the uplift.  One wave per
-// (view, quadrant, group of 64 channels) walks its tile's list exactly as the
-// uplift does; a Gaussian with some contribution queues its weights at the
-// 64 pixels in one of 32 LDS rows (its id beside it).  A full queue (and the
-// last, partial one) is flushed on the matrix cores: out (64 pixels x 64
-// channels) += W^T (64 x 32 rows) G (32 rows x 64 channels), split BF16
-// operands as in the uplift, the four 32x32 output blocks held in registers
-// until the walk ends; each (pixel, channel) is then written once.  The
-// opacity sum_i w_i(p) goes to alpha[v] (group 0).
-constexpr int kRenderCh = 64;
-
-__global__ __launch_bounds__(64, 3) void render_kernel(
+// (view, quadrant, group of 32 NB channels) walks its tile's list exactly as
+// the uplift does; a Gaussian with some contribution queues its weights at
+// the 64 pixels in one of 32 LDS rows (its index beside it).  A full queue
+// (and the last, partial one) is flushed on the matrix cores: out (64 pixels
+// x 32 NB channels) += W^T (64 x 32 rows) G (32 rows x 32 NB channels), split
+// BF16 operands as in the uplift, the 2 x NB 32x32 output blocks held in
+// registers until the walk ends; each (pixel, channel) is then written once.
+// The opacity sum_i w_i(p) goes to alpha[v] (group 0).  NB = 2 (64 channels)
+// for D <= 64, else 4: the walk, repeated for every group of channels, runs
+// half as often, and the 8 output blocks' 128 registers leave 2 waves per
+// SIMD instead of 3.
+template <int NB>
+__global__ __launch_bounds__(64, (NB == 2 ? 3 : 2)) void render_kernel(
     const Rec* __restrict__ rec, const uint32_t* __restrict__ ids, const uint2* __restrict__ ranges,
     const ViewGeom* __restrict__ geom, int64_t n, int tiles_stride, int nviews, int ngroups,
     const float* __restrict__ g, int D, float* const* __restrict__ outs,
@@ -1123,48 +1125,59 @@ __global__ __launch_bounds__(64, 3) void render_kernel(
   // Gaussian reaches (a tile without Gaussians walks nothing)
   if (!decode_quad(ranges, geom, tiles_stride, nviews, ngroups, q, true)) return;
   const int lane = threadIdx.x;
-  const int c0 = q.cg * kRenderCh;
+  const int c0 = q.cg * 32 * NB;
   // this lane's channel in each 32-channel block (a readable one where it has none)
-  const int ch0 = c0 + (lane & 31), ch1 = c0 + 32 + (lane & 31);
-  const bool own0 = ch0 < D, own1 = ch1 < D;
-  f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};  // [pixel block][channel block]
+  int ch[NB];
+  bool own[NB];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    ch[b] = c0 + 32 * b + (lane & 31);
+    own[b] = ch[b] < D;
+    if (!own[b]) ch[b] = 0;
+  }
+  f32x16 acc[2][NB];  // [pixel block][channel block]
+#pragma unroll
+  for (int b = 0; b < NB; b++) acc[0][b] = acc[1][b] = f32x16{};
   float asum = 0.0f;
   int queued = 0;
 
-  // K-step t: queue rows 16 t + 8 (l / 32) + i, i < 8
+  // K-step t: queue rows 16 t + 8 (l / 32) + i, i < 8.  Rows past count
+  // have weight 0 and read the features of row 0 (in this flush), and a lane
+  // without a channel feeds only its own output column, never written: the
+  // loaded features are used as loaded (no select, so no zero fill that would
+  // wait for every load in flight).
   auto flush = [&](int count) {
     __syncthreads();  // rows written (one wave per workgroup: orders LDS)
     for (int t = 0; t < 2 && 16 * t < count; t++) {
-      float w0[8], w1[8], g0[8], g1[8];
+      float w0[8], w1[8];
+      int64_t gid[8];
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const int row = 16 * t + 8 * (lane >> 5) + i;
         const bool ok = row < count;
-        const int64_t gid = ok ? (int64_t)Rg[row] : 0;
+        gid[i] = (int64_t)Rg[ok ? row : 0];
         w0[i] = ok ? Wt[row * kWtPitch + (lane & 31)] : 0.0f;
         w1[i] = ok ? Wt[row * kWtPitch + 32 + (lane & 31)] : 0.0f;
-        const float x0 = g[gid * D + (own0 ? ch0 : 0)];  // no branch around the loads
-        const float x1 = g[gid * D + (own1 ? ch1 : 0)];
-        g0[i] = ok && own0 ? x0 : 0.0f;
-        g1[i] = ok && own1 ? x1 : 0.0f;
       }
-      bf16x8 a0h, a0l, a1h, a1l, b0h, b0l, b1h, b1l;
+      float gb[NB][8];
+#pragma unroll
+      for (int c = 0; c < NB; c++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) gb[c][i] = g[gid[i] * D + ch[c]];
+      bf16x8 a0h, a0l, a1h, a1l;
       split8(w0, a0h, a0l);
       split8(w1, a1h, a1l);
-      split8(g0, b0h, b0l);
-      split8(g1, b1h, b1l);
-      acc00 = mfma(a0h, b0h, acc00);
-      acc01 = mfma(a0h, b1h, acc01);
-      acc10 = mfma(a1h, b0h, acc10);
-      acc11 = mfma(a1h, b1h, acc11);
-      acc00 = mfma(a0l, b0h, acc00);
-      acc01 = mfma(a0l, b1h, acc01);
-      acc10 = mfma(a1l, b0h, acc10);
-      acc11 = mfma(a1l, b1h, acc11);
-      acc00 = mfma(a0h, b0l, acc00);
-      acc01 = mfma(a0h, b1l, acc01);
-      acc10 = mfma(a1h, b0l, acc10);
-      acc11 = mfma(a1h, b1l, acc11);
+#pragma unroll
+      for (int c = 0; c < NB; c++) {
+        bf16x8 bh, bl;
+        split8(gb[c], bh, bl);
+        acc[0][c] = mfma(a0h, bh, acc[0][c]);
+        acc[1][c] = mfma(a1h, bh, acc[1][c]);
+        acc[0][c] = mfma(a0l, bh, acc[0][c]);
+        acc[1][c] = mfma(a1l, bh, acc[1][c]);
+        acc[0][c] = mfma(a0h, bl, acc[0][c]);
+        acc[1][c] = mfma(a1h, bl, acc[1][c]);
+      }
     }
     __syncthreads();  // rows read before they are written again
   };
@@ -1207,8 +1220,9 @@ __global__ __launch_bounds__(64, 3) void render_kernel(
       const int px = q.qx + (m & 7), py = q.qy + (m >> 3);
       if (px < q.g.W && py < q.g.H) {
         const int64_t pix = (int64_t)py * q.g.W + px;
-        if (own0) gptr(out)[pix * D + ch0] = pb ? acc10[r] : acc00[r];
-        if (own1) gptr(out)[pix * D + ch1] = pb ? acc11[r] : acc01[r];
+#pragma unroll
+        for (int c = 0; c < NB; c++)
+          if (own[c]) gptr(out)[pix * D + ch[c]] = acc[pb][c][r];
       }
     }
   }
@@ -1314,11 +1328,16 @@ hipError_t launch_blend(const BlendArgs& a, lv_dtype dtype, int m, hipStream_t s
 hipError_t launch_render(const BlendArgs& a, int m, const float* g, int D, float* const* outs,
                          float* const* alphas, const uint32_t* perm, hipStream_t s) {
   if (m == 0 || a.tiles_stride == 0) return hipSuccess;
-  const int ngroups = (D + kRenderCh - 1) / kRenderCh;
+  const int ch = D > 64 ? 128 : 64;  // channels per wave
+  const int ngroups = (D + ch - 1) / ch;
   const int64_t work = (int64_t)a.tiles_stride * m * ngroups;
   const int64_t blocks = (work + 7) / 8 * 32;  // 4 quadrants per tile, whole rounds of 8 XCDs
-  hipLaunchKernelGGL(render_kernel, dim3((unsigned)blocks), dim3(64), 0, s, a.rec, a.ids, a.ranges,
-                     a.geom, a.n, a.tiles_stride, m, ngroups, g, D, outs, alphas, perm);
+  if (ch == 128)
+    hipLaunchKernelGGL(render_kernel<4>, dim3((unsigned)blocks), dim3(64), 0, s, a.rec, a.ids,
+                       a.ranges, a.geom, a.n, a.tiles_stride, m, ngroups, g, D, outs, alphas, perm);
+  else
+    hipLaunchKernelGGL(render_kernel<2>, dim3((unsigned)blocks), dim3(64), 0, s, a.rec, a.ids,
+                       a.ranges, a.geom, a.n, a.tiles_stride, m, ngroups, g, D, outs, alphas, perm);
   return hipGetLastError();
 }
 
