@@ -99,3 +99,20 @@ def test_render_full_size_view():
     assert amb.sum() <= 0.001 * amb.size
     assert err[ok].max() < 1e-4
     assert np.abs(got_a - ref_a)[ok].max() < 1e-5
+
+
+def test_render_of_a_scene_without_gaussians():
+    """n = 0: no kernel runs, and every output and opacity is set to 0 (the
+    outputs are filled with NaN first)."""
+    from synth.scenes import Scene
+    empty = Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32),
+                  np.zeros((0, 4), np.float32), np.zeros(0, np.float32))
+    cams = [scenes.look_at([0, 0, 4.0], 64, 48, 60.0), scenes.look_at([0, 4.0, 0.5], 33, 17, 50.0)]
+    g0 = lv.Scene.from_arrays(empty)
+    outs = [torch.full((c.height, c.width, 5), float("nan"), device="cuda") for c in cams]
+    alps = [torch.full((c.height, c.width), float("nan"), device="cuda") for c in cams]
+    g0.render(cams, torch.zeros((0, 5), device="cuda"), outs=(outs, alps))
+    torch.cuda.synchronize()
+    for o, a in zip(outs, alps):
+        assert torch.all(o == 0) and torch.all(a == 0)
+    g0.close()
